@@ -1,0 +1,290 @@
+"""Synthetic Wannier models: seeded draws of H(R), C(R) and g(Re,Rp).
+
+Conventions shared by every consumer (they are conventions of the *inputs*,
+not steps of the method):
+
+* Lengths in Angstrom, masses in amu, energies in eV.
+* ``lattice`` rows are the primitive vectors a_1, a_2, a_3 (Cartesian).
+* Real-space vectors are integer triples n, R = n_1 a_1 + n_2 a_2 + n_3 a_3.
+* k and q are given in reduced (crystal) coordinates, k = sum_i x_i b_i.
+* ``h[r, i, j]``   = H_ij(R_r)                         complex,   [nR][nw][nw]
+* ``ifc[r, a, b]`` = C_{a b}(R_r), a = 3*kappa+alpha  real,      [nR][3nat][3nat]
+  (force constants *without* the mass factor, paper Eq. IFC1)
+* ``g[e, p, a, i, j]`` = g^{a}_{ij}(Re_e, Rp_p)        complex,  [nRe][nRp][3nat][nw][nw]
+  (paper Eq. eph_mat_wann, units eV/Angstrom)
+
+Readings of the paper's silent points that shape these draws (Sec. "Wigner-Seitz
+supercell", Eq. wann_ws): one least-distance image per Born-von Karman cell, ties
+broken by the lexicographically smallest integer triple, unit weights; H and C
+are left zero on vectors whose inverse is not in the set so that H(k) and D(q)
+stay Hermitian.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+from typing import Optional
+
+import numpy as np
+
+A_SI = 5.389      # Angstrom, silicon lattice constant of the Sec. 5.4 example
+A_GAAS = 5.556    # Angstrom, GaAs lattice constant of the Sec. 5.1 example
+M_SI = 28.0855
+M_GA = 69.723
+M_AS = 74.9216
+
+
+@dataclasses.dataclass
+class Model:
+    lattice: np.ndarray            # (3,3) rows a_i, Angstrom
+    tau: np.ndarray                # (nat,3) Cartesian atom positions, Angstrom
+    mass: np.ndarray               # (nat,) amu
+    nw: int
+    wf_centres: np.ndarray         # (nw,3) Cartesian, Angstrom (informational)
+    re: np.ndarray                 # (nRe,3) int32, vectors of H(R)
+    w_re: np.ndarray               # (nRe,) weights
+    h: np.ndarray                  # (nRe,nw,nw) complex128
+    rp_ph: np.ndarray              # (nRph,3) int32, vectors of C(R)
+    w_rp_ph: np.ndarray
+    ifc: np.ndarray                # (nRph,3nat,3nat) float64
+    re_g: np.ndarray               # (nReg,3) int32
+    w_re_g: np.ndarray
+    rp_g: np.ndarray               # (nRpg,3) int32
+    w_rp_g: np.ndarray
+    g: np.ndarray                  # (nReg,nRpg,3nat,nw,nw) complex128
+    zstar: Optional[np.ndarray] = None   # (nat,3,3) Born charges, Z*[kappa, beta, alpha]
+    eps_inf: Optional[np.ndarray] = None  # (3,3) high-frequency dielectric tensor
+    name: str = "model"
+
+    @property
+    def nat(self) -> int:
+        return int(self.tau.shape[0])
+
+    @property
+    def nmodes(self) -> int:
+        return 3 * self.nat
+
+    def volume(self) -> float:
+        return float(abs(np.linalg.det(self.lattice)))
+
+
+def fcc_lattice(a: float) -> np.ndarray:
+    return 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+
+
+def sc_lattice(a: float) -> np.ndarray:
+    return a * np.eye(3)
+
+
+def ws_vectors(lattice: np.ndarray, n_grid) -> np.ndarray:
+    """One least-distance lattice vector per Born-von Karman cell of an
+    n1 x n2 x n3 supercell (paper Sec. "Wigner-Seitz supercell", Eq. wann_ws,
+    with all Wannier centres taken at the origin).  Ties go to the
+    lexicographically smallest integer triple.  Returns int32 (N,3) in cell
+    enumeration order."""
+    n_grid = tuple(int(x) for x in np.broadcast_to(np.asarray(n_grid), (3,)))
+    out = []
+    shifts = list(itertools.product(range(-2, 3), repeat=3))
+    scale = float(np.max(np.linalg.norm(lattice, axis=1)))
+    for cell in itertools.product(*(range(n) for n in n_grid)):
+        best = None
+        best_d = None
+        for s in shifts:
+            cand = tuple(cell[i] + n_grid[i] * s[i] for i in range(3))
+            d = float(np.linalg.norm(np.asarray(cand, float) @ lattice))
+            if best is None or d < best_d - 1e-9 * scale or (
+                abs(d - best_d) <= 1e-9 * scale and cand < best
+            ):
+                best, best_d = cand, d
+        out.append(best)
+    return np.asarray(out, dtype=np.int32)
+
+
+def _cnormal(rng, shape, real=False):
+    if real:
+        return rng.standard_normal(shape)
+    z = rng.standard_normal(shape + (2,))
+    return (z[..., 0] + 1j * z[..., 1]) / np.sqrt(2.0)
+
+
+def _index(vecs: np.ndarray) -> dict:
+    return {tuple(int(x) for x in v): i for i, v in enumerate(vecs)}
+
+
+def hermitian_hoppings(rng, vecs, lattice, nw, amp, decay, onsite=None, real=False,
+                       nn_hop=None):
+    """H(R) = onsite*delta_R0 + nn_hop*delta_{R in NN} + amp * X(R) * exp(-|R|/decay),
+    with X(-R) = X(R)^H drawn once per +/-R pair; zero where -R is not in the
+    set.  nn_hop (length nw, real) is a diagonal nearest-neighbour hopping that
+    gives each band a smooth, parabolic-like extremum."""
+    idx = _index(vecs)
+    h = np.zeros((len(vecs), nw, nw), dtype=np.complex128)
+    draws = _cnormal(rng, (len(vecs), nw, nw), real=real)
+    dists = np.linalg.norm(vecs.astype(float) @ lattice, axis=1)
+    dnn = np.min(dists[dists > 1e-9])
+    for i, v in enumerate(vecs):
+        j = idx.get(tuple(-int(x) for x in v))
+        if j is None or j < i:
+            continue
+        dist = float(np.linalg.norm(v.astype(float) @ lattice))
+        x = amp * np.exp(-dist / decay) * draws[i]
+        if i == j:
+            x = 0.5 * (x + x.conj().T)
+            if onsite is not None:
+                x = x + np.diag(onsite)
+            h[i] = x
+        else:
+            if nn_hop is not None and abs(dist - dnn) < 1e-6 * dnn:
+                x = x + np.diag(np.asarray(nn_hop, dtype=float))
+            h[i] = x
+            h[j] = x.conj().T
+    return h
+
+
+def spring_ifc(rng, vecs, lattice, tau, amp, decay):
+    """Force constants as a sum of random positive semi-definite 3x3 springs,
+    one per unordered bond (kappa@0, kappa'@R).  Each spring K adds
+    -K to C_{kk'}(R) and C_{k'k}(-R), +K to C_kk(0) and C_k'k'(0), so the
+    acoustic sum rule and Hermiticity of D(q) hold by construction."""
+    nat = tau.shape[0]
+    idx = _index(vecs)
+    zero = idx[(0, 0, 0)]
+    c = np.zeros((len(vecs), 3 * nat, 3 * nat))
+    for i, v in enumerate(vecs):
+        tv = tuple(int(x) for x in v)
+        j = idx.get(tuple(-x for x in tv))
+        if j is None:
+            continue
+        for ka in range(nat):
+            for kb in range(nat):
+                if ka > kb:
+                    continue
+                if ka == kb and not (tv > tuple(-x for x in tv)):
+                    continue  # self-bonds: count each +/-R once, never R=0
+                b = rng.standard_normal((3, 3))
+                d = float(np.linalg.norm(v.astype(float) @ lattice + tau[kb] - tau[ka]))
+                k = amp * np.exp(-d / decay) * (b @ b.T) / 3.0
+                sa, sb = slice(3 * ka, 3 * ka + 3), slice(3 * kb, 3 * kb + 3)
+                c[i, sa, sb] -= k
+                c[j, sb, sa] -= k.T
+                c[zero, sa, sa] += k
+                c[zero, sb, sb] += k
+    return c
+
+
+def coupling_tensor(rng, re, rp, lattice, nm, nw, amp, decay, real=False):
+    """g(Re,Rp) = amp * Z * exp(-(|Re|+|Rp|)/decay), Z complex (or real) normal."""
+    de = np.linalg.norm(re.astype(float) @ lattice, axis=1)
+    dp = np.linalg.norm(rp.astype(float) @ lattice, axis=1)
+    z = _cnormal(rng, (len(re), len(rp), nm, nw, nw), real=real)
+    env = amp * np.exp(-(de[:, None] + dp[None, :]) / decay)
+    return z * env[:, :, None, None, None]
+
+
+def make_model(
+    *,
+    lattice,
+    tau,
+    mass,
+    nw,
+    n_grid,
+    seed,
+    a_h,
+    a_g,
+    s_k,
+    decay,
+    gap_onsite=3.0,
+    band_step=0.5,
+    nn_hop=0.12,
+    real=False,
+    zstar=None,
+    eps_inf=None,
+    name="model",
+):
+    """Draw a complete synthetic model on the least-distance set of an
+    n_grid^3 supercell (the same set for H, C, Re and Rp)."""
+    lattice = np.asarray(lattice, float)
+    tau = np.asarray(tau, float)
+    mass = np.asarray(mass, float)
+    nat = tau.shape[0]
+    rng = np.random.default_rng(seed)
+    vecs = ws_vectors(lattice, n_grid)
+    nr = len(vecs)
+    nv = nw // 2
+    lev = np.arange(max(nv, nw - nv), dtype=float)
+    # valence levels below -gap_onsite, conduction levels above +gap_onsite;
+    # NN hopping of opposite signs puts the VB maximum and CB minimum at Gamma
+    onsite = np.concatenate([-(gap_onsite + band_step * lev[:nv])[::-1],
+                             gap_onsite + band_step * lev[:nw - nv]])
+    hop = np.concatenate([(nn_hop * (1 + 0.25 * lev[:nv]))[::-1],
+                          -nn_hop * (1 + 0.25 * lev[:nw - nv])])
+    h = hermitian_hoppings(rng, vecs, lattice, nw, a_h, decay, onsite=onsite, real=real,
+                           nn_hop=hop)
+    ifc = spring_ifc(rng, vecs, lattice, tau, s_k, decay)
+    g = coupling_tensor(rng, vecs, vecs, lattice, 3 * nat, nw, a_g, decay, real=real)
+    wf = np.repeat(tau, int(np.ceil(nw / nat)), axis=0)[:nw]
+    ones = np.ones(nr)
+    return Model(
+        lattice=lattice, tau=tau, mass=mass, nw=nw, wf_centres=wf,
+        re=vecs, w_re=ones, h=h, rp_ph=vecs.copy(), w_rp_ph=ones.copy(), ifc=ifc,
+        re_g=vecs.copy(), w_re_g=ones.copy(), rp_g=vecs.copy(), w_rp_g=ones.copy(), g=g,
+        zstar=None if zstar is None else np.asarray(zstar, float),
+        eps_inf=None if eps_inf is None else np.asarray(eps_inf, float),
+        name=name,
+    )
+
+
+def random_points(seed: int, n: int) -> np.ndarray:
+    """n uniform random points in reduced coordinates [0,1)^3 (NumPy PCG64)."""
+    return np.random.default_rng(seed).random((n, 3))
+
+
+SEED_BASE = 20020205
+
+# Workload definitions.  Physical parameters follow the readings listed in the
+# design notes: Gaussian delta exp(-(x/s)^2)/(sqrt(pi) s), mu at the midpoint of
+# the onsite levels (0 eV, inside the gap), omega_cut = 1e-4 eV.
+CONFIGS = {
+    "tiny": dict(
+        lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=4, n_grid=4,
+        a_h=0.05, nn_hop=0.12, a_g=0.5, s_k=0.375, seed=SEED_BASE + 1,
+        nk=200, nq=500, T=300.0, sigma=0.010, mu=0.0, omega_cut=1e-4,
+    ),
+    "si": dict(
+        lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=8, n_grid=8,
+        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 2,
+        nk=5000, nq=1_000_000, window=0.3, T=300.0, sigma=0.005, mu=0.0, omega_cut=1e-4,
+    ),
+    "gaas": dict(
+        lattice="fcc", a=A_GAAS, nat=2, masses=(M_GA, M_AS), nw=8, n_grid=8,
+        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 3,
+        real=True, zstar=2.1, eps_inf=10.9, k_grid=100, window=0.2, T=300.0, sigma=0.005,
+        n_c=1e17, omega_cut=1e-4,
+    ),
+    "dyn": dict(
+        lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=8, n_grid=8,
+        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 2,
+        k_grid=80, n_states=20_000, T=300.0, sigma=0.008, dt=1.0, n_steps=1000,
+        ckpt_every=50, f0_peak=0.1, f0_centre=0.3, f0_width=0.05, omega_cut=1e-4,
+    ),
+}
+
+
+def make_config_model(name: str, *, real=None, n_grid=None, nw=None) -> Model:
+    c = CONFIGS[name]
+    if real is None:
+        real = bool(c.get("real", False))
+    a = c["a"]
+    lat = fcc_lattice(a) if c["lattice"] == "fcc" else sc_lattice(a)
+    tau = np.array([[0.0, 0.0, 0.0], [0.25 * a, 0.25 * a, 0.25 * a]])[: c["nat"]]
+    zstar = eps = None
+    if "zstar" in c:
+        z = c["zstar"]
+        zstar = np.stack([z * np.eye(3), -z * np.eye(3)])
+        eps = c["eps_inf"] * np.eye(3)
+    return make_model(
+        lattice=lat, tau=tau, mass=np.array(c["masses"]),
+        nw=nw or c["nw"], n_grid=n_grid or c["n_grid"], seed=c["seed"],
+        a_h=c["a_h"], a_g=c["a_g"], s_k=c["s_k"], nn_hop=c["nn_hop"], decay=1.5 * a, real=real,
+        zstar=zstar, eps_inf=eps, name=name,
+    )
