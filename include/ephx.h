@@ -1,0 +1,230 @@
+/*
+ * ephx.h -- C ABI of the MI355X (gfx950) electron-phonon hot path.
+ *
+ * The library computes, for a Wannier model {H(Re), force constants C(Rp),
+ * g(Re,Rp)}, the interpolated bands, phonons and e-ph matrix elements
+ * g_mn,nu(k,q), the Gaussian-smeared scattering rates, and the BTE work built
+ * on stored |g|^2 pair tables (collision integral, RK4 carrier dynamics,
+ * iterative linearised BTE), following Zhou et al., "PERTURBO"
+ * (arXiv:2002.02045), Sec. 2.1-2.3 and 4.3.
+ *
+ * Conventions (every entry point)
+ * -------------------------------
+ *  - Every call returns int: EPHX_OK (0) or a negative error code below;
+ *    ephx_last_error() then returns a thread-local message.  No C++ exception
+ *    crosses this boundary.  Arguments are validated before any launch: on an
+ *    error return nothing has been enqueued.
+ *  - Units: energies eV (phonons as hbar*omega in eV), lengths Angstrom,
+ *    masses amu, temperature K, time fs, rates 1/fs.
+ *  - k and q points are reduced (crystal) coordinates, double[n][3].
+ *  - Complex arrays are interleaved (re, im) doubles or floats, row-major.
+ *  - "device" arrays are owned by the caller, allocated on the current HIP
+ *    device, contiguous and row-major; "host" arrays are ordinary host memory.
+ *  - The library owns the opaque handles (ephx_model, ephx_table), their
+ *    device copies and their work buffers; release them with *_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Every
+ *    compute call is asynchronous on it, except where a host output is
+ *    documented (those calls synchronise the stream before returning).
+ *  - Calls on one handle must not overlap in time (they share work buffers);
+ *    calls on distinct handles are independent.
+ *  - Precision: EPHX_FP64 (all steps FP64), EPHX_FP32 (Fourier contractions,
+ *    rotation and projection in FP32, FP32 Fourier sum of H(k+q); phases
+ *    reduced in FP64; eigensolves, eps, omega and rate sums in FP64), or
+ *    EPHX_BF16X3 (as FP32, but the Rp contraction of g runs on bf16 MFMA with
+ *    each FP32 operand split into two bf16 parts and three products kept), or
+ *    EPHX_BF16X6 (three bf16 parts per operand, six products kept).
+ */
+#ifndef EPHX_H
+#define EPHX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPHX_OK 0
+#define EPHX_EINVAL (-1)       /* bad argument: null pointer, size, shape or range */
+#define EPHX_ENOMEM (-2)       /* device allocation failed */
+#define EPHX_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define EPHX_ENOTHERM (-4)     /* model tensors violate H(-R) = H(R)^dag or C_kk'(-R) = C_k'k(R)^T */
+#define EPHX_ENAN (-5)         /* non-finite value detected in an input or result */
+#define EPHX_EUNSUPPORTED (-6) /* valid request outside what this build implements */
+
+#define EPHX_FP64 0
+#define EPHX_FP32 1
+#define EPHX_BF16X3 2
+#define EPHX_BF16X6 3
+
+typedef struct ephx_model ephx_model;
+typedef struct ephx_table ephx_table;
+
+/* Wannier model, all pointers host memory, read only during ephx_model_create.
+ * Real-space vectors are integer triples n (R = n1 a1 + n2 a2 + n3 a3), each
+ * with a weight w (multiplied into the tensor at load).
+ *   h   [n_re][nw][nw] complex           H_ij(Re)              (paper Eq. wannier_2)
+ *   ifc [n_rp_ph][3nat][3nat] real       C_{k a, k' b}(Rp)     (Eq. IFC1, no mass factor)
+ *   g   [n_re_g][n_rp_g][3nat][nw][nw] complex  g^{k a}_ij(Re,Rp) (Eq. eph_mat_wann), eV/Angstrom
+ * Polar models (polar != 0) add the Froehlich term of Eq. e_ph_long with Born
+ * charges zstar[nat][3][3] (index [kappa][beta][alpha]), dielectric tensor
+ * eps_inf[3][3], Ewald parameter alpha_ewald (1/Angstrom^2) and cutoff gcut on
+ * |q+G| (1/Angstrom). */
+typedef struct {
+    double lattice[3][3];      /* rows a_1, a_2, a_3 in Angstrom */
+    int natoms;
+    const double* tau;         /* [natoms][3] Cartesian, Angstrom */
+    const double* mass;        /* [natoms] amu */
+    int nw;
+    int n_re;
+    const int32_t* re;
+    const double* w_re;        /* may be NULL (all 1) */
+    const double* h;
+    int n_rp_ph;
+    const int32_t* rp_ph;
+    const double* w_rp_ph;     /* may be NULL */
+    const double* ifc;
+    int n_re_g;
+    const int32_t* re_g;
+    const double* w_re_g;      /* may be NULL */
+    int n_rp_g;
+    const int32_t* rp_g;
+    const double* w_rp_g;      /* may be NULL */
+    const double* g;
+    int polar;
+    const double* zstar;
+    const double* eps_inf;
+    double alpha_ewald;
+    double gcut;
+} ephx_model_desc;
+
+/* Physical parameters of rates, tables and transport.
+ * sigma: Gaussian width, delta(x) = exp(-(x/sigma)^2)/(sqrt(pi) sigma).
+ * omega_cut: modes with hbar*omega <= omega_cut contribute nothing.
+ * n_q: the normalisation N_q of the q sums (Eq. e_ph_scattering); ignored by
+ *      ephx_rates, which uses the q weights. */
+typedef struct {
+    double temp;
+    double mu;
+    double sigma;
+    double omega_cut;
+    double n_q;
+} ephx_params;
+
+const char* ephx_last_error(void);
+const char* ephx_version(void);
+
+/* Copy a model to the current device.  Checks sizes (nw <= 16, 3*natoms <= 12 in
+ * this build), finiteness and the Hermiticity relations above (relative
+ * tolerance 1e-12) -> EPHX_EINVAL / EPHX_ENAN / EPHX_ENOTHERM.  *out receives
+ * a handle that the caller releases with ephx_model_destroy. */
+int ephx_model_create(const ephx_model_desc* d, ephx_model** out);
+int ephx_model_destroy(ephx_model* m);
+
+/* Band interpolation, Eqs. wannier_3, velocity, wannier_4.
+ * k_red device [nk][3]; eps device [nk][nw] (ascending);
+ * u device [nk][nw][nw] complex128 or NULL, column n is the eigenvector of band n
+ * (H^(W)(k) = U diag(eps) U^dag); vel device [nk][nw][3] (Angstrom/fs) or NULL.
+ * In degenerate groups (gaps < 1e-4 eV) velocities are the eigenvalues of the
+ * group block of U^dag dH/dk U, ascending within the group. */
+int ephx_bands(ephx_model* m, int nk, const double* k_red, double* eps, double* u,
+               double* vel, void* stream);
+
+/* Phonon interpolation, Eq. IFC2: omega device [nq][3nat] (hbar*omega in eV,
+ * ascending in omega^2, negative for omega^2 < 0); evec device
+ * [nq][3nat][3nat] complex128 (column nu = e_nu) or NULL. */
+int ephx_phonons(ephx_model* m, int nq, const double* q_red, double* omega, double* evec,
+                 void* stream);
+
+/* |g_mn,nu(k,q)|^2 for the outer product of a k list and a q list, Eqs.
+ * eph_mat_wann2, eph_mat (+ e_ph_long for polar models).  g2 device
+ * [nk][nq][3nat][nw][nw] indexed [k][q][nu][m][n] (m final band at k+q, n
+ * initial band at k), double for EPHX_FP64, float otherwise.  Modes with
+ * omega <= omega_cut are zero. */
+int ephx_gkq(ephx_model* m, int nk, const double* k_red, int nq, const double* q_red,
+             int precision, double omega_cut, void* g2, void* stream);
+
+/* Scattering rates, Eqs. scatter_rate and BTE_W, summed over the q list with
+ * weights q_w (device [nq], or NULL for 1/nq each):
+ *   Gamma_nk = sum_q w_q sum_{m,nu} (2 pi/hbar)|g_mn,nu|^2 [delta(e_nk - hw - e_mk+q)(1 + N - f_m)
+ *                                                         + delta(e_nk + hw - e_mk+q)(N + f_m)]
+ * f = Fermi-Dirac(mu, temp), N = Bose-Einstein(temp).  gamma device [nk][nw],
+ * gamma_mode device [nk][nw][3nat] or NULL; 1/fs, accumulated in FP64. */
+int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
+               const double* q_red, const double* q_w, int precision, double* gamma,
+               double* gamma_mode, void* stream);
+
+/* Window states on a Gamma-centred n_grid[0] x n_grid[1] x n_grid[2] grid
+ * (Sec. 4.3): grid point (i1,i2,i3) has index (i1*N2 + i2)*N3 + i3 and reduced
+ * coordinates i/N.  mode 0: every (k, band) with band_lo <= band < band_hi and
+ * e_lo < eps < e_hi, the edges first moved to the midpoint between the two
+ * sorted energies straddling them.  mode 1: the `count` lowest states of band
+ * band_lo ordered by (eps, k index), grown while the next energy is within
+ * 1e-9 eV of the last kept.  Results are sorted by (k index, band).
+ * k_idx, band, eps: host arrays of capacity `capacity`; *n_states receives the
+ * number found (EPHX_EINVAL with *n_states set if it exceeds capacity).
+ * Synchronises `stream`. */
+int ephx_grid_states(ephx_model* m, const int n_grid[3], int mode, int band_lo, int band_hi,
+                     double e_lo, double e_hi, int count, int capacity, int* n_states,
+                     int32_t* k_idx, int32_t* band, double* eps, void* stream);
+
+/* Pair table of S grid states (host arrays k_idx[S], band[S] as returned above):
+ * for every ordered pair (s,t), q = k_t - k_s on the grid and
+ *   G[nu][s][t] = 1/2 (|g_{n_t n_s nu}(k_s, q)|^2 + |g_{n_s n_t nu}(k_t, -q)|^2)   (FP32)
+ * together with omega_nu(q).  The symmetrisation gives |g(s->t)|^2 = |g(t->s)|^2,
+ * which exact carrier conservation needs.  precision selects the arithmetic of
+ * the g contractions.  The table keeps O(3nat * S^2) floats on the device. */
+int ephx_table_create(ephx_model* m, const int n_grid[3], int n_states, const int32_t* k_idx,
+                      const int32_t* band, int precision, double omega_cut, ephx_table** out,
+                      void* stream);
+int ephx_table_destroy(ephx_table* t);
+/* Copies G (device float [3nat][S][S]) and state energies (device double [S]). */
+int ephx_table_g2(ephx_table* t, float* g2, double* eps, void* stream);
+
+/* Collision integral of Eq. e_ph_scattering on the table's states:
+ *   I_s = -(2 pi/hbar)(1/N_q) sum_{t,nu} s_nu G[nu][s][t] [delta(e_s - hw - e_t) F_em + delta(e_s + hw - e_t) F_abs]
+ * with F_abs, F_em of Sec. 2.1, N = Bose-Einstein(temp) fixed.  The call
+ * ephx_collision_setup(t, p, mode_scale) (host mode_scale[3nat] or NULL = 1)
+ * must precede the calls below and again after any parameter change.
+ * f and I: device double [S]. */
+int ephx_collision_setup(ephx_table* t, const ephx_params* p, const double* mode_scale,
+                         void* stream);
+int ephx_collision(ephx_table* t, const double* f, double* i_out, void* stream);
+
+/* RK4 carrier dynamics df/dt = I[f] (Eq. BTE_E with E = 0, classic four-stage
+ * Runge-Kutta): n_steps steps of dt fs from f0 (device [S]) into f_out (device
+ * [S]).  If ckpts is not NULL it receives f after every ckpt_every steps,
+ * device [n_steps/ckpt_every + 1][S] (row 0 = f0). */
+int ephx_dynamics(ephx_table* t, const double* f0, double dt, int n_steps, int ckpt_every,
+                  double* f_out, double* ckpts, void* stream);
+
+/* Vector-Jacobian product of the collision integral: given f and lambda
+ * (device [S]), f_bar = lambda^T dI/df (device [S]) and, if s_bar is not
+ * NULL, s_bar[nu] = lambda^T dI/ds_nu (device [3nat]). */
+int ephx_collision_vjp(ephx_table* t, const double* f, const double* lam, double* f_bar,
+                       double* s_bar, void* stream);
+
+/* Backward through ephx_dynamics for a loss L(f_final): given checkpoints
+ * (as written by ephx_dynamics with the same dt, n_steps, ckpt_every) and
+ * f_bar_final = dL/df(t_end) (device [S]), returns dL/df0 (device [S]) and
+ * dL/ds_nu at the current mode scales (device [3nat], or NULL).  Each
+ * checkpoint segment is replayed forward, then differentiated in reverse. */
+int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, int n_steps,
+                      int ckpt_every, const double* f_bar_final, double* f0_bar,
+                      double* s_bar, void* stream);
+
+/* Iterative linearised BTE (Eqs. BTE_lin, BTE_iter, BTE_W) on the table's
+ * states with equilibrium occupations f0 = Fermi-Dirac(p->mu, p->temp):
+ *   Gamma_s = (1/N_q) sum_t W_st, tau = 1/Gamma, F^0 = tau v,
+ *   F^{i+1} = F^0 + (tau/N_q) sum_t W_st F^i.
+ * vel device [S][3] (Angstrom/fs); n_iter = 0 gives the RTA.  F_out device
+ * [S][3] (Angstrom), tau_out device [S] (fs) or NULL.  The mobility of Eq. cond
+ * divided by e n_c, mu_ab = e sum v^a F^b (-df0/de) / sum f0, goes to
+ * mob_out (device double [3][3], cm^2/(V s)) unless NULL. */
+int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
+                  double* f_out, double* tau_out, double* mob_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPHX_H */

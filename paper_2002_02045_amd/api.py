@@ -1,0 +1,242 @@
+"""Python face of the C ABI: allocation of outputs with torch on the current
+device and marshalling of pointers.  Names follow include/ephx.h."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BF16X3, BF16X6, FP32, FP64, EphxError, check, host_ptr, lib, ptr, stream_ptr  # noqa: F401
+
+F64 = torch.float64
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return _lib.PRECISIONS[p]
+    return int(p)
+
+
+def _pts(x):
+    t = torch.as_tensor(x, dtype=F64, device="cuda")
+    if t.ndim != 2 or t.shape[1] != 3:
+        raise ValueError("points must be an (n, 3) array of reduced coordinates")
+    return t.contiguous()
+
+
+class Params:
+    """temp (K), mu (eV), sigma (eV), omega_cut (eV), n_q (q-sum normalisation)."""
+
+    def __init__(self, temp, mu=0.0, sigma=0.01, omega_cut=1e-4, n_q=1.0):
+        self.temp, self.mu, self.sigma, self.omega_cut, self.n_q = temp, mu, sigma, omega_cut, n_q
+
+    def c(self):
+        return _lib.Params(self.temp, self.mu, self.sigma, self.omega_cut, self.n_q)
+
+
+class Model:
+    """Device copy of a Wannier model.  `src` needs the attributes lattice, tau,
+    mass, nw, re, w_re, h, rp_ph, w_rp_ph, ifc, re_g, w_re_g, rp_g, w_rp_g, g
+    and optionally zstar, eps_inf (+ polar = dict(alpha_ewald, gcut))."""
+
+    def __init__(self, src, polar=None):
+        def f64(a):
+            return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+        def c128(a):
+            return np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+
+        def i32(a):
+            return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+        keep = dict(
+            tau=f64(src.tau), mass=f64(src.mass), re=i32(src.re), w_re=f64(src.w_re), h=c128(src.h),
+            rp_ph=i32(src.rp_ph), w_rp_ph=f64(src.w_rp_ph), ifc=f64(src.ifc), re_g=i32(src.re_g),
+            w_re_g=f64(src.w_re_g), rp_g=i32(src.rp_g), w_rp_g=f64(src.w_rp_g), g=c128(src.g))
+        d = _lib.ModelDesc()
+        d.lattice[:] = [float(v) for v in np.asarray(src.lattice, dtype=np.float64).ravel()]
+        d.natoms = keep["tau"].shape[0]
+        d.nw = int(src.nw)
+        d.tau, d.mass = host_ptr(keep["tau"]), host_ptr(keep["mass"])
+        d.n_re, d.re, d.w_re, d.h = len(keep["re"]), host_ptr(keep["re"]), host_ptr(keep["w_re"]), host_ptr(keep["h"])
+        d.n_rp_ph, d.rp_ph, d.w_rp_ph, d.ifc = (len(keep["rp_ph"]), host_ptr(keep["rp_ph"]),
+                                                host_ptr(keep["w_rp_ph"]), host_ptr(keep["ifc"]))
+        d.n_re_g, d.re_g, d.w_re_g = len(keep["re_g"]), host_ptr(keep["re_g"]), host_ptr(keep["w_re_g"])
+        d.n_rp_g, d.rp_g, d.w_rp_g = len(keep["rp_g"]), host_ptr(keep["rp_g"]), host_ptr(keep["w_rp_g"])
+        d.g = host_ptr(keep["g"])
+        if polar is not None:
+            keep["zstar"] = f64(src.zstar)
+            keep["eps"] = f64(src.eps_inf)
+            d.polar = 1
+            d.zstar, d.eps_inf = host_ptr(keep["zstar"]), host_ptr(keep["eps"])
+            d.alpha_ewald, d.gcut = float(polar["alpha_ewald"]), float(polar["gcut"])
+        self._h = C.c_void_p()
+        torch.cuda.init()
+        check(lib.ephx_model_create(C.byref(d), C.byref(self._h)))
+        self.nw = int(src.nw)
+        self.nat = d.natoms
+        self.nmodes = 3 * self.nat
+
+    def close(self):
+        if self._h:
+            check(lib.ephx_model_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def bands(model, k, want_u=True, want_vel=False):
+    """eps (nk,nw), U (nk,nw,nw) complex128 or None, v (nk,nw,3) or None."""
+    kt = _pts(k)
+    nk = kt.shape[0]
+    eps = torch.empty((nk, model.nw), dtype=F64, device="cuda")
+    u = torch.empty((nk, model.nw, model.nw), dtype=torch.complex128, device="cuda") if want_u else None
+    v = torch.empty((nk, model.nw, 3), dtype=F64, device="cuda") if want_vel else None
+    check(lib.ephx_bands(model.handle, nk, ptr(kt), ptr(eps), ptr(u), ptr(v), stream_ptr()))
+    return eps, u, v
+
+
+def phonons(model, q, want_evec=True):
+    qt = _pts(q)
+    nq = qt.shape[0]
+    om = torch.empty((nq, model.nmodes), dtype=F64, device="cuda")
+    ev = torch.empty((nq, model.nmodes, model.nmodes), dtype=torch.complex128, device="cuda") if want_evec else None
+    check(lib.ephx_phonons(model.handle, nq, ptr(qt), ptr(om), ptr(ev), stream_ptr()))
+    return om, ev
+
+
+def gkq(model, k, q, precision="fp64", omega_cut=1e-4, out=None):
+    """|g|^2 as (nk, nq, nmodes, nw, nw) indexed [k][q][nu][m][n]."""
+    p = _prec(precision)
+    kt, qt = _pts(k), _pts(q)
+    shape = (kt.shape[0], qt.shape[0], model.nmodes, model.nw, model.nw)
+    if out is None:
+        out = torch.empty(shape, dtype=F64 if p == FP64 else torch.float32, device="cuda")
+    check(lib.ephx_gkq(model.handle, kt.shape[0], ptr(kt), qt.shape[0], ptr(qt), p, float(omega_cut), ptr(out),
+                       stream_ptr()))
+    return out
+
+
+def rates(model, k, q, params, precision="fp64", q_weights=None, mode_resolved=True):
+    """Scattering rates (nk, nw) in 1/fs and, optionally, per mode (nk, nw, nmodes)."""
+    p = _prec(precision)
+    kt, qt = _pts(k), _pts(q)
+    nk = kt.shape[0]
+    gam = torch.empty((nk, model.nw), dtype=F64, device="cuda")
+    gmode = torch.empty((nk, model.nw, model.nmodes), dtype=F64, device="cuda") if mode_resolved else None
+    qw = None if q_weights is None else torch.as_tensor(q_weights, dtype=F64, device="cuda").contiguous()
+    pc = params.c()
+    check(lib.ephx_rates(model.handle, C.byref(pc), nk, ptr(kt), qt.shape[0], ptr(qt), ptr(qw), p, ptr(gam),
+                         ptr(gmode), stream_ptr()))
+    return gam, gmode
+
+
+def grid_states(model, n_grid, *, mode="window", band_lo=0, band_hi=None, e_lo=0.0, e_hi=0.0, count=0,
+                capacity=None):
+    """Window (mode="window") or lowest-count (mode="lowest") states on a
+    Gamma-centred grid.  Returns numpy (k_idx, band, eps)."""
+    n3 = (C.c_int * 3)(*[int(x) for x in np.broadcast_to(np.asarray(n_grid), (3,))])
+    ngrid = n3[0] * n3[1] * n3[2]
+    if band_hi is None:
+        band_hi = model.nw
+    if capacity is None:
+        capacity = max(int(count) + 64, 1) if mode == "lowest" else ngrid * (band_hi - band_lo)
+    kk = np.empty(capacity, np.int32)
+    bb = np.empty(capacity, np.int32)
+    ee = np.empty(capacity, np.float64)
+    ns = C.c_int(0)
+    check(lib.ephx_grid_states(model.handle, n3, 0 if mode == "window" else 1, int(band_lo), int(band_hi),
+                               float(e_lo), float(e_hi), int(count), int(capacity), C.byref(ns), host_ptr(kk),
+                               host_ptr(bb), host_ptr(ee), stream_ptr()))
+    n = ns.value
+    return kk[:n].copy(), bb[:n].copy(), ee[:n].copy()
+
+
+class PairTable:
+    """Symmetrised |g|^2 table of grid states with collision, dynamics and ITA."""
+
+    def __init__(self, model, n_grid, k_idx, band, precision="fp64", omega_cut=1e-4):
+        self.model = model
+        self.S = len(k_idx)
+        self.nmodes = model.nmodes
+        n3 = (C.c_int * 3)(*[int(x) for x in np.broadcast_to(np.asarray(n_grid), (3,))])
+        self._k = np.ascontiguousarray(k_idx, dtype=np.int32)
+        self._b = np.ascontiguousarray(band, dtype=np.int32)
+        self._h = C.c_void_p()
+        check(lib.ephx_table_create(model.handle, n3, self.S, host_ptr(self._k), host_ptr(self._b),
+                                    _prec(precision), float(omega_cut), C.byref(self._h), stream_ptr()))
+
+    def close(self):
+        if self._h:
+            check(lib.ephx_table_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def g2(self):
+        g = torch.empty((self.nmodes, self.S, self.S), dtype=torch.float32, device="cuda")
+        e = torch.empty(self.S, dtype=F64, device="cuda")
+        check(lib.ephx_table_g2(self._h, ptr(g), ptr(e), stream_ptr()))
+        return g, e
+
+    def setup(self, params, mode_scale=None):
+        pc = params.c()
+        ms = None if mode_scale is None else np.ascontiguousarray(mode_scale, dtype=np.float64)
+        check(lib.ephx_collision_setup(self._h, C.byref(pc), host_ptr(ms), stream_ptr()))
+        self._ms = ms
+
+    def collision(self, f):
+        f = torch.as_tensor(f, dtype=F64, device="cuda").contiguous()
+        out = torch.empty(self.S, dtype=F64, device="cuda")
+        check(lib.ephx_collision(self._h, ptr(f), ptr(out), stream_ptr()))
+        return out
+
+    def dynamics(self, f0, dt, n_steps, ckpt_every=0):
+        f0 = torch.as_tensor(f0, dtype=F64, device="cuda").contiguous()
+        out = torch.empty(self.S, dtype=F64, device="cuda")
+        ck = None
+        if ckpt_every > 0:
+            ck = torch.empty((n_steps // ckpt_every + 1, self.S), dtype=F64, device="cuda")
+        check(lib.ephx_dynamics(self._h, ptr(f0), float(dt), int(n_steps), int(ckpt_every), ptr(out), ptr(ck),
+                                stream_ptr()))
+        return out, ck
+
+    def collision_vjp(self, f, lam, want_s=True):
+        f = torch.as_tensor(f, dtype=F64, device="cuda").contiguous()
+        lam = torch.as_tensor(lam, dtype=F64, device="cuda").contiguous()
+        fb = torch.empty(self.S, dtype=F64, device="cuda")
+        sb = torch.empty(self.nmodes, dtype=F64, device="cuda") if want_s else None
+        check(lib.ephx_collision_vjp(self._h, ptr(f), ptr(lam), ptr(fb), ptr(sb), stream_ptr()))
+        return fb, sb
+
+    def dynamics_vjp(self, ckpts, dt, n_steps, ckpt_every, f_bar, want_s=True):
+        fb = torch.as_tensor(f_bar, dtype=F64, device="cuda").contiguous()
+        f0b = torch.empty(self.S, dtype=F64, device="cuda")
+        sb = torch.empty(self.nmodes, dtype=F64, device="cuda") if want_s else None
+        check(lib.ephx_dynamics_vjp(self._h, ptr(ckpts), float(dt), int(n_steps), int(ckpt_every), ptr(fb),
+                                    ptr(f0b), ptr(sb), stream_ptr()))
+        return f0b, sb
+
+    def mobility(self, params, vel, n_iter):
+        vel = torch.as_tensor(vel, dtype=F64, device="cuda").contiguous()
+        ff = torch.empty((self.S, 3), dtype=F64, device="cuda")
+        tau = torch.empty(self.S, dtype=F64, device="cuda")
+        mob = torch.empty((3, 3), dtype=F64, device="cuda")
+        pc = params.c()
+        check(lib.ephx_mobility(self._h, C.byref(pc), ptr(vel), int(n_iter), ptr(ff), ptr(tau), ptr(mob),
+                                stream_ptr()))
+        return ff, tau, mob

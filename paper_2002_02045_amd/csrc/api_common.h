@@ -1,0 +1,80 @@
+// Host-side state shared by the API translation units.
+#pragma once
+
+#include <functional>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ephx.h"
+#include "internal.h"
+
+namespace ephx {
+
+extern thread_local std::string g_last_error;
+
+// Growable named device buffers owned by a handle.
+struct Workspace {
+    struct Buf {
+        void* ptr = nullptr;
+        size_t size = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    void* get(const std::string& name, size_t bytes);
+    void release();
+};
+
+void hip_check(hipError_t e, const char* what);
+void* dev_upload(const void* host, size_t bytes);
+void require(bool ok, const std::string& msg);
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return EPHX_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return EPHX_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return EPHX_EHIP;
+    }
+}
+
+}  // namespace ephx
+
+struct ephx_model {
+    int device = 0;
+    int nw = 0, nat = 0, nm = 0;
+    double lattice[9] = {0};
+    double bvec[9] = {0};
+    double volume = 0.0;
+    std::vector<double> mass, tau;
+    int n_re = 0, n_rp_ph = 0, n_re_g = 0, n_rp_g = 0;
+    int32_t *d_re = nullptr, *d_rp_ph = nullptr, *d_re_g = nullptr, *d_rp_g = nullptr;
+    double* d_h = nullptr;       // [n_re][nw*nw] complex, weights folded
+    float* d_h32 = nullptr;      // FP32 copy (created on first reduced-precision call)
+    double* d_hvel = nullptr;    // [n_re][3][nw*nw] complex, H(R) * (i R_a)
+    double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
+    double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
+    double* d_minv = nullptr;    // [nm]
+    bool polar = false;
+    double *d_bvec = nullptr, *d_tau = nullptr, *d_zstar = nullptr, *d_eps = nullptr;
+    ephx::PolarDev pd{};
+    std::vector<void*> owned;
+    ephx::Workspace ws;
+    ~ephx_model();
+};
+
+namespace ephx {
+void bands_impl(ephx_model* m, int nk, const double* k, double* eps, double* u, double* vel, hipStream_t st,
+                const std::string& tag);
+void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double* evec, hipStream_t st,
+                  const std::string& tag);
+}  // namespace ephx

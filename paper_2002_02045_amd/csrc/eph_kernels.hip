@@ -1,0 +1,407 @@
+// Per-(k,q) work after the Fourier contractions: band rotation (Eq.
+// eph_mat_wann2), mode projection (Eq. eph_mat), |g|^2, the Gaussian-weighted
+// scattering-rate sums (Eqs. scatter_rate, BTE_W), the Froehlich long-range
+// term (Eq. e_ph_long with the bra-ket of Eq. smooth_phase) and band velocities
+// (Eqs. velocity, wannier_4).
+#include "internal.h"
+
+namespace ephx {
+namespace {
+
+inline void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ cx<T> ld(const T* p, long i) {
+    return {p[2 * i], p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ldd(const double* p, long i) {
+    return {(T)p[2 * i], (T)p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T>& acc, cx<T> a, cx<T> b) {  // acc += a*b
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+template <typename T>
+__device__ __forceinline__ void cjfma(cx<T>& acc, cx<T> a, cx<T> b) {  // acc += conj(a)*b
+    acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
+}
+
+__global__ void k_apply_u_right(int nrp, int nm, int nw, const double* __restrict__ g, const double* __restrict__ u,
+                                double* __restrict__ out) {
+    // out[z][p][x][i][n] = sum_j g[z][p][x][i][j] u[z][j][n]
+    const int z = blockIdx.y;
+    const long per = (long)nrp * nm * nw * nw;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per) return;
+    const int n = (int)(t % nw);
+    const long row = t / nw;  // (p, x, i)
+    const double* gz = g + (long)z * per * 2;
+    const double* uz = u + (long)z * nw * nw * 2;
+    cx<double> acc = {0.0, 0.0};
+    for (int j = 0; j < nw; ++j) cfma(acc, ld(gz, row * nw + j), ld(uz, (long)j * nw + n));
+    out[((long)z * per + t) * 2] = acc.x;
+    out[((long)z * per + t) * 2 + 1] = acc.y;
+}
+
+__global__ void k_apply_u_column(int nrp, int nm, int nw, const double* __restrict__ g, const double* __restrict__ us,
+                                 const int32_t* __restrict__ band, double* __restrict__ out) {
+    // out[z][p][x][i] = sum_j g[z][p][x][i][j] us[z][j][band_z]
+    const int z = blockIdx.y;
+    const long per = (long)nrp * nm * nw;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per) return;
+    const int bz = band[z];
+    const double* gz = g + (long)z * per * nw * 2;
+    const double* uz = us + (long)z * nw * nw * 2;
+    cx<double> acc = {0.0, 0.0};
+    for (int j = 0; j < nw; ++j) cfma(acc, ld(gz, t * nw + j), ld(uz, (long)j * nw + bz));
+    out[((long)z * per + t) * 2] = acc.x;
+    out[((long)z * per + t) * 2 + 1] = acc.y;
+}
+
+__global__ void k_convert(long count, const double* __restrict__ in, float* __restrict__ out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) out[t] = (float)in[t];
+}
+
+template <typename T>
+__device__ __forceinline__ T gauss(T x, T inv_sigma, T norm) {
+    const T y = x * inv_sigma;
+    const T y2 = y * y;
+    if (y2 > (T)200) return (T)0;
+    return norm * exp(-y2);
+}
+__device__ __forceinline__ float gauss_f(float x, float inv_sigma, float norm) {
+    const float y = x * inv_sigma;
+    const float y2 = y * y;
+    if (y2 > 200.f) return 0.f;
+    return norm * expf(-y2);
+}
+
+// One wavefront per (k, q) pair; lane <-> element (m, n), up to 4 elements per lane.
+template <typename T, bool RATES>
+__global__ __launch_bounds__(256) void k_eph_epilogue(EphEpilogue e) {
+    extern __shared__ double red[];  // RATES: [4][nw*nw][nm]
+    constexpr int QPB = 64;
+    const int z = blockIdx.y;
+    const int blk = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nw = e.nw, nm = e.nm, nw2 = nw * nw;
+    const int q0 = blk * QPB, q1 = min(e.nq, q0 + QPB);
+    const T* gwz = reinterpret_cast<const T*>(e.gw) + (long)z * e.nq * nm * nw2 * 2;
+
+    double acc[4][kMaxModes];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < kMaxModes; ++b) acc[a][b] = 0.0;
+
+    const double kt = kBoltzEv * e.temp;
+    for (int ql = q0 + wave; ql < q1; ql += 4) {
+        const long qg = (long)e.q_off + ql;               // global q index
+        const long pair = (long)z * e.nq + ql;
+        const T* gp = gwz + (long)ql * nm * nw2 * 2;
+        const double* uq = e.ukq + pair * nw2 * 2;
+        // per-mode amplitude sqrt(hbar^2/(2 M omega)) handled as amp_nu * e[x][nu] * minv[x]
+        double om[kMaxModes];
+        T amp[kMaxModes];
+        for (int nu = 0; nu < nm; ++nu) {
+            om[nu] = e.omega[qg * nm + nu];
+            amp[nu] = om[nu] > e.omega_cut ? (T)sqrt(kHbar2AmuA2 / (2.0 * om[nu])) : (T)0;
+        }
+        for (int t = 0; t < 4; ++t) {
+            const int el = lane + 64 * t;
+            if (el >= nw2) break;
+            const int m = el / nw, n = el % nw;
+            cx<T> gh[kMaxModes];
+            for (int x = 0; x < nm; ++x) {
+                cx<T> s = {0, 0};
+                for (int i = 0; i < nw; ++i) cjfma(s, ldd<T>(uq, (long)i * nw + m), ld(gp, ((long)x * nw + i) * nw + n));
+                gh[x] = s;
+            }
+            if (e.lr != nullptr) {
+                // Wannier-gauge long-range term C(q) delta_ij, rotated: C(q) [U^dag(k+q) U(k)]_mn
+                cx<T> ov = {0, 0};
+                const double* ukz = e.uk + (long)z * nw2 * 2;
+                for (int i = 0; i < nw; ++i) cjfma(ov, ldd<T>(uq, (long)i * nw + m), ldd<T>(ukz, (long)i * nw + n));
+                for (int x = 0; x < nm; ++x) cfma(gh[x], ldd<T>(e.lr, qg * nm + x), ov);
+            }
+            double fm = 0.0, em = 0.0, en = 0.0;
+            if (RATES) {
+                em = e.ekq[pair * nw + m];
+                en = e.ek[(long)z * nw + n];
+                fm = 1.0 / (exp((em - e.mu) / kt) + 1.0);
+            }
+            for (int nu = 0; nu < nm; ++nu) {
+                cx<T> g = {0, 0};
+                if (amp[nu] != (T)0) {
+                    for (int x = 0; x < nm; ++x) {
+                        cx<T> ev = ldd<T>(e.evec, (qg * nm + x) * nm + nu);
+                        ev.x *= (T)e.minv[x];
+                        ev.y *= (T)e.minv[x];
+                        cfma(g, ev, gh[x]);
+                    }
+                    g.x *= amp[nu];
+                    g.y *= amp[nu];
+                }
+                const T g2 = g.x * g.x + g.y * g.y;
+                if (!RATES) {
+                    const long off = ((((long)(e.k_off + z) * e.nq_total + qg) * nm + nu) * nw + m) * nw + n;
+                    reinterpret_cast<T*>(e.g2)[off] = g2;
+                } else if (amp[nu] != (T)0) {
+                    const double nb = 1.0 / expm1(om[nu] / kt);
+                    const double wq = e.qw ? e.qw[qg] : e.uniform_w;
+                    double d_em, d_ab;
+                    if (sizeof(T) == 4) {
+                        const float is = (float)(1.0 / e.sigma), nr = (float)(1.0 / (sqrt(kPi) * e.sigma));
+                        d_em = gauss_f((float)(en - om[nu] - em), is, nr);
+                        d_ab = gauss_f((float)(en + om[nu] - em), is, nr);
+                    } else {
+                        const double is = 1.0 / e.sigma, nr = 1.0 / (sqrt(kPi) * e.sigma);
+                        d_em = gauss<double>(en - om[nu] - em, is, nr);
+                        d_ab = gauss<double>(en + om[nu] - em, is, nr);
+                    }
+                    acc[t][nu] += wq * (double)g2 * (d_em * (1.0 + nb - fm) + d_ab * (nb + fm));
+                }
+            }
+        }
+    }
+    if (!RATES) return;
+    // deterministic block reduction: [wave][element][nu] -> partial[z][blk][n][nu]
+    for (int t = 0; t < 4; ++t) {
+        const int el = lane + 64 * t;
+        if (el >= nw2) break;
+        for (int nu = 0; nu < nm; ++nu) red[((long)wave * nw2 + el) * nm + nu] = acc[t][nu];
+    }
+    __syncthreads();
+    for (int o = tid; o < nw * nm; o += 256) {
+        const int n = o / nm, nu = o % nm;
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int m = 0; m < nw; ++m) s += red[((long)w * nw2 + m * nw + n) * nm + nu];
+        e.partial[(((long)z * e.nblk + blk) * nw + n) * nm + nu] = s * (2.0 * kPi / kHbarEvFs);
+    }
+}
+
+__global__ void k_rates_reduce(int nblk, int nw, int nm, const double* __restrict__ partial, double* __restrict__ acc) {
+    const int z = blockIdx.x;
+    for (int o = threadIdx.x; o < nw * nm; o += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partial[((long)z * nblk + b) * nw * nm + o];
+        acc[(long)z * nw * nm + o] += s;
+    }
+}
+
+__global__ void k_rates_finish(int nkb, int nw, int nm, const double* __restrict__ acc, double* __restrict__ gamma,
+                               double* __restrict__ gmode) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nkb * nw) return;
+    double s = 0.0;
+    for (int nu = 0; nu < nm; ++nu) {
+        const double v = acc[(long)t * nm + nu];
+        s += v;
+        if (gmode) gmode[(long)t * nm + nu] = v;
+    }
+    gamma[t] = s;
+}
+
+// Froehlich term, one thread per (q, kappa); loops over the G box.
+__global__ void k_frohlich(int nq, const double* __restrict__ q, PolarDev p, double* __restrict__ lr) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq * p.nat) return;
+    const int iq = t / p.nat, kap = t % p.nat;
+    double qr[3];
+    for (int d = 0; d < 3; ++d) qr[d] = q[3 * iq + d] - rint(q[3 * iq + d]);
+    double acc_re[3] = {0, 0, 0}, acc_im[3] = {0, 0, 0};
+    for (int m0 = -p.mmax[0]; m0 <= p.mmax[0]; ++m0)
+        for (int m1 = -p.mmax[1]; m1 <= p.mmax[1]; ++m1)
+            for (int m2 = -p.mmax[2]; m2 <= p.mmax[2]; ++m2) {
+                double v[3];
+                for (int d = 0; d < 3; ++d)
+                    v[d] = (qr[0] + m0) * p.bvec[d] + (qr[1] + m1) * p.bvec[3 + d] + (qr[2] + m2) * p.bvec[6 + d];
+                const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (!(nrm < p.gcut) || !(nrm > 1e-12)) continue;
+                double qeq = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b2 = 0; b2 < 3; ++b2) qeq += v[a] * p.eps[3 * a + b2] * v[b2];
+                const double damp = exp(-qeq / (4.0 * p.alpha)) / qeq;
+                const double arg = -(v[0] * p.tau[3 * kap] + v[1] * p.tau[3 * kap + 1] + v[2] * p.tau[3 * kap + 2]);
+                double sn, cs;
+                sincos(arg, &sn, &cs);
+                for (int a = 0; a < 3; ++a) {
+                    double qz = 0.0;
+                    for (int b2 = 0; b2 < 3; ++b2) qz += v[b2] * p.zstar[(kap * 3 + b2) * 3 + a];
+                    acc_re[a] += damp * cs * qz;
+                    acc_im[a] += damp * sn * qz;
+                }
+            }
+    for (int a = 0; a < 3; ++a) {
+        // i * pref * (re + i im) = pref * (-im + i re)
+        const long o = ((long)iq * 3 * p.nat + 3 * kap + a) * 2;
+        lr[o] = -p.pref * acc_im[a];
+        lr[o + 1] = p.pref * acc_re[a];
+    }
+}
+
+// Velocities: one thread per (k, alpha).  M = U^dag dH_a U restricted to
+// degenerate groups; the group block is diagonalised by a serial cyclic
+// Jacobi (group blocks are tiny), eigenvalues sorted ascending in the group.
+__global__ void k_band_velocity(int nk, int nw, const double* __restrict__ dh, const double* __restrict__ u,
+                                const double* __restrict__ eps, double* __restrict__ vel) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk * 3) return;
+    const int ik = t / 3, a = t % 3;
+    const int nw2 = nw * nw;
+    const double* uk = u + (long)ik * nw2 * 2;
+    const double* hk = dh + ((long)ik * 3 + a) * nw2 * 2;
+    const double* ek = eps + (long)ik * nw;
+    cx<double> mm[kMaxNw * kMaxNw];
+    // M_mn = sum_ij conj(U_im) dH_ij U_jn, only inside degenerate groups
+    int grp[kMaxNw];
+    int g = 0;
+    for (int m = 0; m < nw; ++m) {
+        if (m > 0 && !(ek[m] - ek[m - 1] < kDegTol)) ++g;
+        grp[m] = g;
+    }
+    for (int m = 0; m < nw; ++m)
+        for (int n = 0; n < nw; ++n) {
+            cx<double> s = {0.0, 0.0};
+            if (grp[m] == grp[n]) {
+                for (int i = 0; i < nw; ++i) {
+                    cx<double> r = {0.0, 0.0};
+                    for (int j = 0; j < nw; ++j) cfma(r, ld(hk, (long)i * nw + j), ld(uk, (long)j * nw + n));
+                    cjfma(s, ld(uk, (long)i * nw + m), r);
+                }
+            }
+            mm[m * nw + n] = s;
+        }
+    // Jacobi sweeps on the block-diagonal matrix (cross-group entries stay zero)
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int m = 0; m < nw; ++m)
+            for (int n = 0; n < nw; ++n) {
+                const double v2 = mm[m * nw + n].x * mm[m * nw + n].x + mm[m * nw + n].y * mm[m * nw + n].y;
+                tot += v2;
+                if (m != n) off += v2;
+            }
+        if (!(off > 1e-30 * tot)) break;
+        for (int p = 0; p < nw; ++p)
+            for (int q = p + 1; q < nw; ++q) {
+                if (grp[p] != grp[q]) continue;
+                const cx<double> apq = mm[p * nw + q];
+                const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+                if (!(mag > 0.0)) continue;
+                const double th = (mm[q * nw + q].x - mm[p * nw + p].x) / (2.0 * mag);
+                const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
+                const cx<double> ep = {apq.x / mag, apq.y / mag};
+                // columns: A <- A J, J_pq = s e, J_qp = -s conj(e)
+                for (int r = 0; r < nw; ++r) {
+                    const cx<double> arp = mm[r * nw + p], arq = mm[r * nw + q];
+                    // new col p = c*arp + arq*(-s conj(e)); new col q = arp*(s e) + c*arq
+                    mm[r * nw + p] = {c * arp.x - s * (arq.x * ep.x + arq.y * ep.y), c * arp.y - s * (arq.y * ep.x - arq.x * ep.y)};
+                    mm[r * nw + q] = {c * arq.x + s * (arp.x * ep.x - arp.y * ep.y), c * arq.y + s * (arp.x * ep.y + arp.y * ep.x)};
+                }
+                // rows: A <- J^dag A
+                for (int r = 0; r < nw; ++r) {
+                    const cx<double> apr = mm[p * nw + r], aqr = mm[q * nw + r];
+                    // new row p = c*apr + conj(-s conj(e)) aqr = c apr - s e aqr
+                    // new row q = conj(s e) apr + c aqr
+                    mm[p * nw + r] = {c * apr.x - s * (ep.x * aqr.x - ep.y * aqr.y), c * apr.y - s * (ep.x * aqr.y + ep.y * aqr.x)};
+                    mm[q * nw + r] = {c * aqr.x + s * (ep.x * apr.x + ep.y * apr.y), c * aqr.y + s * (ep.x * apr.y - ep.y * apr.x)};
+                }
+            }
+    }
+    // ascending order inside each group
+    double d[kMaxNw];
+    for (int m = 0; m < nw; ++m) d[m] = mm[m * nw + m].x;
+    for (int m = 0; m < nw; ++m)
+        for (int n = m + 1; n < nw && grp[n] == grp[m]; ++n)
+            if (d[n] < d[m]) {
+                const double tmp = d[m];
+                d[m] = d[n];
+                d[n] = tmp;
+            }
+    for (int m = 0; m < nw; ++m) vel[((long)ik * nw + m) * 3 + a] = d[m] / kHbarEvFs;
+}
+
+}  // namespace
+
+void apply_u_right(int Z, int nrp, int nm, int nw, const double* g, const double* u, double* out, hipStream_t st) {
+    const long per = (long)nrp * nm * nw * nw;
+    hipLaunchKernelGGL(k_apply_u_right, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw, g, u, out);
+    check_launch("apply_u_right");
+}
+
+void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const double* us, const int32_t* band,
+                    double* out, hipStream_t st) {
+    const long per = (long)nrp * nm * nw;
+    hipLaunchKernelGGL(k_apply_u_column, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw, g,
+                       us, band, out);
+    check_launch("apply_u_column");
+}
+
+void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, in, out);
+    check_launch("convert");
+}
+
+int eph_epilogue_blocks(int nq) { return (nq + 63) / 64; }
+
+void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st) {
+    dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
+    if (f32)
+        hipLaunchKernelGGL((k_eph_epilogue<float, false>), grid, dim3(256), 0, st, e);
+    else
+        hipLaunchKernelGGL((k_eph_epilogue<double, false>), grid, dim3(256), 0, st, e);
+    check_launch("eph_epilogue_g2");
+}
+
+void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {
+    dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
+    const size_t lds = (size_t)4 * e.nw * e.nw * e.nm * sizeof(double);
+    if (lds > 65536) throw Error{-6, "rates: nw^2 * 3nat too large for one workgroup's reduction buffer"};
+    if (f32)
+        hipLaunchKernelGGL((k_eph_epilogue<float, true>), grid, dim3(256), lds, st, e);
+    else
+        hipLaunchKernelGGL((k_eph_epilogue<double, true>), grid, dim3(256), lds, st, e);
+    check_launch("eph_epilogue_rates");
+}
+
+void rates_reduce(int nkb, int nblk, int nw, int nm, const double* partial, double* acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_rates_reduce, dim3(nkb), dim3(128), 0, st, nblk, nw, nm, partial, acc);
+    check_launch("rates_reduce");
+}
+
+void rates_finish(int nkb, int nw, int nm, const double* acc, double* gamma, double* gmode, hipStream_t st) {
+    const int n = nkb * nw;
+    hipLaunchKernelGGL(k_rates_finish, dim3((n + 127) / 128), dim3(128), 0, st, nkb, nw, nm, acc, gamma, gmode);
+    check_launch("rates_finish");
+}
+
+void frohlich(int nq, const double* q, const PolarDev& p, double* lr, hipStream_t st) {
+    const int n = nq * p.nat;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_frohlich, dim3((n + 127) / 128), dim3(128), 0, st, nq, q, p, lr);
+    check_launch("frohlich");
+}
+
+void band_velocity(int nk, int nw, const double* dh, const double* u, const double* eps, double* vel, hipStream_t st) {
+    const int n = nk * 3;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_band_velocity, dim3((n + 63) / 64), dim3(64), 0, st, nk, nw, dh, u, eps, vel);
+    check_launch("band_velocity");
+}
+
+}  // namespace ephx

@@ -1,0 +1,488 @@
+// Host side of the C ABI declared in include/ephx.h: argument checks, model
+// upload, work buffers and the orchestration of the kernels for bands,
+// phonons, g(k,q) and scattering rates.  BTE entry points live in bte_api.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ephx.h"
+#include "api_common.h"
+
+namespace ephx {
+
+thread_local std::string g_last_error;
+
+void Workspace::release() {
+    for (auto& kv : bufs)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    bufs.clear();
+}
+
+void* Workspace::get(const std::string& name, size_t bytes) {
+    Buf& b = bufs[name];
+    if (b.size >= bytes && b.ptr) return b.ptr;
+    if (b.ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.size = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{EPHX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + name + " failed"};
+    }
+    b.ptr = p;
+    b.size = bytes;
+    return p;
+}
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Error{EPHX_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void* dev_upload(const void* host, size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{EPHX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    if (host) hip_check(hipMemcpy(p, host, bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    return p;
+}
+
+void require(bool ok, const std::string& msg) {
+    if (!ok) throw Error{EPHX_EINVAL, msg};
+}
+
+static bool finite_all(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+static std::map<std::vector<int>, int> index_of(const int32_t* v, int n) {
+    std::map<std::vector<int>, int> m;
+    for (int i = 0; i < n; ++i) m[{v[3 * i], v[3 * i + 1], v[3 * i + 2]}] = i;
+    return m;
+}
+
+}  // namespace ephx
+
+using namespace ephx;
+
+ephx_model::~ephx_model() {
+    ws.release();
+    for (void* p : owned)
+        if (p) (void)hipFree(p);
+}
+
+extern "C" const char* ephx_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* ephx_version(void) { return "ephx 0.1 gfx950"; }
+
+extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
+    return guarded([&] {
+        require(d != nullptr && out != nullptr, "model_create: null argument");
+        *out = nullptr;
+        require(d->natoms >= 1 && 3 * d->natoms <= kMaxModes, "model_create: need 1 <= natoms <= 4");
+        require(d->nw >= 1 && d->nw <= kMaxNw, "model_create: need 1 <= nw <= 16");
+        require(d->n_re >= 1 && d->n_rp_ph >= 1 && d->n_re_g >= 1 && d->n_rp_g >= 1, "model_create: empty vector set");
+        require(d->tau && d->mass && d->re && d->h && d->rp_ph && d->ifc && d->re_g && d->rp_g && d->g,
+                "model_create: null array");
+        const int nw = d->nw, nat = d->natoms, nm = 3 * nat, nw2 = nw * nw;
+        const size_t nh = (size_t)d->n_re * nw2 * 2, nc = (size_t)d->n_rp_ph * nm * nm;
+        const size_t ng = (size_t)d->n_re_g * d->n_rp_g * nm * nw2 * 2;
+        if (!finite_all(d->h, nh) || !finite_all(d->ifc, nc) || !finite_all(d->g, ng) ||
+            !finite_all(d->tau, 3 * nat) || !finite_all(d->mass, nat) || !finite_all(&d->lattice[0][0], 9))
+            throw Error{EPHX_ENAN, "model_create: non-finite value in the model"};
+        for (int a = 0; a < nat; ++a) require(d->mass[a] > 0.0, "model_create: masses must be positive");
+        double det = d->lattice[0][0] * (d->lattice[1][1] * d->lattice[2][2] - d->lattice[1][2] * d->lattice[2][1]) -
+                     d->lattice[0][1] * (d->lattice[1][0] * d->lattice[2][2] - d->lattice[1][2] * d->lattice[2][0]) +
+                     d->lattice[0][2] * (d->lattice[1][0] * d->lattice[2][1] - d->lattice[1][1] * d->lattice[2][0]);
+        require(std::fabs(det) > 1e-12, "model_create: singular lattice");
+        // Hermiticity: H(-R) = H(R)^dag and C_kk'(-R) = C_k'k(R)^T where -R is in the set
+        {
+            auto idx = index_of(d->re, d->n_re);
+            double hmax = 0.0;
+            for (size_t i = 0; i < nh; ++i) hmax = std::fmax(hmax, std::fabs(d->h[i]));
+            for (int r = 0; r < d->n_re; ++r) {
+                auto it = idx.find({-d->re[3 * r], -d->re[3 * r + 1], -d->re[3 * r + 2]});
+                if (it == idx.end()) continue;
+                const int s = it->second;
+                const double wr = d->w_re ? d->w_re[r] : 1.0, ws_ = d->w_re ? d->w_re[s] : 1.0;
+                for (int i = 0; i < nw; ++i)
+                    for (int j = 0; j < nw; ++j) {
+                        const double* a = d->h + ((size_t)r * nw2 + i * nw + j) * 2;
+                        const double* b = d->h + ((size_t)s * nw2 + j * nw + i) * 2;
+                        if (std::fabs(wr * a[0] - ws_ * b[0]) > 1e-12 * hmax ||
+                            std::fabs(wr * a[1] + ws_ * b[1]) > 1e-12 * hmax)
+                            throw Error{EPHX_ENOTHERM, "model_create: H(-R) != H(R)^dagger"};
+                    }
+            }
+            auto idc = index_of(d->rp_ph, d->n_rp_ph);
+            double cmax = 0.0;
+            for (size_t i = 0; i < nc; ++i) cmax = std::fmax(cmax, std::fabs(d->ifc[i]));
+            for (int r = 0; r < d->n_rp_ph; ++r) {
+                auto it = idc.find({-d->rp_ph[3 * r], -d->rp_ph[3 * r + 1], -d->rp_ph[3 * r + 2]});
+                if (it == idc.end()) continue;
+                const int s = it->second;
+                const double wr = d->w_rp_ph ? d->w_rp_ph[r] : 1.0, ws_ = d->w_rp_ph ? d->w_rp_ph[s] : 1.0;
+                for (int a = 0; a < nm; ++a)
+                    for (int b = 0; b < nm; ++b)
+                        if (std::fabs(wr * d->ifc[(size_t)r * nm * nm + a * nm + b] -
+                                      ws_ * d->ifc[(size_t)s * nm * nm + b * nm + a]) > 1e-12 * cmax)
+                            throw Error{EPHX_ENOTHERM, "model_create: C(-R) != C(R)^T"};
+            }
+        }
+        if (d->polar) {
+            require(d->zstar && d->eps_inf, "model_create: polar model needs zstar and eps_inf");
+            require(d->alpha_ewald > 0 && d->gcut > 0, "model_create: polar model needs alpha_ewald, gcut > 0");
+        }
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        ephx_model* m = new ephx_model();
+        try {
+            m->device = dev;
+            m->nw = nw;
+            m->nat = nat;
+            m->nm = nm;
+            std::memcpy(m->lattice, &d->lattice[0][0], sizeof(m->lattice));
+            m->mass.assign(d->mass, d->mass + nat);
+            m->tau.assign(d->tau, d->tau + 3 * nat);
+            m->n_re = d->n_re;
+            m->n_rp_ph = d->n_rp_ph;
+            m->n_re_g = d->n_re_g;
+            m->n_rp_g = d->n_rp_g;
+            m->volume = std::fabs(det);
+            // inverse-transpose times 2 pi: reciprocal vectors b_i as rows
+            {
+                const double* L = m->lattice;
+                double inv[9];
+                inv[0] = (L[4] * L[8] - L[5] * L[7]) / det;
+                inv[1] = (L[2] * L[7] - L[1] * L[8]) / det;
+                inv[2] = (L[1] * L[5] - L[2] * L[4]) / det;
+                inv[3] = (L[5] * L[6] - L[3] * L[8]) / det;
+                inv[4] = (L[0] * L[8] - L[2] * L[6]) / det;
+                inv[5] = (L[2] * L[3] - L[0] * L[5]) / det;
+                inv[6] = (L[3] * L[7] - L[4] * L[6]) / det;
+                inv[7] = (L[1] * L[6] - L[0] * L[7]) / det;
+                inv[8] = (L[0] * L[4] - L[1] * L[3]) / det;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) m->bvec[3 * i + j] = 2.0 * kPi * inv[3 * j + i];
+            }
+            auto up = [&](const void* h, size_t bytes) {
+                void* p = dev_upload(h, bytes);
+                m->owned.push_back(p);
+                return p;
+            };
+            m->d_re = (int32_t*)up(d->re, sizeof(int32_t) * 3 * d->n_re);
+            m->d_rp_ph = (int32_t*)up(d->rp_ph, sizeof(int32_t) * 3 * d->n_rp_ph);
+            m->d_re_g = (int32_t*)up(d->re_g, sizeof(int32_t) * 3 * d->n_re_g);
+            m->d_rp_g = (int32_t*)up(d->rp_g, sizeof(int32_t) * 3 * d->n_rp_g);
+            // H(R) with weights folded in, and H(R) * (i R_a) for velocities
+            std::vector<double> h(nh), hv((size_t)d->n_re * 3 * nw2 * 2);
+            for (int r = 0; r < d->n_re; ++r) {
+                const double w = d->w_re ? d->w_re[r] : 1.0;
+                double rc[3];
+                for (int a = 0; a < 3; ++a)
+                    rc[a] = d->re[3 * r] * m->lattice[a] + d->re[3 * r + 1] * m->lattice[3 + a] + d->re[3 * r + 2] * m->lattice[6 + a];
+                for (int e = 0; e < nw2; ++e) {
+                    const double re_ = w * d->h[((size_t)r * nw2 + e) * 2], im_ = w * d->h[((size_t)r * nw2 + e) * 2 + 1];
+                    h[((size_t)r * nw2 + e) * 2] = re_;
+                    h[((size_t)r * nw2 + e) * 2 + 1] = im_;
+                    for (int a = 0; a < 3; ++a) {
+                        // (re + i im) * (i R_a) = -im R_a + i re R_a
+                        hv[(((size_t)r * 3 + a) * nw2 + e) * 2] = -im_ * rc[a];
+                        hv[(((size_t)r * 3 + a) * nw2 + e) * 2 + 1] = re_ * rc[a];
+                    }
+                }
+            }
+            m->d_h = (double*)up(h.data(), h.size() * sizeof(double));
+            {
+                std::vector<float> h32(h.begin(), h.end());
+                m->d_h32 = (float*)up(h32.data(), h32.size() * sizeof(float));
+            }
+            m->d_hvel = (double*)up(hv.data(), hv.size() * sizeof(double));
+            // C(R) / sqrt(M_k M_k') as complex, weights folded
+            std::vector<double> cm((size_t)d->n_rp_ph * nm * nm * 2, 0.0);
+            for (int r = 0; r < d->n_rp_ph; ++r) {
+                const double w = d->w_rp_ph ? d->w_rp_ph[r] : 1.0;
+                for (int a = 0; a < nm; ++a)
+                    for (int b = 0; b < nm; ++b)
+                        cm[(((size_t)r * nm + a) * nm + b) * 2] =
+                            w * d->ifc[((size_t)r * nm + a) * nm + b] / std::sqrt(d->mass[a / 3] * d->mass[b / 3]);
+            }
+            m->d_cm = (double*)up(cm.data(), cm.size() * sizeof(double));
+            // g(Re,Rp) with both weights folded
+            {
+                const size_t per = (size_t)nm * nw2 * 2;
+                std::vector<double> g(ng);
+                for (int e = 0; e < d->n_re_g; ++e)
+                    for (int p = 0; p < d->n_rp_g; ++p) {
+                        const double w = (d->w_re_g ? d->w_re_g[e] : 1.0) * (d->w_rp_g ? d->w_rp_g[p] : 1.0);
+                        const size_t o = ((size_t)e * d->n_rp_g + p) * per;
+                        for (size_t i = 0; i < per; ++i) g[o + i] = w * d->g[o + i];
+                    }
+                m->d_g = (double*)up(g.data(), ng * sizeof(double));
+            }
+            std::vector<double> minv(nm);
+            for (int a = 0; a < nm; ++a) minv[a] = 1.0 / std::sqrt(d->mass[a / 3]);
+            m->d_minv = (double*)up(minv.data(), nm * sizeof(double));
+            m->polar = d->polar != 0;
+            if (m->polar) {
+                m->d_bvec = (double*)up(m->bvec, 9 * sizeof(double));
+                m->d_tau = (double*)up(d->tau, 3 * nat * sizeof(double));
+                m->d_zstar = (double*)up(d->zstar, 9 * nat * sizeof(double));
+                m->d_eps = (double*)up(d->eps_inf, 9 * sizeof(double));
+                PolarDev& p = m->pd;
+                p.bvec = m->d_bvec;
+                p.tau = m->d_tau;
+                p.zstar = m->d_zstar;
+                p.eps = m->d_eps;
+                p.pref = 4.0 * kPi * kE2Over4PiEps0 / m->volume;
+                p.alpha = d->alpha_ewald;
+                p.gcut = d->gcut;
+                p.nat = nat;
+                // |m_i| <= (gcut + |q|) |a_i| / (2 pi), |q| <= half the sum of |b_i|
+                double bsum = 0.0;
+                for (int i = 0; i < 3; ++i)
+                    bsum += std::sqrt(m->bvec[3 * i] * m->bvec[3 * i] + m->bvec[3 * i + 1] * m->bvec[3 * i + 1] +
+                                      m->bvec[3 * i + 2] * m->bvec[3 * i + 2]);
+                for (int i = 0; i < 3; ++i) {
+                    const double al = std::sqrt(m->lattice[3 * i] * m->lattice[3 * i] + m->lattice[3 * i + 1] * m->lattice[3 * i + 1] +
+                                                m->lattice[3 * i + 2] * m->lattice[3 * i + 2]);
+                    p.mmax[i] = (int)std::ceil((d->gcut + 0.5 * bsum) * al / (2.0 * kPi)) + 1;
+                }
+            }
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+extern "C" int ephx_model_destroy(ephx_model* m) {
+    return guarded([&] {
+        if (!m) return;
+        (void)hipDeviceSynchronize();
+        delete m;
+    });
+}
+
+namespace ephx {
+
+// eps/U (and optionally velocities) for nk points; chunked.
+void bands_impl(ephx_model* m, int nk, const double* k, double* eps, double* u, double* vel, hipStream_t st,
+                const std::string& tag) {
+    const int nw = m->nw, nw2 = nw * nw;
+    const int chunk = 1 << 16;
+    for (int k0 = 0; k0 < nk; k0 += chunk) {
+        const int n = std::min(chunk, nk - k0);
+        double* hk = (double*)m->ws.get(tag + ".hk", (size_t)n * nw2 * 16);
+        phase_gemm_f64(n, nw2, m->n_re, 1, k + 3L * k0, nullptr, m->d_re, m->d_h, 0, hk, 0, st);
+        double* uu = u ? u + (size_t)k0 * nw2 * 2 : (vel ? (double*)m->ws.get(tag + ".u", (size_t)n * nw2 * 16) : nullptr);
+        eig_herm(n, nw, hk, 0, nw2, eps + (size_t)k0 * nw, uu, st);
+        if (vel) {
+            double* dh = (double*)m->ws.get(tag + ".dh", (size_t)n * 3 * nw2 * 16);
+            phase_gemm_f64(n, 3 * nw2, m->n_re, 1, k + 3L * k0, nullptr, m->d_re, m->d_hvel, 0, dh, 0, st);
+            band_velocity(n, nw, dh, uu, eps + (size_t)k0 * nw, vel + (size_t)k0 * nw * 3, st);
+        }
+    }
+}
+
+void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double* evec, hipStream_t st,
+                  const std::string& tag) {
+    const int nm = m->nm, nm2 = nm * nm;
+    const int chunk = 1 << 17;
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
+        const int n = std::min(chunk, nq - q0);
+        double* dq = (double*)m->ws.get(tag + ".dq", (size_t)n * nm2 * 16);
+        phase_gemm_f64(n, nm2, m->n_rp_ph, 1, q + 3L * q0, nullptr, m->d_rp_ph, m->d_cm, 0, dq, 0, st);
+        eig_herm(n, nm, dq, 0, nm2, omega + (size_t)q0 * nm, evec ? evec + (size_t)q0 * nm2 * 2 : nullptr, st);
+    }
+    phonon_omega((long)nq * nm, omega, st);
+}
+
+// Shared driver of ephx_gkq (rates == false) and ephx_rates (rates == true).
+void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q, int precision,
+                double omega_cut, void* g2, const ephx_params* p, const double* qw, double* gamma,
+                double* gmode, hipStream_t st) {
+    const int nw = m->nw, nm = m->nm, nw2 = nw * nw;
+    const long ngcol = (long)nm * nw2;                 // columns of the Rp contraction
+    const long nre_cols = (long)m->n_rp_g * ngcol;     // columns of the Re contraction
+    const bool f32 = precision != EPHX_FP64;
+    // phonons (and the long-range term) at every q of the call
+    double* om = (double*)m->ws.get("drv.omega", (size_t)nq * nm * 8);
+    double* ev = (double*)m->ws.get("drv.evec", (size_t)nq * nm * nm * 16);
+    phonons_impl(m, nq, q, om, ev, st, "drv");
+    double* lr = nullptr;
+    if (m->polar) {
+        lr = (double*)m->ws.get("drv.lr", (size_t)nq * nm * 16);
+        frohlich(nq, q, m->pd, lr, st);
+    }
+    // batch sizes: Bk k points x Qc q points per inner step
+    const int bk = std::max(1, std::min(nk, std::max(1, (int)(((size_t)3 << 30) / (nre_cols * 16 * 2)))));
+    const int bk_eff = std::min(bk, 16);
+    const long pairs_target = 1L << 19;
+    const int qc = (int)std::max(64L, std::min((long)nq, pairs_target / bk_eff));
+    const int kp = ((m->n_rp_g + 31) / 32) * 32;
+
+    double* ek = (double*)m->ws.get("drv.ek", (size_t)bk_eff * nw * 8);
+    double* uk = (double*)m->ws.get("drv.uk", (size_t)bk_eff * nw2 * 16);
+    double* gk = (double*)m->ws.get("drv.gk", (size_t)bk_eff * nre_cols * 16);
+    double* gp = (double*)m->ws.get("drv.gp", (size_t)bk_eff * nre_cols * 16);
+    float* gp32 = nullptr;
+    uint16_t* gpbf = nullptr;
+    if (precision == EPHX_FP32) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
+    const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+    if (nsplit) gpbf = (uint16_t*)m->ws.get("drv.gpbf", (size_t)bk_eff * 2 * nsplit * ngcol * kp * 2);
+    const size_t npair = (size_t)bk_eff * qc;
+    void* hkq = m->ws.get("drv.hkq", npair * nw2 * (f32 ? 8 : 16));
+    double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
+    double* ukq = (double*)m->ws.get("drv.ukq", npair * nw2 * 16);
+    void* gw = m->ws.get("drv.gw", npair * ngcol * (f32 ? 8 : 16));
+    const int nblk = eph_epilogue_blocks(qc);
+    double* partial = nullptr;
+    double* acc = nullptr;
+    if (gamma) {
+        partial = (double*)m->ws.get("drv.partial", (size_t)bk_eff * nblk * nw * nm * 8);
+        acc = (double*)m->ws.get("drv.acc", (size_t)bk_eff * nw * nm * 8);
+    }
+    for (int k0 = 0; k0 < nk; k0 += bk_eff) {
+        const int nb = std::min(bk_eff, nk - k0);
+        const double* kb = k + 3L * k0;
+        bands_impl(m, nb, kb, ek, uk, nullptr, st, "drv.bk");
+        // Re contraction (FP64, amortised over all q), then U(k) on the right
+        phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+        apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
+        if (precision == EPHX_FP32) convert_f64_f32((long)nb * nre_cols * 2, gp, gp32, st);
+        if (nsplit) split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
+        if (acc) hip_check(hipMemsetAsync(acc, 0, (size_t)nb * nw * nm * 8, st), "hipMemsetAsync");
+        for (int q0 = 0; q0 < nq; q0 += qc) {
+            const int nqc = std::min(qc, nq - q0);
+            const double* qb = q + 3L * q0;
+            // H(k+q) for every pair, then its eigenpairs in FP64
+            if (f32)
+                phase_gemm_f32(nqc, nw2, m->n_re, nb, qb, kb, m->d_re, m->d_h32, 0, (float*)hkq, (long)nqc * nw2, st);
+            else
+                phase_gemm_f64(nqc, nw2, m->n_re, nb, qb, kb, m->d_re, m->d_h, 0, (double*)hkq, (long)nqc * nw2, st);
+            eig_herm(nb * nqc, nw, hkq, f32 ? 1 : 0, nw2, ekq, ukq, st);
+            // Rp contraction per k
+            if (precision == EPHX_FP64)
+                phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, (double*)gw,
+                               (long)nqc * ngcol, st);
+            else if (precision == EPHX_FP32)
+                phase_gemm_f32(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp32, nre_cols, (float*)gw,
+                               (long)nqc * ngcol, st);
+            else
+                phase_gemm_bf16(nsplit, nqc, (int)ngcol, m->n_rp_g, kp, nb, qb, nullptr, m->d_rp_g, gpbf,
+                                2L * nsplit * ngcol * kp, (float*)gw, (long)nqc * ngcol, st);
+            EphEpilogue e{};
+            e.nkb = nb;
+            e.nq = nqc;
+            e.q_off = q0;
+            e.nw = nw;
+            e.nm = nm;
+            e.gw = gw;
+            e.ukq = ukq;
+            e.ekq = ekq;
+            e.ek = ek;
+            e.uk = uk;
+            e.omega = om;
+            e.evec = ev;
+            e.lr = lr;
+            e.minv = m->d_minv;
+            e.omega_cut = omega_cut;
+            if (!gamma) {
+                e.g2 = g2;
+                e.nq_total = nq;
+                e.k_off = k0;
+                eph_epilogue_g2(e, f32 ? 1 : 0, st);
+            } else {
+                e.temp = p->temp;
+                e.mu = p->mu;
+                e.sigma = p->sigma;
+                e.qw = qw;
+                e.uniform_w = 1.0 / nq;
+                e.partial = partial;
+                e.nblk = eph_epilogue_blocks(nqc);
+                eph_epilogue_rates(e, f32 ? 1 : 0, st);
+                rates_reduce(nb, e.nblk, nw, nm, partial, acc, st);
+            }
+        }
+        if (gamma)
+            rates_finish(nb, nw, nm, acc, gamma + (size_t)k0 * nw, gmode ? gmode + (size_t)k0 * nw * nm : nullptr, st);
+    }
+}
+
+}  // namespace ephx
+
+extern "C" int ephx_bands(ephx_model* m, int nk, const double* k_red, double* eps, double* u, double* vel,
+                          void* stream) {
+    return guarded([&] {
+        require(m != nullptr, "bands: null model");
+        require(nk >= 0, "bands: nk < 0");
+        if (nk == 0) return;
+        require(k_red && eps, "bands: null array");
+        bands_impl(m, nk, k_red, eps, u, vel, (hipStream_t)stream, "bands");
+    });
+}
+
+extern "C" int ephx_phonons(ephx_model* m, int nq, const double* q_red, double* omega, double* evec, void* stream) {
+    return guarded([&] {
+        require(m != nullptr, "phonons: null model");
+        require(nq >= 0, "phonons: nq < 0");
+        if (nq == 0) return;
+        require(q_red && omega, "phonons: null array");
+        phonons_impl(m, nq, q_red, omega, evec, (hipStream_t)stream, "phonons");
+    });
+}
+
+static void check_precision(int precision) {
+    require(precision == EPHX_FP64 || precision == EPHX_FP32 || precision == EPHX_BF16X3 ||
+                precision == EPHX_BF16X6,
+            "unknown precision");
+}
+
+extern "C" int ephx_gkq(ephx_model* m, int nk, const double* k_red, int nq, const double* q_red, int precision,
+                        double omega_cut, void* g2, void* stream) {
+    return guarded([&] {
+        require(m != nullptr, "gkq: null model");
+        require(nk >= 0 && nq >= 0, "gkq: negative size");
+        if (nk == 0 || nq == 0) return;
+        require(k_red && q_red && g2, "gkq: null array");
+        require(std::isfinite(omega_cut), "gkq: omega_cut not finite");
+        check_precision(precision);
+        eph_driver(m, nk, k_red, nq, q_red, precision, omega_cut, g2, nullptr, nullptr, nullptr, nullptr,
+                   (hipStream_t)stream);
+    });
+}
+
+extern "C" int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
+                          const double* q_red, const double* q_w, int precision, double* gamma, double* gamma_mode,
+                          void* stream) {
+    return guarded([&] {
+        require(m != nullptr && p != nullptr, "rates: null argument");
+        require(nk >= 0 && nq >= 0, "rates: negative size");
+        require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
+                "rates: need temp > 0, sigma > 0, finite mu and omega_cut");
+        if (nk == 0) return;
+        require(k_red && gamma, "rates: null array");
+        check_precision(precision);
+        if (nq == 0) {
+            hip_check(hipMemsetAsync(gamma, 0, (size_t)nk * m->nw * 8, (hipStream_t)stream), "hipMemsetAsync");
+            if (gamma_mode)
+                hip_check(hipMemsetAsync(gamma_mode, 0, (size_t)nk * m->nw * m->nm * 8, (hipStream_t)stream),
+                          "hipMemsetAsync");
+            return;
+        }
+        require(q_red != nullptr, "rates: null q array");
+        eph_driver(m, nk, k_red, nq, q_red, precision, p->omega_cut, nullptr, p, q_w, gamma, gamma_mode,
+                   (hipStream_t)stream);
+    });
+}

@@ -1,0 +1,178 @@
+// Internal declarations shared by the host API and the kernel files of the
+// electron-phonon library.  Not part of the public ABI (see include/ephx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace ephx {
+
+// Physical constants (CODATA 2018); energies in eV, time in fs.
+constexpr double kHbarEvFs = 0.6582119569;              // hbar, eV*fs
+constexpr double kBoltzEv = 8.617333262e-5;             // k_B, eV/K
+constexpr double kHbar2AmuA2 = 0.004180159280496722;    // hbar^2/(amu*A^2), eV
+constexpr double kE2Over4PiEps0 = 14.3996454784;        // e^2/(4 pi eps0), eV*A
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kDegTol = 1e-4;                        // degenerate-group threshold, eV
+
+constexpr int kMaxNw = 16;      // Wannier functions handled by the per-pair kernels
+constexpr int kMaxModes = 12;   // 3*natoms handled by the per-pair kernels
+constexpr int kEigMax = 8;      // largest matrix of the wavefront Jacobi eigensolver
+
+// Thrown inside the host code, converted to an error code at the ABI edge.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// ------------------------------------------------------------------ launchers
+// Phase contractions  C[z][m][n] = sum_r exp(2 pi i (x_m + x0_z) . n_r) B[z][r][n]
+// (complex interleaved).  x: [M][3] reduced coordinates (device), x0: [Z][3] or
+// nullptr, nvec: [K][3] int32 (device), B stride sB and C stride sC in complex
+// elements per z.
+void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x0,
+                    const int32_t* nvec, const double* B, long sB, double* C, long sC,
+                    hipStream_t st);
+void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0,
+                    const int32_t* nvec, const float* B, long sB, float* C, long sC,
+                    hipStream_t st);
+// Split-bf16 contraction: B given as 2*nsplit bf16 planes [Z][2*nsplit][N][Kp]
+// (re parts then im parts), Kp % 32 == 0; nsplit 2 = BF16x3, 3 = BF16x6.
+void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
+                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC,
+                     hipStream_t st);
+// Split complex double B[Z][K][N] into those planes.
+void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
+                    hipStream_t st);
+
+// Hermitian eigensolver, one wavefront per n x n matrix (n <= kEigMax), FP64.
+// A: [batch] matrices of n*n complex (stride strideA complex elements),
+// float (a_f32 = 1) or double.  evals [batch][n] ascending; evecs [batch][n][n]
+// complex double (column j = eigenvector j) or nullptr.
+void eig_herm(int batch, int n, const void* A, int a_f32, long strideA, double* evals,
+              double* evecs, hipStream_t st);
+
+// omega_nu = sign(lam) sqrt(|hbar^2/amu/A^2 * lam|) in place.
+void phonon_omega(long count, double* lam, hipStream_t st);
+
+// g'(z)[p][x][i][n] = sum_j g(z)[p][x][i][j] U(z)[j][n]; complex double in and out.
+void apply_u_right(int Z, int nrp, int nm, int nw, const double* g, const double* u,
+                   double* out, hipStream_t st);
+void convert_f64_f32(long count, const double* in, float* out, hipStream_t st);
+
+struct EphEpilogue {
+    int nkb;            // k points in the batch (grid.y)
+    int nq;             // q points in the chunk
+    int q_off;          // global index of the first q of the chunk
+    int nw, nm;
+    const void* gw;     // [nkb][nq][nm][nw][nw] complex (float or double)
+    const double* ukq;  // [nkb][nq][nw][nw] complex
+    const double* ekq;  // [nkb][nq][nw]
+    const double* ek;   // [nkb][nw]
+    const double* uk;   // [nkb][nw][nw] complex (polar term)
+    const double* omega;  // [nq_total][nm]
+    const double* evec;   // [nq_total][nm][nm] complex
+    const double* lr;     // [nq_total][nm] complex long-range term, or nullptr
+    const double* minv;   // [nm] 1/sqrt(M_kappa)
+    double omega_cut;
+    // |g|^2 output mode
+    void* g2;            // [nk_total][nq_total][nm][nw][nw]
+    long nq_total;
+    int k_off;
+    // rates mode
+    double temp, mu, sigma;
+    const double* qw;    // [nq_total] or nullptr (then uniform_w)
+    double uniform_w;
+    double* partial;     // [nkb][nblk][nw][nm]
+    int nblk;
+};
+void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st);
+void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st);
+int eph_epilogue_blocks(int nq);
+// acc[z][n][nu] += sum_b partial[z][b][n][nu]
+void rates_reduce(int nkb, int nblk, int nw, int nm, const double* partial, double* acc,
+                  hipStream_t st);
+void rates_finish(int nkb, int nw, int nm, const double* acc, double* gamma, double* gamma_mode,
+                  hipStream_t st);
+
+// Froehlich term: lr[q][3*kappa+a] (complex double) for q in [nq][3].
+struct PolarDev {
+    const double* bvec;   // [3][3] rows b_i
+    const double* tau;    // [nat][3]
+    const double* zstar;  // [nat][3][3]
+    const double* eps;    // [3][3]
+    double pref, alpha, gcut;
+    int nat, mmax[3];
+};
+void frohlich(int nq, const double* q, const PolarDev& p, double* lr, hipStream_t st);
+
+// Band velocities from H(k) derivatives: dh [nk][3][nw][nw] complex, u, eps -> vel [nk][nw][3]
+void band_velocity(int nk, int nw, const double* dh, const double* u, const double* eps,
+                   double* vel, hipStream_t st);
+
+// ---------------------------------------------------------------- BTE side
+struct PairEpilogue {
+    int ns_chunk;         // sources in this chunk (grid.y)
+    int s_off;            // global index of first source
+    int S;                // states (targets)
+    int nw, nm;
+    const void* gw;       // [ns_chunk][S][nm][nw] complex (float or double)
+    const double* ut;     // [S][nw][nw] complex, U(k_t)
+    const int32_t* band;  // [S]
+    const int32_t* kc;    // [S][3] grid coordinates
+    int n1, n2, n3;
+    const double* omega;  // [Ngrid][nm]
+    const double* evec;   // [Ngrid][nm][nm] complex
+    const double* lr;     // [Ngrid][nm] complex or nullptr
+    const double* us;     // [S][nw][nw] complex, U(k_s) (polar term)
+    const double* minv;
+    double omega_cut;
+    float* g2raw;         // [nm][S][S]
+};
+void pair_epilogue(const PairEpilogue& e, int f32, hipStream_t st);
+// g'(s)[p][x][i] = sum_j g(s)[p][x][i][j] U(k_s)[j][band_s]
+void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const double* us,
+                    const int32_t* band, double* out, hipStream_t st);
+void table_symmetrise(int nm, int S, float* g2, hipStream_t st);
+void gather_omega_pairs(int S, int nm, const int32_t* kc, int n1, int n2, int n3,
+                        const double* omega, float* om_pairs, hipStream_t st);
+void build_collision_matrix(int S, int nm, const float* g2, const float* om_pairs,
+                            const double* eps, double temp, double sigma, double omega_cut,
+                            const double* mode_scale, float* pmat, float* pmode, hipStream_t st);
+void build_transport_matrix(int S, int nm, const float* g2, const float* om_pairs,
+                            const double* eps, double temp, double mu, double sigma,
+                            double omega_cut, float* wmat, hipStream_t st);
+
+// Streaming pass over a dense S x S float matrix P:
+//   rowp[a][ct][s] = sum_{t in col tile ct} P[s][t] x_a[t]      (a < na)
+//   colp[b][rt][t] = sum_{s in row tile rt} P[s][t] y_b[s]      (b < nb)
+struct StreamPlan {
+    int S;
+    int n_rt, n_ct;       // row and column tiles
+};
+StreamPlan stream_plan(int S);
+void stream_pass(const StreamPlan& pl, const float* P, int na, const double* const* x, int nb,
+                 const double* const* y, double* rowp, double* colp, hipStream_t st);
+// I_s = -c [ f_s R_s - (1-f_s) C_s ] with R, C the reduced partials; optional
+// RK4 stage update: acc += w_acc * dt * I ; f_stage = f_base + a_next * dt * I.
+struct CollisionFinish {
+    int S;
+    int n_rt, n_ct;
+    const double* rowp;   // [n_ct][S]
+    const double* colp;   // [n_rt][S]
+    const double* f;      // occupations the integral is evaluated at
+    double c;             // (2 pi/hbar)/N_q
+    double* i_out;        // I (may be nullptr)
+    // stage update (enabled when acc != nullptr)
+    double* acc;
+    double w_acc;         // weight of this stage in the RK4 combination (times dt)
+    const double* f_base;
+    double a_next;        // f_next = f_base + a_next * I
+    double* f_next;
+};
+void collision_finish(const CollisionFinish& cf, hipStream_t st);
+void axpy_copy(int S, const double* x, double a, const double* y, double* out, hipStream_t st);
+
+}  // namespace ephx

@@ -1,0 +1,358 @@
+// Phase-factor Fourier contractions on MFMA (gfx950).
+//
+//   C[z][m][n] = sum_r exp(2 pi i (x_m + x0_z) . n_r) B[z][r][n]        (complex)
+//
+// This single contraction is every Fourier sum of the method: H(k) (Eq.
+// wannier_3), D(q) (Eq. IFC2), the Re sum g(k,Rp) and the Rp sum g^W(k,q)
+// of Eq. eph_mat_wann2, and H(k+q) per (k,q) pair.  The phase matrix A is
+// generated in registers: the argument t = x.n is formed in FP64 and reduced
+// to [-1/2, 1/2) before sin/cos, so A is never read from memory.
+//
+// Tiling: a 256-thread workgroup owns a 64-row x (16*CB)-column output tile;
+// wave w computes rows 16w..16w+15 with 16x16 MFMA blocks.  B is staged
+// through LDS one K chunk at a time.  Complex products use four real MFMAs:
+//   Cre += Are*Bre - Aim*Bim ,  Cim += Are*Bim + Aim*Bre.
+// MFMA 16x16xK operand layout: lane l holds A[l%16][k-group l/16] and
+// B[k-group l/16][l%16].  Accumulator element v of lane l is C[r][l%16] with
+// r = 4*(l/16) + v for the f32 and bf16 instructions but r = l/16 + 4*v for
+// v_mfma_f64_16x16x4f64 (measured on gfx950).
+#include "internal.h"
+
+namespace ephx {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ double reduced_arg(double a, double b, double c, const int32_t* n) {
+    double t = fma(a, (double)n[0], fma(b, (double)n[1], c * (double)n[2]));
+    return t - rint(t);
+}
+
+__device__ __forceinline__ void phase_of(double r, double& c, double& s) { sincospi(2.0 * r, &s, &c); }
+__device__ __forceinline__ void phase_of(double r, float& c, float& s) {
+    sincospif((float)(2.0 * r), &s, &c);
+}
+
+__device__ __forceinline__ dbl4 mfma(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct AccOf;
+template <> struct AccOf<double> {
+    typedef dbl4 type;
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct AccOf<float> {
+    typedef flt4 type;
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int kBM = 64;
+constexpr int kKC = 16;
+
+template <typename T, int CB>
+__global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const double* __restrict__ x,
+                                                    const double* __restrict__ x0,
+                                                    const int32_t* __restrict__ nvec,
+                                                    const T* __restrict__ B, long sB,
+                                                    T* __restrict__ C, long sC) {
+    typedef typename AccOf<T>::type acc_t;
+    constexpr int BN = 16 * CB;
+    __shared__ T bs[kKC][BN][2];
+    __shared__ int32_t ns[kKC][3];
+    const int z = blockIdx.z;
+    const int row0 = blockIdx.y * kBM;
+    const int col0 = blockIdx.x * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const T* bz = B + (long)z * sB * 2;
+    T* cz = C + (long)z * sC * 2;
+
+    const int arow = row0 + wave * 16 + li;
+    const bool rowok = arow < M;
+    double xa = 0.0, xb = 0.0, xc = 0.0;
+    if (rowok) {
+        xa = x[3 * arow];
+        xb = x[3 * arow + 1];
+        xc = x[3 * arow + 2];
+    }
+    if (x0 != nullptr) {
+        xa += x0[3 * z];
+        xb += x0[3 * z + 1];
+        xc += x0[3 * z + 2];
+    }
+
+    acc_t are[CB], aim[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        are[cb] = acc_t{0, 0, 0, 0};
+        aim[cb] = acc_t{0, 0, 0, 0};
+    }
+
+    for (int kc = 0; kc < K; kc += kKC) {
+        for (int e = tid; e < kKC * BN; e += 256) {
+            const int kk = e / BN, nn = e % BN;
+            const int r = kc + kk, col = col0 + nn;
+            T re = 0, im = 0;
+            if (r < K && col < N) {
+                const long off = ((long)r * N + col) * 2;
+                re = bz[off];
+                im = bz[off + 1];
+            }
+            bs[kk][nn][0] = re;
+            bs[kk][nn][1] = im;
+        }
+        if (tid < kKC * 3) {
+            const int kk = tid / 3, d = tid % 3;
+            ns[kk][d] = (kc + kk < K) ? nvec[3 * (kc + kk) + d] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kKC / 4; ++s) {
+            const int kk = 4 * s + lk;
+            T pc = 0, ps = 0;
+            if (rowok && kc + kk < K) phase_of(reduced_arg(xa, xb, xc, ns[kk]), pc, ps);
+            const T nps = -ps;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const T bre = bs[kk][cb * 16 + li][0];
+                const T bim = bs[kk][cb * 16 + li][1];
+                are[cb] = mfma(pc, bre, are[cb]);
+                are[cb] = mfma(nps, bim, are[cb]);
+                aim[cb] = mfma(pc, bim, aim[cb]);
+                aim[cb] = mfma(ps, bre, aim[cb]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = col0 + cb * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + wave * 16 + AccOf<T>::row(lk, v);
+            if (row < M && col < N) {
+                const long off = ((long)row * N + col) * 2;
+                cz[off] = are[cb][v];
+                cz[off + 1] = aim[cb][v];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ split-bf16 variants
+__device__ __forceinline__ unsigned short bf16_bits_rn(float f) {
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// split x into NS bf16 parts (round to nearest even each time): x ~ p0 + p1 (+ p2)
+template <int NS>
+__device__ __forceinline__ void split_n(float x, unsigned short* part) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        part[i] = bf16_bits_rn(x);
+        x -= bf16_to_float(part[i]);
+    }
+}
+
+__device__ __forceinline__ flt4 mfma_bf(const u16x8& a, const u16x8& b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+constexpr int kBK = 32;     // K per MFMA step
+constexpr int kPadK = 8;    // LDS row padding (bf16 elements)
+
+// NS = 2: "BF16x3" (products p_i q_j with i + j <= 1, three per real product);
+// NS = 3: "BF16x6" (i + j <= 2, six per real product).  Accumulation in FP32;
+// the smallest products are issued first.
+template <int CB, int NS>
+__global__ __launch_bounds__(256) void k_phase_gemm_bf16(int M, int N, int K, int Kp,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ x0,
+                                                         const int32_t* __restrict__ nvec,
+                                                         const uint16_t* __restrict__ Bs, long sB,
+                                                         float* __restrict__ C, long sC) {
+    constexpr int BN = 16 * CB;
+    constexpr int NP = 2 * NS;   // planes: re parts 0..NS-1, im parts NS..2NS-1
+    __shared__ __attribute__((aligned(16))) uint16_t bsh[NP][BN][kBK + kPadK];
+    __shared__ int32_t ns[kBK][3];
+    const int z = blockIdx.z;
+    const int row0 = blockIdx.y * kBM;
+    const int col0 = blockIdx.x * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const uint16_t* bz = Bs + (long)z * sB;
+    float* cz = C + (long)z * sC * 2;
+
+    const int arow = row0 + wave * 16 + li;
+    const bool rowok = arow < M;
+    double xa = 0.0, xb = 0.0, xc = 0.0;
+    if (rowok) {
+        xa = x[3 * arow];
+        xb = x[3 * arow + 1];
+        xc = x[3 * arow + 2];
+    }
+    if (x0 != nullptr) {
+        xa += x0[3 * z];
+        xb += x0[3 * z + 1];
+        xc += x0[3 * z + 2];
+    }
+    flt4 are[CB], aim[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        are[cb] = flt4{0, 0, 0, 0};
+        aim[cb] = flt4{0, 0, 0, 0};
+    }
+    for (int kc = 0; kc < Kp; kc += kBK) {
+        // stage the planes of a [BN][32] chunk: 16-byte loads along K
+        for (int e = tid; e < NP * BN * (kBK / 8); e += 256) {
+            const int seg = e % (kBK / 8);
+            const int nn = (e / (kBK / 8)) % BN;
+            const int pl = e / ((kBK / 8) * BN);
+            const int col = col0 + nn;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (col < N) v = *reinterpret_cast<const uint4*>(bz + ((long)pl * N + col) * Kp + kc + seg * 8);
+            *reinterpret_cast<uint4*>(&bsh[pl][nn][seg * 8]) = v;
+        }
+        if (tid < kBK * 3) {
+            const int kk = tid / 3, d = tid % 3;
+            ns[kk][d] = (kc + kk < K) ? nvec[3 * (kc + kk) + d] : 0;
+        }
+        __syncthreads();
+        u16x8 ar[NS], ai[NS], nai[NS];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int kk = 8 * lk + j;
+            float pc = 0.f, ps = 0.f;
+            if (rowok && kc + kk < K) phase_of(reduced_arg(xa, xb, xc, ns[kk]), pc, ps);
+            unsigned short pr[NS], pi[NS];
+            split_n<NS>(pc, pr);
+            split_n<NS>(ps, pi);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                ar[t][j] = pr[t];
+                ai[t][j] = pi[t];
+                nai[t][j] = pi[t] ^ 0x8000u;
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int nn = cb * 16 + li;
+            u16x8 br[NS], bi[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                br[t] = *reinterpret_cast<const u16x8*>(&bsh[t][nn][8 * lk]);
+                bi[t] = *reinterpret_cast<const u16x8*>(&bsh[NS + t][nn][8 * lk]);
+            }
+#pragma unroll
+            for (int ord = NS - 1; ord >= 0; --ord) {
+#pragma unroll
+                for (int i = 0; i <= ord; ++i) {
+                    const int j = ord - i;
+                    are[cb] = mfma_bf(ar[i], br[j], are[cb]);
+                    are[cb] = mfma_bf(nai[i], bi[j], are[cb]);
+                    aim[cb] = mfma_bf(ar[i], bi[j], aim[cb]);
+                    aim[cb] = mfma_bf(ai[i], br[j], aim[cb]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = col0 + cb * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + wave * 16 + AccOf<float>::row(lk, v);
+            if (row < M && col < N) {
+                const long off = ((long)row * N + col) * 2;
+                cz[off] = are[cb][v];
+                cz[off + 1] = aim[cb][v];
+            }
+        }
+    }
+}
+
+template <int NS>
+__global__ void k_split_bf16(int K, int N, int Kp, const double* __restrict__ B, uint16_t* __restrict__ out) {
+    // one thread per (z, n, k) output element, k fastest; planes re_0..re_{NS-1}, im_0..
+    const int z = blockIdx.z;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)N * Kp) return;
+    const int n = (int)(idx / Kp), k = (int)(idx % Kp);
+    float re = 0.f, im = 0.f;
+    if (k < K) {
+        const long off = ((long)z * K * N + (long)k * N + n) * 2;
+        re = (float)B[off];
+        im = (float)B[off + 1];
+    }
+    unsigned short pr[NS], pi[NS];
+    split_n<NS>(re, pr);
+    split_n<NS>(im, pi);
+    uint16_t* oz = out + (long)z * 2 * NS * N * Kp;
+    for (int t = 0; t < NS; ++t) {
+        oz[((long)t * N + n) * Kp + k] = pr[t];
+        oz[((long)(NS + t) * N + n) * Kp + k] = pi[t];
+    }
+}
+
+inline void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+}  // namespace
+
+void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
+                    const double* B, long sB, double* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    check_launch("phase_gemm_f64");
+}
+
+void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
+                    const float* B, long sB, float* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    hipLaunchKernelGGL((k_phase_gemm<float, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    check_launch("phase_gemm_f32");
+}
+
+void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
+                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    if (Kp % kBK != 0 || Kp < K) throw Error{-1, "phase_gemm_bf16: bad Kp"};
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    if (nsplit == 2)
+        hipLaunchKernelGGL((k_phase_gemm_bf16<4, 2>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC);
+    else if (nsplit == 3)
+        hipLaunchKernelGGL((k_phase_gemm_bf16<4, 3>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC);
+    else
+        throw Error{-1, "phase_gemm_bf16: nsplit must be 2 or 3"};
+    check_launch("phase_gemm_bf16");
+}
+
+void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out, hipStream_t st) {
+    const long total = (long)N * Kp;
+    dim3 grid((unsigned)((total + 255) / 256), 1, Z);
+    if (nsplit == 2)
+        hipLaunchKernelGGL(k_split_bf16<2>, grid, dim3(256), 0, st, K, N, Kp, B, out);
+    else
+        hipLaunchKernelGGL(k_split_bf16<3>, grid, dim3(256), 0, st, K, N, Kp, B, out);
+    check_launch("split_bf16");
+}
+
+}  // namespace ephx
