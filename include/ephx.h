@@ -27,9 +27,9 @@
  *    documented (those calls synchronise the stream before returning).
  *  - Calls on one handle must not overlap in time (they share work buffers);
  *    calls on distinct handles are independent.
- *  - Precision: EPHX_FP64 (all steps FP64), EPHX_FP32 (Fourier contractions,
- *    rotation and projection in FP32, FP32 Fourier sum of H(k+q); phases
- *    reduced in FP64; eigensolves, eps, omega and rate sums in FP64), or
+ *  - Precision: EPHX_FP64 (all steps FP64), EPHX_FP32 (Rp contraction of g,
+ *    band rotation and mode projection in FP32; phases reduced in FP64; the Re
+ *    contraction, H(k+q), eigensolves, eps, omega and rate sums in FP64), or
  *    EPHX_BF16X3 (as FP32, but the Rp contraction of g runs on bf16 MFMA with
  *    each FP32 operand split into two bf16 parts and three products kept), or
  *    EPHX_BF16X6 (three bf16 parts per operand, six products kept).
@@ -177,8 +177,9 @@ int ephx_table_create(ephx_model* m, const int n_grid[3], int n_states, const in
                       const int32_t* band, int precision, double omega_cut, ephx_table** out,
                       void* stream);
 int ephx_table_destroy(ephx_table* t);
-/* Copies G (device float [3nat][S][S]) and state energies (device double [S]). */
-int ephx_table_g2(ephx_table* t, float* g2, double* eps, void* stream);
+/* Copies G (device [3nat][S][S]: double for an EPHX_FP64 table, float
+ * otherwise; or NULL) and the state energies (device double [S], or NULL). */
+int ephx_table_g2(ephx_table* t, void* g2, double* eps, void* stream);
 
 /* Collision integral of Eq. e_ph_scattering on the table's states:
  *   I_s = -(2 pi/hbar)(1/N_q) sum_{t,nu} s_nu G[nu][s][t] [delta(e_s - hw - e_t) F_em + delta(e_s + hw - e_t) F_abs]
@@ -222,6 +223,17 @@ int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, int n_steps
  * mob_out (device double [3][3], cm^2/(V s)) unless NULL. */
 int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
                   double* f_out, double* tau_out, double* mob_out, void* stream);
+
+/* Stage timers (instrumentation, not part of the method).  While enabled,
+ * the library brackets each launch of its main kernels with HIP events on the
+ * launch stream, keyed by stage name: "re_contraction", "hkq_fourier",
+ * "eig_hkq", "rp_contraction", "epilogue", "phonons", "bands",
+ * "table_pairs", "collision_stream", "collision_finish".
+ * ephx_timer_get synchronises the recorded events and returns the number of
+ * launches and their summed duration in ms (zeros for an unknown stage). */
+int ephx_timer_enable(int on);
+int ephx_timer_reset(void);
+int ephx_timer_get(const char* stage, int* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

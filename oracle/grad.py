@@ -45,4 +45,4 @@ def dynamics_grad(f0, eps, g2s, omega, *, dt, n_steps, e_ref, **coll_kw):
     s = torch.ones(g2s.shape[-1], dtype=torch.float64, requires_grad=True)
     e = dynamics_mean_energy(f0t, eps, g2s, omega, s, dt=dt, n_steps=n_steps, e_ref=e_ref, **coll_kw)
     e.backward()
-    return float(e), f0t.grad, s.grad
+    return float(e.detach()), f0t.grad, s.grad

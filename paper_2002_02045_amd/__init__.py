@@ -2,19 +2,20 @@
 (Zhou et al., arXiv:2002.02045): Wannier interpolation of g_mn,nu(k,q) and the
 Boltzmann-equation scattering work built on it, behind the C ABI of
 include/ephx.h.  This package is the thin Python binding; see ``api``.
+
+The compiled library is loaded on first use of any public name (so that
+``paper_2002_02045_amd.build`` can run before it exists); using the binding
+without a built libephx.so raises ImportError.
 """
-from .api import (  # noqa: F401
-    FP32,
-    FP64,
-    BF16X3,
-    BF16X6,
-    EphxError,
-    Model,
-    PairTable,
-    Params,
-    bands,
-    gkq,
-    grid_states,
-    phonons,
-    rates,
-)
+_PUBLIC = ("FP32", "FP64", "BF16X3", "BF16X6", "EphxError", "Model", "PairTable", "Params",
+           "bands", "gkq", "grid_states", "phonons", "rates", "timer_enable", "timer_reset", "timer_get")
+
+
+def __getattr__(name):
+    if name in _PUBLIC:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)
+
+
+__all__ = list(_PUBLIC)

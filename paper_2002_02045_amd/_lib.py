@@ -76,6 +76,9 @@ _SIGS = {
     "ephx_collision_vjp": ([_P, _P, _P, _P, _P, _P], _I),
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),
     "ephx_mobility": ([_P, _P, _P, _I, _P, _P, _P, _P], _I),
+    "ephx_timer_enable": ([_I], _I),
+    "ephx_timer_reset": ([], _I),
+    "ephx_timer_get": ([C.c_char_p, _P, _P], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -103,3 +106,19 @@ def ptr(t):
 
 def host_ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def timer_enable(on=True):
+    check(lib.ephx_timer_enable(1 if on else 0))
+
+
+def timer_reset():
+    check(lib.ephx_timer_reset())
+
+
+def timer_get(stage):
+    """(launches, total_ms) of a stage; synchronises its events."""
+    n = C.c_int(0)
+    ms = C.c_double(0.0)
+    check(lib.ephx_timer_get(stage.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value

@@ -8,7 +8,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BF16X3, BF16X6, FP32, FP64, EphxError, check, host_ptr, lib, ptr, stream_ptr  # noqa: F401
+from ._lib import (BF16X3, BF16X6, FP32, FP64, EphxError, check, host_ptr, lib, ptr, stream_ptr,  # noqa: F401
+                   timer_enable, timer_get, timer_reset)
 
 F64 = torch.float64
 
@@ -169,6 +170,7 @@ class PairTable:
         self.model = model
         self.S = len(k_idx)
         self.nmodes = model.nmodes
+        self.precision = _prec(precision)
         n3 = (C.c_int * 3)(*[int(x) for x in np.broadcast_to(np.asarray(n_grid), (3,))])
         self._k = np.ascontiguousarray(k_idx, dtype=np.int32)
         self._b = np.ascontiguousarray(band, dtype=np.int32)
@@ -188,7 +190,8 @@ class PairTable:
             pass
 
     def g2(self):
-        g = torch.empty((self.nmodes, self.S, self.S), dtype=torch.float32, device="cuda")
+        dt = F64 if self.precision == FP64 else torch.float32
+        g = torch.empty((self.nmodes, self.S, self.S), dtype=dt, device="cuda")
         e = torch.empty(self.S, dtype=F64, device="cuda")
         check(lib.ephx_table_g2(self._h, ptr(g), ptr(e), stream_ptr()))
         return g, e

@@ -29,6 +29,16 @@ void hip_check(hipError_t e, const char* what);
 void* dev_upload(const void* host, size_t bytes);
 void require(bool ok, const std::string& msg);
 
+// Stage timers: HIP events around launches while enabled.
+struct StageTimer {
+    const char* name;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    StageTimer(const char* n, hipStream_t s);
+    void stop();   // records the end event (idempotent)
+    ~StageTimer() { stop(); }
+};
+
 template <class F>
 int guarded(F&& f) {
     try {
@@ -59,7 +69,6 @@ struct ephx_model {
     int n_re = 0, n_rp_ph = 0, n_re_g = 0, n_rp_g = 0;
     int32_t *d_re = nullptr, *d_rp_ph = nullptr, *d_re_g = nullptr, *d_rp_g = nullptr;
     double* d_h = nullptr;       // [n_re][nw*nw] complex, weights folded
-    float* d_h32 = nullptr;      // FP32 copy (created on first reduced-precision call)
     double* d_hvel = nullptr;    // [n_re][3][nw*nw] complex, H(R) * (i R_a)
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex

@@ -1,37 +1,541 @@
-// BTE entry points (grid states, pair tables, collision, dynamics, ITA).
+// BTE entry points of the C ABI: grid states, pair tables, the collision
+// integral, RK4 dynamics and their adjoints, and the iterative linearised BTE.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
 #include "../../include/ephx.h"
 #include "api_common.h"
 
 using namespace ephx;
 
-extern "C" int ephx_grid_states(ephx_model*, const int*, int, int, int, double, double, int, int, int*, int32_t*,
-                                int32_t*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "grid_states: not built yet"}; });
+struct ephx_table {
+    ephx_model* m = nullptr;
+    int S = 0;
+    int n1 = 0, n2 = 0, n3 = 0;
+    int nm = 0, nw = 0;
+    bool f32 = true;
+    long ld = 0;
+    int32_t* d_kc = nullptr;      // [S][3]
+    int32_t* d_band = nullptr;    // [S]
+    double* d_eps = nullptr;      // [S]
+    double* d_omega = nullptr;    // [Ngrid][nm]
+    void* d_g2 = nullptr;         // [nm][S][ld]
+    void* d_p = nullptr;          // [S][ld] collision matrix
+    void* d_w = nullptr;          // [S][ld] transport matrix
+    double* d_scale = nullptr;    // [nm] collision mode scales
+    double* d_unit = nullptr;     // [nm] ones (transport matrix)
+    double* d_ones = nullptr;     // [S]
+    ephx_params par{};
+    bool ready = false;
+    double c = 0.0;               // (2 pi/hbar)/N_q
+    StreamPlan plan{};
+    std::vector<void*> owned;
+    Workspace ws;
+    ~ephx_table() {
+        ws.release();
+        for (void* p : owned)
+            if (p) (void)hipFree(p);
+    }
+    void* alloc(size_t bytes) {
+        void* p = dev_upload(nullptr, bytes);
+        owned.push_back(p);
+        return p;
+    }
+};
+
+namespace {
+
+void grid_dims(const int* n_grid, int& n1, int& n2, int& n3) {
+    require(n_grid != nullptr, "null grid");
+    n1 = n_grid[0];
+    n2 = n_grid[1];
+    n3 = n_grid[2];
+    require(n1 >= 1 && n2 >= 1 && n3 >= 1, "grid dimensions must be >= 1");
+    require((long)n1 * n2 * n3 <= (1L << 28), "grid too large");
 }
-extern "C" int ephx_table_create(ephx_model*, const int*, int, const int32_t*, const int32_t*, int, double,
-                                 ephx_table**, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "table_create: not built yet"}; });
+
+std::vector<double> grid_points(int n1, int n2, int n3) {
+    const long ng = (long)n1 * n2 * n3;
+    std::vector<double> k(ng * 3);
+    for (long i = 0; i < ng; ++i) {
+        const long a = i / ((long)n2 * n3), b = (i / n3) % n2, c = i % n3;
+        k[3 * i] = (double)a / n1;
+        k[3 * i + 1] = (double)b / n2;
+        k[3 * i + 2] = (double)c / n3;
+    }
+    return k;
 }
-extern "C" int ephx_table_destroy(ephx_table*) { return EPHX_OK; }
-extern "C" int ephx_table_g2(ephx_table*, float*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "table_g2: not built yet"}; });
+
+// edge moved to the midpoint between the sorted energies straddling it
+double snap_edge(const std::vector<double>& e, double edge) {
+    auto it = std::lower_bound(e.begin(), e.end(), edge);
+    if (e.empty()) return edge;
+    if (it == e.begin()) return e.front() - 1.0;
+    if (it == e.end()) return e.back() + 1.0;
+    return 0.5 * (*(it - 1) + *it);
 }
-extern "C" int ephx_collision_setup(ephx_table*, const ephx_params*, const double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "collision_setup: not built yet"}; });
+
+void one_pass(ephx_table* t, const void* mat, int na, VecPtrs x, int nb, VecPtrs y, double* rowp, double* colp,
+              hipStream_t st, const char* tag) {
+    StageTimer tm(tag, st);
+    stream_pass(t->plan, t->ld, mat, t->f32 ? 1 : 0, na, x, nb, y, rowp, colp, st);
 }
-extern "C" int ephx_collision(ephx_table*, const double*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "collision: not built yet"}; });
+
+// I at occupations y; optional RK4 stage update
+void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, int acc_init, double w_acc,
+                    const double* f_base, double a_next, double* f_next, hipStream_t st) {
+    const int S = t->S;
+    double* omf = (double*)t->ws.get("c.omf", S * 8);
+    double* rowp = (double*)t->ws.get("c.rowp", (size_t)t->plan.n_ct * S * 8);
+    double* colp = (double*)t->ws.get("c.colp", (size_t)t->plan.n_rt * S * 8);
+    occ_vectors(S, y, nullptr, omf, nullptr, nullptr, st);
+    VecPtrs x{{omf, nullptr, nullptr, nullptr}}, yy{{y, nullptr, nullptr, nullptr}};
+    one_pass(t, t->d_p, 1, x, 1, yy, rowp, colp, st, "collision_stream");
+    CollisionFinish cf{};
+    cf.S = S;
+    cf.n_rt = t->plan.n_rt;
+    cf.n_ct = t->plan.n_ct;
+    cf.rowp = rowp;
+    cf.colp = colp;
+    cf.f = y;
+    cf.c = t->c;
+    cf.i_out = i_out;
+    cf.acc = acc;
+    cf.acc_init = acc_init;
+    cf.w_acc = w_acc;
+    cf.f_base = f_base;
+    cf.a_next = a_next;
+    cf.f_next = f_next;
+    StageTimer tm("collision_finish", st);
+    collision_finish(cf, st);
 }
-extern "C" int ephx_dynamics(ephx_table*, const double*, double, int, int, double*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "dynamics: not built yet"}; });
+
+// f_bar = lam^T dI/df at f; s_bar (=/+=) lam^T dI/ds
+void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, double* fbar, double* sbar,
+                        int s_accumulate, hipStream_t st) {
+    const int S = t->S;
+    double* o0 = (double*)t->ws.get("v.o0", S * 8);
+    double* o1 = (double*)t->ws.get("v.o1", S * 8);
+    double* o2 = (double*)t->ws.get("v.o2", S * 8);
+    double* rowp = (double*)t->ws.get("v.rowp", (size_t)2 * t->plan.n_ct * S * 8);
+    double* colp = (double*)t->ws.get("v.colp", (size_t)2 * t->plan.n_rt * S * 8);
+    occ_vectors(S, f, lam, o0, o1, o2, st);
+    // rows: P(1-f), P(lam(1-f)); columns: P^T f, P^T (lam f)
+    VecPtrs x{{o0, o1, nullptr, nullptr}}, y{{f, o2, nullptr, nullptr}};
+    one_pass(t, t->d_p, 2, x, 2, y, rowp, colp, st, "collision_stream");
+    vjp_finish(S, t->plan.n_ct, t->plan.n_rt, rowp, colp, lam, t->c, fbar, st);
+    if (sbar) {
+        double* part = (double*)t->ws.get("v.part", (size_t)t->nm * S * 8);
+        mode_vjp(S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
+                 t->par.temp, t->par.sigma, t->par.omega_cut, f, lam, part, t->c, sbar, s_accumulate, st);
+    }
 }
-extern "C" int ephx_collision_vjp(ephx_table*, const double*, const double*, double*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "collision_vjp: not built yet"}; });
+
+// One RK4 step f -> f_new; stage inputs optionally saved (Y1..Y4)
+void rk4_step(ephx_table* t, const double* f, double dt, double* f_new, double* y2, double* y3, double* y4,
+              hipStream_t st) {
+    // stage 1 at f: acc = f + dt/6 k1 ; y2 = f + dt/2 k1
+    collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st);
+    collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st);
+    collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st);
+    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st);
 }
-extern "C" int ephx_dynamics_vjp(ephx_table*, const double*, double, int, int, const double*, double*, double*,
-                                 void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "dynamics_vjp: not built yet"}; });
+
+void require_ready(ephx_table* t) {
+    require(t != nullptr, "null table");
+    require(t->ready, "ephx_collision_setup must be called first");
 }
-extern "C" int ephx_mobility(ephx_table*, const ephx_params*, const double*, int, double*, double*, double*, void*) {
-    return guarded([&] { throw Error{EPHX_EUNSUPPORTED, "mobility: not built yet"}; });
+
+}  // namespace
+
+extern "C" int ephx_grid_states(ephx_model* m, const int n_grid[3], int mode, int band_lo, int band_hi, double e_lo,
+                                double e_hi, int count, int capacity, int* n_states, int32_t* k_idx, int32_t* band,
+                                double* eps, void* stream) {
+    return guarded([&] {
+        require(m != nullptr && n_states != nullptr, "grid_states: null argument");
+        *n_states = 0;
+        int n1, n2, n3;
+        grid_dims(n_grid, n1, n2, n3);
+        require(mode == 0 || mode == 1, "grid_states: mode must be 0 (window) or 1 (lowest)");
+        require(0 <= band_lo && band_lo < m->nw, "grid_states: band_lo out of range");
+        if (mode == 0) require(band_lo < band_hi && band_hi <= m->nw, "grid_states: bad band range");
+        if (mode == 1) require(count >= 1, "grid_states: count must be >= 1");
+        require(capacity >= 0 && (capacity == 0 || (k_idx && band && eps)), "grid_states: null output");
+        hipStream_t st = (hipStream_t)stream;
+        const long ng = (long)n1 * n2 * n3;
+        const int nw = m->nw;
+        std::vector<double> kp = grid_points(n1, n2, n3);
+        double* dk = (double*)m->ws.get("gs.k", ng * 3 * 8);
+        double* de = (double*)m->ws.get("gs.e", ng * nw * 8);
+        hip_check(hipMemcpyAsync(dk, kp.data(), ng * 3 * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        bands_impl(m, (int)ng, dk, de, nullptr, nullptr, st, "gs");
+        std::vector<double> e(ng * nw);
+        hip_check(hipMemcpyAsync(e.data(), de, ng * nw * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        std::vector<std::pair<long, int>> sel;
+        if (mode == 0) {
+            std::vector<double> all;
+            all.reserve(ng * (band_hi - band_lo));
+            for (long k = 0; k < ng; ++k)
+                for (int b = band_lo; b < band_hi; ++b) all.push_back(e[k * nw + b]);
+            std::sort(all.begin(), all.end());
+            const double lo = snap_edge(all, e_lo), hi = snap_edge(all, e_hi);
+            for (long k = 0; k < ng; ++k)
+                for (int b = band_lo; b < band_hi; ++b) {
+                    const double v = e[k * nw + b];
+                    if (v > lo && v < hi) sel.push_back({k, b});
+                }
+        } else {
+            std::vector<long> order(ng);
+            std::iota(order.begin(), order.end(), 0L);
+            std::stable_sort(order.begin(), order.end(), [&](long a, long b) {
+                const double ea = e[a * nw + band_lo], eb = e[b * nw + band_lo];
+                return ea < eb || (ea == eb && a < b);
+            });
+            long n = std::min<long>(count, ng);
+            while (n < ng && std::fabs(e[order[n] * nw + band_lo] - e[order[n - 1] * nw + band_lo]) <= 1e-9) ++n;
+            std::vector<long> ks(order.begin(), order.begin() + n);
+            std::sort(ks.begin(), ks.end());
+            for (long k : ks) sel.push_back({k, band_lo});
+        }
+        *n_states = (int)sel.size();
+        if ((long)sel.size() > capacity) throw Error{EPHX_EINVAL, "grid_states: more states than capacity"};
+        for (size_t i = 0; i < sel.size(); ++i) {
+            k_idx[i] = (int32_t)sel[i].first;
+            band[i] = sel[i].second;
+            eps[i] = e[sel[i].first * nw + sel[i].second];
+        }
+    });
+}
+
+extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_states, const int32_t* k_idx,
+                                 const int32_t* band, int precision, double omega_cut, ephx_table** out,
+                                 void* stream) {
+    return guarded([&] {
+        require(m != nullptr && out != nullptr, "table_create: null argument");
+        *out = nullptr;
+        int n1, n2, n3;
+        grid_dims(n_grid, n1, n2, n3);
+        require(n_states >= 1 && n_states <= 60000, "table_create: need 1 <= n_states <= 60000");
+        require(k_idx && band, "table_create: null state arrays");
+        require(precision == EPHX_FP64 || precision == EPHX_FP32 || precision == EPHX_BF16X3 ||
+                    precision == EPHX_BF16X6,
+                "table_create: unknown precision");
+        require(std::isfinite(omega_cut), "table_create: omega_cut not finite");
+        const long ng = (long)n1 * n2 * n3;
+        for (int s = 0; s < n_states; ++s) {
+            require(k_idx[s] >= 0 && k_idx[s] < ng, "table_create: k index out of range");
+            require(band[s] >= 0 && band[s] < m->nw, "table_create: band out of range");
+        }
+        hipStream_t st = (hipStream_t)stream;
+        const int S = n_states, nw = m->nw, nm = m->nm, nw2 = nw * nw;
+        ephx_table* t = new ephx_table();
+        try {
+            t->m = m;
+            t->S = S;
+            t->n1 = n1;
+            t->n2 = n2;
+            t->n3 = n3;
+            t->nm = nm;
+            t->nw = nw;
+            t->f32 = precision != EPHX_FP64;
+            t->ld = table_ld(S);
+            t->plan = stream_plan(S);
+            const size_t esz = t->f32 ? 4 : 8;
+            // states: grid coordinates, reduced points, negated points
+            std::vector<int32_t> kc(3 * S);
+            std::vector<double> ks(3 * S), nks(3 * S);
+            for (int s = 0; s < S; ++s) {
+                const long i = k_idx[s];
+                kc[3 * s] = (int32_t)(i / ((long)n2 * n3));
+                kc[3 * s + 1] = (int32_t)((i / n3) % n2);
+                kc[3 * s + 2] = (int32_t)(i % n3);
+                ks[3 * s] = (double)kc[3 * s] / n1;
+                ks[3 * s + 1] = (double)kc[3 * s + 1] / n2;
+                ks[3 * s + 2] = (double)kc[3 * s + 2] / n3;
+                for (int d = 0; d < 3; ++d) nks[3 * s + d] = -ks[3 * s + d];
+            }
+            t->d_kc = (int32_t*)t->alloc(3 * S * 4);
+            t->d_band = (int32_t*)t->alloc(S * 4);
+            hip_check(hipMemcpy(t->d_kc, kc.data(), 3 * S * 4, hipMemcpyHostToDevice), "hipMemcpy");
+            hip_check(hipMemcpy(t->d_band, band, S * 4, hipMemcpyHostToDevice), "hipMemcpy");
+            double* dks = (double*)t->ws.get("t.ks", 3 * S * 8);
+            double* dnks = (double*)t->ws.get("t.nks", 3 * S * 8);
+            hip_check(hipMemcpy(dks, ks.data(), 3 * S * 8, hipMemcpyHostToDevice), "hipMemcpy");
+            hip_check(hipMemcpy(dnks, nks.data(), 3 * S * 8, hipMemcpyHostToDevice), "hipMemcpy");
+            // bands at the states
+            double* eall = (double*)t->ws.get("t.eall", (size_t)S * nw * 8);
+            double* us = (double*)t->ws.get("t.u", (size_t)S * nw2 * 16);
+            bands_impl(m, S, dks, eall, us, nullptr, st, "tab");
+            {
+                std::vector<double> e((size_t)S * nw), es(S);
+                hip_check(hipMemcpyAsync(e.data(), eall, (size_t)S * nw * 8, hipMemcpyDeviceToHost, st), "copy");
+                hip_check(hipStreamSynchronize(st), "sync");
+                for (int s = 0; s < S; ++s) es[s] = e[(size_t)s * nw + band[s]];
+                t->d_eps = (double*)t->alloc(S * 8);
+                hip_check(hipMemcpy(t->d_eps, es.data(), S * 8, hipMemcpyHostToDevice), "hipMemcpy");
+            }
+            // phonons on the whole grid (every q = k_t - k_s is a grid point)
+            std::vector<double> qp = grid_points(n1, n2, n3);
+            double* dq = (double*)t->ws.get("t.q", ng * 3 * 8);
+            hip_check(hipMemcpy(dq, qp.data(), ng * 3 * 8, hipMemcpyHostToDevice), "hipMemcpy");
+            t->d_omega = (double*)t->alloc(ng * nm * 8);
+            double* evec = (double*)t->ws.get("t.evec", (size_t)ng * nm * nm * 16);
+            phonons_impl(m, (int)ng, dq, t->d_omega, evec, st, "tab");
+            double* lr = nullptr;
+            if (m->polar) {
+                lr = (double*)t->ws.get("t.lr", (size_t)ng * nm * 16);
+                frohlich((int)ng, dq, m->pd, lr, st);
+            }
+            // the table
+            t->d_g2 = t->alloc((size_t)nm * S * t->ld * esz);
+            hip_check(hipMemsetAsync(t->d_g2, 0, (size_t)nm * S * t->ld * esz, st), "hipMemsetAsync");
+            const long nre_cols = (long)m->n_rp_g * nm * nw2;
+            const long ncol = (long)nm * nw;       // Rp-contraction columns per source
+            const int kp = ((m->n_rp_g + 31) / 32) * 32;
+            const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+            int sc = (int)std::max(1L, std::min<long>(64, (1L << 29) / std::max(1L, (long)S * ncol * 16)));
+            sc = std::min(sc, S);
+            double* gk = (double*)t->ws.get("t.gk", (size_t)sc * nre_cols * 16);
+            double* gcol = (double*)t->ws.get("t.gcol", (size_t)sc * m->n_rp_g * ncol * 16);
+            float* gcol32 = t->f32 && !nsplit ? (float*)t->ws.get("t.gcol32", (size_t)sc * m->n_rp_g * ncol * 8) : nullptr;
+            uint16_t* gbf = nsplit ? (uint16_t*)t->ws.get("t.gbf", (size_t)sc * 2 * nsplit * ncol * kp * 2) : nullptr;
+            void* gwt = t->ws.get("t.gwt", (size_t)sc * S * ncol * (t->f32 ? 8 : 16));
+            for (int s0 = 0; s0 < S; s0 += sc) {
+                const int nb = std::min(sc, S - s0);
+                StageTimer tm("table_pairs", st);
+                phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, dks + 3L * s0, nullptr, m->d_re_g, m->d_g, 0, gk, 0,
+                               st);
+                apply_u_column(nb, m->n_rp_g, nm, nw, gk, us + (size_t)s0 * nw2 * 2, t->d_band + s0, gcol, st);
+                const long sB = (long)m->n_rp_g * ncol;
+                if (precision == EPHX_FP64) {
+                    phase_gemm_f64(S, (int)ncol, m->n_rp_g, nb, dks, dnks + 3L * s0, m->d_rp_g, gcol, sB,
+                                   (double*)gwt, (long)S * ncol, st);
+                } else if (!nsplit) {
+                    convert_f64_f32((long)nb * sB * 2, gcol, gcol32, st);
+                    phase_gemm_f32(S, (int)ncol, m->n_rp_g, nb, dks, dnks + 3L * s0, m->d_rp_g, gcol32, sB,
+                                   (float*)gwt, (long)S * ncol, st);
+                } else {
+                    split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ncol, kp, gcol, gbf, st);
+                    phase_gemm_bf16(nsplit, S, (int)ncol, m->n_rp_g, kp, nb, dks, dnks + 3L * s0, m->d_rp_g, gbf,
+                                    2L * nsplit * ncol * kp, (float*)gwt, (long)S * ncol, st);
+                }
+                PairEpilogue e{};
+                e.ns_chunk = nb;
+                e.s_off = s0;
+                e.S = S;
+                e.nw = nw;
+                e.nm = nm;
+                e.gw = gwt;
+                e.ut = us;
+                e.band = t->d_band;
+                e.kc = t->d_kc;
+                e.n1 = n1;
+                e.n2 = n2;
+                e.n3 = n3;
+                e.omega = t->d_omega;
+                e.evec = evec;
+                e.lr = lr;
+                e.us = us;
+                e.minv = m->d_minv;
+                e.omega_cut = omega_cut;
+                pair_epilogue(e, t->f32 ? 1 : 0, t->ld, t->d_g2, st);
+            }
+            table_symmetrise(nm, S, t->ld, t->d_g2, t->f32 ? 1 : 0, st);
+            t->d_ones = (double*)t->alloc(S * 8);
+            fill(S, 1.0, t->d_ones, st);
+            t->d_scale = (double*)t->alloc(nm * 8);
+            t->d_unit = (double*)t->alloc(nm * 8);
+            fill(nm, 1.0, t->d_unit, st);
+            t->par.omega_cut = omega_cut;
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            // release the build buffers
+            t->ws.release();
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+    });
+}
+
+extern "C" int ephx_table_destroy(ephx_table* t) {
+    return guarded([&] {
+        if (!t) return;
+        (void)hipDeviceSynchronize();
+        delete t;
+    });
+}
+
+extern "C" int ephx_table_g2(ephx_table* t, void* g2, double* eps, void* stream) {
+    return guarded([&] {
+        require(t != nullptr, "table_g2: null table");
+        hipStream_t st = (hipStream_t)stream;
+        const size_t esz = t->f32 ? 4 : 8;
+        if (g2)
+            hip_check(hipMemcpy2DAsync(g2, t->S * esz, t->d_g2, t->ld * esz, t->S * esz, (size_t)t->nm * t->S,
+                                       hipMemcpyDeviceToDevice, st),
+                      "hipMemcpy2DAsync");
+        if (eps) hip_check(hipMemcpyAsync(eps, t->d_eps, t->S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    });
+}
+
+extern "C" int ephx_collision_setup(ephx_table* t, const ephx_params* p, const double* mode_scale, void* stream) {
+    return guarded([&] {
+        require(t != nullptr && p != nullptr, "collision_setup: null argument");
+        require(p->temp > 0 && p->sigma > 0 && p->n_q > 0 && std::isfinite(p->omega_cut),
+                "collision_setup: need temp > 0, sigma > 0, n_q > 0");
+        hipStream_t st = (hipStream_t)stream;
+        std::vector<double> sc(t->nm, 1.0);
+        if (mode_scale)
+            for (int i = 0; i < t->nm; ++i) {
+                require(std::isfinite(mode_scale[i]), "collision_setup: non-finite mode scale");
+                sc[i] = mode_scale[i];
+            }
+        hip_check(hipMemcpyAsync(t->d_scale, sc.data(), t->nm * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        const size_t esz = t->f32 ? 4 : 8;
+        if (!t->d_p) {
+            t->d_p = t->alloc((size_t)t->S * t->ld * esz);
+            hip_check(hipMemsetAsync(t->d_p, 0, (size_t)t->S * t->ld * esz, st), "hipMemsetAsync");
+        }
+        build_matrix(0, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
+                     t->d_eps, p->temp, p->mu, p->sigma, p->omega_cut, t->d_scale, t->d_p, st);
+        t->par = *p;
+        t->c = 2.0 * kPi / kHbarEvFs / p->n_q;
+        t->ready = true;
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+extern "C" int ephx_collision(ephx_table* t, const double* f, double* i_out, void* stream) {
+    return guarded([&] {
+        require_ready(t);
+        require(f && i_out, "collision: null array");
+        collision_eval(t, f, i_out, nullptr, 0, 0.0, nullptr, 0.0, nullptr, (hipStream_t)stream);
+    });
+}
+
+extern "C" int ephx_dynamics(ephx_table* t, const double* f0, double dt, int n_steps, int ckpt_every, double* f_out,
+                             double* ckpts, void* stream) {
+    return guarded([&] {
+        require_ready(t);
+        require(f0 && f_out, "dynamics: null array");
+        require(n_steps >= 0 && std::isfinite(dt), "dynamics: bad step count or dt");
+        require(!ckpts || ckpt_every >= 1, "dynamics: ckpt_every must be >= 1 with checkpoints");
+        hipStream_t st = (hipStream_t)stream;
+        const int S = t->S;
+        double* fa = (double*)t->ws.get("d.fa", S * 8);
+        double* fb = (double*)t->ws.get("d.fb", S * 8);
+        double* y2 = (double*)t->ws.get("d.y2", S * 8);
+        double* y3 = (double*)t->ws.get("d.y3", S * 8);
+        double* y4 = (double*)t->ws.get("d.y4", S * 8);
+        hip_check(hipMemcpyAsync(fa, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        if (ckpts) hip_check(hipMemcpyAsync(ckpts, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        for (int n = 0; n < n_steps; ++n) {
+            rk4_step(t, fa, dt, fb, y2, y3, y4, st);
+            std::swap(fa, fb);
+            if (ckpts && (n + 1) % ckpt_every == 0)
+                hip_check(hipMemcpyAsync(ckpts + (size_t)((n + 1) / ckpt_every) * S, fa, S * 8,
+                                         hipMemcpyDeviceToDevice, st),
+                          "hipMemcpyAsync");
+        }
+        hip_check(hipMemcpyAsync(f_out, fa, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    });
+}
+
+extern "C" int ephx_collision_vjp(ephx_table* t, const double* f, const double* lam, double* f_bar, double* s_bar,
+                                  void* stream) {
+    return guarded([&] {
+        require_ready(t);
+        require(f && lam && f_bar, "collision_vjp: null array");
+        collision_vjp_impl(t, f, lam, f_bar, s_bar, 0, (hipStream_t)stream);
+    });
+}
+
+extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, int n_steps, int ckpt_every,
+                                 const double* f_bar_final, double* f0_bar, double* s_bar, void* stream) {
+    return guarded([&] {
+        require_ready(t);
+        require(ckpts && f_bar_final && f0_bar, "dynamics_vjp: null array");
+        require(n_steps >= 0 && ckpt_every >= 1 && n_steps % ckpt_every == 0,
+                "dynamics_vjp: n_steps must be a multiple of ckpt_every >= 1");
+        hipStream_t st = (hipStream_t)stream;
+        const int S = t->S;
+        const int L = ckpt_every;
+        double* a = (double*)t->ws.get("b.a", S * 8);
+        double* kb = (double*)t->ws.get("b.kb", S * 8);
+        double* yb[4];
+        for (int i = 0; i < 4; ++i) yb[i] = (double*)t->ws.get("b.yb" + std::to_string(i), S * 8);
+        double* ys = (double*)t->ws.get("b.ys", (size_t)L * 4 * S * 8);   // stage inputs of the segment
+        double* fn = (double*)t->ws.get("b.fn", S * 8);
+        hip_check(hipMemcpyAsync(a, f_bar_final, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        if (s_bar) hip_check(hipMemsetAsync(s_bar, 0, t->nm * 8, st), "hipMemsetAsync");
+        const int nseg = n_steps / L;
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            // replay the segment, keeping the four stage inputs of each step
+            const double* cur = ckpts + (size_t)seg * S;
+            for (int j = 0; j < L; ++j) {
+                double* y1 = ys + ((size_t)j * 4) * S;
+                hip_check(hipMemcpyAsync(y1, cur, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+                rk4_step(t, y1, dt, fn, y1 + S, y1 + 2 * S, y1 + 3 * S, st);
+                cur = fn;
+            }
+            for (int j = L - 1; j >= 0; --j) {
+                const double* Y[4];
+                for (int i = 0; i < 4; ++i) Y[i] = ys + ((size_t)j * 4 + i) * S;
+                // k4b = dt/6 a ; Y4b = J4^T k4b
+                lincomb(S, Lincomb{1, 0.0, {dt / 6.0}, {a}}, kb, st);
+                collision_vjp_impl(t, Y[3], kb, yb[3], s_bar, 1, st);
+                // k3b = dt/3 a + dt Y4b
+                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt}, {a, yb[3]}}, kb, st);
+                collision_vjp_impl(t, Y[2], kb, yb[2], s_bar, 1, st);
+                // k2b = dt/3 a + dt/2 Y3b
+                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt / 2.0}, {a, yb[2]}}, kb, st);
+                collision_vjp_impl(t, Y[1], kb, yb[1], s_bar, 1, st);
+                // k1b = dt/6 a + dt/2 Y2b
+                lincomb(S, Lincomb{2, 0.0, {dt / 6.0, dt / 2.0}, {a, yb[1]}}, kb, st);
+                collision_vjp_impl(t, Y[0], kb, yb[0], s_bar, 1, st);
+                // a <- a + Y1b + Y2b + Y3b + Y4b
+                lincomb(S, Lincomb{5, 0.0, {1.0, 1.0, 1.0, 1.0, 1.0}, {a, yb[0], yb[1], yb[2], yb[3]}}, a, st);
+            }
+        }
+        hip_check(hipMemcpyAsync(f0_bar, a, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    });
+}
+
+extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter, double* f_out,
+                             double* tau_out, double* mob_out, void* stream) {
+    return guarded([&] {
+        require(t != nullptr && p != nullptr, "mobility: null argument");
+        require(vel != nullptr, "mobility: null velocities");
+        require(n_iter >= 0, "mobility: n_iter < 0");
+        require(p->temp > 0 && p->sigma > 0 && p->n_q > 0 && std::isfinite(p->mu), "mobility: bad parameters");
+        hipStream_t st = (hipStream_t)stream;
+        const int S = t->S;
+        const size_t esz = t->f32 ? 4 : 8;
+        if (!t->d_w) {
+            t->d_w = t->alloc((size_t)S * t->ld * esz);
+            hip_check(hipMemsetAsync(t->d_w, 0, (size_t)S * t->ld * esz, st), "hipMemsetAsync");
+        }
+        build_matrix(1, S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
+                     p->temp, p->mu, p->sigma, p->omega_cut, t->d_unit, t->d_w, st);
+        double* tau = (double*)t->ws.get("m.tau", S * 8);
+        double* f0 = (double*)t->ws.get("m.f0", 3 * S * 8);
+        double* f = (double*)t->ws.get("m.f", 3 * S * 8);
+        double* fn = (double*)t->ws.get("m.fn", 3 * S * 8);
+        double* rowp = (double*)t->ws.get("m.rowp", (size_t)3 * t->plan.n_ct * S * 8);
+        VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
+        one_pass(t, t->d_w, 1, one, 0, none, rowp, nullptr, st, "transport_stream");
+        ita_gamma(S, t->plan.n_ct, rowp, p->n_q, vel, tau, f0, f, st);
+        for (int it = 0; it < n_iter; ++it) {
+            VecPtrs x{{f, f + S, f + 2 * S, nullptr}};
+            one_pass(t, t->d_w, 3, x, 0, none, rowp, nullptr, st, "transport_stream");
+            ita_update(S, t->plan.n_ct, rowp, p->n_q, tau, f0, fn, st);
+            std::swap(f, fn);
+        }
+        mobility_reduce(S, t->d_eps, vel, f, p->mu, p->temp, f_out, mob_out, st);
+        if (tau_out) hip_check(hipMemcpyAsync(tau_out, tau, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    });
 }

@@ -1,2 +1,601 @@
-// BTE kernels
-namespace ephx {}
+// Boltzmann-equation kernels on grid states (paper Sec. 2.1 and 4.3).
+//
+// Pair table.  For states s = (k_s, n_s) and t = (k_t, n_t) on one grid,
+// q = k_t - k_s and the table holds G[nu][s][t] = 1/2(|g(s->t)|^2 + |g(t->s)|^2).
+//
+// Collision integral in matrix form.  With Delta = e_s - e_t and the mode sum
+// done once when parameters are set,
+//   P_st = sum_nu s_nu G[nu][s][t] [ delta(Delta - hw)(N+1) + delta(Delta + hw) N ],
+// Eq. e_ph_scattering becomes (using G_st = G_ts, omega(-q) = omega(q) and the
+// evenness of the Gaussian)
+//   I_s = -(2 pi/hbar)(1/N_q) [ f_s sum_t P_st (1 - f_t) - (1 - f_s) sum_t P_ts f_t ],
+// so one pass over P (row sums and column sums together) evaluates I for any
+// f: 4 S^2 bytes instead of the 4 S^2 3nat bytes of the per-mode table.
+//
+// Streaming pass.  A 256-thread workgroup owns a 256-row x 1024-column tile;
+// each wave walks 64 rows, each lane holds 16 columns (four 16-byte loads per
+// row, each instruction reading 1 KB contiguously).  Row sums are reduced
+// across the wave with shuffles, column sums stay in registers and are
+// combined across the four waves through LDS at the end.  Partials go to
+// rowp[a][col tile][row] and colp[b][row tile][col] and are reduced in a fixed
+// order by the finishing kernel (no atomics; results are deterministic).
+#include "internal.h"
+
+namespace ephx {
+namespace {
+
+inline void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ cx<T> ldc(const T* p, long i) {
+    return {p[2 * i], p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ldcd(const double* p, long i) {
+    return {(T)p[2 * i], (T)p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+template <typename T>
+__device__ __forceinline__ void cjfma(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
+}
+
+__device__ __forceinline__ long grid_q(const int32_t* kc, int s, int t, int n1, int n2, int n3) {
+    int a = kc[3 * t] - kc[3 * s], b = kc[3 * t + 1] - kc[3 * s + 1], c = kc[3 * t + 2] - kc[3 * s + 2];
+    a += a < 0 ? n1 : 0;
+    b += b < 0 ? n2 : 0;
+    c += c < 0 ? n3 : 0;
+    return ((long)a * n2 + b) * n3 + c;
+}
+
+// One thread per (source s in chunk, target t): rotation with conj(U(k_t))[:, n_t],
+// mode projection with e(q)/sqrt(M) and sqrt(hbar^2/(2 M omega)), |g|^2 (FP32).
+__global__ void k_pair_epilogue_f32(PairEpilogue e, long ld) {
+    const int z = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= e.S) return;
+    const int s = e.s_off + z;
+    const int nw = e.nw, nm = e.nm;
+    const long iq = grid_q(e.kc, s, t, e.n1, e.n2, e.n3);
+    const float* gp = reinterpret_cast<const float*>(e.gw) + ((long)z * e.S + t) * nm * nw * 2;
+    const int bt = e.band[t];
+    const double* ut = e.ut + (long)t * nw * nw * 2;
+    cx<float> gh[kMaxModes];
+    for (int x = 0; x < nm; ++x) {
+        cx<float> a = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(a, ldcd<float>(ut, (long)i * nw + bt), ldc(gp, (long)x * nw + i));
+        gh[x] = a;
+    }
+    if (e.lr != nullptr) {
+        const double* us = e.us + (long)s * nw * nw * 2;
+        const int bs = e.band[s];
+        cx<float> ov = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(ov, ldcd<float>(ut, (long)i * nw + bt), ldcd<float>(us, (long)i * nw + bs));
+        for (int x = 0; x < nm; ++x) cfma(gh[x], ldcd<float>(e.lr, iq * nm + x), ov);
+    }
+    for (int nu = 0; nu < nm; ++nu) {
+        const double om = e.omega[iq * nm + nu];
+        float g2 = 0.f;
+        if (om > e.omega_cut) {
+            cx<float> g = {0, 0};
+            for (int x = 0; x < nm; ++x) {
+                cx<float> ev = ldcd<float>(e.evec, (iq * nm + x) * nm + nu);
+                ev.x *= (float)e.minv[x];
+                ev.y *= (float)e.minv[x];
+                cfma(g, ev, gh[x]);
+            }
+            const float amp2 = (float)(kHbar2AmuA2 / (2.0 * om));
+            g2 = amp2 * (g.x * g.x + g.y * g.y);
+        }
+        e.g2raw[((long)nu * e.S + s) * ld + t] = g2;
+    }
+}
+
+// FP64 variant writing a double table
+__global__ void k_pair_epilogue_f64(PairEpilogue e, long ld, double* g2out) {
+    const int z = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= e.S) return;
+    const int s = e.s_off + z;
+    const int nw = e.nw, nm = e.nm;
+    const long iq = grid_q(e.kc, s, t, e.n1, e.n2, e.n3);
+    const double* gp = reinterpret_cast<const double*>(e.gw) + ((long)z * e.S + t) * nm * nw * 2;
+    const int bt = e.band[t];
+    const double* ut = e.ut + (long)t * nw * nw * 2;
+    cx<double> gh[kMaxModes];
+    for (int x = 0; x < nm; ++x) {
+        cx<double> a = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(a, ldc(ut, (long)i * nw + bt), ldc(gp, (long)x * nw + i));
+        gh[x] = a;
+    }
+    if (e.lr != nullptr) {
+        const double* us = e.us + (long)s * nw * nw * 2;
+        const int bs = e.band[s];
+        cx<double> ov = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(ov, ldc(ut, (long)i * nw + bt), ldc(us, (long)i * nw + bs));
+        for (int x = 0; x < nm; ++x) cfma(gh[x], ldc(e.lr, iq * nm + x), ov);
+    }
+    for (int nu = 0; nu < nm; ++nu) {
+        const double om = e.omega[iq * nm + nu];
+        double g2 = 0.0;
+        if (om > e.omega_cut) {
+            cx<double> g = {0, 0};
+            for (int x = 0; x < nm; ++x) {
+                cx<double> ev = ldc(e.evec, (iq * nm + x) * nm + nu);
+                ev.x *= e.minv[x];
+                ev.y *= e.minv[x];
+                cfma(g, ev, gh[x]);
+            }
+            const double amp = sqrt(kHbar2AmuA2 / (2.0 * om));
+            g2 = amp * amp * (g.x * g.x + g.y * g.y);
+        }
+        g2out[((long)nu * e.S + s) * ld + t] = g2;
+    }
+}
+
+// G <- (G + G^T)/2 per mode, in place, 32x32 tiles with i <= j
+template <typename T>
+__global__ void k_symmetrise(int S, long ld, T* g) {
+    __shared__ T a[32][33], b[32][33];
+    const int nu = blockIdx.z;
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bi > bj) return;
+    T* gn = g + (long)nu * S * ld;
+    const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        a[r][tx] = (i < S && j < S) ? gn[(long)i * ld + j] : (T)0;
+        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        b[r][tx] = (i2 < S && j2 < S) ? gn[(long)i2 * ld + j2] : (T)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < S && j < S) gn[(long)i * ld + j] = (T)0.5 * (a[r][tx] + b[tx][r]);
+        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        if (i2 < S && j2 < S) gn[(long)i2 * ld + j2] = (T)0.5 * (b[r][tx] + a[tx][r]);
+    }
+}
+
+// P[s][t] = sum_nu scale_nu G[nu][s][t] w_nu(s,t) with
+//   collision:  w = delta(D - hw)(N+1) + delta(D + hw) N
+//   transport:  w = (2 pi/hbar)[delta(D - hw)(1 + N - f0_t) + delta(D + hw)(N + f0_t)]
+template <typename T, bool TRANSPORT>
+__global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2, const int32_t* __restrict__ kc,
+                               int n1, int n2, int n3, const double* __restrict__ omega,
+                               const double* __restrict__ eps, double temp, double mu, double sigma,
+                               double omega_cut, const double* __restrict__ scale, T* __restrict__ out) {
+    const int s = blockIdx.x;
+    const int t = blockIdx.y * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    const long iq = grid_q(kc, s, t, n1, n2, n3);
+    const double d = eps[s] - eps[t];
+    const double kt = kBoltzEv * temp;
+    const double is = 1.0 / sigma, nrm = 1.0 / (sqrt(kPi) * sigma);
+    double f0t = 0.0;
+    if (TRANSPORT) f0t = 1.0 / (exp((eps[t] - mu) / kt) + 1.0);
+    double acc = 0.0;
+    for (int nu = 0; nu < nm; ++nu) {
+        const double om = omega[iq * nm + nu];
+        if (!(om > omega_cut)) continue;
+        const double nb = 1.0 / expm1(om / kt);
+        const double x1 = (d - om) * is, x2 = (d + om) * is;
+        const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+        const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+        const double w = TRANSPORT ? (de * (1.0 + nb - f0t) + da * (nb + f0t)) : (de * (nb + 1.0) + da * nb);
+        acc += scale[nu] * (double)g2[((long)nu * S + s) * ld + t] * w;
+    }
+    out[(long)s * ld + t] = (T)(TRANSPORT ? acc * (2.0 * kPi / kHbarEvFs) : acc);
+}
+
+// ---------------------------------------------------------------- streaming pass
+constexpr int kTR = 256;          // rows per tile
+constexpr int kTC = 1024;         // columns per tile
+constexpr int kCPL = kTC / 64;    // columns per lane (16)
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    typedef float4 type;
+};
+template <>
+struct Vec4<double> {
+    typedef double4 type;
+};
+
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restrict__ P, VecPtrs xa,
+                                                VecPtrs yb, double* __restrict__ rowp,
+                                                double* __restrict__ colp, int n_ct, int n_rt) {
+    __shared__ double cred[NB > 0 ? NB : 1][kTC];
+    const int ct = blockIdx.x, rt = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int c0 = ct * kTC;
+    // lane columns: c0 + 4*(lane + 64*j) + u, j = 0..3, u = 0..3
+    double xv[NA > 0 ? NA : 1][kCPL];
+    for (int a = 0; a < NA; ++a)
+        for (int j = 0; j < 4; ++j)
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + 4 * (lane + 64 * j) + u;
+                xv[a][4 * j + u] = c < S ? xa.p[a][c] : 0.0;
+            }
+    double cacc[NB > 0 ? NB : 1][kCPL];
+    for (int b = 0; b < NB; ++b)
+        for (int i = 0; i < kCPL; ++i) cacc[b][i] = 0.0;
+    const int r_end = min(S, (rt + 1) * kTR);
+    for (int r = rt * kTR + wave; r < r_end; r += 4) {
+        const T* row = P + (long)r * ld + c0;
+        double pv[kCPL];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * (lane + 64 * j);
+            typename Vec4<T>::type v;
+            if (c0 + c < ld) {
+                v = *reinterpret_cast<const typename Vec4<T>::type*>(row + c);
+            } else {
+                v.x = v.y = v.z = v.w = (T)0;
+            }
+            pv[4 * j] = (double)v.x;
+            pv[4 * j + 1] = (double)v.y;
+            pv[4 * j + 2] = (double)v.z;
+            pv[4 * j + 3] = (double)v.w;
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            double sa = 0.0;
+#pragma unroll
+            for (int i = 0; i < kCPL; ++i) sa = fma(pv[i], xv[a][i], sa);
+            for (int w = 32; w >= 1; w >>= 1) sa += __shfl_xor(sa, w, 64);
+            if (lane == 0) rowp[((long)a * n_ct + ct) * S + r] = sa;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double yr = yb.p[b][r];
+#pragma unroll
+            for (int i = 0; i < kCPL; ++i) cacc[b][i] = fma(pv[i], yr, cacc[b][i]);
+        }
+    }
+    if (NB > 0) {
+        // combine the four waves' column sums in a fixed order
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w) {
+                for (int b = 0; b < NB; ++b)
+                    for (int j = 0; j < 4; ++j)
+                        for (int u = 0; u < 4; ++u) {
+                            const int c = 4 * (lane + 64 * j) + u;
+                            cred[b][c] = (w == 0 ? 0.0 : cred[b][c]) + cacc[b][4 * j + u];
+                        }
+            }
+            __syncthreads();
+        }
+        for (int b = 0; b < NB; ++b)
+            for (int c = tid; c < kTC; c += 256)
+                if (c0 + c < S) colp[((long)b * n_rt + rt) * S + c0 + c] = cred[b][c];
+    }
+}
+
+__global__ void k_collision_finish(CollisionFinish cf) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= cf.S) return;
+    double r = 0.0, c = 0.0;
+    for (int ct = 0; ct < cf.n_ct; ++ct) r += cf.rowp[(long)ct * cf.S + s];
+    for (int rt = 0; rt < cf.n_rt; ++rt) c += cf.colp[(long)rt * cf.S + s];
+    const double f = cf.f[s];
+    const double i = -cf.c * (f * r - (1.0 - f) * c);
+    if (cf.i_out) cf.i_out[s] = i;
+    if (cf.acc) {
+        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * i;
+        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * i;
+    }
+}
+
+// f_bar_u = -c [ lam_u (R0_u + C0_u) - C1_u - R1_u ]
+__global__ void k_vjp_finish(int S, int n_ct, int n_rt, const double* __restrict__ rowp,
+                             const double* __restrict__ colp, const double* __restrict__ lam, double c,
+                             double* __restrict__ fbar) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= S) return;
+    double r0 = 0.0, r1 = 0.0, c0 = 0.0, c1 = 0.0;
+    for (int ct = 0; ct < n_ct; ++ct) {
+        r0 += rowp[(long)ct * S + u];
+        r1 += rowp[((long)n_ct + ct) * S + u];
+    }
+    for (int rt = 0; rt < n_rt; ++rt) {
+        c0 += colp[(long)rt * S + u];
+        c1 += colp[((long)n_rt + rt) * S + u];
+    }
+    fbar[u] = -c * (lam[u] * (r0 + c0) - c1 - r1);
+}
+
+// s_bar_nu partial: for row s, sum_t P^nu_st b_t (lam_s - lam_t) * a_s, P^nu from
+// the per-mode table and the collision weights; one block per (row s, mode).
+template <typename T>
+__global__ void k_mode_vjp(int S, int nm, long ld, const T* __restrict__ g2, const int32_t* __restrict__ kc, int n1,
+                           int n2, int n3, const double* __restrict__ omega, const double* __restrict__ eps,
+                           double temp, double sigma, double omega_cut, const double* __restrict__ f,
+                           const double* __restrict__ lam, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int s = blockIdx.x, nu = blockIdx.y;
+    const double kt = kBoltzEv * temp;
+    const double is = 1.0 / sigma, nrm = 1.0 / (sqrt(kPi) * sigma);
+    const double fs = f[s], ls = lam[s];
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < S; t += 256) {
+        const long iq = grid_q(kc, s, t, n1, n2, n3);
+        const double om = omega[iq * nm + nu];
+        if (!(om > omega_cut)) continue;
+        const double nb = 1.0 / expm1(om / kt);
+        const double d = eps[s] - eps[t];
+        const double x1 = (d - om) * is, x2 = (d + om) * is;
+        const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+        const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+        const double p = (double)g2[((long)nu * S + s) * ld + t] * (de * (nb + 1.0) + da * nb);
+        acc += p * (1.0 - f[t]) * (ls - lam[t]);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)nu * S + s] = fs * red[0];
+}
+
+__global__ void k_sum_rows(int S, int nm, const double* __restrict__ part, double c, double* __restrict__ out,
+                           int accumulate) {
+    __shared__ double red[256];
+    const int nu = blockIdx.x;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < S; s += 256) acc += part[(long)nu * S + s];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[nu] = (accumulate ? out[nu] : 0.0) - c * red[0];
+}
+
+// ITA update: F[s][a] = F0[s][a] + tau_s/N_q * sum_ct rowp[a][ct][s]; also gamma from a ones pass
+__global__ void k_ita_gamma(int S, int n_ct, const double* __restrict__ rowp, double n_q, const double* __restrict__ vel,
+                            double* __restrict__ tau, double* __restrict__ f0, double* __restrict__ f) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double g = 0.0;
+    for (int ct = 0; ct < n_ct; ++ct) g += rowp[(long)ct * S + s];
+    const double ts = n_q / g;
+    tau[s] = ts;
+    for (int a = 0; a < 3; ++a) {
+        f0[(long)a * S + s] = ts * vel[3 * s + a];
+        f[(long)a * S + s] = ts * vel[3 * s + a];
+    }
+}
+
+__global__ void k_ita_update(int S, int n_ct, const double* __restrict__ rowp, double n_q, const double* __restrict__ tau,
+                             const double* __restrict__ f0, double* __restrict__ f) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    for (int a = 0; a < 3; ++a) {
+        double r = 0.0;
+        for (int ct = 0; ct < n_ct; ++ct) r += rowp[((long)a * n_ct + ct) * S + s];
+        f[(long)a * S + s] = f0[(long)a * S + s] + tau[s] / n_q * r;
+    }
+}
+
+// mu_ab = 0.1 sum_s v^a F^b f0(1-f0)/(kT) / sum_s f0, one block; also F out as [S][3]
+__global__ void k_mobility(int S, const double* __restrict__ eps, const double* __restrict__ vel,
+                           const double* __restrict__ f, double mu, double temp, double* __restrict__ fout,
+                           double* __restrict__ mob) {
+    __shared__ double red[10][256];
+    const double kt = kBoltzEv * temp;
+    double acc[10];
+    for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+    for (int s = threadIdx.x; s < S; s += 256) {
+        const double f0 = 1.0 / (exp((eps[s] - mu) / kt) + 1.0);
+        const double w = f0 * (1.0 - f0) / kt;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc[3 * a + b] += vel[3 * s + a] * f[(long)b * S + s] * w;
+        acc[9] += f0;
+        if (fout)
+            for (int b = 0; b < 3; ++b) fout[3 * s + b] = f[(long)b * S + s];
+    }
+    for (int i = 0; i < 10; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int i = 0; i < 10; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9 && mob) mob[threadIdx.x] = 0.1 * red[threadIdx.x][0] / red[9][0];
+}
+
+__global__ void k_axpy_copy(int S, const double* __restrict__ x, double a, const double* __restrict__ y,
+                            double* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) out[s] = x[s] + a * (y ? y[s] : 0.0);
+}
+
+// out = sum_i c_i v_i (v_i may be the same array as out); terms with null v are skipped
+__global__ void k_lincomb(int S, Lincomb lc, double* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double acc = lc.c0;
+    for (int i = 0; i < lc.n; ++i) acc += lc.c[i] * lc.v[i][s];
+    out[s] = acc;
+}
+
+// out0 = 1 - f, out1 = lam (1 - f), out2 = lam f (out1/out2 skipped when lam is null)
+__global__ void k_occ_vectors(int S, const double* __restrict__ f, const double* __restrict__ lam, double* __restrict__ o0,
+                              double* __restrict__ o1, double* __restrict__ o2) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const double fs = f[s];
+    o0[s] = 1.0 - fs;
+    if (lam) {
+        o1[s] = lam[s] * (1.0 - fs);
+        o2[s] = lam[s] * fs;
+    }
+}
+
+__global__ void k_fill(long n, double v, double* out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+}  // namespace
+
+long table_ld(int S) { return ((long)S + 63) / 64 * 64; }
+
+void pair_epilogue(const PairEpilogue& e, int f32, long ld, void* g2out, hipStream_t st) {
+    dim3 grid((e.S + 127) / 128, e.ns_chunk);
+    if (f32) {
+        PairEpilogue ee = e;
+        ee.g2raw = (float*)g2out;
+        hipLaunchKernelGGL(k_pair_epilogue_f32, grid, dim3(128), 0, st, ee, ld);
+    } else {
+        hipLaunchKernelGGL(k_pair_epilogue_f64, grid, dim3(128), 0, st, e, ld, (double*)g2out);
+    }
+    check_launch("pair_epilogue");
+}
+
+void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st) {
+    const int nb = (S + 31) / 32;
+    dim3 grid(nb, nb, nm);
+    if (f32)
+        hipLaunchKernelGGL(k_symmetrise<float>, grid, dim3(32, 8), 0, st, S, ld, (float*)g2);
+    else
+        hipLaunchKernelGGL(k_symmetrise<double>, grid, dim3(32, 8), 0, st, S, ld, (double*)g2);
+    check_launch("table_symmetrise");
+}
+
+void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2,
+                  int n3, const double* omega, const double* eps, double temp, double mu, double sigma,
+                  double omega_cut, const double* scale, void* out, hipStream_t st) {
+    dim3 grid(S, (S + 255) / 256);
+    if (f32) {
+        if (transport)
+            hipLaunchKernelGGL((k_build_matrix<float, true>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (float*)out);
+        else
+            hipLaunchKernelGGL((k_build_matrix<float, false>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (float*)out);
+    } else {
+        if (transport)
+            hipLaunchKernelGGL((k_build_matrix<double, true>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (double*)out);
+        else
+            hipLaunchKernelGGL((k_build_matrix<double, false>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (double*)out);
+    }
+    check_launch("build_matrix");
+}
+
+StreamPlan stream_plan(int S) {
+    StreamPlan p;
+    p.S = S;
+    p.n_rt = (S + kTR - 1) / kTR;
+    p.n_ct = (S + kTC - 1) / kTC;
+    return p;
+}
+
+void stream_pass(const StreamPlan& pl, long ld, const void* P, int f32, int na, VecPtrs x, int nb, VecPtrs y,
+                 double* rowp, double* colp, hipStream_t st) {
+    dim3 grid(pl.n_ct, pl.n_rt);
+#define EPHX_STREAM(T, A, B)                                                                                   \
+    hipLaunchKernelGGL((k_stream<T, A, B>), grid, dim3(256), 0, st, pl.S, ld, (const T*)P, x, y, rowp, colp, \
+                       pl.n_ct, pl.n_rt)
+    if (f32) {
+        if (na == 1 && nb == 1) EPHX_STREAM(float, 1, 1);
+        else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
+        else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
+        else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
+        else throw Error{-1, "stream_pass: unsupported vector counts"};
+    } else {
+        if (na == 1 && nb == 1) EPHX_STREAM(double, 1, 1);
+        else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
+        else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
+        else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
+        else throw Error{-1, "stream_pass: unsupported vector counts"};
+    }
+#undef EPHX_STREAM
+    check_launch("stream_pass");
+}
+
+void collision_finish(const CollisionFinish& cf, hipStream_t st) {
+    hipLaunchKernelGGL(k_collision_finish, dim3((cf.S + 255) / 256), dim3(256), 0, st, cf);
+    check_launch("collision_finish");
+}
+
+void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
+                double* fbar, hipStream_t st) {
+    hipLaunchKernelGGL(k_vjp_finish, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, n_rt, rowp, colp, lam, c, fbar);
+    check_launch("vjp_finish");
+}
+
+void mode_vjp(int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2, int n3,
+              const double* omega, const double* eps, double temp, double sigma, double omega_cut, const double* f,
+              const double* lam, double* part, double c, double* sbar, int accumulate, hipStream_t st) {
+    dim3 grid(S, nm);
+    if (f32)
+        hipLaunchKernelGGL(k_mode_vjp<float>, grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc, n1, n2, n3,
+                           omega, eps, temp, sigma, omega_cut, f, lam, part);
+    else
+        hipLaunchKernelGGL(k_mode_vjp<double>, grid, dim3(256), 0, st, S, nm, ld, (const double*)g2, kc, n1, n2, n3,
+                           omega, eps, temp, sigma, omega_cut, f, lam, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(nm), dim3(256), 0, st, S, nm, part, c, sbar, accumulate);
+    check_launch("mode_vjp");
+}
+
+void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0, double* f,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_ita_gamma, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, rowp, n_q, vel, tau, f0, f);
+    check_launch("ita_gamma");
+}
+
+void ita_update(int S, int n_ct, const double* rowp, double n_q, const double* tau, const double* f0, double* f,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_ita_update, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, rowp, n_q, tau, f0, f);
+    check_launch("ita_update");
+}
+
+void mobility_reduce(int S, const double* eps, const double* vel, const double* f, double mu, double temp,
+                     double* fout, double* mob, hipStream_t st) {
+    hipLaunchKernelGGL(k_mobility, dim3(1), dim3(256), 0, st, S, eps, vel, f, mu, temp, fout, mob);
+    check_launch("mobility");
+}
+
+void axpy_copy(int S, const double* x, double a, const double* y, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_copy, dim3((S + 255) / 256), dim3(256), 0, st, S, x, a, y, out);
+    check_launch("axpy_copy");
+}
+
+void lincomb(int S, const Lincomb& lc, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_lincomb, dim3((S + 255) / 256), dim3(256), 0, st, S, lc, out);
+    check_launch("lincomb");
+}
+
+void occ_vectors(int S, const double* f, const double* lam, double* o0, double* o1, double* o2, hipStream_t st) {
+    hipLaunchKernelGGL(k_occ_vectors, dim3((S + 255) / 256), dim3(256), 0, st, S, f, lam, o0, o1, o2);
+    check_launch("occ_vectors");
+}
+
+void fill(long n, double v, double* out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, out);
+    check_launch("fill");
+}
+
+}  // namespace ephx

@@ -41,6 +41,36 @@ void* Workspace::get(const std::string& name, size_t bytes) {
     return p;
 }
 
+// ---------------------------------------------------------------- stage timers
+namespace {
+struct TimerState {
+    bool on = false;
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev;
+} g_timer;
+}  // namespace
+
+StageTimer::StageTimer(const char* n, hipStream_t s) : name(n), st(s) {
+    if (!g_timer.on) return;
+    if (hipEventCreate(&e0) != hipSuccess) {
+        e0 = nullptr;
+        return;
+    }
+    (void)hipEventRecord(e0, st);
+}
+
+void StageTimer::stop() {
+    if (!e0) return;
+    hipEvent_t e1 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        e0 = nullptr;
+        return;
+    }
+    (void)hipEventRecord(e1, st);
+    g_timer.ev[name].push_back({e0, e1});
+    e0 = nullptr;
+}
+
 void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw Error{EPHX_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
@@ -82,6 +112,39 @@ ephx_model::~ephx_model() {
 }
 
 extern "C" const char* ephx_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int ephx_timer_reset(void) {
+    return guarded([&] {
+        for (auto& kv : g_timer.ev)
+            for (auto& pr : kv.second) {
+                (void)hipEventSynchronize(pr.second);
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        g_timer.ev.clear();
+    });
+}
+
+extern "C" int ephx_timer_enable(int on) {
+    return guarded([&] { g_timer.on = on != 0; });
+}
+
+extern "C" int ephx_timer_get(const char* stage, int* launches, double* total_ms) {
+    return guarded([&] {
+        require(stage && launches && total_ms, "timer_get: null argument");
+        *launches = 0;
+        *total_ms = 0.0;
+        auto it = g_timer.ev.find(stage);
+        if (it == g_timer.ev.end()) return;
+        for (auto& pr : it->second) {
+            hip_check(hipEventSynchronize(pr.second), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+            *total_ms += ms;
+            *launches += 1;
+        }
+    });
+}
 extern "C" const char* ephx_version(void) { return "ephx 0.1 gfx950"; }
 
 extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
@@ -202,10 +265,6 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                 }
             }
             m->d_h = (double*)up(h.data(), h.size() * sizeof(double));
-            {
-                std::vector<float> h32(h.begin(), h.end());
-                m->d_h32 = (float*)up(h32.data(), h32.size() * sizeof(float));
-            }
             m->d_hvel = (double*)up(hv.data(), hv.size() * sizeof(double));
             // C(R) / sqrt(M_k M_k') as complex, weights folded
             std::vector<double> cm((size_t)d->n_rp_ph * nm * nm * 2, 0.0);
@@ -319,7 +378,10 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     // phonons (and the long-range term) at every q of the call
     double* om = (double*)m->ws.get("drv.omega", (size_t)nq * nm * 8);
     double* ev = (double*)m->ws.get("drv.evec", (size_t)nq * nm * nm * 16);
-    phonons_impl(m, nq, q, om, ev, st, "drv");
+    {
+        StageTimer t("phonons", st);
+        phonons_impl(m, nq, q, om, ev, st, "drv");
+    }
     double* lr = nullptr;
     if (m->polar) {
         lr = (double*)m->ws.get("drv.lr", (size_t)nq * nm * 16);
@@ -342,7 +404,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
     if (nsplit) gpbf = (uint16_t*)m->ws.get("drv.gpbf", (size_t)bk_eff * 2 * nsplit * ngcol * kp * 2);
     const size_t npair = (size_t)bk_eff * qc;
-    void* hkq = m->ws.get("drv.hkq", npair * nw2 * (f32 ? 8 : 16));
+    void* hkq = m->ws.get("drv.hkq", npair * nw2 * 16);
     double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
     double* ukq = (double*)m->ws.get("drv.ukq", npair * nw2 * 16);
     void* gw = m->ws.get("drv.gw", npair * ngcol * (f32 ? 8 : 16));
@@ -358,7 +420,10 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         const double* kb = k + 3L * k0;
         bands_impl(m, nb, kb, ek, uk, nullptr, st, "drv.bk");
         // Re contraction (FP64, amortised over all q), then U(k) on the right
-        phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+        {
+            StageTimer t("re_contraction", st);
+            phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+        }
         apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
         if (precision == EPHX_FP32) convert_f64_f32((long)nb * nre_cols * 2, gp, gp32, st);
         if (nsplit) split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
@@ -366,13 +431,19 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         for (int q0 = 0; q0 < nq; q0 += qc) {
             const int nqc = std::min(qc, nq - q0);
             const double* qb = q + 3L * q0;
-            // H(k+q) for every pair, then its eigenpairs in FP64
-            if (f32)
-                phase_gemm_f32(nqc, nw2, m->n_re, nb, qb, kb, m->d_re, m->d_h32, 0, (float*)hkq, (long)nqc * nw2, st);
-            else
+            // H(k+q) for every pair and its eigenpairs, in FP64 for every precision:
+            // an FP32 sum perturbs H by ~1e-7 |H| and mixes bands closer than
+            // ~1e-2 eV at the 1e-5 level of |g|^2.
+            {
+                StageTimer t("hkq_fourier", st);
                 phase_gemm_f64(nqc, nw2, m->n_re, nb, qb, kb, m->d_re, m->d_h, 0, (double*)hkq, (long)nqc * nw2, st);
-            eig_herm(nb * nqc, nw, hkq, f32 ? 1 : 0, nw2, ekq, ukq, st);
+            }
+            {
+                StageTimer t("eig_hkq", st);
+                eig_herm(nb * nqc, nw, hkq, 0, nw2, ekq, ukq, st);
+            }
             // Rp contraction per k
+            StageTimer trp("rp_contraction", st);
             if (precision == EPHX_FP64)
                 phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, (double*)gw,
                                (long)nqc * ngcol, st);
@@ -382,6 +453,8 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             else
                 phase_gemm_bf16(nsplit, nqc, (int)ngcol, m->n_rp_g, kp, nb, qb, nullptr, m->d_rp_g, gpbf,
                                 2L * nsplit * ngcol * kp, (float*)gw, (long)nqc * ngcol, st);
+            trp.stop();
+            StageTimer tep("epilogue", st);
             EphEpilogue e{};
             e.nkb = nb;
             e.nq = nqc;

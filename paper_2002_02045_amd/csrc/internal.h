@@ -129,34 +129,37 @@ struct PairEpilogue {
     const double* us;     // [S][nw][nw] complex, U(k_s) (polar term)
     const double* minv;
     double omega_cut;
-    float* g2raw;         // [nm][S][S]
+    float* g2raw;         // set by the launcher for FP32 tables
 };
-void pair_epilogue(const PairEpilogue& e, int f32, hipStream_t st);
+// Leading dimension (elements) of S x S tables: rows start 256-byte aligned.
+long table_ld(int S);
+void pair_epilogue(const PairEpilogue& e, int f32, long ld, void* g2out, hipStream_t st);
 // g'(s)[p][x][i] = sum_j g(s)[p][x][i][j] U(k_s)[j][band_s]
 void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const double* us,
                     const int32_t* band, double* out, hipStream_t st);
-void table_symmetrise(int nm, int S, float* g2, hipStream_t st);
-void gather_omega_pairs(int S, int nm, const int32_t* kc, int n1, int n2, int n3,
-                        const double* omega, float* om_pairs, hipStream_t st);
-void build_collision_matrix(int S, int nm, const float* g2, const float* om_pairs,
-                            const double* eps, double temp, double sigma, double omega_cut,
-                            const double* mode_scale, float* pmat, float* pmode, hipStream_t st);
-void build_transport_matrix(int S, int nm, const float* g2, const float* om_pairs,
-                            const double* eps, double temp, double mu, double sigma,
-                            double omega_cut, float* wmat, hipStream_t st);
+void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st);
+// transport = 0: collision matrix P (mode scales applied);
+// transport = 1: scattering probabilities W (Eq. BTE_W, 1/fs, scale ignored but required)
+void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc,
+                  int n1, int n2, int n3, const double* omega, const double* eps, double temp,
+                  double mu, double sigma, double omega_cut, const double* scale, void* out,
+                  hipStream_t st);
 
-// Streaming pass over a dense S x S float matrix P:
+// Streaming pass over a dense S x S matrix P (row stride ld):
 //   rowp[a][ct][s] = sum_{t in col tile ct} P[s][t] x_a[t]      (a < na)
 //   colp[b][rt][t] = sum_{s in row tile rt} P[s][t] y_b[s]      (b < nb)
+struct VecPtrs {
+    const double* p[4];
+};
 struct StreamPlan {
     int S;
     int n_rt, n_ct;       // row and column tiles
 };
 StreamPlan stream_plan(int S);
-void stream_pass(const StreamPlan& pl, const float* P, int na, const double* const* x, int nb,
-                 const double* const* y, double* rowp, double* colp, hipStream_t st);
+void stream_pass(const StreamPlan& pl, long ld, const void* P, int f32, int na, VecPtrs x, int nb, VecPtrs y,
+                 double* rowp, double* colp, hipStream_t st);
 // I_s = -c [ f_s R_s - (1-f_s) C_s ] with R, C the reduced partials; optional
-// RK4 stage update: acc += w_acc * dt * I ; f_stage = f_base + a_next * dt * I.
+// RK4 stage update: acc = (acc_init ? f_base : acc) + w_acc * I ; f_next = f_base + a_next * I.
 struct CollisionFinish {
     int S;
     int n_rt, n_ct;
@@ -165,14 +168,36 @@ struct CollisionFinish {
     const double* f;      // occupations the integral is evaluated at
     double c;             // (2 pi/hbar)/N_q
     double* i_out;        // I (may be nullptr)
-    // stage update (enabled when acc != nullptr)
-    double* acc;
-    double w_acc;         // weight of this stage in the RK4 combination (times dt)
+    double* acc;          // stage accumulator (nullptr: no update)
+    int acc_init;
+    double w_acc;
     const double* f_base;
-    double a_next;        // f_next = f_base + a_next * I
-    double* f_next;
+    double a_next;
+    double* f_next;       // may be nullptr
 };
 void collision_finish(const CollisionFinish& cf, hipStream_t st);
+void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
+                double* fbar, hipStream_t st);
+// s_bar[nu] (= or +=) -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t); part: [nm][S] scratch
+void mode_vjp(int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2, int n3,
+              const double* omega, const double* eps, double temp, double sigma, double omega_cut,
+              const double* f, const double* lam, double* part, double c, double* sbar, int accumulate,
+              hipStream_t st);
+void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0,
+               double* f, hipStream_t st);
+void ita_update(int S, int n_ct, const double* rowp, double n_q, const double* tau, const double* f0, double* f,
+                hipStream_t st);
+void mobility_reduce(int S, const double* eps, const double* vel, const double* f, double mu, double temp,
+                     double* fout, double* mob, hipStream_t st);
+struct Lincomb {
+    int n;
+    double c0;
+    double c[5];
+    const double* v[5];
+};
+void lincomb(int S, const Lincomb& lc, double* out, hipStream_t st);
+void occ_vectors(int S, const double* f, const double* lam, double* o0, double* o1, double* o2, hipStream_t st);
 void axpy_copy(int S, const double* x, double a, const double* y, double* out, hipStream_t st);
+void fill(long n, double v, double* out, hipStream_t st);
 
 }  // namespace ephx

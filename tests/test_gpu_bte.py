@@ -1,0 +1,248 @@
+"""GPU parity of the Boltzmann-equation half against the FP64 oracle, through
+the C ABI: grid/window states (bit-exact), the symmetrised pair table, the
+collision integral, RK4 dynamics, their adjoints and the iterative BTE.
+
+Tolerances: FP64 tables 1e-10 relative to the largest entry / result;
+FP32 tables 1e-5 (|g|^2) and 1e-4 (collision, dynamics); carrier number
+conserved to 1e-12 of sum |I|.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import group_labels
+from oracle import bte, grad, grid, interp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2002_02045_amd as px
+    return px
+
+
+@pytest.fixture(scope="module")
+def tiny(lib):
+    m = synth.make_config_model("tiny")
+    return m, lib.Model(m)
+
+
+def _oracle_states(m, n, count):
+    pts = grid.grid_points(n)
+    eps, _ = interp.bands(m, pts)
+    return grid.lowest_states(eps.numpy(), m.nw // 2, count), eps.numpy()
+
+
+def test_grid_states_bit_exact(lib, tiny):
+    _say("grid states tiny model 8^3")
+    m, dm = tiny
+    n = (8, 8, 8)
+    pts = grid.grid_points(n)
+    eps, _ = interp.bands(m, pts)
+    cbm = float(eps[:, m.nw // 2].min())
+    ko, bo = grid.window_states(eps.numpy(), m.nw // 2, m.nw, cbm - 0.01, cbm + 0.6)
+    kg, bg, eg = lib.grid_states(dm, n, mode="window", band_lo=m.nw // 2, band_hi=m.nw,
+                                 e_lo=cbm - 0.01, e_hi=cbm + 0.6)
+    assert len(ko) > 20
+    assert np.array_equal(ko, kg) and np.array_equal(bo, bg)
+    assert np.allclose(eg, eps.numpy()[ko, bo], atol=1e-12)
+    ko, bo = grid.lowest_states(eps.numpy(), m.nw // 2, 37)
+    kg, bg, _ = lib.grid_states(dm, n, mode="lowest", band_lo=m.nw // 2, count=37)
+    assert np.array_equal(ko, kg) and np.array_equal(bo, bg)
+    with pytest.raises(lib.EphxError):
+        lib.grid_states(dm, n, mode="lowest", band_lo=m.nw // 2, count=37, capacity=10)
+
+
+def _mode_group_sums(g2, omega):
+    """Sum a (nu, s, t) table over degenerate mode groups of each pair's q."""
+    lab = group_labels(np.asarray(omega))                 # (s, t, nu)
+    oh = torch.nn.functional.one_hot(torch.as_tensor(lab), g2.shape[0]).double()
+    return torch.einsum("vst,stva->ast", torch.as_tensor(np.asarray(g2), dtype=torch.float64), oh)
+
+
+@pytest.fixture(scope="module")
+def small_case(tiny):
+    m, _ = tiny
+    n = (6, 6, 6)
+    (kk, bb), _ = _oracle_states(m, n, 60)
+    g2s, om = bte.pair_table(m, n, kk, bb)
+    eps = bte.state_energies(m, kk, bb, n)
+    return n, kk, bb, g2s, om, eps
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)])
+def test_table_parity(lib, tiny, small_case, prec, tol):
+    _say("pair table tiny 6^3, S=60, prec=%s" % prec)
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = small_case
+    t = lib.PairTable(dm, n, kk, bb, precision=prec)
+    g, e = t.g2()
+    ref = _mode_group_sums(g2s.permute(2, 0, 1).numpy(), om.numpy())
+    got = _mode_group_sums(g.double().cpu().numpy(), om.numpy())
+    err = float((got - ref).abs().max() / ref.abs().max())
+    _say("  table error %.3e" % err)
+    assert err <= tol
+    assert float((e.cpu() - eps).abs().max()) <= 1e-12 * float(eps.abs().max())
+    assert torch.allclose(g.cpu(), g.cpu().transpose(1, 2))          # symmetrised
+
+
+@pytest.fixture(scope="module")
+def big_case(tiny):
+    """S = 1030 states: the streaming pass covers 5 row tiles and 2 column
+    tiles with ragged edges."""
+    m, _ = tiny
+    n = (12, 12, 12)
+    (kk, bb), _ = _oracle_states(m, n, 1030)
+    _say("oracle pair table S=%d (slow)" % len(kk))
+    g2s, om = bte.pair_table(m, n, kk, bb)
+    eps = bte.state_energies(m, kk, bb, n)
+    return n, kk, bb, g2s, om, eps
+
+
+PAR = dict(temp=300.0, sigma=0.02)
+
+
+def _oracle_collision(case, f, scale=None):
+    n, kk, bb, g2s, om, eps = case
+    nq = float(np.prod(n))
+    return bte.collision(torch.as_tensor(f), eps, g2s, om, n_q=nq, mode_scale=scale, **PAR)
+
+
+@pytest.fixture(scope="module")
+def big_table(lib, tiny, big_case):
+    m, dm = tiny
+    n, kk, bb = big_case[:3]
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=float(np.prod(n))))
+    return t
+
+
+def test_collision_parity_and_conservation(lib, big_case, big_table):
+    _say("collision S=1030 fp64")
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        f = rng.random(len(big_case[1])) * (0.5 if trial else 1e-3)
+        ref = _oracle_collision(big_case, f)
+        got = big_table.collision(f).cpu()
+        err = float((got - ref).abs().max() / ref.abs().max())
+        cons = abs(float(got.sum())) / float(got.abs().sum())
+        _say("  collision error %.3e, conservation %.3e" % (err, cons))
+        assert err <= 1e-10
+        assert cons <= 1e-12
+
+
+def test_collision_mode_scales(lib, tiny, small_case):
+    m, dm = tiny
+    n, kk, bb = small_case[:3]
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    s = np.array([1.0, 0.5, 2.0, 0.0, 1.5, 0.7])
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=float(np.prod(n))), mode_scale=s)
+    f = np.random.default_rng(4).random(len(kk)) * 0.3
+    ref = _oracle_collision(small_case, f, torch.as_tensor(s))
+    got = t.collision(f).cpu()
+    assert float((got - ref).abs().max() / ref.abs().max()) <= 1e-10
+
+
+def test_dynamics_parity_and_checkpoints(lib, big_case, big_table):
+    _say("RK4 dynamics S=1030 fp64, 12 steps")
+    n, kk, bb, g2s, om, eps = big_case
+    e0 = float(eps.min())
+    f0 = 0.1 * np.exp(-((eps.numpy() - e0 - 0.3) / 0.1) ** 2)
+    nq = float(np.prod(n))
+    rhs = lambda x: bte.collision(x, eps, g2s, om, n_q=nq, **PAR)
+    ref, saved = bte.integrate(torch.as_tensor(f0), 1.0, 12, rhs, keep_every=4)
+    got, ck = big_table.dynamics(f0, 1.0, 12, ckpt_every=4)
+    err = float((got.cpu() - ref).abs().max() / ref.abs().max())
+    _say("  dynamics error %.3e" % err)
+    assert err <= 1e-10
+    for i, s in enumerate(saved):
+        assert float((ck[i].cpu() - s).abs().max()) <= 1e-10 * float(s.abs().max())
+    assert abs(float(got.sum()) - f0.sum()) <= 1e-12 * f0.sum()
+
+
+def test_collision_vjp_parity(lib, tiny, small_case):
+    _say("collision VJP fp64")
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = small_case
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=float(np.prod(n))))
+    rng = np.random.default_rng(5)
+    f = torch.as_tensor(rng.random(len(kk)) * 0.4).requires_grad_(True)
+    s = torch.ones(m.nmodes, dtype=torch.float64, requires_grad=True)
+    lam = torch.as_tensor(rng.standard_normal(len(kk)))
+    i = bte.collision(f, eps, g2s, om, n_q=float(np.prod(n)), mode_scale=s, **PAR)
+    (i * lam).sum().backward()
+    fb, sb = t.collision_vjp(f.detach().numpy(), lam.numpy())
+    assert float((fb.cpu() - f.grad).abs().max() / f.grad.abs().max()) <= 1e-10
+    assert float((sb.cpu() - s.grad).abs().max() / s.grad.abs().max()) <= 1e-10
+
+
+def test_dynamics_vjp_parity(lib, tiny, small_case):
+    _say("dynamics VJP fp64, 10 steps, checkpoints every 5")
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = small_case
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    nq = 100.0 * float(np.prod(n))         # slows the dynamics so that dt = 1 fs is stable
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=nq))
+    e0 = float(eps.min())
+    f0 = 0.1 * np.exp(-((eps.numpy() - e0 - 0.3) / 0.1) ** 2) + 0.01
+    e_val, df0, ds = grad.dynamics_grad(torch.as_tensor(f0), eps, g2s, om, dt=1.0, n_steps=10, e_ref=e0,
+                                        n_q=nq, **PAR)
+    ff, ck = t.dynamics(f0, 1.0, 10, ckpt_every=5)
+    fc = ff.cpu()
+    en = eps - e0
+    etot = float((en * fc).sum() / fc.sum())
+    fbar = (en - etot) / fc.sum()                        # dE/df at the end
+    g0, gs = t.dynamics_vjp(ck, 1.0, 10, 5, fbar.numpy())
+    assert np.isfinite(e_val) and float(fc.sum()) > 0
+    assert abs(etot - e_val) <= 1e-12 * abs(e_val)
+    assert float((g0.cpu() - df0).abs().max() / df0.abs().max()) <= 1e-9
+    assert float((gs.cpu() - ds).abs().max() / ds.abs().max()) <= 1e-9
+
+
+def test_fp32_table_collision_and_dynamics(lib, tiny, small_case):
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = small_case
+    t = lib.PairTable(dm, n, kk, bb, precision="fp32")
+    nq = float(np.prod(n))
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=nq))
+    f = np.random.default_rng(6).random(len(kk)) * 0.4
+    ref = _oracle_collision(small_case, f)
+    got = t.collision(f).cpu()
+    assert float((got - ref).abs().max() / ref.abs().max()) <= 1e-4
+    assert abs(float(got.sum())) <= 1e-12 * float(got.abs().sum())
+
+
+def test_mobility_parity_real_model(lib):
+    _say("ITA mobility, real tiny model 8^3")
+    m = synth.make_config_model("tiny", real=True)
+    dm = lib.Model(m)
+    n = (8, 8, 8)
+    pts = grid.grid_points(n)
+    eps_g, _ = interp.bands(m, pts)
+    cbm = float(eps_g[:, m.nw // 2].min())
+    kk, bb = grid.window_states(eps_g.numpy(), m.nw // 2, m.nw, cbm - 0.01, cbm + 0.5)
+    g2s, om = bte.pair_table(m, n, kk, bb)
+    eps = bte.state_energies(m, kk, bb, n)
+    _, _, v = interp.bands(m, bte.state_points(kk, n), velocity=True)
+    vel = v[torch.arange(len(bb)), torch.as_tensor(bb)]
+    nq = float(np.prod(n))
+    mu = cbm - 0.3
+    w = bte.transport_matrix(eps, g2s, om, temp=300.0, mu=mu, sigma=0.02)
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    for it in (0, 5):
+        fo, tau_o = bte.ita(w, vel, nq, it)
+        mob_o = bte.mobility(eps, vel, fo, mu=mu, temp=300.0)
+        ff, tau, mob = t.mobility(lib.Params(temp=300.0, mu=mu, sigma=0.02, n_q=nq), vel.numpy(), it)
+        assert float((tau.cpu() - tau_o).abs().max() / tau_o.abs().max()) <= 1e-10
+        assert float((ff.cpu() - fo).abs().max() / fo.abs().max()) <= 1e-10
+        assert float((mob.cpu() - mob_o).abs().max() / mob_o.abs().max()) <= 1e-10
