@@ -33,6 +33,9 @@ def _parse():
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dyn-steps", type=int, default=200, help="timed RK4 steps of the dynamics workload (0: skip)")
+    ap.add_argument("--dyn-grid", type=int, default=80)
+    ap.add_argument("--dyn-states", type=int, default=20_000)
     return ap.parse_args()
 
 
@@ -142,6 +145,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(model, kpts, q, cfg, args.cpu_seconds)
 
+    dyn = None
+    if args.dyn_steps > 0:
+        dyn = dynamics_bench(px, dm, model, args)
+
     out = {
         "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, Si-like)",
         "value": r["pairs_per_s"],
@@ -163,8 +170,77 @@ def main():
         "cpu_baseline": cpu,
         "by_precision": {p: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in d.items()}
                          for p, d in results.items()},
+        "dynamics": dyn,
     }
     print(json.dumps(out), flush=True)
+
+
+def dynamics_bench(px, dm, model, args):
+    """BTE collision steps/s: RK4 time stepping of f_nk(t) (Eq. BTE_E with E = 0,
+    collision integral of Eq. e_ph_scattering) on the lowest conduction states of
+    an n^3 Gamma-centred grid with a stored FP32 |g|^2 pair table.  One step =
+    four collision evaluations + stage updates."""
+    import torch
+
+    import synth
+    cfg = synth.CONFIGS["dyn"]
+    n = (args.dyn_grid,) * 3
+    nw = model.nw
+    t0 = time.perf_counter()
+    kk, bb, ee = px.grid_states(dm, n, mode="lowest", band_lo=nw // 2, count=args.dyn_states)
+    t_states = time.perf_counter() - t0
+    S = len(kk)
+    t0 = time.perf_counter()
+    tab = px.PairTable(dm, n, kk, bb, precision="fp32")
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    nq = float(np.prod(n))
+    par = px.Params(temp=cfg["T"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"], n_q=nq)
+    t0 = time.perf_counter()
+    tab.setup(par)
+    t_setup = time.perf_counter() - t0
+    cbm = float(ee.min())
+    f0 = cfg["f0_peak"] * np.exp(-((ee - cbm - cfg["f0_centre"]) ** 2) / (2 * cfg["f0_width"] ** 2))
+    f0 = torch.as_tensor(f0, device="cuda")
+    log("dynamics: %d states (span %.3f eV) on %s grid; states %.1fs, table %.1fs, setup %.1fs" % (
+        S, float(ee.max() - ee.min()), "x".join(map(str, n)), t_states, t_table, t_setup))
+    tab.dynamics(f0, cfg["dt"], 2)                         # warmup
+    torch.cuda.synchronize()
+    px.timer_reset()
+    px.timer_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f1, _ = tab.dynamics(f0, cfg["dt"], args.dyn_steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    px.timer_enable(False)
+    ns, ms = px.timer_get("collision_stream")
+    nf, msf = px.timer_get("collision_finish")
+    px.timer_reset()
+    ld = (S + 63) // 64 * 64
+    alg_bytes = 4.0 * S * S                               # the FP32 collision matrix, read once
+    achieved = alg_bytes / (ms / ns * 1e-3) / 1e9
+    drift = abs(float(f1.sum() - f0.sum())) / float(f0.sum())
+    if not np.isfinite(drift):
+        raise RuntimeError("dynamics produced non-finite occupations")
+    log("dynamics: %.1f RK4 steps/s, collision_stream %.3f ms avg = %.0f GB/s (%.1f%% of HBM), number drift %.2e" % (
+        args.dyn_steps / dt, ms / ns, achieved, 100 * achieved / HBM_GBS, drift))
+    out = {
+        "metric": "BTE collision steps/s (RK4 steps of the carrier dynamics)",
+        "value": args.dyn_steps / dt, "unit": "RK4 steps/s", "steps": args.dyn_steps,
+        "ms_per_step": 1e3 * dt / args.dyn_steps, "dtype": "f32 table, f64 state",
+        "config": {"workload": "si-like dynamics: %s grid, %d lowest conduction states (span %.3f eV), 6 modes, "
+                               "FP32 pair table, sigma=8 meV, T_ph=300 K, dt=1 fs" % (
+                                   "x".join(map(str, n)), S, float(ee.max() - ee.min()))},
+        "roofline": {"bound": "hbm", "kernel": "collision_stream", "achieved": round(achieved, 1),
+                     "peak": HBM_GBS, "unit": "GB/s", "frac": round(achieved / HBM_GBS, 4), "traffic": None,
+                     "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5)},
+        "collision_evals_per_s": ns / (1e-3 * (ms + msf)) if ms > 0 else None,
+        "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
+        "carrier_number_drift": drift,
+    }
+    tab.close()
+    return out
 
 
 def group_sums(px, dm, ks, qs, g2):

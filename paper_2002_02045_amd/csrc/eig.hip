@@ -1,138 +1,170 @@
 // Batched Hermitian eigensolver in FP64 for the small matrices of the method:
 // H(k) and H(k+q) (n = Nw, Eq. wannier_3) and D(q) (n = 3 nat, Eq. IFC2).
 //
-// One 64-lane wavefront owns one matrix (n <= 8, lane = matrix element
-// (i, j)).  Cyclic Jacobi with the round-robin (tournament) ordering applies
-// n/2 disjoint plane rotations at once, so every lane updates its element from
-// four entries of the previous iterate:
-//   A'_ij = a_i a_j A_ij + a_i b_j A_ij' + conj(b_i) a_j A_i'j + conj(b_i) b_j A_i'j'
-//   V'_ij = a_j V_ij + b_j V_ij'
-// where j' is the partner of j in the current round and column j of the
-// rotation is (a_j at row j, b_j at row j').  A pair (p, q) with a_pq =
-// |a_pq| e^{i phi} uses t = sgn(th)/(|th| + sqrt(th^2+1)), th = (a_qq - a_pp)/(2|a_pq|),
-// c = 1/sqrt(1+t^2), s = t c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi} (Golub & Van Loan,
-// "Matrix Computations", Sec. 8.5, in its complex Hermitian form).  Sweeps run
-// until the off-diagonal Frobenius norm is below 1e-15 of the total, then the
-// eigenpairs are sorted ascending.
+// Cyclic Jacobi with the round-robin (tournament) ordering, so each round
+// applies n/2 disjoint plane rotations at once (Golub & Van Loan, "Matrix
+// Computations", Sec. 8.5, in its complex Hermitian form).  For a pair (p, q)
+// with a_pq = |a_pq| e^{i phi}:
+//   th = (a_qq - a_pp)/(2|a_pq|), t = sgn(th)/(|th| + sqrt(th^2 + 1)),
+//   c = 1/sqrt(1 + t^2), s = t c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi},
+// and A <- J^dag A J, V <- V J.
+//
+// Layout: one lane per matrix row, R = 2^ceil(log2 n) lanes per matrix, so a
+// 64-lane wavefront works on 64/R matrices at once.  Column rotations (A J,
+// V J) act inside a lane's own row; row rotations (J^dag A) take the partner
+// row with cross-lane shuffles.  The matrix order n is a template parameter,
+// which unrolls every round of the tournament into register code.  Sweeps
+// run until the off-diagonal Frobenius norm of every matrix in the wavefront
+// is below 1e-15 of its norm; eigenpairs are then sorted ascending.
 #include "internal.h"
 
 namespace ephx {
 namespace {
 
-__device__ __forceinline__ int rr_partner(int idx, int r, int ne) {
+template <int NE>
+__device__ __forceinline__ int rr_partner(int idx, int r) {
     // circle method: position 0 fixed, the others rotate by r each round
-    const int m = ne - 1;
-    int pos;
-    if (idx == 0) pos = 0;
-    else pos = ((idx - 1 - r) % m + m) % m + 1;
-    const int pp = ne - 1 - pos;
-    if (pp == 0) return 0;
-    return (pp - 1 + r) % m + 1;
+    constexpr int m = NE - 1;
+    const int pos = idx == 0 ? 0 : ((idx - 1 - r) % m + m) % m + 1;
+    const int pp = NE - 1 - pos;
+    return pp == 0 ? 0 : (pp - 1 + r) % m + 1;
 }
 
-struct cplx {
-    double x, y;
-};
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ __forceinline__ cplx cconj(cplx a) { return {a.x, -a.y}; }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ cplx cscale(double s, cplx a) { return {s * a.x, s * a.y}; }
+__device__ __forceinline__ double shfl(double v, int src) { return __shfl(v, src, 64); }
 
-template <typename Tin>
-__global__ __launch_bounds__(64) void k_eig_herm(int batch, int n, const Tin* __restrict__ A, long strideA,
-                                                 double* __restrict__ evals, double* __restrict__ evecs) {
-    __shared__ cplx a[64];
-    __shared__ cplx v[64];
-    __shared__ double ra[kEigMax + 1];
-    __shared__ cplx rb[kEigMax + 1];
-    __shared__ int rank[kEigMax];
-    const int b = blockIdx.x;
-    if (b >= batch) return;
-    const int l = threadIdx.x;
-    const int nn = n * n;
-    const bool act = l < nn;
-    const int i = act ? l / n : 0, j = act ? l % n : 0;
-    const Tin* ab = A + (long)b * strideA * 2;
-    if (act) {
-        // Hermitian part 0.5 (A + A^dag)
-        const double xr = (double)ab[2 * (i * n + j)], xi = (double)ab[2 * (i * n + j) + 1];
-        const double yr = (double)ab[2 * (j * n + i)], yi = (double)ab[2 * (j * n + i) + 1];
-        a[l] = {0.5 * (xr + yr), 0.5 * (xi - yi)};
-        v[l] = {i == j ? 1.0 : 0.0, 0.0};
+template <typename Tin, int N>
+__global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restrict__ A, long strideA,
+                                                  double* __restrict__ evals, double* __restrict__ evecs) {
+    constexpr int R = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
+    constexpr int NE = N + (N & 1);
+    const int lane = threadIdx.x & 63;
+    const long slot = ((long)blockIdx.x * 256 + threadIdx.x) / R;
+    const int i = lane % R;
+    const int base = lane - i;
+    const bool valid = slot < batch;
+    const bool act = valid && i < N;
+    double ar[N], ai[N], vr[N], vi[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        ar[j] = ai[j] = vi[j] = 0.0;
+        vr[j] = (j == i) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    const int ne = n + (n & 1);
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        // convergence test on the current iterate
-        double off = 0.0, tot = 0.0;
-        if (act) {
-            const double m2 = a[l].x * a[l].x + a[l].y * a[l].y;
-            tot = m2;
-            off = (i != j) ? m2 : 0.0;
+    if (act) {
+        const Tin* ab = A + slot * strideA * 2;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            // Hermitian part 0.5 (A + A^dag)
+            const double xr = (double)ab[2 * (i * N + j)], xi = (double)ab[2 * (i * N + j) + 1];
+            const double yr = (double)ab[2 * (j * N + i)], yi = (double)ab[2 * (j * N + i) + 1];
+            ar[j] = 0.5 * (xr + yr);
+            ai[j] = 0.5 * (xi - yi);
         }
-        for (int w = 32; w >= 1; w >>= 1) {
+    }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double m2 = ar[j] * ar[j] + ai[j] * ai[j];
+            tot += m2;
+            off += (j != i) ? m2 : 0.0;
+        }
+#pragma unroll
+        for (int w = R / 2; w >= 1; w >>= 1) {
             off += __shfl_xor(off, w, 64);
             tot += __shfl_xor(tot, w, 64);
         }
-        if (!(off > 1e-30 * tot)) break;
-        for (int r = 0; r < ne - 1; ++r) {
-            if (l < ne) {
-                ra[l] = 1.0;
-                rb[l] = {0.0, 0.0};
+        const bool done = !(off > 1e-30 * tot);
+        if (__all(done)) break;
+#pragma unroll
+        for (int r = 0; r < NE - 1; ++r) {
+            const int p = i < NE ? rr_partner<NE>(i, r) : i;
+            // rotation of the pair (i, p), computed by its lower lane
+            double dself = 0.0, apr = 0.0, api = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                dself = (j == i) ? ar[j] : dself;
+                apr = (j == p) ? ar[j] : apr;
+                api = (j == p) ? ai[j] : api;
             }
-            __syncthreads();
-            if (act && i < j && rr_partner(i, r, ne) == j) {
-                const cplx apq = a[i * n + j];
-                const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+            const double dpart = shfl(dself, base + (p < R ? p : i));
+            double c = 1.0, ser = 0.0, sei = 0.0;   // se = s e^{i phi}
+            if (i < p && p < N) {
+                const double mag = sqrt(apr * apr + api * api);
                 if (mag > 0.0) {
-                    const double th = (a[j * n + j].x - a[i * n + i].x) / (2.0 * mag);
+                    const double th = (dpart - dself) / (2.0 * mag);
                     const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                    const double c = 1.0 / sqrt(t * t + 1.0);
+                    c = 1.0 / sqrt(t * t + 1.0);
                     const double s = t * c;
-                    const cplx e = {apq.x / mag, apq.y / mag};
-                    ra[i] = c;
-                    ra[j] = c;
-                    rb[i] = cscale(-s, cconj(e));   // J_{j,i}: row j of column i
-                    rb[j] = cscale(s, e);           // J_{i,j}: row i of column j
+                    ser = s * apr / mag;
+                    sei = s * api / mag;
                 }
             }
-            __syncthreads();
-            cplx na = {0, 0}, nv = {0, 0};
-            if (act) {
-                const int ip = rr_partner(i, r, ne), jp = rr_partner(j, r, ne);
-                const double ai = ra[i], aj = ra[j];
-                const cplx bi = rb[i], bj = rb[j];
-                na = cscale(ai * aj, a[i * n + j]);
-                if (jp < n) na = cadd(na, cscale(ai, cmul(a[i * n + jp], bj)));
-                if (ip < n) na = cadd(na, cscale(aj, cmul(cconj(bi), a[ip * n + j])));
-                if (ip < n && jp < n) na = cadd(na, cmul(cmul(cconj(bi), a[ip * n + jp]), bj));
-                nv = cscale(aj, v[i * n + j]);
-                if (jp < n) nv = cadd(nv, cmul(v[i * n + jp], bj));
+            // column rotations A J and V J, every pair of the round (indices are compile-time)
+#pragma unroll
+            for (int p0 = 0; p0 < N; ++p0) {
+                const int q0 = rr_partner<NE>(p0, r);
+                if (!(p0 < q0 && q0 < N)) continue;
+                const double cc = shfl(c, base + p0), sr = shfl(ser, base + p0), si = shfl(sei, base + p0);
+                // (AJ)_{.p} = c A_.p - conj(se) A_.q ; (AJ)_{.q} = se A_.p + c A_.q
+                const double xr = ar[p0], xi = ai[p0], yr = ar[q0], yi = ai[q0];
+                ar[p0] = cc * xr - (sr * yr + si * yi);
+                ai[p0] = cc * xi - (sr * yi - si * yr);
+                ar[q0] = (sr * xr - si * xi) + cc * yr;
+                ai[q0] = (sr * xi + si * xr) + cc * yi;
+                const double ur = vr[p0], ui = vi[p0], wr = vr[q0], wi = vi[q0];
+                vr[p0] = cc * ur - (sr * wr + si * wi);
+                vi[p0] = cc * ui - (sr * wi - si * wr);
+                vr[q0] = (sr * ur - si * ui) + cc * wr;
+                vi[q0] = (sr * ui + si * ur) + cc * wi;
             }
-            __syncthreads();
-            if (act) {
-                a[l] = na;
-                v[l] = nv;
+            // row rotation J^dag A with the partner row
+            const int lo = i < p ? i : p;
+            const double co = shfl(c, base + (lo < R ? lo : i));
+            const double sro = shfl(ser, base + (lo < R ? lo : i));
+            const double sio = shfl(sei, base + (lo < R ? lo : i));
+            const int src = base + (p < R ? p : i);
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const double qr = shfl(ar[j], src), qi = shfl(ai[j], src);
+                if (p < N && p != i) {
+                    if (i < p) {
+                        // (J^dag A)_{p.} = c A_p. - se A_q.
+                        const double nr = co * ar[j] - (sro * qr - sio * qi);
+                        const double ni = co * ai[j] - (sro * qi + sio * qr);
+                        ar[j] = nr;
+                        ai[j] = ni;
+                    } else {
+                        // (J^dag A)_{q.} = conj(se) A_p. + c A_q.
+                        const double nr = (sro * qr + sio * qi) + co * ar[j];
+                        const double ni = (sro * qi - sio * qr) + co * ai[j];
+                        ar[j] = nr;
+                        ai[j] = ni;
+                    }
+                }
             }
-            __syncthreads();
         }
     }
     // sort ascending, ties by index
-    if (l < n) {
-        const double d = a[l * n + l].x;
-        int rk = 0;
-        for (int m = 0; m < n; ++m) {
-            const double dm = a[m * n + m].x;
-            rk += (dm < d || (dm == d && m < l)) ? 1 : 0;
-        }
-        rank[l] = rk;
-        evals[(long)b * n + rk] = d;
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) d = (j == i) ? ar[j] : d;
+    int rk = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const double dm = shfl(d, base + m);
+        rk += (dm < d || (dm == d && m < i)) ? 1 : 0;
     }
-    __syncthreads();
-    if (evecs != nullptr && act) {
-        const long off = ((long)b * nn + i * n + rank[j]) * 2;
-        evecs[off] = v[l].x;
-        evecs[off + 1] = v[l].y;
+    if (act) evals[slot * N + rk] = d;
+    if (evecs != nullptr) {
+#pragma unroll
+        for (int c2 = 0; c2 < N; ++c2) {
+            const int rc = __shfl(rk, base + c2, 64);
+            if (act) {
+                const long off = ((slot * N + i) * N + rc) * 2;
+                evecs[off] = vr[c2];
+                evecs[off + 1] = vi[c2];
+            }
+        }
     }
 }
 
@@ -143,6 +175,27 @@ __global__ void k_phonon_omega(long count, double* lam) {
     lam[t] = (w2 >= 0.0 ? 1.0 : -1.0) * sqrt(fabs(w2));
 }
 
+template <typename Tin>
+void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, double* evecs, hipStream_t st) {
+    const int R = n <= 1 ? 1 : (n <= 2 ? 2 : (n <= 4 ? 4 : 8));
+    const long threads = (long)batch * R;
+    dim3 grid((unsigned)((threads + 255) / 256));
+    switch (n) {
+#define EPHX_EIG_CASE(NN) \
+    case NN: hipLaunchKernelGGL((k_eig_rows<Tin, NN>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); break;
+        EPHX_EIG_CASE(1)
+        EPHX_EIG_CASE(2)
+        EPHX_EIG_CASE(3)
+        EPHX_EIG_CASE(4)
+        EPHX_EIG_CASE(5)
+        EPHX_EIG_CASE(6)
+        EPHX_EIG_CASE(7)
+        EPHX_EIG_CASE(8)
+#undef EPHX_EIG_CASE
+        default: throw Error{-6, "eig_herm: matrix order above 8 is not supported in this build"};
+    }
+}
+
 }  // namespace
 
 void eig_herm(int batch, int n, const void* A, int a_f32, long strideA, double* evals, double* evecs,
@@ -150,11 +203,9 @@ void eig_herm(int batch, int n, const void* A, int a_f32, long strideA, double* 
     if (batch <= 0) return;
     if (n < 1 || n > kEigMax) throw Error{-6, "eig_herm: matrix order above 8 is not supported in this build"};
     if (a_f32)
-        hipLaunchKernelGGL(k_eig_herm<float>, dim3(batch), dim3(64), 0, st, batch, n, (const float*)A, strideA,
-                           evals, evecs);
+        launch_eig(batch, n, (const float*)A, strideA, evals, evecs, st);
     else
-        hipLaunchKernelGGL(k_eig_herm<double>, dim3(batch), dim3(64), 0, st, batch, n, (const double*)A,
-                           strideA, evals, evecs);
+        launch_eig(batch, n, (const double*)A, strideA, evals, evecs, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
 }

@@ -88,109 +88,132 @@ __device__ __forceinline__ float gauss_f(float x, float inv_sigma, float norm) {
     return norm * expf(-y2);
 }
 
-// One wavefront per (k, q) pair; lane <-> element (m, n), up to 4 elements per lane.
+// One 64-lane workgroup walks QPB consecutive (k, q) pairs of one k.  Per pair
+// the wavefront stages g'(k,q), U(k+q), the scaled mode eigenvectors
+// e[x][nu] sqrt(hbar^2/(2 M_x omega_nu)), the Bose factors, and the final-band
+// energies and Fermi factors in LDS (each computed once per pair); then lane
+// <-> element (m, n) (up to 4 elements per lane) forms
+//   g^H[x] = sum_i conj(U_im(k+q)) g'[x][i][n],  g_nu = sum_x es[x][nu] g^H[x]
+// and either writes |g_nu|^2 or accumulates the delta-weighted rate terms.
+constexpr int kQPB = 16;
+
 template <typename T, bool RATES>
-__global__ __launch_bounds__(256) void k_eph_epilogue(EphEpilogue e) {
-    extern __shared__ double red[];  // RATES: [4][nw*nw][nm]
-    constexpr int QPB = 64;
+__global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int nw = e.nw, nm = e.nm, nw2 = nw * nw, ng = nm * nw2;
+    cx<T>* s_gw = reinterpret_cast<cx<T>*>(smem);           // [nm][nw][nw]
+    cx<T>* s_u = s_gw + ng;                                  // [nw][nw]
+    cx<T>* s_es = s_u + nw2;                                 // [nm][nm]
+    double* s_d = reinterpret_cast<double*>(s_es + nm * nm); // nb[nm], om[nm], em[nw], fm[nw]
+    double* s_nb = s_d;
+    double* s_om = s_d + nm;
+    double* s_em = s_d + 2 * nm;
+    double* s_fm = s_d + 2 * nm + nw;
     const int z = blockIdx.y;
     const int blk = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nw = e.nw, nm = e.nm, nw2 = nw * nw;
-    const int q0 = blk * QPB, q1 = min(e.nq, q0 + QPB);
-    const T* gwz = reinterpret_cast<const T*>(e.gw) + (long)z * e.nq * nm * nw2 * 2;
+    const int lane = threadIdx.x;
+    const int q0 = blk * kQPB, q1 = min(e.nq, q0 + kQPB);
+    const T* gwz = reinterpret_cast<const T*>(e.gw) + (long)z * e.nq * ng * 2;
+    const double kt = kBoltzEv * e.temp;
 
     double acc[4][kMaxModes];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < kMaxModes; ++b) acc[a][b] = 0.0;
-
-    const double kt = kBoltzEv * e.temp;
-    for (int ql = q0 + wave; ql < q1; ql += 4) {
-        const long qg = (long)e.q_off + ql;               // global q index
-        const long pair = (long)z * e.nq + ql;
-        const T* gp = gwz + (long)ql * nm * nw2 * 2;
-        const double* uq = e.ukq + pair * nw2 * 2;
-        // per-mode amplitude sqrt(hbar^2/(2 M omega)) handled as amp_nu * e[x][nu] * minv[x]
-        double om[kMaxModes];
-        T amp[kMaxModes];
-        for (int nu = 0; nu < nm; ++nu) {
-            om[nu] = e.omega[qg * nm + nu];
-            amp[nu] = om[nu] > e.omega_cut ? (T)sqrt(kHbar2AmuA2 / (2.0 * om[nu])) : (T)0;
+    double en[4] = {0.0, 0.0, 0.0, 0.0};
+    if (RATES)
+        for (int t = 0; t < 4; ++t) {
+            const int el = lane + 64 * t;
+            if (el < nw2) en[t] = e.ek[(long)z * nw + el % nw];
         }
+    const T is = (T)(1.0 / e.sigma), nrm = (T)(1.0 / (sqrt(kPi) * e.sigma));
+
+    for (int ql = q0; ql < q1; ++ql) {
+        const long qg = (long)e.q_off + ql;
+        const long pair = (long)z * e.nq + ql;
+        const T* gp = gwz + (long)ql * ng * 2;
+        const double* uq = e.ukq + pair * nw2 * 2;
+        for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
+        for (int i = lane; i < nw2; i += 64) s_u[i] = ldd<T>(uq, i);
+        for (int i = lane; i < nm * nm; i += 64) {
+            const int x = i / nm, nu = i % nm;
+            const double om = e.omega[qg * nm + nu];
+            const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
+            s_es[i] = {(T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu)]), (T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu) + 1])};
+        }
+        if (lane < nm) {
+            const double om = e.omega[qg * nm + lane];
+            s_om[lane] = om;
+            s_nb[lane] = om > e.omega_cut ? 1.0 / expm1(om / kt) : 0.0;
+        }
+        if (RATES && lane < nw) {
+            const double em = e.ekq[pair * nw + lane];
+            s_em[lane] = em;
+            s_fm[lane] = 1.0 / (exp((em - e.mu) / kt) + 1.0);
+        }
+        __syncthreads();
+        const double wq = RATES ? (e.qw ? e.qw[qg] : e.uniform_w) : 0.0;
         for (int t = 0; t < 4; ++t) {
             const int el = lane + 64 * t;
             if (el >= nw2) break;
             const int m = el / nw, n = el % nw;
             cx<T> gh[kMaxModes];
             for (int x = 0; x < nm; ++x) {
-                cx<T> s = {0, 0};
-                for (int i = 0; i < nw; ++i) cjfma(s, ldd<T>(uq, (long)i * nw + m), ld(gp, ((long)x * nw + i) * nw + n));
-                gh[x] = s;
+                cx<T> a = {0, 0};
+                for (int i = 0; i < nw; ++i) cjfma(a, s_u[i * nw + m], s_gw[(x * nw + i) * nw + n]);
+                gh[x] = a;
             }
             if (e.lr != nullptr) {
                 // Wannier-gauge long-range term C(q) delta_ij, rotated: C(q) [U^dag(k+q) U(k)]_mn
                 cx<T> ov = {0, 0};
                 const double* ukz = e.uk + (long)z * nw2 * 2;
-                for (int i = 0; i < nw; ++i) cjfma(ov, ldd<T>(uq, (long)i * nw + m), ldd<T>(ukz, (long)i * nw + n));
+                for (int i = 0; i < nw; ++i) cjfma(ov, s_u[i * nw + m], ldd<T>(ukz, (long)i * nw + n));
                 for (int x = 0; x < nm; ++x) cfma(gh[x], ldd<T>(e.lr, qg * nm + x), ov);
             }
-            double fm = 0.0, em = 0.0, en = 0.0;
-            if (RATES) {
-                em = e.ekq[pair * nw + m];
-                en = e.ek[(long)z * nw + n];
-                fm = 1.0 / (exp((em - e.mu) / kt) + 1.0);
-            }
+            const double em = RATES ? s_em[m] : 0.0, fm = RATES ? s_fm[m] : 0.0;
             for (int nu = 0; nu < nm; ++nu) {
+                const double om = s_om[nu];
                 cx<T> g = {0, 0};
-                if (amp[nu] != (T)0) {
-                    for (int x = 0; x < nm; ++x) {
-                        cx<T> ev = ldd<T>(e.evec, (qg * nm + x) * nm + nu);
-                        ev.x *= (T)e.minv[x];
-                        ev.y *= (T)e.minv[x];
-                        cfma(g, ev, gh[x]);
-                    }
-                    g.x *= amp[nu];
-                    g.y *= amp[nu];
-                }
+                for (int x = 0; x < nm; ++x) cfma(g, s_es[x * nm + nu], gh[x]);
                 const T g2 = g.x * g.x + g.y * g.y;
                 if (!RATES) {
                     const long off = ((((long)(e.k_off + z) * e.nq_total + qg) * nm + nu) * nw + m) * nw + n;
-                    reinterpret_cast<T*>(e.g2)[off] = g2;
-                } else if (amp[nu] != (T)0) {
-                    const double nb = 1.0 / expm1(om[nu] / kt);
-                    const double wq = e.qw ? e.qw[qg] : e.uniform_w;
-                    double d_em, d_ab;
-                    if (sizeof(T) == 4) {
-                        const float is = (float)(1.0 / e.sigma), nr = (float)(1.0 / (sqrt(kPi) * e.sigma));
-                        d_em = gauss_f((float)(en - om[nu] - em), is, nr);
-                        d_ab = gauss_f((float)(en + om[nu] - em), is, nr);
-                    } else {
-                        const double is = 1.0 / e.sigma, nr = 1.0 / (sqrt(kPi) * e.sigma);
-                        d_em = gauss<double>(en - om[nu] - em, is, nr);
-                        d_ab = gauss<double>(en + om[nu] - em, is, nr);
-                    }
-                    acc[t][nu] += wq * (double)g2 * (d_em * (1.0 + nb - fm) + d_ab * (nb + fm));
+                    reinterpret_cast<T*>(e.g2)[off] = om > e.omega_cut ? g2 : (T)0;
+                } else if (om > e.omega_cut) {
+                    const double nb = s_nb[nu];
+                    const T x1 = (T)(en[t] - om - em) * is, x2 = (T)(en[t] + om - em) * is;
+                    const T d_em = x1 * x1 > (T)200 ? (T)0 : nrm * exp(-x1 * x1);
+                    const T d_ab = x2 * x2 > (T)200 ? (T)0 : nrm * exp(-x2 * x2);
+                    acc[t][nu] += wq * (double)g2 * ((double)d_em * (1.0 + nb - fm) + (double)d_ab * (nb + fm));
                 }
             }
         }
+        __syncthreads();
     }
     if (!RATES) return;
-    // deterministic block reduction: [wave][element][nu] -> partial[z][blk][n][nu]
+    // deterministic reduction over m: [element][nu] in LDS -> partial[z][blk][n][nu]
+    double* red = reinterpret_cast<double*>(smem);
     for (int t = 0; t < 4; ++t) {
         const int el = lane + 64 * t;
         if (el >= nw2) break;
-        for (int nu = 0; nu < nm; ++nu) red[((long)wave * nw2 + el) * nm + nu] = acc[t][nu];
+        for (int nu = 0; nu < nm; ++nu) red[(long)el * nm + nu] = acc[t][nu];
     }
     __syncthreads();
-    for (int o = tid; o < nw * nm; o += 256) {
+    for (int o = lane; o < nw * nm; o += 64) {
         const int n = o / nm, nu = o % nm;
-        double s = 0.0;
-        for (int w = 0; w < 4; ++w)
-            for (int m = 0; m < nw; ++m) s += red[((long)w * nw2 + m * nw + n) * nm + nu];
-        e.partial[(((long)z * e.nblk + blk) * nw + n) * nm + nu] = s * (2.0 * kPi / kHbarEvFs);
+        double sum = 0.0;
+        for (int m = 0; m < nw; ++m) sum += red[((long)m * nw + n) * nm + nu];
+        e.partial[(((long)z * e.nblk + blk) * nw + n) * nm + nu] = sum * (2.0 * kPi / kHbarEvFs);
     }
+}
+
+template <typename T>
+size_t epilogue_lds(int nw, int nm) {
+    const size_t ng = (size_t)nm * nw * nw;
+    const size_t stage = (ng + nw * nw + nm * nm) * 2 * sizeof(T) + (2 * nm + 2 * nw) * sizeof(double);
+    const size_t red = (size_t)nw * nw * nm * sizeof(double);
+    return stage > red ? stage : red;
 }
 
 __global__ void k_rates_reduce(int nblk, int nw, int nm, const double* __restrict__ partial, double* __restrict__ acc) {
@@ -357,25 +380,27 @@ void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {
     check_launch("convert");
 }
 
-int eph_epilogue_blocks(int nq) { return (nq + 63) / 64; }
+int eph_epilogue_blocks(int nq) { return (nq + kQPB - 1) / kQPB; }
 
 void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
+    const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);
+    if (lds > 65536) throw Error{-6, "gkq: nw^2 * 3nat too large for one workgroup's staging buffer"};
     if (f32)
-        hipLaunchKernelGGL((k_eph_epilogue<float, false>), grid, dim3(256), 0, st, e);
+        hipLaunchKernelGGL((k_eph_epilogue<float, false>), grid, dim3(64), lds, st, e);
     else
-        hipLaunchKernelGGL((k_eph_epilogue<double, false>), grid, dim3(256), 0, st, e);
+        hipLaunchKernelGGL((k_eph_epilogue<double, false>), grid, dim3(64), lds, st, e);
     check_launch("eph_epilogue_g2");
 }
 
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
-    const size_t lds = (size_t)4 * e.nw * e.nw * e.nm * sizeof(double);
-    if (lds > 65536) throw Error{-6, "rates: nw^2 * 3nat too large for one workgroup's reduction buffer"};
+    const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);
+    if (lds > 65536) throw Error{-6, "rates: nw^2 * 3nat too large for one workgroup's staging buffer"};
     if (f32)
-        hipLaunchKernelGGL((k_eph_epilogue<float, true>), grid, dim3(256), lds, st, e);
+        hipLaunchKernelGGL((k_eph_epilogue<float, true>), grid, dim3(64), lds, st, e);
     else
-        hipLaunchKernelGGL((k_eph_epilogue<double, true>), grid, dim3(256), lds, st, e);
+        hipLaunchKernelGGL((k_eph_epilogue<double, true>), grid, dim3(64), lds, st, e);
     check_launch("eph_epilogue_rates");
 }
 

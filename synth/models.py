@@ -243,7 +243,9 @@ SEED_BASE = 20020205
 
 # Workload definitions.  Physical parameters follow the readings listed in the
 # design notes: Gaussian delta exp(-(x/s)^2)/(sqrt(pi) s), mu at the midpoint of
-# the onsite levels (0 eV, inside the gap), omega_cut = 1e-4 eV.
+# the onsite levels (0 eV, inside the gap), omega_cut = 1e-4 eV.  The coupling
+# amplitude a_g of the Si-like models gives |g| of tens of meV and relaxation
+# rates of ~0.1/fs near the band edge, so RK4 with dt = 1 fs is stable.
 CONFIGS = {
     "tiny": dict(
         lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=4, n_grid=4,
@@ -252,18 +254,18 @@ CONFIGS = {
     ),
     "si": dict(
         lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=8, n_grid=8,
-        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 2,
+        a_h=0.015, nn_hop=0.1, a_g=0.09, s_k=0.1, seed=SEED_BASE + 2,
         nk=5000, nq=1_000_000, window=0.3, T=300.0, sigma=0.005, mu=0.0, omega_cut=1e-4,
     ),
     "gaas": dict(
         lattice="fcc", a=A_GAAS, nat=2, masses=(M_GA, M_AS), nw=8, n_grid=8,
-        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 3,
+        a_h=0.015, nn_hop=0.1, a_g=0.09, s_k=0.1, seed=SEED_BASE + 3,
         real=True, zstar=2.1, eps_inf=10.9, k_grid=100, window=0.2, T=300.0, sigma=0.005,
         n_c=1e17, omega_cut=1e-4,
     ),
     "dyn": dict(
         lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=8, n_grid=8,
-        a_h=0.015, nn_hop=0.1, a_g=0.5, s_k=0.1, seed=SEED_BASE + 2,
+        a_h=0.015, nn_hop=0.1, a_g=0.09, s_k=0.1, seed=SEED_BASE + 2,
         k_grid=80, n_states=20_000, T=300.0, sigma=0.008, dt=1.0, n_steps=1000,
         ckpt_every=50, f0_peak=0.1, f0_centre=0.3, f0_width=0.05, omega_cut=1e-4,
     ),

@@ -153,3 +153,26 @@ def test_error_paths(lib, tiny):
     assert ei.value.code == -5
     e0, _, _ = lib.bands(dm, np.zeros((0, 3)))
     assert e0.shape == (0, m.nw)
+
+
+def test_polar_gkq_and_rates_parity(lib):
+    """GaAs-like polar model: the Froehlich term (Eq. e_ph_long, smooth-phase
+    bra-ket) is added in the Wannier gauge before the rotation."""
+    _say("polar gkq/rates parity (GaAs-like, 4^3 set, nw=4)")
+    m = synth.make_config_model("gaas", n_grid=4, nw=4)
+    a = synth.models.A_GAAS
+    pol = dict(alpha_ewald=(2 * np.pi / a) ** 2, gcut=4 * 2 * np.pi / a)
+    dm = lib.Model(m, polar=pol)
+    k = synth.random_points(111, 12)
+    q = np.vstack([synth.random_points(112, 70), 1e-3 * np.array([[0.3, -0.2, 0.1]])])   # includes small q
+    blk = eph.eph_pipeline(m, k, q, polar=pol)
+    ref = group_sums_g2(blk["g"].abs() ** 2, blk["eps_k"], blk["eps_kq"], blk["omega"])
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        g2 = lib.gkq(dm, k, q, precision=prec)
+        got = group_sums_g2(g2.double().cpu().numpy(), blk["eps_k"], blk["eps_kq"], blk["omega"])
+        emax, _ = g2_error(got, ref)
+        _say("  polar |g|^2 error %s: %.3e" % (prec, emax))
+        assert emax <= tol
+    go, _ = eph.rates(m, k, q, temp=300.0, mu=0.0, sigma=0.05, polar=pol)
+    g, _ = lib.rates(dm, k, q, lib.Params(temp=300.0, mu=0.0, sigma=0.05))
+    assert rate_error(g.cpu().numpy(), go.numpy()) <= 1e-10
