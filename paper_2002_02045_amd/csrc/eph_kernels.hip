@@ -74,20 +74,6 @@ __global__ void k_convert(long count, const double* __restrict__ in, float* __re
     if (t < count) out[t] = (float)in[t];
 }
 
-template <typename T>
-__device__ __forceinline__ T gauss(T x, T inv_sigma, T norm) {
-    const T y = x * inv_sigma;
-    const T y2 = y * y;
-    if (y2 > (T)200) return (T)0;
-    return norm * exp(-y2);
-}
-__device__ __forceinline__ float gauss_f(float x, float inv_sigma, float norm) {
-    const float y = x * inv_sigma;
-    const float y2 = y * y;
-    if (y2 > 200.f) return 0.f;
-    return norm * expf(-y2);
-}
-
 // One 64-lane workgroup walks QPB consecutive (k, q) pairs of one k.  Per pair
 // the wavefront stages g'(k,q), U(k+q), the scaled mode eigenvectors
 // e[x][nu] sqrt(hbar^2/(2 M_x omega_nu)), the Bose factors, and the final-band
@@ -97,10 +83,14 @@ __device__ __forceinline__ float gauss_f(float x, float inv_sigma, float norm) {
 // and either writes |g_nu|^2 or accumulates the delta-weighted rate terms.
 constexpr int kQPB = 16;
 
-template <typename T, bool RATES>
+// NW, NM > 0 fix the band and mode counts at compile time (fully unrolled,
+// register-resident accumulators); NW = NM = 0 is the runtime-sized fallback.
+template <typename T, bool RATES, int NW, int NM>
 __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int nw = e.nw, nm = e.nm, nw2 = nw * nw, ng = nm * nw2;
+    constexpr int EPT = NW > 0 ? (NW * NW + 63) / 64 : 4;      // elements per lane
+    constexpr int MM = NM > 0 ? NM : kMaxModes;
+    const int nw = NW > 0 ? NW : e.nw, nm = NM > 0 ? NM : e.nm, nw2 = nw * nw, ng = nm * nw2;
     cx<T>* s_gw = reinterpret_cast<cx<T>*>(smem);           // [nm][nw][nw]
     cx<T>* s_u = s_gw + ng;                                  // [nw][nw]
     cx<T>* s_es = s_u + nw2;                                 // [nm][nm]
@@ -116,14 +106,17 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
     const T* gwz = reinterpret_cast<const T*>(e.gw) + (long)z * e.nq * ng * 2;
     const double kt = kBoltzEv * e.temp;
 
-    double acc[4][kMaxModes];
+    double acc[EPT][MM];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < EPT; ++a)
 #pragma unroll
-        for (int b = 0; b < kMaxModes; ++b) acc[a][b] = 0.0;
-    double en[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < MM; ++b) acc[a][b] = 0.0;
+    double en[EPT];
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) en[t] = 0.0;
     if (RATES)
-        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
             const int el = lane + 64 * t;
             if (el < nw2) en[t] = e.ek[(long)z * nw + el % nw];
         }
@@ -154,14 +147,17 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
         }
         __syncthreads();
         const double wq = RATES ? (e.qw ? e.qw[qg] : e.uniform_w) : 0.0;
-        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
             const int el = lane + 64 * t;
             if (el >= nw2) break;
             const int m = el / nw, n = el % nw;
-            cx<T> gh[kMaxModes];
-            for (int x = 0; x < nm; ++x) {
+            cx<T> gh[MM];  // register-resident when NM is fixed
+#pragma unroll
+            for (int x = 0; x < MM; ++x) {
                 cx<T> a = {0, 0};
-                for (int i = 0; i < nw; ++i) cjfma(a, s_u[i * nw + m], s_gw[(x * nw + i) * nw + n]);
+                if (x < nm)
+                    for (int i = 0; i < nw; ++i) cjfma(a, s_u[i * nw + m], s_gw[(x * nw + i) * nw + n]);
                 gh[x] = a;
             }
             if (e.lr != nullptr) {
@@ -169,13 +165,19 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
                 cx<T> ov = {0, 0};
                 const double* ukz = e.uk + (long)z * nw2 * 2;
                 for (int i = 0; i < nw; ++i) cjfma(ov, s_u[i * nw + m], ldd<T>(ukz, (long)i * nw + n));
-                for (int x = 0; x < nm; ++x) cfma(gh[x], ldd<T>(e.lr, qg * nm + x), ov);
+#pragma unroll
+                for (int x = 0; x < MM; ++x)
+                    if (x < nm) cfma(gh[x], ldd<T>(e.lr, qg * nm + x), ov);
             }
             const double em = RATES ? s_em[m] : 0.0, fm = RATES ? s_fm[m] : 0.0;
-            for (int nu = 0; nu < nm; ++nu) {
+#pragma unroll
+            for (int nu = 0; nu < MM; ++nu) {
+                if (nu >= nm) break;
                 const double om = s_om[nu];
                 cx<T> g = {0, 0};
-                for (int x = 0; x < nm; ++x) cfma(g, s_es[x * nm + nu], gh[x]);
+#pragma unroll
+                for (int x = 0; x < MM; ++x)
+                    if (x < nm) cfma(g, s_es[x * nm + nu], gh[x]);
                 const T g2 = g.x * g.x + g.y * g.y;
                 if (!RATES) {
                     const long off = ((((long)(e.k_off + z) * e.nq_total + qg) * nm + nu) * nw + m) * nw + n;
@@ -194,10 +196,13 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
     if (!RATES) return;
     // deterministic reduction over m: [element][nu] in LDS -> partial[z][blk][n][nu]
     double* red = reinterpret_cast<double*>(smem);
-    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
         const int el = lane + 64 * t;
         if (el >= nw2) break;
-        for (int nu = 0; nu < nm; ++nu) red[(long)el * nm + nu] = acc[t][nu];
+#pragma unroll
+        for (int nu = 0; nu < MM; ++nu)
+            if (nu < nm) red[(long)el * nm + nu] = acc[t][nu];
     }
     __syncthreads();
     for (int o = lane; o < nw * nm; o += 64) {
@@ -206,6 +211,16 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
         for (int m = 0; m < nw; ++m) sum += red[((long)m * nw + n) * nm + nu];
         e.partial[(((long)z * e.nblk + blk) * nw + n) * nm + nu] = sum * (2.0 * kPi / kHbarEvFs);
     }
+}
+
+template <typename T, bool RATES>
+void launch_epilogue(const EphEpilogue& e, dim3 grid, size_t lds, hipStream_t st) {
+    if (e.nw == 8 && e.nm == 6)
+        hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 8, 6>), grid, dim3(64), lds, st, e);
+    else if (e.nw == 4 && e.nm == 6)
+        hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 4, 6>), grid, dim3(64), lds, st, e);
+    else
+        hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 0, 0>), grid, dim3(64), lds, st, e);
 }
 
 template <typename T>
@@ -386,10 +401,8 @@ void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
     const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);
     if (lds > 65536) throw Error{-6, "gkq: nw^2 * 3nat too large for one workgroup's staging buffer"};
-    if (f32)
-        hipLaunchKernelGGL((k_eph_epilogue<float, false>), grid, dim3(64), lds, st, e);
-    else
-        hipLaunchKernelGGL((k_eph_epilogue<double, false>), grid, dim3(64), lds, st, e);
+    if (f32) launch_epilogue<float, false>(e, grid, lds, st);
+    else launch_epilogue<double, false>(e, grid, lds, st);
     check_launch("eph_epilogue_g2");
 }
 
@@ -397,10 +410,8 @@ void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
     const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);
     if (lds > 65536) throw Error{-6, "rates: nw^2 * 3nat too large for one workgroup's staging buffer"};
-    if (f32)
-        hipLaunchKernelGGL((k_eph_epilogue<float, true>), grid, dim3(64), lds, st, e);
-    else
-        hipLaunchKernelGGL((k_eph_epilogue<double, true>), grid, dim3(64), lds, st, e);
+    if (f32) launch_epilogue<float, true>(e, grid, lds, st);
+    else launch_epilogue<double, true>(e, grid, lds, st);
     check_launch("eph_epilogue_rates");
 }
 
