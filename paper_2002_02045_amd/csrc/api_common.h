@@ -70,6 +70,9 @@ struct ephx_model {
     int32_t *d_re = nullptr, *d_rp_ph = nullptr, *d_re_g = nullptr, *d_rp_g = nullptr;
     double* d_h = nullptr;       // [n_re][nw*nw] complex, weights folded
     double* d_hvel = nullptr;    // [n_re][3][nw*nw] complex, H(R) * (i R_a)
+    int n_re_half = 0;           // Hermitian half set: R = 0 and one of each +/-R pair
+    int32_t* d_re_half = nullptr;
+    double* d_h_half = nullptr;  // [n_re_half][2][nw*nw] complex: H+H^dag, i(H-H^dag)
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
     double* d_minv = nullptr;    // [nm]

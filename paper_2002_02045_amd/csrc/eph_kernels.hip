@@ -81,7 +81,7 @@ __global__ void k_convert(long count, const double* __restrict__ in, float* __re
 // <-> element (m, n) (up to 4 elements per lane) forms
 //   g^H[x] = sum_i conj(U_im(k+q)) g'[x][i][n],  g_nu = sum_x es[x][nu] g^H[x]
 // and either writes |g_nu|^2 or accumulates the delta-weighted rate terms.
-constexpr int kQPB = 16;
+constexpr int kQPB = 32;
 
 // NW, NM > 0 fix the band and mode counts at compile time (fully unrolled,
 // register-resident accumulators); NW = NM = 0 is the runtime-sized fallback.
@@ -231,13 +231,15 @@ size_t epilogue_lds(int nw, int nm) {
     return stage > red ? stage : red;
 }
 
-__global__ void k_rates_reduce(int nblk, int nw, int nm, const double* __restrict__ partial, double* __restrict__ acc) {
-    const int z = blockIdx.x;
-    for (int o = threadIdx.x; o < nw * nm; o += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partial[((long)z * nblk + b) * nw * nm + o];
-        acc[(long)z * nw * nm + o] += s;
-    }
+// acc[z][o] += sum_b partial[z][b][o]: one 64-lane workgroup per (z, o), each lane a
+// fixed strided subset, then a fixed shuffle tree (deterministic).
+__global__ __launch_bounds__(64) void k_rates_reduce(int nblk, int nwm, const double* __restrict__ partial,
+                                                     double* __restrict__ acc) {
+    const int z = blockIdx.y, o = blockIdx.x, lane = threadIdx.x;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += partial[((long)z * nblk + b) * nwm + o];
+    for (int w = 32; w >= 1; w >>= 1) s += __shfl_xor(s, w, 64);
+    if (lane == 0) acc[(long)z * nwm + o] += s;
 }
 
 __global__ void k_rates_finish(int nkb, int nw, int nm, const double* __restrict__ acc, double* __restrict__ gamma,
@@ -416,7 +418,7 @@ void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {
 }
 
 void rates_reduce(int nkb, int nblk, int nw, int nm, const double* partial, double* acc, hipStream_t st) {
-    hipLaunchKernelGGL(k_rates_reduce, dim3(nkb), dim3(128), 0, st, nblk, nw, nm, partial, acc);
+    hipLaunchKernelGGL(k_rates_reduce, dim3(nw * nm, nkb), dim3(64), 0, st, nblk, nw * nm, partial, acc);
     check_launch("rates_reduce");
 }
 

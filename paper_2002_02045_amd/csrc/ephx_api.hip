@@ -265,6 +265,60 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                 }
             }
             m->d_h = (double*)up(h.data(), h.size() * sizeof(double));
+            {
+                // Hermitian half set.  The Hermitian part of sum_R e^{ik.R} H(R) equals
+                //   sum_half [cos(k.R)(M + M^dag) + sin(k.R) i(M - M^dag)],
+                // M = (H(R) + H(-R)^dag)/2 for a +/-R pair (taken once), M = H(R)/2 for a
+                // vector whose -R is absent, and the R = 0 term (H(0) + H(0)^dag)/2.
+                auto idx = index_of(d->re, d->n_re);
+                std::vector<int32_t> rh;
+                std::vector<double> hh;
+                std::vector<double> mre(nw2), mim(nw2);
+                for (int r = 0; r < d->n_re; ++r) {
+                    const int a = d->re[3 * r], b = d->re[3 * r + 1], c = d->re[3 * r + 2];
+                    const bool zero = a == 0 && b == 0 && c == 0;
+                    auto it = idx.find({-a, -b, -c});
+                    const bool paired = it != idx.end();
+                    if (paired && !zero && std::vector<int>{a, b, c} < std::vector<int>{-a, -b, -c}) continue;
+                    const int s2 = paired ? it->second : -1;
+                    for (int e = 0; e < nw2; ++e) {
+                        const int i = e / nw, j = e % nw;
+                        const double* x = &h[((size_t)r * nw2 + e) * 2];
+                        double yr = 0.0, yi = 0.0;  // (H(-R)^dag)_ij = conj(H(-R)_ji)
+                        if (paired) {
+                            const double* y = &h[((size_t)s2 * nw2 + j * nw + i) * 2];
+                            yr = y[0];
+                            yi = -y[1];
+                        }
+                        mre[e] = 0.5 * (x[0] + yr);
+                        mim[e] = 0.5 * (x[1] + yi);
+                    }
+                    rh.insert(rh.end(), {a, b, c});
+                    for (int part = 0; part < 2; ++part)
+                        for (int e = 0; e < nw2; ++e) {
+                            const int i = e / nw, j = e % nw;
+                            const double pr = mre[e], pi = mim[e];               // M_ij
+                            const double qr = mre[j * nw + i], qi = -mim[j * nw + i];  // (M^dag)_ij
+                            double re_, im_;
+                            if (zero) {
+                                // R = 0 (M already Hermitian part of H(0)): cos = 1, sin = 0
+                                re_ = part == 0 ? pr : 0.0;
+                                im_ = part == 0 ? pi : 0.0;
+                            } else if (part == 0) {  // M + M^dag
+                                re_ = pr + qr;
+                                im_ = pi + qi;
+                            } else {  // i (M - M^dag)
+                                re_ = -(pi - qi);
+                                im_ = pr - qr;
+                            }
+                            hh.push_back(re_);
+                            hh.push_back(im_);
+                        }
+                }
+                m->n_re_half = (int)(rh.size() / 3);
+                m->d_re_half = (int32_t*)up(rh.data(), rh.size() * sizeof(int32_t));
+                m->d_h_half = (double*)up(hh.data(), hh.size() * sizeof(double));
+            }
             m->d_hvel = (double*)up(hv.data(), hv.size() * sizeof(double));
             // C(R) / sqrt(M_k M_k') as complex, weights folded
             std::vector<double> cm((size_t)d->n_rp_ph * nm * nm * 2, 0.0);
@@ -343,7 +397,7 @@ void bands_impl(ephx_model* m, int nk, const double* k, double* eps, double* u, 
     for (int k0 = 0; k0 < nk; k0 += chunk) {
         const int n = std::min(chunk, nk - k0);
         double* hk = (double*)m->ws.get(tag + ".hk", (size_t)n * nw2 * 16);
-        phase_gemm_f64(n, nw2, m->n_re, 1, k + 3L * k0, nullptr, m->d_re, m->d_h, 0, hk, 0, st);
+        phase_gemm_herm_f64(n, nw2, m->n_re_half, 1, k + 3L * k0, nullptr, m->d_re_half, m->d_h_half, hk, 0, st);
         double* uu = u ? u + (size_t)k0 * nw2 * 2 : (vel ? (double*)m->ws.get(tag + ".u", (size_t)n * nw2 * 16) : nullptr);
         eig_herm(n, nw, hk, 0, nw2, eps + (size_t)k0 * nw, uu, st);
         if (vel) {
@@ -436,7 +490,8 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             // ~1e-2 eV at the 1e-5 level of |g|^2.
             {
                 StageTimer t("hkq_fourier", st);
-                phase_gemm_f64(nqc, nw2, m->n_re, nb, qb, kb, m->d_re, m->d_h, 0, (double*)hkq, (long)nqc * nw2, st);
+                phase_gemm_herm_f64(nqc, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, (double*)hkq,
+                                    (long)nqc * nw2, st);
             }
             {
                 StageTimer t("eig_hkq", st);

@@ -35,6 +35,10 @@ struct Error {
 void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const double* B, long sB, double* C, long sC,
                     hipStream_t st);
+// Hermitian Fourier sum over a half set (see phase_gemm.hip): B = [Kh][2][N] complex
+// (A_r, B_r), real coefficients cos/sin of 2 pi (x_m + x0_z).n_r; B shared by all z.
+void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const double* x0,
+                         const int32_t* nvec, const double* B, double* C, long sC, hipStream_t st);
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const float* B, long sB, float* C, long sC,
                     hipStream_t st);

@@ -56,7 +56,12 @@ template <> struct AccOf<float> {
 constexpr int kBM = 64;
 constexpr int kKC = 16;
 
-template <typename T, int CB>
+// HERM = true: Hermitian sums H(x) = sum_r [cos(2 pi x.n_r) A_r + sin(2 pi x.n_r) B_r]
+// over half of a +/-R symmetric set, with A_r = H(R)+H(R)^dag, B_r = i(H(R)-H(R)^dag)
+// (A_0 = H(0), B_0 = 0); B holds [r][2][N] complex.  Real coefficients against
+// complex columns need two MFMAs per complex product instead of four, over half
+// the vectors.
+template <typename T, int CB, bool HERM = false>
 __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const double* __restrict__ x,
                                                     const double* __restrict__ x0,
                                                     const int32_t* __restrict__ nvec,
@@ -64,7 +69,8 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
                                                     T* __restrict__ C, long sC) {
     typedef typename AccOf<T>::type acc_t;
     constexpr int BN = 16 * CB;
-    __shared__ T bs[kKC][BN][2];
+    constexpr int NB = HERM ? 2 : 1;
+    __shared__ T bs[kKC][BN][2 * NB];
     __shared__ int32_t ns[kKC][3];
     const int z = blockIdx.z;
     const int row0 = blockIdx.y * kBM;
@@ -100,14 +106,17 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
         for (int e = tid; e < kKC * BN; e += 256) {
             const int kk = e / BN, nn = e % BN;
             const int r = kc + kk, col = col0 + nn;
-            T re = 0, im = 0;
-            if (r < K && col < N) {
-                const long off = ((long)r * N + col) * 2;
-                re = bz[off];
-                im = bz[off + 1];
+#pragma unroll
+            for (int h = 0; h < NB; ++h) {
+                T re = 0, im = 0;
+                if (r < K && col < N) {
+                    const long off = (((long)r * NB + h) * N + col) * 2;
+                    re = bz[off];
+                    im = bz[off + 1];
+                }
+                bs[kk][nn][2 * h] = re;
+                bs[kk][nn][2 * h + 1] = im;
             }
-            bs[kk][nn][0] = re;
-            bs[kk][nn][1] = im;
         }
         if (tid < kKC * 3) {
             const int kk = tid / 3, d = tid % 3;
@@ -124,10 +133,19 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
             for (int cb = 0; cb < CB; ++cb) {
                 const T bre = bs[kk][cb * 16 + li][0];
                 const T bim = bs[kk][cb * 16 + li][1];
-                are[cb] = mfma(pc, bre, are[cb]);
-                are[cb] = mfma(nps, bim, are[cb]);
-                aim[cb] = mfma(pc, bim, aim[cb]);
-                aim[cb] = mfma(ps, bre, aim[cb]);
+                if (HERM) {
+                    const T b2re = bs[kk][cb * 16 + li][2 * NB - 2];
+                    const T b2im = bs[kk][cb * 16 + li][2 * NB - 1];
+                    are[cb] = mfma(pc, bre, are[cb]);
+                    are[cb] = mfma(ps, b2re, are[cb]);
+                    aim[cb] = mfma(pc, bim, aim[cb]);
+                    aim[cb] = mfma(ps, b2im, aim[cb]);
+                } else {
+                    are[cb] = mfma(pc, bre, are[cb]);
+                    are[cb] = mfma(nps, bim, are[cb]);
+                    aim[cb] = mfma(pc, bim, aim[cb]);
+                    aim[cb] = mfma(ps, bre, aim[cb]);
+                }
             }
         }
         __syncthreads();
@@ -315,19 +333,44 @@ inline void check_launch(const char* what) {
 
 }  // namespace
 
+// Column blocks per workgroup: as many as the output width uses, up to 8.
+static int pick_cb(int N, int cap) {
+    if (N <= 48) return 3;
+    if (N <= 64 || cap <= 4) return 4;
+    return 8;
+}
+
 void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
                     const double* B, long sB, double* C, long sC, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
-    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
-    hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    const int cb = pick_cb(N, 4);
+    dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
+    if (cb == 3)
+        hipLaunchKernelGGL((k_phase_gemm<double, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    else
+        hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
     check_launch("phase_gemm_f64");
+}
+
+void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const double* x0, const int32_t* nvec,
+                         const double* B, double* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, x0, nvec, B, 0L, C, sC);
+    check_launch("phase_gemm_herm_f64");
 }
 
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
                     const float* B, long sB, float* C, long sC, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
-    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
-    hipLaunchKernelGGL((k_phase_gemm<float, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    const int cb = pick_cb(N, 8);
+    dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
+    if (cb == 3)
+        hipLaunchKernelGGL((k_phase_gemm<float, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    else if (cb == 4)
+        hipLaunchKernelGGL((k_phase_gemm<float, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+    else
+        hipLaunchKernelGGL((k_phase_gemm<float, 8>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
     check_launch("phase_gemm_f32");
 }
 
@@ -335,13 +378,21 @@ void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const doubl
                      const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0 || Kp < K) throw Error{-1, "phase_gemm_bf16: bad Kp"};
-    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
-    if (nsplit == 2)
-        hipLaunchKernelGGL((k_phase_gemm_bf16<4, 2>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC);
-    else if (nsplit == 3)
-        hipLaunchKernelGGL((k_phase_gemm_bf16<4, 3>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC);
-    else
-        throw Error{-1, "phase_gemm_bf16: nsplit must be 2 or 3"};
+    if (nsplit != 2 && nsplit != 3) throw Error{-1, "phase_gemm_bf16: nsplit must be 2 or 3"};
+    const int cb = pick_cb(N, 8);
+    dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
+#define EPHX_BF(CBV, NSV) \
+    hipLaunchKernelGGL((k_phase_gemm_bf16<CBV, NSV>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC)
+    if (nsplit == 2) {
+        if (cb == 3) EPHX_BF(3, 2);
+        else if (cb == 4) EPHX_BF(4, 2);
+        else EPHX_BF(8, 2);
+    } else {
+        if (cb == 3) EPHX_BF(3, 3);
+        else if (cb == 4) EPHX_BF(4, 3);
+        else EPHX_BF(8, 3);
+    }
+#undef EPHX_BF
     check_launch("phase_gemm_bf16");
 }
 
