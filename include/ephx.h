@@ -153,6 +153,18 @@ int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red,
                const double* q_red, const double* q_w, int precision, double* gamma,
                double* gamma_mode, void* stream);
 
+/* Adjoint of ephx_rates with respect to the coupling tensor (FP64): for
+ * L = sum_nk gamma_bar[n][k] Gamma_nk (gamma_bar device [nk][nw]), writes
+ * g_bar = dL/dRe g(Re,Rp) + i dL/dIm g(Re,Rp), device complex128 with the
+ * layout of the model's g, [n_re_g][n_rp_g][3nat][nw][nw] (overwritten).  The
+ * eigenvectors of H and D do not depend on g, so the chain is the adjoint of
+ * Eqs. eph_mat, eph_mat_wann2 and scatter_rate: per pair
+ * g_bar = 2 (2 pi/hbar) gamma_bar w_q D g, back through the mode projection and
+ * rotation, then the conjugate-phase sums over q and k. */
+int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
+                   const double* q_red, const double* q_w, const double* gamma_bar, double* g_bar,
+                   void* stream);
+
 /* Window states on a Gamma-centred n_grid[0] x n_grid[1] x n_grid[2] grid
  * (Sec. 4.3): grid point (i1,i2,i3) has index (i1*N2 + i2)*N3 + i3 and reduced
  * coordinates i/N.  mode 0: every (k, band) with band_lo <= band < band_hi and

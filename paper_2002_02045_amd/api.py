@@ -79,6 +79,7 @@ class Model:
         self.nw = int(src.nw)
         self.nat = d.natoms
         self.nmodes = 3 * self.nat
+        self.g_shape = tuple(np.asarray(src.g).shape)
 
     def close(self):
         if self._h:
@@ -140,6 +141,34 @@ def rates(model, k, q, params, precision="fp64", q_weights=None, mode_resolved=T
     check(lib.ephx_rates(model.handle, C.byref(pc), nk, ptr(kt), qt.shape[0], ptr(qt), ptr(qw), p, ptr(gam),
                          ptr(gmode), stream_ptr()))
     return gam, gmode
+
+
+def rates_vjp(model, k, q, params, gamma_bar, q_weights=None):
+    """dL/dg(Re,Rp) (complex128, layout of the model's g) for L = sum gamma_bar * Gamma."""
+    kt, qt = _pts(k), _pts(q)
+    gb = torch.as_tensor(gamma_bar, dtype=F64, device="cuda").contiguous()
+    qw = None if q_weights is None else torch.as_tensor(q_weights, dtype=F64, device="cuda").contiguous()
+    out = torch.empty(model.g_shape, dtype=torch.complex128, device="cuda")
+    pc = params.c()
+    check(lib.ephx_rates_vjp(model.handle, C.byref(pc), kt.shape[0], ptr(kt), qt.shape[0], ptr(qt), ptr(qw), ptr(gb),
+                             ptr(out), stream_ptr()))
+    return out
+
+
+class RatesFunction(torch.autograd.Function):
+    """Gamma(g(Re,Rp)) with the hand-written adjoint (FP64).  The forward takes
+    the coupling tensor as a complex128 tensor only to connect the graph; the
+    library's model holds the values that are used."""
+
+    @staticmethod
+    def forward(ctx, g, model, k, q, params):
+        gam, _ = rates(model, k, q, params, precision="fp64", mode_resolved=False)
+        ctx.model, ctx.k, ctx.q, ctx.params = model, k, q, params
+        return gam
+
+    @staticmethod
+    def backward(ctx, gbar):
+        return rates_vjp(ctx.model, ctx.k, ctx.q, ctx.params, gbar), None, None, None, None
 
 
 def grid_states(model, n_grid, *, mode="window", band_lo=0, band_hi=None, e_lo=0.0, e_hi=0.0, count=0,

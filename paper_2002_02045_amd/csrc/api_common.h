@@ -76,6 +76,9 @@ struct ephx_model {
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
     double* d_minv = nullptr;    // [nm]
+    double* d_wg = nullptr;      // [n_re_g][n_rp_g] weight products, only if not all 1
+    double* d_nrp_g = nullptr;   // -Rp then -Re as doubles (adjoint sums), created on first use
+    double* d_nre_g = nullptr;
     bool polar = false;
     double *d_bvec = nullptr, *d_tau = nullptr, *d_zstar = nullptr, *d_eps = nullptr;
     ephx::PolarDev pd{};

@@ -216,48 +216,69 @@ struct Vec4<double> {
     typedef double4 type;
 };
 
+template <typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ P, long ld, int r, bool ok, int c0, int lane,
+                                         typename Vec4<T>::type (&v)[4]) {
+    const T* row = P + (long)r * ld + c0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = 4 * (lane + 64 * j);
+        if (ok && c0 + c < ld) {
+            v[j] = *reinterpret_cast<const typename Vec4<T>::type*>(row + c);
+        } else {
+            v[j].x = v[j].y = v[j].z = v[j].w = (T)0;
+        }
+    }
+}
+
+// The loads of the next two rows are issued before the current row is reduced,
+// so each wave keeps two rows in flight while it computes (software pipelining).
 template <typename T, int NA, int NB>
-__global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restrict__ P, VecPtrs xa,
-                                                VecPtrs yb, double* __restrict__ rowp,
-                                                double* __restrict__ colp, int n_ct, int n_rt) {
+__global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restrict__ P, VecPtrs xa, VecPtrs yb,
+                                                double* __restrict__ rowp, double* __restrict__ colp, int n_ct,
+                                                int n_rt) {
     __shared__ double cred[NB > 0 ? NB : 1][kTC];
     const int ct = blockIdx.x, rt = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int c0 = ct * kTC;
     // lane columns: c0 + 4*(lane + 64*j) + u, j = 0..3, u = 0..3
     double xv[NA > 0 ? NA : 1][kCPL];
+#pragma unroll
     for (int a = 0; a < NA; ++a)
+#pragma unroll
         for (int j = 0; j < 4; ++j)
+#pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + 4 * (lane + 64 * j) + u;
                 xv[a][4 * j + u] = c < S ? xa.p[a][c] : 0.0;
             }
     double cacc[NB > 0 ? NB : 1][kCPL];
+#pragma unroll
     for (int b = 0; b < NB; ++b)
+#pragma unroll
         for (int i = 0; i < kCPL; ++i) cacc[b][i] = 0.0;
     const int r_end = min(S, (rt + 1) * kTR);
-    for (int r = rt * kTR + wave; r < r_end; r += 4) {
-        const T* row = P + (long)r * ld + c0;
-        double pv[kCPL];
+    int r = rt * kTR + wave;
+    typename Vec4<T>::type cur[4], nxt[4], nx2[4];
+    load_row(P, ld, r, r < r_end, c0, lane, nxt);
+    load_row(P, ld, r + 4, r + 4 < r_end, c0, lane, nx2);
+    for (; r < r_end; r += 4) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int c = 4 * (lane + 64 * j);
-            typename Vec4<T>::type v;
-            if (c0 + c < ld) {
-                v = *reinterpret_cast<const typename Vec4<T>::type*>(row + c);
-            } else {
-                v.x = v.y = v.z = v.w = (T)0;
-            }
-            pv[4 * j] = (double)v.x;
-            pv[4 * j + 1] = (double)v.y;
-            pv[4 * j + 2] = (double)v.z;
-            pv[4 * j + 3] = (double)v.w;
+            cur[j] = nxt[j];
+            nxt[j] = nx2[j];
         }
+        load_row(P, ld, r + 8, r + 8 < r_end, c0, lane, nx2);
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             double sa = 0.0;
 #pragma unroll
-            for (int i = 0; i < kCPL; ++i) sa = fma(pv[i], xv[a][i], sa);
+            for (int j = 0; j < 4; ++j) {
+                sa = fma((double)cur[j].x, xv[a][4 * j], sa);
+                sa = fma((double)cur[j].y, xv[a][4 * j + 1], sa);
+                sa = fma((double)cur[j].z, xv[a][4 * j + 2], sa);
+                sa = fma((double)cur[j].w, xv[a][4 * j + 3], sa);
+            }
             for (int w = 32; w >= 1; w >>= 1) sa += __shfl_xor(sa, w, 64);
             if (lane == 0) rowp[((long)a * n_ct + ct) * S + r] = sa;
         }
@@ -265,15 +286,23 @@ __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restr
         for (int b = 0; b < NB; ++b) {
             const double yr = yb.p[b][r];
 #pragma unroll
-            for (int i = 0; i < kCPL; ++i) cacc[b][i] = fma(pv[i], yr, cacc[b][i]);
+            for (int j = 0; j < 4; ++j) {
+                cacc[b][4 * j] = fma((double)cur[j].x, yr, cacc[b][4 * j]);
+                cacc[b][4 * j + 1] = fma((double)cur[j].y, yr, cacc[b][4 * j + 1]);
+                cacc[b][4 * j + 2] = fma((double)cur[j].z, yr, cacc[b][4 * j + 2]);
+                cacc[b][4 * j + 3] = fma((double)cur[j].w, yr, cacc[b][4 * j + 3]);
+            }
         }
     }
     if (NB > 0) {
         // combine the four waves' column sums in a fixed order
         for (int w = 0; w < 4; ++w) {
             if (wave == w) {
+#pragma unroll
                 for (int b = 0; b < NB; ++b)
+#pragma unroll
                     for (int j = 0; j < 4; ++j)
+#pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int c = 4 * (lane + 64 * j) + u;
                             cred[b][c] = (w == 0 ? 0.0 : cred[b][c]) + cacc[b][4 * j + u];

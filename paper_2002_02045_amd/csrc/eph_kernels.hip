@@ -69,6 +69,132 @@ __global__ void k_apply_u_column(int nrp, int nm, int nw, const double* __restri
     out[((long)z * per + t) * 2 + 1] = acc.y;
 }
 
+constexpr int kQPB = 32;   // (k, q) pairs per epilogue workgroup
+
+__global__ void k_apply_u_right_adj(int nrp, int nm, int nw, const double* __restrict__ g, const double* __restrict__ u,
+                                    double* __restrict__ out) {
+    // out[z][p][x][i][j] = sum_n g[z][p][x][i][n] conj(u[z][j][n])
+    const int z = blockIdx.y;
+    const long per = (long)nrp * nm * nw * nw;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per) return;
+    const int j = (int)(t % nw);
+    const long row = t / nw;
+    const double* gz = g + (long)z * per * 2;
+    const double* uz = u + (long)z * nw * nw * 2;
+    cx<double> acc = {0.0, 0.0};
+    for (int n = 0; n < nw; ++n) {
+        const cx<double> a = ld(gz, row * nw + n), b = ld(uz, (long)j * nw + n);
+        acc.x += a.x * b.x + a.y * b.y;   // a * conj(b)
+        acc.y += a.y * b.x - a.x * b.y;
+    }
+    out[((long)z * per + t) * 2] = acc.x;
+    out[((long)z * per + t) * 2 + 1] = acc.y;
+}
+
+// Adjoint of the per-pair epilogue for L = sum_nk lam_nk Gamma_nk (FP64).  With
+// D = delta(e_n - hw - e_m)(1 + N - f_m) + delta(e_n + hw - e_m)(N + f_m):
+//   gbar_mn,nu   = 2 (2 pi/hbar) lam_n w_q D g_mn,nu          (gradient of lam w c D |g|^2)
+//   gHbar[x]_mn  = sum_nu conj(es[x][nu]) gbar_mn,nu          (adjoint of the mode projection)
+//   g'Wbar[x]_in = sum_m U_im(k+q) gHbar[x]_mn                 (adjoint of U^dag(k+q) .)
+// The long-range term enters through g (it does not depend on g(Re,Rp)).
+__global__ __launch_bounds__(64) void k_eph_adjoint(EphEpilogue e, const double* __restrict__ lam,
+                                                    double* __restrict__ gwbar) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int nw = e.nw, nm = e.nm, nw2 = nw * nw, ng = nm * nw2;
+    cx<double>* s_gw = reinterpret_cast<cx<double>*>(smem);
+    cx<double>* s_gb = s_gw + ng;
+    cx<double>* s_u = s_gb + ng;
+    cx<double>* s_es = s_u + nw2;
+    double* s_nb = reinterpret_cast<double*>(s_es + nm * nm);
+    double* s_om = s_nb + nm;
+    double* s_em = s_om + nm;
+    double* s_fm = s_em + nw;
+    const int z = blockIdx.y, blk = blockIdx.x, lane = threadIdx.x;
+    const int q0 = blk * kQPB, q1 = min(e.nq, q0 + kQPB);
+    const double* gwz = reinterpret_cast<const double*>(e.gw) + (long)z * e.nq * ng * 2;
+    const double kt = kBoltzEv * e.temp;
+    const double is = 1.0 / e.sigma, nrm = 1.0 / (sqrt(kPi) * e.sigma);
+    const double c2 = 2.0 * (2.0 * kPi / kHbarEvFs);
+    for (int ql = q0; ql < q1; ++ql) {
+        const long qg = (long)e.q_off + ql;
+        const long pair = (long)z * e.nq + ql;
+        const double* gp = gwz + (long)ql * ng * 2;
+        const double* uq = e.ukq + pair * nw2 * 2;
+        for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
+        for (int i = lane; i < nw2; i += 64) s_u[i] = ld(uq, i);
+        for (int i = lane; i < nm * nm; i += 64) {
+            const int x = i / nm, nu = i % nm;
+            const double om = e.omega[qg * nm + nu];
+            const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
+            s_es[i] = {amp * e.evec[2 * ((qg * nm + x) * nm + nu)], amp * e.evec[2 * ((qg * nm + x) * nm + nu) + 1]};
+        }
+        if (lane < nm) {
+            const double om = e.omega[qg * nm + lane];
+            s_om[lane] = om;
+            s_nb[lane] = om > e.omega_cut ? 1.0 / expm1(om / kt) : 0.0;
+        }
+        if (lane < nw) {
+            const double em = e.ekq[pair * nw + lane];
+            s_em[lane] = em;
+            s_fm[lane] = 1.0 / (exp((em - e.mu) / kt) + 1.0);
+        }
+        __syncthreads();
+        const double wq = e.qw ? e.qw[qg] : e.uniform_w;
+        for (int el = lane; el < nw2; el += 64) {
+            const int m = el / nw, n = el % nw;
+            cx<double> gh[kMaxModes];
+            for (int x = 0; x < nm; ++x) {
+                cx<double> a = {0, 0};
+                for (int i = 0; i < nw; ++i) cjfma(a, s_u[i * nw + m], s_gw[(x * nw + i) * nw + n]);
+                gh[x] = a;
+            }
+            if (e.lr != nullptr) {
+                cx<double> ov = {0, 0};
+                const double* ukz = e.uk + (long)z * nw2 * 2;
+                for (int i = 0; i < nw; ++i) cjfma(ov, s_u[i * nw + m], ld(ukz, (long)i * nw + n));
+                for (int x = 0; x < nm; ++x) cfma(gh[x], ld(e.lr, qg * nm + x), ov);
+            }
+            const double en = e.ek[(long)z * nw + n], em = s_em[m], fm = s_fm[m];
+            const double ln = lam[(long)(e.k_off + z) * nw + n];
+            cx<double> ghb[kMaxModes];
+            for (int x = 0; x < nm; ++x) ghb[x] = {0.0, 0.0};
+            for (int nu = 0; nu < nm; ++nu) {
+                const double om = s_om[nu];
+                if (!(om > e.omega_cut)) continue;
+                cx<double> g = {0, 0};
+                for (int x = 0; x < nm; ++x) cfma(g, s_es[x * nm + nu], gh[x]);
+                const double nb = s_nb[nu];
+                const double x1 = (en - om - em) * is, x2 = (en + om - em) * is;
+                const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+                const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+                const double w = c2 * ln * wq * (de * (1.0 + nb - fm) + da * (nb + fm));
+                const cx<double> gb = {w * g.x, w * g.y};
+                for (int x = 0; x < nm; ++x) cjfma(ghb[x], s_es[x * nm + nu], gb);
+            }
+            for (int x = 0; x < nm; ++x) s_gb[(x * nw + m) * nw + n] = ghb[x];
+        }
+        __syncthreads();
+        double* out = gwbar + ((long)z * e.nq + ql) * ng * 2;
+        for (int o = lane; o < ng; o += 64) {
+            const int x = o / nw2, i = (o / nw) % nw, n = o % nw;
+            cx<double> a = {0, 0};
+            for (int m = 0; m < nw; ++m) cfma(a, s_u[i * nw + m], s_gb[(x * nw + m) * nw + n]);
+            out[2 * o] = a.x;
+            out[2 * o + 1] = a.y;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_scale_rows(long rows, long cols, const double* __restrict__ w, double* __restrict__ data) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    const double s = w[t / cols];
+    data[2 * t] *= s;
+    data[2 * t + 1] *= s;
+}
+
 __global__ void k_convert(long count, const double* __restrict__ in, float* __restrict__ out) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) out[t] = (float)in[t];
@@ -81,7 +207,6 @@ __global__ void k_convert(long count, const double* __restrict__ in, float* __re
 // <-> element (m, n) (up to 4 elements per lane) forms
 //   g^H[x] = sum_i conj(U_im(k+q)) g'[x][i][n],  g_nu = sum_x es[x][nu] g^H[x]
 // and either writes |g_nu|^2 or accumulates the delta-weighted rate terms.
-constexpr int kQPB = 32;
 
 // NW, NM > 0 fix the band and mode counts at compile time (fully unrolled,
 // register-resident accumulators); NW = NM = 0 is the runtime-sized fallback.
@@ -389,6 +514,29 @@ void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const doubl
     hipLaunchKernelGGL(k_apply_u_column, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw, g,
                        us, band, out);
     check_launch("apply_u_column");
+}
+
+void apply_u_right_adj(int Z, int nrp, int nm, int nw, const double* g, const double* u, double* out, hipStream_t st) {
+    const long per = (long)nrp * nm * nw * nw;
+    hipLaunchKernelGGL(k_apply_u_right_adj, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw, g, u,
+                       out);
+    check_launch("apply_u_right_adj");
+}
+
+void eph_adjoint_epilogue(const EphEpilogue& e, const double* lam, double* gw_bar, hipStream_t st) {
+    dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
+    const size_t ng = (size_t)e.nm * e.nw * e.nw;
+    const size_t lds = (2 * ng + e.nw * e.nw + e.nm * e.nm) * 16 + (2 * e.nm + 2 * e.nw) * 8;
+    if (lds > 65536) throw Error{-6, "rates_vjp: nw^2 * 3nat too large for one workgroup's staging buffer"};
+    hipLaunchKernelGGL(k_eph_adjoint, grid, dim3(64), lds, st, e, lam, gw_bar);
+    check_launch("eph_adjoint_epilogue");
+}
+
+void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t st) {
+    const long n = rows * cols;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, cols, w, data);
+    check_launch("scale_rows");
 }
 
 void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {

@@ -342,6 +342,17 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                     }
                 m->d_g = (double*)up(g.data(), ng * sizeof(double));
             }
+            {
+                bool unit = true;
+                std::vector<double> wg((size_t)d->n_re_g * d->n_rp_g);
+                for (int e = 0; e < d->n_re_g; ++e)
+                    for (int p = 0; p < d->n_rp_g; ++p) {
+                        const double w = (d->w_re_g ? d->w_re_g[e] : 1.0) * (d->w_rp_g ? d->w_rp_g[p] : 1.0);
+                        wg[(size_t)e * d->n_rp_g + p] = w;
+                        unit = unit && w == 1.0;
+                    }
+                if (!unit) m->d_wg = (double*)up(wg.data(), wg.size() * sizeof(double));
+            }
             std::vector<double> minv(nm);
             for (int a = 0; a < nm; ++a) minv[a] = 1.0 / std::sqrt(d->mass[a / 3]);
             m->d_minv = (double*)up(minv.data(), nm * sizeof(double));
@@ -549,6 +560,123 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
 }
 
 }  // namespace ephx
+
+namespace ephx {
+
+// dL/dg(Re,Rp) for L = sum_nk lam_nk Gamma_nk, FP64.  Recomputes the forward
+// quantities per k batch and q chunk, then
+//   per pair:  g'W_bar = U(k+q) sum_nu conj(e amp) 2c lam w D g        (adjoint epilogue)
+//   g'(k,Rp)_bar += sum_q e^{-iq.Rp} g'W_bar(k,q)                      (adjoint Rp sum)
+//   g(k,Rp)_bar   = g'(k,Rp)_bar U(k)^dag
+//   g(Re,Rp)_bar += sum_k e^{-ik.Re} g(k,Rp)_bar                       (adjoint Re sum)
+void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k, int nq, const double* q,
+                    const double* qw, const double* lam, double* gbar, hipStream_t st) {
+    const int nw = m->nw, nm = m->nm, nw2 = nw * nw;
+    const long ngcol = (long)nm * nw2;
+    const long nre_cols = (long)m->n_rp_g * ngcol;
+    double* om = (double*)m->ws.get("adj.omega", (size_t)nq * nm * 8);
+    double* ev = (double*)m->ws.get("adj.evec", (size_t)nq * nm * nm * 16);
+    phonons_impl(m, nq, q, om, ev, st, "adj");
+    double* lr = nullptr;
+    if (m->polar) {
+        lr = (double*)m->ws.get("adj.lr", (size_t)nq * nm * 16);
+        frohlich(nq, q, m->pd, lr, st);
+    }
+    // negated real-space vectors as doubles (rows of the adjoint sums)
+    if (!m->d_nrp_g) {
+        std::vector<int32_t> hv(3 * (m->n_rp_g + m->n_re_g));
+        hip_check(hipMemcpy(hv.data(), m->d_rp_g, 3 * m->n_rp_g * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+        hip_check(hipMemcpy(hv.data() + 3 * m->n_rp_g, m->d_re_g, 3 * m->n_re_g * 4, hipMemcpyDeviceToHost),
+                  "hipMemcpy");
+        std::vector<double> dv(hv.size());
+        for (size_t i = 0; i < hv.size(); ++i) dv[i] = -(double)hv[i];
+        m->d_nrp_g = (double*)dev_upload(dv.data(), dv.size() * 8);
+        m->owned.push_back(m->d_nrp_g);
+        m->d_nre_g = m->d_nrp_g + 3 * m->n_rp_g;
+    }
+    const int bk = std::min(nk, 16);
+    const int qc = (int)std::max(64L, std::min((long)nq, (1L << 17) / bk));
+    double* ek = (double*)m->ws.get("adj.ek", (size_t)bk * nw * 8);
+    double* uk = (double*)m->ws.get("adj.uk", (size_t)bk * nw2 * 16);
+    double* gk = (double*)m->ws.get("adj.gk", (size_t)bk * nre_cols * 16);
+    double* gp = (double*)m->ws.get("adj.gp", (size_t)bk * nre_cols * 16);
+    double* gpb = (double*)m->ws.get("adj.gpb", (size_t)bk * nre_cols * 16);
+    const size_t npair = (size_t)bk * qc;
+    double* hkq = (double*)m->ws.get("adj.hkq", npair * nw2 * 16);
+    double* ekq = (double*)m->ws.get("adj.ekq", npair * nw * 8);
+    double* ukq = (double*)m->ws.get("adj.ukq", npair * nw2 * 16);
+    double* gw = (double*)m->ws.get("adj.gw", npair * ngcol * 16);
+    double* gwb = (double*)m->ws.get("adj.gwb", npair * ngcol * 16);
+    hip_check(hipMemsetAsync(gbar, 0, (size_t)m->n_re_g * nre_cols * 16, st), "hipMemsetAsync");
+    for (int k0 = 0; k0 < nk; k0 += bk) {
+        const int nb = std::min(bk, nk - k0);
+        const double* kb = k + 3L * k0;
+        bands_impl(m, nb, kb, ek, uk, nullptr, st, "adj.bk");
+        phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+        apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
+        for (int q0 = 0; q0 < nq; q0 += qc) {
+            const int nqc = std::min(qc, nq - q0);
+            const double* qb = q + 3L * q0;
+            phase_gemm_herm_f64(nqc, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, hkq,
+                                (long)nqc * nw2, st);
+            eig_herm(nb * nqc, nw, hkq, 0, nw2, ekq, ukq, st);
+            phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, gw,
+                           (long)nqc * ngcol, st);
+            EphEpilogue e{};
+            e.nkb = nb;
+            e.nq = nqc;
+            e.q_off = q0;
+            e.nw = nw;
+            e.nm = nm;
+            e.gw = gw;
+            e.ukq = ukq;
+            e.ekq = ekq;
+            e.ek = ek;
+            e.uk = uk;
+            e.omega = om;
+            e.evec = ev;
+            e.lr = lr;
+            e.minv = m->d_minv;
+            e.omega_cut = p->omega_cut;
+            e.temp = p->temp;
+            e.mu = p->mu;
+            e.sigma = p->sigma;
+            e.qw = qw;
+            e.uniform_w = 1.0 / nq;
+            e.k_off = k0;
+            eph_adjoint_epilogue(e, lam, gwb, st);
+            // g'(k,Rp)_bar (+)= sum_q e^{-i q.Rp} g'W_bar(k,q): rows Rp, contraction over the q chunk
+            phase_gemm_adj_f64(m->n_rp_g, (int)ngcol, nqc, nb, m->d_nrp_g, qb, gwb, (long)nqc * ngcol, gpb,
+                               nre_cols, q0 > 0 ? 1 : 0, st);
+        }
+        apply_u_right_adj(nb, m->n_rp_g, nm, nw, gpb, uk, gk, st);
+        // g(Re,Rp)_bar += sum_k e^{-i k.Re} g(k,Rp)_bar
+        phase_gemm_adj_f64(m->n_re_g, (int)nre_cols, nb, 1, m->d_nre_g, kb, gk, 0, gbar, 0, 1, st);
+    }
+    if (m->d_wg) scale_rows((long)m->n_re_g * m->n_rp_g, ngcol, m->d_wg, gbar, st);
+}
+
+}  // namespace ephx
+
+extern "C" int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
+                              const double* q_red, const double* q_w, const double* gamma_bar, double* g_bar,
+                              void* stream) {
+    return guarded([&] {
+        require(m != nullptr && p != nullptr, "rates_vjp: null argument");
+        require(nk >= 0 && nq >= 0, "rates_vjp: negative size");
+        require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
+                "rates_vjp: need temp > 0, sigma > 0, finite mu and omega_cut");
+        require(g_bar != nullptr, "rates_vjp: null output");
+        hipStream_t st = (hipStream_t)stream;
+        if (nk == 0 || nq == 0) {
+            hip_check(hipMemsetAsync(g_bar, 0, (size_t)m->n_re_g * m->n_rp_g * m->nm * m->nw * m->nw * 16, st),
+                      "hipMemsetAsync");
+            return;
+        }
+        require(k_red && q_red && gamma_bar, "rates_vjp: null array");
+        rates_vjp_impl(m, p, nk, k_red, nq, q_red, q_w, gamma_bar, g_bar, st);
+    });
+}
 
 extern "C" int ephx_bands(ephx_model* m, int nk, const double* k_red, double* eps, double* u, double* vel,
                           void* stream) {

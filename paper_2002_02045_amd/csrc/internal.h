@@ -35,6 +35,10 @@ struct Error {
 void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const double* B, long sB, double* C, long sC,
                     hipStream_t st);
+// Adjoint sums C[z][m][n] (+)= sum_k exp(2 pi i x_m . p_k) B[z][k][n] with real
+// points on both sides (x: [M][3], p: [K][3]), FP64.
+void phase_gemm_adj_f64(int M, int N, int K, int Z, const double* x, const double* kpts, const double* B,
+                        long sB, double* C, long sC, int accumulate, hipStream_t st);
 // Hermitian Fourier sum over a half set (see phase_gemm.hip): B = [Kh][2][N] complex
 // (A_r, B_r), real coefficients cos/sin of 2 pi (x_m + x0_z).n_r; B shared by all z.
 void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const double* x0,
@@ -65,6 +69,12 @@ void phonon_omega(long count, double* lam, hipStream_t st);
 void apply_u_right(int Z, int nrp, int nm, int nw, const double* g, const double* u,
                    double* out, hipStream_t st);
 void convert_f64_f32(long count, const double* in, float* out, hipStream_t st);
+// data[r][c] *= w[r] for complex data [rows][cols]
+void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t st);
+// out(z)[p][x][i][j] = sum_n g'(z)[p][x][i][n] conj(U(z)[j][n])   (adjoint of apply_u_right)
+void apply_u_right_adj(int Z, int nrp, int nm, int nw, const double* g, const double* u, double* out,
+                       hipStream_t st);
+
 
 struct EphEpilogue {
     int nkb;            // k points in the batch (grid.y)
@@ -93,6 +103,8 @@ struct EphEpilogue {
     int nblk;
 };
 void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st);
+// per pair: gw_bar[x][i][n] = sum_m U(k+q)_im sum_nu conj(es[x][nu]) 2 c lam_n w_q D_mnu g_mnu (FP64)
+void eph_adjoint_epilogue(const EphEpilogue& e, const double* lam, double* gw_bar, hipStream_t st);
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st);
 int eph_epilogue_blocks(int nq);
 // acc[z][n][nu] += sum_b partial[z][b][n][nu]

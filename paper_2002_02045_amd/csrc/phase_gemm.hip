@@ -16,6 +16,8 @@
 // B[k-group l/16][l%16].  Accumulator element v of lane l is C[r][l%16] with
 // r = 4*(l/16) + v for the f32 and bf16 instructions but r = l/16 + 4*v for
 // v_mfma_f64_16x16x4f64 (measured on gfx950).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ephx {
@@ -26,7 +28,8 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ double reduced_arg(double a, double b, double c, const int32_t* n) {
+template <typename NT>
+__device__ __forceinline__ double reduced_arg(double a, double b, double c, const NT* n) {
     double t = fma(a, (double)n[0], fma(b, (double)n[1], c * (double)n[2]));
     return t - rint(t);
 }
@@ -61,17 +64,22 @@ constexpr int kKC = 16;
 // (A_0 = H(0), B_0 = 0); B holds [r][2][N] complex.  Real coefficients against
 // complex columns need two MFMAs per complex product instead of four, over half
 // the vectors.
-template <typename T, int CB, bool HERM = false>
+// KD = true: the contraction-side points are real (double [K][3]) instead of
+// integer vectors -- used by the adjoint sums over q and k; ACC = true adds the
+// product to C.
+template <typename T, int CB, bool HERM = false, bool KD = false, bool ACC = false>
 __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const double* __restrict__ x,
                                                     const double* __restrict__ x0,
-                                                    const int32_t* __restrict__ nvec,
+                                                    const void* __restrict__ nvec_,
                                                     const T* __restrict__ B, long sB,
                                                     T* __restrict__ C, long sC) {
     typedef typename AccOf<T>::type acc_t;
+    typedef typename std::conditional<KD, double, int32_t>::type NT;
+    const NT* nvec = reinterpret_cast<const NT*>(nvec_);
     constexpr int BN = 16 * CB;
     constexpr int NB = HERM ? 2 : 1;
     __shared__ T bs[kKC][BN][2 * NB];
-    __shared__ int32_t ns[kKC][3];
+    __shared__ NT ns[kKC][3];
     const int z = blockIdx.z;
     const int row0 = blockIdx.y * kBM;
     const int col0 = blockIdx.x * BN;
@@ -158,8 +166,8 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
             const int row = row0 + wave * 16 + AccOf<T>::row(lk, v);
             if (row < M && col < N) {
                 const long off = ((long)row * N + col) * 2;
-                cz[off] = are[cb][v];
-                cz[off + 1] = aim[cb][v];
+                cz[off] = ACC ? cz[off] + are[cb][v] : are[cb][v];
+                cz[off + 1] = ACC ? cz[off + 1] + aim[cb][v] : aim[cb][v];
             }
         }
     }
@@ -350,6 +358,19 @@ void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x
     else
         hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
     check_launch("phase_gemm_f64");
+}
+
+void phase_gemm_adj_f64(int M, int N, int K, int Z, const double* x, const double* kpts, const double* B, long sB,
+                        double* C, long sC, int accumulate, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0 || K <= 0) return;
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    if (accumulate)
+        hipLaunchKernelGGL((k_phase_gemm<double, 4, false, true, true>), grid, dim3(256), 0, st, M, N, K, x,
+                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC);
+    else
+        hipLaunchKernelGGL((k_phase_gemm<double, 4, false, true, false>), grid, dim3(256), 0, st, M, N, K, x,
+                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC);
+    check_launch("phase_gemm_adj_f64");
 }
 
 void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const double* x0, const int32_t* nvec,
