@@ -30,7 +30,6 @@ struct ephx_table {
     ephx_params par{};
     bool ready = false;
     double c = 0.0;               // (2 pi/hbar)/N_q
-    StreamPlan plan{};
     std::vector<void*> owned;
     Workspace ws;
     ~ephx_table() {
@@ -77,26 +76,29 @@ double snap_edge(const std::vector<double>& e, double edge) {
     return 0.5 * (*(it - 1) + *it);
 }
 
-void one_pass(ephx_table* t, const void* mat, int na, VecPtrs x, int nb, VecPtrs y, double* rowp, double* colp,
+StreamPlan plan_for(const ephx_table* t, int na, int nb) { return stream_plan(t->S, t->f32 ? 1 : 0, na, nb); }
+
+void one_pass(ephx_table* t, const StreamPlan& pl, const void* mat, VecPtrs x, VecPtrs y, double* rowp, double* colp,
               hipStream_t st, const char* tag) {
     StageTimer tm(tag, st);
-    stream_pass(t->plan, t->ld, mat, t->f32 ? 1 : 0, na, x, nb, y, rowp, colp, st);
+    stream_pass(pl, t->ld, mat, x, y, rowp, colp, st);
 }
 
 // I at occupations y; optional RK4 stage update
 void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, int acc_init, double w_acc,
                     const double* f_base, double a_next, double* f_next, hipStream_t st) {
     const int S = t->S;
+    const StreamPlan pl = plan_for(t, 1, 1);
     double* omf = (double*)t->ws.get("c.omf", S * 8);
-    double* rowp = (double*)t->ws.get("c.rowp", (size_t)t->plan.n_ct * S * 8);
-    double* colp = (double*)t->ws.get("c.colp", (size_t)t->plan.n_rt * S * 8);
+    double* rowp = (double*)t->ws.get("c.rowp", (size_t)pl.n_ct * S * 8);
+    double* colp = (double*)t->ws.get("c.colp", (size_t)pl.n_rt * S * 8);
     occ_vectors(S, y, nullptr, omf, nullptr, nullptr, st);
     VecPtrs x{{omf, nullptr, nullptr, nullptr}}, yy{{y, nullptr, nullptr, nullptr}};
-    one_pass(t, t->d_p, 1, x, 1, yy, rowp, colp, st, "collision_stream");
+    one_pass(t, pl, t->d_p, x, yy, rowp, colp, st, "collision_stream");
     CollisionFinish cf{};
     cf.S = S;
-    cf.n_rt = t->plan.n_rt;
-    cf.n_ct = t->plan.n_ct;
+    cf.n_rt = pl.n_rt;
+    cf.n_ct = pl.n_ct;
     cf.rowp = rowp;
     cf.colp = colp;
     cf.f = y;
@@ -119,13 +121,14 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     double* o0 = (double*)t->ws.get("v.o0", S * 8);
     double* o1 = (double*)t->ws.get("v.o1", S * 8);
     double* o2 = (double*)t->ws.get("v.o2", S * 8);
-    double* rowp = (double*)t->ws.get("v.rowp", (size_t)2 * t->plan.n_ct * S * 8);
-    double* colp = (double*)t->ws.get("v.colp", (size_t)2 * t->plan.n_rt * S * 8);
+    const StreamPlan pl = plan_for(t, 2, 2);
+    double* rowp = (double*)t->ws.get("v.rowp", (size_t)2 * pl.n_ct * S * 8);
+    double* colp = (double*)t->ws.get("v.colp", (size_t)2 * pl.n_rt * S * 8);
     occ_vectors(S, f, lam, o0, o1, o2, st);
     // rows: P(1-f), P(lam(1-f)); columns: P^T f, P^T (lam f)
     VecPtrs x{{o0, o1, nullptr, nullptr}}, y{{f, o2, nullptr, nullptr}};
-    one_pass(t, t->d_p, 2, x, 2, y, rowp, colp, st, "collision_stream");
-    vjp_finish(S, t->plan.n_ct, t->plan.n_rt, rowp, colp, lam, t->c, fbar, st);
+    one_pass(t, pl, t->d_p, x, y, rowp, colp, st, "collision_stream");
+    vjp_finish(S, pl.n_ct, pl.n_rt, rowp, colp, lam, t->c, fbar, st);
     if (sbar) {
         double* part = (double*)t->ws.get("v.part", (size_t)t->nm * S * 8);
         mode_vjp(S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
@@ -242,7 +245,6 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
             t->nw = nw;
             t->f32 = precision != EPHX_FP64;
             t->ld = table_ld(S);
-            t->plan = stream_plan(S);
             const size_t esz = t->f32 ? 4 : 8;
             // states: grid coordinates, reduced points, negated points
             std::vector<int32_t> kc(3 * S);
@@ -525,14 +527,15 @@ extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* 
         double* f0 = (double*)t->ws.get("m.f0", 3 * S * 8);
         double* f = (double*)t->ws.get("m.f", 3 * S * 8);
         double* fn = (double*)t->ws.get("m.fn", 3 * S * 8);
-        double* rowp = (double*)t->ws.get("m.rowp", (size_t)3 * t->plan.n_ct * S * 8);
+        const StreamPlan pl1 = plan_for(t, 1, 0), pl3 = plan_for(t, 3, 0);
+        double* rowp = (double*)t->ws.get("m.rowp", (size_t)3 * pl3.n_ct * S * 8);
         VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
-        one_pass(t, t->d_w, 1, one, 0, none, rowp, nullptr, st, "transport_stream");
-        ita_gamma(S, t->plan.n_ct, rowp, p->n_q, vel, tau, f0, f, st);
+        one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
+        ita_gamma(S, pl1.n_ct, rowp, p->n_q, vel, tau, f0, f, st);
         for (int it = 0; it < n_iter; ++it) {
             VecPtrs x{{f, f + S, f + 2 * S, nullptr}};
-            one_pass(t, t->d_w, 3, x, 0, none, rowp, nullptr, st, "transport_stream");
-            ita_update(S, t->plan.n_ct, rowp, p->n_q, tau, f0, fn, st);
+            one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
+            ita_update(S, pl3.n_ct, rowp, p->n_q, tau, f0, fn, st);
             std::swap(f, fn);
         }
         mobility_reduce(S, t->d_eps, vel, f, p->mu, p->temp, f_out, mob_out, st);

@@ -19,6 +19,9 @@
 // combined across the four waves through LDS at the end.  Partials go to
 // rowp[a][col tile][row] and colp[b][row tile][col] and are reduced in a fixed
 // order by the finishing kernel (no atomics; results are deterministic).
+#include <algorithm>
+#include <atomic>
+
 #include "internal.h"
 
 namespace ephx {
@@ -201,7 +204,10 @@ __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2,
 }
 
 // ---------------------------------------------------------------- streaming pass
-constexpr int kTR = 256;          // rows per tile
+// A block owns a column tile of kTC columns (kCPL per lane) and a run of rpb
+// rows; its four waves take the rows of the run in turn.  rpb is chosen on the
+// host so that the whole grid is resident at once (one wave of blocks): a
+// second, partly filled wave of blocks would leave HBM idle at the end.
 constexpr int kTC = 1024;         // columns per tile
 constexpr int kCPL = kTC / 64;    // columns per lane (16)
 
@@ -216,6 +222,20 @@ struct Vec4<double> {
     typedef double4 type;
 };
 
+// Nontemporal loads: the matrix is streamed once per pass and is far larger
+// than the caches, so its lines should not evict the reused vectors x, y.
+__device__ __forceinline__ float4 ld_stream(const float* p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ double4 ld_stream(const double* p) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 a = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    const v2 b = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p + 2));
+    return make_double4(a.x, a.y, b.x, b.y);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_row(const T* __restrict__ P, long ld, int r, bool ok, int c0, int lane,
                                          typename Vec4<T>::type (&v)[4]) {
@@ -224,19 +244,52 @@ __device__ __forceinline__ void load_row(const T* __restrict__ P, long ld, int r
     for (int j = 0; j < 4; ++j) {
         const int c = 4 * (lane + 64 * j);
         if (ok && c0 + c < ld) {
-            v[j] = *reinterpret_cast<const typename Vec4<T>::type*>(row + c);
+            v[j] = ld_stream(row + c);
         } else {
             v[j].x = v[j].y = v[j].z = v[j].w = (T)0;
         }
     }
 }
 
-// The loads of the next two rows are issued before the current row is reduced,
-// so each wave keeps two rows in flight while it computes (software pipelining).
+// one row of the tile: NA row sums (reduced over the wavefront) and NB column
+// accumulations, all in FP64
+template <typename T, int NA, int NB>
+__device__ __forceinline__ void stream_row(int S, int r, int lane, int ct, int n_ct,
+                                           const typename Vec4<T>::type (&v)[4], const double (&xv)[NA > 0 ? NA : 1][kCPL],
+                                           double (&cacc)[NB > 0 ? NB : 1][kCPL], const VecPtrs& yb,
+                                           double* __restrict__ rowp) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        double sa = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sa = fma((double)v[j].x, xv[a][4 * j], sa);
+            sa = fma((double)v[j].y, xv[a][4 * j + 1], sa);
+            sa = fma((double)v[j].z, xv[a][4 * j + 2], sa);
+            sa = fma((double)v[j].w, xv[a][4 * j + 3], sa);
+        }
+        for (int w = 32; w >= 1; w >>= 1) sa += __shfl_xor(sa, w, 64);
+        if (lane == 0) rowp[((long)a * n_ct + ct) * S + r] = sa;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const double yr = yb.p[b][r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cacc[b][4 * j] = fma((double)v[j].x, yr, cacc[b][4 * j]);
+            cacc[b][4 * j + 1] = fma((double)v[j].y, yr, cacc[b][4 * j + 1]);
+            cacc[b][4 * j + 2] = fma((double)v[j].z, yr, cacc[b][4 * j + 2]);
+            cacc[b][4 * j + 3] = fma((double)v[j].w, yr, cacc[b][4 * j + 3]);
+        }
+    }
+}
+
+// Two register sets X, Y alternate: while one row is reduced the other's loads
+// are in flight, and no register copy has to wait on an outstanding load.
 template <typename T, int NA, int NB>
 __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restrict__ P, VecPtrs xa, VecPtrs yb,
                                                 double* __restrict__ rowp, double* __restrict__ colp, int n_ct,
-                                                int n_rt) {
+                                                int n_rt, int rpb) {
     __shared__ double cred[NB > 0 ? NB : 1][kTC];
     const int ct = blockIdx.x, rt = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -257,42 +310,17 @@ __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restr
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < kCPL; ++i) cacc[b][i] = 0.0;
-    const int r_end = min(S, (rt + 1) * kTR);
-    int r = rt * kTR + wave;
-    typename Vec4<T>::type cur[4], nxt[4], nx2[4];
-    load_row(P, ld, r, r < r_end, c0, lane, nxt);
-    load_row(P, ld, r + 4, r + 4 < r_end, c0, lane, nx2);
-    for (; r < r_end; r += 4) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            cur[j] = nxt[j];
-            nxt[j] = nx2[j];
-        }
-        load_row(P, ld, r + 8, r + 8 < r_end, c0, lane, nx2);
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            double sa = 0.0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                sa = fma((double)cur[j].x, xv[a][4 * j], sa);
-                sa = fma((double)cur[j].y, xv[a][4 * j + 1], sa);
-                sa = fma((double)cur[j].z, xv[a][4 * j + 2], sa);
-                sa = fma((double)cur[j].w, xv[a][4 * j + 3], sa);
-            }
-            for (int w = 32; w >= 1; w >>= 1) sa += __shfl_xor(sa, w, 64);
-            if (lane == 0) rowp[((long)a * n_ct + ct) * S + r] = sa;
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const double yr = yb.p[b][r];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                cacc[b][4 * j] = fma((double)cur[j].x, yr, cacc[b][4 * j]);
-                cacc[b][4 * j + 1] = fma((double)cur[j].y, yr, cacc[b][4 * j + 1]);
-                cacc[b][4 * j + 2] = fma((double)cur[j].z, yr, cacc[b][4 * j + 2]);
-                cacc[b][4 * j + 3] = fma((double)cur[j].w, yr, cacc[b][4 * j + 3]);
-            }
-        }
+    const int r_beg = rt * rpb;
+    const int r_end = min(S, r_beg + rpb);
+    int r = r_beg + wave;
+    typename Vec4<T>::type X[4], Y[4];
+    load_row(P, ld, r, r < r_end, c0, lane, X);
+    load_row(P, ld, r + 4, r + 4 < r_end, c0, lane, Y);
+    for (; r < r_end; r += 8) {
+        stream_row<T, NA, NB>(S, r, lane, ct, n_ct, X, xv, cacc, yb, rowp);
+        load_row(P, ld, r + 8, r + 8 < r_end, c0, lane, X);
+        if (r + 4 < r_end) stream_row<T, NA, NB>(S, r + 4, lane, ct, n_ct, Y, xv, cacc, yb, rowp);
+        load_row(P, ld, r + 12, r + 12 < r_end, c0, lane, Y);
     }
     if (NB > 0) {
         // combine the four waves' column sums in a fixed order
@@ -532,21 +560,64 @@ void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32
     check_launch("build_matrix");
 }
 
-StreamPlan stream_plan(int S) {
-    StreamPlan p;
+namespace {
+// blocks of one stream kernel instance resident on the current device at once
+template <typename T, int NA, int NB>
+int stream_slots() {
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cache[kMaxDev];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) throw Error{-3, "stream_plan: hipGetDevice failed"};
+    const int slot = dev >= 0 && dev < kMaxDev ? dev : -1;
+    int v = slot >= 0 ? cache[slot].load(std::memory_order_relaxed) : 0;
+    if (v == 0) {
+        int occ = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_stream<T, NA, NB>, 256, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            throw Error{-3, "stream_plan: occupancy query failed"};
+        v = std::max(1, occ) * std::max(1, cus);
+        if (slot >= 0) cache[slot].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+}  // namespace
+
+StreamPlan stream_plan(int S, int f32, int na, int nb) {
+    StreamPlan p{};
     p.S = S;
-    p.n_rt = (S + kTR - 1) / kTR;
+    p.f32 = f32;
+    p.na = na;
+    p.nb = nb;
+    if (S <= 0) return p;
+    int slots = 0;
+#define EPHX_SLOTS(T)                                             \
+    if (na == 1 && nb == 1) slots = stream_slots<T, 1, 1>();      \
+    else if (na == 2 && nb == 2) slots = stream_slots<T, 2, 2>(); \
+    else if (na == 1 && nb == 0) slots = stream_slots<T, 1, 0>(); \
+    else if (na == 3 && nb == 0) slots = stream_slots<T, 3, 0>(); \
+    else throw Error{-1, "stream_plan: unsupported vector counts"};
+    if (f32) {
+        EPHX_SLOTS(float)
+    } else {
+        EPHX_SLOTS(double)
+    }
+#undef EPHX_SLOTS
     p.n_ct = (S + kTC - 1) / kTC;
+    const int n_rt = std::max(1, slots / p.n_ct);
+    p.rpb = ((S + n_rt - 1) / n_rt + 3) / 4 * 4;
+    p.n_rt = (S + p.rpb - 1) / p.rpb;
     return p;
 }
 
-void stream_pass(const StreamPlan& pl, long ld, const void* P, int f32, int na, VecPtrs x, int nb, VecPtrs y,
-                 double* rowp, double* colp, hipStream_t st) {
+void stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
+                 hipStream_t st) {
+    if (pl.S <= 0) return;
     dim3 grid(pl.n_ct, pl.n_rt);
 #define EPHX_STREAM(T, A, B)                                                                                   \
     hipLaunchKernelGGL((k_stream<T, A, B>), grid, dim3(256), 0, st, pl.S, ld, (const T*)P, x, y, rowp, colp, \
-                       pl.n_ct, pl.n_rt)
-    if (f32) {
+                       pl.n_ct, pl.n_rt, pl.rpb)
+    const int na = pl.na, nb = pl.nb;
+    if (pl.f32) {
         if (na == 1 && nb == 1) EPHX_STREAM(float, 1, 1);
         else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
         else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);

@@ -167,13 +167,17 @@ void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32
 struct VecPtrs {
     const double* p[4];
 };
+// The plan fixes the kernel instance and its tiling; the finish kernels sum
+// the n_ct row partials and n_rt column partials it produces.
 struct StreamPlan {
     int S;
+    int f32, na, nb;      // matrix precision and vector counts
     int n_rt, n_ct;       // row and column tiles
+    int rpb;              // rows per row tile
 };
-StreamPlan stream_plan(int S);
-void stream_pass(const StreamPlan& pl, long ld, const void* P, int f32, int na, VecPtrs x, int nb, VecPtrs y,
-                 double* rowp, double* colp, hipStream_t st);
+StreamPlan stream_plan(int S, int f32, int na, int nb);
+void stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
+                 hipStream_t st);
 // I_s = -c [ f_s R_s - (1-f_s) C_s ] with R, C the reduced partials; optional
 // RK4 stage update: acc = (acc_init ? f_base : acc) + w_acc * I ; f_next = f_base + a_next * I.
 struct CollisionFinish {
