@@ -467,7 +467,11 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     uint16_t* gpbf = nullptr;
     if (precision == EPHX_FP32) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
     const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
-    if (nsplit) gpbf = (uint16_t*)m->ws.get("drv.gpbf", (size_t)bk_eff * 2 * nsplit * ngcol * kp * 2);
+    uint16_t* qpl = nullptr;
+    if (nsplit) {
+        gpbf = (uint16_t*)m->ws.get("drv.gpbf", (size_t)bk_eff * 2 * nsplit * ngcol * kp * 2);
+        qpl = (uint16_t*)m->ws.get("drv.qpl", (size_t)2 * nsplit * qc * kp * 2);
+    }
     const size_t npair = (size_t)bk_eff * qc;
     void* hkq = m->ws.get("drv.hkq", npair * nw2 * 16);
     double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
@@ -516,9 +520,12 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             else if (precision == EPHX_FP32)
                 phase_gemm_f32(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp32, nre_cols, (float*)gw,
                                (long)nqc * ngcol, st);
-            else
-                phase_gemm_bf16(nsplit, nqc, (int)ngcol, m->n_rp_g, kp, nb, qb, nullptr, m->d_rp_g, gpbf,
-                                2L * nsplit * ngcol * kp, (float*)gw, (long)nqc * ngcol, st);
+            else {
+                // phases of the q chunk, shared by every k of the batch
+                phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
+                gemm_bf16_planes(nsplit, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp, (float*)gw,
+                                 (long)nqc * ngcol, st);
+            }
             trp.stop();
             StageTimer tep("epilogue", st);
             EphEpilogue e{};

@@ -51,6 +51,12 @@ void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x
 void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
                      const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC,
                      hipStream_t st);
+// Split-bf16 phase planes [2*nsplit][M][Kp] of exp(2 pi i x_m . n_r) (cos parts
+// then sin parts), and the contraction C[z] = A B[z] that reads them.
+void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const int32_t* nvec, uint16_t* out,
+                       hipStream_t st);
+void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
+                      float* C, long sC, hipStream_t st);
 // Split complex double B[Z][K][N] into those planes.
 void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
                     hipStream_t st);

@@ -334,6 +334,158 @@ __global__ void k_split_bf16(int K, int N, int Kp, const double* __restrict__ B,
     }
 }
 
+// Split-bf16 phase planes of one point set, computed once and read by every
+// contraction over the same points (all k of a batch, all column blocks):
+//   planes[t][m][r]      = part t of cos(2 pi x_m . n_r)      (t < NS)
+//   planes[NS + t][m][r] = part t of sin(2 pi x_m . n_r)
+// r padded to Kp with zero parts.  The values equal those the in-register
+// path generates (same reduced argument, same FP32 sin/cos, same split).
+template <int NS>
+__global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ x, const int32_t* __restrict__ nvec,
+                               uint16_t* __restrict__ out) {
+    const int kg = Kp / 8;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (m, group of 8 r)
+    if (idx >= (long)M * kg) return;
+    const int m = (int)(idx / kg), r0 = (int)(idx % kg) * 8;
+    const double xa = x[3L * m], xb = x[3L * m + 1], xc = x[3L * m + 2];
+    u16x8 pr[NS], pi[NS];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float pc = 0.f, ps = 0.f;
+        if (r0 + j < K) phase_of(reduced_arg(xa, xb, xc, nvec + 3L * (r0 + j)), pc, ps);
+        unsigned short hr[NS], hi[NS];
+        split_n<NS>(pc, hr);
+        split_n<NS>(ps, hi);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            pr[t][j] = hr[t];
+            pi[t][j] = hi[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        *reinterpret_cast<u16x8*>(out + ((long)t * M + m) * Kp + r0) = pr[t];
+        *reinterpret_cast<u16x8*>(out + ((long)(NS + t) * M + m) * Kp + r0) = pi[t];
+    }
+}
+
+// C[z] = A B[z] with A given as phase planes [2NS][M][Kp] and B[z] as planes
+// [2NS][N][Kp].  A wave owns 32 rows (two 16-row fragments) so each B fragment
+// read from LDS feeds twice the MFMAs of the in-register path.  Workgroups are
+// numbered so that each of the 8 XCDs (which receive consecutive workgroup ids
+// in turn) runs a contiguous range of (column, row, z) tiles: the B panel of one
+// z then stays in that XCD's L2 while its row tiles stream the shared A planes.
+constexpr int kWR = 2;                 // 16-row fragments per wave
+constexpr int kBMP = 64 * kWR;         // rows per workgroup
+
+template <int CB, int NS>
+__global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
+                                                          const uint16_t* __restrict__ As,
+                                                          const uint16_t* __restrict__ Bs, long sB,
+                                                          float* __restrict__ C, long sC) {
+    constexpr int BN = 16 * CB;
+    constexpr int NP = 2 * NS;
+    __shared__ __attribute__((aligned(16))) uint16_t bsh[NP][BN][kBK + kPadK];
+    // workgroup id -> tile id, contiguous per XCD
+    const int nblk = nbx * nby * nz;
+    const int b = blockIdx.x;
+    const int xcd = b % 8, slot = b / 8;
+    const int base = nblk / 8, rem = nblk % 8;
+    const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
+    const int bx = tile % nbx, by = (tile / nbx) % nby, z = tile / (nbx * nby);
+    const int row0 = by * kBMP, col0 = bx * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const uint16_t* bz = Bs + (long)z * sB;
+    float* cz = C + (long)z * sC * 2;
+    flt4 are[kWR][CB], aim[kWR][CB];
+#pragma unroll
+    for (int f = 0; f < kWR; ++f)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            are[f][cb] = flt4{0, 0, 0, 0};
+            aim[f][cb] = flt4{0, 0, 0, 0};
+        }
+    const uint16_t* arow[kWR];
+    bool rok[kWR];
+#pragma unroll
+    for (int f = 0; f < kWR; ++f) {
+        const int row = row0 + wave * 16 * kWR + f * 16 + li;
+        rok[f] = row < M;
+        arow[f] = As + (long)(rok[f] ? row : 0) * Kp + 8 * lk;
+    }
+    const long plane = (long)M * Kp;
+    const u16x8 sign = {0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u};
+    for (int kc = 0; kc < Kp; kc += kBK) {
+        // A fragments of this chunk, issued before the B staging
+        u16x8 ar[kWR][NS], ai[kWR][NS];
+#pragma unroll
+        for (int f = 0; f < kWR; ++f)
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+                ar[f][t] = rok[f] ? *reinterpret_cast<const u16x8*>(arow[f] + t * plane + kc) : zero;
+                ai[f][t] = rok[f] ? *reinterpret_cast<const u16x8*>(arow[f] + (NS + t) * plane + kc) : zero;
+            }
+        for (int e = tid; e < NP * BN * (kBK / 8); e += 256) {
+            const int seg = e % (kBK / 8);
+            const int nn = (e / (kBK / 8)) % BN;
+            const int pl = e / ((kBK / 8) * BN);
+            const int col = col0 + nn;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (col < N) v = *reinterpret_cast<const uint4*>(bz + ((long)pl * N + col) * Kp + kc + seg * 8);
+            *reinterpret_cast<uint4*>(&bsh[pl][nn][seg * 8]) = v;
+        }
+        __syncthreads();
+        u16x8 nai[kWR][NS];
+#pragma unroll
+        for (int f = 0; f < kWR; ++f)
+#pragma unroll
+            for (int t = 0; t < NS; ++t) nai[f][t] = ai[f][t] ^ sign;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int nn = cb * 16 + li;
+            u16x8 br[NS], bi[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                br[t] = *reinterpret_cast<const u16x8*>(&bsh[t][nn][8 * lk]);
+                bi[t] = *reinterpret_cast<const u16x8*>(&bsh[NS + t][nn][8 * lk]);
+            }
+#pragma unroll
+            for (int ord = NS - 1; ord >= 0; --ord) {
+#pragma unroll
+                for (int i = 0; i <= ord; ++i) {
+                    const int j = ord - i;
+#pragma unroll
+                    for (int f = 0; f < kWR; ++f) {
+                        are[f][cb] = mfma_bf(ar[f][i], br[j], are[f][cb]);
+                        are[f][cb] = mfma_bf(nai[f][i], bi[j], are[f][cb]);
+                        aim[f][cb] = mfma_bf(ar[f][i], bi[j], aim[f][cb]);
+                        aim[f][cb] = mfma_bf(ai[f][i], br[j], aim[f][cb]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < kWR; ++f)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int col = col0 + cb * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + wave * 16 * kWR + f * 16 + AccOf<float>::row(lk, v);
+                if (row < M && col < N) {
+                    const long off = ((long)row * N + col) * 2;
+                    cz[off] = are[f][cb][v];
+                    cz[off + 1] = aim[f][cb][v];
+                }
+            }
+        }
+}
+
 inline void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
@@ -415,6 +567,47 @@ void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const doubl
     }
 #undef EPHX_BF
     check_launch("phase_gemm_bf16");
+}
+
+void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const int32_t* nvec, uint16_t* out,
+                       hipStream_t st) {
+    if (M <= 0) return;
+    if (Kp % kBK != 0 || Kp < K) throw Error{-1, "phase_planes_bf16: bad Kp"};
+    const long total = (long)M * (Kp / 8);
+    dim3 grid((unsigned)((total + 255) / 256));
+    if (nsplit == 2)
+        hipLaunchKernelGGL(k_phase_planes<2>, grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
+    else if (nsplit == 3)
+        hipLaunchKernelGGL(k_phase_planes<3>, grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
+    else
+        throw Error{-1, "phase_planes_bf16: nsplit must be 2 or 3"};
+    check_launch("phase_planes_bf16");
+}
+
+void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
+                      float* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
+    if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
+    const int cb = pick_cb(N, 8);
+    const int nbx = (N + 16 * cb - 1) / (16 * cb), nby = (M + kBMP - 1) / kBMP;
+    const long nblk = (long)nbx * nby * Z;
+    if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
+    dim3 grid((unsigned)nblk);
+#define EPHX_BFP(CBV, NSV)                                                                                      \
+    hipLaunchKernelGGL((k_gemm_bf16_planes<CBV, NSV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, sB, \
+                       C, sC)
+    if (nsplit == 2) {
+        if (cb == 3) EPHX_BFP(3, 2);
+        else if (cb == 4) EPHX_BFP(4, 2);
+        else EPHX_BFP(8, 2);
+    } else {
+        if (cb == 3) EPHX_BFP(3, 3);
+        else if (cb == 4) EPHX_BFP(4, 3);
+        else EPHX_BFP(8, 3);
+    }
+#undef EPHX_BFP
+    check_launch("gemm_bf16_planes");
 }
 
 void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out, hipStream_t st) {
