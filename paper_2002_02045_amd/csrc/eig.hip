@@ -1,170 +1,218 @@
 // Batched Hermitian eigensolver in FP64 for the small matrices of the method:
 // H(k) and H(k+q) (n = Nw, Eq. wannier_3) and D(q) (n = 3 nat, Eq. IFC2).
 //
-// Cyclic Jacobi with the round-robin (tournament) ordering, so each round
-// applies n/2 disjoint plane rotations at once (Golub & Van Loan, "Matrix
-// Computations", Sec. 8.5, in its complex Hermitian form).  For a pair (p, q)
-// with a_pq = |a_pq| e^{i phi}:
+// Cyclic Jacobi with plane rotations applied to disjoint pairs in parallel
+// (Golub & Van Loan, "Matrix Computations", Sec. 8.5, in its complex Hermitian
+// form).  For a pair (p, q), p < q, with a_pq = |a_pq| e^{i phi}:
 //   th = (a_qq - a_pp)/(2|a_pq|), t = sgn(th)/(|th| + sqrt(th^2 + 1)),
 //   c = 1/sqrt(1 + t^2), s = t c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi},
 // and A <- J^dag A J, V <- V J.
 //
-// Layout: one lane per matrix row, R = 2^ceil(log2 n) lanes per matrix, so a
-// 64-lane wavefront works on 64/R matrices at once.  Column rotations (A J,
-// V J) act inside a lane's own row; row rotations (J^dag A) take the partner
-// row with cross-lane shuffles.  The matrix order n is a template parameter,
-// which unrolls every round of the tournament into register code.  Sweeps
-// run until the off-diagonal Frobenius norm of every matrix in the wavefront
-// is below 1e-15 of its norm; eigenpairs are then sorted ascending.
+// Layout: one lane per matrix row, R = 2^ceil(log2 n) lanes per matrix (rows
+// and columns beyond n are zero and never rotate), 64/R matrices per
+// wavefront.  Round m = 1..R-1 of a sweep pairs row i with row i^m; over a
+// sweep every pair meets once.  Lane i keeps its row in lane-relative order:
+// register d holds column i^d (the diagonal is register 0).  Then every
+// exchange between lanes is "read register e of lane i^x" with x and e fixed
+// at compile time, which the DPP lane permutations do inside the VALU (XOR 1,
+// 2, 3 by quad permutes, XOR 7 by the half-row mirror, XOR 4..6 by both),
+// with no LDS round trip.  Sweeps run until the off-diagonal Frobenius norm of
+// every matrix in the wavefront is below 1e-15 of its norm; eigenpairs are
+// then sorted ascending.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ephx {
 namespace {
 
-template <int NE>
-__device__ __forceinline__ int rr_partner(int idx, int r) {
-    // circle method: position 0 fixed, the others rotate by r each round
-    constexpr int m = NE - 1;
-    const int pos = idx == 0 ? 0 : ((idx - 1 - r) % m + m) % m + 1;
-    const int pp = NE - 1 - pos;
-    return pp == 0 ? 0 : (pp - 1 + r) % m + 1;
+// value of lane (lane ^ X) within each group of 8 lanes
+template <int X>
+__device__ __forceinline__ int xlane(int v) {
+    static_assert(X >= 0 && X < 8, "lane offset");
+    constexpr int kQuad = X == 1 || X == 6 ? 0xB1 : (X == 2 || X == 5 ? 0x4E : 0x1B);   // XOR 1, 2, 3
+    constexpr int kMirror = 0x141;                                                      // lane -> 7 - lane
+    if (X == 0) return v;
+    if (X <= 3) return __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, false);
+    if (X == 7) return __builtin_amdgcn_update_dpp(0, v, kMirror, 0xF, 0xF, false);
+    const int w = __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, false);   // X ^ 7 in {3, 2, 1}
+    return __builtin_amdgcn_update_dpp(0, w, kMirror, 0xF, 0xF, false);
+}
+template <int X>
+__device__ __forceinline__ double xlane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = xlane<X>((int)(b & 0xffffffffLL)), hi = xlane<X>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ double shfl(double v, int src) { return __shfl(v, src, 64); }
+struct Cx {
+    double r, i;
+};
+
+// Columns c1 = i^D (register D) and c2 = i^D^M (register E = D^M) form one pair
+// of the round, rotated with the parameters of lane i^D's pair.  With X_p, X_q
+// the columns of the pair (p < q),
+//   (XJ)_{.p} = c X_p - conj(se) X_q ,   (XJ)_{.q} = c X_q + se X_p ,
+// so each register is updated as  x_D <- c x_D + s_D x_E,  x_E <- c x_E + s_E x_D
+// with s = -conj(se) for the p column and s = se for the q column: the two
+// differ only in the sign of the real part, so no operand is selected.
+template <int R, int M, int D>
+__device__ __forceinline__ void column_pair(int i, Cx (&a)[R], Cx (&v)[R], double c, double sr, double si) {
+    constexpr int E = D ^ M;
+    constexpr int kTop = M >= 4 ? 4 : (M >= 2 ? 2 : 1);   // highest bit of M
+    const double cc = xlane<D>(c), s_r = xlane<D>(sr), s_i = xlane<D>(si);
+    const bool d_is_p = ((i ^ D) & kTop) == 0;
+    const double rd = d_is_p ? -s_r : s_r;   // real part of s_D; s_E has -rd
+    const Cx xd = a[D], xe = a[E];
+    a[D] = Cx{fma(cc, xd.r, fma(rd, xe.r, -s_i * xe.i)), fma(cc, xd.i, fma(rd, xe.i, s_i * xe.r))};
+    a[E] = Cx{fma(cc, xe.r, fma(-rd, xd.r, -s_i * xd.i)), fma(cc, xe.i, fma(-rd, xd.i, s_i * xd.r))};
+    const Cx yd = v[D], ye = v[E];
+    v[D] = Cx{fma(cc, yd.r, fma(rd, ye.r, -s_i * ye.i)), fma(cc, yd.i, fma(rd, ye.i, s_i * ye.r))};
+    v[E] = Cx{fma(cc, ye.r, fma(-rd, yd.r, -s_i * yd.i)), fma(cc, ye.i, fma(-rd, yd.i, s_i * yd.r))};
+}
+
+template <int R, int M, int D>
+__device__ __forceinline__ void column_pairs(int i, Cx (&a)[R], Cx (&v)[R], double c, double sr, double si) {
+    if constexpr (D < R) {
+        if constexpr (D < (D ^ M)) column_pair<R, M, D>(i, a, v, c, sr, si);
+        column_pairs<R, M, D + 1>(i, a, v, c, sr, si);
+    }
+}
+
+template <int R, int M, int D>
+__device__ __forceinline__ void fetch_partner_row(const Cx (&a)[R], Cx (&q)[R]) {
+    // partner row i^M, column i^D sits in the partner's register D^M
+    if constexpr (D < R) {
+        q[D].r = xlane<M>(a[D ^ M].r);
+        q[D].i = xlane<M>(a[D ^ M].i);
+        fetch_partner_row<R, M, D + 1>(a, q);
+    }
+}
+
+template <int R, int M>
+__device__ __forceinline__ void jacobi_round(int i, Cx (&a)[R], Cx (&v)[R]) {
+    // rotation of the pair (i, i^M), evaluated by its lower lane and copied
+    const bool lower = i < (i ^ M);
+    const double dself = a[0].r;
+    const double dpart = xlane<M>(a[0].r);
+    const double apr = a[M].r, api = a[M].i;   // A[i][i^M]
+    const double mag = sqrt(apr * apr + api * api);
+    const double th = (dpart - dself) / (2.0 * mag);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+    const double c0 = 1.0 / sqrt(t * t + 1.0);
+    const double s0 = t * c0;
+    const bool rot = mag > 0.0;
+    double c = rot ? c0 : 1.0;
+    double sr = rot ? s0 * apr / mag : 0.0;
+    double si = rot ? s0 * api / mag : 0.0;
+    const double cp = xlane<M>(c), srp = xlane<M>(sr), sip = xlane<M>(si);
+    c = lower ? c : cp;
+    sr = lower ? sr : srp;
+    si = lower ? si : sip;
+    // column rotations A J and V J for every pair of the round
+    column_pairs<R, M, 0>(i, a, v, c, sr, si);
+    // row rotation J^dag A with the partner row: lower row p <- c A_p - se A_q,
+    // upper row q <- c A_q + conj(se) A_p, i.e. a <- c a + t q with
+    // t = (-sr, -si) or (sr, -si)
+    Cx q[R];
+    fetch_partner_row<R, M, 0>(a, q);
+    const double tr = lower ? -sr : sr;
+#pragma unroll
+    for (int d = 0; d < R; ++d)
+        a[d] = Cx{fma(c, a[d].r, fma(tr, q[d].r, si * q[d].i)), fma(c, a[d].i, fma(tr, q[d].i, -si * q[d].r))};
+}
+
+template <int R, int M>
+__device__ __forceinline__ void jacobi_sweep(int i, Cx (&a)[R], Cx (&v)[R]) {
+    if constexpr (M < R) {
+        jacobi_round<R, M>(i, a, v);
+        jacobi_sweep<R, M + 1>(i, a, v);
+    }
+}
+
+template <int R, int X>
+__device__ __forceinline__ double group_sum(double x) {
+    if constexpr (X < R) return group_sum<R, 2 * X>(x + xlane<X>(x));
+    return x;
+}
+
+template <int R, int E>
+__device__ __forceinline__ void rank_step(int i, int n, double d, int& rk) {
+    if constexpr (E < R) {
+        const double de = xlane<E>(d);
+        const int j = i ^ E;
+        rk += (E != 0 && j < n && (de < d || (de == d && j < i))) ? 1 : 0;
+        rank_step<R, E + 1>(i, n, d, rk);
+    }
+}
+
+template <int R, int E, typename F>
+__device__ __forceinline__ void for_offsets(F&& f) {
+    if constexpr (E < R) {
+        f(std::integral_constant<int, E>{});
+        for_offsets<R, E + 1>(f);
+    }
+}
 
 template <typename Tin, int N>
 __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restrict__ A, long strideA,
                                                   double* __restrict__ evals, double* __restrict__ evecs) {
     constexpr int R = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
-    constexpr int NE = N + (N & 1);
     const int lane = threadIdx.x & 63;
     const long slot = ((long)blockIdx.x * 256 + threadIdx.x) / R;
     const int i = lane % R;
-    const int base = lane - i;
     const bool valid = slot < batch;
     const bool act = valid && i < N;
-    double ar[N], ai[N], vr[N], vi[N];
+    Cx a[R], v[R];
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        ar[j] = ai[j] = vi[j] = 0.0;
-        vr[j] = (j == i) ? 1.0 : 0.0;
+    for (int d = 0; d < R; ++d) {
+        a[d] = Cx{0.0, 0.0};
+        v[d] = Cx{d == 0 ? 1.0 : 0.0, 0.0};
     }
     if (act) {
         const Tin* ab = A + slot * strideA * 2;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            // Hermitian part 0.5 (A + A^dag)
-            const double xr = (double)ab[2 * (i * N + j)], xi = (double)ab[2 * (i * N + j) + 1];
-            const double yr = (double)ab[2 * (j * N + i)], yi = (double)ab[2 * (j * N + i) + 1];
-            ar[j] = 0.5 * (xr + yr);
-            ai[j] = 0.5 * (xi - yi);
+        for (int d = 0; d < R; ++d) {
+            const int j = i ^ d;
+            if (j < N) {
+                // Hermitian part 0.5 (A + A^dag)
+                const double xr = (double)ab[2 * (i * N + j)], xi = (double)ab[2 * (i * N + j) + 1];
+                const double yr = (double)ab[2 * (j * N + i)], yi = (double)ab[2 * (j * N + i) + 1];
+                a[d] = Cx{0.5 * (xr + yr), 0.5 * (xi - yi)};
+            }
         }
     }
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, tot = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double m2 = ar[j] * ar[j] + ai[j] * ai[j];
+        for (int d = 0; d < R; ++d) {
+            const double m2 = a[d].r * a[d].r + a[d].i * a[d].i;
             tot += m2;
-            off += (j != i) ? m2 : 0.0;
+            off += d != 0 ? m2 : 0.0;
         }
-#pragma unroll
-        for (int w = R / 2; w >= 1; w >>= 1) {
-            off += __shfl_xor(off, w, 64);
-            tot += __shfl_xor(tot, w, 64);
-        }
+        off = group_sum<R, 1>(off);
+        tot = group_sum<R, 1>(tot);
         const bool done = !(off > 1e-30 * tot);
         if (__all(done)) break;
-#pragma unroll
-        for (int r = 0; r < NE - 1; ++r) {
-            const int p = i < NE ? rr_partner<NE>(i, r) : i;
-            // rotation of the pair (i, p), computed by its lower lane
-            double dself = 0.0, apr = 0.0, api = 0.0;
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                dself = (j == i) ? ar[j] : dself;
-                apr = (j == p) ? ar[j] : apr;
-                api = (j == p) ? ai[j] : api;
-            }
-            const double dpart = shfl(dself, base + (p < R ? p : i));
-            double c = 1.0, ser = 0.0, sei = 0.0;   // se = s e^{i phi}
-            if (i < p && p < N) {
-                const double mag = sqrt(apr * apr + api * api);
-                if (mag > 0.0) {
-                    const double th = (dpart - dself) / (2.0 * mag);
-                    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                    c = 1.0 / sqrt(t * t + 1.0);
-                    const double s = t * c;
-                    ser = s * apr / mag;
-                    sei = s * api / mag;
-                }
-            }
-            // column rotations A J and V J, every pair of the round (indices are compile-time)
-#pragma unroll
-            for (int p0 = 0; p0 < N; ++p0) {
-                const int q0 = rr_partner<NE>(p0, r);
-                if (!(p0 < q0 && q0 < N)) continue;
-                const double cc = shfl(c, base + p0), sr = shfl(ser, base + p0), si = shfl(sei, base + p0);
-                // (AJ)_{.p} = c A_.p - conj(se) A_.q ; (AJ)_{.q} = se A_.p + c A_.q
-                const double xr = ar[p0], xi = ai[p0], yr = ar[q0], yi = ai[q0];
-                ar[p0] = cc * xr - (sr * yr + si * yi);
-                ai[p0] = cc * xi - (sr * yi - si * yr);
-                ar[q0] = (sr * xr - si * xi) + cc * yr;
-                ai[q0] = (sr * xi + si * xr) + cc * yi;
-                const double ur = vr[p0], ui = vi[p0], wr = vr[q0], wi = vi[q0];
-                vr[p0] = cc * ur - (sr * wr + si * wi);
-                vi[p0] = cc * ui - (sr * wi - si * wr);
-                vr[q0] = (sr * ur - si * ui) + cc * wr;
-                vi[q0] = (sr * ui + si * ur) + cc * wi;
-            }
-            // row rotation J^dag A with the partner row
-            const int lo = i < p ? i : p;
-            const double co = shfl(c, base + (lo < R ? lo : i));
-            const double sro = shfl(ser, base + (lo < R ? lo : i));
-            const double sio = shfl(sei, base + (lo < R ? lo : i));
-            const int src = base + (p < R ? p : i);
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                const double qr = shfl(ar[j], src), qi = shfl(ai[j], src);
-                if (p < N && p != i) {
-                    if (i < p) {
-                        // (J^dag A)_{p.} = c A_p. - se A_q.
-                        const double nr = co * ar[j] - (sro * qr - sio * qi);
-                        const double ni = co * ai[j] - (sro * qi + sio * qr);
-                        ar[j] = nr;
-                        ai[j] = ni;
-                    } else {
-                        // (J^dag A)_{q.} = conj(se) A_p. + c A_q.
-                        const double nr = (sro * qr + sio * qi) + co * ar[j];
-                        const double ni = (sro * qi - sio * qr) + co * ai[j];
-                        ar[j] = nr;
-                        ai[j] = ni;
-                    }
-                }
-            }
-        }
+        jacobi_sweep<R, 1>(i, a, v);
     }
     // sort ascending, ties by index
-    double d = 0.0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) d = (j == i) ? ar[j] : d;
+    const double dv = a[0].r;
     int rk = 0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const double dm = shfl(d, base + m);
-        rk += (dm < d || (dm == d && m < i)) ? 1 : 0;
-    }
-    if (act) evals[slot * N + rk] = d;
+    rank_step<R, 0>(i, N, dv, rk);
+    if (act) evals[slot * N + rk] = dv;
     if (evecs != nullptr) {
-#pragma unroll
-        for (int c2 = 0; c2 < N; ++c2) {
-            const int rc = __shfl(rk, base + c2, 64);
-            if (act) {
+        // V[i][c] with c = i^e sits in register e; its column goes to rank(c)
+        for_offsets<R, 0>([&](auto ec) {
+            constexpr int E = decltype(ec)::value;
+            const int rc = xlane<E>(rk);
+            const int c = i ^ E;
+            if (act && c < N) {
                 const long off = ((slot * N + i) * N + rc) * 2;
-                evecs[off] = vr[c2];
-                evecs[off + 1] = vi[c2];
+                evecs[off] = v[E].r;
+                evecs[off + 1] = v[E].i;
             }
-        }
+        });
     }
 }
 
