@@ -30,6 +30,29 @@ def rates_grad_g(model, k, q, lam, **rate_kw):
     return float(loss.detach()), gt.grad
 
 
+def mobility_of(model, n_grid, k_idx, band, vel, *, mu, temp, sigma, n_q, n_iter, omega_cut=1e-4, polar=None):
+    """Mobility tensor (Eq. cond over e n_c) after n_iter iterations of the
+    linearised BTE (Eqs. BTE_W, BTE_iter) on the symmetrised pair table of the
+    given grid states; differentiable in model.g."""
+    g2s, om = bte.pair_table(model, n_grid, k_idx, band, omega_cut=omega_cut, polar=polar)
+    eps = bte.state_energies(model, k_idx, band, n_grid)
+    w = bte.transport_matrix(eps, g2s, om, temp=temp, mu=mu, sigma=sigma, omega_cut=omega_cut)
+    ff, _ = bte.ita(w, vel, n_q, n_iter)
+    return bte.mobility(eps, vel, ff, mu=mu, temp=temp)
+
+
+def mobility_grad_g(model, n_grid, k_idx, band, vel, lam, **kw):
+    """dL/dg(Re,Rp) for L = sum_ab lam_ab mu_ab with mu from mobility_of: the
+    chain g -> |g|^2 table -> W -> (tau, F) -> mu, by autograd."""
+    m = copy.copy(model)
+    gt = torch.as_tensor(model.g, dtype=torch.complex128).clone().requires_grad_(True)
+    m.g = gt
+    mob = mobility_of(m, n_grid, k_idx, band, vel, **kw)
+    loss = (mob * t64(lam)).sum()
+    loss.backward()
+    return float(loss.detach()), gt.grad
+
+
 def dynamics_mean_energy(f0, eps, g2s, omega, mode_scale, *, dt, n_steps, e_ref, **coll_kw):
     """Mean carrier energy sum_s (eps_s - e_ref) f_s / sum_s f_s after n_steps RK4
     steps of df/dt = I[f] (Eq. BTE_E with E = 0)."""

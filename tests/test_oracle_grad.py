@@ -6,7 +6,7 @@ import numpy as np
 import torch
 
 import synth
-from oracle import bte, eph, grad
+from oracle import bte, eph, grad, grid, interp
 
 
 def test_rates_gradient_wrt_g_matches_finite_differences(tiny_model):
@@ -58,3 +58,41 @@ def test_dynamics_gradient_matches_finite_differences():
         ep = float(grad.dynamics_mean_energy(f0, eps, g2s, om, sp, **kw))
         em = float(grad.dynamics_mean_energy(f0, eps, g2s, om, sm, **kw))
         assert abs((ep - em) / (2 * h) - float(ds[nu])) <= 1e-6 * float(ds.abs().max())
+
+
+def _mobility_case():
+    m = synth.make_config_model("tiny", real=True)
+    n = (4, 4, 4)
+    eps_g, _ = interp.bands(m, grid.grid_points(n))
+    cbm = float(eps_g[:, m.nw // 2].min())
+    kk, bb = grid.window_states(eps_g.numpy(), m.nw // 2, m.nw, cbm - 0.01, cbm + 1.0)
+    _, _, v = interp.bands(m, bte.state_points(kk, n), velocity=True)
+    vel = v[torch.arange(len(bb)), torch.as_tensor(bb)]
+    kw = dict(mu=cbm - 0.3, temp=300.0, sigma=0.1, n_q=float(np.prod(n)), n_iter=3)
+    return m, n, kk, bb, vel, kw
+
+
+def test_mobility_gradient_wrt_g_matches_finite_differences():
+    m, n, kk, bb, vel, kw = _mobility_case()
+    assert len(kk) >= 8
+    lam = np.random.default_rng(55).standard_normal((3, 3))
+    loss, g_bar = grad.mobility_grad_g(m, n, kk, bb, vel, lam, **kw)
+    assert np.isfinite(loss) and float(g_bar.abs().max()) > 0
+    rng = np.random.default_rng(56)
+    h = 1e-6
+    # random directions over the whole tensor and single entries
+    dirs = [rng.standard_normal(m.g.shape) + 1j * rng.standard_normal(m.g.shape) for _ in range(2)]
+    for _ in range(3):
+        d = np.zeros(m.g.shape, dtype=np.complex128)
+        d[tuple(int(rng.integers(0, s)) for s in m.g.shape)] = 1.0 if rng.random() < 0.5 else 1j
+        dirs.append(d)
+    for d in dirs:
+        mp = copy.deepcopy(m)
+        mm = copy.deepcopy(m)
+        mp.g = m.g + h * d
+        mm.g = m.g - h * d
+        lp = float((grad.mobility_of(mp, n, kk, bb, vel, **kw) * torch.as_tensor(lam)).sum())
+        lm = float((grad.mobility_of(mm, n, kk, bb, vel, **kw) * torch.as_tensor(lam)).sum())
+        fd = (lp - lm) / (2 * h)
+        ad = float((g_bar.conj() * torch.as_tensor(d)).real.sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3 * float(g_bar.abs().sum()))
