@@ -236,6 +236,20 @@ int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, int n_steps
 int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
                   double* f_out, double* tau_out, double* mob_out, void* stream);
 
+/* Adjoint of ephx_mobility with respect to the coupling tensor (FP64): for
+ * L = sum_ab mob_bar[a][b] mu_ab (mob_bar device double [3][3]) and the same
+ * table, p, vel and n_iter as the forward call, writes g_bar = dL/dRe g(Re,Rp)
+ * + i dL/dIm g(Re,Rp) (device complex128, layout of the model's g, overwritten).
+ * The chain is the reverse of Eqs. BTE_iter and cond (the iteration is rerun
+ * and kept, then reversed with one pass of W^T per iteration), W_bar through
+ * Eq. BTE_W and the symmetrisation of the table, and the adjoint of Eqs.
+ * eph_mat and eph_mat_wann2 for every ordered pair of states: conjugate-phase
+ * sums over the targets (q = k_t - k_s) and the sources.  The forward g is
+ * recomputed in FP64 whatever the table's precision.  Synchronises the stream
+ * before returning (the workspace is reused by the next call). */
+int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
+                      const double* mob_bar, double* g_bar, void* stream);
+
 /* Stage timers (instrumentation, not part of the method).  While enabled,
  * the library brackets each launch of its main kernels with HIP events on the
  * launch stream, keyed by stage name: "re_contraction", "hkq_fourier",

@@ -171,6 +171,22 @@ class RatesFunction(torch.autograd.Function):
         return rates_vjp(ctx.model, ctx.k, ctx.q, ctx.params, gbar), None, None, None, None
 
 
+class MobilityFunction(torch.autograd.Function):
+    """mu(g(Re,Rp)) (3x3, cm^2/(V s)) of a pair table with the hand-written
+    adjoint (FP64).  As for RatesFunction, g only connects the graph: the
+    table built from the library's model holds the values that are used."""
+
+    @staticmethod
+    def forward(ctx, g, table, params, vel, n_iter):
+        _, _, mob = table.mobility(params, vel, n_iter)
+        ctx.table, ctx.params, ctx.vel, ctx.n_iter = table, params, vel, n_iter
+        return mob
+
+    @staticmethod
+    def backward(ctx, mob_bar):
+        return ctx.table.mobility_vjp(ctx.params, ctx.vel, ctx.n_iter, mob_bar), None, None, None, None
+
+
 def grid_states(model, n_grid, *, mode="window", band_lo=0, band_hi=None, e_lo=0.0, e_hi=0.0, count=0,
                 capacity=None):
     """Window (mode="window") or lowest-count (mode="lowest") states on a
@@ -272,3 +288,12 @@ class PairTable:
         check(lib.ephx_mobility(self._h, C.byref(pc), ptr(vel), int(n_iter), ptr(ff), ptr(tau), ptr(mob),
                                 stream_ptr()))
         return ff, tau, mob
+
+    def mobility_vjp(self, params, vel, n_iter, mob_bar):
+        """dL/dg(Re,Rp) (complex128, layout of the model's g) for L = sum mob_bar * mu."""
+        vel = torch.as_tensor(vel, dtype=F64, device="cuda").contiguous()
+        mb = torch.as_tensor(mob_bar, dtype=F64, device="cuda").contiguous()
+        out = torch.empty(self.model.g_shape, dtype=torch.complex128, device="cuda")
+        pc = params.c()
+        check(lib.ephx_mobility_vjp(self._h, C.byref(pc), ptr(vel), int(n_iter), ptr(mb), ptr(out), stream_ptr()))
+        return out

@@ -92,4 +92,5 @@ void bands_impl(ephx_model* m, int nk, const double* k, double* eps, double* u, 
                 const std::string& tag);
 void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double* evec, hipStream_t st,
                   const std::string& tag);
+void negated_vectors(ephx_model* m);
 }  // namespace ephx

@@ -28,6 +28,7 @@ struct ephx_table {
     double* d_unit = nullptr;     // [nm] ones (transport matrix)
     double* d_ones = nullptr;     // [S]
     ephx_params par{};
+    double build_cut = 0.0;       // omega cut of the table's |g|^2
     bool ready = false;
     double c = 0.0;               // (2 pi/hbar)/N_q
     std::vector<void*> owned;
@@ -352,6 +353,7 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
             t->d_unit = (double*)t->alloc(nm * 8);
             fill(nm, 1.0, t->d_unit, st);
             t->par.omega_cut = omega_cut;
+            t->build_cut = omega_cut;
             hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
             // release the build buffers
             t->ws.release();
@@ -540,5 +542,151 @@ extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* 
         }
         mobility_reduce(S, t->d_eps, vel, f, p->mu, p->temp, f_out, mob_out, st);
         if (tau_out) hip_check(hipMemcpyAsync(tau_out, tau, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    });
+}
+
+// dL/dg(Re,Rp) for L = sum_ab lam_ab mu_ab, mu from ephx_mobility with the same
+// arguments.  The iteration is rerun keeping F^0..F^n, reversed with one
+// column pass over W per step, and the resulting W_bar (never stored) is taken
+// back through the transport weights, the symmetrisation, the table epilogue,
+// the Rp sum over the targets of each source, U(k_s) and the Re sum, per
+// chunk of source states, all in FP64.
+extern "C" int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
+                                 const double* mob_bar, double* g_bar, void* stream) {
+    return guarded([&] {
+        require(t != nullptr && p != nullptr, "mobility_vjp: null argument");
+        require(vel != nullptr && mob_bar != nullptr && g_bar != nullptr, "mobility_vjp: null array");
+        require(n_iter >= 0, "mobility_vjp: n_iter < 0");
+        require(p->temp > 0 && p->sigma > 0 && p->n_q > 0 && std::isfinite(p->mu), "mobility_vjp: bad parameters");
+        ephx_model* m = t->m;
+        hipStream_t st = (hipStream_t)stream;
+        const int S = t->S, nm = t->nm, nw = t->nw, nw2 = nw * nw;
+        const size_t esz = t->f32 ? 4 : 8;
+        // forward iteration with its history
+        if (!t->d_w) {
+            t->d_w = t->alloc((size_t)S * t->ld * esz);
+            hip_check(hipMemsetAsync(t->d_w, 0, (size_t)S * t->ld * esz, st), "hipMemsetAsync");
+        }
+        build_matrix(1, S, nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
+                     p->temp, p->mu, p->sigma, p->omega_cut, t->d_unit, t->d_w, st);
+        const long s3 = 3L * S;
+        double* tau = (double*)t->ws.get("mv.tau", S * 8);
+        double* fh = (double*)t->ws.get("mv.fh", (size_t)(n_iter + 1) * s3 * 8);
+        double* fscr = (double*)t->ws.get("mv.f", s3 * 8);
+        const StreamPlan pl1 = plan_for(t, 1, 0), pl3 = plan_for(t, 3, 0), plc = plan_for(t, 0, 3);
+        double* rowp = (double*)t->ws.get("mv.rowp", (size_t)3 * pl3.n_ct * S * 8);
+        double* colp = (double*)t->ws.get("mv.colp", (size_t)3 * plc.n_rt * S * 8);
+        VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
+        one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
+        ita_gamma(S, pl1.n_ct, rowp, p->n_q, vel, tau, fh, fscr, st);
+        for (int it = 0; it < n_iter; ++it) {
+            const double* fi = fh + it * s3;
+            VecPtrs x{{fi, fi + S, fi + 2 * S, nullptr}};
+            one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
+            ita_update(S, pl3.n_ct, rowp, p->n_q, tau, fh, fh + (it + 1) * s3, st);
+        }
+        // reverse
+        double* fbar = (double*)t->ws.get("mv.fbar", s3 * 8);
+        double* taubar = (double*)t->ws.get("mv.taubar", S * 8);
+        double* ubar = (double*)t->ws.get("mv.ubar", (size_t)std::max(1, n_iter) * s3 * 8);
+        double* gambar = (double*)t->ws.get("mv.gambar", S * 8);
+        mob_seed(S, t->d_eps, vel, mob_bar, p->mu, p->temp, fbar, st);
+        for (int it = n_iter - 1; it >= 0; --it) {
+            double* ui = ubar + it * s3;
+            ita_adj_step(S, tau, fbar, fh + (it + 1) * s3, taubar, ui, it == n_iter - 1 ? 1 : 0, st);
+            VecPtrs y{{ui, ui + S, ui + 2 * S, nullptr}};
+            one_pass(t, plc, t->d_w, none, y, nullptr, colp, st, "transport_stream");
+            ita_adj_cols(S, plc.n_rt, colp, p->n_q, fbar, st);
+        }
+        ita_adj_final(S, tau, fbar, vel, taubar, n_iter == 0 ? 1 : 0, gambar, st);
+
+        // states, their U(k), phonon eigenvectors on the grid, long-range term
+        std::vector<int32_t> kc(3 * S);
+        hip_check(hipMemcpyAsync(kc.data(), t->d_kc, 3 * S * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        std::vector<double> ks(3 * S), nks(3 * S);
+        const int nn[3] = {t->n1, t->n2, t->n3};
+        for (int i = 0; i < 3 * S; ++i) {
+            ks[i] = (double)kc[i] / nn[i % 3];
+            nks[i] = -ks[i];
+        }
+        double* dks = (double*)t->ws.get("mv.ks", 3 * S * 8);
+        double* dnks = (double*)t->ws.get("mv.nks", 3 * S * 8);
+        hip_check(hipMemcpyAsync(dks, ks.data(), 3 * S * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(dnks, nks.data(), 3 * S * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        double* eall = (double*)t->ws.get("mv.eall", (size_t)S * nw * 8);
+        double* us = (double*)t->ws.get("mv.u", (size_t)S * nw2 * 16);
+        bands_impl(m, S, dks, eall, us, nullptr, st, "mv");
+        const long ng = (long)t->n1 * t->n2 * t->n3;
+        std::vector<double> qp = grid_points(t->n1, t->n2, t->n3);
+        double* dq = (double*)t->ws.get("mv.q", ng * 3 * 8);
+        hip_check(hipMemcpyAsync(dq, qp.data(), ng * 3 * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        double* omg = (double*)t->ws.get("mv.om", ng * nm * 8);
+        double* evec = (double*)t->ws.get("mv.evec", (size_t)ng * nm * nm * 16);
+        phonons_impl(m, (int)ng, dq, omg, evec, st, "mv");
+        double* lr = nullptr;
+        if (m->polar) {
+            lr = (double*)t->ws.get("mv.lr", (size_t)ng * nm * 16);
+            frohlich((int)ng, dq, m->pd, lr, st);
+        }
+        negated_vectors(m);
+        const long ncol = (long)nm * nw;
+        const long nre_cols = (long)m->n_rp_g * nm * nw2;
+        hip_check(hipMemsetAsync(g_bar, 0, (size_t)m->n_re_g * nre_cols * 16, st), "hipMemsetAsync");
+        int sc = (int)std::max(1L, std::min<long>(64, (1L << 28) / std::max(1L, (long)S * ncol * 16)));
+        sc = std::min(sc, S);
+        double* gk = (double*)t->ws.get("mv.gk", (size_t)sc * nre_cols * 16);
+        double* gcol = (double*)t->ws.get("mv.gcol", (size_t)sc * m->n_rp_g * ncol * 16);
+        double* gwt = (double*)t->ws.get("mv.gw", (size_t)sc * S * ncol * 16);
+        double* gwb = (double*)t->ws.get("mv.gwb", (size_t)sc * S * ncol * 16);
+        const long sB = (long)m->n_rp_g * ncol;
+        for (int s0 = 0; s0 < S; s0 += sc) {
+            const int nb = std::min(sc, S - s0);
+            StageTimer tm("mobility_adjoint_pairs", st);
+            phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, dks + 3L * s0, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+            apply_u_column(nb, m->n_rp_g, nm, nw, gk, us + (size_t)s0 * nw2 * 2, t->d_band + s0, gcol, st);
+            phase_gemm_f64(S, (int)ncol, m->n_rp_g, nb, dks, dnks + 3L * s0, m->d_rp_g, gcol, sB, gwt, (long)S * ncol,
+                           st);
+            PairAdjoint pa{};
+            pa.ns_chunk = nb;
+            pa.s_off = s0;
+            pa.S = S;
+            pa.nw = nw;
+            pa.nm = nm;
+            pa.gw = gwt;
+            pa.ut = us;
+            pa.us = us;
+            pa.band = t->d_band;
+            pa.kc = t->d_kc;
+            pa.n1 = t->n1;
+            pa.n2 = t->n2;
+            pa.n3 = t->n3;
+            pa.omega = omg;
+            pa.evec = evec;
+            pa.lr = lr;
+            pa.minv = m->d_minv;
+            pa.omega_cut_table = t->build_cut;
+            pa.n_hist = 3 * n_iter;
+            pa.ubar = ubar;
+            pa.fhist = fh;
+            pa.gamma_bar = gambar;
+            pa.n_q = p->n_q;
+            pa.eps = t->d_eps;
+            pa.temp = p->temp;
+            pa.mu = p->mu;
+            pa.sigma = p->sigma;
+            pa.omega_cut = p->omega_cut;
+            pa.gw_bar = gwb;
+            pair_adjoint(pa, st);
+            // g'(k_s,Rp)_bar = sum_t exp(-2 pi i (k_t - k_s).Rp) g'W_bar(s,t): the sum over
+            // exp(-2 pi i k_t.Rp) here, the exp(2 pi i k_s.Rp) factor with U(k_s)^dag
+            phase_gemm_adj_f64(m->n_rp_g, (int)ncol, S, nb, m->d_nrp_g, dks, gwb, (long)S * ncol, gcol, sB, 0, st);
+            apply_u_column_adj(nb, m->n_rp_g, nm, nw, s0, gcol, dks, m->d_rp_g, us, t->d_band, gk, st);
+            // g(Re,Rp)_bar += sum_s exp(-2 pi i k_s.Re) g(k_s,Rp)_bar
+            phase_gemm_adj_f64(m->n_re_g, (int)nre_cols, nb, 1, m->d_nre_g, dks + 3L * s0, gk, 0, g_bar, 0, 1, st);
+        }
+        if (m->d_wg) scale_rows((long)m->n_re_g * m->n_rp_g, nm * nw2, m->d_wg, g_bar, st);
+        // keep the workspace alive until the stream has used it
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     });
 }

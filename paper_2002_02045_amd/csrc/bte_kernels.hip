@@ -479,6 +479,190 @@ __global__ void k_mobility(int S, const double* __restrict__ eps, const double* 
     if (threadIdx.x < 9 && mob) mob[threadIdx.x] = 0.1 * red[threadIdx.x][0] / red[9][0];
 }
 
+// ---------------------------------------------------------------- mobility adjoint
+// Reverse of the iteration (Eqs. BTE_iter, cond) for L = sum_ab lam_ab mu_ab, with
+//   F^{i+1} = tau (v + (1/N_q) W F^i),  F^0 = tau v,  tau_s = N_q / sum_t W_st.
+// F and its adjoint are stored [3][S].
+
+// F_bar_b(s) = 0.1 sum_a lam_ab v^a_s f0_s (1 - f0_s)/kT / sum_t f0_t  (one block)
+__global__ void k_mob_seed(int S, const double* __restrict__ eps, const double* __restrict__ vel,
+                           const double* __restrict__ lam, double mu, double temp, double* __restrict__ fbar) {
+    __shared__ double red[256];
+    const double kt = kBoltzEv * temp;
+    double a = 0.0;
+    for (int s = threadIdx.x; s < S; s += 256) a += 1.0 / (exp((eps[s] - mu) / kt) + 1.0);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double tot = red[0];
+    for (int s = threadIdx.x; s < S; s += 256) {
+        const double f0 = 1.0 / (exp((eps[s] - mu) / kt) + 1.0);
+        const double w = 0.1 * f0 * (1.0 - f0) / kt / tot;
+        for (int b = 0; b < 3; ++b) {
+            double c = 0.0;
+            for (int a2 = 0; a2 < 3; ++a2) c += lam[3 * a2 + b] * vel[3 * s + a2];
+            fbar[(long)b * S + s] = w * c;
+        }
+    }
+}
+
+// step i (F^{i+1} = tau u^i): tau_bar += sum_b Fbar^{i+1}_b F^{i+1}_b / tau ; ubar^i = tau Fbar^{i+1}
+__global__ void k_ita_adj_step(int S, const double* __restrict__ tau, const double* __restrict__ fbar,
+                               const double* __restrict__ fnext, double* __restrict__ taubar,
+                               double* __restrict__ ubar, int first) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double tb = first ? 0.0 : taubar[s];
+    for (int b = 0; b < 3; ++b) {
+        const long o = (long)b * S + s;
+        tb += fbar[o] * fnext[o] / tau[s];
+        ubar[o] = tau[s] * fbar[o];
+    }
+    taubar[s] = tb;
+}
+
+// Fbar^i_t = (1/N_q) sum_s W_st ubar^i_s from the column partials of one pass
+__global__ void k_ita_adj_cols(int S, int n_rt, const double* __restrict__ colp, double n_q, double* __restrict__ fbar) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    for (int b = 0; b < 3; ++b) {
+        double c = 0.0;
+        for (int rt = 0; rt < n_rt; ++rt) c += colp[((long)b * n_rt + rt) * S + t];
+        fbar[(long)b * S + t] = c / n_q;
+    }
+}
+
+// F^0 = tau v: tau_bar += sum_b Fbar^0_b v_b ; Gamma_bar = -tau^2 tau_bar, so that
+// W_bar_st gets Gamma_bar_s / N_q from the row sum
+__global__ void k_ita_adj_final(int S, const double* __restrict__ tau, const double* __restrict__ fbar0,
+                                const double* __restrict__ vel, const double* __restrict__ taubar, int first,
+                                double* __restrict__ gbar) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double tb = first ? 0.0 : taubar[s];
+    for (int b = 0; b < 3; ++b) tb += fbar0[(long)b * S + s] * vel[3 * s + b];
+    gbar[s] = -tau[s] * tau[s] * tb;
+}
+
+// transport weight of one mode for the transition s -> t (Delta = e_s - e_t),
+// the same expression as the transport matrix uses
+__device__ __forceinline__ double transport_weight(double d, double om, double f0t, double kt, double is, double nrm,
+                                                   double omega_cut) {
+    if (!(om > omega_cut)) return 0.0;
+    const double nb = 1.0 / expm1(om / kt);
+    const double x1 = (d - om) * is, x2 = (d + om) * is;
+    const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+    const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+    return de * (1.0 + nb - f0t) + da * (nb + f0t);
+}
+
+// One thread per (source s in chunk, target t).  W_bar_st = (1/N_q)(sum_h ubar_h(s) F_h(t)
+// + Gamma_bar_s); dL/d|g_nu(s->t)|^2 = 1/2 (2 pi/hbar)(w_nu(s,t) W_bar_st + w_nu(t,s) W_bar_ts)
+// (the table holds the symmetrised G); g_nu(s->t) is recomputed from the FP64
+// Rp contraction exactly as the table epilogue forms it, and the adjoint of
+// |g|^2 -> mode projection -> band rotation gives the Rp-contraction adjoint
+// g'W_bar[x][i] = U(k_t)[i][n_t] sum_nu amp minv_x conj(e_x,nu) 2 c_nu g_nu.
+__global__ void k_pair_adjoint(PairAdjoint e) {
+    const int z = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= e.S) return;
+    const int s = e.s_off + z;
+    const int S = e.S, nw = e.nw, nm = e.nm;
+    double wst = e.gamma_bar[s], wts = e.gamma_bar[t];
+    for (int h = 0; h < e.n_hist; ++h) {
+        wst = fma(e.ubar[(long)h * S + s], e.fhist[(long)h * S + t], wst);
+        wts = fma(e.ubar[(long)h * S + t], e.fhist[(long)h * S + s], wts);
+    }
+    wst /= e.n_q;
+    wts /= e.n_q;
+    const long iq = grid_q(e.kc, s, t, e.n1, e.n2, e.n3);
+    const long iqr = grid_q(e.kc, t, s, e.n1, e.n2, e.n3);
+    const double kt = kBoltzEv * e.temp;
+    const double is = 1.0 / e.sigma, nrm = 1.0 / (sqrt(kPi) * e.sigma);
+    const double f0s = 1.0 / (exp((e.eps[s] - e.mu) / kt) + 1.0);
+    const double f0t = 1.0 / (exp((e.eps[t] - e.mu) / kt) + 1.0);
+    const double d = e.eps[s] - e.eps[t];
+    const double* gp = e.gw + ((long)z * S + t) * nm * nw * 2;
+    const int bt = e.band[t];
+    const double* ut = e.ut + (long)t * nw * nw * 2;
+    cx<double> gh[kMaxModes], gb[kMaxModes];
+    for (int x = 0; x < nm; ++x) {
+        cx<double> a = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(a, ldc(ut, (long)i * nw + bt), ldc(gp, (long)x * nw + i));
+        gh[x] = a;
+        gb[x] = {0, 0};
+    }
+    if (e.lr != nullptr) {
+        const double* us = e.us + (long)s * nw * nw * 2;
+        const int bs = e.band[s];
+        cx<double> ov = {0, 0};
+        for (int i = 0; i < nw; ++i) cjfma(ov, ldc(ut, (long)i * nw + bt), ldc(us, (long)i * nw + bs));
+        for (int x = 0; x < nm; ++x) cfma(gh[x], ldc(e.lr, iq * nm + x), ov);
+    }
+    const double pref = 0.5 * (2.0 * kPi / kHbarEvFs);
+    for (int nu = 0; nu < nm; ++nu) {
+        const double om = e.omega[iq * nm + nu];
+        if (!(om > e.omega_cut_table)) continue;
+        const double c = pref * (transport_weight(d, om, f0t, kt, is, nrm, e.omega_cut) * wst +
+                                 transport_weight(-d, e.omega[iqr * nm + nu], f0s, kt, is, nrm, e.omega_cut) * wts);
+        const double amp = sqrt(kHbar2AmuA2 / (2.0 * om));
+        cx<double> g = {0, 0};
+        for (int x = 0; x < nm; ++x) {
+            cx<double> ev = ldc(e.evec, (iq * nm + x) * nm + nu);
+            ev.x *= e.minv[x];
+            ev.y *= e.minv[x];
+            cfma(g, ev, gh[x]);
+        }
+        // gbar_nu = 2 c g_nu (amp folded in twice: once in g, once in the adjoint)
+        const double sc = 2.0 * c * amp * amp;
+        const cx<double> gbn = {sc * g.x, sc * g.y};
+        for (int x = 0; x < nm; ++x) {
+            cx<double> ev = ldc(e.evec, (iq * nm + x) * nm + nu);
+            ev.x *= e.minv[x];
+            ev.y *= e.minv[x];
+            cjfma(gb[x], ev, gbn);
+        }
+    }
+    double* out = e.gw_bar + ((long)z * S + t) * nm * nw * 2;
+    for (int x = 0; x < nm; ++x)
+        for (int i = 0; i < nw; ++i) {
+            const cx<double> u = ldc(ut, (long)i * nw + bt);
+            out[2 * ((long)x * nw + i)] = u.x * gb[x].x - u.y * gb[x].y;
+            out[2 * ((long)x * nw + i) + 1] = u.x * gb[x].y + u.y * gb[x].x;
+        }
+}
+
+// Adjoint of g'(s)[p][x][i] = sum_j g(s)[p][x][i][j] U(k_s)[j][n_s], with the
+// phase exp(2 pi i k_s . Rp_p) that turns a sum over exp(-2 pi i k_t . Rp) into
+// one over exp(-2 pi i (k_t - k_s) . Rp):
+//   out[z][p][x][i][j] = exp(2 pi i k_s . Rp_p) in[z][p][x][i] conj(U(k_s)[j][n_s])
+__global__ void k_apply_u_column_adj(int nrp, int nm, int nw, int s_off, const double* __restrict__ in,
+                                     const double* __restrict__ ks, const int32_t* __restrict__ rp,
+                                     const double* __restrict__ us, const int32_t* __restrict__ band,
+                                     double* __restrict__ out) {
+    const int z = blockIdx.y;
+    const int s = s_off + z;
+    const long per = (long)nrp * nm * nw * nw;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    const int j = (int)(idx % nw);
+    const long pxi = idx / nw;
+    const int p = (int)(pxi / ((long)nm * nw));
+    double arg = ks[3 * s] * rp[3 * p] + ks[3 * s + 1] * rp[3 * p + 1] + ks[3 * s + 2] * rp[3 * p + 2];
+    arg -= rint(arg);
+    double sn, cs;
+    sincospi(2.0 * arg, &sn, &cs);
+    const cx<double> a = ldc(in, (long)z * nrp * nm * nw + pxi);
+    const cx<double> u = ldc(us, ((long)s * nw + j) * nw + band[s]);
+    // (cs + i sn) a conj(u)
+    const double ar = cs * a.x - sn * a.y, ai = cs * a.y + sn * a.x;
+    out[2 * ((long)z * per + idx)] = ar * u.x + ai * u.y;
+    out[2 * ((long)z * per + idx) + 1] = ai * u.x - ar * u.y;
+}
+
 __global__ void k_axpy_copy(int S, const double* __restrict__ x, double a, const double* __restrict__ y,
                             double* __restrict__ out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -595,6 +779,7 @@ StreamPlan stream_plan(int S, int f32, int na, int nb) {
     else if (na == 2 && nb == 2) slots = stream_slots<T, 2, 2>(); \
     else if (na == 1 && nb == 0) slots = stream_slots<T, 1, 0>(); \
     else if (na == 3 && nb == 0) slots = stream_slots<T, 3, 0>(); \
+    else if (na == 0 && nb == 3) slots = stream_slots<T, 0, 3>(); \
     else throw Error{-1, "stream_plan: unsupported vector counts"};
     if (f32) {
         EPHX_SLOTS(float)
@@ -622,12 +807,14 @@ void stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtr
         else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
         else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
         else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
+        else if (na == 0 && nb == 3) EPHX_STREAM(float, 0, 3);
         else throw Error{-1, "stream_pass: unsupported vector counts"};
     } else {
         if (na == 1 && nb == 1) EPHX_STREAM(double, 1, 1);
         else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
         else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
         else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
+        else if (na == 0 && nb == 3) EPHX_STREAM(double, 0, 3);
         else throw Error{-1, "stream_pass: unsupported vector counts"};
     }
 #undef EPHX_STREAM
@@ -675,6 +862,46 @@ void mobility_reduce(int S, const double* eps, const double* vel, const double* 
                      double* fout, double* mob, hipStream_t st) {
     hipLaunchKernelGGL(k_mobility, dim3(1), dim3(256), 0, st, S, eps, vel, f, mu, temp, fout, mob);
     check_launch("mobility");
+}
+
+void mob_seed(int S, const double* eps, const double* vel, const double* lam, double mu, double temp, double* fbar,
+              hipStream_t st) {
+    hipLaunchKernelGGL(k_mob_seed, dim3(1), dim3(256), 0, st, S, eps, vel, lam, mu, temp, fbar);
+    check_launch("mob_seed");
+}
+
+void ita_adj_step(int S, const double* tau, const double* fbar, const double* fnext, double* taubar, double* ubar,
+                  int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_ita_adj_step, dim3((S + 255) / 256), dim3(256), 0, st, S, tau, fbar, fnext, taubar, ubar,
+                       first);
+    check_launch("ita_adj_step");
+}
+
+void ita_adj_cols(int S, int n_rt, const double* colp, double n_q, double* fbar, hipStream_t st) {
+    hipLaunchKernelGGL(k_ita_adj_cols, dim3((S + 255) / 256), dim3(256), 0, st, S, n_rt, colp, n_q, fbar);
+    check_launch("ita_adj_cols");
+}
+
+void ita_adj_final(int S, const double* tau, const double* fbar0, const double* vel, const double* taubar, int first,
+                   double* gbar, hipStream_t st) {
+    hipLaunchKernelGGL(k_ita_adj_final, dim3((S + 255) / 256), dim3(256), 0, st, S, tau, fbar0, vel, taubar, first,
+                       gbar);
+    check_launch("ita_adj_final");
+}
+
+void pair_adjoint(const PairAdjoint& e, hipStream_t st) {
+    if (e.nm > kMaxModes) throw Error{-6, "pair_adjoint: more modes than supported"};
+    dim3 grid((e.S + 127) / 128, e.ns_chunk);
+    hipLaunchKernelGGL(k_pair_adjoint, grid, dim3(128), 0, st, e);
+    check_launch("pair_adjoint");
+}
+
+void apply_u_column_adj(int Z, int nrp, int nm, int nw, int s_off, const double* in, const double* ks,
+                        const int32_t* rp, const double* us, const int32_t* band, double* out, hipStream_t st) {
+    const long per = (long)nrp * nm * nw * nw;
+    hipLaunchKernelGGL(k_apply_u_column_adj, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw,
+                       s_off, in, ks, rp, us, band, out);
+    check_launch("apply_u_column_adj");
 }
 
 void axpy_copy(int S, const double* x, double a, const double* y, double* out, hipStream_t st) {

@@ -570,6 +570,20 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
 
 namespace ephx {
 
+// Negated real-space vectors -Rp, -Re of g(Re,Rp) as doubles: the row points of
+// the adjoint Fourier sums.  Created on first use and kept with the model.
+void negated_vectors(ephx_model* m) {
+    if (m->d_nrp_g) return;
+    std::vector<int32_t> hv(3 * (m->n_rp_g + m->n_re_g));
+    hip_check(hipMemcpy(hv.data(), m->d_rp_g, 3 * m->n_rp_g * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    hip_check(hipMemcpy(hv.data() + 3 * m->n_rp_g, m->d_re_g, 3 * m->n_re_g * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    std::vector<double> dv(hv.size());
+    for (size_t i = 0; i < hv.size(); ++i) dv[i] = -(double)hv[i];
+    m->d_nrp_g = (double*)dev_upload(dv.data(), dv.size() * 8);
+    m->owned.push_back(m->d_nrp_g);
+    m->d_nre_g = m->d_nrp_g + 3 * m->n_rp_g;
+}
+
 // dL/dg(Re,Rp) for L = sum_nk lam_nk Gamma_nk, FP64.  Recomputes the forward
 // quantities per k batch and q chunk, then
 //   per pair:  g'W_bar = U(k+q) sum_nu conj(e amp) 2c lam w D g        (adjoint epilogue)
@@ -589,18 +603,7 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
         lr = (double*)m->ws.get("adj.lr", (size_t)nq * nm * 16);
         frohlich(nq, q, m->pd, lr, st);
     }
-    // negated real-space vectors as doubles (rows of the adjoint sums)
-    if (!m->d_nrp_g) {
-        std::vector<int32_t> hv(3 * (m->n_rp_g + m->n_re_g));
-        hip_check(hipMemcpy(hv.data(), m->d_rp_g, 3 * m->n_rp_g * 4, hipMemcpyDeviceToHost), "hipMemcpy");
-        hip_check(hipMemcpy(hv.data() + 3 * m->n_rp_g, m->d_re_g, 3 * m->n_re_g * 4, hipMemcpyDeviceToHost),
-                  "hipMemcpy");
-        std::vector<double> dv(hv.size());
-        for (size_t i = 0; i < hv.size(); ++i) dv[i] = -(double)hv[i];
-        m->d_nrp_g = (double*)dev_upload(dv.data(), dv.size() * 8);
-        m->owned.push_back(m->d_nrp_g);
-        m->d_nre_g = m->d_nrp_g + 3 * m->n_rp_g;
-    }
+    negated_vectors(m);
     const int bk = std::min(nk, 16);
     const int qc = (int)std::max(64L, std::min((long)nq, (1L << 17) / bk));
     double* ek = (double*)m->ws.get("adj.ek", (size_t)bk * nw * 8);

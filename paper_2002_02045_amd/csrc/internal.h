@@ -153,6 +153,41 @@ struct PairEpilogue {
     double omega_cut;
     float* g2raw;         // set by the launcher for FP32 tables
 };
+// Adjoint of the table epilogue for the mobility gradient (see bte_kernels.hip).
+struct PairAdjoint {
+    int ns_chunk, s_off, S, nw, nm;
+    const double* gw;         // [ns_chunk][S][nm][nw] complex, FP64 Rp contraction
+    const double* ut;         // [S][nw][nw] complex, U(k) of the states
+    const double* us;         // same array (polar overlap)
+    const int32_t* band;
+    const int32_t* kc;
+    int n1, n2, n3;
+    const double* omega;      // [Ngrid][nm]
+    const double* evec;       // [Ngrid][nm][nm] complex
+    const double* lr;         // [Ngrid][nm] complex or nullptr
+    const double* minv;
+    double omega_cut_table;   // cut of the table's |g|^2
+    int n_hist;               // W_bar_st = (1/N_q)(sum_h ubar[h][s] fhist[h][t] + gamma_bar[s])
+    const double* ubar;
+    const double* fhist;
+    const double* gamma_bar;
+    double n_q;
+    const double* eps;        // transport weights (as in the transport matrix)
+    double temp, mu, sigma, omega_cut;
+    double* gw_bar;           // [ns_chunk][S][nm][nw] complex
+};
+void pair_adjoint(const PairAdjoint& e, hipStream_t st);
+// out[z][p][x][i][j] = exp(2 pi i k_s.Rp_p) in[z][p][x][i] conj(U(k_s)[j][band_s]), s = s_off + z
+void apply_u_column_adj(int Z, int nrp, int nm, int nw, int s_off, const double* in, const double* ks,
+                        const int32_t* rp, const double* us, const int32_t* band, double* out, hipStream_t st);
+// reverse of the ITA (layouts [3][S])
+void mob_seed(int S, const double* eps, const double* vel, const double* lam, double mu, double temp, double* fbar,
+              hipStream_t st);
+void ita_adj_step(int S, const double* tau, const double* fbar, const double* fnext, double* taubar, double* ubar,
+                  int first, hipStream_t st);
+void ita_adj_cols(int S, int n_rt, const double* colp, double n_q, double* fbar, hipStream_t st);
+void ita_adj_final(int S, const double* tau, const double* fbar0, const double* vel, const double* taubar, int first,
+                   double* gbar, hipStream_t st);
 // Leading dimension (elements) of S x S tables: rows start 256-byte aligned.
 long table_ld(int S);
 void pair_epilogue(const PairEpilogue& e, int f32, long ld, void* g2out, hipStream_t st);

@@ -6,6 +6,7 @@ Tolerances: FP64 tables 1e-10 relative to the largest entry / result;
 FP32 tables 1e-5 (|g|^2) and 1e-4 (collision, dynamics); carrier number
 conserved to 1e-12 of sum |I|.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -246,3 +247,59 @@ def test_mobility_parity_real_model(lib):
         assert float((tau.cpu() - tau_o).abs().max() / tau_o.abs().max()) <= 1e-10
         assert float((ff.cpu() - fo).abs().max() / fo.abs().max()) <= 1e-10
         assert float((mob.cpu() - mob_o).abs().max() / mob_o.abs().max()) <= 1e-10
+
+
+def _mobility_adjoint_case(window, sigma, n_iter):
+    m = synth.make_config_model("tiny", real=True)
+    n = (8, 8, 8)
+    eps_g, _ = interp.bands(m, grid.grid_points(n))
+    cbm = float(eps_g[:, m.nw // 2].min())
+    kk, bb = grid.window_states(eps_g.numpy(), m.nw // 2, m.nw, cbm - 0.01, cbm + window)
+    _, _, v = interp.bands(m, bte.state_points(kk, n), velocity=True)
+    vel = v[torch.arange(len(bb)), torch.as_tensor(bb)]
+    kw = dict(mu=cbm - 0.3, temp=300.0, sigma=sigma, n_q=float(np.prod(n)), n_iter=n_iter)
+    return m, n, kk, bb, vel, kw
+
+
+@pytest.mark.parametrize("n_iter", [0, 4])
+def test_mobility_vjp_matches_oracle_gradient(lib, n_iter):
+    # S = 76 states: two chunks of source states
+    m, n, kk, bb, vel, kw = _mobility_adjoint_case(0.9, 0.05, n_iter)
+    _say("mobility adjoint vs oracle gradient, S=%d, n_iter=%d" % (len(kk), n_iter))
+    assert len(kk) > 64
+    lam = np.random.default_rng(60 + n_iter).standard_normal((3, 3))
+    _, g_ref = grad.mobility_grad_g(m, n, kk, bb, vel, lam, **kw)
+    dm = lib.Model(m)
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    par = lib.Params(temp=kw["temp"], mu=kw["mu"], sigma=kw["sigma"], n_q=kw["n_q"])
+    g_bar = t.mobility_vjp(par, vel.numpy(), n_iter, lam).cpu()
+    err = float((g_bar - g_ref).abs().max() / g_ref.abs().max())
+    _say("  max rel err %.2e" % err)
+    assert err <= 1e-10
+    # the autograd.Function routes its backward through the same entry point
+    gt = torch.zeros(dm.g_shape, dtype=torch.complex128, device="cuda", requires_grad=True)
+    mob = lib.MobilityFunction.apply(gt, t, par, vel.numpy(), n_iter)
+    (mob * torch.as_tensor(lam, device=mob.device)).sum().backward()
+    assert torch.equal(gt.grad.cpu(), g_bar)
+
+
+def test_mobility_vjp_directional_finite_difference(lib):
+    m, n, kk, bb, vel, kw = _mobility_adjoint_case(0.9, 0.05, 3)
+    _say("mobility adjoint vs GPU central difference, S=%d" % len(kk))
+    lam = np.random.default_rng(70).standard_normal((3, 3))
+    par = lib.Params(temp=kw["temp"], mu=kw["mu"], sigma=kw["sigma"], n_q=kw["n_q"])
+    t = lib.PairTable(lib.Model(m), n, kk, bb, precision="fp64")
+    g_bar = t.mobility_vjp(par, vel.numpy(), 3, lam).cpu()
+    rng = np.random.default_rng(71)
+    d = rng.standard_normal(m.g.shape) + 1j * rng.standard_normal(m.g.shape)
+    h = 1e-5
+    vals = []
+    for sgn in (1.0, -1.0):
+        mm = dataclasses.replace(m, g=m.g + sgn * h * d)
+        tt = lib.PairTable(lib.Model(mm), n, kk, bb, precision="fp64")
+        _, _, mob = tt.mobility(par, vel.numpy(), 3)
+        vals.append(float((mob.cpu() * torch.as_tensor(lam)).sum()))
+    fd = (vals[0] - vals[1]) / (2 * h)
+    ad = float((g_bar.conj() * torch.as_tensor(d)).real.sum())
+    _say("  fd %.10e adjoint %.10e" % (fd, ad))
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
