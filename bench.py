@@ -108,7 +108,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         px.timer_enable(False)
-        stages = {s: px.timer_get(s) for s in ("rp_contraction", "hkq_fourier", "eig_hkq", "epilogue",
+        stages = {s: px.timer_get(s) for s in ("rp_contraction", "rp_phases", "hkq_fourier", "eig_hkq", "epilogue",
                                                 "re_contraction", "phonons")}
         px.timer_reset()
         pairs = steps * kb * args.nq

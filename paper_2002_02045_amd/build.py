@@ -10,7 +10,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libephx.so")
-SOURCES = ["phase_gemm.hip", "eig.hip", "eph_kernels.hip", "ephx_api.hip", "bte_kernels.hip", "bte_api.hip"]
+SOURCES = ["phase_gemm.hip", "eig.hip", "eph_kernels.hip", "eph_wide.hip", "ephx_api.hip", "bte_kernels.hip",
+           "bte_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions in device code

@@ -93,4 +93,6 @@ void bands_impl(ephx_model* m, int nk, const double* k, double* eps, double* u, 
 void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double* evec, hipStream_t st,
                   const std::string& tag);
 void negated_vectors(ephx_model* m);
+// models beyond the per-pair register kernels (batched-GEMM path only)
+inline bool is_wide(const ephx_model* m) { return m->nw > kMaxNw || m->nm > kMaxModes; }
 }  // namespace ephx

@@ -216,6 +216,160 @@ __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restri
     }
 }
 
+// Larger matrices (8 < n <= 128, e.g. H(k) of a 64-function model, D(q) of a
+// 40-atom cell): one 256-thread workgroup per matrix, the same rotations and
+// convergence test, with the n/2 disjoint rotations of a round (circle-method
+// ordering) applied by all threads at once.  A (overwritten) and V (the
+// eigenvector output) live in global memory, which the workgroup's own L1/L2
+// serve; the rotation parameters of a round go through LDS.
+constexpr int kWgMax = 128;
+
+__device__ __forceinline__ int circle_index(int pos, int r, int ne) {
+    return pos == 0 ? 0 : (pos - 1 + r) % (ne - 1) + 1;
+}
+
+__global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, long strideA, double* __restrict__ evals,
+                                                double* __restrict__ evecs) {
+    __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
+    __shared__ double rc[kWgMax / 2], rsr[kWgMax / 2], rsi[kWgMax / 2];
+    __shared__ double red[2][256];
+    __shared__ double dg[kWgMax];
+    __shared__ int rk[kWgMax];
+    const int tid = threadIdx.x;
+    const long mi = blockIdx.x;
+    double* a = A + mi * strideA * 2;
+    double* v = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
+    const int nn = n * n;
+    // Hermitian part 0.5 (A + A^dag), V = I
+    for (int e = tid; e < nn; e += 256) {
+        const int i = e / n, j = e % n;
+        if (i < j) {
+            const double xr = 0.5 * (a[2 * e] + a[2 * (j * n + i)]);
+            const double xi = 0.5 * (a[2 * e + 1] - a[2 * (j * n + i) + 1]);
+            a[2 * e] = xr;
+            a[2 * e + 1] = xi;
+            a[2 * (j * n + i)] = xr;
+            a[2 * (j * n + i) + 1] = -xi;
+        } else if (i == j) {
+            a[2 * e + 1] = 0.0;
+        }
+        if (v) {
+            v[2 * e] = i == j ? 1.0 : 0.0;
+            v[2 * e + 1] = 0.0;
+        }
+    }
+    __syncthreads();
+    const int ne = n + (n & 1), np = ne / 2;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < nn; e += 256) {
+            const double m2 = a[2 * e] * a[2 * e] + a[2 * e + 1] * a[2 * e + 1];
+            tot += m2;
+            off += (e / n != e % n) ? m2 : 0.0;
+        }
+        red[0][tid] = off;
+        red[1][tid] = tot;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (tid < w) {
+                red[0][tid] += red[0][tid + w];
+                red[1][tid] += red[1][tid + w];
+            }
+            __syncthreads();
+        }
+        const bool done = !(red[0][0] > 1e-30 * red[1][0]);
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < ne - 1; ++r) {
+            if (tid < np) {
+                const int i1 = circle_index(tid, r, ne), i2 = circle_index(ne - 1 - tid, r, ne);
+                const int p = i1 < i2 ? i1 : i2, q = i1 < i2 ? i2 : i1;
+                double c = 1.0, sr = 0.0, si = 0.0;
+                if (q < n) {
+                    const double apr = a[2 * (p * n + q)], api = a[2 * (p * n + q) + 1];
+                    const double mag = sqrt(apr * apr + api * api);
+                    if (mag > 0.0) {
+                        const double th = (a[2 * (q * n + q)] - a[2 * (p * n + p)]) / (2.0 * mag);
+                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        const double s = t * c;
+                        sr = s * apr / mag;
+                        si = s * api / mag;
+                    }
+                }
+                pp[tid] = p;
+                qq[tid] = q < n ? q : p;   // a dummy partner never rotates
+                rc[tid] = c;
+                rsr[tid] = sr;
+                rsi[tid] = si;
+            }
+            __syncthreads();
+            // columns: (AJ)_{.p} = c A_.p - conj(se) A_.q ; (AJ)_{.q} = se A_.p + c A_.q ; V likewise
+            for (int e = tid; e < np * n; e += 256) {
+                const int k = e / n, i = e % n;
+                const int p = pp[k], q = qq[k];
+                if (p == q) continue;
+                const double c = rc[k], sr = rsr[k], si = rsi[k];
+                double* x = a + 2 * (i * n + p);
+                double* y = a + 2 * (i * n + q);
+                const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
+                x[0] = c * xr - (sr * yr + si * yi);
+                x[1] = c * xi - (sr * yi - si * yr);
+                y[0] = (sr * xr - si * xi) + c * yr;
+                y[1] = (sr * xi + si * xr) + c * yi;
+                if (v) {
+                    double* u = v + 2 * (i * n + p);
+                    double* w = v + 2 * (i * n + q);
+                    const double ur = u[0], ui = u[1], wr = w[0], wi = w[1];
+                    u[0] = c * ur - (sr * wr + si * wi);
+                    u[1] = c * ui - (sr * wi - si * wr);
+                    w[0] = (sr * ur - si * ui) + c * wr;
+                    w[1] = (sr * ui + si * ur) + c * wi;
+                }
+            }
+            __syncthreads();
+            // rows: (J^dag A)_{p.} = c A_p. - se A_q. ; (J^dag A)_{q.} = conj(se) A_p. + c A_q.
+            for (int e = tid; e < np * n; e += 256) {
+                const int k = e / n, j = e % n;
+                const int p = pp[k], q = qq[k];
+                if (p == q) continue;
+                const double c = rc[k], sr = rsr[k], si = rsi[k];
+                double* x = a + 2 * (p * n + j);
+                double* y = a + 2 * (q * n + j);
+                const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
+                x[0] = c * xr - (sr * yr - si * yi);
+                x[1] = c * xi - (sr * yi + si * yr);
+                y[0] = (sr * xr + si * xi) + c * yr;
+                y[1] = (sr * xi - si * xr) + c * yi;
+            }
+            __syncthreads();
+        }
+    }
+    // sort ascending, ties by index
+    for (int i = tid; i < n; i += 256) dg[i] = a[2 * (i * n + i)];
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+        int r = 0;
+        for (int m = 0; m < n; ++m) r += (dg[m] < dg[i] || (dg[m] == dg[i] && m < i)) ? 1 : 0;
+        rk[i] = r;
+        evals[mi * n + r] = dg[i];
+    }
+    __syncthreads();
+    if (v) {
+        // permute the columns of V through A's storage
+        for (int e = tid; e < nn; e += 256) {
+            a[2 * e] = v[2 * e];
+            a[2 * e + 1] = v[2 * e + 1];
+        }
+        __syncthreads();
+        for (int e = tid; e < nn; e += 256) {
+            const int i = e / n, c = e % n;
+            v[2 * (i * n + rk[c])] = a[2 * e];
+            v[2 * (i * n + rk[c]) + 1] = a[2 * e + 1];
+        }
+    }
+}
+
 __global__ void k_phonon_omega(long count, double* lam) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
@@ -246,10 +400,16 @@ void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, dou
 
 }  // namespace
 
-void eig_herm(int batch, int n, const void* A, int a_f32, long strideA, double* evals, double* evecs,
-              hipStream_t st) {
+void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals, double* evecs, hipStream_t st) {
     if (batch <= 0) return;
-    if (n < 1 || n > kEigMax) throw Error{-6, "eig_herm: matrix order above 8 is not supported in this build"};
+    if (n < 1 || n > kWgMax) throw Error{-6, "eig_herm: matrix order above 128 is not supported"};
+    if (n > kEigMax) {
+        if (a_f32) throw Error{-1, "eig_herm: matrices above order 8 must be FP64"};
+        hipLaunchKernelGGL(k_eig_wg, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals, evecs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
+        return;
+    }
     if (a_f32)
         launch_eig(batch, n, (const float*)A, strideA, evals, evecs, st);
     else

@@ -1,0 +1,306 @@
+// Per-pair work of the e-ph matrix elements for large models (Nw > 16 or more
+// than 12 modes, e.g. a 40-atom cell with 64 Wannier functions), where one
+// pair's block Nw x Nw x 3nat no longer fits a workgroup's registers and LDS.
+// The rotation and the mode projection (Eq. eph_mat with g^H of Eq.
+// eph_mat_wann2) are then batched complex GEMMs on MFMA:
+//
+//   rotation    g^H[pair][x] = U(k+q)^dag g'^W[pair][x]        (Nw x Nw x Nw per x)
+//   long range  g^H[pair][x] += C_x(q) U(k+q)^dag U(k)          (polar models)
+//   projection  g[pair]      = P(q) g^H[pair],  P_nu,x = sqrt(hbar/2 w_nu) e_x,nu / sqrt(M_x)
+//
+// where g'^W already carries U(k) on the right (applied once per k).  The
+// rates reduction (Eqs. scatter_rate, BTE_W) and the |g|^2 output then read g.
+#include "internal.h"
+
+namespace ephx {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+inline void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+__device__ __forceinline__ dbl4 mfma(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    typedef dbl4 type;
+    // accumulator element v of lane l is C[l/16 + 4v][l%16] for the f64 instruction
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Acc<float> {
+    typedef flt4 type;
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int kT = 64;    // output tile (rows and columns)
+constexpr int kKs = 16;   // K per staging step
+
+// Batched complex GEMM, C[b] = op(A[b]) B[b], row-major, interleaved complex.
+// op(A)(m,k) = A[m*lda + k], or conj(A[k*lda + m]) when CA.  The batch index is
+// b = (b0 * n1 + b1), offsets b0*s?0 + b1*s?1 (complex elements).  256 threads
+// own a 64 x 64 tile: wave w the rows 16w..16w+15, four 16-column MFMA blocks.
+template <typename T, typename TA, typename TB, bool CA>
+__global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int ntl, CBatch bt, const TA* __restrict__ A,
+                                               long lda, const TB* __restrict__ B, long ldb, T* __restrict__ C,
+                                               long ldc) {
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T as[kKs][kT][2];   // [k][m]
+    __shared__ T bs[kKs][kT][2];   // [k][n]
+    long bid = blockIdx.x;
+    const int nti = (int)(bid % ntl);
+    bid /= ntl;
+    const int mti = (int)(bid % mt);
+    bid /= mt;
+    const long b1 = bid % bt.n1, b0 = bid / bt.n1;
+    A += 2 * (b0 * bt.sa0 + b1 * bt.sa1);
+    B += 2 * (b0 * bt.sb0 + b1 * bt.sb1);
+    C += 2 * (b0 * bt.sc0 + b1 * bt.sc1);
+    const int row0 = mti * kT, col0 = nti * kT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    acc_t are[4], aim[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        are[cb] = acc_t{0, 0, 0, 0};
+        aim[cb] = acc_t{0, 0, 0, 0};
+    }
+    for (int kc = 0; kc < K; kc += kKs) {
+        for (int e = tid; e < kKs * kT; e += 256) {
+            // A: for CA the stored matrix is read along m (contiguous), else along k
+            int kk, m;
+            if (CA) {
+                kk = e / kT;
+                m = e % kT;
+            } else {
+                m = e / kKs;
+                kk = e % kKs;
+            }
+            T re = 0, im = 0;
+            if (kc + kk < K && row0 + m < M) {
+                if (CA) {
+                    const long o = (long)(kc + kk) * lda + row0 + m;
+                    re = (T)A[2 * o];
+                    im = -(T)A[2 * o + 1];
+                } else {
+                    const long o = (long)(row0 + m) * lda + kc + kk;
+                    re = (T)A[2 * o];
+                    im = (T)A[2 * o + 1];
+                }
+            }
+            as[kk][m][0] = re;
+            as[kk][m][1] = im;
+            const int kb = e / kT, n = e % kT;
+            T br = 0, bi = 0;
+            if (kc + kb < K && col0 + n < N) {
+                const long o = (long)(kc + kb) * ldb + col0 + n;
+                br = (T)B[2 * o];
+                bi = (T)B[2 * o + 1];
+            }
+            bs[kb][n][0] = br;
+            bs[kb][n][1] = bi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kKs / 4; ++s) {
+            const int kk = 4 * s + lk;
+            const T ar = as[kk][wave * 16 + li][0], ai = as[kk][wave * 16 + li][1];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const T br = bs[kk][cb * 16 + li][0], bi = bs[kk][cb * 16 + li][1];
+                are[cb] = mfma(ar, br, are[cb]);
+                are[cb] = mfma(-ai, bi, are[cb]);
+                aim[cb] = mfma(ar, bi, aim[cb]);
+                aim[cb] = mfma(ai, br, aim[cb]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int col = col0 + cb * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + wave * 16 + Acc<T>::row(lk, v);
+            if (row < M && col < N) {
+                const long o = (long)row * ldc + col;
+                C[2 * o] = are[cb][v];
+                C[2 * o + 1] = aim[cb][v];
+            }
+        }
+    }
+}
+
+template <typename T, typename TA, typename TB, bool CA>
+void launch_cgemm(int M, int N, int K, long nbatch, const CBatch& bt, const TA* A, long lda, const TB* B, long ldb,
+                  T* C, long ldc, hipStream_t st) {
+    const int mt = (M + kT - 1) / kT, ntl = (N + kT - 1) / kT;
+    const long blocks = nbatch * mt * ntl;
+    if (blocks <= 0) return;
+    if (blocks > 0x7fffffffL) throw Error{-1, "cgemm: grid too large"};
+    hipLaunchKernelGGL((k_cgemm<T, TA, TB, CA>), dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, mt, ntl, bt, A,
+                       lda, B, ldb, C, ldc);
+    check_launch("cgemm");
+}
+
+// P[q][nu][x] = sqrt(hbar^2/(2 M_x omega_nu)) e_x,nu(q) (zero for omega <= cut)
+__global__ void k_proj_matrix(int nq, int q_off, int nm, const double* __restrict__ omega, const double* __restrict__ evec,
+                              const double* __restrict__ minv, double omega_cut, double* __restrict__ P) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = (long)nm * nm;
+    if (t >= nq * per) return;
+    const long q = t / per;
+    const int nu = (int)((t % per) / nm), x = (int)(t % nm);
+    const long qg = q_off + q;
+    const double om = omega[qg * nm + nu];
+    const double amp = om > omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * minv[x] : 0.0;
+    P[2 * t] = amp * evec[2 * ((qg * nm + x) * nm + nu)];
+    P[2 * t + 1] = amp * evec[2 * ((qg * nm + x) * nm + nu) + 1];
+}
+
+// gh[pair][x][m][n] += C_x(q) ov[pair][m][n]
+template <typename T>
+__global__ void k_polar_add(long npair, int nq, int q_off, int nm, int nw2, const double* __restrict__ lr,
+                            const double* __restrict__ ov, T* __restrict__ gh) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = (long)nm * nw2;
+    if (t >= npair * per) return;
+    const long pair = t / per;
+    const int x = (int)((t % per) / nw2), mn = (int)(t % nw2);
+    const long qg = q_off + pair % nq;
+    const double cr = lr[2 * (qg * nm + x)], ci = lr[2 * (qg * nm + x) + 1];
+    const double orr = ov[2 * (pair * nw2 + mn)], oi = ov[2 * (pair * nw2 + mn) + 1];
+    gh[2 * t] += (T)(cr * orr - ci * oi);
+    gh[2 * t + 1] += (T)(cr * oi + ci * orr);
+}
+
+// |g|^2 into the [nk][nq_total][nm][nw][nw] output
+template <typename T>
+__global__ void k_wide_g2(WideChunk w) {
+    const long per = (long)w.nm * w.nw * w.nw;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)w.nkb * w.nq * per) return;
+    const long pair = t / per, el = t % per;
+    const int z = (int)(pair / w.nq), q = (int)(pair % w.nq);
+    const T* g = reinterpret_cast<const T*>(w.g);
+    const T gr = g[2 * t], gi = g[2 * t + 1];
+    const long off = ((long)(w.k_off + z) * w.nq_total + w.q_off + q) * per + el;
+    reinterpret_cast<T*>(w.g2)[off] = gr * gr + gi * gi;
+}
+
+// partial[z][blk][n][nu] = (2 pi/hbar) x sum over the block's q and all m of
+//   w_q |g_mn,nu|^2 [delta(e_n - hw - e_m)(1 + N - f_m) + delta(e_n + hw - e_m)(N + f_m)]
+template <typename T>
+__global__ __launch_bounds__(256) void k_wide_rates(WideChunk w) {
+    const int z = blockIdx.y, blk = blockIdx.x;
+    const int nw = w.nw, nm = w.nm;
+    const int q0 = blk * w.qpb, q1 = min(w.nq, q0 + w.qpb);
+    const double kt = kBoltzEv * w.temp;
+    const double is = 1.0 / w.sigma, nrm = 1.0 / (sqrt(kPi) * w.sigma);
+    const T* g = reinterpret_cast<const T*>(w.g);
+    for (int o = threadIdx.x; o < nm * nw; o += blockDim.x) {
+        const int nu = o / nw, n = o % nw;
+        const double en = w.ek[(long)z * nw + n];
+        double acc = 0.0;
+        for (int q = q0; q < q1; ++q) {
+            const long qg = (long)w.q_off + q;
+            const double om = w.omega[qg * nm + nu];
+            if (!(om > w.omega_cut)) continue;
+            const double nb = 1.0 / expm1(om / kt);
+            const double wq = w.qw ? w.qw[qg] : w.uniform_w;
+            const long pair = (long)z * w.nq + q;
+            const T* gp = g + 2 * ((pair * nm + nu) * nw) * nw;
+            double s = 0.0;
+            for (int m = 0; m < nw; ++m) {
+                const double em = w.ekq[pair * nw + m];
+                const double fm = 1.0 / (exp((em - w.mu) / kt) + 1.0);
+                const double gr = (double)gp[2 * (m * nw + n)], gi = (double)gp[2 * (m * nw + n) + 1];
+                const double x1 = (en - om - em) * is, x2 = (en + om - em) * is;
+                const double d_em = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+                const double d_ab = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+                s += (gr * gr + gi * gi) * (d_em * (1.0 + nb - fm) + d_ab * (nb + fm));
+            }
+            acc += wq * s;
+        }
+        w.partial[(((long)z * w.nblk + blk) * nw + n) * nm + nu] = acc * (2.0 * kPi / kHbarEvFs);
+    }
+}
+
+template <typename T>
+void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
+    const int nw = w.nw, nm = w.nm, nw2 = nw * nw;
+    const long npair = (long)w.nkb * w.nq;
+    T* gw = reinterpret_cast<T*>(w.g);
+    T* gh = reinterpret_cast<T*>(w.gh);
+    // rotation: batch (pair, x), A = U(k+q)^dag
+    {
+        CBatch b{};
+        b.n1 = nm;
+        b.sa0 = nw2;
+        b.sa1 = 0;
+        b.sb0 = (long)nm * nw2;
+        b.sb1 = nw2;
+        b.sc0 = (long)nm * nw2;
+        b.sc1 = nw2;
+        launch_cgemm<T, double, T, true>(nw, nw, nw, npair * nm, b, w.ukq, nw, gw, nw, gh, nw, st);
+    }
+    if (w.lr != nullptr) {
+        // ov = U(k+q)^dag U(k): batch (z, q)
+        CBatch b{};
+        b.n1 = w.nq;
+        b.sa0 = (long)w.nq * nw2;
+        b.sa1 = nw2;
+        b.sb0 = nw2;
+        b.sb1 = 0;
+        b.sc0 = (long)w.nq * nw2;
+        b.sc1 = nw2;
+        launch_cgemm<double, double, double, true>(nw, nw, nw, npair, b, w.ukq, nw, w.uk, nw, w.ov, nw, st);
+        const long tot = npair * nm * nw2;
+        hipLaunchKernelGGL(k_polar_add<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, npair, w.nq, w.q_off,
+                           nm, nw2, w.lr, w.ov, gh);
+        check_launch("polar_add");
+    }
+    // projection: batch (z, q), A = P(q), result over g'^W's storage
+    {
+        const long tot = (long)w.nq * nm * nm;
+        hipLaunchKernelGGL(k_proj_matrix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.nq, w.q_off, nm,
+                           w.omega, w.evec, w.minv, w.omega_cut, w.pmat);
+        check_launch("proj_matrix");
+        CBatch b{};
+        b.n1 = w.nq;
+        b.sa0 = 0;
+        b.sa1 = (long)nm * nm;
+        b.sb0 = (long)w.nq * nm * nw2;
+        b.sb1 = (long)nm * nw2;
+        b.sc0 = b.sb0;
+        b.sc1 = b.sb1;
+        launch_cgemm<T, double, T, false>(nm, nw2, nm, npair, b, w.pmat, nm, gh, nw2, gw, nw2, st);
+    }
+    if (rates) {
+        hipLaunchKernelGGL(k_wide_rates<T>, dim3(w.nblk, w.nkb), dim3(256), 0, st, w);
+        check_launch("wide_rates");
+    } else {
+        const long tot = npair * nm * nw2;
+        hipLaunchKernelGGL(k_wide_g2<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w);
+        check_launch("wide_g2");
+    }
+}
+
+}  // namespace
+
+void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st) {
+    if (w.nkb <= 0 || w.nq <= 0) return;
+    if (f32)
+        wide_chunk<float>(w, rates, st);
+    else
+        wide_chunk<double>(w, rates, st);
+}
+
+}  // namespace ephx

@@ -151,8 +151,8 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
     return guarded([&] {
         require(d != nullptr && out != nullptr, "model_create: null argument");
         *out = nullptr;
-        require(d->natoms >= 1 && 3 * d->natoms <= kMaxModes, "model_create: need 1 <= natoms <= 4");
-        require(d->nw >= 1 && d->nw <= kMaxNw, "model_create: need 1 <= nw <= 16");
+        require(d->natoms >= 1 && 3 * d->natoms <= kMaxModesWide, "model_create: need 1 <= natoms <= 42");
+        require(d->nw >= 1 && d->nw <= kMaxNwWide, "model_create: need 1 <= nw <= 64");
         require(d->n_re >= 1 && d->n_rp_ph >= 1 && d->n_re_g >= 1 && d->n_rp_g >= 1, "model_create: empty vector set");
         require(d->tau && d->mass && d->re && d->h && d->rp_ph && d->ifc && d->re_g && d->rp_g && d->g,
                 "model_create: null array");
@@ -454,9 +454,14 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     }
     // batch sizes: Bk k points x Qc q points per inner step
     const int bk = std::max(1, std::min(nk, std::max(1, (int)(((size_t)3 << 30) / (nre_cols * 16 * 2)))));
-    const int bk_eff = std::min(bk, 16);
-    const long pairs_target = 1L << 19;
-    const int qc = (int)std::max(64L, std::min((long)nq, pairs_target / bk_eff));
+    // large models: the per-pair blocks (nm nw^2 complex, twice) set the chunk size
+    const bool wide = nw > kMaxNw || nm > kMaxModes;
+    const long pair_bytes = ngcol * (f32 ? 8 : 16) * 2 + (long)nw2 * 48;
+    const long wide_pairs = std::max(16L, (6L << 30) / pair_bytes);
+    int bk_eff = std::min(bk, 16);
+    if (wide) bk_eff = std::max(1, std::min<int>(bk_eff, (int)(wide_pairs / 16)));
+    const long pairs_target = wide ? wide_pairs : 1L << 19;
+    const int qc = (int)std::max(wide ? 1L : 64L, std::min((long)nq, pairs_target / bk_eff));
     const int kp = ((m->n_rp_g + 31) / 32) * 32;
 
     double* ek = (double*)m->ws.get("drv.ek", (size_t)bk_eff * nw * 8);
@@ -477,6 +482,9 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
     double* ukq = (double*)m->ws.get("drv.ukq", npair * nw2 * 16);
     void* gw = m->ws.get("drv.gw", npair * ngcol * (f32 ? 8 : 16));
+    void* gh = wide ? m->ws.get("drv.gh", npair * ngcol * (f32 ? 8 : 16)) : nullptr;
+    double* pmat = wide ? (double*)m->ws.get("drv.pmat", (size_t)qc * nm * nm * 16) : nullptr;
+    double* ovb = wide && m->polar ? (double*)m->ws.get("drv.ov", npair * nw2 * 16) : nullptr;
     const int nblk = eph_epilogue_blocks(qc);
     double* partial = nullptr;
     double* acc = nullptr;
@@ -512,6 +520,11 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
                 StageTimer t("eig_hkq", st);
                 eig_herm(nb * nqc, nw, hkq, 0, nw2, ekq, ukq, st);
             }
+            // phases of the q chunk for the split-bf16 paths, shared by every k of the batch
+            if (nsplit) {
+                StageTimer tph("rp_phases", st);
+                phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
+            }
             // Rp contraction per k
             StageTimer trp("rp_contraction", st);
             if (precision == EPHX_FP64)
@@ -521,13 +534,48 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
                 phase_gemm_f32(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp32, nre_cols, (float*)gw,
                                (long)nqc * ngcol, st);
             else {
-                // phases of the q chunk, shared by every k of the batch
-                phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
                 gemm_bf16_planes(nsplit, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp, (float*)gw,
                                  (long)nqc * ngcol, st);
             }
             trp.stop();
             StageTimer tep("epilogue", st);
+            if (wide) {
+                WideChunk w{};
+                w.nkb = nb;
+                w.nq = nqc;
+                w.q_off = q0;
+                w.nw = nw;
+                w.nm = nm;
+                w.g = gw;
+                w.gh = gh;
+                w.pmat = pmat;
+                w.ov = ovb;
+                w.ukq = ukq;
+                w.ekq = ekq;
+                w.ek = ek;
+                w.uk = uk;
+                w.omega = om;
+                w.evec = ev;
+                w.lr = lr;
+                w.minv = m->d_minv;
+                w.omega_cut = omega_cut;
+                w.g2 = g2;
+                w.nq_total = nq;
+                w.k_off = k0;
+                if (gamma) {
+                    w.temp = p->temp;
+                    w.mu = p->mu;
+                    w.sigma = p->sigma;
+                    w.qw = qw;
+                    w.uniform_w = 1.0 / nq;
+                    w.partial = partial;
+                    w.nblk = eph_epilogue_blocks(nqc);
+                    w.qpb = (nqc + w.nblk - 1) / w.nblk;
+                }
+                eph_wide_chunk(w, f32 ? 1 : 0, gamma ? 1 : 0, st);
+                if (gamma) rates_reduce(nb, w.nblk, nw, nm, partial, acc, st);
+                continue;
+            }
             EphEpilogue e{};
             e.nkb = nb;
             e.nq = nqc;
@@ -677,6 +725,8 @@ extern "C" int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const
         require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
                 "rates_vjp: need temp > 0, sigma > 0, finite mu and omega_cut");
         require(g_bar != nullptr, "rates_vjp: null output");
+        if (is_wide(m))
+            throw Error{EPHX_EUNSUPPORTED, "rates_vjp: not built for models with nw > 16 or more than 12 modes"};
         hipStream_t st = (hipStream_t)stream;
         if (nk == 0 || nq == 0) {
             hip_check(hipMemsetAsync(g_bar, 0, (size_t)m->n_re_g * m->n_rp_g * m->nm * m->nw * m->nw * 16, st),
@@ -695,6 +745,7 @@ extern "C" int ephx_bands(ephx_model* m, int nk, const double* k_red, double* ep
         require(nk >= 0, "bands: nk < 0");
         if (nk == 0) return;
         require(k_red && eps, "bands: null array");
+        if (vel && m->nw > kMaxNw) throw Error{EPHX_EUNSUPPORTED, "bands: velocities not built for nw > 16"};
         bands_impl(m, nk, k_red, eps, u, vel, (hipStream_t)stream, "bands");
     });
 }

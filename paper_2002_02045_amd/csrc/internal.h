@@ -20,6 +20,8 @@ constexpr double kDegTol = 1e-4;                        // degenerate-group thre
 constexpr int kMaxNw = 16;      // Wannier functions handled by the per-pair kernels
 constexpr int kMaxModes = 12;   // 3*natoms handled by the per-pair kernels
 constexpr int kEigMax = 8;      // largest matrix of the wavefront Jacobi eigensolver
+constexpr int kMaxNwWide = 64;  // Wannier functions of the batched-GEMM path
+constexpr int kMaxModesWide = 126;   // 3*natoms of the batched-GEMM path (eigensolver n <= 128)
 
 // Thrown inside the host code, converted to an error code at the ABI edge.
 struct Error {
@@ -61,12 +63,12 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
 void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
                     hipStream_t st);
 
-// Hermitian eigensolver, one wavefront per n x n matrix (n <= kEigMax), FP64.
-// A: [batch] matrices of n*n complex (stride strideA complex elements),
-// float (a_f32 = 1) or double.  evals [batch][n] ascending; evecs [batch][n][n]
-// complex double (column j = eigenvector j) or nullptr.
-void eig_herm(int batch, int n, const void* A, int a_f32, long strideA, double* evals,
-              double* evecs, hipStream_t st);
+// Hermitian eigensolver in FP64: n <= kEigMax by wavefronts (64/n-ish matrices
+// each), 8 < n <= 128 by one workgroup per matrix.  A: [batch] matrices of n*n
+// complex (stride strideA complex elements), float (a_f32 = 1, n <= 8 only) or
+// double; for n > 8 A is overwritten.  evals [batch][n] ascending; evecs
+// [batch][n][n] complex double (column j = eigenvector j) or nullptr.
+void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals, double* evecs, hipStream_t st);
 
 // omega_nu = sign(lam) sqrt(|hbar^2/amu/A^2 * lam|) in place.
 void phonon_omega(long count, double* lam, hipStream_t st);
@@ -118,6 +120,38 @@ void rates_reduce(int nkb, int nblk, int nw, int nm, const double* partial, doub
                   hipStream_t st);
 void rates_finish(int nkb, int nw, int nm, const double* acc, double* gamma, double* gamma_mode,
                   hipStream_t st);
+
+// Large models (nw > kMaxNw or 3nat > kMaxModes): per-pair rotation and mode
+// projection as batched complex GEMMs on MFMA (eph_wide.hip).
+struct CBatch {                 // batch index b = b0 * n1 + b1; offsets in complex elements
+    long n1;
+    long sa0, sa1, sb0, sb1, sc0, sc1;
+};
+struct WideChunk {
+    int nkb, nq, q_off, nw, nm;
+    void* g;              // [nkb][nq][nm][nw][nw] Rp contraction (U(k) applied), overwritten by g_mn,nu
+    void* gh;             // same size, work
+    double* pmat;         // [nq][nm][nm] complex, work
+    double* ov;           // [nkb][nq][nw][nw] complex, work (polar) or nullptr
+    const double* ukq;    // [nkb][nq][nw][nw]
+    const double* ekq;    // [nkb][nq][nw]
+    const double* ek;     // [nkb][nw]
+    const double* uk;     // [nkb][nw][nw]
+    const double* omega;  // [nq_total][nm]
+    const double* evec;   // [nq_total][nm][nm]
+    const double* lr;     // [nq_total][nm] or nullptr
+    const double* minv;
+    double omega_cut;
+    void* g2;             // |g|^2 output [nk_total][nq_total][nm][nw][nw]
+    long nq_total;
+    int k_off;
+    double temp, mu, sigma;
+    const double* qw;
+    double uniform_w;
+    double* partial;      // [nkb][nblk][nw][nm]
+    int nblk, qpb;
+};
+void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st);
 
 // Froehlich term: lr[q][3*kappa+a] (complex double) for q in [nq][3].
 struct PolarDev {

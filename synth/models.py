@@ -239,6 +239,26 @@ def random_points(seed: int, n: int) -> np.ndarray:
     return np.random.default_rng(seed).random((n, 3))
 
 
+def random_positions(seed: int, nat: int, a: float, min_sep: float) -> np.ndarray:
+    """nat atoms at uniform random positions in a simple-cubic cell of side a,
+    drawn one at a time and redrawn while closer than min_sep (minimum image) to
+    an earlier atom."""
+    rng = np.random.default_rng(seed)
+    pos = []
+    while len(pos) < nat:
+        x = rng.random(3) * a
+        ok = True
+        for y in pos:
+            d = x - y
+            d -= a * np.round(d / a)
+            if np.linalg.norm(d) < min_sep:
+                ok = False
+                break
+        if ok:
+            pos.append(x)
+    return np.array(pos)
+
+
 SEED_BASE = 20020205
 
 # Workload definitions.  Physical parameters follow the readings listed in the
@@ -263,6 +283,21 @@ CONFIGS = {
         real=True, zstar=2.1, eps_inf=10.9, k_grid=100, window=0.2, T=300.0, sigma=0.005,
         n_c=1e17, omega_cut=1e-4,
     ),
+    # just past the per-pair register kernels (nw > 16, 3nat > 12): the
+    # batched-GEMM path at a size the oracle handles
+    "wide": dict(
+        lattice="sc", a=6.0, nat=5, masses=(12.0, 14.0, 16.0, 28.0), nw=20, n_grid=3,
+        a_h=0.05, nn_hop=0.12, a_g=0.3, s_k=0.3, seed=SEED_BASE + 4, positions="random", min_sep=1.8,
+        T=300.0, sigma=0.02, mu=0.0, omega_cut=1e-4,
+    ),
+    # large cell: 40 atoms (120 modes), 64 Wannier functions on a simple-cubic
+    # 10 Angstrom cell; the real-space sets default to the 3^3 supercell (the
+    # 6^3 set's g(Re,Rp) alone is 183 GB in complex64)
+    "cell": dict(
+        lattice="sc", a=10.0, nat=40, masses=(12.0, 14.0, 16.0, 28.0), nw=64, n_grid=3,
+        a_h=0.015, nn_hop=0.1, a_g=0.05, s_k=0.1, seed=SEED_BASE + 5, positions="random", min_sep=1.8,
+        nk=2000, nq=200_000, window=0.3, T=300.0, sigma=0.005, mu=0.0, omega_cut=1e-4,
+    ),
     "dyn": dict(
         lattice="fcc", a=A_SI, nat=2, masses=(M_SI, M_SI), nw=8, n_grid=8,
         a_h=0.015, nn_hop=0.1, a_g=0.09, s_k=0.1, seed=SEED_BASE + 2,
@@ -278,14 +313,19 @@ def make_config_model(name: str, *, real=None, n_grid=None, nw=None) -> Model:
         real = bool(c.get("real", False))
     a = c["a"]
     lat = fcc_lattice(a) if c["lattice"] == "fcc" else sc_lattice(a)
-    tau = np.array([[0.0, 0.0, 0.0], [0.25 * a, 0.25 * a, 0.25 * a]])[: c["nat"]]
+    if c.get("positions") == "random":
+        tau = random_positions(c["seed"] + 17, c["nat"], a, c["min_sep"])
+        masses = np.resize(np.asarray(c["masses"], float), c["nat"])
+    else:
+        tau = np.array([[0.0, 0.0, 0.0], [0.25 * a, 0.25 * a, 0.25 * a]])[: c["nat"]]
+        masses = np.array(c["masses"])
     zstar = eps = None
     if "zstar" in c:
         z = c["zstar"]
         zstar = np.stack([z * np.eye(3), -z * np.eye(3)])
         eps = c["eps_inf"] * np.eye(3)
     return make_model(
-        lattice=lat, tau=tau, mass=np.array(c["masses"]),
+        lattice=lat, tau=tau, mass=masses,
         nw=nw or c["nw"], n_grid=n_grid or c["n_grid"], seed=c["seed"],
         a_h=c["a_h"], a_g=c["a_g"], s_k=c["s_k"], nn_hop=c["nn_hop"], decay=1.5 * a, real=real,
         zstar=zstar, eps_inf=eps, name=name,
