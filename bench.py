@@ -36,6 +36,8 @@ def _parse():
     ap.add_argument("--dyn-steps", type=int, default=200, help="timed RK4 steps of the dynamics workload (0: skip)")
     ap.add_argument("--dyn-grid", type=int, default=80)
     ap.add_argument("--dyn-states", type=int, default=20_000)
+    ap.add_argument("--cell-k", type=int, default=8, help="k points of the large-cell slice (0: skip)")
+    ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
     return ap.parse_args()
 
 
@@ -156,6 +158,11 @@ def main():
     if args.dyn_steps > 0:
         dyn = dynamics_bench(px, dm, model, args)
 
+    cell = None
+    if args.cell_k > 0:
+        del dm
+        cell = cell_bench(px, args)
+
     out = {
         "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, Si-like)",
         "value": r["pairs_per_s"],
@@ -178,6 +185,7 @@ def main():
         "by_precision": {p: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in d.items()}
                          for p, d in results.items()},
         "dynamics": dyn,
+        "large_cell": cell,
     }
     print(json.dumps(out), flush=True)
 
@@ -248,6 +256,79 @@ def dynamics_bench(px, dm, model, args):
     }
     tab.close()
     return out
+
+
+def cell_bench(px, args):
+    """Large cell (40 atoms, 120 modes, 64 Wannier functions, simple-cubic
+    10 Angstrom cell, 3^3 real-space sets): scattering rates on a slice of
+    k points in the 0.3 eV window above the CBM against random q, per
+    precision, with the stage split and the MFMA rates of the Rp contraction
+    and of the batched rotation + projection GEMMs."""
+    import torch
+
+    import synth
+    cfg = synth.CONFIGS["cell"]
+    t0 = time.perf_counter()
+    m = synth.make_config_model("cell")
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dm = px.Model(m)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    nw, nm, n_rp, n_re = m.nw, m.nmodes, len(m.rp_g), len(m.re_g)
+    log("large cell: nw=%d modes=%d Re=%d Rp=%d, g(Re,Rp) %.1f GB; generated %.1fs, loaded %.1fs"
+        % (nw, nm, n_re, n_rp, m.g.nbytes / 1e9, t_gen, t_load))
+    del m
+    cb = nw // 2
+    cand = synth.random_points(cfg["seed"] + 100, 20_000)
+    ec, _, _ = px.bands(dm, cand, want_u=False)
+    ecb = ec[:, cb].cpu().numpy()
+    cbm = float(ecb.min())
+    sel = cand[(ecb - cbm >= 0.0) & (ecb - cbm <= cfg["window"])]
+    ks = sel[:args.cell_k] if len(sel) >= args.cell_k else cand[np.argsort(ecb)[:args.cell_k]]
+    q = synth.random_points(cfg["seed"] + 200, args.cell_q)
+    qd = torch.as_tensor(q, device="cuda")
+    par = px.Params(temp=cfg["T"], mu=cfg["mu"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"])
+    pairs = len(ks) * len(q)
+    fl_rp = 8.0 * n_rp * nm * nw * nw
+    fl_ep = 8.0 * nm * nw ** 3 + 8.0 * nm * nm * nw * nw       # rotation + projection per pair
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
+        px.rates(dm, ks[:1], qd[:64], par, precision=prec)
+        torch.cuda.synchronize()
+        px.timer_reset()
+        px.timer_enable(True)
+        t0 = time.perf_counter()
+        px.rates(dm, ks, qd, par, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        px.timer_enable(False)
+        st = {s: px.timer_get(s) for s in ("rp_contraction", "rp_phases", "epilogue", "hkq_fourier", "eig_hkq",
+                                            "re_contraction", "phonons")}
+        px.timer_reset()
+        rp_ms, ep_ms = st["rp_contraction"][1], st["epilogue"][1]
+        res[prec] = dict(pairs_per_s=pairs / dt, ms=round(1e3 * dt, 3),
+                         stage_ms={s: round(v[1], 3) for s, v in st.items()},
+                         rp_tflops=round(fl_rp * pairs / (rp_ms * 1e-3) / 1e12, 2) if rp_ms > 0 else None,
+                         rot_proj_tflops=round(fl_ep * pairs / (ep_ms * 1e-3) / 1e12, 2) if ep_ms > 0 else None)
+        log("large cell %s: %.3e pairs/s, rp %.1f TFLOP/s, rotation+projection %.1f TFLOP/s; stages %s" % (
+            prec, pairs / dt, res[prec]["rp_tflops"] or 0, res[prec]["rot_proj_tflops"] or 0, res[prec]["stage_ms"]))
+    # |g|^2 error vs FP64 on a sample (degenerate-group sums)
+    ke, qe = ks[:2], q[:16]
+    ref = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision="fp64"))
+    bmax = ref.flatten(2).abs().max(dim=2).values
+    for prec in ("fp32", "bf16x3", "bf16x6"):
+        got = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision=prec).double())
+        res[prec]["g2_err_vs_fp64"] = float(((got - ref).abs().flatten(2).max(dim=2).values
+                                             / bmax.clamp_min(1e-300)).max())
+    del dm
+    return {
+        "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, large cell)",
+        "config": {"workload": "large cell: 40 atoms (120 modes), Nw=64, simple cubic a=10 A, %d Re x %d Rp "
+                               "(3^3 sets), %d window k x %d random q, T=300 K, sigma=5 meV" % (n_re, n_rp, len(ks), len(q))},
+        "flops_per_pair": {"rp_contraction": fl_rp, "rotation_projection": fl_ep},
+        "by_precision": res,
+    }
 
 
 def group_sums(px, dm, ks, qs, g2):

@@ -197,40 +197,52 @@ __global__ void k_wide_g2(WideChunk w) {
 
 // partial[z][blk][n][nu] = (2 pi/hbar) x sum over the block's q and all m of
 //   w_q |g_mn,nu|^2 [delta(e_n - hw - e_m)(1 + N - f_m) + delta(e_n + hw - e_m)(N + f_m)]
+// Workgroup (output tile of 256 (nu, n), q block, k): one thread per (nu, n);
+// the energies and occupations at k+q of the block's q are staged in LDS.  The
+// Gaussians are evaluated in T, as in the register epilogue of small models.
+constexpr int kWideQ = 32;    // q per block (the partial layout's block size)
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_wide_rates(WideChunk w) {
-    const int z = blockIdx.y, blk = blockIdx.x;
+    __shared__ double s_em[kWideQ][kMaxNwWide], s_fm[kWideQ][kMaxNwWide];
+    const int z = blockIdx.z, blk = blockIdx.y;
     const int nw = w.nw, nm = w.nm;
     const int q0 = blk * w.qpb, q1 = min(w.nq, q0 + w.qpb);
     const double kt = kBoltzEv * w.temp;
-    const double is = 1.0 / w.sigma, nrm = 1.0 / (sqrt(kPi) * w.sigma);
-    const T* g = reinterpret_cast<const T*>(w.g);
-    for (int o = threadIdx.x; o < nm * nw; o += blockDim.x) {
-        const int nu = o / nw, n = o % nw;
-        const double en = w.ek[(long)z * nw + n];
-        double acc = 0.0;
-        for (int q = q0; q < q1; ++q) {
-            const long qg = (long)w.q_off + q;
-            const double om = w.omega[qg * nm + nu];
-            if (!(om > w.omega_cut)) continue;
-            const double nb = 1.0 / expm1(om / kt);
-            const double wq = w.qw ? w.qw[qg] : w.uniform_w;
-            const long pair = (long)z * w.nq + q;
-            const T* gp = g + 2 * ((pair * nm + nu) * nw) * nw;
-            double s = 0.0;
-            for (int m = 0; m < nw; ++m) {
-                const double em = w.ekq[pair * nw + m];
-                const double fm = 1.0 / (exp((em - w.mu) / kt) + 1.0);
-                const double gr = (double)gp[2 * (m * nw + n)], gi = (double)gp[2 * (m * nw + n) + 1];
-                const double x1 = (en - om - em) * is, x2 = (en + om - em) * is;
-                const double d_em = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
-                const double d_ab = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
-                s += (gr * gr + gi * gi) * (d_em * (1.0 + nb - fm) + d_ab * (nb + fm));
-            }
-            acc += wq * s;
-        }
-        w.partial[(((long)z * w.nblk + blk) * nw + n) * nm + nu] = acc * (2.0 * kPi / kHbarEvFs);
+    for (int e = threadIdx.x; e < (q1 - q0) * nw; e += blockDim.x) {
+        const int ql = e / nw, m = e % nw;
+        const double em = w.ekq[((long)z * w.nq + q0 + ql) * nw + m];
+        s_em[ql][m] = em;
+        s_fm[ql][m] = 1.0 / (exp((em - w.mu) / kt) + 1.0);
     }
+    __syncthreads();
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nm * nw) return;
+    const int nu = o / nw, n = o % nw;
+    const T is = (T)(1.0 / w.sigma), nrm = (T)(1.0 / (sqrt(kPi) * w.sigma));
+    const T* g = reinterpret_cast<const T*>(w.g);
+    const double en = w.ek[(long)z * nw + n];
+    double acc = 0.0;
+    for (int q = q0; q < q1; ++q) {
+        const long qg = (long)w.q_off + q;
+        const double om = w.omega[qg * nm + nu];
+        if (!(om > w.omega_cut)) continue;
+        const double nb = 1.0 / expm1(om / kt);
+        const double wq = w.qw ? w.qw[qg] : w.uniform_w;
+        const long pair = (long)z * w.nq + q;
+        const T* gp = g + 2 * ((pair * nm + nu) * nw) * nw + 2 * n;
+        double s = 0.0;
+        for (int m = 0; m < nw; ++m) {
+            const double em = s_em[q - q0][m], fm = s_fm[q - q0][m];
+            const T gr = gp[2 * m * nw], gi = gp[2 * m * nw + 1];
+            const T x1 = (T)(en - om - em) * is, x2 = (T)(en + om - em) * is;
+            const T d_em = x1 * x1 > (T)200 ? (T)0 : nrm * exp(-x1 * x1);
+            const T d_ab = x2 * x2 > (T)200 ? (T)0 : nrm * exp(-x2 * x2);
+            s += (double)(gr * gr + gi * gi) * ((double)d_em * (1.0 + nb - fm) + (double)d_ab * (nb + fm));
+        }
+        acc += wq * s;
+    }
+    w.partial[(((long)z * w.nblk + blk) * nw + n) * nm + nu] = acc * (2.0 * kPi / kHbarEvFs);
 }
 
 template <typename T>
@@ -284,7 +296,8 @@ void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
         launch_cgemm<T, double, T, false>(nm, nw2, nm, npair, b, w.pmat, nm, gh, nw2, gw, nw2, st);
     }
     if (rates) {
-        hipLaunchKernelGGL(k_wide_rates<T>, dim3(w.nblk, w.nkb), dim3(256), 0, st, w);
+        if (w.qpb > kWideQ) throw Error{-1, "wide_rates: q block too large"};
+        hipLaunchKernelGGL(k_wide_rates<T>, dim3((nm * nw + 255) / 256, w.nblk, w.nkb), dim3(256), 0, st, w);
         check_launch("wide_rates");
     } else {
         const long tot = npair * nm * nw2;
