@@ -36,6 +36,8 @@ def _parse():
     ap.add_argument("--dyn-steps", type=int, default=200, help="timed RK4 steps of the dynamics workload (0: skip)")
     ap.add_argument("--dyn-grid", type=int, default=80)
     ap.add_argument("--dyn-states", type=int, default=20_000)
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="first run a 1 GiB device fill and a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--cell-k", type=int, default=8, help="k points of the large-cell slice (0: skip)")
     ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
     return ap.parse_args()
@@ -65,6 +67,17 @@ def main():
 
     import synth
     import paper_2002_02045_amd as px
+
+    if args.pmc_calibrate:
+        # known traffic for scaling FETCH_SIZE / WRITE_SIZE: the fill writes 1 GiB,
+        # the copy reads 1 GiB and writes 1 GiB
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration: fill writes %d bytes; copy reads %d and writes %d bytes" % (a.nbytes, a.nbytes, b.nbytes))
+        del a, b
 
     cfg = synth.CONFIGS["si"]
     t0 = time.time()
@@ -144,8 +157,9 @@ def main():
     ok = [p for p in results if results[p]["g2_err_vs_fp64"] <= 1e-5]
     head = max(ok, key=lambda p: results[p]["pairs_per_s"]) if ok else "fp64"
     r = results[head]
-    roof = {"bound": "mfma", "kernel": "rp_contraction (phase_gemm)", "achieved": round(r["rp_tflops"], 3),
-            "peak": round(PEAK_TFLOPS[head], 1), "unit": "TFLOP/s", "frac": round(r["rp_frac"], 4), "traffic": None,
+    roof = {"bound": "mfma", "kernel": "rp_contraction (%s)" % RP_KERNEL[head], "achieved": round(r["rp_tflops"], 3),
+            "peak": round(PEAK_TFLOPS[head], 1), "unit": "TFLOP/s", "frac": round(r["rp_frac"], 4),
+            "traffic": measured_traffic(RP_KERNEL[head]), "traffic_unit": "HBM bytes per launch",
             "flops_per_pair": 8.0 * n_rp * nw * nw * nm, "avg_launch_ms": round(r["rp_avg_ms"], 4),
             "mfma_products_per_flop": SPLIT_PRODUCTS[head],
             "mfma_tflops": round(r["rp_tflops"] * SPLIT_PRODUCTS[head], 1)}
@@ -248,7 +262,8 @@ def dynamics_bench(px, dm, model, args):
                                "FP32 pair table, sigma=8 meV, T_ph=300 K, dt=1 fs" % (
                                    "x".join(map(str, n)), S, float(ee.max() - ee.min()))},
         "roofline": {"bound": "hbm", "kernel": "collision_stream", "achieved": round(achieved, 1),
-                     "peak": HBM_GBS, "unit": "GB/s", "frac": round(achieved / HBM_GBS, 4), "traffic": None,
+                     "peak": HBM_GBS, "unit": "GB/s", "frac": round(achieved / HBM_GBS, 4),
+            "traffic": measured_traffic("k_stream<float, 1, 1>"), "traffic_unit": "HBM bytes per launch",
                      "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5)},
         "collision_evals_per_s": ns / (1e-3 * (ms + msf)) if ms > 0 else None,
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
@@ -329,6 +344,30 @@ def cell_bench(px, args):
         "flops_per_pair": {"rp_contraction": fl_rp, "rotation_projection": fl_ep},
         "by_precision": res,
     }
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the PMC record in profiles/, or None
+    when there is none or the kernel's source has changed since it was taken."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(here, "profiles", "hbm_traffic_pmc.md")).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))["kernels"].get(kernel)
+        if rec is None:
+            return None
+        with open(os.path.join(here, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+
+
+# kernel behind each precision's Rp contraction (Si-like shape: 384 output columns)
+RP_KERNEL = {"fp64": "k_phase_gemm<double, 4>", "fp32": "k_phase_gemm<float, 8>",
+             "bf16x3": "k_gemm_bf16_planes<8, 2>", "bf16x6": "k_gemm_bf16_planes<8, 3>"}
 
 
 def group_sums(px, dm, ks, qs, g2):

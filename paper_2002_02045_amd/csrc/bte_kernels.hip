@@ -12,10 +12,11 @@
 // so one pass over P (row sums and column sums together) evaluates I for any
 // f: 4 S^2 bytes instead of the 4 S^2 3nat bytes of the per-mode table.
 //
-// Streaming pass.  A 256-thread workgroup owns a 256-row x 1024-column tile;
-// each wave walks 64 rows, each lane holds 16 columns (four 16-byte loads per
-// row, each instruction reading 1 KB contiguously).  Row sums are reduced
-// across the wave with shuffles, column sums stay in registers and are
+// Streaming pass.  A 256-thread workgroup owns a 1024-column tile and a run of
+// rows sized so that the whole grid is resident at once; its four waves take
+// the rows in turn, each lane holding 16 columns (four 16-byte nontemporal
+// loads per row, one instruction reading 1 KB contiguously).  Row sums are
+// reduced across the wave with shuffles, column sums stay in registers and are
 // combined across the four waves through LDS at the end.  Partials go to
 // rowp[a][col tile][row] and colp[b][row tile][col] and are reduced in a fixed
 // order by the finishing kernel (no atomics; results are deterministic).
