@@ -370,22 +370,44 @@ __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ 
 }
 
 // C[z] = A B[z] with A given as phase planes [2NS][M][Kp] and B[z] as planes
-// [2NS][N][Kp].  A wave owns 32 rows (two 16-row fragments) so each B fragment
-// read from LDS feeds twice the MFMAs of the in-register path.  Workgroups are
-// numbered so that each of the 8 XCDs (which receive consecutive workgroup ids
-// in turn) runs a contiguous range of (column, row, z) tiles: the B panel of one
-// z then stays in that XCD's L2 while its row tiles stream the shared A planes.
-constexpr int kWR = 2;                 // 16-row fragments per wave
-constexpr int kBMP = 64 * kWR;         // rows per workgroup
+// [2NS][N][Kp], on the 32x32x16 bf16 MFMA (twice the rate of the 16x16x32
+// shape on gfx950, measured from registers).  Operand lane l holds row (A) or
+// column (B) l%32 and the 8 consecutive k of group l/32; accumulator element v
+// of lane l is C[8(v/4) + 4(l/32) + v%4][l%32].  A workgroup owns 128 rows x
+// 32*CT columns, wave w the rows 32w..32w+31 against all CT column tiles.
+// Workgroups are numbered so that each of the 8 XCDs (which receive
+// consecutive workgroup ids in turn) runs a contiguous range of (column, row, z)
+// tiles: the B panel of one z stays in that XCD's L2 while its row tiles
+// stream the shared A planes.
+//
+// Software pipeline, one barrier per K chunk of 32: while the MFMAs of chunk c
+// run, the B panel of chunk c+1 streams into the other half of a double LDS
+// buffer by direct global->LDS loads (each wave instruction fills 1 KB: 16
+// rows x 64 bytes) and the A fragments of chunk c+1 load into registers.  LDS
+// rows are 64 bytes with their four 16-byte segments XOR-swizzled by bits 2-3
+// of the row, so the 16-lane passes of a ds_read_b128 hit distinct banks.
+typedef float flt16 __attribute__((ext_vector_type(16)));
 
-template <int CB, int NS>
+__device__ __forceinline__ flt16 mfma_bf32(const u16x8& a, const u16x8& b, flt16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+constexpr int kBMP = 128;              // rows per workgroup (32 per wave)
+
+__device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) & 3); }
+
+template <int CT, int NS>
 __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
                                                           const uint16_t* __restrict__ As,
                                                           const uint16_t* __restrict__ Bs, long sB,
                                                           float* __restrict__ C, long sC) {
-    constexpr int BN = 16 * CB;
+    constexpr int BN = 32 * CT;
     constexpr int NP = 2 * NS;
-    __shared__ __attribute__((aligned(16))) uint16_t bsh[NP][BN][kBK + kPadK];
+    constexpr int PLANE = BN * kBK;          // bf16 elements of one plane in one buffer
+    constexpr int BUF = NP * PLANE;
+    constexpr int NBLK = NP * (BN / 16);     // 1 KB blocks per chunk
+    __shared__ __attribute__((aligned(16))) uint16_t bsh[2 * BUF];
     // workgroup id -> tile id, contiguous per XCD
     const int nblk = nbx * nby * nz;
     const int b = blockIdx.x;
@@ -395,95 +417,115 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
     const int bx = tile % nbx, by = (tile / nbx) % nby, z = tile / (nbx * nby);
     const int row0 = by * kBMP, col0 = bx * BN;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int l32 = lane & 31, kg = lane >> 5;
     const uint16_t* bz = Bs + (long)z * sB;
     float* cz = C + (long)z * sC * 2;
-    flt4 are[kWR][CB], aim[kWR][CB];
+    flt16 are[CT], aim[CT];
 #pragma unroll
-    for (int f = 0; f < kWR; ++f)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            are[f][cb] = flt4{0, 0, 0, 0};
-            aim[f][cb] = flt4{0, 0, 0, 0};
+        for (int v = 0; v < 16; ++v) {
+            are[ct][v] = 0.f;
+            aim[ct][v] = 0.f;
         }
-    const uint16_t* arow[kWR];
-    bool rok[kWR];
-#pragma unroll
-    for (int f = 0; f < kWR; ++f) {
-        const int row = row0 + wave * 16 * kWR + f * 16 + li;
-        rok[f] = row < M;
-        arow[f] = As + (long)(rok[f] ? row : 0) * Kp + 8 * lk;
-    }
+    // rows and columns past the edge load the last valid one: their results are
+    // never stored, and the loads need no branch
+    const int arow_i = min(row0 + wave * 32 + l32, M - 1);
+    const uint16_t* arow = As + (long)arow_i * Kp + 8 * kg;
     const long plane = (long)M * Kp;
     const u16x8 sign = {0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u};
-    for (int kc = 0; kc < Kp; kc += kBK) {
-        // A fragments of this chunk, issued before the B staging
-        u16x8 ar[kWR][NS], ai[kWR][NS];
+    // B panel of the chunk at kc into buffer h: wave w fills blocks w, w+4, ...;
+    // lane l writes row (l/4) of the block, LDS segment l%4
+    static_assert(NBLK % 4 == 0, "whole blocks per wave");
+    auto issue_b = [&](int kc, int h) {
 #pragma unroll
-        for (int f = 0; f < kWR; ++f)
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-                ar[f][t] = rok[f] ? *reinterpret_cast<const u16x8*>(arow[f] + t * plane + kc) : zero;
-                ai[f][t] = rok[f] ? *reinterpret_cast<const u16x8*>(arow[f] + (NS + t) * plane + kc) : zero;
-            }
-        for (int e = tid; e < NP * BN * (kBK / 8); e += 256) {
-            const int seg = e % (kBK / 8);
-            const int nn = (e / (kBK / 8)) % BN;
-            const int pl = e / ((kBK / 8) * BN);
-            const int col = col0 + nn;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (col < N) v = *reinterpret_cast<const uint4*>(bz + ((long)pl * N + col) * Kp + kc + seg * 8);
-            *reinterpret_cast<uint4*>(&bsh[pl][nn][seg * 8]) = v;
+        for (int j = 0; j < NBLK / 4; ++j) {
+            const int i = 4 * j + wave;
+            const int pl = i / (BN / 16), rb = i % (BN / 16);
+            const int r = rb * 16 + (lane >> 2);
+            const int col = min(col0 + r, N - 1);
+            uint16_t* dst = bsh + h * BUF + pl * PLANE + rb * 16 * kBK;
+            __builtin_amdgcn_global_load_lds((const void*)(bz + ((long)pl * N + col) * Kp + kc + 8 * swz(r, lane & 3)),
+                                             (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
         }
-        __syncthreads();
-        u16x8 nai[kWR][NS];
+    };
+    // A fragments of the chunk at kc: k-steps s = 0, 1 of 16
+    u16x8 anr[2][NS], ani[2][NS];
+    auto load_a = [&](int kc) {
 #pragma unroll
-        for (int f = 0; f < kWR; ++f)
-#pragma unroll
-            for (int t = 0; t < NS; ++t) nai[f][t] = ai[f][t] ^ sign;
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int nn = cb * 16 + li;
-            u16x8 br[NS], bi[NS];
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
-                br[t] = *reinterpret_cast<const u16x8*>(&bsh[t][nn][8 * lk]);
-                bi[t] = *reinterpret_cast<const u16x8*>(&bsh[NS + t][nn][8 * lk]);
+                anr[s][t] = *reinterpret_cast<const u16x8*>(arow + t * plane + kc + 16 * s);
+                ani[s][t] = *reinterpret_cast<const u16x8*>(arow + (NS + t) * plane + kc + 16 * s);
             }
+    };
+    issue_b(0, 0);
+    load_a(0);
+    int h = 0;
+    for (int kc = 0; kc < Kp; kc += kBK, h ^= 1) {
+        // chunk kc's panel and fragments have arrived (this wave's loads), and
+        // every wave has finished reading the other buffer
+        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        u16x8 ar[2][NS], ai[2][NS], nai[2][NS];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                ar[s][t] = anr[s][t];
+                ai[s][t] = ani[s][t];
+                nai[s][t] = ani[s][t] ^ sign;
+            }
+        if (kc + kBK < Kp) {
+            issue_b(kc + kBK, h ^ 1);
+            load_a(kc + kBK);
+        }
+        const uint16_t* bb = bsh + h * BUF;
+        // groups g = (column tile, k-step); the B fragments of group g+1 are read
+        // from LDS while the MFMAs of group g run
+        u16x8 br[2][NS], bi[2][NS];
+        auto read_b = [&](int g, int slotb) {
+            const int nn = (g >> 1) * 32 + l32;
+            const int so = nn * kBK + 8 * swz(nn, 2 * (g & 1) + kg);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                br[slotb][t] = *reinterpret_cast<const u16x8*>(bb + t * PLANE + so);
+                bi[slotb][t] = *reinterpret_cast<const u16x8*>(bb + (NS + t) * PLANE + so);
+            }
+        };
+        read_b(0, 0);
+#pragma unroll
+        for (int g = 0; g < 2 * CT; ++g) {
+            if (g + 1 < 2 * CT) read_b(g + 1, (g + 1) & 1);
+            const int ct = g >> 1, s = g & 1, cs = g & 1;
 #pragma unroll
             for (int ord = NS - 1; ord >= 0; --ord) {
 #pragma unroll
                 for (int i = 0; i <= ord; ++i) {
                     const int j = ord - i;
-#pragma unroll
-                    for (int f = 0; f < kWR; ++f) {
-                        are[f][cb] = mfma_bf(ar[f][i], br[j], are[f][cb]);
-                        are[f][cb] = mfma_bf(nai[f][i], bi[j], are[f][cb]);
-                        aim[f][cb] = mfma_bf(ar[f][i], bi[j], aim[f][cb]);
-                        aim[f][cb] = mfma_bf(ai[f][i], br[j], aim[f][cb]);
-                    }
+                    are[ct] = mfma_bf32(ar[s][i], br[cs][j], are[ct]);
+                    aim[ct] = mfma_bf32(ar[s][i], bi[cs][j], aim[ct]);
+                    are[ct] = mfma_bf32(nai[s][i], bi[cs][j], are[ct]);
+                    aim[ct] = mfma_bf32(ai[s][i], br[cs][j], aim[ct]);
                 }
             }
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int f = 0; f < kWR; ++f)
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = col0 + ct * 32 + l32;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int col = col0 + cb * 16 + li;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = row0 + wave * 16 * kWR + f * 16 + AccOf<float>::row(lk, v);
-                if (row < M && col < N) {
-                    const long off = ((long)row * N + col) * 2;
-                    cz[off] = are[f][cb][v];
-                    cz[off + 1] = aim[f][cb][v];
-                }
+        for (int v = 0; v < 16; ++v) {
+            const int row = row0 + wave * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+            if (row < M && col < N) {
+                const long off = ((long)row * N + col) * 2;
+                cz[off] = are[ct][v];
+                cz[off + 1] = aim[ct][v];
             }
         }
+    }
 }
 
 inline void check_launch(const char* what) {
@@ -589,22 +631,20 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
-    const int cb = pick_cb(N, 8);
-    const int nbx = (N + 16 * cb - 1) / (16 * cb), nby = (M + kBMP - 1) / kBMP;
+    const int ct = N <= 64 ? 2 : 4;
+    const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + kBMP - 1) / kBMP;
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
     dim3 grid((unsigned)nblk);
-#define EPHX_BFP(CBV, NSV)                                                                                      \
-    hipLaunchKernelGGL((k_gemm_bf16_planes<CBV, NSV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, sB, \
+#define EPHX_BFP(CTV, NSV)                                                                                      \
+    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, sB, \
                        C, sC)
     if (nsplit == 2) {
-        if (cb == 3) EPHX_BFP(3, 2);
-        else if (cb == 4) EPHX_BFP(4, 2);
-        else EPHX_BFP(8, 2);
+        if (ct == 2) EPHX_BFP(2, 2);
+        else EPHX_BFP(4, 2);
     } else {
-        if (cb == 3) EPHX_BFP(3, 3);
-        else if (cb == 4) EPHX_BFP(4, 3);
-        else EPHX_BFP(8, 3);
+        if (ct == 2) EPHX_BFP(2, 3);
+        else EPHX_BFP(4, 3);
     }
 #undef EPHX_BFP
     check_launch("gemm_bf16_planes");
