@@ -269,8 +269,61 @@ def dynamics_bench(px, dm, model, args):
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,
     }
+    out["transport"] = transport_bench(px, dm, tab, kk, bb, ee, n, f1, cfg)
     tab.close()
     return out
+
+
+def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
+    """On the dynamics states: ITA mobility (Eqs. BTE_iter, cond, 10 iterations,
+    FP32 transport matrix), the TDF by tetrahedra on 512 energies with sigma and
+    Seebeck (Eqs. cond_tdf2, cond_tdf, seebeck), and the population p(E,t) of the
+    final occupations (Eq. pop)."""
+    import torch
+
+    pts = np.stack([kk // (n[1] * n[2]), (kk // n[2]) % n[1], kk % n[2]], axis=-1) / np.asarray(n, dtype=np.float64)
+    _, _, v = px.bands(dm, pts, want_u=False, want_vel=True)
+    vel = v[torch.arange(len(bb), device=v.device), torch.as_tensor(bb, device=v.device)].contiguous()
+    cbm = float(ee.min())
+    par = px.Params(temp=cfg["T"], mu=cbm - 0.2, sigma=cfg["sigma"], omega_cut=cfg["omega_cut"], n_q=float(np.prod(n)))
+    energies = np.linspace(cbm, float(ee.max()), 512)
+    tab.mobility(par, vel, 10)
+    tab.tdf(par, vel, torch.zeros_like(vel), energies[:4])          # builds the tetrahedra
+    torch.cuda.synchronize()
+    px.timer_reset()
+    px.timer_enable(True)
+    t0 = time.perf_counter()
+    ff, _, mob = tab.mobility(par, vel, 10)
+    torch.cuda.synchronize()
+    t_ita = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sig_e, sigma, seebeck = tab.tdf(par, vel, ff, energies)
+    t_tdf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pop = tab.population(f_t, energies)
+    t_pop = time.perf_counter() - t0
+    px.timer_enable(False)
+    n_st, ms_st = px.timer_get("transport_stream")
+    _, ms_tdf = px.timer_get("tdf_tetra")
+    _, ms_pop = px.timer_get("population_tetra")
+    px.timer_reset()
+    S = len(kk)
+    alg = 4.0 * S * S
+    log("transport: ITA 10 iterations %.1f ms (stream %.3f ms avg = %.0f GB/s), TDF %d energies %.1f ms, "
+        "population %.1f ms; mu_xx %.4g cm^2/Vs, S_xx %.4g uV/K" % (
+            1e3 * t_ita, ms_st / n_st, alg / (ms_st / n_st * 1e-3) / 1e9, len(energies), 1e3 * t_tdf, 1e3 * t_pop,
+            float(mob[0, 0]), 1e6 * float(seebeck[0, 0])))
+    return {
+        "ita_ms": round(1e3 * t_ita, 3), "ita_iterations": 10,
+        "transport_stream_avg_ms": round(ms_st / n_st, 5),
+        "transport_stream_gbs": round(alg / (ms_st / n_st * 1e-3) / 1e9, 1),
+        "tdf_ms": round(1e3 * t_tdf, 3), "tdf_kernel_ms": round(ms_tdf, 3), "energies": len(energies),
+        "population_ms": round(1e3 * t_pop, 3), "population_kernel_ms": round(ms_pop, 3),
+        "mobility_xx_cm2_per_Vs": float(mob[0, 0]), "sigma_xx_S_per_m": float(sigma[0, 0]),
+        "seebeck_xx_uV_per_K": 1e6 * float(seebeck[0, 0]),
+        "population_integral": float(np.trapezoid(pop.cpu().numpy(), energies)),
+        "carriers": float(f_t.sum()),
+    }
 
 
 def cell_bench(px, args):

@@ -250,6 +250,27 @@ int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_
 int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
                       const double* mob_bar, double* g_bar, void* stream);
 
+/* Transport distribution function, Eq. cond_tdf2, by linear tetrahedron
+ * integration (Sec. 4.3) over the table's states: the grid's cubes are cut
+ * into 6 tetrahedra along their (0,0,0)-(1,1,1) diagonal and a tetrahedron
+ * enters for each band whose four corners are all table states.
+ *   Sigma_ab(E) = (2/(N_k Omega)) sum_nk v^a F^b delta(E - eps_nk)
+ * with spin degeneracy 2, N_k the grid size and Omega the cell volume.
+ * vel and f_ita: device [S][3] (Angstrom/fs; F as returned by ephx_mobility,
+ * Angstrom); e_grid: device [n_e] ascending energies (eV), 2 <= n_e <= 65535.
+ * Outputs (device, each may be NULL): tdf [n_e][3][3] in 1/(fs Angstrom eV);
+ * sigma [3][3], Eq. cond_tdf, in S/m; seebeck [3][3], Eq. seebeck with the
+ * electron charge -e, in V/K (both by the trapezoid rule on e_grid, f0 at
+ * p->mu and p->temp).  Synchronises the stream before returning. */
+int ephx_tdf(ephx_table* t, const ephx_params* p, const double* vel, const double* f_ita, int n_e,
+             const double* e_grid, double* tdf, double* sigma, double* seebeck, void* stream);
+
+/* Carrier population, Eq. pop: pop[e] = sum_nk f_nk delta(eps_nk - E_e) (1/eV)
+ * by the same tetrahedra; f device [S], e_grid device [n_e], pop device [n_e].
+ * Synchronises the stream before returning. */
+int ephx_population(ephx_table* t, const double* f, int n_e, const double* e_grid, double* pop,
+                    void* stream);
+
 /* Stage timers (instrumentation, not part of the method).  While enabled,
  * the library brackets each launch of its main kernels with HIP events on the
  * launch stream, keyed by stage name: "re_contraction", "hkq_fourier",

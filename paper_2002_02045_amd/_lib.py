@@ -78,6 +78,8 @@ _SIGS = {
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),
     "ephx_mobility": ([_P, _P, _P, _I, _P, _P, _P, _P], _I),
     "ephx_mobility_vjp": ([_P, _P, _P, _I, _P, _P, _P], _I),
+    "ephx_tdf": ([_P, _P, _P, _P, _I, _P, _P, _P, _P, _P], _I),
+    "ephx_population": ([_P, _P, _I, _P, _P, _P], _I),
     "ephx_timer_enable": ([_I], _I),
     "ephx_timer_reset": ([], _I),
     "ephx_timer_get": ([C.c_char_p, _P, _P], _I),

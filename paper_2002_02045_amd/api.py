@@ -289,6 +289,27 @@ class PairTable:
                                 stream_ptr()))
         return ff, tau, mob
 
+    def tdf(self, params, vel, f_ita, energies):
+        """(TDF [n_E][3][3] in 1/(fs A eV), sigma [3][3] in S/m, Seebeck [3][3] in V/K)."""
+        vel = torch.as_tensor(vel, dtype=F64, device="cuda").contiguous()
+        ff = torch.as_tensor(f_ita, dtype=F64, device="cuda").contiguous()
+        eg = torch.as_tensor(energies, dtype=F64, device="cuda").contiguous()
+        out = torch.empty((eg.shape[0], 3, 3), dtype=F64, device="cuda")
+        sig = torch.empty((3, 3), dtype=F64, device="cuda")
+        see = torch.empty((3, 3), dtype=F64, device="cuda")
+        pc = params.c()
+        check(lib.ephx_tdf(self._h, C.byref(pc), ptr(vel), ptr(ff), int(eg.shape[0]), ptr(eg), ptr(out), ptr(sig),
+                           ptr(see), stream_ptr()))
+        return out, sig, see
+
+    def population(self, f, energies):
+        """p(E) = sum_nk f_nk delta(eps_nk - E) (1/eV) on the energy grid."""
+        ff = torch.as_tensor(f, dtype=F64, device="cuda").contiguous()
+        eg = torch.as_tensor(energies, dtype=F64, device="cuda").contiguous()
+        out = torch.empty(eg.shape[0], dtype=F64, device="cuda")
+        check(lib.ephx_population(self._h, ptr(ff), int(eg.shape[0]), ptr(eg), ptr(out), stream_ptr()))
+        return out
+
     def mobility_vjp(self, params, vel, n_iter, mob_bar):
         """dL/dg(Re,Rp) (complex128, layout of the model's g) for L = sum mob_bar * mu."""
         vel = torch.as_tensor(vel, dtype=F64, device="cuda").contiguous()

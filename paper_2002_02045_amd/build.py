@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libephx.so")
 SOURCES = ["phase_gemm.hip", "eig.hip", "eph_kernels.hip", "eph_wide.hip", "ephx_api.hip", "bte_kernels.hip",
-           "bte_api.hip"]
+           "tetra.hip", "bte_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions in device code

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ephx.h"
@@ -33,6 +34,9 @@ struct ephx_table {
     double c = 0.0;               // (2 pi/hbar)/N_q
     std::vector<void*> owned;
     Workspace ws;
+    std::vector<int32_t> h_kc, h_band;   // host copies of the states
+    int32_t* d_tet = nullptr;            // [n_tet][4] tetrahedra of window states, built on first use
+    int n_tet = -1;
     ~ephx_table() {
         ws.release();
         for (void* p : owned)
@@ -266,6 +270,8 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
             t->d_band = (int32_t*)t->alloc(S * 4);
             hip_check(hipMemcpy(t->d_kc, kc.data(), 3 * S * 4, hipMemcpyHostToDevice), "hipMemcpy");
             hip_check(hipMemcpy(t->d_band, band, S * 4, hipMemcpyHostToDevice), "hipMemcpy");
+            t->h_kc = kc;
+            t->h_band.assign(band, band + S);
             double* dks = (double*)t->ws.get("t.ks", 3 * S * 8);
             double* dnks = (double*)t->ws.get("t.nks", 3 * S * 8);
             hip_check(hipMemcpy(dks, ks.data(), 3 * S * 8, hipMemcpyHostToDevice), "hipMemcpy");
@@ -689,6 +695,115 @@ extern "C" int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const doub
         }
         if (m->d_wg) scale_rows((long)m->n_re_g * m->n_rp_g, nm * nw2, m->d_wg, g_bar, st);
         // keep the workspace alive until the stream has used it
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+namespace ephx {
+namespace {
+
+// Tetrahedra of the window states: every grid cube is cut into 6 tetrahedra
+// along its (0,0,0)-(1,1,1) diagonal; one enters per band whose four corners
+// are all states.  Ordered by (cube origin index, path, band).
+void ensure_tetrahedra(ephx_table* t) {
+    if (t->n_tet >= 0) return;
+    const int S = t->S;
+    const long n1 = t->n1, n2 = t->n2, n3 = t->n3;
+    auto lin = [&](long a, long b, long c) { return ((a % n1 + n1) % n1 * n2 + (b % n2 + n2) % n2) * n3 + (c % n3 + n3) % n3; };
+    std::unordered_map<long, int> state;
+    std::vector<int> bands;
+    for (int s = 0; s < S; ++s) {
+        const long k = lin(t->h_kc[3 * s], t->h_kc[3 * s + 1], t->h_kc[3 * s + 2]);
+        state[k * t->nw + t->h_band[s]] = s;
+        bands.push_back(t->h_band[s]);
+    }
+    std::sort(bands.begin(), bands.end());
+    bands.erase(std::unique(bands.begin(), bands.end()), bands.end());
+    std::vector<long> origins;
+    for (int s = 0; s < S; ++s)
+        for (int d = 0; d < 8; ++d)
+            origins.push_back(lin(t->h_kc[3 * s] - (d & 1), t->h_kc[3 * s + 1] - ((d >> 1) & 1), t->h_kc[3 * s + 2] - ((d >> 2) & 1)));
+    std::sort(origins.begin(), origins.end());
+    origins.erase(std::unique(origins.begin(), origins.end()), origins.end());
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    std::vector<int32_t> tets;
+    for (long o : origins) {
+        const long c0[3] = {o / (n2 * n3), (o / n3) % n2, o % n3};
+        for (int pth = 0; pth < 6; ++pth) {
+            long cr[4][3];
+            for (int d = 0; d < 3; ++d) {
+                cr[0][d] = c0[d];
+                cr[1][d] = c0[d] + (perm[pth][0] == d ? 1 : 0);
+                cr[2][d] = cr[1][d] + (perm[pth][1] == d ? 1 : 0);
+                cr[3][d] = c0[d] + 1;
+            }
+            long kc4[4];
+            for (int j = 0; j < 4; ++j) kc4[j] = lin(cr[j][0], cr[j][1], cr[j][2]);
+            for (int b : bands) {
+                int st4[4];
+                bool all = true;
+                for (int j = 0; j < 4 && all; ++j) {
+                    auto it = state.find(kc4[j] * t->nw + b);
+                    if (it == state.end()) all = false;
+                    else st4[j] = it->second;
+                }
+                if (all) tets.insert(tets.end(), st4, st4 + 4);
+            }
+        }
+    }
+    t->n_tet = (int)(tets.size() / 4);
+    if (t->n_tet > 0) {
+        t->d_tet = (int32_t*)t->alloc(tets.size() * 4);
+        hip_check(hipMemcpy(t->d_tet, tets.data(), tets.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+}
+
+constexpr double kSigmaUnit = 1.602176634e6;   // e^2/(fs Angstrom eV) in S/m
+constexpr double kSpin = 2.0;                  // spin degeneracy of Eq. cond_tdf2
+
+}  // namespace
+}  // namespace ephx
+
+extern "C" int ephx_tdf(ephx_table* t, const ephx_params* p, const double* vel, const double* f_ita, int n_e,
+                        const double* e_grid, double* tdf, double* sigma, double* seebeck, void* stream) {
+    return guarded([&] {
+        require(t != nullptr && p != nullptr, "tdf: null argument");
+        require(vel != nullptr && f_ita != nullptr && e_grid != nullptr, "tdf: null array");
+        require(n_e >= 2 && n_e <= 65535, "tdf: need 2 <= n_e <= 65535");
+        require(p->temp > 0 && std::isfinite(p->mu), "tdf: bad parameters");
+        hipStream_t st = (hipStream_t)stream;
+        ensure_tetrahedra(t);
+        const int S = t->S;
+        double* x = (double*)t->ws.get("td.x", (size_t)9 * S * 8);
+        double* part = (double*)t->ws.get("td.part", (size_t)std::max(1, tetra_chunks(t->n_tet)) * n_e * 9 * 8);
+        double* out = tdf ? tdf : (double*)t->ws.get("td.out", (size_t)n_e * 9 * 8);
+        vf_products(S, vel, f_ita, x, st);
+        const double nk = (double)t->n1 * t->n2 * t->n3;
+        StageTimer tm("tdf_tetra", st);
+        tetra_sum(t->n_tet, t->d_tet, t->d_eps, 9, x, n_e, e_grid, kSpin / (nk * t->m->volume), part, out, st);
+        tm.stop();
+        if (sigma && seebeck) {
+            tdf_transport(n_e, e_grid, out, p->mu, p->temp, kSigmaUnit, sigma, seebeck, st);
+        } else if (sigma || seebeck) {
+            double* tmp = (double*)t->ws.get("td.tmp", 18 * 8);
+            tdf_transport(n_e, e_grid, out, p->mu, p->temp, kSigmaUnit, sigma ? sigma : tmp, seebeck ? seebeck : tmp + 9,
+                          st);
+        }
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+extern "C" int ephx_population(ephx_table* t, const double* f, int n_e, const double* e_grid, double* pop,
+                               void* stream) {
+    return guarded([&] {
+        require(t != nullptr && f != nullptr && e_grid != nullptr && pop != nullptr, "population: null argument");
+        require(n_e >= 1 && n_e <= 65535, "population: need 1 <= n_e <= 65535");
+        hipStream_t st = (hipStream_t)stream;
+        ensure_tetrahedra(t);
+        double* part = (double*)t->ws.get("pp.part", (size_t)std::max(1, tetra_chunks(t->n_tet)) * n_e * 8);
+        StageTimer tm("population_tetra", st);
+        tetra_sum(t->n_tet, t->d_tet, t->d_eps, 1, f, n_e, e_grid, 1.0, part, pop, st);
+        tm.stop();
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     });
 }

@@ -222,6 +222,16 @@ void ita_adj_step(int S, const double* tau, const double* fbar, const double* fn
 void ita_adj_cols(int S, int n_rt, const double* colp, double n_q, double* fbar, hipStream_t st);
 void ita_adj_final(int S, const double* tau, const double* fbar0, const double* vel, const double* taubar, int first,
                    double* gbar, hipStream_t st);
+// Linear tetrahedron integration (tetra.hip): out[e][comp] = scale * sum_T (1/6)
+// sum_j c_j(E_e) x[T_j][comp], nc <= 9 components; partial holds
+// tetra_chunks(n_tet) * n_e * nc doubles.
+int tetra_chunks(int n_tet);
+void tetra_sum(int n_tet, const int32_t* tet, const double* eps, int nc, const double* x, int n_e, const double* egrid,
+               double scale, double* partial, double* out, hipStream_t st);
+void vf_products(int S, const double* vel, const double* ff, double* x, hipStream_t st);
+// sigma (S/m) and Seebeck (V/K) from the TDF [n_e][3][3] by the trapezoid rule
+void tdf_transport(int n_e, const double* egrid, const double* tdf, double mu, double temp, double sigma_unit,
+                   double* sigma, double* seebeck, hipStream_t st);
 // Leading dimension (elements) of S x S tables: rows start 256-byte aligned.
 long table_ld(int S);
 void pair_epilogue(const PairEpilogue& e, int f32, long ld, void* g2out, hipStream_t st);

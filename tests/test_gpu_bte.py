@@ -303,3 +303,31 @@ def test_mobility_vjp_directional_finite_difference(lib):
     ad = float((g_bar.conj() * torch.as_tensor(d)).real.sum())
     _say("  fd %.10e adjoint %.10e" % (fd, ad))
     assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+def test_tdf_seebeck_population_parity(lib):
+    """Tetrahedron integration of the TDF (Eq. cond_tdf2), conductivity and
+    Seebeck from it (Eqs. cond_tdf, seebeck) and the carrier population
+    (Eq. pop) against the oracle, on the GPU's own v and F."""
+    from oracle import tetra
+    m, n, kk, bb, vel, kw = _mobility_adjoint_case(0.9, 0.05, 4)
+    _say("TDF / Seebeck / population, S=%d" % len(kk))
+    dm = lib.Model(m)
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    par = lib.Params(temp=kw["temp"], mu=kw["mu"], sigma=kw["sigma"], n_q=kw["n_q"])
+    ff, _, _ = t.mobility(par, vel.numpy(), 4)
+    eps = bte.state_energies(m, kk, bb, n).numpy()
+    tets = tetra.tetrahedra(kk, bb, n)
+    assert len(tets) > 0
+    energies = np.linspace(eps.min() - 0.01, eps.max() + 0.01, 61)
+    ref = tetra.tdf(eps, vel.numpy(), ff.cpu().numpy(), tets, energies, float(np.prod(n)), m.volume())
+    sig_ref, see_ref = tetra.transport_from_tdf(energies, ref, kw["mu"], kw["temp"])
+    got, sig, see = t.tdf(par, vel.numpy(), ff, energies)
+    scale = float(np.abs(ref).max())
+    assert float(np.abs(got.cpu().numpy() - ref).max()) <= 1e-10 * scale
+    assert float(np.abs(sig.cpu().numpy() - sig_ref).max()) <= 1e-10 * float(np.abs(sig_ref).max())
+    assert float(np.abs(see.cpu().numpy() - see_ref).max()) <= 1e-9 * float(np.abs(see_ref).max())
+    f = np.random.default_rng(80).random(len(kk))
+    p_ref = tetra.population(eps, f, tets, energies)
+    p = t.population(f, energies).cpu().numpy()
+    assert float(np.abs(p - p_ref).max()) <= 1e-10 * float(np.abs(p_ref).max())
