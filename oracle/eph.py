@@ -127,10 +127,13 @@ def eph_pipeline(model, k, q, polar=None, omega_cut=1e-4):
     nw = model.nw
     eps_kq = eps_kq.reshape(nk, nq, nw)
     u_kq = u_kq.reshape(nk, nq, nw, nw)
-    omega, evec = phonons(model, q)
+    # polar = dict(alpha_ewald, gcut[, lo_to]): the Froehlich term, and with
+    # lo_to the dipole-dipole part of D(q) as well
+    ew = None if polar is None else dict(alpha_ewald=polar["alpha_ewald"], gcut=polar["gcut"])
+    omega, evec = phonons(model, q, dipole=ew if polar is not None and polar.get("lo_to") else None)
     gw = g_wannier(model, k, q)
     if polar is not None:
-        lr = frohlich(model, q, **polar)                         # (nq, nm)
+        lr = frohlich(model, q, **ew)                            # (nq, nm)
         eye = torch.eye(nw, dtype=C128)
         gw = gw + lr[None, :, :, None, None] * eye
     gh = band_basis(gw, u_kq, u_k)

@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
-from .units import HBAR_EV_FS, HBAR2_AMU_A2, KB_EV, SQRT_PI, TWO_PI
+from .units import E2_4PIEPS0, HBAR_EV_FS, HBAR2_AMU_A2, KB_EV, SQRT_PI, TWO_PI
 
 F64 = torch.float64
 C128 = torch.complex128
@@ -76,20 +78,74 @@ def bands(model, k, velocity=False, deg_tol=1e-4):
 
 # ---------------------------------------------------------------- phonons
 
-def dynamical_matrix(model, q):
+def dipole_matrix(model, q, alpha_ewald, gcut):
+    """Long-range dipole-dipole part of the force constants in reciprocal space
+    (the polar correction the paper takes from Gonze & Lee 1997, Sec. 2.3),
+    eV/Angstrom^2, no mass factor:
+
+      D^dd_{ka,k'b}(q) = (4 pi e^2/(4 pi eps0) / Omega) [
+            sum_{G, q+G != 0, |q+G| < gcut} T_kk'(q+G)_ab e^{i (q+G).(tau_k - tau_k')}
+          - delta_kk' sum_k'' sum_{G != 0, |G| < gcut} T_kk''(G)_ab e^{i G.(tau_k - tau_k'')} ],
+      T_kk'(K)_ab = [K.Z*_k]_a [K.Z*_k']_b e^{-K.eps.K/(4 Lambda)} / (K.eps.K).
+
+    The phase (q+G).(tau_k - tau_k') is the one of D(q) = sum_R e^{iq.R} C(R)
+    with C_kk'(R) coupling kappa in cell 0 to kappa' in cell R.  q is brought to
+    [-1/2,1/2)^3 first, as for the Froehlich term; the subtracted q = 0 sum keeps
+    the acoustic sum rule."""
+    q = t64(q)
+    lat = t64(model.lattice)
+    bvec = TWO_PI * torch.linalg.inv(lat).T
+    zs = t64(model.zstar)
+    eps = t64(model.eps_inf)
+    tau = t64(model.tau)
+    nat = tau.shape[0]
+    omega_cell = abs(float(torch.linalg.det(lat)))
+    pref = 4.0 * math.pi * E2_4PIEPS0 / omega_cell
+    mmax = int(math.ceil((gcut + float(torch.linalg.norm(bvec, dim=1).sum())) *
+                         float(torch.linalg.norm(lat, dim=1).max()) / TWO_PI)) + 1
+    rng = torch.arange(-mmax, mmax + 1, dtype=F64)
+    gvec = torch.stack(torch.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3) @ bvec
+
+    def block_sum(kv):
+        # sum over the vectors kv of T_kk'(K) e^{i K.(tau_k - tau_k')}, (nat,3,nat,3)
+        norm = torch.linalg.norm(kv, dim=1)
+        keep = (norm < gcut) & (norm > 1e-12)
+        kv = kv[keep]
+        kek = torch.einsum("ga,ab,gb->g", kv, eps, kv)
+        damp = torch.exp(-kek / (4.0 * alpha_ewald)) / kek
+        kz = torch.einsum("gb,kba->gka", kv, zs)                  # [K.Z*_k]_a
+        ph = torch.exp(1j * (kv @ tau.T))                         # e^{i K.tau_k}
+        kzc = kz.to(C128) * ph[:, :, None]
+        return torch.einsum("g,gka,glb->kalb", damp.to(C128), kzc, kzc.conj())
+
+    corr = block_sum(gvec).sum(dim=2)                             # (nat,3,3): sum over k''
+    qr = q - torch.round(q)
+    out = torch.zeros((q.shape[0], 3 * nat, 3 * nat), dtype=C128)
+    for iq in range(q.shape[0]):
+        blk = block_sum((qr[iq] @ bvec)[None, :] + gvec)
+        for k in range(nat):
+            blk[k, :, k, :] -= corr[k]
+        out[iq] = pref * blk.reshape(3 * nat, 3 * nat)
+    return out
+
+
+def dynamical_matrix(model, q, dipole=None):
     """D(q) = sum_Rp w e^{iq.Rp} C(Rp) / sqrt(M_kappa M_kappa')  (Eq. IFC2, with
-    the mass factor the force constants of Eq. IFC1 leave out)."""
+    the mass factor the force constants of Eq. IFC1 leave out), plus the
+    dipole-dipole part when dipole = dict(alpha_ewald, gcut) is given."""
     p = phases(q, model.rp_ph) * t64(model.w_rp_ph)
     m = t64(model.mass).repeat_interleave(3)
     c = torch.as_tensor(model.ifc, dtype=F64).to(C128)
     d = torch.einsum("qr,rab->qab", p, c)
+    if dipole is not None:
+        d = d + dipole_matrix(model, q, **dipole)
     return d / torch.sqrt(m[:, None] * m[None, :])
 
 
-def phonons(model, q):
+def phonons(model, q, dipole=None):
     """Phonon energies hbar*omega_nu (eV, ascending in omega^2; a negative
     omega^2 gives a negative value) and eigenvectors e_nu (columns) of D(q)."""
-    d = dynamical_matrix(model, q)
+    d = dynamical_matrix(model, q, dipole)
     d = 0.5 * (d + d.mH)
     lam, e = torch.linalg.eigh(d)
     hw2 = HBAR2_AMU_A2 * lam
