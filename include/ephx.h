@@ -65,10 +65,14 @@ typedef struct ephx_table ephx_table;
  *   h   [n_re][nw][nw] complex           H_ij(Re)              (paper Eq. wannier_2)
  *   ifc [n_rp_ph][3nat][3nat] real       C_{k a, k' b}(Rp)     (Eq. IFC1, no mass factor)
  *   g   [n_re_g][n_rp_g][3nat][nw][nw] complex  g^{k a}_ij(Re,Rp) (Eq. eph_mat_wann), eV/Angstrom
- * Polar models (polar != 0) add the Froehlich term of Eq. e_ph_long with Born
- * charges zstar[nat][3][3] (index [kappa][beta][alpha]), dielectric tensor
- * eps_inf[3][3], Ewald parameter alpha_ewald (1/Angstrom^2) and cutoff gcut on
- * |q+G| (1/Angstrom). */
+ * Polar models (polar != 0) carry Born charges zstar[nat][3][3] (index
+ * [kappa][beta][alpha]), the dielectric tensor eps_inf[3][3], an Ewald parameter
+ * alpha_ewald (1/Angstrom^2) and a cutoff gcut on |q+G| (1/Angstrom).  Bit 0 of
+ * polar adds the Froehlich term of Eq. e_ph_long to g; bit 1 adds the
+ * dipole-dipole (LO-TO) part of the force constants to D(q) (Sec. 2.3, the
+ * reciprocal-space sum over K = q+G with the q = 0 sum subtracted on the
+ * diagonal blocks, so the acoustic sum rule holds; ifc is then the short-range
+ * part). */
 typedef struct {
     double lattice[3][3];      /* rows a_1, a_2, a_3 in Angstrom */
     int natoms;

@@ -70,7 +70,7 @@ class Model:
         if polar is not None:
             keep["zstar"] = f64(src.zstar)
             keep["eps"] = f64(src.eps_inf)
-            d.polar = 1
+            d.polar = 1 | (2 if polar.get("lo_to") else 0)
             d.zstar, d.eps_inf = host_ptr(keep["zstar"]), host_ptr(keep["eps"])
             d.alpha_ewald, d.gcut = float(polar["alpha_ewald"]), float(polar["gcut"])
         self._h = C.c_void_p()

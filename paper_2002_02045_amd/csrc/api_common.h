@@ -79,7 +79,9 @@ struct ephx_model {
     double* d_wg = nullptr;      // [n_re_g][n_rp_g] weight products, only if not all 1
     double* d_nrp_g = nullptr;   // -Rp then -Re as doubles (adjoint sums), created on first use
     double* d_nre_g = nullptr;
-    bool polar = false;
+    bool polar = false;          // Froehlich term in g
+    bool dipole = false;         // dipole-dipole (LO-TO) part of D(q)
+    double* d_dipcorr = nullptr; // [nat][3][3] complex sum-rule term
     double *d_bvec = nullptr, *d_tau = nullptr, *d_zstar = nullptr, *d_eps = nullptr;
     ephx::PolarDev pd{};
     std::vector<void*> owned;

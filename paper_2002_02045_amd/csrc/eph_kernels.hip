@@ -418,6 +418,67 @@ __global__ void k_frohlich(int nq, const double* __restrict__ q, PolarDev p, dou
     }
 }
 
+// Dipole-dipole (LO-TO) part of D(q), added to the mass-scaled D(q) before the
+// eigensolve.  One thread per (q, kappa, kappa') block:
+//   D_{ka,k'b} += minv_ka minv_k'b pref [ sum_{G, q+G != 0, |q+G| < gcut}
+//        [K.Z_k]_a [K.Z_k']_b e^{-K.eps.K/(4 Lambda)}/(K.eps.K) e^{i K.(tau_k - tau_k')}
+//        - delta_kk' corr_k(a,b) ],  K = q + G, q brought to [-1/2,1/2)^3,
+// with corr the q = 0 sum over G != 0 and all k'' (acoustic sum rule).
+__global__ void k_dipole_add(int nq, const double* __restrict__ q, PolarDev p, const double* __restrict__ corr,
+                             const double* __restrict__ minv, double* __restrict__ D) {
+    const int nat = p.nat, nm = 3 * nat;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nq * nat * nat) return;
+    const int iq = (int)(t / (nat * nat)), k1 = (int)(t % (nat * nat)) / nat, k2 = (int)(t % nat);
+    double qr[3];
+    for (int d = 0; d < 3; ++d) qr[d] = q[3 * iq + d] - rint(q[3 * iq + d]);
+    const double dt[3] = {p.tau[3 * k1] - p.tau[3 * k2], p.tau[3 * k1 + 1] - p.tau[3 * k2 + 1],
+                          p.tau[3 * k1 + 2] - p.tau[3 * k2 + 2]};
+    double are[9] = {0}, aim[9] = {0};
+    for (int m0 = -p.mmax[0]; m0 <= p.mmax[0]; ++m0)
+        for (int m1 = -p.mmax[1]; m1 <= p.mmax[1]; ++m1)
+            for (int m2 = -p.mmax[2]; m2 <= p.mmax[2]; ++m2) {
+                double v[3];
+                for (int d = 0; d < 3; ++d)
+                    v[d] = (qr[0] + m0) * p.bvec[d] + (qr[1] + m1) * p.bvec[3 + d] + (qr[2] + m2) * p.bvec[6 + d];
+                const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (!(nrm < p.gcut) || !(nrm > 1e-12)) continue;
+                double kek = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b2 = 0; b2 < 3; ++b2) kek += v[a] * p.eps[3 * a + b2] * v[b2];
+                const double damp = exp(-kek / (4.0 * p.alpha)) / kek;
+                double sn, cs;
+                sincos(v[0] * dt[0] + v[1] * dt[1] + v[2] * dt[2], &sn, &cs);
+                double z1[3], z2[3];
+                for (int a = 0; a < 3; ++a) {
+                    z1[a] = z2[a] = 0.0;
+                    for (int b2 = 0; b2 < 3; ++b2) {
+                        z1[a] += v[b2] * p.zstar[(k1 * 3 + b2) * 3 + a];
+                        z2[a] += v[b2] * p.zstar[(k2 * 3 + b2) * 3 + a];
+                    }
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b2 = 0; b2 < 3; ++b2) {
+                        const double w = damp * z1[a] * z2[b2];
+                        are[3 * a + b2] += w * cs;
+                        aim[3 * a + b2] += w * sn;
+                    }
+            }
+    double* dq = D + (long)iq * nm * nm * 2;
+    for (int a = 0; a < 3; ++a)
+        for (int b2 = 0; b2 < 3; ++b2) {
+            double re = are[3 * a + b2], im = aim[3 * a + b2];
+            if (k1 == k2) {
+                re -= corr[2 * ((k1 * 3 + a) * 3 + b2)];
+                im -= corr[2 * ((k1 * 3 + a) * 3 + b2) + 1];
+            }
+            const int r = 3 * k1 + a, c = 3 * k2 + b2;
+            const double s = p.pref * minv[r] * minv[c];
+            dq[2 * ((long)r * nm + c)] += s * re;
+            dq[2 * ((long)r * nm + c) + 1] += s * im;
+        }
+}
+
 // Velocities: one thread per (k, alpha).  M = U^dag dH_a U restricted to
 // degenerate groups; the group block is diagonalised by a serial cyclic
 // Jacobi (group blocks are tiny), eigenvalues sorted ascending in the group.
@@ -574,6 +635,14 @@ void rates_finish(int nkb, int nw, int nm, const double* acc, double* gamma, dou
     const int n = nkb * nw;
     hipLaunchKernelGGL(k_rates_finish, dim3((n + 127) / 128), dim3(128), 0, st, nkb, nw, nm, acc, gamma, gmode);
     check_launch("rates_finish");
+}
+
+void dipole_add(int nq, const double* q, const PolarDev& p, const double* corr, const double* minv, double* D,
+                hipStream_t st) {
+    const long n = (long)nq * p.nat * p.nat;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_dipole_add, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, nq, q, p, corr, minv, D);
+    check_launch("dipole_add");
 }
 
 void frohlich(int nq, const double* q, const PolarDev& p, double* lr, hipStream_t st) {

@@ -356,8 +356,9 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
             std::vector<double> minv(nm);
             for (int a = 0; a < nm; ++a) minv[a] = 1.0 / std::sqrt(d->mass[a / 3]);
             m->d_minv = (double*)up(minv.data(), nm * sizeof(double));
-            m->polar = d->polar != 0;
-            if (m->polar) {
+            m->polar = (d->polar & 1) != 0;
+            m->dipole = (d->polar & 2) != 0;
+            if (d->polar != 0) {
                 m->d_bvec = (double*)up(m->bvec, 9 * sizeof(double));
                 m->d_tau = (double*)up(d->tau, 3 * nat * sizeof(double));
                 m->d_zstar = (double*)up(d->zstar, 9 * nat * sizeof(double));
@@ -380,6 +381,44 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                     const double al = std::sqrt(m->lattice[3 * i] * m->lattice[3 * i] + m->lattice[3 * i + 1] * m->lattice[3 * i + 1] +
                                                 m->lattice[3 * i + 2] * m->lattice[3 * i + 2]);
                     p.mmax[i] = (int)std::ceil((d->gcut + 0.5 * bsum) * al / (2.0 * kPi)) + 1;
+                }
+                if (m->dipole) {
+                    // q = 0 sum over G != 0 and all k'' of the dipole-dipole blocks
+                    std::vector<double> corr(2 * 9 * nat, 0.0);
+                    for (int m0 = -p.mmax[0]; m0 <= p.mmax[0]; ++m0)
+                        for (int m1 = -p.mmax[1]; m1 <= p.mmax[1]; ++m1)
+                            for (int m2 = -p.mmax[2]; m2 <= p.mmax[2]; ++m2) {
+                                double v[3];
+                                for (int c = 0; c < 3; ++c)
+                                    v[c] = m0 * m->bvec[c] + m1 * m->bvec[3 + c] + m2 * m->bvec[6 + c];
+                                const double nrm = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                                if (!(nrm < d->gcut) || !(nrm > 1e-12)) continue;
+                                double kek = 0.0;
+                                for (int a = 0; a < 3; ++a)
+                                    for (int b2 = 0; b2 < 3; ++b2) kek += v[a] * d->eps_inf[3 * a + b2] * v[b2];
+                                const double damp = std::exp(-kek / (4.0 * d->alpha_ewald)) / kek;
+                                for (int k1 = 0; k1 < nat; ++k1) {
+                                    double z1[3];
+                                    for (int a = 0; a < 3; ++a) {
+                                        z1[a] = 0.0;
+                                        for (int b2 = 0; b2 < 3; ++b2) z1[a] += v[b2] * d->zstar[(k1 * 3 + b2) * 3 + a];
+                                    }
+                                    for (int k2 = 0; k2 < nat; ++k2) {
+                                        double z2[3], arg = 0.0;
+                                        for (int a = 0; a < 3; ++a) {
+                                            z2[a] = 0.0;
+                                            for (int b2 = 0; b2 < 3; ++b2) z2[a] += v[b2] * d->zstar[(k2 * 3 + b2) * 3 + a];
+                                            arg += v[a] * (d->tau[3 * k1 + a] - d->tau[3 * k2 + a]);
+                                        }
+                                        for (int a = 0; a < 3; ++a)
+                                            for (int b2 = 0; b2 < 3; ++b2) {
+                                                corr[2 * ((k1 * 3 + a) * 3 + b2)] += damp * z1[a] * z2[b2] * std::cos(arg);
+                                                corr[2 * ((k1 * 3 + a) * 3 + b2) + 1] += damp * z1[a] * z2[b2] * std::sin(arg);
+                                            }
+                                    }
+                                }
+                            }
+                    m->d_dipcorr = (double*)up(corr.data(), corr.size() * sizeof(double));
                 }
             }
         } catch (...) {
@@ -427,6 +466,7 @@ void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double*
         const int n = std::min(chunk, nq - q0);
         double* dq = (double*)m->ws.get(tag + ".dq", (size_t)n * nm2 * 16);
         phase_gemm_f64(n, nm2, m->n_rp_ph, 1, q + 3L * q0, nullptr, m->d_rp_ph, m->d_cm, 0, dq, 0, st);
+        if (m->dipole) dipole_add(n, q + 3L * q0, m->pd, m->d_dipcorr, m->d_minv, dq, st);
         eig_herm(n, nm, dq, 0, nm2, omega + (size_t)q0 * nm, evec ? evec + (size_t)q0 * nm2 * 2 : nullptr, st);
     }
     phonon_omega((long)nq * nm, omega, st);

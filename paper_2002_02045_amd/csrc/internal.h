@@ -163,6 +163,10 @@ struct PolarDev {
     int nat, mmax[3];
 };
 void frohlich(int nq, const double* q, const PolarDev& p, double* lr, hipStream_t st);
+// D[q] += dipole-dipole part of the mass-scaled dynamical matrix (LO-TO);
+// corr: [nat][3][3] complex q = 0 sum-rule term; D [nq][3nat][3nat] complex.
+void dipole_add(int nq, const double* q, const PolarDev& p, const double* corr, const double* minv, double* D,
+                hipStream_t st);
 
 // Band velocities from H(k) derivatives: dh [nk][3][nw][nw] complex, u, eps -> vel [nk][nw][3]
 void band_velocity(int nk, int nw, const double* dh, const double* u, const double* eps,

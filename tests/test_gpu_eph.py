@@ -214,3 +214,38 @@ def test_rates_vjp_parity_and_finite_difference(lib, tiny):
     gam = lib.RatesFunction.apply(gt, dm, k, q, p)
     (gam * torch.as_tensor(lam, device="cuda")).sum().backward()
     assert torch.allclose(gt.grad.cpu(), gb)
+
+
+def test_lo_to_phonons_gkq_rates_parity(lib):
+    """Dipole-dipole (LO-TO) part of D(q) on the GPU vs the oracle: phonons
+    (including Gamma and a small q, where the splitting is non-analytic), and
+    |g|^2 and rates, which see it through omega and e."""
+    _say("LO-TO parity (GaAs-like, 4^3 set, nw=4)")
+    m = synth.make_config_model("gaas", n_grid=4, nw=4)
+    a = synth.models.A_GAAS
+    pol = dict(alpha_ewald=(2 * np.pi / a) ** 2, gcut=4 * 2 * np.pi / a, lo_to=True)
+    dip = dict(alpha_ewald=pol["alpha_ewald"], gcut=pol["gcut"])
+    dm = lib.Model(m, polar=pol)
+    q = np.vstack([np.zeros((1, 3)), 1e-3 * np.array([[0.3, -0.2, 0.1]]), synth.random_points(131, 60)])
+    om, ev = lib.phonons(dm, q)
+    oo, _ = interp.phonons(m, q, dipole=dip)
+    wmax = float(oo.abs().max())
+    assert float((om.cpu()[1:] - oo[1:]).abs().max()) <= 1e-10 * wmax
+    assert float(om.cpu()[0, :3].abs().max()) <= 1e-6 * wmax
+    assert float((om.cpu()[0, 3:] - oo[0, 3:]).abs().max()) <= 1e-10 * wmax
+    d = interp.dynamical_matrix(m, q, dipole=dip)
+    lam = om.cpu().sign() * om.cpu() ** 2 / 0.004180159280496722
+    res = d @ ev.cpu() - ev.cpu() * lam[:, None, :]
+    assert float(res.abs().max()) <= 1e-10 * float(lam.abs().max())
+    k = synth.random_points(132, 6)
+    qq = q[1:40]
+    blk = eph.eph_pipeline(m, k, qq, polar=pol)
+    ref = group_sums_g2(blk["g"].abs() ** 2, blk["eps_k"], blk["eps_kq"], blk["omega"])
+    g2 = lib.gkq(dm, k, qq, precision="fp64")
+    got = group_sums_g2(g2.double().cpu().numpy(), blk["eps_k"], blk["eps_kq"], blk["omega"])
+    emax, _ = g2_error(got, ref)
+    _say("  LO-TO |g|^2 error fp64: %.3e" % emax)
+    assert emax <= 1e-10
+    go, _ = eph.rates(m, k, qq, temp=300.0, mu=0.0, sigma=0.05, polar=pol)
+    g, _ = lib.rates(dm, k, qq, lib.Params(temp=300.0, mu=0.0, sigma=0.05))
+    assert rate_error(g.cpu().numpy(), go.numpy()) <= 1e-10
