@@ -19,5 +19,6 @@ from .models import (  # noqa: F401
     make_model,
     make_config_model,
     random_points,
+    cauchy_points,
     CONFIGS,
 )

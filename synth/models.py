@@ -259,6 +259,21 @@ def random_positions(seed: int, nat: int, a: float, min_sep: float) -> np.ndarra
     return np.array(pos)
 
 
+def cauchy_points(seed: int, n: int, gamma: float):
+    """n q points concentrated near Gamma for importance sampling of the q sum
+    (Sec. 4.3): each reduced coordinate from a Cauchy distribution of scale
+    gamma wrapped onto [-1/2, 1/2).  Returns (q, w) with w = 1/(n p(q)), p the
+    product of the wrapped densities p(x) = sinh(2 pi gamma)/(cosh(2 pi gamma) -
+    cos(2 pi x)), so that sum_q w f(q) estimates the zone average of f."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n, 3))
+    x = gamma * np.tan(np.pi * (u - 0.5))
+    x = x - np.floor(x + 0.5)
+    s, c = np.sinh(2 * np.pi * gamma), np.cosh(2 * np.pi * gamma)
+    p = np.prod(s / (c - np.cos(2 * np.pi * x)), axis=1)
+    return x, 1.0 / (n * p)
+
+
 SEED_BASE = 20020205
 
 # Workload definitions.  Physical parameters follow the readings listed in the

@@ -249,3 +249,41 @@ def test_lo_to_phonons_gkq_rates_parity(lib):
     go, _ = eph.rates(m, k, qq, temp=300.0, mu=0.0, sigma=0.05, polar=pol)
     g, _ = lib.rates(dm, k, qq, lib.Params(temp=300.0, mu=0.0, sigma=0.05))
     assert rate_error(g.cpu().numpy(), go.numpy()) <= 1e-10
+
+
+def test_cauchy_sampled_rates(lib):
+    """Importance sampling of the q sum (Sec. 4.3): Cauchy points around Gamma
+    with weights 1/(n p(q)).  Parity of the weighted polar rates vs the oracle,
+    then agreement of the Cauchy and uniform Monte Carlo estimates over
+    independent seeds (both unbiased) on the GPU alone."""
+    _say("Cauchy-sampled rates (GaAs-like with LO-TO, nw=4)")
+    m = synth.make_config_model("gaas", n_grid=4, nw=4)
+    a = synth.models.A_GAAS
+    pol = dict(alpha_ewald=(2 * np.pi / a) ** 2, gcut=4 * 2 * np.pi / a, lo_to=True)
+    dm = lib.Model(m, polar=pol)
+    k = np.array([[0.01, 0.02, -0.015], [0.05, 0.0, 0.0], [0.1, 0.1, 0.1]])
+    par = dict(temp=300.0, mu=0.0, sigma=0.05)
+    p = lib.Params(omega_cut=1e-4, **par)
+    q, w = synth.cauchy_points(141, 60, 0.05)
+    go, _ = eph.rates(m, k, q, q_weights=w, polar=pol, **par)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        g, _ = lib.rates(dm, k, q, p, precision=prec, q_weights=w)
+        err = rate_error(g.cpu().numpy(), go.numpy())
+        _say("  weighted rates error %s: %.3e" % (prec, err))
+        assert err <= tol
+    n, seeds = 16384, 6
+    est_c, est_u = [], []
+    for s in range(seeds):
+        qc, wc = synth.cauchy_points(1000 + s, n, 0.05)
+        est_c.append(lib.rates(dm, k, qc, p, q_weights=wc, mode_resolved=False)[0].cpu().numpy())
+        est_u.append(lib.rates(dm, k, synth.random_points(2000 + s, n), p, mode_resolved=False)[0].cpu().numpy())
+    est_c, est_u = np.array(est_c), np.array(est_u)
+    mc, mu_ = est_c.mean(0), est_u.mean(0)
+    se = np.sqrt(est_c.var(0, ddof=1) / seeds + est_u.var(0, ddof=1) / seeds)
+    live = mu_ > 1e-3 * mu_.max()
+    assert live.any()
+    z = np.abs(mc - mu_)[live] / np.maximum(se[live], 1e-12 * mu_.max())
+    ratio = est_u.var(0, ddof=1)[live] / np.maximum(est_c.var(0, ddof=1)[live], 1e-300)
+    _say("  states %d, max |z| %.2f, variance ratio uniform/Cauchy median %.2f"
+         % (int(live.sum()), float(z.max()), float(np.median(ratio))))
+    assert float(z.max()) <= 5.0
