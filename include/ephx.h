@@ -56,6 +56,10 @@ extern "C" {
 #define EPHX_BF16X3 2
 #define EPHX_BF16X6 3
 
+/* Time steppers of ephx_dynamics_field (Sec. 2.1, carrier dynamics) */
+#define EPHX_RK4 0
+#define EPHX_EULER 1
+
 typedef struct ephx_model ephx_model;
 typedef struct ephx_table ephx_table;
 
@@ -213,6 +217,23 @@ int ephx_collision(ephx_table* t, const double* f, double* i_out, void* stream);
  * device [n_steps/ckpt_every + 1][S] (row 0 = f0). */
 int ephx_dynamics(ephx_table* t, const double* f0, double dt, int n_steps, int ckpt_every,
                   double* f_out, double* ckpts, void* stream);
+
+/* Carrier dynamics with an external field and a choice of stepper, Eq. BTE_E:
+ *   df_s/dt = I[f]_s + (|e|/hbar) E . grad_k f_s
+ * (the electron's charge is -|e|, so a distribution drifts in k at -|e|E/hbar).
+ * grad_k f is the central difference along the grid's reduced directions,
+ * band by band: with a_i the lattice rows and N_i the grid,
+ *   E . grad_k f_s = sum_i (E . a_i / 2 pi) (N_i/2) (f[s + e_i] - f[s - e_i]),
+ * where a neighbour that is not a state of the table counts as empty (f = 0).
+ * efield: host [3] in V/Angstrom, or NULL for E = 0.  method: EPHX_RK4 (the
+ * classic four stages) or EPHX_EULER (first order, one collision pass per
+ * step).  f0, f_out, ckpts as for ephx_dynamics; with EPHX_RK4 and E = 0 the
+ * result equals ephx_dynamics'.  The neighbour table (24 bytes per state) is
+ * built on the first call with a field.  ephx_dynamics_vjp differentiates the
+ * RK4, E = 0 dynamics only. */
+int ephx_dynamics_field(ephx_table* t, const double* f0, double dt, int n_steps, int method,
+                        const double* efield, int ckpt_every, double* f_out, double* ckpts,
+                        void* stream);
 
 /* Vector-Jacobian product of the collision integral: given f and lambda
  * (device [S]), f_bar = lambda^T dI/df (device [S]) and, if s_bar is not

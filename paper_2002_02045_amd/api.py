@@ -253,14 +253,23 @@ class PairTable:
         check(lib.ephx_collision(self._h, ptr(f), ptr(out), stream_ptr()))
         return out
 
-    def dynamics(self, f0, dt, n_steps, ckpt_every=0):
+    def dynamics(self, f0, dt, n_steps, ckpt_every=0, method="rk4", efield=None):
+        """f after n_steps steps of dt fs ("rk4" or "euler"), with an optional
+        field (V/Angstrom, Cartesian); checkpoints every ckpt_every steps."""
         f0 = torch.as_tensor(f0, dtype=F64, device="cuda").contiguous()
         out = torch.empty(self.S, dtype=F64, device="cuda")
         ck = None
         if ckpt_every > 0:
             ck = torch.empty((n_steps // ckpt_every + 1, self.S), dtype=F64, device="cuda")
-        check(lib.ephx_dynamics(self._h, ptr(f0), float(dt), int(n_steps), int(ckpt_every), ptr(out), ptr(ck),
-                                stream_ptr()))
+        meth = {"rk4": 0, "euler": 1}[method]
+        if efield is None and meth == 0:
+            check(lib.ephx_dynamics(self._h, ptr(f0), float(dt), int(n_steps), int(ckpt_every), ptr(out), ptr(ck),
+                                    stream_ptr()))
+        else:
+            arr = None if efield is None else (C.c_double * 3)(*[float(x) for x in efield])
+            ef = None if arr is None else C.addressof(arr)
+            check(lib.ephx_dynamics_field(self._h, ptr(f0), float(dt), int(n_steps), meth, ef, int(ckpt_every),
+                                          ptr(out), ptr(ck), stream_ptr()))
         return out, ck
 
     def collision_vjp(self, f, lam, want_s=True):

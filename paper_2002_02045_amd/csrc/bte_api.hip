@@ -37,6 +37,7 @@ struct ephx_table {
     std::vector<int32_t> h_kc, h_band;   // host copies of the states
     int32_t* d_tet = nullptr;            // [n_tet][4] tetrahedra of window states, built on first use
     int n_tet = -1;
+    int32_t* d_nbr = nullptr;            // [S][6] grid neighbours of each state (field drift), built on first use
     ~ephx_table() {
         ws.release();
         for (void* p : owned)
@@ -90,8 +91,15 @@ void one_pass(ephx_table* t, const StreamPlan& pl, const void* mat, VecPtrs x, V
 }
 
 // I at occupations y; optional RK4 stage update
+// Field drift of the stage update: neighbour table and coefficients
+struct Field {
+    const int32_t* nbr = nullptr;
+    double dc[3] = {0.0, 0.0, 0.0};
+};
+
 void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, int acc_init, double w_acc,
-                    const double* f_base, double a_next, double* f_next, hipStream_t st) {
+                    const double* f_base, double a_next, double* f_next, hipStream_t st,
+                    const Field* fld = nullptr) {
     const int S = t->S;
     const StreamPlan pl = plan_for(t, 1, 1);
     double* omf = (double*)t->ws.get("c.omf", S * 8);
@@ -115,6 +123,8 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
     cf.f_base = f_base;
     cf.a_next = a_next;
     cf.f_next = f_next;
+    cf.nbr = fld ? fld->nbr : nullptr;
+    for (int d = 0; d < 3; ++d) cf.dc[d] = fld ? fld->dc[d] : 0.0;
     StageTimer tm("collision_finish", st);
     collision_finish(cf, st);
 }
@@ -143,12 +153,46 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
 
 // One RK4 step f -> f_new; stage inputs optionally saved (Y1..Y4)
 void rk4_step(ephx_table* t, const double* f, double dt, double* f_new, double* y2, double* y3, double* y4,
-              hipStream_t st) {
+              hipStream_t st, const Field* fld = nullptr) {
     // stage 1 at f: acc = f + dt/6 k1 ; y2 = f + dt/2 k1
-    collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st);
-    collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st);
-    collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st);
-    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st);
+    collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st, fld);
+    collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st, fld);
+    collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st, fld);
+    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st, fld);
+}
+
+// One explicit Euler step f -> f_new = f + dt (I[f] + drift)
+void euler_step(ephx_table* t, const double* f, double dt, double* f_new, hipStream_t st, const Field* fld) {
+    collision_eval(t, f, nullptr, f_new, 1, dt, f, 0.0, nullptr, st, fld);
+}
+
+// Neighbours of each state along +/- each reduced direction, same band, on
+// the periodic grid; -1 where that state is not in the table.
+void ensure_neighbours(ephx_table* t) {
+    if (t->d_nbr) return;
+    const int S = t->S;
+    const long n[3] = {t->n1, t->n2, t->n3};
+    auto lin = [&](const long* c) {
+        long r = 0;
+        for (int d = 0; d < 3; ++d) r = r * n[d] + ((c[d] % n[d]) + n[d]) % n[d];
+        return r;
+    };
+    std::unordered_map<long, int> state;
+    for (int s = 0; s < S; ++s) {
+        const long c[3] = {t->h_kc[3 * s], t->h_kc[3 * s + 1], t->h_kc[3 * s + 2]};
+        state[lin(c) * t->nw + t->h_band[s]] = s;
+    }
+    std::vector<int32_t> nbr((size_t)S * 6, -1);
+    for (int s = 0; s < S; ++s)
+        for (int d = 0; d < 3; ++d)
+            for (int j = 0; j < 2; ++j) {
+                long c[3] = {t->h_kc[3 * s], t->h_kc[3 * s + 1], t->h_kc[3 * s + 2]};
+                c[d] += j == 0 ? 1 : -1;
+                auto it = state.find(lin(c) * t->nw + t->h_band[s]);
+                if (it != state.end()) nbr[(size_t)s * 6 + 2 * d + j] = it->second;
+            }
+    t->d_nbr = (int32_t*)t->alloc(nbr.size() * 4);
+    hip_check(hipMemcpy(t->d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
 }
 
 void require_ready(ephx_table* t) {
@@ -431,13 +475,34 @@ extern "C" int ephx_collision(ephx_table* t, const double* f, double* i_out, voi
 
 extern "C" int ephx_dynamics(ephx_table* t, const double* f0, double dt, int n_steps, int ckpt_every, double* f_out,
                              double* ckpts, void* stream) {
+    return ephx_dynamics_field(t, f0, dt, n_steps, EPHX_RK4, nullptr, ckpt_every, f_out, ckpts, stream);
+}
+
+extern "C" int ephx_dynamics_field(ephx_table* t, const double* f0, double dt, int n_steps, int method,
+                                   const double* efield, int ckpt_every, double* f_out, double* ckpts, void* stream) {
     return guarded([&] {
         require_ready(t);
         require(f0 && f_out, "dynamics: null array");
         require(n_steps >= 0 && std::isfinite(dt), "dynamics: bad step count or dt");
         require(!ckpts || ckpt_every >= 1, "dynamics: ckpt_every must be >= 1 with checkpoints");
+        require(method == EPHX_RK4 || method == EPHX_EULER, "dynamics: method must be EPHX_RK4 or EPHX_EULER");
         hipStream_t st = (hipStream_t)stream;
         const int S = t->S;
+        Field fld;
+        const bool field = efield && (efield[0] != 0.0 || efield[1] != 0.0 || efield[2] != 0.0);
+        if (field) {
+            require(std::isfinite(efield[0]) && std::isfinite(efield[1]) && std::isfinite(efield[2]),
+                    "dynamics: non-finite field");
+            ensure_neighbours(t);
+            fld.nbr = t->d_nbr;
+            const int nd[3] = {t->n1, t->n2, t->n3};
+            for (int d = 0; d < 3; ++d) {
+                const double* a = t->m->lattice + 3 * d;
+                const double ea = efield[0] * a[0] + efield[1] * a[1] + efield[2] * a[2];
+                fld.dc[d] = ea / (2.0 * kPi * kHbarEvFs) * (0.5 * nd[d]);
+            }
+        }
+        const Field* fp = field ? &fld : nullptr;
         double* fa = (double*)t->ws.get("d.fa", S * 8);
         double* fb = (double*)t->ws.get("d.fb", S * 8);
         double* y2 = (double*)t->ws.get("d.y2", S * 8);
@@ -446,7 +511,8 @@ extern "C" int ephx_dynamics(ephx_table* t, const double* f0, double dt, int n_s
         hip_check(hipMemcpyAsync(fa, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
         if (ckpts) hip_check(hipMemcpyAsync(ckpts, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
         for (int n = 0; n < n_steps; ++n) {
-            rk4_step(t, fa, dt, fb, y2, y3, y4, st);
+            if (method == EPHX_RK4) rk4_step(t, fa, dt, fb, y2, y3, y4, st, fp);
+            else euler_step(t, fa, dt, fb, st, fp);
             std::swap(fa, fb);
             if (ckpts && (n + 1) % ckpt_every == 0)
                 hip_check(hipMemcpyAsync(ckpts + (size_t)((n + 1) / ckpt_every) * S, fa, S * 8,

@@ -355,8 +355,16 @@ __global__ void k_collision_finish(CollisionFinish cf) {
     const double i = -cf.c * (f * r - (1.0 - f) * c);
     if (cf.i_out) cf.i_out[s] = i;
     if (cf.acc) {
-        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * i;
-        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * i;
+        double rhs = i;
+        if (cf.nbr) {
+            const int32_t* nb = cf.nbr + 6L * s;
+            for (int d = 0; d < 3; ++d) {
+                const int p = nb[2 * d], m = nb[2 * d + 1];
+                rhs += cf.dc[d] * ((p >= 0 ? cf.f[p] : 0.0) - (m >= 0 ? cf.f[m] : 0.0));
+            }
+        }
+        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * rhs;
+        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * rhs;
     }
 }
 

@@ -283,6 +283,11 @@ struct CollisionFinish {
     const double* f_base;
     double a_next;
     double* f_next;       // may be nullptr
+    // field drift added to I in the stage update (not in i_out): nbr [S][6]
+    // holds the +/- neighbour along each reduced direction (-1 = empty state),
+    // dc[i] = (|e|/hbar)(E . a_i)/(2 pi) (N_i/2); nbr nullptr = no field
+    const int32_t* nbr;
+    double dc[3];
 };
 void collision_finish(const CollisionFinish& cf, hipStream_t st);
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,

@@ -15,7 +15,7 @@ import torch
 
 import synth
 from helpers import group_labels
-from oracle import bte, grad, grid, interp
+from oracle import bte, drift, grad, grid, interp
 
 pytestmark = pytest.mark.gpu
 
@@ -168,6 +168,37 @@ def test_dynamics_parity_and_checkpoints(lib, big_case, big_table):
     for i, s in enumerate(saved):
         assert float((ck[i].cpu() - s).abs().max()) <= 1e-10 * float(s.abs().max())
     assert abs(float(got.sum()) - f0.sum()) <= 1e-12 * f0.sum()
+
+
+@pytest.mark.parametrize("method", ["rk4", "euler"])
+def test_field_dynamics_parity(lib, tiny, big_case, big_table, method):
+    """Eq. BTE_E with E != 0: collisions plus the grid drift term, RK4 and
+    Euler steppers, on the S=1030 window (its edge has empty neighbours)."""
+    _say("field dynamics S=1030 fp64, %s, 8 steps" % method)
+    m, _ = tiny
+    n, kk, bb, g2s, om, eps = big_case
+    E = np.array([2e-3, -1e-3, 1.5e-3])
+    e0 = float(eps.min())
+    f0 = 0.1 * np.exp(-((eps.numpy() - e0 - 0.1) / 0.1) ** 2)
+    nq = float(np.prod(n))
+    nbr = drift.neighbours(kk, bb, n)
+    assert (nbr >= 0).any() and (nbr < 0).any()
+    rhs = lambda x: (bte.collision(x, eps, g2s, om, n_q=nq, **PAR)
+                     + torch.as_tensor(drift.drift(x.numpy(), nbr, m.lattice, n, E)))
+    step = bte.rk4_step if method == "rk4" else bte.euler_step
+    ref, saved = bte.integrate(torch.as_tensor(f0), 1.0, 8, rhs, step=step, keep_every=4)
+    got, ck = big_table.dynamics(f0, 1.0, 8, ckpt_every=4, method=method, efield=E)
+    err = float((got.cpu() - ref).abs().max() / ref.abs().max())
+    _say("  field dynamics error %s: %.3e" % (method, err))
+    assert err <= 1e-10
+    for i, s in enumerate(saved):
+        assert float((ck[i].cpu() - s).abs().max()) <= 1e-10 * float(s.abs().max())
+    # the field moves carriers: the result differs from E = 0 well beyond tolerance
+    zero, _ = big_table.dynamics(f0, 1.0, 8, method=method, efield=[0.0, 0.0, 0.0])
+    assert float((zero.cpu() - ref).abs().max()) > 1e-6 * float(ref.abs().max())
+    if method == "rk4":
+        plain, _ = big_table.dynamics(f0, 1.0, 8)
+        assert torch.equal(zero, plain)
 
 
 def test_collision_vjp_parity(lib, tiny, small_case):
