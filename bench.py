@@ -247,13 +247,30 @@ def dynamics_bench(px, dm, model, args):
     nf, msf = px.timer_get("collision_finish")
     px.timer_reset()
     ld = (S + 63) // 64 * 64
-    alg_bytes = 4.0 * S * S                               # the FP32 collision matrix, read once
+    # the FP32 collision matrix is stored in energy order and tiles of state
+    # pairs further apart than omega_max + 6 sigma (exact zeros) are not read:
+    # the algorithmic bytes of a pass are the entries of the live tiles
+    live, n_live, n_tiles = tab.stream_info("collision")
+    alg_bytes = 4.0 * live
     achieved = alg_bytes / (ms / ns * 1e-3) / 1e9
     drift = abs(float(f1.sum() - f0.sum())) / float(f0.sum())
     if not np.isfinite(drift):
         raise RuntimeError("dynamics produced non-finite occupations")
-    log("dynamics: %.1f RK4 steps/s, collision_stream %.3f ms avg = %.0f GB/s (%.1f%% of HBM), number drift %.2e" % (
-        args.dyn_steps / dt, ms / ns, achieved, 100 * achieved / HBM_GBS, drift))
+    log("dynamics: %.1f RK4 steps/s, collision_stream %.3f ms avg = %.0f GB/s (%.1f%% of HBM) over %d of %d tiles "
+        "(%.3f of the dense matrix), number drift %.2e" % (
+            args.dyn_steps / dt, ms / ns, achieved, 100 * achieved / HBM_GBS, n_live, n_tiles, live / S ** 2, drift))
+    # Euler stepping in a field (Eq. BTE_E with E != 0): one collision pass
+    # and the grid drift per step
+    efield = [1e-4, 0.0, 0.0]                             # V/Angstrom (10 kV/cm)
+    tab.dynamics(f0, cfg["dt"], 2, method="euler", efield=efield)     # warmup, builds the neighbour table
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f2, _ = tab.dynamics(f0, cfg["dt"], args.dyn_steps, method="euler", efield=efield)
+    torch.cuda.synchronize()
+    dt_e = time.perf_counter() - t0
+    if not bool(torch.isfinite(f2).all()):
+        raise RuntimeError("field dynamics produced non-finite occupations")
+    log("dynamics: %.1f Euler steps/s with E = %g V/A along x" % (args.dyn_steps / dt_e, efield[0]))
     out = {
         "metric": "BTE collision steps/s (RK4 steps of the carrier dynamics)",
         "value": args.dyn_steps / dt, "unit": "RK4 steps/s", "steps": args.dyn_steps,
@@ -264,10 +281,12 @@ def dynamics_bench(px, dm, model, args):
         "roofline": {"bound": "hbm", "kernel": "collision_stream", "achieved": round(achieved, 1),
                      "peak": HBM_GBS, "unit": "GB/s", "frac": round(achieved / HBM_GBS, 4),
             "traffic": measured_traffic("k_stream<float, 1, 1>"), "traffic_unit": "HBM bytes per launch",
-                     "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5)},
+                     "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5),
+                     "dense_bytes": 4.0 * S * S, "live_tiles": n_live, "tiles": n_tiles},
         "collision_evals_per_s": ns / (1e-3 * (ms + msf)) if ms > 0 else None,
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,
+        "euler_field_steps_per_s": args.dyn_steps / dt_e, "euler_field_V_per_A": efield,
     }
     out["transport"] = transport_bench(px, dm, tab, kk, bb, ee, n, f1, cfg)
     tab.close()
@@ -304,17 +323,19 @@ def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
     t_pop = time.perf_counter() - t0
     px.timer_enable(False)
     n_st, ms_st = px.timer_get("transport_stream")
+    _, ms_build = px.timer_get("matrix_build")
     _, ms_tdf = px.timer_get("tdf_tetra")
     _, ms_pop = px.timer_get("population_tetra")
     px.timer_reset()
     S = len(kk)
-    alg = 4.0 * S * S
-    log("transport: ITA 10 iterations %.1f ms (stream %.3f ms avg = %.0f GB/s), TDF %d energies %.1f ms, "
-        "population %.1f ms; mu_xx %.4g cm^2/Vs, S_xx %.4g uV/K" % (
-            1e3 * t_ita, ms_st / n_st, alg / (ms_st / n_st * 1e-3) / 1e9, len(energies), 1e3 * t_tdf, 1e3 * t_pop,
+    alg = 4.0 * tab.stream_info("transport")[0]
+    log("transport: ITA 10 iterations %.1f ms (W build %.1f ms, stream %.3f ms avg = %.0f GB/s), TDF %d energies "
+        "%.1f ms, population %.1f ms; mu_xx %.4g cm^2/Vs, S_xx %.4g uV/K" % (
+            1e3 * t_ita, ms_build, ms_st / n_st, alg / (ms_st / n_st * 1e-3) / 1e9, len(energies), 1e3 * t_tdf,
+            1e3 * t_pop,
             float(mob[0, 0]), 1e6 * float(seebeck[0, 0])))
     return {
-        "ita_ms": round(1e3 * t_ita, 3), "ita_iterations": 10,
+        "ita_ms": round(1e3 * t_ita, 3), "ita_iterations": 10, "w_build_ms": round(ms_build, 3),
         "transport_stream_avg_ms": round(ms_st / n_st, 5),
         "transport_stream_gbs": round(alg / (ms_st / n_st * 1e-3) / 1e9, 1),
         "tdf_ms": round(1e3 * t_tdf, 3), "tdf_kernel_ms": round(ms_tdf, 3), "energies": len(energies),

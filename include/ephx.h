@@ -211,6 +211,18 @@ int ephx_collision_setup(ephx_table* t, const ephx_params* p, const double* mode
                          void* stream);
 int ephx_collision(ephx_table* t, const double* f, double* i_out, void* stream);
 
+/* Storage of the collision matrix (matrix 0, after ephx_collision_setup) or
+ * the transport matrix (matrix 1, after ephx_mobility): both are kept with
+ * rows and columns in ascending state energy, and the Gaussian delta of
+ * Eq. BTE_W is taken as zero beyond 6 sigma, so every block of state pairs
+ * whose energies differ by more than the largest phonon energy + 6 sigma is
+ * zero and is not read.  live_entries: matrix entries one pass reads (the
+ * collision pass, or one iteration of the iterative BTE); n_live_tiles of
+ * n_tiles tiles of up to 1024 columns are read.  A compaction of storage
+ * order only: results agree with the dense matrix up to summation order. */
+int ephx_table_stream_info(ephx_table* t, int matrix, long long* live_entries, int* n_live_tiles,
+                           int* n_tiles, void* stream);
+
 /* RK4 carrier dynamics df/dt = I[f] (Eq. BTE_E with E = 0, classic four-stage
  * Runge-Kutta): n_steps steps of dt fs from f0 (device [S]) into f_out (device
  * [S]).  If ckpts is not NULL it receives f after every ckpt_every steps,

@@ -75,6 +75,7 @@ _SIGS = {
     "ephx_collision": ([_P, _P, _P, _P], _I),
     "ephx_dynamics": ([_P, _P, _D, _I, _I, _P, _P, _P], _I),
     "ephx_dynamics_field": ([_P, _P, _D, _I, _I, _P, _I, _P, _P, _P], _I),
+    "ephx_table_stream_info": ([_P, _I, _P, _P, _P, _P], _I),
     "ephx_collision_vjp": ([_P, _P, _P, _P, _P, _P], _I),
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),
     "ephx_mobility": ([_P, _P, _P, _I, _P, _P, _P, _P], _I),

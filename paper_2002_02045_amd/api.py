@@ -272,6 +272,15 @@ class PairTable:
                                           ptr(out), ptr(ck), stream_ptr()))
         return out, ck
 
+    def stream_info(self, matrix="collision"):
+        """(entries read per pass, live tiles, tiles) of the energy-banded
+        collision ("collision") or transport ("transport") matrix."""
+        n = C.c_longlong(0)
+        a, b = C.c_int(0), C.c_int(0)
+        check(lib.ephx_table_stream_info(self._h, {"collision": 0, "transport": 1}[matrix], C.byref(n), C.byref(a),
+                                         C.byref(b), stream_ptr()))
+        return int(n.value), int(a.value), int(b.value)
+
     def collision_vjp(self, f, lam, want_s=True):
         f = torch.as_tensor(f, dtype=F64, device="cuda").contiguous()
         lam = torch.as_tensor(lam, dtype=F64, device="cuda").contiguous()

@@ -2,6 +2,7 @@
 // integral, RK4 dynamics and their adjoints, and the iterative linearised BTE.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
 #include <unordered_map>
 #include <vector>
@@ -38,6 +39,18 @@ struct ephx_table {
     int32_t* d_tet = nullptr;            // [n_tet][4] tetrahedra of window states, built on first use
     int n_tet = -1;
     int32_t* d_nbr = nullptr;            // [S][6] grid neighbours of each state (field drift), built on first use
+    // P and W are stored with rows and columns in ascending state energy; tiles
+    // of state pairs further apart than the band half-width are exact zeros
+    int32_t* d_perm = nullptr;           // [S] state of each matrix row/column
+    std::vector<double> h_esort;         // energies in that order
+    double omega_max = -1.0;             // largest phonon energy on the grid
+    double band[2] = {0.0, 0.0};         // half-widths of the stored P (0) and W (1)
+    int gen[2] = {0, 0};                 // rebuild counters of P and W
+    struct CachedPlan {
+        StreamPlan pl;
+        int gen;
+    };
+    std::map<int, CachedPlan> plans;     // key: matrix * 64 + na * 8 + nb
     ~ephx_table() {
         ws.release();
         for (void* p : owned)
@@ -82,12 +95,66 @@ double snap_edge(const std::vector<double>& e, double edge) {
     return 0.5 * (*(it - 1) + *it);
 }
 
-StreamPlan plan_for(const ephx_table* t, int na, int nb) { return stream_plan(t->S, t->f32 ? 1 : 0, na, nb); }
+// Energy order of the states and the largest phonon energy, once per table.
+void ensure_order(ephx_table* t, hipStream_t st) {
+    if (t->d_perm) return;
+    const int S = t->S;
+    std::vector<double> e(S);
+    const long nom = (long)t->n1 * t->n2 * t->n3 * t->nm;
+    std::vector<double> om(nom);
+    hip_check(hipMemcpyAsync(e.data(), t->d_eps, (size_t)S * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(om.data(), t->d_omega, (size_t)nom * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<int32_t> perm(S);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return e[a] < e[b]; });
+    t->h_esort.resize(S);
+    for (int i = 0; i < S; ++i) t->h_esort[i] = e[perm[i]];
+    double wmax = 0.0;
+    for (double w : om)
+        if (std::isfinite(w)) wmax = std::max(wmax, w);
+    t->omega_max = wmax;
+    t->d_perm = (int32_t*)t->alloc((size_t)std::max(1, S) * 4);
+    hip_check(hipMemcpy(t->d_perm, perm.data(), (size_t)S * 4, hipMemcpyHostToDevice), "hipMemcpy");
+}
 
-void one_pass(ephx_table* t, const StreamPlan& pl, const void* mat, VecPtrs x, VecPtrs y, double* rowp, double* colp,
-              hipStream_t st, const char* tag) {
+// Build P (matrix 0) or W (matrix 1) in energy order and record its band.
+void build_banded(ephx_table* t, int matrix, const ephx_params* p, const double* scale, void* out, hipStream_t st) {
+    ensure_order(t, st);
+    StageTimer tm("matrix_build", st);
+    build_matrix(matrix, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
+                 t->d_eps, p->temp, p->mu, p->sigma, p->omega_cut, scale, t->d_perm, out, st);
+    // |e_s - e_t| > omega + 6 sigma (with a margin for rounding) puts both
+    // delta arguments beyond the cut for every mode
+    t->band[matrix] = t->omega_max + 6.0 * p->sigma * (1.0 + 1e-9) + 1e-12;
+    ++t->gen[matrix];
+}
+
+StreamPlan plan_for(ephx_table* t, int matrix, int na, int nb, hipStream_t st) {
+    const int key = matrix * 64 + na * 8 + nb;
+    auto it = t->plans.find(key);
+    if (it != t->plans.end() && it->second.gen == t->gen[matrix]) return it->second.pl;
+    std::vector<int32_t> tiles;
+    int n_live = 0;
+    StreamPlan pl = stream_plan_banded(t->S, t->f32 ? 1 : 0, na, nb, t->h_esort, t->band[matrix], tiles, n_live);
+    // earlier passes on this stream may still read the old list
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    int32_t* d = (int32_t*)t->ws.get("tiles." + std::to_string(key), std::max<size_t>(8, tiles.size() * 4));
+    if (!tiles.empty()) hip_check(hipMemcpy(d, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    pl.tiles = d;
+    pl.perm = t->d_perm;
+    const size_t S1 = (size_t)std::max(1, t->S);
+    pl.gbuf = (double*)t->ws.get("gbuf." + std::to_string(key), (size_t)std::max(1, na + nb) * S1 * 8);
+    pl.rout = na > 0 ? (double*)t->ws.get("rout." + std::to_string(key), (size_t)na * S1 * 8) : nullptr;
+    pl.cout = nb > 0 ? (double*)t->ws.get("cout." + std::to_string(key), (size_t)nb * S1 * 8) : nullptr;
+    t->plans[key] = {pl, t->gen[matrix]};
+    return pl;
+}
+
+PassOut one_pass(ephx_table* t, const StreamPlan& pl, const void* mat, VecPtrs x, VecPtrs y, double* rowp,
+                 double* colp, hipStream_t st, const char* tag) {
     StageTimer tm(tag, st);
-    stream_pass(pl, t->ld, mat, x, y, rowp, colp, st);
+    return stream_pass(pl, t->ld, mat, x, y, rowp, colp, st);
 }
 
 // I at occupations y; optional RK4 stage update
@@ -101,19 +168,19 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
                     const double* f_base, double a_next, double* f_next, hipStream_t st,
                     const Field* fld = nullptr) {
     const int S = t->S;
-    const StreamPlan pl = plan_for(t, 1, 1);
+    const StreamPlan pl = plan_for(t, 0, 1, 1, st);
     double* omf = (double*)t->ws.get("c.omf", S * 8);
     double* rowp = (double*)t->ws.get("c.rowp", (size_t)pl.n_ct * S * 8);
     double* colp = (double*)t->ws.get("c.colp", (size_t)pl.n_rt * S * 8);
     occ_vectors(S, y, nullptr, omf, nullptr, nullptr, st);
     VecPtrs x{{omf, nullptr, nullptr, nullptr}}, yy{{y, nullptr, nullptr, nullptr}};
-    one_pass(t, pl, t->d_p, x, yy, rowp, colp, st, "collision_stream");
+    const PassOut po = one_pass(t, pl, t->d_p, x, yy, rowp, colp, st, "collision_stream");
     CollisionFinish cf{};
     cf.S = S;
-    cf.n_rt = pl.n_rt;
-    cf.n_ct = pl.n_ct;
-    cf.rowp = rowp;
-    cf.colp = colp;
+    cf.n_rt = po.n_rt;
+    cf.n_ct = po.n_ct;
+    cf.rowp = po.rowp;
+    cf.colp = po.colp;
     cf.f = y;
     cf.c = t->c;
     cf.i_out = i_out;
@@ -136,14 +203,14 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     double* o0 = (double*)t->ws.get("v.o0", S * 8);
     double* o1 = (double*)t->ws.get("v.o1", S * 8);
     double* o2 = (double*)t->ws.get("v.o2", S * 8);
-    const StreamPlan pl = plan_for(t, 2, 2);
+    const StreamPlan pl = plan_for(t, 0, 2, 2, st);
     double* rowp = (double*)t->ws.get("v.rowp", (size_t)2 * pl.n_ct * S * 8);
     double* colp = (double*)t->ws.get("v.colp", (size_t)2 * pl.n_rt * S * 8);
     occ_vectors(S, f, lam, o0, o1, o2, st);
     // rows: P(1-f), P(lam(1-f)); columns: P^T f, P^T (lam f)
     VecPtrs x{{o0, o1, nullptr, nullptr}}, y{{f, o2, nullptr, nullptr}};
-    one_pass(t, pl, t->d_p, x, y, rowp, colp, st, "collision_stream");
-    vjp_finish(S, pl.n_ct, pl.n_rt, rowp, colp, lam, t->c, fbar, st);
+    const PassOut po = one_pass(t, pl, t->d_p, x, y, rowp, colp, st, "collision_stream");
+    vjp_finish(S, po.n_ct, po.n_rt, po.rowp, po.colp, lam, t->c, fbar, st);
     if (sbar) {
         double* part = (double*)t->ws.get("v.part", (size_t)t->nm * S * 8);
         mode_vjp(S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
@@ -456,12 +523,36 @@ extern "C" int ephx_collision_setup(ephx_table* t, const ephx_params* p, const d
             t->d_p = t->alloc((size_t)t->S * t->ld * esz);
             hip_check(hipMemsetAsync(t->d_p, 0, (size_t)t->S * t->ld * esz, st), "hipMemsetAsync");
         }
-        build_matrix(0, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
-                     t->d_eps, p->temp, p->mu, p->sigma, p->omega_cut, t->d_scale, t->d_p, st);
+        build_banded(t, 0, p, t->d_scale, t->d_p, st);
         t->par = *p;
         t->c = 2.0 * kPi / kHbarEvFs / p->n_q;
         t->ready = true;
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+extern "C" int ephx_table_stream_info(ephx_table* t, int matrix, long long* live_entries, int* n_live_tiles,
+                                      int* n_tiles, void* stream) {
+    return guarded([&] {
+        require(t != nullptr && live_entries && n_live_tiles && n_tiles, "stream_info: null argument");
+        require(matrix == 0 || matrix == 1, "stream_info: matrix must be 0 (collision) or 1 (transport)");
+        require(t->gen[matrix] > 0, "stream_info: that matrix has not been built");
+        const StreamPlan pl = matrix == 0 ? plan_for(t, 0, 1, 1, (hipStream_t)stream)
+                                          : plan_for(t, 1, 3, 0, (hipStream_t)stream);
+        std::vector<int32_t> tiles((size_t)2 * pl.n_tiles);
+        if (pl.n_tiles > 0)
+            hip_check(hipMemcpy(tiles.data(), pl.tiles, tiles.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+        long long n = 0;
+        for (int i = 0; i < pl.n_live; ++i) {
+            const int ct = tiles[2 * i], rt = tiles[2 * i + 1];
+            const long long rows = std::min(t->S, (rt + 1) * pl.rpb) - (long long)rt * pl.rpb;
+            const long long c0 = (long long)ct * kStreamTileCols;
+            const long long cols = std::min<long long>(t->S, c0 + kStreamTileCols) - c0;
+            n += rows * cols;
+        }
+        *live_entries = n;
+        *n_live_tiles = pl.n_live;
+        *n_tiles = pl.n_tiles;
     });
 }
 
@@ -597,21 +688,20 @@ extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* 
             t->d_w = t->alloc((size_t)S * t->ld * esz);
             hip_check(hipMemsetAsync(t->d_w, 0, (size_t)S * t->ld * esz, st), "hipMemsetAsync");
         }
-        build_matrix(1, S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
-                     p->temp, p->mu, p->sigma, p->omega_cut, t->d_unit, t->d_w, st);
+        build_banded(t, 1, p, t->d_unit, t->d_w, st);
         double* tau = (double*)t->ws.get("m.tau", S * 8);
         double* f0 = (double*)t->ws.get("m.f0", 3 * S * 8);
         double* f = (double*)t->ws.get("m.f", 3 * S * 8);
         double* fn = (double*)t->ws.get("m.fn", 3 * S * 8);
-        const StreamPlan pl1 = plan_for(t, 1, 0), pl3 = plan_for(t, 3, 0);
+        const StreamPlan pl1 = plan_for(t, 1, 1, 0, st), pl3 = plan_for(t, 1, 3, 0, st);
         double* rowp = (double*)t->ws.get("m.rowp", (size_t)3 * pl3.n_ct * S * 8);
         VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
-        one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
-        ita_gamma(S, pl1.n_ct, rowp, p->n_q, vel, tau, f0, f, st);
+        PassOut po = one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
+        ita_gamma(S, po.n_ct, po.rowp, p->n_q, vel, tau, f0, f, st);
         for (int it = 0; it < n_iter; ++it) {
             VecPtrs x{{f, f + S, f + 2 * S, nullptr}};
-            one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
-            ita_update(S, pl3.n_ct, rowp, p->n_q, tau, f0, fn, st);
+            po = one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
+            ita_update(S, po.n_ct, po.rowp, p->n_q, tau, f0, fn, st);
             std::swap(f, fn);
         }
         mobility_reduce(S, t->d_eps, vel, f, p->mu, p->temp, f_out, mob_out, st);
@@ -641,23 +731,23 @@ extern "C" int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const doub
             t->d_w = t->alloc((size_t)S * t->ld * esz);
             hip_check(hipMemsetAsync(t->d_w, 0, (size_t)S * t->ld * esz, st), "hipMemsetAsync");
         }
-        build_matrix(1, S, nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
-                     p->temp, p->mu, p->sigma, p->omega_cut, t->d_unit, t->d_w, st);
+        build_banded(t, 1, p, t->d_unit, t->d_w, st);
         const long s3 = 3L * S;
         double* tau = (double*)t->ws.get("mv.tau", S * 8);
         double* fh = (double*)t->ws.get("mv.fh", (size_t)(n_iter + 1) * s3 * 8);
         double* fscr = (double*)t->ws.get("mv.f", s3 * 8);
-        const StreamPlan pl1 = plan_for(t, 1, 0), pl3 = plan_for(t, 3, 0), plc = plan_for(t, 0, 3);
+        const StreamPlan pl1 = plan_for(t, 1, 1, 0, st), pl3 = plan_for(t, 1, 3, 0, st),
+                         plc = plan_for(t, 1, 0, 3, st);
         double* rowp = (double*)t->ws.get("mv.rowp", (size_t)3 * pl3.n_ct * S * 8);
         double* colp = (double*)t->ws.get("mv.colp", (size_t)3 * plc.n_rt * S * 8);
         VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
-        one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
-        ita_gamma(S, pl1.n_ct, rowp, p->n_q, vel, tau, fh, fscr, st);
+        PassOut po = one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
+        ita_gamma(S, po.n_ct, po.rowp, p->n_q, vel, tau, fh, fscr, st);
         for (int it = 0; it < n_iter; ++it) {
             const double* fi = fh + it * s3;
             VecPtrs x{{fi, fi + S, fi + 2 * S, nullptr}};
-            one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
-            ita_update(S, pl3.n_ct, rowp, p->n_q, tau, fh, fh + (it + 1) * s3, st);
+            po = one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
+            ita_update(S, po.n_ct, po.rowp, p->n_q, tau, fh, fh + (it + 1) * s3, st);
         }
         // reverse
         double* fbar = (double*)t->ws.get("mv.fbar", s3 * 8);
@@ -669,8 +759,8 @@ extern "C" int ephx_mobility_vjp(ephx_table* t, const ephx_params* p, const doub
             double* ui = ubar + it * s3;
             ita_adj_step(S, tau, fbar, fh + (it + 1) * s3, taubar, ui, it == n_iter - 1 ? 1 : 0, st);
             VecPtrs y{{ui, ui + S, ui + 2 * S, nullptr}};
-            one_pass(t, plc, t->d_w, none, y, nullptr, colp, st, "transport_stream");
-            ita_adj_cols(S, plc.n_rt, colp, p->n_q, fbar, st);
+            const PassOut pc = one_pass(t, plc, t->d_w, none, y, nullptr, colp, st, "transport_stream");
+            ita_adj_cols(S, pc.n_rt, pc.colp, p->n_q, fbar, st);
         }
         ita_adj_final(S, tau, fbar, vel, taubar, n_iter == 0 ? 1 : 0, gambar, st);
 

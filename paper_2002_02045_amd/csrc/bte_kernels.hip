@@ -180,10 +180,18 @@ template <typename T, bool TRANSPORT>
 __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2, const int32_t* __restrict__ kc,
                                int n1, int n2, int n3, const double* __restrict__ omega,
                                const double* __restrict__ eps, double temp, double mu, double sigma,
-                               double omega_cut, const double* __restrict__ scale, T* __restrict__ out) {
-    const int s = blockIdx.x;
-    const int t = blockIdx.y * blockDim.x + threadIdx.x;
-    if (t >= S) return;
+                               double omega_cut, const double* __restrict__ scale,
+                               const int32_t* __restrict__ perm, T* __restrict__ out) {
+    // 1-D grid of 256-column chunks, rows padded to a multiple of 8.  Blocks are
+    // dealt to the 8 XCDs in turn, so every chunk of row i lands on XCD i % 8
+    // and the gathered reads of G[.][perm[i]][.] share that XCD's L2.
+    const int nch = (S + 255) / 256;
+    const long b = blockIdx.x;
+    const long local = b >> 3;
+    const int i = (int)(local / nch) * 8 + (int)(b & 7);
+    const int j = (int)(local % nch) * 256 + threadIdx.x;
+    if (i >= S || j >= S) return;
+    const int s = perm ? perm[i] : i, t = perm ? perm[j] : j;
     const long iq = grid_q(kc, s, t, n1, n2, n3);
     const double d = eps[s] - eps[t];
     const double kt = kBoltzEv * temp;
@@ -196,12 +204,12 @@ __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2,
         if (!(om > omega_cut)) continue;
         const double nb = 1.0 / expm1(om / kt);
         const double x1 = (d - om) * is, x2 = (d + om) * is;
-        const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
-        const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+        const double de = x1 * x1 > kDeltaCut2 ? 0.0 : nrm * exp(-x1 * x1);
+        const double da = x2 * x2 > kDeltaCut2 ? 0.0 : nrm * exp(-x2 * x2);
         const double w = TRANSPORT ? (de * (1.0 + nb - f0t) + da * (nb + f0t)) : (de * (nb + 1.0) + da * nb);
         acc += scale[nu] * (double)g2[((long)nu * S + s) * ld + t] * w;
     }
-    out[(long)s * ld + t] = (T)(TRANSPORT ? acc * (2.0 * kPi / kHbarEvFs) : acc);
+    out[(long)i * ld + j] = (T)(TRANSPORT ? acc * (2.0 * kPi / kHbarEvFs) : acc);
 }
 
 // ---------------------------------------------------------------- streaming pass
@@ -209,7 +217,7 @@ __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2,
 // rows; its four waves take the rows of the run in turn.  rpb is chosen on the
 // host so that the whole grid is resident at once (one wave of blocks): a
 // second, partly filled wave of blocks would leave HBM idle at the end.
-constexpr int kTC = 1024;         // columns per tile
+constexpr int kTC = kStreamTileCols; // columns per tile
 constexpr int kCPL = kTC / 64;    // columns per lane (16)
 
 template <typename T>
@@ -287,14 +295,29 @@ __device__ __forceinline__ void stream_row(int S, int r, int lane, int ct, int n
 
 // Two register sets X, Y alternate: while one row is reduced the other's loads
 // are in flight, and no register copy has to wait on an outstanding load.
+// Everything here is in matrix order (vectors gathered beforehand).  Block b
+// takes tile tiles[b]; blocks from n_live on hold tiles of exact zeros and only
+// write zero partials.
 template <typename T, int NA, int NB>
 __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restrict__ P, VecPtrs xa, VecPtrs yb,
                                                 double* __restrict__ rowp, double* __restrict__ colp, int n_ct,
-                                                int n_rt, int rpb) {
+                                                int n_rt, int rpb, const int32_t* __restrict__ tiles, int n_live) {
     __shared__ double cred[NB > 0 ? NB : 1][kTC];
-    const int ct = blockIdx.x, rt = blockIdx.y;
+    const int ct = tiles[2 * blockIdx.x], rt = tiles[2 * blockIdx.x + 1];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int c0 = ct * kTC;
+    const int r_beg = rt * rpb;
+    const int r_end = min(S, r_beg + rpb);
+    if ((int)blockIdx.x >= n_live) {
+        for (int r = r_beg + tid; r < r_end; r += 256)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) rowp[((long)a * n_ct + ct) * S + r] = 0.0;
+        for (int c = tid; c < kTC; c += 256)
+            if (c0 + c < S)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) colp[((long)b * n_rt + rt) * S + c0 + c] = 0.0;
+        return;
+    }
     // lane columns: c0 + 4*(lane + 64*j) + u, j = 0..3, u = 0..3
     double xv[NA > 0 ? NA : 1][kCPL];
 #pragma unroll
@@ -311,8 +334,6 @@ __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restr
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < kCPL; ++i) cacc[b][i] = 0.0;
-    const int r_beg = rt * rpb;
-    const int r_end = min(S, r_beg + rpb);
     int r = r_beg + wave;
     typename Vec4<T>::type X[4], Y[4];
     load_row(P, ld, r, r < r_end, c0, lane, X);
@@ -406,8 +427,8 @@ __global__ void k_mode_vjp(int S, int nm, long ld, const T* __restrict__ g2, con
         const double nb = 1.0 / expm1(om / kt);
         const double d = eps[s] - eps[t];
         const double x1 = (d - om) * is, x2 = (d + om) * is;
-        const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
-        const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+        const double de = x1 * x1 > kDeltaCut2 ? 0.0 : nrm * exp(-x1 * x1);
+        const double da = x2 * x2 > kDeltaCut2 ? 0.0 : nrm * exp(-x2 * x2);
         const double p = (double)g2[((long)nu * S + s) * ld + t] * (de * (nb + 1.0) + da * nb);
         acc += p * (1.0 - f[t]) * (ls - lam[t]);
     }
@@ -563,8 +584,8 @@ __device__ __forceinline__ double transport_weight(double d, double om, double f
     if (!(om > omega_cut)) return 0.0;
     const double nb = 1.0 / expm1(om / kt);
     const double x1 = (d - om) * is, x2 = (d + om) * is;
-    const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
-    const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+    const double de = x1 * x1 > kDeltaCut2 ? 0.0 : nrm * exp(-x1 * x1);
+    const double da = x2 * x2 > kDeltaCut2 ? 0.0 : nrm * exp(-x2 * x2);
     return de * (1.0 + nb - f0t) + da * (nb + f0t);
 }
 
@@ -733,22 +754,23 @@ void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st)
 
 void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2,
                   int n3, const double* omega, const double* eps, double temp, double mu, double sigma,
-                  double omega_cut, const double* scale, void* out, hipStream_t st) {
-    dim3 grid(S, (S + 255) / 256);
+                  double omega_cut, const double* scale, const int32_t* perm, void* out, hipStream_t st) {
+    if (S <= 0) return;
+    dim3 grid((unsigned)((long)(S + 255) / 256 * ((S + 7) / 8 * 8)));
     if (f32) {
         if (transport)
             hipLaunchKernelGGL((k_build_matrix<float, true>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
-                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (float*)out);
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out);
         else
             hipLaunchKernelGGL((k_build_matrix<float, false>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
-                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (float*)out);
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out);
     } else {
         if (transport)
             hipLaunchKernelGGL((k_build_matrix<double, true>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
-                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (double*)out);
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out);
         else
             hipLaunchKernelGGL((k_build_matrix<double, false>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
-                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, (double*)out);
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out);
     }
     check_launch("build_matrix");
 }
@@ -775,13 +797,8 @@ int stream_slots() {
 }
 }  // namespace
 
-StreamPlan stream_plan(int S, int f32, int na, int nb) {
-    StreamPlan p{};
-    p.S = S;
-    p.f32 = f32;
-    p.na = na;
-    p.nb = nb;
-    if (S <= 0) return p;
+namespace {
+int slot_count(int f32, int na, int nb) {
     int slots = 0;
 #define EPHX_SLOTS(T)                                             \
     if (na == 1 && nb == 1) slots = stream_slots<T, 1, 1>();      \
@@ -796,6 +813,18 @@ StreamPlan stream_plan(int S, int f32, int na, int nb) {
         EPHX_SLOTS(double)
     }
 #undef EPHX_SLOTS
+    return slots;
+}
+}  // namespace
+
+StreamPlan stream_plan(int S, int f32, int na, int nb) {
+    StreamPlan p{};
+    p.S = S;
+    p.f32 = f32;
+    p.na = na;
+    p.nb = nb;
+    if (S <= 0) return p;
+    const int slots = slot_count(f32, na, nb);
     p.n_ct = (S + kTC - 1) / kTC;
     const int n_rt = std::max(1, slots / p.n_ct);
     p.rpb = ((S + n_rt - 1) / n_rt + 3) / 4 * 4;
@@ -803,31 +832,125 @@ StreamPlan stream_plan(int S, int f32, int na, int nb) {
     return p;
 }
 
-void stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
-                 hipStream_t st) {
-    if (pl.S <= 0) return;
-    dim3 grid(pl.n_ct, pl.n_rt);
-#define EPHX_STREAM(T, A, B)                                                                                   \
-    hipLaunchKernelGGL((k_stream<T, A, B>), grid, dim3(256), 0, st, pl.S, ld, (const T*)P, x, y, rowp, colp, \
-                       pl.n_ct, pl.n_rt, pl.rpb)
-    const int na = pl.na, nb = pl.nb;
-    if (pl.f32) {
-        if (na == 1 && nb == 1) EPHX_STREAM(float, 1, 1);
-        else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
-        else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
-        else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
-        else if (na == 0 && nb == 3) EPHX_STREAM(float, 0, 3);
-        else throw Error{-1, "stream_pass: unsupported vector counts"};
-    } else {
-        if (na == 1 && nb == 1) EPHX_STREAM(double, 1, 1);
-        else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
-        else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
-        else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
-        else if (na == 0 && nb == 3) EPHX_STREAM(double, 0, 3);
-        else throw Error{-1, "stream_pass: unsupported vector counts"};
+StreamPlan stream_plan_banded(int S, int f32, int na, int nb, const std::vector<double>& esort, double half_width,
+                              std::vector<int32_t>& tiles, int& n_live) {
+    StreamPlan p = stream_plan(S, f32, na, nb);
+    tiles.clear();
+    n_live = 0;
+    if (S <= 0) return p;
+    if ((int)esort.size() != S) throw Error{-1, "stream_plan_banded: energy list size"};
+    const int slots = slot_count(f32, na, nb);
+    const int n_ct = p.n_ct;
+    // a tile is live unless every row energy is further than half_width from every column energy
+    auto live = [&](int rpb, int rt, int ct) {
+        const int r0 = rt * rpb, r1 = std::min(S, r0 + rpb);
+        const int c0 = ct * kTC, c1 = std::min(S, c0 + kTC);
+        const double gap = std::max(esort[c0] - esort[r1 - 1], esort[r0] - esort[c1 - 1]);
+        return !(gap > half_width);
+    };
+    auto count = [&](int rpb) {
+        const int n_rt = (S + rpb - 1) / rpb;
+        int n = 0;
+        for (int rt = 0; rt < n_rt; ++rt)
+            for (int ct = 0; ct < n_ct; ++ct) n += live(rpb, rt, ct) ? 1 : 0;
+        return n;
+    };
+    // smallest row tiles whose live tiles still fit one resident wave
+    int best = p.rpb;
+    for (int n_rt = p.n_rt + 1; n_rt <= 8 * p.n_rt; n_rt += std::max(1, p.n_rt / 16)) {
+        const int rpb = ((S + n_rt - 1) / n_rt + 3) / 4 * 4;
+        if (rpb < 4 || rpb >= best) continue;
+        if (count(rpb) > slots) break;
+        best = rpb;
     }
+    p.rpb = best;
+    p.n_rt = (S + best - 1) / best;
+    std::vector<int32_t> dead;
+    for (int rt = 0; rt < p.n_rt; ++rt)
+        for (int ct = 0; ct < n_ct; ++ct) {
+            std::vector<int32_t>& dst = live(best, rt, ct) ? tiles : dead;
+            dst.push_back(ct);
+            dst.push_back(rt);
+        }
+    n_live = (int)tiles.size() / 2;
+    tiles.insert(tiles.end(), dead.begin(), dead.end());
+    p.n_live = n_live;
+    p.n_tiles = (int)tiles.size() / 2;
+    return p;
+}
+
+namespace {
+// out[k][i] = v_k[perm[i]] for the na + nb vectors of a pass: matrix order
+__global__ void k_gather_vectors(int S, int nv, const int32_t* __restrict__ perm, VecPtrs x, VecPtrs y, int na,
+                                 double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const int s = perm[i];
+    for (int k = 0; k < nv; ++k) out[(long)k * S + i] = k < na ? x.p[k][s] : y.p[k - na][s];
+}
+
+// rout[a][perm[i]] = sum_ct rowp[a][ct][i], cout[b][perm[i]] = sum_rt colp[b][rt][i]
+// (fixed order: deterministic)
+__global__ void k_reduce_partials(int S, int na, int n_ct, const double* __restrict__ rowp, int nb, int n_rt,
+                                  const double* __restrict__ colp, const int32_t* __restrict__ perm,
+                                  double* __restrict__ rout, double* __restrict__ cout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const int s = perm[i];
+    for (int a = 0; a < na; ++a) {
+        double acc = 0.0;
+        for (int ct = 0; ct < n_ct; ++ct) acc += rowp[((long)a * n_ct + ct) * S + i];
+        rout[(long)a * S + s] = acc;
+    }
+    for (int b = 0; b < nb; ++b) {
+        double acc = 0.0;
+        for (int rt = 0; rt < n_rt; ++rt) acc += colp[((long)b * n_rt + rt) * S + i];
+        cout[(long)b * S + s] = acc;
+    }
+}
+}  // namespace
+
+PassOut stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
+                    hipStream_t st) {
+    PassOut out{pl.rout, 1, pl.cout, 1};
+    if (pl.S <= 0) return out;
+    if (!pl.tiles || !pl.perm || !pl.gbuf || (pl.na > 0 && !pl.rout) || (pl.nb > 0 && !pl.cout))
+        throw Error{-1, "stream_pass: incomplete plan"};
+    const int nv = pl.na + pl.nb;
+    const dim3 vg((pl.S + 255) / 256);
+    hipLaunchKernelGGL(k_gather_vectors, vg, dim3(256), 0, st, pl.S, nv, pl.perm, x, y, pl.na, pl.gbuf);
+    check_launch("gather_vectors");
+    VecPtrs xg{{nullptr, nullptr, nullptr, nullptr}}, yg{{nullptr, nullptr, nullptr, nullptr}};
+    for (int k = 0; k < pl.na; ++k) xg.p[k] = pl.gbuf + (long)k * pl.S;
+    for (int k = 0; k < pl.nb; ++k) yg.p[k] = pl.gbuf + (long)(pl.na + k) * pl.S;
+    if (pl.n_tiles > 0) {
+        dim3 grid(pl.n_tiles);
+#define EPHX_STREAM(T, A, B)                                                                                      \
+    hipLaunchKernelGGL((k_stream<T, A, B>), grid, dim3(256), 0, st, pl.S, ld, (const T*)P, xg, yg, rowp, colp, \
+                       pl.n_ct, pl.n_rt, pl.rpb, pl.tiles, pl.n_live)
+        const int na = pl.na, nb = pl.nb;
+        if (pl.f32) {
+            if (na == 1 && nb == 1) EPHX_STREAM(float, 1, 1);
+            else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
+            else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
+            else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
+            else if (na == 0 && nb == 3) EPHX_STREAM(float, 0, 3);
+            else throw Error{-1, "stream_pass: unsupported vector counts"};
+        } else {
+            if (na == 1 && nb == 1) EPHX_STREAM(double, 1, 1);
+            else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
+            else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
+            else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
+            else if (na == 0 && nb == 3) EPHX_STREAM(double, 0, 3);
+            else throw Error{-1, "stream_pass: unsupported vector counts"};
+        }
 #undef EPHX_STREAM
-    check_launch("stream_pass");
+        check_launch("stream_pass");
+    }
+    hipLaunchKernelGGL(k_reduce_partials, vg, dim3(256), 0, st, pl.S, pl.na, pl.n_ct, rowp, pl.nb, pl.n_rt, colp,
+                       pl.perm, pl.rout, pl.cout);
+    check_launch("reduce_partials");
+    return out;
 }
 
 void collision_finish(const CollisionFinish& cf, hipStream_t st) {

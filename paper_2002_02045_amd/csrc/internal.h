@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace ephx {
 
@@ -15,6 +16,11 @@ constexpr double kBoltzEv = 8.617333262e-5;             // k_B, eV/K
 constexpr double kHbar2AmuA2 = 0.004180159280496722;    // hbar^2/(amu*A^2), eV
 constexpr double kE2Over4PiEps0 = 14.3996454784;        // e^2/(4 pi eps0), eV*A
 constexpr double kPi = 3.14159265358979323846;
+// The BTE table matrices take the Gaussian delta as zero beyond 6 sigma
+// ((x/sigma)^2 > 36, a factor e^-36 below the peak), so that tiles of state
+// pairs further apart in energy than the largest phonon plus 6 sigma are exact
+// zeros and need not be stored or read.
+constexpr double kDeltaCut2 = 36.0;
 constexpr double kDegTol = 1e-4;                        // degenerate-group threshold, eV
 
 constexpr int kMaxNw = 16;      // Wannier functions handled by the per-pair kernels
@@ -244,11 +250,12 @@ void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const doubl
                     const int32_t* band, double* out, hipStream_t st);
 void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st);
 // transport = 0: collision matrix P (mode scales applied);
-// transport = 1: scattering probabilities W (Eq. BTE_W, 1/fs, scale ignored but required)
+// transport = 1: scattering probabilities W (Eq. BTE_W, 1/fs, scale ignored but required).
+// Row/column i of out is state perm[i] (perm nullptr: identity).
 void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc,
                   int n1, int n2, int n3, const double* omega, const double* eps, double temp,
-                  double mu, double sigma, double omega_cut, const double* scale, void* out,
-                  hipStream_t st);
+                  double mu, double sigma, double omega_cut, const double* scale, const int32_t* perm,
+                  void* out, hipStream_t st);
 
 // Streaming pass over a dense S x S matrix P (row stride ld):
 //   rowp[a][ct][s] = sum_{t in col tile ct} P[s][t] x_a[t]      (a < na)
@@ -258,15 +265,42 @@ struct VecPtrs {
 };
 // The plan fixes the kernel instance and its tiling; the finish kernels sum
 // the n_ct row partials and n_rt column partials it produces.
+// The matrix is stored in the state order `perm` (row/column i is state
+// perm[i]) and only the listed tiles are launched: entries [0, n_live) are
+// (column tile, row tile) pairs that are read, the rest are tiles known to
+// hold only zeros, whose partials are written as 0 without reading the
+// matrix.  A pass gathers the vectors into matrix order (gbuf), streams, and
+// reduces the partials back into state order (rout [na][S], cout [nb][S]).
 struct StreamPlan {
     int S;
     int f32, na, nb;      // matrix precision and vector counts
     int n_rt, n_ct;       // row and column tiles
     int rpb;              // rows per row tile
+    const int32_t* tiles; // device [n_tiles][2]
+    int n_live, n_tiles;
+    const int32_t* perm;  // device [S]
+    double* gbuf;         // device [na + nb][S]
+    double* rout;         // device [na][S]
+    double* cout;         // device [nb][S]
 };
+// Where the finishing kernels read a pass's results: n_ct row partials per
+// row sum and n_rt column partials per column sum, in state order.
+struct PassOut {
+    const double* rowp;
+    int n_ct;
+    const double* colp;
+    int n_rt;
+};
+constexpr int kStreamTileCols = 1024;   // columns per tile of the streaming pass
 StreamPlan stream_plan(int S, int f32, int na, int nb);
-void stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
-                 hipStream_t st);
+// Tiling of a matrix stored in ascending-energy order (esort[i] = energy of
+// row/column i) whose entries vanish where the two energies differ by more
+// than half_width: row tiles are made as small as keeps the live tiles within
+// one resident wave of blocks.  tiles receives the host tile list, live first.
+StreamPlan stream_plan_banded(int S, int f32, int na, int nb, const std::vector<double>& esort, double half_width,
+                              std::vector<int32_t>& tiles, int& n_live);
+PassOut stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
+                    hipStream_t st);
 // I_s = -c [ f_s R_s - (1-f_s) C_s ] with R, C the reduced partials; optional
 // RK4 stage update: acc = (acc_init ? f_base : acc) + w_acc * I ; f_next = f_base + a_next * I.
 struct CollisionFinish {

@@ -129,6 +129,12 @@ def big_table(lib, tiny, big_case):
 
 def test_collision_parity_and_conservation(lib, big_case, big_table):
     _say("collision S=1030 fp64")
+    # the matrix is stored in energy order and tiles of pairs further apart
+    # than omega_max + 6 sigma are skipped: this case has such tiles
+    live, n_live, n_tiles = big_table.stream_info("collision")
+    S = len(big_case[1])
+    _say("  banded collision matrix: %d of %d tiles read, %.3f of the entries" % (n_live, n_tiles, live / S ** 2))
+    assert 0 < n_live < n_tiles and live < S * S
     rng = np.random.default_rng(3)
     for trial in range(3):
         f = rng.random(len(big_case[1])) * (0.5 if trial else 1e-3)
