@@ -245,6 +245,7 @@ def dynamics_bench(px, dm, model, args):
     px.timer_enable(False)
     ns, ms = px.timer_get("collision_stream")
     nf, msf = px.timer_get("collision_finish")
+    npm, mspm = px.timer_get("stream_permute")
     px.timer_reset()
     ld = (S + 63) // 64 * 64
     # the FP32 collision matrix is stored in energy order and tiles of state
@@ -283,7 +284,8 @@ def dynamics_bench(px, dm, model, args):
             "traffic": measured_traffic("k_stream<float, 1, 1>"), "traffic_unit": "HBM bytes per launch",
                      "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5),
                      "dense_bytes": 4.0 * S * S, "live_tiles": n_live, "tiles": n_tiles},
-        "collision_evals_per_s": ns / (1e-3 * (ms + msf)) if ms > 0 else None,
+        "collision_evals_per_s": ns / (1e-3 * (ms + msf + mspm)) if ms > 0 else None,
+        "gather_reduce_ms_per_pass": round(mspm / max(1, ns), 5),
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,
         "euler_field_steps_per_s": args.dyn_steps / dt_e, "euler_field_V_per_A": efield,
@@ -441,7 +443,7 @@ def measured_traffic(kernel):
 
 # kernel behind each precision's Rp contraction (Si-like shape: 384 output columns)
 RP_KERNEL = {"fp64": "k_phase_gemm<double, 4>", "fp32": "k_phase_gemm<float, 8>",
-             "bf16x3": "k_gemm_bf16_planes<8, 2>", "bf16x6": "k_gemm_bf16_planes<8, 3>"}
+             "bf16x3": "k_gemm_bf16_planes<4, 2>", "bf16x6": "k_gemm_bf16_planes<4, 3>"}
 
 
 def group_sums(px, dm, ks, qs, g2):

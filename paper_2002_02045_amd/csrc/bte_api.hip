@@ -151,10 +151,20 @@ StreamPlan plan_for(ephx_table* t, int matrix, int na, int nb, hipStream_t st) {
     return pl;
 }
 
+// The stage timer `tag` covers the streaming kernel alone; the gather and the
+// reduction are timed as "stream_permute".
 PassOut one_pass(ephx_table* t, const StreamPlan& pl, const void* mat, VecPtrs x, VecPtrs y, double* rowp,
                  double* colp, hipStream_t st, const char* tag) {
-    StageTimer tm(tag, st);
-    return stream_pass(pl, t->ld, mat, x, y, rowp, colp, st);
+    {
+        StageTimer tm("stream_permute", st);
+        stream_gather(pl, x, y, st);
+    }
+    {
+        StageTimer tm(tag, st);
+        stream_run(pl, t->ld, mat, rowp, colp, st);
+    }
+    StageTimer tm("stream_permute", st);
+    return stream_reduce(pl, rowp, colp, st);
 }
 
 // I at occupations y; optional RK4 stage update

@@ -910,16 +910,17 @@ __global__ void k_reduce_partials(int S, int na, int n_ct, const double* __restr
 }
 }  // namespace
 
-PassOut stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
-                    hipStream_t st) {
-    PassOut out{pl.rout, 1, pl.cout, 1};
-    if (pl.S <= 0) return out;
+void stream_gather(const StreamPlan& pl, VecPtrs x, VecPtrs y, hipStream_t st) {
+    if (pl.S <= 0) return;
     if (!pl.tiles || !pl.perm || !pl.gbuf || (pl.na > 0 && !pl.rout) || (pl.nb > 0 && !pl.cout))
-        throw Error{-1, "stream_pass: incomplete plan"};
-    const int nv = pl.na + pl.nb;
-    const dim3 vg((pl.S + 255) / 256);
-    hipLaunchKernelGGL(k_gather_vectors, vg, dim3(256), 0, st, pl.S, nv, pl.perm, x, y, pl.na, pl.gbuf);
+        throw Error{-1, "stream_gather: incomplete plan"};
+    hipLaunchKernelGGL(k_gather_vectors, dim3((pl.S + 255) / 256), dim3(256), 0, st, pl.S, pl.na + pl.nb, pl.perm, x,
+                       y, pl.na, pl.gbuf);
     check_launch("gather_vectors");
+}
+
+void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, double* colp, hipStream_t st) {
+    if (pl.S <= 0) return;
     VecPtrs xg{{nullptr, nullptr, nullptr, nullptr}}, yg{{nullptr, nullptr, nullptr, nullptr}};
     for (int k = 0; k < pl.na; ++k) xg.p[k] = pl.gbuf + (long)k * pl.S;
     for (int k = 0; k < pl.nb; ++k) yg.p[k] = pl.gbuf + (long)(pl.na + k) * pl.S;
@@ -947,8 +948,13 @@ PassOut stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, Vec
 #undef EPHX_STREAM
         check_launch("stream_pass");
     }
-    hipLaunchKernelGGL(k_reduce_partials, vg, dim3(256), 0, st, pl.S, pl.na, pl.n_ct, rowp, pl.nb, pl.n_rt, colp,
-                       pl.perm, pl.rout, pl.cout);
+}
+
+PassOut stream_reduce(const StreamPlan& pl, const double* rowp, const double* colp, hipStream_t st) {
+    PassOut out{pl.rout, 1, pl.cout, 1};
+    if (pl.S <= 0) return out;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((pl.S + 255) / 256), dim3(256), 0, st, pl.S, pl.na, pl.n_ct, rowp,
+                       pl.nb, pl.n_rt, colp, pl.perm, pl.rout, pl.cout);
     check_launch("reduce_partials");
     return out;
 }

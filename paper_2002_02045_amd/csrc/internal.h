@@ -299,8 +299,11 @@ StreamPlan stream_plan(int S, int f32, int na, int nb);
 // one resident wave of blocks.  tiles receives the host tile list, live first.
 StreamPlan stream_plan_banded(int S, int f32, int na, int nb, const std::vector<double>& esort, double half_width,
                               std::vector<int32_t>& tiles, int& n_live);
-PassOut stream_pass(const StreamPlan& pl, long ld, const void* P, VecPtrs x, VecPtrs y, double* rowp, double* colp,
-                    hipStream_t st);
+// One pass = gather the vectors into matrix order, stream the live tiles into
+// partials (matrix order), reduce the partials into state order.
+void stream_gather(const StreamPlan& pl, VecPtrs x, VecPtrs y, hipStream_t st);
+void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, double* colp, hipStream_t st);
+PassOut stream_reduce(const StreamPlan& pl, const double* rowp, const double* colp, hipStream_t st);
 // I_s = -c [ f_s R_s - (1-f_s) C_s ] with R, C the reduced partials; optional
 // RK4 stage update: acc = (acc_init ? f_base : acc) + w_acc * I ; f_next = f_base + a_next * I.
 struct CollisionFinish {
