@@ -1,0 +1,116 @@
+"""Parity at the full Si-like size, in the launch configuration the benchmark
+times (16 k points per Rp contraction launch, q chunks of 32,768), on sampled
+outputs the FP64 oracle computes one by one.
+
+Model: the benchmark's Si-like model (Nw = 8, 6 modes, 512 Re x 512 Rp).
+- |g|^2: 16 k x 65,536 q through the library (two q chunks per k batch); the
+  oracle recomputes 16 k x 48 sampled q, including both sides of the chunk
+  boundary and the last q.
+- Rates: 16 k against the benchmark's 10^6 random q.  The q weights are zero
+  except on 64 sampled q (1/64 each), so the library streams every chunk of the
+  full list while the result depends only on the sample, which the oracle
+  evaluates directly.  A second property holds at any size: splitting the q
+  list in two and recombining the halves by their weights gives the same rates.
+Tolerances as elsewhere: FP64 1e-10; FP32 / BF16x6 |g|^2 1e-5, BF16x3 2e-5;
+rates 1e-4 for the reduced precisions.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import g2_error, group_sums_g2, rate_error
+from oracle import eph
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4), ("bf16x6", 1e-5, 1e-4), ("bf16x3", 2e-5, 1e-4)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2002_02045_amd as px
+    return px
+
+
+@pytest.fixture(scope="module")
+def si(lib):
+    _say("Si-like model (512 Re x 512 Rp), full size")
+    m = synth.make_config_model("si")
+    return m, lib.Model(m)
+
+
+@pytest.mark.parametrize("prec,tol_g2,tol_rate", PRECS)
+def test_full_size_gkq_sampled(lib, si, prec, tol_g2, tol_rate):
+    m, dm = si
+    k = synth.random_points(311, 16)
+    q = synth.random_points(312, 65536)
+    _say("gkq 16 k x 65536 q, prec=%s" % prec)
+    g2 = lib.gkq(dm, k, q, precision=prec)
+    rng = np.random.default_rng(313)
+    idx = np.unique(np.concatenate([[0, 1, 32767, 32768, 32769, 65535], rng.choice(65536, 42, replace=False)]))
+    blk = eph.eph_pipeline(m, k, q[idx])
+    ref = group_sums_g2(blk["g"].abs() ** 2, blk["eps_k"], blk["eps_kq"], blk["omega"])
+    got = group_sums_g2(g2[:, torch.as_tensor(idx, device=g2.device)].double().cpu().numpy(), blk["eps_k"],
+                        blk["eps_kq"], blk["omega"])
+    emax, e99 = g2_error(got, ref)
+    _say("  |g|^2 error %s on %d sampled pairs: max %.3e p99 %.3e" % (prec, 16 * len(idx), emax, e99))
+    assert emax <= tol_g2
+    del g2
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def full_q():
+    cfg = synth.CONFIGS["si"]
+    return synth.random_points(cfg["seed"] + 200, cfg["nq"])
+
+
+@pytest.mark.parametrize("prec,tol_g2,tol_rate", PRECS)
+def test_full_size_rates_sampled(lib, si, full_q, prec, tol_g2, tol_rate):
+    m, dm = si
+    cfg = synth.CONFIGS["si"]
+    k = synth.random_points(314, 16)
+    nq = len(full_q)
+    rng = np.random.default_rng(315)
+    idx = np.sort(rng.choice(nq, 64, replace=False))
+    w = np.zeros(nq)
+    w[idx] = 1.0 / len(idx)
+    par = dict(temp=cfg["T"], mu=cfg["mu"], sigma=cfg["sigma"])
+    p = lib.Params(omega_cut=cfg["omega_cut"], **par)
+    _say("rates 16 k x %d q (64 weighted), prec=%s" % (nq, prec))
+    g, gm = lib.rates(dm, k, full_q, p, precision=prec, q_weights=w)
+    go, gmo = eph.rates(m, k, full_q[idx], q_weights=np.full(len(idx), 1.0 / len(idx)), **par)
+    err = rate_error(g.cpu().numpy(), go.numpy())
+    errm = rate_error(gm.cpu().numpy(), gmo.numpy())
+    _say("  rates error %s: %.3e (per mode %.3e), %d of %d states above the floor" % (
+        prec, err, errm, int((go.numpy() >= 1e-6 * go.numpy().max()).sum()), go.numel()))
+    assert float(go.max()) > 0
+    assert err <= tol_rate and errm <= tol_rate
+
+
+def test_full_size_rates_split_q(lib, si, full_q):
+    """Rates over the full q list = the weight-combined rates of its two halves
+    (a split that does not fall on a chunk boundary)."""
+    m, dm = si
+    cfg = synth.CONFIGS["si"]
+    k = synth.random_points(316, 16)
+    p = lib.Params(temp=cfg["T"], mu=cfg["mu"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"])
+    nq = len(full_q)
+    cut = 400_001
+    _say("rates split-q property, 16 k x %d q (FP64)" % nq)
+    g, _ = lib.rates(dm, k, full_q, p, precision="fp64", mode_resolved=False)
+    g1, _ = lib.rates(dm, k, full_q[:cut], p, precision="fp64", mode_resolved=False)
+    g2, _ = lib.rates(dm, k, full_q[cut:], p, precision="fp64", mode_resolved=False)
+    comb = (cut * g1 + (nq - cut) * g2) / nq
+    err = rate_error(comb.cpu().numpy(), g.cpu().numpy())
+    _say("  split-q error %.3e" % err)
+    assert err <= 1e-12
+    assert float(g.min()) >= 0.0
