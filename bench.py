@@ -195,6 +195,8 @@ def main():
                                "%d random q, T=300 K, sigma=5 meV" % (kb, nk_total, args.nq),
                    "precision": head},
         "roofline": roof,
+        "speedup_vs_fp64_gpu": (round(r["pairs_per_s"] / results["fp64"]["pairs_per_s"], 3)
+                                if "fp64" in results else None),
         "cpu_baseline": cpu,
         "by_precision": {p: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in d.items()}
                          for p, d in results.items()},

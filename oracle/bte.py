@@ -53,6 +53,28 @@ def pair_table(model, n_grid, k_idx, band, *, omega_cut=1e-4, polar=None):
     return 0.5 * (raw + raw.transpose(0, 1)), om
 
 
+def pair_entries(model, n_grid, k_idx, band, pairs, *, omega_cut=1e-4, polar=None):
+    """Entries of `pair_table` at the listed ordered pairs (s, t) only, each
+    evaluated from its definition (for sampling tables too large to build
+    here).  Returns (g2s [P, nmodes], omega [P, nmodes])."""
+    n_grid = np.asarray(n_grid)
+    ks = state_points(k_idx, n_grid)
+    cs = grid_coords(k_idx, n_grid)
+    nm = model.nmodes
+    g2s = torch.zeros((len(pairs), nm), dtype=F64)
+    om = torch.zeros((len(pairs), nm), dtype=F64)
+    for i, (s, t) in enumerate(pairs):
+        q_st = ((cs[t] - cs[s]) % n_grid) / n_grid
+        q_ts = ((cs[s] - cs[t]) % n_grid) / n_grid
+        a = eph_pipeline(model, ks[s:s + 1], q_st[None], polar, omega_cut)
+        b = eph_pipeline(model, ks[t:t + 1], q_ts[None], polar, omega_cut)
+        g_st = a["g"][0, 0, :, int(band[t]), int(band[s])].abs() ** 2
+        g_ts = b["g"][0, 0, :, int(band[s]), int(band[t])].abs() ** 2
+        g2s[i] = 0.5 * (g_st + g_ts)
+        om[i] = a["omega"][0]
+    return g2s, om
+
+
 def collision(f, eps, g2s, omega, *, temp, sigma, n_q, omega_cut=1e-4, mode_scale=None):
     """e-ph collision integral, Eq. e_ph_scattering with F_abs and F_em:
 

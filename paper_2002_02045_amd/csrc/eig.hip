@@ -95,16 +95,20 @@ __device__ __forceinline__ void jacobi_round(int i, Cx (&a)[R], Cx (&v)[R]) {
     const bool lower = i < (i ^ M);
     const double dself = a[0].r;
     const double dpart = xlane<M>(a[0].r);
+    // t and s of the header, divided by |a_pq| so that neither |a_pq| nor the
+    // phase needs its own root or quotient: with d = a_qq - a_pp and
+    // m2 = |a_pq|^2, t/|a_pq| = 2 sgn(d)/(|d| + sqrt(d^2 + 4 m2)) and
+    // se = (t/|a_pq|) c a_pq
     const double apr = a[M].r, api = a[M].i;   // A[i][i^M]
-    const double mag = sqrt(apr * apr + api * api);
-    const double th = (dpart - dself) / (2.0 * mag);
-    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-    const double c0 = 1.0 / sqrt(t * t + 1.0);
-    const double s0 = t * c0;
-    const bool rot = mag > 0.0;
+    const double m2 = apr * apr + api * api;
+    const double d = dpart - dself;
+    const double tm = (d >= 0.0 ? 2.0 : -2.0) / (fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
+    const double c0 = 1.0 / sqrt(fma(tm * tm, m2, 1.0));
+    const double w = tm * c0;
+    const bool rot = m2 > 0.0;
     double c = rot ? c0 : 1.0;
-    double sr = rot ? s0 * apr / mag : 0.0;
-    double si = rot ? s0 * api / mag : 0.0;
+    double sr = rot ? w * apr : 0.0;
+    double si = rot ? w * api : 0.0;
     const double cp = xlane<M>(c), srp = xlane<M>(sr), sip = xlane<M>(si);
     c = lower ? c : cp;
     sr = lower ? sr : srp;

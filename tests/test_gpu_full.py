@@ -114,3 +114,68 @@ def test_full_size_rates_split_q(lib, si, full_q):
     _say("  split-q error %.3e" % err)
     assert err <= 1e-12
     assert float(g.min()) >= 0.0
+
+
+def test_full_size_dynamics_table_sampled(lib, si):
+    """The dynamics workload at its full size: the 20,000 lowest conduction
+    states of the 80^3 grid (selected by the oracle's energies, and by the
+    library, bit for bit), the FP32 symmetrised pair table sampled against the
+    oracle's per-pair definition, and carrier conservation of the banded
+    collision pass on the full table."""
+    from oracle import bte, grid, interp
+    m, dm = si
+    cfg = synth.CONFIGS["dyn"]
+    n = (cfg["k_grid"],) * 3
+    pts = grid.grid_points(n)
+    _say("oracle energies on the 80^3 grid")
+    eps = np.concatenate([interp.bands(m, pts[i:i + 65536])[0].numpy() for i in range(0, len(pts), 65536)])
+    kk, bb = grid.lowest_states(eps, m.nw // 2, cfg["n_states"])
+    kg, bg, eg = lib.grid_states(dm, n, mode="lowest", band_lo=m.nw // 2, count=cfg["n_states"])
+    assert np.array_equal(kk, kg) and np.array_equal(bb, bg)
+    S = len(kk)
+    _say("FP32 table S=%d" % S)
+    t = lib.PairTable(dm, n, kk, bb, precision="fp32")
+    g, _ = t.g2()
+    rng = np.random.default_rng(317)
+    e_s = eps[kk, bb]
+    order = np.argsort(e_s)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, S, size=(40, 2))]
+    # pairs close in energy (the ones the collision integral weighs) and the diagonal
+    pairs += [(int(order[i]), int(order[i + 1 + j])) for i, j in zip(rng.integers(0, S - 10, 20), rng.integers(0, 8, 20))]
+    pairs += [(0, 0), (S - 1, S - 1)]
+    ref, om = bte.pair_entries(m, n, kk, bb, pairs)
+    si_ = torch.as_tensor([p[0] for p in pairs], device=g.device)
+    ti_ = torch.as_tensor([p[1] for p in pairs], device=g.device)
+    got = g[:, si_, ti_].T.double().cpu()                    # [P][nu]
+    worst = 0.0
+    for i in range(len(pairs)):
+        lab = group_labels_modes(om[i].numpy())
+        gs = np.bincount(lab, weights=got[i].numpy())
+        rs = np.bincount(lab, weights=ref[i].numpy())
+        scale = max(float(ref[i].abs().max()), 1e-300)
+        worst = max(worst, float(np.abs(gs - rs).max()) / scale if ref[i].abs().max() > 0 else float(np.abs(gs).max()))
+    _say("  table error on %d sampled pairs: %.3e" % (len(pairs), worst))
+    assert worst <= 1e-5
+    del g
+    torch.cuda.empty_cache()
+    t.setup(lib.Params(temp=cfg["T"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"], n_q=float(np.prod(n))))
+    live, n_live, n_tiles = t.stream_info("collision")
+    f0 = cfg["f0_peak"] * np.exp(-((e_s - e_s.min() - cfg["f0_centre"]) ** 2) / (2 * cfg["f0_width"] ** 2))
+    i_out = t.collision(f0).cpu()
+    cons = abs(float(i_out.sum())) / float(i_out.abs().sum())
+    _say("  banded pass: %d of %d tiles (%.3f of S^2); conservation %.2e" % (n_live, n_tiles, live / S ** 2, cons))
+    assert 0 < n_live < n_tiles
+    assert cons <= 1e-12
+    t.close()
+
+
+def group_labels_modes(omega, tol=1e-4):
+    """Degenerate groups of one q's modes (sorted energies within tol)."""
+    order = np.argsort(omega)
+    lab = np.zeros(len(omega), dtype=np.int64)
+    g = 0
+    for i in range(1, len(order)):
+        if omega[order[i]] - omega[order[i - 1]] > tol:
+            g += 1
+        lab[order[i]] = g
+    return lab

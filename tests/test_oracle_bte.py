@@ -228,3 +228,18 @@ def test_pair_table_symmetric_and_matches_direct_pairs(tiny_model):
     ga = eph.g2(tiny_model, pts[kk[s]][None], q[None])[0, 0, :, bb[t], bb[s]]
     gb = eph.g2(tiny_model, pts[kk[t]][None], -q[None])[0, 0, :, bb[s], bb[t]]
     assert torch.allclose(g2s[s, t], 0.5 * (ga + gb), rtol=1e-10)
+
+
+def test_pair_entries_match_the_table():
+    """The per-pair evaluation used to sample large tables gives the entries of
+    the full table (same definition, evaluated two ways)."""
+    m = synth.make_config_model("tiny")
+    n = (4, 4, 4)
+    eps, _ = interp.bands(m, grid.grid_points(n))
+    kk, bb = grid.lowest_states(eps.numpy(), m.nw // 2, 12)
+    g2s, om = bte.pair_table(m, n, kk, bb)
+    pairs = [(0, 0), (0, 5), (5, 0), (3, 11), (11, 7), (6, 6)]
+    e2, eo = bte.pair_entries(m, n, kk, bb, pairs)
+    for i, (s, t) in enumerate(pairs):
+        assert torch.allclose(e2[i], g2s[s, t], rtol=1e-12, atol=1e-300)
+        assert torch.allclose(eo[i], om[s, t], rtol=1e-12, atol=1e-300)
