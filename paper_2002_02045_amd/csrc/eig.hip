@@ -49,6 +49,21 @@ struct Cx {
     double r, i;
 };
 
+// 1/b and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// each (quadratic convergence from the estimate's ~1e-8 relative error to the
+// last bits); b > 0, x >= 1 where they are used.
+__device__ __forceinline__ double recip(double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    y = y * fma(-b, y, 2.0);
+    return y * fma(-b, y, 2.0);
+}
+__device__ __forceinline__ double rsqrt1(double x) {
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
 // Columns c1 = i^D (register D) and c2 = i^D^M (register E = D^M) form one pair
 // of the round, rotated with the parameters of lane i^D's pair.  With X_p, X_q
 // the columns of the pair (p < q),
@@ -102,8 +117,8 @@ __device__ __forceinline__ void jacobi_round(int i, Cx (&a)[R], Cx (&v)[R]) {
     const double apr = a[M].r, api = a[M].i;   // A[i][i^M]
     const double m2 = apr * apr + api * api;
     const double d = dpart - dself;
-    const double tm = (d >= 0.0 ? 2.0 : -2.0) / (fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
-    const double c0 = 1.0 / sqrt(fma(tm * tm, m2, 1.0));
+    const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
+    const double c0 = rsqrt1(fma(tm * tm, m2, 1.0));
     const double w = tm * c0;
     const bool rot = m2 > 0.0;
     double c = rot ? c0 : 1.0;
