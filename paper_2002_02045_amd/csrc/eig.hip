@@ -238,15 +238,19 @@ __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restri
 // Larger matrices (8 < n <= 128, e.g. H(k) of a 64-function model, D(q) of a
 // 40-atom cell): one 256-thread workgroup per matrix, the same rotations and
 // convergence test, with the n/2 disjoint rotations of a round (circle-method
-// ordering) applied by all threads at once.  A (overwritten) and V (the
-// eigenvector output) live in global memory, which the workgroup's own L1/L2
-// serve; the rotation parameters of a round go through LDS.
+// ordering) applied by all threads at once.  Every round is three barriers
+// apart, so the latency of A and V decides the time: for n <= 64 both live in
+// LDS (2 x 64 KB); larger A (overwritten) and V (the eigenvector output) stay
+// in global memory, served by the workgroup's L1/L2.  The rotation parameters
+// of a round go through LDS.
 constexpr int kWgMax = 128;
+constexpr int kWgLds = 64;     // largest order kept in LDS
 
 __device__ __forceinline__ int circle_index(int pos, int r, int ne) {
     return pos == 0 ? 0 : (pos - 1 + r) % (ne - 1) + 1;
 }
 
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, long strideA, double* __restrict__ evals,
                                                 double* __restrict__ evecs) {
     __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
@@ -254,22 +258,26 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     __shared__ double red[2][256];
     __shared__ double dg[kWgMax];
     __shared__ int rk[kWgMax];
+    __shared__ double sbuf[kLds ? 4 * kWgLds * kWgLds : 2];
     const int tid = threadIdx.x;
     const long mi = blockIdx.x;
-    double* a = A + mi * strideA * 2;
-    double* v = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
+    double* ga = A + mi * strideA * 2;
+    double* gv = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
+    double* a = kLds ? sbuf : ga;
+    double* v = kLds ? (gv ? sbuf + 2 * kWgLds * kWgLds : nullptr) : gv;
     const int nn = n * n;
     // Hermitian part 0.5 (A + A^dag), V = I
     for (int e = tid; e < nn; e += 256) {
         const int i = e / n, j = e % n;
         if (i < j) {
-            const double xr = 0.5 * (a[2 * e] + a[2 * (j * n + i)]);
-            const double xi = 0.5 * (a[2 * e + 1] - a[2 * (j * n + i) + 1]);
+            const double xr = 0.5 * (ga[2 * e] + ga[2 * (j * n + i)]);
+            const double xi = 0.5 * (ga[2 * e + 1] - ga[2 * (j * n + i) + 1]);
             a[2 * e] = xr;
             a[2 * e + 1] = xi;
             a[2 * (j * n + i)] = xr;
             a[2 * (j * n + i) + 1] = -xi;
         } else if (i == j) {
+            a[2 * e] = ga[2 * e];
             a[2 * e + 1] = 0.0;
         }
         if (v) {
@@ -306,14 +314,15 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
                 double c = 1.0, sr = 0.0, si = 0.0;
                 if (q < n) {
                     const double apr = a[2 * (p * n + q)], api = a[2 * (p * n + q) + 1];
-                    const double mag = sqrt(apr * apr + api * api);
-                    if (mag > 0.0) {
-                        const double th = (a[2 * (q * n + q)] - a[2 * (p * n + p)]) / (2.0 * mag);
-                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        const double s = t * c;
-                        sr = s * apr / mag;
-                        si = s * api / mag;
+                    const double m2 = apr * apr + api * api;
+                    if (m2 > 0.0) {
+                        // t/|a_pq| and se as in the wavefront solver
+                        const double d = a[2 * (q * n + q)] - a[2 * (p * n + p)];
+                        const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
+                        c = rsqrt1(fma(tm * tm, m2, 1.0));
+                        const double w = tm * c;
+                        sr = w * apr;
+                        si = w * api;
                     }
                 }
                 pp[tid] = p;
@@ -374,17 +383,26 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
         evals[mi * n + r] = dg[i];
     }
     __syncthreads();
-    if (v) {
-        // permute the columns of V through A's storage
-        for (int e = tid; e < nn; e += 256) {
-            a[2 * e] = v[2 * e];
-            a[2 * e + 1] = v[2 * e + 1];
-        }
-        __syncthreads();
-        for (int e = tid; e < nn; e += 256) {
-            const int i = e / n, c = e % n;
-            v[2 * (i * n + rk[c])] = a[2 * e];
-            v[2 * (i * n + rk[c]) + 1] = a[2 * e + 1];
+    if (gv) {
+        if (kLds) {
+            // columns of V go to their ranks directly
+            for (int e = tid; e < nn; e += 256) {
+                const int i = e / n, c = e % n;
+                gv[2 * (i * n + rk[c])] = v[2 * e];
+                gv[2 * (i * n + rk[c]) + 1] = v[2 * e + 1];
+            }
+        } else {
+            // permute the columns of V through A's storage
+            for (int e = tid; e < nn; e += 256) {
+                a[2 * e] = v[2 * e];
+                a[2 * e + 1] = v[2 * e + 1];
+            }
+            __syncthreads();
+            for (int e = tid; e < nn; e += 256) {
+                const int i = e / n, c = e % n;
+                v[2 * (i * n + rk[c])] = a[2 * e];
+                v[2 * (i * n + rk[c]) + 1] = a[2 * e + 1];
+            }
         }
     }
 }
@@ -424,7 +442,12 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
     if (n < 1 || n > kWgMax) throw Error{-6, "eig_herm: matrix order above 128 is not supported"};
     if (n > kEigMax) {
         if (a_f32) throw Error{-1, "eig_herm: matrices above order 8 must be FP64"};
-        hipLaunchKernelGGL(k_eig_wg, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals, evecs);
+        if (n <= kWgLds)
+            hipLaunchKernelGGL(k_eig_wg<true>, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
+                               evecs);
+        else
+            hipLaunchKernelGGL(k_eig_wg<false>, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
+                               evecs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
         return;
