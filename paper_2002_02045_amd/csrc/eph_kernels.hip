@@ -247,30 +247,107 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
         }
     const T is = (T)(1.0 / e.sigma), nrm = (T)(1.0 / (sqrt(kPi) * e.sigma));
 
-    for (int ql = q0; ql < q1; ++ql) {
+    // Per-pair inputs: with fixed sizes, the next pair's are loaded into
+    // registers while the current pair is computed (one pair of prefetch), so
+    // the loads' latency overlaps the arithmetic; the runtime-sized fallback
+    // loads them in place.
+    constexpr bool kPre = NW > 0 && NM > 0;
+    constexpr int GPL = kPre ? (NM * NW * NW + 63) / 64 : 1;   // g' elements per lane
+    constexpr int UPL = kPre ? (NW * NW + 63) / 64 : 1;        // U elements per lane
+    constexpr int EPL = kPre ? (NM * NM + 63) / 64 : 1;        // e(q) elements per lane
+    cx<T> rg[GPL], ru[UPL];
+    double rom_es[EPL], rev_r[EPL], rev_i[EPL], rom = 0.0, rem = 0.0;
+    auto fetch = [&](int ql) {
         const long qg = (long)e.q_off + ql;
         const long pair = (long)z * e.nq + ql;
         const T* gp = gwz + (long)ql * ng * 2;
         const double* uq = e.ukq + pair * nw2 * 2;
-        for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
-        for (int i = lane; i < nw2; i += 64) s_u[i] = ldd<T>(uq, i);
-        for (int i = lane; i < nm * nm; i += 64) {
-            const int x = i / nm, nu = i % nm;
-            const double om = e.omega[qg * nm + nu];
-            const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
-            s_es[i] = {(T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu)]), (T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu) + 1])};
+#pragma unroll
+        for (int j = 0; j < GPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < ng) rg[j] = ld(gp, i);
+        }
+#pragma unroll
+        for (int j = 0; j < UPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < nw2) ru[j] = ldd<T>(uq, i);
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < nm * nm) {
+                const int x = i / nm, nu = i % nm;
+                rom_es[j] = e.omega[qg * nm + nu];
+                rev_r[j] = e.evec[2 * ((qg * nm + x) * nm + nu)];
+                rev_i[j] = e.evec[2 * ((qg * nm + x) * nm + nu) + 1];
+            }
+        }
+        if (lane < nm) rom = e.omega[qg * nm + lane];
+        if (RATES && lane < nw) rem = e.ekq[pair * nw + lane];
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int j = 0; j < GPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < ng) s_gw[i] = rg[j];
+        }
+#pragma unroll
+        for (int j = 0; j < UPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < nw2) s_u[i] = ru[j];
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            const int i = lane + 64 * j;
+            if (i < nm * nm) {
+                const int x = i / nm;
+                const double om = rom_es[j];
+                const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
+                s_es[i] = {(T)(amp * rev_r[j]), (T)(amp * rev_i[j])};
+            }
         }
         if (lane < nm) {
-            const double om = e.omega[qg * nm + lane];
-            s_om[lane] = om;
-            s_nb[lane] = om > e.omega_cut ? 1.0 / expm1(om / kt) : 0.0;
+            s_om[lane] = rom;
+            s_nb[lane] = rom > e.omega_cut ? 1.0 / expm1(rom / kt) : 0.0;
         }
         if (RATES && lane < nw) {
-            const double em = e.ekq[pair * nw + lane];
-            s_em[lane] = em;
-            s_fm[lane] = 1.0 / (exp((em - e.mu) / kt) + 1.0);
+            s_em[lane] = rem;
+            s_fm[lane] = 1.0 / (exp((rem - e.mu) / kt) + 1.0);
         }
-        __syncthreads();
+    };
+    if (kPre && q0 < q1) fetch(q0);
+
+    for (int ql = q0; ql < q1; ++ql) {
+        const long qg = (long)e.q_off + ql;
+        if constexpr (kPre) {
+            stage();
+            __syncthreads();
+            if (ql + 1 < q1) fetch(ql + 1);
+        } else {
+            const long pair = (long)z * e.nq + ql;
+            const T* gp = gwz + (long)ql * ng * 2;
+            const double* uq = e.ukq + pair * nw2 * 2;
+            for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
+            for (int i = lane; i < nw2; i += 64) s_u[i] = ldd<T>(uq, i);
+            for (int i = lane; i < nm * nm; i += 64) {
+                const int x = i / nm, nu = i % nm;
+                const double om = e.omega[qg * nm + nu];
+                const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
+                s_es[i] = {(T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu)]),
+                           (T)(amp * e.evec[2 * ((qg * nm + x) * nm + nu) + 1])};
+            }
+            if (lane < nm) {
+                const double om = e.omega[qg * nm + lane];
+                s_om[lane] = om;
+                s_nb[lane] = om > e.omega_cut ? 1.0 / expm1(om / kt) : 0.0;
+            }
+            if (RATES && lane < nw) {
+                const double em = e.ekq[pair * nw + lane];
+                s_em[lane] = em;
+                s_fm[lane] = 1.0 / (exp((em - e.mu) / kt) + 1.0);
+            }
+            __syncthreads();
+        }
         const double wq = RATES ? (e.qw ? e.qw[qg] : e.uniform_w) : 0.0;
 #pragma unroll
         for (int t = 0; t < EPT; ++t) {
