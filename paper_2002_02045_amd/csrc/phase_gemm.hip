@@ -78,7 +78,10 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
     const NT* nvec = reinterpret_cast<const NT*>(nvec_);
     constexpr int BN = 16 * CB;
     constexpr int NB = HERM ? 2 : 1;
-    __shared__ T bs[kKC][BN][2 * NB];
+    // component-major rows: the 16 lanes of a read phase take 16 consecutive
+    // columns of one component, one contiguous run of LDS words (no bank
+    // conflicts; a column-major [BN][components] layout had 3.7 per read)
+    __shared__ T bs[kKC][2 * NB][BN];
     __shared__ NT ns[kKC][3];
     const int z = blockIdx.z;
     const int row0 = blockIdx.y * kBM;
@@ -122,8 +125,8 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
                     re = bz[off];
                     im = bz[off + 1];
                 }
-                bs[kk][nn][2 * h] = re;
-                bs[kk][nn][2 * h + 1] = im;
+                bs[kk][2 * h][nn] = re;
+                bs[kk][2 * h + 1][nn] = im;
             }
         }
         if (tid < kKC * 3) {
@@ -139,11 +142,11 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
             const T nps = -ps;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                const T bre = bs[kk][cb * 16 + li][0];
-                const T bim = bs[kk][cb * 16 + li][1];
+                const T bre = bs[kk][0][cb * 16 + li];
+                const T bim = bs[kk][1][cb * 16 + li];
                 if (HERM) {
-                    const T b2re = bs[kk][cb * 16 + li][2 * NB - 2];
-                    const T b2im = bs[kk][cb * 16 + li][2 * NB - 1];
+                    const T b2re = bs[kk][2 * NB - 2][cb * 16 + li];
+                    const T b2im = bs[kk][2 * NB - 1][cb * 16 + li];
                     are[cb] = mfma(pc, bre, are[cb]);
                     are[cb] = mfma(ps, b2re, are[cb]);
                     aim[cb] = mfma(pc, bim, aim[cb]);
