@@ -37,6 +37,7 @@
 #ifndef EPHX_H
 #define EPHX_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -150,6 +151,27 @@ int ephx_phonons(ephx_model* m, int nq, const double* q_red, double* omega, doub
  * omega <= omega_cut are zero. */
 int ephx_gkq(ephx_model* m, int nk, const double* k_red, int nq, const double* q_red,
              int precision, double omega_cut, void* g2, void* stream);
+
+/* |g_mn,nu(k,q)|^2 for a list of (k, q) pairs instead of the outer product:
+ * pair j is (k_red[ik[j]], q_red[iq[j]]).  ik, iq: host int32 [npairs], each
+ * index in range (else EPHX_EINVAL); k_red device [nk][3], q_red device
+ * [nq][3].  g2 device [npairs][3nat][nw][nw] (double for EPHX_FP64, float
+ * otherwise), the values of ephx_gkq for those pairs.  Pairs are processed
+ * grouped by k (each group one k against its q list), so the call is efficient
+ * when many pairs share a k.  Synchronises `stream` before returning. */
+int ephx_gkq_pairs(ephx_model* m, int nk, const double* k_red, int nq, const double* q_red, int npairs,
+                   const int32_t* ik, const int32_t* iq, int precision, double omega_cut, void* g2,
+                   void* stream);
+
+/* Device bytes of the work buffers that one ephx_gkq (call = EPHX_CALL_GKQ)
+ * or ephx_rates (EPHX_CALL_RATES) call of nk k points and nq q points at the
+ * given precision takes from the model's workspace (kept by the model for
+ * later calls, released by ephx_model_destroy); inputs and outputs are the
+ * caller's and not counted.  For ephx_gkq_pairs, query EPHX_CALL_GKQ with
+ * nk = 1 and nq = the largest number of pairs sharing one k. */
+#define EPHX_CALL_GKQ 0
+#define EPHX_CALL_RATES 1
+int ephx_workspace_query(ephx_model* m, int call, int nk, int nq, int precision, size_t* bytes);
 
 /* Scattering rates, Eqs. scatter_rate and BTE_W, summed over the q list with
  * weights q_w (device [nq], or NULL for 1/nq each):

@@ -75,6 +75,8 @@ _SIGS = {
     "ephx_collision": ([_P, _P, _P, _P], _I),
     "ephx_dynamics": ([_P, _P, _D, _I, _I, _P, _P, _P], _I),
     "ephx_dynamics_field": ([_P, _P, _D, _I, _I, _P, _I, _P, _P, _P], _I),
+    "ephx_gkq_pairs": ([_P, _I, _P, _I, _P, _I, _P, _P, _I, _D, _P, _P], _I),
+    "ephx_workspace_query": ([_P, _I, _I, _I, _I, _P], _I),
     "ephx_table_stream_info": ([_P, _I, _P, _P, _P, _P], _I),
     "ephx_collision_vjp": ([_P, _P, _P, _P, _P, _P], _I),
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),

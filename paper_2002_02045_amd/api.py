@@ -129,6 +129,31 @@ def gkq(model, k, q, precision="fp64", omega_cut=1e-4, out=None):
     return out
 
 
+def gkq_pairs(model, k, q, ik, iq, precision="fp64", omega_cut=1e-4):
+    """|g|^2 of the pairs (k[ik[j]], q[iq[j]]) as (npairs, nmodes, nw, nw)."""
+    p = _prec(precision)
+    kt, qt = _pts(k), _pts(q)
+    ik = np.ascontiguousarray(ik, dtype=np.int32)
+    iq = np.ascontiguousarray(iq, dtype=np.int32)
+    if ik.shape != iq.shape or ik.ndim != 1:
+        raise ValueError("ik and iq must be 1-D of the same length")
+    out = torch.empty((len(ik), model.nmodes, model.nw, model.nw), dtype=F64 if p == FP64 else torch.float32,
+                      device="cuda")
+    check(lib.ephx_gkq_pairs(model.handle, kt.shape[0], ptr(kt), qt.shape[0], ptr(qt), len(ik),
+                             ik.ctypes.data_as(C.c_void_p), iq.ctypes.data_as(C.c_void_p), p, float(omega_cut),
+                             ptr(out), stream_ptr()))
+    return out
+
+
+def workspace_query(model, call, nk, nq, precision="fp64"):
+    """Device bytes of the work buffers one gkq ("gkq") or rates ("rates") call of
+    nk x nq takes from the model's workspace."""
+    n = C.c_size_t(0)
+    check(lib.ephx_workspace_query(model.handle, {"gkq": 0, "rates": 1}[call], int(nk), int(nq), _prec(precision),
+                                   C.byref(n)))
+    return int(n.value)
+
+
 def rates(model, k, q, params, precision="fp64", q_weights=None, mode_resolved=True):
     """Scattering rates (nk, nw) in 1/fs and, optionally, per mode (nk, nw, nmodes)."""
     p = _prec(precision)

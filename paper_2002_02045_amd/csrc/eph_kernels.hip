@@ -685,6 +685,41 @@ void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {
 
 int eph_epilogue_blocks(int nq) { return (nq + kQPB - 1) / kQPB; }
 
+namespace {
+__global__ void k_gather_points(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                                double* __restrict__ dst) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const long i = idx[j];
+    dst[3L * j] = src[3 * i];
+    dst[3L * j + 1] = src[3 * i + 1];
+    dst[3L * j + 2] = src[3 * i + 2];
+}
+
+__global__ void k_scatter_blocks(int n, const int32_t* __restrict__ pos, const uint32_t* __restrict__ src,
+                                 uint32_t* __restrict__ dst, long words) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * words) return;
+    const long j = e / words, w = e % words;
+    dst[(long)pos[j] * words + w] = src[e];
+}
+}  // namespace
+
+void gather_points(int n, const int32_t* idx, const double* src, double* dst, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_points, dim3((n + 255) / 256), dim3(256), 0, st, n, idx, src, dst);
+    check_launch("gather_points");
+}
+
+void scatter_blocks(int n, const int32_t* pos, const void* src, void* dst, long words, hipStream_t st) {
+    if (n <= 0 || words <= 0) return;
+    const long total = (long)n * words;
+    if ((total + 255) / 256 > 0x7fffffffL) throw Error{-1, "scatter_blocks: too large"};
+    hipLaunchKernelGGL(k_scatter_blocks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, pos,
+                       (const uint32_t*)src, (uint32_t*)dst, words);
+    check_launch("scatter_blocks");
+}
+
 void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
     const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);

@@ -1,11 +1,13 @@
 // Host side of the C ABI declared in include/ephx.h: argument checks, model
 // upload, work buffers and the orchestration of the kernels for bands,
 // phonons, g(k,q) and scattering rates.  BTE entry points live in bte_api.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -473,13 +475,68 @@ void phonons_impl(ephx_model* m, int nq, const double* q, double* omega, double*
 }
 
 // Shared driver of ephx_gkq (rates == false) and ephx_rates (rates == true).
+// Batch shape of the rates / |g|^2 driver: bk_eff k points x qc q points per
+// inner step, and the sizes of its work buffers.
+struct DriverPlan {
+    int nw, nm, nw2, bk_eff, qc, kp, nsplit;
+    long ngcol, nre_cols;
+    bool f32, wide;
+    size_t npair;
+};
+
+DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
+    DriverPlan d{};
+    d.nw = m->nw;
+    d.nm = m->nm;
+    d.nw2 = d.nw * d.nw;
+    d.ngcol = (long)d.nm * d.nw2;                    // columns of the Rp contraction
+    d.nre_cols = (long)m->n_rp_g * d.ngcol;          // columns of the Re contraction
+    d.f32 = precision != EPHX_FP64;
+    const int bk = std::max(1, std::min(nk, std::max(1, (int)(((size_t)3 << 30) / (d.nre_cols * 16 * 2)))));
+    // large models: the per-pair blocks (nm nw^2 complex, twice) set the chunk size
+    d.wide = d.nw > kMaxNw || d.nm > kMaxModes;
+    const long pair_bytes = d.ngcol * (d.f32 ? 8 : 16) * 2 + (long)d.nw2 * 48;
+    const long wide_pairs = std::max(16L, (6L << 30) / pair_bytes);
+    d.bk_eff = std::min(bk, 16);
+    if (d.wide) d.bk_eff = std::max(1, std::min<int>(d.bk_eff, (int)(wide_pairs / 16)));
+    const long pairs_target = d.wide ? wide_pairs : 1L << 19;
+    d.qc = (int)std::max(d.wide ? 1L : 64L, std::min((long)std::max(nq, 1), pairs_target / d.bk_eff));
+    d.kp = ((m->n_rp_g + 31) / 32) * 32;
+    d.nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+    d.npair = (size_t)d.bk_eff * d.qc;
+    return d;
+}
+
+// Bytes of the driver's work buffers for one call of this shape (the buffers
+// eph_driver, and the band and phonon interpolation it calls, take from the
+// model's workspace).
+size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, bool rates) {
+    const size_t nm = d.nm, nw = d.nw, nw2 = d.nw2;
+    size_t b = (size_t)nq * nm * 8 + (size_t)nq * nm * nm * 16;          // omega, e
+    if (m->polar) b += (size_t)nq * nm * 16;                              // long-range term
+    b += (size_t)std::min(nq, 1 << 17) * nm * nm * 16;                    // D(q) chunk
+    b += (size_t)d.bk_eff * (nw * 8 + nw2 * 16 + nw2 * 16);               // eps(k), U(k), H(k)
+    b += (size_t)d.bk_eff * d.nre_cols * 16 * 2;                          // g(k,Rp), g(k,Rp) U(k)
+    if (!d.nsplit && d.f32) b += (size_t)d.bk_eff * d.nre_cols * 8;
+    if (d.nsplit) {
+        b += (size_t)d.bk_eff * 2 * d.nsplit * d.ngcol * d.kp * 2;        // B planes
+        b += (size_t)2 * d.nsplit * d.qc * d.kp * 2;                      // phase planes
+    }
+    b += d.npair * (nw2 * 16 + nw * 8 + nw2 * 16);                        // H(k+q), eps, U
+    b += d.npair * d.ngcol * (d.f32 ? 8 : 16) * (d.wide ? 2 : 1);         // g^W (and g^H)
+    if (d.wide) b += (size_t)d.qc * nm * nm * 16 + (m->polar ? d.npair * nw2 * 16 : 0);
+    if (rates) b += (size_t)d.bk_eff * eph_epilogue_blocks(d.qc) * nw * nm * 8 + (size_t)d.bk_eff * nw * nm * 8;
+    return b;
+}
+
 void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q, int precision,
                 double omega_cut, void* g2, const ephx_params* p, const double* qw, double* gamma,
                 double* gmode, hipStream_t st) {
-    const int nw = m->nw, nm = m->nm, nw2 = nw * nw;
-    const long ngcol = (long)nm * nw2;                 // columns of the Rp contraction
-    const long nre_cols = (long)m->n_rp_g * ngcol;     // columns of the Re contraction
-    const bool f32 = precision != EPHX_FP64;
+    const DriverPlan dp = driver_plan(m, nk, nq, precision);
+    const int nw = dp.nw, nm = dp.nm, nw2 = dp.nw2;
+    const long ngcol = dp.ngcol;
+    const long nre_cols = dp.nre_cols;
+    const bool f32 = dp.f32;
     // phonons (and the long-range term) at every q of the call
     double* om = (double*)m->ws.get("drv.omega", (size_t)nq * nm * 8);
     double* ev = (double*)m->ws.get("drv.evec", (size_t)nq * nm * nm * 16);
@@ -492,17 +549,11 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         lr = (double*)m->ws.get("drv.lr", (size_t)nq * nm * 16);
         frohlich(nq, q, m->pd, lr, st);
     }
-    // batch sizes: Bk k points x Qc q points per inner step
-    const int bk = std::max(1, std::min(nk, std::max(1, (int)(((size_t)3 << 30) / (nre_cols * 16 * 2)))));
-    // large models: the per-pair blocks (nm nw^2 complex, twice) set the chunk size
-    const bool wide = nw > kMaxNw || nm > kMaxModes;
-    const long pair_bytes = ngcol * (f32 ? 8 : 16) * 2 + (long)nw2 * 48;
-    const long wide_pairs = std::max(16L, (6L << 30) / pair_bytes);
-    int bk_eff = std::min(bk, 16);
-    if (wide) bk_eff = std::max(1, std::min<int>(bk_eff, (int)(wide_pairs / 16)));
-    const long pairs_target = wide ? wide_pairs : 1L << 19;
-    const int qc = (int)std::max(wide ? 1L : 64L, std::min((long)nq, pairs_target / bk_eff));
-    const int kp = ((m->n_rp_g + 31) / 32) * 32;
+    // batch sizes: bk_eff k points x qc q points per inner step
+    const bool wide = dp.wide;
+    const int bk_eff = dp.bk_eff;
+    const int qc = dp.qc;
+    const int kp = dp.kp;
 
     double* ek = (double*)m->ws.get("drv.ek", (size_t)bk_eff * nw * 8);
     double* uk = (double*)m->ws.get("drv.uk", (size_t)bk_eff * nw2 * 16);
@@ -511,13 +562,13 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     float* gp32 = nullptr;
     uint16_t* gpbf = nullptr;
     if (precision == EPHX_FP32) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
-    const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+    const int nsplit = dp.nsplit;
     uint16_t* qpl = nullptr;
     if (nsplit) {
         gpbf = (uint16_t*)m->ws.get("drv.gpbf", (size_t)bk_eff * 2 * nsplit * ngcol * kp * 2);
         qpl = (uint16_t*)m->ws.get("drv.qpl", (size_t)2 * nsplit * qc * kp * 2);
     }
-    const size_t npair = (size_t)bk_eff * qc;
+    const size_t npair = dp.npair;
     void* hkq = m->ws.get("drv.hkq", npair * nw2 * 16);
     double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
     double* ukq = (double*)m->ws.get("drv.ukq", npair * nw2 * 16);
@@ -817,6 +868,66 @@ extern "C" int ephx_gkq(ephx_model* m, int nk, const double* k_red, int nq, cons
         check_precision(precision);
         eph_driver(m, nk, k_red, nq, q_red, precision, omega_cut, g2, nullptr, nullptr, nullptr, nullptr,
                    (hipStream_t)stream);
+    });
+}
+
+extern "C" int ephx_gkq_pairs(ephx_model* m, int nk, const double* k_red, int nq, const double* q_red, int npairs,
+                              const int32_t* ik, const int32_t* iq, int precision, double omega_cut, void* g2,
+                              void* stream) {
+    return guarded([&] {
+        require(m != nullptr, "gkq_pairs: null model");
+        require(nk >= 0 && nq >= 0 && npairs >= 0, "gkq_pairs: negative size");
+        if (npairs == 0) return;
+        require(k_red && q_red && ik && iq && g2, "gkq_pairs: null array");
+        require(std::isfinite(omega_cut), "gkq_pairs: omega_cut not finite");
+        check_precision(precision);
+        for (int j = 0; j < npairs; ++j)
+            require(0 <= ik[j] && ik[j] < nk && 0 <= iq[j] && iq[j] < nq, "gkq_pairs: pair index out of range");
+        hipStream_t st = (hipStream_t)stream;
+        // pairs grouped by k (stable): each group is one k against its q list
+        std::vector<int32_t> order(npairs);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ik[a] < ik[b]; });
+        std::vector<int32_t> qsel(npairs);
+        for (int j = 0; j < npairs; ++j) qsel[j] = iq[order[j]];
+        int32_t* d_qsel = (int32_t*)m->ws.get("gp.qsel", (size_t)npairs * 4);
+        int32_t* d_pos = (int32_t*)m->ws.get("gp.pos", (size_t)npairs * 4);
+        double* d_q = (double*)m->ws.get("gp.q", (size_t)npairs * 3 * 8);
+        hip_check(hipMemcpyAsync(d_qsel, qsel.data(), (size_t)npairs * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(d_pos, order.data(), (size_t)npairs * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        gather_points(npairs, d_qsel, q_red, d_q, st);
+        const long words = (long)m->nm * m->nw * m->nw * (precision == EPHX_FP64 ? 2 : 1);
+        int gmax = 0;
+        for (int a = 0; a < npairs;) {
+            int b = a;
+            while (b < npairs && ik[order[b]] == ik[order[a]]) ++b;
+            gmax = std::max(gmax, b - a);
+            a = b;
+        }
+        void* tmp = m->ws.get("gp.out", (size_t)gmax * words * 4);
+        for (int a = 0; a < npairs;) {
+            int b = a;
+            while (b < npairs && ik[order[b]] == ik[order[a]]) ++b;
+            eph_driver(m, 1, k_red + 3L * ik[order[a]], b - a, d_q + 3L * a, precision, omega_cut, tmp, nullptr,
+                       nullptr, nullptr, nullptr, st);
+            scatter_blocks(b - a, d_pos + a, tmp, g2, words, st);
+            a = b;
+        }
+        // the host index arrays above are read by the copies queued on st
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+extern "C" int ephx_workspace_query(ephx_model* m, int call, int nk, int nq, int precision, size_t* bytes) {
+    return guarded([&] {
+        require(m != nullptr && bytes != nullptr, "workspace_query: null argument");
+        require(call == EPHX_CALL_GKQ || call == EPHX_CALL_RATES, "workspace_query: unknown call");
+        require(nk >= 0 && nq >= 0, "workspace_query: negative size");
+        check_precision(precision);
+        *bytes = 0;
+        if (nk == 0 || nq == 0) return;
+        const DriverPlan d = driver_plan(m, nk, nq, precision);
+        *bytes = driver_workspace_bytes(m, d, nq, call == EPHX_CALL_RATES);
     });
 }
 

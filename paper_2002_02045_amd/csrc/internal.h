@@ -121,6 +121,10 @@ void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st);
 void eph_adjoint_epilogue(const EphEpilogue& e, const double* lam, double* gw_bar, hipStream_t st);
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st);
 int eph_epilogue_blocks(int nq);
+// dst[j][0..2] = src[idx[j]][0..2] (double points)
+void gather_points(int n, const int32_t* idx, const double* src, double* dst, hipStream_t st);
+// block pos[j] of dst = block j of src, blocks of `words` 32-bit words
+void scatter_blocks(int n, const int32_t* pos, const void* src, void* dst, long words, hipStream_t st);
 // acc[z][n][nu] += sum_b partial[z][b][n][nu]
 void rates_reduce(int nkb, int nblk, int nw, int nm, const double* partial, double* acc,
                   hipStream_t st);

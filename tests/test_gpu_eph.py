@@ -287,3 +287,44 @@ def test_cauchy_sampled_rates(lib):
     _say("  states %d, max |z| %.2f, variance ratio uniform/Cauchy median %.2f"
          % (int(live.sum()), float(z.max()), float(np.median(ratio))))
     assert float(z.max()) <= 5.0
+
+
+def test_gkq_pairs_parity(lib, tiny):
+    """The pair-list form of |g|^2: arbitrary (k, q) pairs, repeated k and q,
+    unsorted, against the oracle pair by pair."""
+    m, dm = tiny
+    k = synth.random_points(151, 5)
+    q = synth.random_points(152, 40)
+    rng = np.random.default_rng(153)
+    ik = rng.integers(0, 5, 70).astype(np.int32)
+    iq = rng.integers(0, 40, 70).astype(np.int32)
+    blk = eph.eph_pipeline(m, k, q)
+    g = blk["g"].abs() ** 2                                   # [k][q][nu][m][n]
+    ref_all = group_sums_g2(g, blk["eps_k"], blk["eps_kq"], blk["omega"])
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)):
+        got = lib.gkq_pairs(dm, k, q, ik, iq, precision=prec).double().cpu()
+        # place each pair's block in an outer-product array to reuse the group sums
+        full = torch.zeros_like(g)
+        full[torch.as_tensor(ik, dtype=torch.long), torch.as_tensor(iq, dtype=torch.long)] = got
+        gs = group_sums_g2(full, blk["eps_k"], blk["eps_kq"], blk["omega"])
+        sel = (torch.as_tensor(ik, dtype=torch.long), torch.as_tensor(iq, dtype=torch.long))
+        d = (gs[sel] - ref_all[sel]).abs().flatten(1).max(dim=1).values
+        s = ref_all[sel].abs().flatten(1).max(dim=1).values
+        err = float((d / s.clamp_min(1e-300)).max())
+        _say("  gkq_pairs error %s: %.3e" % (prec, err))
+        assert err <= tol
+    with pytest.raises(lib.EphxError):
+        lib.gkq_pairs(dm, k, q, np.array([5], np.int32), np.array([0], np.int32))
+
+
+def test_workspace_query(lib, tiny):
+    m, dm = tiny
+    b1 = lib.workspace_query(dm, "gkq", 4, 1000, "fp32")
+    b2 = lib.workspace_query(dm, "gkq", 4, 100000, "fp32")
+    br = lib.workspace_query(dm, "rates", 4, 100000, "fp32")
+    bb = lib.workspace_query(dm, "gkq", 4, 100000, "bf16x6")
+    assert 0 < b1 < b2 <= br
+    assert bb > 0
+    assert lib.workspace_query(dm, "gkq", 0, 10, "fp64") == 0
+    with pytest.raises(lib.EphxError):
+        lib.workspace_query(dm, "gkq", -1, 10, "fp64")
