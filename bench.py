@@ -38,7 +38,7 @@ def _parse():
     ap.add_argument("--dyn-states", type=int, default=20_000)
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="first run a 1 GiB device fill and a 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--cell-k", type=int, default=8, help="k points of the large-cell slice (0: skip)")
+    ap.add_argument("--cell-k", type=int, default=32, help="k points of the large-cell slice (0: skip)")
     ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
     return ap.parse_args()
 
