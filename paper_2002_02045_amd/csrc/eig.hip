@@ -32,11 +32,13 @@ __device__ __forceinline__ int xlane(int v) {
     static_assert(X >= 0 && X < 8, "lane offset");
     constexpr int kQuad = X == 1 || X == 6 ? 0xB1 : (X == 2 || X == 5 ? 0x4E : 0x1B);   // XOR 1, 2, 3
     constexpr int kMirror = 0x141;                                                      // lane -> 7 - lane
+    // every lane has a source under these permutations, so the destination is
+    // written in full (bound_ctrl set: no "old" value has to be placed first)
     if (X == 0) return v;
-    if (X <= 3) return __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, false);
-    if (X == 7) return __builtin_amdgcn_update_dpp(0, v, kMirror, 0xF, 0xF, false);
-    const int w = __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, false);   // X ^ 7 in {3, 2, 1}
-    return __builtin_amdgcn_update_dpp(0, w, kMirror, 0xF, 0xF, false);
+    if (X <= 3) return __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, true);
+    if (X == 7) return __builtin_amdgcn_update_dpp(0, v, kMirror, 0xF, 0xF, true);
+    const int w = __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, true);   // X ^ 7 in {3, 2, 1}
+    return __builtin_amdgcn_update_dpp(0, w, kMirror, 0xF, 0xF, true);
 }
 template <int X>
 __device__ __forceinline__ double xlane(double v) {
