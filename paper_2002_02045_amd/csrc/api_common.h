@@ -73,6 +73,8 @@ struct ephx_model {
     int n_re_half = 0;           // Hermitian half set: R = 0 and one of each +/-R pair
     int32_t* d_re_half = nullptr;
     double* d_h_half = nullptr;  // [n_re_half][2][nw*nw] complex: H+H^dag, i(H-H^dag)
+    int h_pack = 0;              // reals per packed Hermitian matrix: nw*nw rounded up to even
+    double* d_h_pack = nullptr;  // [n_re_half][2][h_pack]: the same, packed (nw <= 8 only)
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
     double* d_minv = nullptr;    // [nm]

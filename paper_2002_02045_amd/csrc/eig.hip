@@ -175,7 +175,11 @@ __device__ __forceinline__ void for_offsets(F&& f) {
     }
 }
 
-template <typename Tin, int N>
+// PK = false: A holds n*n complex entries per matrix (stride strideA complex
+// elements) and the Hermitian part 0.5 (A + A^dag) is taken.  PK = true: A
+// holds the packed Hermitian form, n*n reals per matrix (stride strideA reals)
+// with P[i][j] = Re X_ij for i <= j and P[i][j] = Im X_ji for i > j.
+template <typename Tin, int N, bool PK = false>
 __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restrict__ A, long strideA,
                                                   double* __restrict__ evals, double* __restrict__ evecs) {
     constexpr int R = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
@@ -190,7 +194,19 @@ __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restri
         a[d] = Cx{0.0, 0.0};
         v[d] = Cx{d == 0 ? 1.0 : 0.0, 0.0};
     }
-    if (act) {
+    if (act && PK) {
+        const Tin* ab = A + slot * strideA;
+#pragma unroll
+        for (int d = 0; d < R; ++d) {
+            const int j = i ^ d;
+            if (j < N) {
+                const int lo = i < j ? i : j, hi = i < j ? j : i;
+                const double re = (double)ab[lo * N + hi];
+                const double im = d == 0 ? 0.0 : (i < j ? 1.0 : -1.0) * (double)ab[hi * N + lo];
+                a[d] = Cx{re, im};
+            }
+        }
+    } else if (act) {
         const Tin* ab = A + slot * strideA * 2;
 #pragma unroll
         for (int d = 0; d < R; ++d) {
@@ -416,14 +432,16 @@ __global__ void k_phonon_omega(long count, double* lam) {
     lam[t] = (w2 >= 0.0 ? 1.0 : -1.0) * sqrt(fabs(w2));
 }
 
-template <typename Tin>
+template <typename Tin, bool PK = false>
 void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, double* evecs, hipStream_t st) {
     const int R = n <= 1 ? 1 : (n <= 2 ? 2 : (n <= 4 ? 4 : 8));
     const long threads = (long)batch * R;
     dim3 grid((unsigned)((threads + 255) / 256));
     switch (n) {
 #define EPHX_EIG_CASE(NN) \
-    case NN: hipLaunchKernelGGL((k_eig_rows<Tin, NN>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); break;
+    case NN:                                                                                                \
+        hipLaunchKernelGGL((k_eig_rows<Tin, NN, PK>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); \
+        break;
         EPHX_EIG_CASE(1)
         EPHX_EIG_CASE(2)
         EPHX_EIG_CASE(3)
@@ -460,6 +478,15 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
         launch_eig(batch, n, (const double*)A, strideA, evals, evecs, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
+}
+
+void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, hipStream_t st) {
+    if (batch <= 0) return;
+    if (n < 1 || n > kEigMax) throw Error{-6, "eig_herm_packed: matrix order must be 1..8"};
+    if (strideP < (long)n * n) throw Error{-1, "eig_herm_packed: stride below n*n"};
+    launch_eig<double, true>(batch, n, P, strideP, evals, evecs, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{-3, std::string("eig_herm_packed: ") + hipGetErrorString(e)};
 }
 
 void phonon_omega(long count, double* lam, hipStream_t st) {

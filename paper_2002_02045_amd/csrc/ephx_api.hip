@@ -320,6 +320,22 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                 m->n_re_half = (int)(rh.size() / 3);
                 m->d_re_half = (int32_t*)up(rh.data(), rh.size() * sizeof(int32_t));
                 m->d_h_half = (double*)up(hh.data(), hh.size() * sizeof(double));
+                if (nw <= kEigMax) {
+                    // packed form of each Hermitian A_r, B_r: Re of the upper triangle
+                    // (diagonal included) in place, Im of the upper triangle mirrored
+                    // into the lower one, padded to an even count
+                    const int pk = nw2 + (nw2 & 1);
+                    std::vector<double> hp((size_t)m->n_re_half * 2 * pk, 0.0);
+                    for (size_t rp = 0; rp < (size_t)m->n_re_half * 2; ++rp)
+                        for (int i = 0; i < nw; ++i)
+                            for (int j = 0; j < nw; ++j) {
+                                const int lo = i < j ? i : j, hi = i < j ? j : i;
+                                const double* x = &hh[(rp * nw2 + lo * nw + hi) * 2];
+                                hp[rp * pk + i * nw + j] = i <= j ? x[0] : x[1];
+                            }
+                    m->h_pack = pk;
+                    m->d_h_pack = (double*)up(hp.data(), hp.size() * sizeof(double));
+                }
             }
             m->d_hvel = (double*)up(hv.data(), hv.size() * sizeof(double));
             // C(R) / sqrt(M_k M_k') as complex, weights folded
@@ -510,6 +526,32 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
 // Bytes of the driver's work buffers for one call of this shape (the buffers
 // eph_driver, and the band and phonon interpolation it calls, take from the
 // model's workspace).
+// H(k+q) of every pair of a (k batch) x (q chunk) block, pair index k * nq + q,
+// and its eigenpairs, in FP64.  With the packed half set (nw <= 8) the phases of
+// the k batch are folded into the coefficients once per batch (hfold) and each
+// H(k+q) is formed as nw*nw packed reals: one cos/sin(2 pi q.R) serves every k
+// and the Hermitian output needs half the products of the complex one.
+static void hkq_fold(ephx_model* m, int nb, const double* kb, double* hfold, hipStream_t st) {
+    if (m->d_h_pack) fold_herm_f64(nb, kb, m->n_re_half, m->d_re_half, m->h_pack, m->d_h_pack, hfold, st);
+}
+static void hkq_fourier(ephx_model* m, int nb, const double* kb, const double* hfold, int nq, const double* qb,
+                        double* hkq, hipStream_t st) {
+    const int nw2 = m->nw * m->nw;
+    if (m->d_h_pack)
+        phase_gemm_herm_groups_f64(nq, nb, m->h_pack, m->n_re_half, qb, m->d_re_half, hfold, hkq, st);
+    else
+        phase_gemm_herm_f64(nq, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, hkq, (long)nq * nw2, st);
+}
+static void hkq_eig(ephx_model* m, long npair, double* hkq, double* ekq, double* ukq, hipStream_t st) {
+    if (m->d_h_pack)
+        eig_herm_packed((int)npair, m->nw, hkq, m->h_pack, ekq, ukq, st);
+    else
+        eig_herm((int)npair, m->nw, hkq, 0, m->nw * m->nw, ekq, ukq, st);
+}
+static size_t hfold_bytes(const ephx_model* m, int nb) {
+    return m->d_h_pack ? (size_t)m->n_re_half * 2 * nb * m->h_pack * 8 : 0;
+}
+
 size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, bool rates) {
     const size_t nm = d.nm, nw = d.nw, nw2 = d.nw2;
     size_t b = (size_t)nq * nm * 8 + (size_t)nq * nm * nm * 16;          // omega, e
@@ -523,6 +565,7 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
         b += (size_t)2 * d.nsplit * d.qc * d.kp * 2;                      // phase planes
     }
     b += d.npair * (nw2 * 16 + nw * 8 + nw2 * 16);                        // H(k+q), eps, U
+    b += hfold_bytes(m, d.bk_eff);                                        // k-folded half set
     b += d.npair * d.ngcol * (d.f32 ? 8 : 16) * (d.wide ? 2 : 1);         // g^W (and g^H)
     if (d.wide) b += (size_t)d.qc * nm * nm * 16 + (m->polar ? d.npair * nw2 * 16 : 0);
     if (rates) b += (size_t)d.bk_eff * eph_epilogue_blocks(d.qc) * nw * nm * 8 + (size_t)d.bk_eff * nw * nm * 8;
@@ -570,6 +613,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     }
     const size_t npair = dp.npair;
     void* hkq = m->ws.get("drv.hkq", npair * nw2 * 16);
+    double* hfold = (double*)m->ws.get("drv.hfold", hfold_bytes(m, bk_eff));
     double* ekq = (double*)m->ws.get("drv.ekq", npair * nw * 8);
     double* ukq = (double*)m->ws.get("drv.ukq", npair * nw2 * 16);
     void* gw = m->ws.get("drv.gw", npair * ngcol * (f32 ? 8 : 16));
@@ -587,6 +631,10 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         const int nb = std::min(bk_eff, nk - k0);
         const double* kb = k + 3L * k0;
         bands_impl(m, nb, kb, ek, uk, nullptr, st, "drv.bk");
+        {
+            StageTimer t("hkq_fourier", st);
+            hkq_fold(m, nb, kb, hfold, st);
+        }
         // Re contraction (FP64, amortised over all q), then U(k) on the right
         {
             StageTimer t("re_contraction", st);
@@ -604,12 +652,11 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             // ~1e-2 eV at the 1e-5 level of |g|^2.
             {
                 StageTimer t("hkq_fourier", st);
-                phase_gemm_herm_f64(nqc, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, (double*)hkq,
-                                    (long)nqc * nw2, st);
+                hkq_fourier(m, nb, kb, hfold, nqc, qb, (double*)hkq, st);
             }
             {
                 StageTimer t("eig_hkq", st);
-                eig_herm(nb * nqc, nw, hkq, 0, nw2, ekq, ukq, st);
+                hkq_eig(m, (long)nb * nqc, (double*)hkq, ekq, ukq, st);
             }
             // phases of the q chunk for the split-bf16 paths, shared by every k of the batch
             if (nsplit) {
@@ -752,6 +799,7 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
     double* gpb = (double*)m->ws.get("adj.gpb", (size_t)bk * nre_cols * 16);
     const size_t npair = (size_t)bk * qc;
     double* hkq = (double*)m->ws.get("adj.hkq", npair * nw2 * 16);
+    double* hfold = (double*)m->ws.get("adj.hfold", hfold_bytes(m, bk));
     double* ekq = (double*)m->ws.get("adj.ekq", npair * nw * 8);
     double* ukq = (double*)m->ws.get("adj.ukq", npair * nw2 * 16);
     double* gw = (double*)m->ws.get("adj.gw", npair * ngcol * 16);
@@ -763,12 +811,12 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
         bands_impl(m, nb, kb, ek, uk, nullptr, st, "adj.bk");
         phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
         apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
+        hkq_fold(m, nb, kb, hfold, st);
         for (int q0 = 0; q0 < nq; q0 += qc) {
             const int nqc = std::min(qc, nq - q0);
             const double* qb = q + 3L * q0;
-            phase_gemm_herm_f64(nqc, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, hkq,
-                                (long)nqc * nw2, st);
-            eig_herm(nb * nqc, nw, hkq, 0, nw2, ekq, ukq, st);
+            hkq_fourier(m, nb, kb, hfold, nqc, qb, hkq, st);
+            hkq_eig(m, (long)nb * nqc, hkq, ekq, ukq, st);
             phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, gw,
                            (long)nqc * ngcol, st);
             EphEpilogue e{};

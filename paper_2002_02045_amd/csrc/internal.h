@@ -51,6 +51,16 @@ void phase_gemm_adj_f64(int M, int N, int K, int Z, const double* x, const doubl
 // (A_r, B_r), real coefficients cos/sin of 2 pi (x_m + x0_z).n_r; B shared by all z.
 void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const double* x0,
                          const int32_t* nvec, const double* B, double* C, long sC, hipStream_t st);
+// H(k+q) for every (k, q) of a batch in the packed Hermitian form (n*n reals,
+// P[i][j] = Re H_ij for i <= j, Im H_ji for i > j), two steps:
+//  fold_herm_f64: hpack [Kh][2][P] (packed A_r, B_r; P = n*n rounded up to even)
+//    -> out [Kh][2][nk][P], the coefficients of the sum at k + q as a sum over q;
+//  phase_gemm_herm_groups_f64: C [nk][M][P] = sum_r cos/sin(2 pi x_m.n_r) out_r,
+//    one phase per (m, r) for all nk matrices (B given as [Kh][2][nk*P/2] complex).
+void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int P, const double* hpack, double* out,
+                   hipStream_t st);
+void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
+                                double* C, hipStream_t st);
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const float* B, long sB, float* C, long sC,
                     hipStream_t st);
@@ -75,6 +85,9 @@ void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, ui
 // double; for n > 8 A is overwritten.  evals [batch][n] ascending; evecs
 // [batch][n][n] complex double (column j = eigenvector j) or nullptr.
 void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals, double* evecs, hipStream_t st);
+// The same for n <= 8 from the packed Hermitian form: n*n reals per matrix
+// (stride strideP reals), P[i][j] = Re X_ij for i <= j, Im X_ji for i > j.
+void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, hipStream_t st);
 
 // omega_nu = sign(lam) sqrt(|hbar^2/amu/A^2 * lam|) in place.
 void phonon_omega(long count, double* lam, hipStream_t st);

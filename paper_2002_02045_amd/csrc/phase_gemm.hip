@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
                                                     const double* __restrict__ x0,
                                                     const void* __restrict__ nvec_,
                                                     const T* __restrict__ B, long sB,
-                                                    T* __restrict__ C, long sC) {
+                                                    T* __restrict__ C, long sC, int cg) {
     typedef typename AccOf<T>::type acc_t;
     typedef typename std::conditional<KD, double, int32_t>::type NT;
     const NT* nvec = reinterpret_cast<const NT*>(nvec_);
@@ -168,7 +168,9 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
         for (int v = 0; v < 4; ++v) {
             const int row = row0 + wave * 16 + AccOf<T>::row(lk, v);
             if (row < M && col < N) {
-                const long off = ((long)row * N + col) * 2;
+                // cg > 0: the columns are groups of cg (one matrix each), stored
+                // group-major as [N/cg][M][cg]
+                const long off = (cg > 0 ? ((long)(col / cg) * M + row) * cg + col % cg : (long)row * N + col) * 2;
                 cz[off] = ACC ? cz[off] + are[cb][v] : are[cb][v];
                 cz[off + 1] = ACC ? cz[off + 1] + aim[cb][v] : aim[cb][v];
             }
@@ -531,6 +533,30 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
     }
 }
 
+// Packed Hermitian form of an n x n Hermitian X: n*n reals with
+// P[i][j] = Re X_ij for i <= j and P[i][j] = Im X_ji for i > j.  The map is real
+// and linear, so real combinations of packed matrices are packed combinations.
+// Folding k into the half-set coefficients (angle addition): the sum at k + q,
+//   sum_r cos(2 pi (k+q).n_r) A_r + sin(2 pi (k+q).n_r) B_r,
+// is the same sum over q with
+//   A_r(k) = cos(2 pi k.n_r) A_r + sin(2 pi k.n_r) B_r,
+//   B_r(k) = cos(2 pi k.n_r) B_r - sin(2 pi k.n_r) A_r,
+// so one phase of q serves every k of a batch.  hpack: [Kh][2][P], out:
+// [Kh][2][nk][P]; one thread per output pair (r, k, e).
+__global__ void k_fold_herm(int nk, const double* __restrict__ kpts, int Kh, const int32_t* __restrict__ nvec, int P,
+                            const double* __restrict__ hpack, double* __restrict__ out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)Kh * nk * P) return;
+    const int e = (int)(t % P);
+    const long rk = t / P;
+    const int kk = (int)(rk % nk), r = (int)(rk / nk);
+    double c, s;
+    phase_of(reduced_arg(kpts[3 * kk], kpts[3 * kk + 1], kpts[3 * kk + 2], nvec + 3 * r), c, s);
+    const double a = hpack[(long)r * 2 * P + e], b = hpack[((long)r * 2 + 1) * P + e];
+    out[((long)r * 2 * nk + kk) * P + e] = fma(c, a, s * b);
+    out[(((long)r * 2 + 1) * nk + kk) * P + e] = fma(c, b, -s * a);
+}
+
 inline void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
@@ -551,9 +577,9 @@ void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x
     const int cb = pick_cb(N, 4);
     dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
     if (cb == 3)
-        hipLaunchKernelGGL((k_phase_gemm<double, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+        hipLaunchKernelGGL((k_phase_gemm<double, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     else
-        hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+        hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     check_launch("phase_gemm_f64");
 }
 
@@ -563,10 +589,10 @@ void phase_gemm_adj_f64(int M, int N, int K, int Z, const double* x, const doubl
     dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
     if (accumulate)
         hipLaunchKernelGGL((k_phase_gemm<double, 4, false, true, true>), grid, dim3(256), 0, st, M, N, K, x,
-                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC);
+                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC, 0);
     else
         hipLaunchKernelGGL((k_phase_gemm<double, 4, false, true, false>), grid, dim3(256), 0, st, M, N, K, x,
-                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC);
+                           (const double*)nullptr, (const void*)kpts, B, sB, C, sC, 0);
     check_launch("phase_gemm_adj_f64");
 }
 
@@ -574,8 +600,30 @@ void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const dou
                          const double* B, double* C, long sC, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
     dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
-    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, x0, nvec, B, 0L, C, sC);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, x0, nvec, B, 0L, C, sC, 0);
     check_launch("phase_gemm_herm_f64");
+}
+
+void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int P, const double* hpack, double* out,
+                   hipStream_t st) {
+    const long total = (long)Kh * nk * P;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_fold_herm, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nk, kpts, Kh, nvec, P,
+                       hpack, out);
+    check_launch("fold_herm_f64");
+}
+
+void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
+                                double* C, hipStream_t st) {
+    if (M <= 0 || nk <= 0 || Kh <= 0) return;
+    if (P <= 0 || P % 2 != 0) throw Error{-1, "phase_gemm_herm_groups_f64: P must be even"};
+    const int cg = P / 2, N = nk * cg;
+    // column blocks fastest: the 8 XCDs take the blocks in turn, so each XCD
+    // reads the coefficients of a fixed subset of the k
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, 1);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
+                       nvec, B, 0L, C, 0L, cg);
+    check_launch("phase_gemm_herm_groups_f64");
 }
 
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
@@ -584,11 +632,11 @@ void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x
     const int cb = pick_cb(N, 8);
     dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
     if (cb == 3)
-        hipLaunchKernelGGL((k_phase_gemm<float, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+        hipLaunchKernelGGL((k_phase_gemm<float, 3>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     else if (cb == 4)
-        hipLaunchKernelGGL((k_phase_gemm<float, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+        hipLaunchKernelGGL((k_phase_gemm<float, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     else
-        hipLaunchKernelGGL((k_phase_gemm<float, 8>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC);
+        hipLaunchKernelGGL((k_phase_gemm<float, 8>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     check_launch("phase_gemm_f32");
 }
 
