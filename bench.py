@@ -128,7 +128,7 @@ def main():
         px.timer_reset()
         pairs = steps * kb * args.nq
         rp_n, rp_ms = stages["rp_contraction"]
-        flops_pair = 8.0 * n_rp * nw * nw * nm
+        flops_pair = rp_flops_per_pair(model.rp_g, nw, nm)
         achieved = flops_pair * pairs / (rp_ms * 1e-3) / 1e12 if rp_ms > 0 else 0.0
         results[prec] = dict(
             pairs_per_s=pairs / dt, ms_per_step=1e3 * dt / steps, steps=steps,
@@ -160,7 +160,7 @@ def main():
     roof = {"bound": "mfma", "kernel": "rp_contraction (%s)" % RP_KERNEL[head], "achieved": round(r["rp_tflops"], 3),
             "peak": round(PEAK_TFLOPS[head], 1), "unit": "TFLOP/s", "frac": round(r["rp_frac"], 4),
             "traffic": measured_traffic(RP_KERNEL[head]), "traffic_unit": "HBM bytes per launch",
-            "flops_per_pair": 8.0 * n_rp * nw * nw * nm, "avg_launch_ms": round(r["rp_avg_ms"], 4),
+            "flops_per_pair": rp_flops_per_pair(model.rp_g, nw, nm), "avg_launch_ms": round(r["rp_avg_ms"], 4),
             "mfma_products_per_flop": SPLIT_PRODUCTS[head],
             "mfma_tflops": round(r["rp_tflops"] * SPLIT_PRODUCTS[head], 1)}
 
@@ -369,6 +369,7 @@ def cell_bench(px, args):
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t0
     nw, nm, n_rp, n_re = m.nw, m.nmodes, len(m.rp_g), len(m.re_g)
+    fl_rp = rp_flops_per_pair(m.rp_g, nw, nm)
     log("large cell: nw=%d modes=%d Re=%d Rp=%d, g(Re,Rp) %.1f GB; generated %.1fs, loaded %.1fs"
         % (nw, nm, n_re, n_rp, m.g.nbytes / 1e9, t_gen, t_load))
     del m
@@ -383,7 +384,6 @@ def cell_bench(px, args):
     qd = torch.as_tensor(q, device="cuda")
     par = px.Params(temp=cfg["T"], mu=cfg["mu"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"])
     pairs = len(ks) * len(q)
-    fl_rp = 8.0 * n_rp * nm * nw * nw
     fl_ep = 8.0 * nm * nw ** 3 + 8.0 * nm * nm * nw * nw       # rotation + projection per pair
     res = {}
     for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
@@ -443,9 +443,32 @@ def measured_traffic(kernel):
         return None
 
 
-# kernel behind each precision's Rp contraction (Si-like shape: 384 output columns)
-RP_KERNEL = {"fp64": "k_phase_gemm<double, 4>", "fp32": "k_phase_gemm<float, 8>",
-             "bf16x3": "k_gemm_bf16_planes<4, 2>", "bf16x6": "k_gemm_bf16_planes<4, 3>"}
+# kernel behind each precision's Rp contraction (Si-like shape: 384 output columns,
+# half-set form with real coefficients)
+RP_KERNEL = {"fp64": "k_phase_gemm<double, 4, true, false, false>", "fp32": "k_phase_gemm<float, 8, true, false, false>",
+             "bf16x3": "k_gemm_bf16_planes<4, 2, true>", "bf16x6": "k_gemm_bf16_planes<4, 3, true>"}
+
+
+def rp_flops_per_pair(rp, nw, nm):
+    """Algorithmic flops of the Rp contraction per (k, q) pair.  The library sums
+    over the half set (each +/-R pair once, unpaired vectors once) with real
+    coefficients cos and sin(2 pi q.R): per output column 2 real x complex
+    products (8 flops) per half vector, 4 for R = 0 (no sine).  Without a pair the
+    complex sum runs: 8 flops per vector and column."""
+    v = [tuple(int(c) for c in r) for r in np.asarray(rp)]
+    idx = {r: i for i, r in enumerate(v)}
+    if len(idx) != len(v):
+        return 8.0 * len(v) * nw * nw * nm
+    kh = 0
+    for i, r in enumerate(v):
+        j = idx.get(tuple(-c for c in r), -1)
+        if 0 <= j < i:
+            continue
+        kh += 1
+    if kh == len(v):
+        return 8.0 * len(v) * nw * nw * nm
+    entries = 2 * kh - (1 if (0, 0, 0) in idx else 0)
+    return 4.0 * entries * nw * nw * nm
 
 
 def group_sums(px, dm, ks, qs, g2):

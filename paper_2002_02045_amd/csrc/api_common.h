@@ -75,6 +75,9 @@ struct ephx_model {
     double* d_h_half = nullptr;  // [n_re_half][2][nw*nw] complex: H+H^dag, i(H-H^dag)
     int h_pack = 0;              // reals per packed Hermitian matrix: nw*nw rounded up to even
     double* d_h_pack = nullptr;  // [n_re_half][2][h_pack]: the same, packed (nw <= 8 only)
+    int n_rp_half = 0;           // half set of the Rp vectors of g: one of each +/-Rp pair, unpaired once
+    int32_t* d_rp_half = nullptr;  // [n_rp_half][3] its vectors
+    int32_t* d_rp_pair = nullptr;  // [n_rp_half][2] index of R and of -R (-1: absent) in the Rp list
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
     double* d_minv = nullptr;    // [nm]

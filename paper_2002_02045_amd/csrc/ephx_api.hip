@@ -248,6 +248,26 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
             m->d_rp_ph = (int32_t*)up(d->rp_ph, sizeof(int32_t) * 3 * d->n_rp_ph);
             m->d_re_g = (int32_t*)up(d->re_g, sizeof(int32_t) * 3 * d->n_re_g);
             m->d_rp_g = (int32_t*)up(d->rp_g, sizeof(int32_t) * 3 * d->n_rp_g);
+            {
+                // half set of the Rp list for the Rp sum with real coefficients: each
+                // +/-R pair once (at its first member), every unpaired vector once;
+                // left empty if the list repeats a vector
+                auto idp = index_of(d->rp_g, d->n_rp_g);
+                if ((int)idp.size() == d->n_rp_g) {
+                    std::vector<int32_t> rv, pr;
+                    for (int p = 0; p < d->n_rp_g; ++p) {
+                        const int a = d->rp_g[3 * p], b = d->rp_g[3 * p + 1], c = d->rp_g[3 * p + 2];
+                        auto it = idp.find({-a, -b, -c});
+                        const int n = (it != idp.end() && it->second != p) ? it->second : -1;
+                        if (n >= 0 && n < p) continue;
+                        rv.insert(rv.end(), {a, b, c});
+                        pr.insert(pr.end(), {p, n});
+                    }
+                    m->n_rp_half = (int)(pr.size() / 2);
+                    m->d_rp_half = (int32_t*)up(rv.data(), rv.size() * sizeof(int32_t));
+                    m->d_rp_pair = (int32_t*)up(pr.data(), pr.size() * sizeof(int32_t));
+                }
+            }
             // H(R) with weights folded in, and H(R) * (i R_a) for velocities
             std::vector<double> h(nh), hv((size_t)d->n_re * 3 * nw2 * 2);
             for (int r = 0; r < d->n_re; ++r) {
@@ -498,6 +518,8 @@ struct DriverPlan {
     long ngcol, nre_cols;
     bool f32, wide;
     size_t npair;
+    bool half;     // Rp sum over the half set with real coefficients
+    int kh, kh16;  // half-set size, and rounded up to 16
 };
 
 DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
@@ -517,15 +539,16 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
     if (d.wide) d.bk_eff = std::max(1, std::min<int>(d.bk_eff, (int)(wide_pairs / 16)));
     const long pairs_target = d.wide ? wide_pairs : 1L << 19;
     d.qc = (int)std::max(d.wide ? 1L : 64L, std::min((long)std::max(nq, 1), pairs_target / d.bk_eff));
-    d.kp = ((m->n_rp_g + 31) / 32) * 32;
+    // the half set pays whenever the Rp list holds a +/-R pair (R != 0)
+    d.half = m->n_rp_half > 0 && m->n_rp_half < m->n_rp_g;
+    d.kh = m->n_rp_half;
+    d.kh16 = ((d.kh + 15) / 16) * 16;
+    d.kp = d.half ? 2 * d.kh16 : ((m->n_rp_g + 31) / 32) * 32;
     d.nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
     d.npair = (size_t)d.bk_eff * d.qc;
     return d;
 }
 
-// Bytes of the driver's work buffers for one call of this shape (the buffers
-// eph_driver, and the band and phonon interpolation it calls, take from the
-// model's workspace).
 // H(k+q) of every pair of a (k batch) x (q chunk) block, pair index k * nq + q,
 // and its eigenpairs, in FP64.  With the packed half set (nw <= 8) the phases of
 // the k batch are folded into the coefficients once per batch (hfold) and each
@@ -552,6 +575,9 @@ static size_t hfold_bytes(const ephx_model* m, int nb) {
     return m->d_h_pack ? (size_t)m->n_re_half * 2 * nb * m->h_pack * 8 : 0;
 }
 
+// Bytes of the driver's work buffers for one call of this shape (the buffers
+// eph_driver, and the band and phonon interpolation it calls, take from the
+// model's workspace).
 size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, bool rates) {
     const size_t nm = d.nm, nw = d.nw, nw2 = d.nw2;
     size_t b = (size_t)nq * nm * 8 + (size_t)nq * nm * nm * 16;          // omega, e
@@ -559,7 +585,8 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
     b += (size_t)std::min(nq, 1 << 17) * nm * nm * 16;                    // D(q) chunk
     b += (size_t)d.bk_eff * (nw * 8 + nw2 * 16 + nw2 * 16);               // eps(k), U(k), H(k)
     b += (size_t)d.bk_eff * d.nre_cols * 16 * 2;                          // g(k,Rp), g(k,Rp) U(k)
-    if (!d.nsplit && d.f32) b += (size_t)d.bk_eff * d.nre_cols * 8;
+    if (!d.nsplit && d.half) b += (size_t)d.bk_eff * d.kh * 2 * d.ngcol * (d.f32 ? 8 : 16);   // half-set coefficients
+    else if (!d.nsplit && d.f32) b += (size_t)d.bk_eff * d.nre_cols * 8;
     if (d.nsplit) {
         b += (size_t)d.bk_eff * 2 * d.nsplit * d.ngcol * d.kp * 2;        // B planes
         b += (size_t)2 * d.nsplit * d.qc * d.kp * 2;                      // phase planes
@@ -604,7 +631,10 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     double* gp = (double*)m->ws.get("drv.gp", (size_t)bk_eff * nre_cols * 16);
     float* gp32 = nullptr;
     uint16_t* gpbf = nullptr;
-    if (precision == EPHX_FP32) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
+    void* gph = nullptr;   // half-set coefficients [k][Kh][2][ngcol] complex (FP64, FP32)
+    const bool half = dp.half;
+    if (half && !dp.nsplit) gph = m->ws.get("drv.gph", (size_t)bk_eff * dp.kh * 2 * ngcol * (f32 ? 8 : 16));
+    if (precision == EPHX_FP32 && !half) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
     const int nsplit = dp.nsplit;
     uint16_t* qpl = nullptr;
     if (nsplit) {
@@ -641,8 +671,17 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
         }
         apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
-        if (precision == EPHX_FP32) convert_f64_f32((long)nb * nre_cols * 2, gp, gp32, st);
-        if (nsplit) split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
+        if (half) {
+            if (nsplit)
+                split_bf16_half(nsplit, nb, m->n_rp_g, (int)ngcol, dp.kh, dp.kh16, m->d_rp_pair, gp, gpbf, st);
+            else if (precision == EPHX_FP32)
+                half_combine_f32(nb, m->n_rp_g, (int)ngcol, dp.kh, m->d_rp_pair, gp, (float*)gph, st);
+            else
+                half_combine_f64(nb, m->n_rp_g, (int)ngcol, dp.kh, m->d_rp_pair, gp, (double*)gph, st);
+        } else {
+            if (precision == EPHX_FP32) convert_f64_f32((long)nb * nre_cols * 2, gp, gp32, st);
+            if (nsplit) split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
+        }
         if (acc) hip_check(hipMemsetAsync(acc, 0, (size_t)nb * nw * nm * 8, st), "hipMemsetAsync");
         for (int q0 = 0; q0 < nq; q0 += qc) {
             const int nqc = std::min(qc, nq - q0);
@@ -661,20 +700,29 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             // phases of the q chunk for the split-bf16 paths, shared by every k of the batch
             if (nsplit) {
                 StageTimer tph("rp_phases", st);
-                phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
+                if (half)
+                    phase_planes_half(nsplit, nqc, dp.kh, dp.kh16, qb, m->d_rp_half, qpl, st);
+                else
+                    phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
             }
             // Rp contraction per k
             StageTimer trp("rp_contraction", st);
-            if (precision == EPHX_FP64)
+            const long sh = (long)dp.kh * 2 * ngcol;
+            if (nsplit)
+                gemm_bf16_planes(nsplit, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp, (float*)gw,
+                                 (long)nqc * ngcol, half ? 1 : 0, st);
+            else if (half && precision == EPHX_FP64)
+                phase_gemm_half_f64(nqc, (int)ngcol, dp.kh, nb, qb, m->d_rp_half, (const double*)gph, sh,
+                                    (double*)gw, (long)nqc * ngcol, st);
+            else if (half)
+                phase_gemm_half_f32(nqc, (int)ngcol, dp.kh, nb, qb, m->d_rp_half, (const float*)gph, sh, (float*)gw,
+                                    (long)nqc * ngcol, st);
+            else if (precision == EPHX_FP64)
                 phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, (double*)gw,
                                (long)nqc * ngcol, st);
-            else if (precision == EPHX_FP32)
+            else
                 phase_gemm_f32(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp32, nre_cols, (float*)gw,
                                (long)nqc * ngcol, st);
-            else {
-                gemm_bf16_planes(nsplit, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp, (float*)gw,
-                                 (long)nqc * ngcol, st);
-            }
             trp.stop();
             StageTimer tep("epilogue", st);
             if (wide) {

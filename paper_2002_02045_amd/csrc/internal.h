@@ -73,8 +73,28 @@ void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const doubl
 // then sin parts), and the contraction C[z] = A B[z] that reads them.
 void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const int32_t* nvec, uint16_t* out,
                        hipStream_t st);
+// real_a = 1: A is real, [nsplit][M][Kp] (half-set cos and sin parts along k).
 void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
-                      float* C, long sC, hipStream_t st);
+                      float* C, long sC, int real_a, hipStream_t st);
+// Half-set form of a Fourier sum over a list closed under R -> -R apart from
+// unpaired vectors (see phase_gemm.hip): pair [Kh][2] = (index of R_h, index of
+// -R_h or -1) into the list, G [Z][K][N] complex double.
+//  half_combine_*: [Z][Kh][2][N] complex coefficients (Gc_h, Gs_h);
+//  phase_gemm_half_*: C[z] = sum_h cos(2 pi x.R_h) Gc_h + sin(2 pi x.R_h) Gs_h,
+//    B = those coefficients (stride sB complex per z), nvec = the R_h;
+//  split_bf16_half / phase_planes_half: split-bf16 planes of the coefficients
+//    [Z][2 nsplit][N][2 Kh16] and of the real phases [nsplit][M][2 Kh16] for
+//    gemm_bf16_planes with real_a = 1 (Kh16 = Kh rounded up to 16).
+void half_combine_f64(int Z, int K, int N, int Kh, const int32_t* pair, const double* G, double* out, hipStream_t st);
+void half_combine_f32(int Z, int K, int N, int Kh, const int32_t* pair, const double* G, float* out, hipStream_t st);
+void phase_gemm_half_f64(int M, int N, int Kh, int Z, const double* x, const int32_t* nvec, const double* B, long sB,
+                         double* C, long sC, hipStream_t st);
+void phase_gemm_half_f32(int M, int N, int Kh, int Z, const double* x, const int32_t* nvec, const float* B, long sB,
+                         float* C, long sC, hipStream_t st);
+void split_bf16_half(int nsplit, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair, const double* G,
+                     uint16_t* out, hipStream_t st);
+void phase_planes_half(int nsplit, int M, int Kh, int Kh16, const double* x, const int32_t* nvec, uint16_t* out,
+                       hipStream_t st);
 // Split complex double B[Z][K][N] into those planes.
 void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
                     hipStream_t st);

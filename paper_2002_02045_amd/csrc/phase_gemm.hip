@@ -402,7 +402,9 @@ constexpr int kBMP = 128;              // rows per workgroup (32 per wave)
 
 __device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) & 3); }
 
-template <int CT, int NS>
+// RA = true: A is real, [NS][M][Kp] (the cos and sin parts of a half-set sum
+// side by side along k), and C = A B takes two MFMAs per product instead of four.
+template <int CT, int NS, bool RA = false>
 __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
                                                           const uint16_t* __restrict__ As,
                                                           const uint16_t* __restrict__ Bs, long sB,
@@ -463,7 +465,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
                 anr[s][t] = *reinterpret_cast<const u16x8*>(arow + t * plane + kc + 16 * s);
-                ani[s][t] = *reinterpret_cast<const u16x8*>(arow + (NS + t) * plane + kc + 16 * s);
+                if (!RA) ani[s][t] = *reinterpret_cast<const u16x8*>(arow + (NS + t) * plane + kc + 16 * s);
             }
     };
     issue_b(0, 0);
@@ -480,8 +482,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
                 ar[s][t] = anr[s][t];
-                ai[s][t] = ani[s][t];
-                nai[s][t] = ani[s][t] ^ sign;
+                if (!RA) {
+                    ai[s][t] = ani[s][t];
+                    nai[s][t] = ani[s][t] ^ sign;
+                }
             }
         if (kc + kBK < Kp) {
             issue_b(kc + kBK, h ^ 1);
@@ -512,8 +516,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
                     const int j = ord - i;
                     are[ct] = mfma_bf32(ar[s][i], br[cs][j], are[ct]);
                     aim[ct] = mfma_bf32(ar[s][i], bi[cs][j], aim[ct]);
-                    are[ct] = mfma_bf32(nai[s][i], bi[cs][j], are[ct]);
-                    aim[ct] = mfma_bf32(ai[s][i], br[cs][j], aim[ct]);
+                    if (!RA) {
+                        are[ct] = mfma_bf32(nai[s][i], bi[cs][j], are[ct]);
+                        aim[ct] = mfma_bf32(ai[s][i], br[cs][j], aim[ct]);
+                    }
                 }
             }
         }
@@ -530,6 +536,96 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
                 cz[off + 1] = aim[ct][v];
             }
         }
+    }
+}
+
+// Half-set form of a Fourier sum over a vector list that is closed under
+// R -> -R apart from some unpaired vectors:
+//   sum_p e^{2 pi i x.R_p} G_p = sum_h cos(2 pi x.R_h) Gc_h + sin(2 pi x.R_h) Gs_h
+// with Gc_h = G_p + G_n, Gs_h = i (G_p - G_n) for a pair (p, n), R_n = -R_p, and
+// Gc_h = G_p, Gs_h = i G_p for an unpaired vector (R = 0 among them).  The
+// coefficients are real, so a pair costs half the products of the complex sum.
+// pair: [Kh][2] = (p, n), n = -1 when unpaired.  G: [Z][K][N] complex double.
+// k_half_combine writes [Z][Kh][2][N] complex (Gc_h, Gs_h) in T.
+template <typename T>
+__global__ void k_half_combine(int K, int N, int Kh, const int32_t* __restrict__ pair, const double* __restrict__ G,
+                               T* __restrict__ out) {
+    const int z = blockIdx.z;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (h, n), n fastest
+    if (idx >= (long)Kh * N) return;
+    const int h = (int)(idx / N), n = (int)(idx % N);
+    const double* gz = G + (long)z * K * N * 2;
+    const int p = pair[2 * h], q = pair[2 * h + 1];
+    const double ar = gz[((long)p * N + n) * 2], ai = gz[((long)p * N + n) * 2 + 1];
+    const double br = q >= 0 ? gz[((long)q * N + n) * 2] : 0.0, bi = q >= 0 ? gz[((long)q * N + n) * 2 + 1] : 0.0;
+    T* oz = out + (long)z * Kh * 2 * N * 2;
+    oz[((long)h * 2 * N + n) * 2] = (T)(ar + br);
+    oz[((long)h * 2 * N + n) * 2 + 1] = (T)(ai + bi);
+    oz[(((long)h * 2 + 1) * N + n) * 2] = (T)(bi - ai);
+    oz[(((long)h * 2 + 1) * N + n) * 2 + 1] = (T)(ar - br);
+}
+
+// The same coefficients as split-bf16 planes for the real-A contraction:
+// [Z][2NS][N][2 Kh16] (re parts, then im parts), k = h for Gc_h and Kh16 + h for
+// Gs_h, zero parts at h >= Kh (Kh16 = Kh rounded up to 16).
+template <int NS>
+__global__ void k_split_bf16_half(int K, int N, int Kh, int Kh16, const int32_t* __restrict__ pair,
+                                  const double* __restrict__ G, uint16_t* __restrict__ out) {
+    const int z = blockIdx.z;
+    const int Kp = 2 * Kh16;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (n, k), k fastest
+    if (idx >= (long)N * Kp) return;
+    const int n = (int)(idx / Kp), k = (int)(idx % Kp);
+    const bool sn = k >= Kh16;
+    const int h = sn ? k - Kh16 : k;
+    float re = 0.f, im = 0.f;
+    if (h < Kh) {
+        const double* gz = G + (long)z * K * N * 2;
+        const int p = pair[2 * h], q = pair[2 * h + 1];
+        const double ar = gz[((long)p * N + n) * 2], ai = gz[((long)p * N + n) * 2 + 1];
+        const double br = q >= 0 ? gz[((long)q * N + n) * 2] : 0.0;
+        const double bi = q >= 0 ? gz[((long)q * N + n) * 2 + 1] : 0.0;
+        re = (float)(sn ? bi - ai : ar + br);
+        im = (float)(sn ? ar - br : ai + bi);
+    }
+    unsigned short pr[NS], pi[NS];
+    split_n<NS>(re, pr);
+    split_n<NS>(im, pi);
+    uint16_t* oz = out + (long)z * 2 * NS * N * Kp;
+    for (int t = 0; t < NS; ++t) {
+        oz[((long)t * N + n) * Kp + k] = pr[t];
+        oz[((long)(NS + t) * N + n) * Kp + k] = pi[t];
+    }
+}
+
+// Real phase planes of a half set for the same contraction: [NS][M][2 Kh16],
+// part t of cos(2 pi x_m.R_h) at k = h and of sin(2 pi x_m.R_h) at Kh16 + h.
+template <int NS>
+__global__ void k_phase_planes_half(int M, int Kh, int Kh16, const double* __restrict__ x,
+                                    const int32_t* __restrict__ nvec, uint16_t* __restrict__ out) {
+    const int kg = Kh16 / 8, Kp = 2 * Kh16;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (m, group of 8 h)
+    if (idx >= (long)M * kg) return;
+    const int m = (int)(idx / kg), h0 = (int)(idx % kg) * 8;
+    const double xa = x[3L * m], xb = x[3L * m + 1], xc = x[3L * m + 2];
+    u16x8 pr[NS], pi[NS];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float pc = 0.f, ps = 0.f;
+        if (h0 + j < Kh) phase_of(reduced_arg(xa, xb, xc, nvec + 3L * (h0 + j)), pc, ps);
+        unsigned short hr[NS], hi[NS];
+        split_n<NS>(pc, hr);
+        split_n<NS>(ps, hi);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            pr[t][j] = hr[t];
+            pi[t][j] = hi[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        *reinterpret_cast<u16x8*>(out + ((long)t * M + m) * Kp + h0) = pr[t];
+        *reinterpret_cast<u16x8*>(out + ((long)t * M + m) * Kp + Kh16 + h0) = pi[t];
     }
 }
 
@@ -678,7 +774,7 @@ void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const 
 }
 
 void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
-                      float* C, long sC, hipStream_t st) {
+                      float* C, long sC, int real_a, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
@@ -687,18 +783,98 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
     dim3 grid((unsigned)nblk);
-#define EPHX_BFP(CTV, NSV)                                                                                      \
-    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, sB, \
-                       C, sC)
-    if (nsplit == 2) {
-        if (ct == 2) EPHX_BFP(2, 2);
-        else EPHX_BFP(4, 2);
+#define EPHX_BFP(CTV, NSV, RAV)                                                                                  \
+    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV, RAV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, \
+                       sB, C, sC)
+    if (real_a) {
+        if (nsplit == 2) {
+            if (ct == 2) EPHX_BFP(2, 2, true);
+            else EPHX_BFP(4, 2, true);
+        } else {
+            if (ct == 2) EPHX_BFP(2, 3, true);
+            else EPHX_BFP(4, 3, true);
+        }
+    } else if (nsplit == 2) {
+        if (ct == 2) EPHX_BFP(2, 2, false);
+        else EPHX_BFP(4, 2, false);
     } else {
-        if (ct == 2) EPHX_BFP(2, 3);
-        else EPHX_BFP(4, 3);
+        if (ct == 2) EPHX_BFP(2, 3, false);
+        else EPHX_BFP(4, 3, false);
     }
 #undef EPHX_BFP
     check_launch("gemm_bf16_planes");
+}
+
+void half_combine_f64(int Z, int K, int N, int Kh, const int32_t* pair, const double* G, double* out, hipStream_t st) {
+    const long total = (long)Kh * N;
+    if (total <= 0 || Z <= 0) return;
+    dim3 grid((unsigned)((total + 255) / 256), 1, Z);
+    hipLaunchKernelGGL(k_half_combine<double>, grid, dim3(256), 0, st, K, N, Kh, pair, G, out);
+    check_launch("half_combine_f64");
+}
+
+void half_combine_f32(int Z, int K, int N, int Kh, const int32_t* pair, const double* G, float* out, hipStream_t st) {
+    const long total = (long)Kh * N;
+    if (total <= 0 || Z <= 0) return;
+    dim3 grid((unsigned)((total + 255) / 256), 1, Z);
+    hipLaunchKernelGGL(k_half_combine<float>, grid, dim3(256), 0, st, K, N, Kh, pair, G, out);
+    check_launch("half_combine_f32");
+}
+
+void split_bf16_half(int nsplit, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair, const double* G,
+                     uint16_t* out, hipStream_t st) {
+    if (Kh16 % 16 != 0 || Kh16 < Kh) throw Error{-1, "split_bf16_half: bad Kh16"};
+    const long total = (long)N * 2 * Kh16;
+    if (total <= 0 || Z <= 0) return;
+    dim3 grid((unsigned)((total + 255) / 256), 1, Z);
+    if (nsplit == 2)
+        hipLaunchKernelGGL(k_split_bf16_half<2>, grid, dim3(256), 0, st, K, N, Kh, Kh16, pair, G, out);
+    else if (nsplit == 3)
+        hipLaunchKernelGGL(k_split_bf16_half<3>, grid, dim3(256), 0, st, K, N, Kh, Kh16, pair, G, out);
+    else
+        throw Error{-1, "split_bf16_half: nsplit must be 2 or 3"};
+    check_launch("split_bf16_half");
+}
+
+void phase_planes_half(int nsplit, int M, int Kh, int Kh16, const double* x, const int32_t* nvec, uint16_t* out,
+                       hipStream_t st) {
+    if (M <= 0) return;
+    if (Kh16 % 16 != 0 || Kh16 < Kh) throw Error{-1, "phase_planes_half: bad Kh16"};
+    const long total = (long)M * (Kh16 / 8);
+    dim3 grid((unsigned)((total + 255) / 256));
+    if (nsplit == 2)
+        hipLaunchKernelGGL(k_phase_planes_half<2>, grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
+    else if (nsplit == 3)
+        hipLaunchKernelGGL(k_phase_planes_half<3>, grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
+    else
+        throw Error{-1, "phase_planes_half: nsplit must be 2 or 3"};
+    check_launch("phase_planes_half");
+}
+
+void phase_gemm_half_f64(int M, int N, int Kh, int Z, const double* x, const int32_t* nvec, const double* B, long sB,
+                         double* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
+                       nvec, B, sB, C, sC, 0);
+    check_launch("phase_gemm_half_f64");
+}
+
+void phase_gemm_half_f32(int M, int N, int Kh, int Z, const double* x, const int32_t* nvec, const float* B, long sB,
+                         float* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    const int cb = pick_cb(N, 8);
+    dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
+    if (cb == 3)
+        hipLaunchKernelGGL((k_phase_gemm<float, 3, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
+                           nvec, B, sB, C, sC, 0);
+    else if (cb == 4)
+        hipLaunchKernelGGL((k_phase_gemm<float, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
+                           nvec, B, sB, C, sC, 0);
+    else
+        hipLaunchKernelGGL((k_phase_gemm<float, 8, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
+                           nvec, B, sB, C, sC, 0);
+    check_launch("phase_gemm_half_f32");
 }
 
 void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out, hipStream_t st) {

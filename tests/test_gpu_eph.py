@@ -103,6 +103,28 @@ def test_gkq_parity(lib, tiny, gkq_case, prec, tol):
     assert emax <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)])
+def test_gkq_parity_one_sided_rp(lib, prec, tol):
+    """An Rp list without any +/-R pair (R = 0 and the vectors that are
+    lexicographically positive) leaves the half-set form nothing to gain, so the
+    library sums over the list with complex phases; parity of that path."""
+    import dataclasses
+    m = synth.make_config_model("tiny")
+    keep = [i for i, r in enumerate(m.rp_g.tolist()) if tuple(r) >= (0, 0, 0)]
+    m = dataclasses.replace(m, rp_g=m.rp_g[keep], w_rp_g=m.w_rp_g[keep], g=m.g[:, keep])
+    v = {tuple(r) for r in m.rp_g.tolist()}
+    assert not any(tuple(-c for c in r) in v for r in v if r != (0, 0, 0))
+    _say("gkq parity one-sided Rp list (%d vectors) prec=%s" % (len(keep), prec))
+    k = synth.random_points(131, 5)
+    q = synth.random_points(132, 70)
+    blk, ref = _oracle_g2_groups(m, k, q)
+    g2 = lib.gkq(lib.Model(m), k, q, precision=prec)
+    got = group_sums_g2(g2.double().cpu().numpy(), blk["eps_k"], blk["eps_kq"], blk["omega"])
+    emax, e99 = g2_error(got, ref)
+    _say("  |g|^2 error %s: max %.3e  p99 %.3e" % (prec, emax, e99))
+    assert emax <= tol
+
+
 def test_rates_parity(lib, tiny):
     _say("rates parity tiny model")
     m, dm = tiny
