@@ -778,7 +778,9 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
-    const int ct = N <= 64 ? 2 : 4;
+    // real A: 96-column tiles where they divide N (72 KB of LDS for BF16x6, two
+    // workgroups per CU)
+    const int ct = N <= 64 ? 2 : (real_a && N % 96 == 0 ? 3 : 4);
     const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + kBMP - 1) / kBMP;
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
@@ -789,9 +791,11 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
     if (real_a) {
         if (nsplit == 2) {
             if (ct == 2) EPHX_BFP(2, 2, true);
+            else if (ct == 3) EPHX_BFP(3, 2, true);
             else EPHX_BFP(4, 2, true);
         } else {
             if (ct == 2) EPHX_BFP(2, 3, true);
+            else if (ct == 3) EPHX_BFP(3, 3, true);
             else EPHX_BFP(4, 3, true);
         }
     } else if (nsplit == 2) {
