@@ -446,7 +446,7 @@ def measured_traffic(kernel):
 # kernel behind each precision's Rp contraction (Si-like shape: 384 output columns,
 # half-set form with real coefficients)
 RP_KERNEL = {"fp64": "k_phase_gemm<double, 4, true, false, false>", "fp32": "k_phase_gemm<float, 8, true, false, false>",
-             "bf16x3": "k_gemm_bf16_planes<4, 2, true>", "bf16x6": "k_gemm_bf16_planes<4, 3, true>"}
+             "bf16x3": "k_gemm_bf16_planes<3, 2, true>", "bf16x6": "k_gemm_bf16_planes<3, 3, true>"}
 
 
 def rp_flops_per_pair(rp, nw, nm):
