@@ -14,9 +14,9 @@
 // sweep every pair meets once.  Lane i keeps its row in lane-relative order:
 // register d holds column i^d (the diagonal is register 0).  Then every
 // exchange between lanes is "read register e of lane i^x" with x and e fixed
-// at compile time, which the DPP lane permutations do inside the VALU (XOR 1,
-// 2, 3 by quad permutes, XOR 7 by the half-row mirror, XOR 4..6 by both),
-// with no LDS round trip.  Sweeps run until the off-diagonal Frobenius norm of
+// at compile time: XOR 1, 2, 3 by DPP quad permutes and XOR 7 by the DPP
+// half-row mirror inside the VALU, XOR 4..6 by the LDS crossbar's bit-mask
+// swizzle (no memory access).  Sweeps run until the off-diagonal Frobenius norm of
 // every matrix in the wavefront is below 1e-15 of its norm; eigenpairs are
 // then sorted ascending.
 #include <type_traits>
@@ -30,15 +30,18 @@ namespace {
 template <int X>
 __device__ __forceinline__ int xlane(int v) {
     static_assert(X >= 0 && X < 8, "lane offset");
-    constexpr int kQuad = X == 1 || X == 6 ? 0xB1 : (X == 2 || X == 5 ? 0x4E : 0x1B);   // XOR 1, 2, 3
+    constexpr int kQuad = X == 1 ? 0xB1 : (X == 2 ? 0x4E : 0x1B);   // XOR 1, 2, 3
     constexpr int kMirror = 0x141;                                                      // lane -> 7 - lane
     // every lane has a source under these permutations, so the destination is
-    // written in full (bound_ctrl set: no "old" value has to be placed first)
+    // written in full (bound_ctrl set: no "old" value has to be placed first);
+    // the callers run with every lane of the wavefront active
     if (X == 0) return v;
     if (X <= 3) return __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, true);
     if (X == 7) return __builtin_amdgcn_update_dpp(0, v, kMirror, 0xF, 0xF, true);
-    const int w = __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, true);   // X ^ 7 in {3, 2, 1}
-    return __builtin_amdgcn_update_dpp(0, w, kMirror, 0xF, 0xF, true);
+    // XOR 4..6 would take two DPP moves; the LDS crossbar's bit-mask swizzle
+    // (lane ^ X within groups of 32, no memory access) does it in one
+    // instruction outside the VALU, which this solver keeps busy
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
 }
 template <int X>
 __device__ __forceinline__ double xlane(double v) {
