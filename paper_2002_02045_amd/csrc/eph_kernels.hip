@@ -200,6 +200,31 @@ __global__ void k_convert(long count, const double* __restrict__ in, float* __re
     if (t < count) out[t] = (float)in[t];
 }
 
+// The factors the epilogue stages per pair that depend on q alone (scaled mode
+// eigenvectors e[x][nu] sqrt(hbar^2/(2 M_x omega_nu)) and Bose factors) or on
+// the pair's k+q energies alone (Fermi factors), formed once per chunk with
+// the same expressions, so the values are those the per-pair path forms.
+template <typename T>
+__global__ void k_mode_factors(int nq, int q_off, int nm, const double* __restrict__ omega,
+                               const double* __restrict__ evec, const double* __restrict__ minv, double omega_cut,
+                               double temp, cx<T>* __restrict__ es, double* __restrict__ nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (q, x, nu)
+    if (t >= (long)nq * nm * nm) return;
+    const int i = (int)(t % (nm * nm));
+    const long ql = t / (nm * nm), qg = q_off + ql;
+    const int x = i / nm, nu = i % nm;
+    const double om = omega[qg * nm + nu];
+    const double amp = om > omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * minv[x] : 0.0;
+    es[t] = {(T)(amp * evec[2 * ((qg * nm + x) * nm + nu)]), (T)(amp * evec[2 * ((qg * nm + x) * nm + nu) + 1])};
+    if (x == 0) nb[ql * nm + nu] = om > omega_cut ? 1.0 / expm1(om / (kBoltzEv * temp)) : 0.0;
+}
+
+__global__ void k_fermi_factors(long n, const double* __restrict__ eps, double mu, double temp,
+                                double* __restrict__ f) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) f[t] = 1.0 / (exp((eps[t] - mu) / (kBoltzEv * temp)) + 1.0);
+}
+
 // One 64-lane workgroup walks QPB consecutive (k, q) pairs of one k.  Per pair
 // the wavefront stages g'(k,q), U(k+q), the scaled mode eigenvectors
 // e[x][nu] sqrt(hbar^2/(2 M_x omega_nu)), the Bose factors, and the final-band
@@ -255,8 +280,11 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
     constexpr int GPL = kPre ? (NM * NW * NW + 63) / 64 : 1;   // g' elements per lane
     constexpr int UPL = kPre ? (NW * NW + 63) / 64 : 1;        // U elements per lane
     constexpr int EPL = kPre ? (NM * NM + 63) / 64 : 1;        // e(q) elements per lane
-    cx<T> rg[GPL], ru[UPL];
-    double rom_es[EPL], rev_r[EPL], rev_i[EPL], rom = 0.0, rem = 0.0;
+    // (the fixed-size instances read the mode and Fermi factors formed once per
+    // chunk; their launcher guarantees them)
+    cx<T> rg[GPL], ru[UPL], res[EPL];
+    double rom = 0.0, rem = 0.0, rnb = 0.0, rfm = 0.0;
+    const cx<T>* esq = reinterpret_cast<const cx<T>*>(e.esq);
     auto fetch = [&](int ql) {
         const long qg = (long)e.q_off + ql;
         const long pair = (long)z * e.nq + ql;
@@ -275,15 +303,16 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
             const int i = lane + 64 * j;
-            if (i < nm * nm) {
-                const int x = i / nm, nu = i % nm;
-                rom_es[j] = e.omega[qg * nm + nu];
-                rev_r[j] = e.evec[2 * ((qg * nm + x) * nm + nu)];
-                rev_i[j] = e.evec[2 * ((qg * nm + x) * nm + nu) + 1];
-            }
+            if (i < nm * nm) res[j] = esq[(long)ql * nm * nm + i];
         }
-        if (lane < nm) rom = e.omega[qg * nm + lane];
-        if (RATES && lane < nw) rem = e.ekq[pair * nw + lane];
+        if (lane < nm) {
+            rom = e.omega[qg * nm + lane];
+            rnb = e.nbq[(long)ql * nm + lane];
+        }
+        if (RATES && lane < nw) {
+            rem = e.ekq[pair * nw + lane];
+            rfm = e.fkq[pair * nw + lane];
+        }
     };
     auto stage = [&]() {
 #pragma unroll
@@ -299,20 +328,15 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
             const int i = lane + 64 * j;
-            if (i < nm * nm) {
-                const int x = i / nm;
-                const double om = rom_es[j];
-                const double amp = om > e.omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * e.minv[x] : 0.0;
-                s_es[i] = {(T)(amp * rev_r[j]), (T)(amp * rev_i[j])};
-            }
+            if (i < nm * nm) s_es[i] = res[j];
         }
         if (lane < nm) {
             s_om[lane] = rom;
-            s_nb[lane] = rom > e.omega_cut ? 1.0 / expm1(rom / kt) : 0.0;
+            s_nb[lane] = rnb;
         }
         if (RATES && lane < nw) {
             s_em[lane] = rem;
-            s_fm[lane] = 1.0 / (exp((rem - e.mu) / kt) + 1.0);
+            s_fm[lane] = rfm;
         }
     };
     if (kPre && q0 < q1) fetch(q0);
@@ -417,7 +441,12 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 
 template <typename T, bool RATES>
 void launch_epilogue(const EphEpilogue& e, dim3 grid, size_t lds, hipStream_t st) {
-    if (e.nw == 8 && e.nm == 6)
+    // the fixed-size instances read the precomputed factors; without them the
+    // runtime-sized instance forms them per pair
+    const bool pre = e.esq != nullptr && e.nbq != nullptr && (!RATES || e.fkq != nullptr);
+    if (!pre)
+        hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 0, 0>), grid, dim3(64), lds, st, e);
+    else if (e.nw == 8 && e.nm == 6)
         hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 8, 6>), grid, dim3(64), lds, st, e);
     else if (e.nw == 4 && e.nm == 6)
         hipLaunchKernelGGL((k_eph_epilogue<T, RATES, 4, 6>), grid, dim3(64), lds, st, e);
@@ -727,6 +756,24 @@ void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st) {
     if (f32) launch_epilogue<float, false>(e, grid, lds, st);
     else launch_epilogue<double, false>(e, grid, lds, st);
     check_launch("eph_epilogue_g2");
+}
+
+void eph_epilogue_factors(const EphEpilogue& e, int f32, void* esq, double* nbq, double* fkq, hipStream_t st) {
+    const long n = (long)e.nq * e.nm * e.nm;
+    if (n > 0) {
+        const dim3 grid((unsigned)((n + 255) / 256));
+        if (f32)
+            hipLaunchKernelGGL(k_mode_factors<float>, grid, dim3(256), 0, st, e.nq, e.q_off, e.nm, e.omega, e.evec,
+                               e.minv, e.omega_cut, e.temp, (cx<float>*)esq, nbq);
+        else
+            hipLaunchKernelGGL(k_mode_factors<double>, grid, dim3(256), 0, st, e.nq, e.q_off, e.nm, e.omega, e.evec,
+                               e.minv, e.omega_cut, e.temp, (cx<double>*)esq, nbq);
+    }
+    const long nf = (long)e.nkb * e.nq * e.nw;
+    if (fkq != nullptr && nf > 0)
+        hipLaunchKernelGGL(k_fermi_factors, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, nf, e.ekq, e.mu,
+                           e.temp, fkq);
+    check_launch("eph_epilogue_factors");
 }
 
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {

@@ -596,6 +596,7 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
     b += d.npair * d.ngcol * (d.f32 ? 8 : 16) * (d.wide ? 2 : 1);         // g^W (and g^H)
     if (d.wide) b += (size_t)d.qc * nm * nm * 16 + (m->polar ? d.npair * nw2 * 16 : 0);
     if (rates) b += (size_t)d.bk_eff * eph_epilogue_blocks(d.qc) * nw * nm * 8 + (size_t)d.bk_eff * nw * nm * 8;
+    if (!d.wide) b += (size_t)d.qc * nm * nm * (d.f32 ? 8 : 16) + (size_t)d.qc * nm * 8 + (rates ? d.npair * nw * 8 : 0);
     return b;
 }
 
@@ -651,6 +652,13 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     double* pmat = wide ? (double*)m->ws.get("drv.pmat", (size_t)qc * nm * nm * 16) : nullptr;
     double* ovb = wide && m->polar ? (double*)m->ws.get("drv.ov", npair * nw2 * 16) : nullptr;
     const int nblk = eph_epilogue_blocks(qc);
+    void* esq = nullptr;
+    double *nbq = nullptr, *fkq = nullptr;
+    if (!wide) {
+        esq = m->ws.get("drv.esq", (size_t)qc * nm * nm * (f32 ? 8 : 16));
+        nbq = (double*)m->ws.get("drv.nbq", (size_t)qc * nm * 8);
+        if (gamma) fkq = (double*)m->ws.get("drv.fkq", npair * nw * 8);
+    }
     double* partial = nullptr;
     double* acc = nullptr;
     if (gamma) {
@@ -778,15 +786,22 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             e.lr = lr;
             e.minv = m->d_minv;
             e.omega_cut = omega_cut;
+            if (gamma) {
+                e.temp = p->temp;
+                e.mu = p->mu;
+                e.sigma = p->sigma;
+            }
+            // mode factors of the chunk's q, Fermi factors of its pairs: once per chunk
+            e.esq = esq;
+            e.nbq = nbq;
+            e.fkq = gamma ? fkq : nullptr;
+            eph_epilogue_factors(e, f32 ? 1 : 0, esq, nbq, gamma ? fkq : nullptr, st);
             if (!gamma) {
                 e.g2 = g2;
                 e.nq_total = nq;
                 e.k_off = k0;
                 eph_epilogue_g2(e, f32 ? 1 : 0, st);
             } else {
-                e.temp = p->temp;
-                e.mu = p->mu;
-                e.sigma = p->sigma;
                 e.qw = qw;
                 e.uniform_w = 1.0 / nq;
                 e.partial = partial;

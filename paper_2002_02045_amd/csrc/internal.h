@@ -138,6 +138,11 @@ struct EphEpilogue {
     const double* lr;     // [nq_total][nm] complex long-range term, or nullptr
     const double* minv;   // [nm] 1/sqrt(M_kappa)
     double omega_cut;
+    // per-q and per-pair factors formed once by eph_epilogue_factors (nullptr:
+    // the epilogue forms them per pair)
+    const void* esq;      // [nq][nm][nm] complex (float or double): e[x][nu] sqrt(hbar^2/(2 M_x omega_nu))
+    const double* nbq;    // [nq][nm] Bose factors
+    const double* fkq;    // [nkb][nq][nw] Fermi factors of the k+q states (rates mode)
     // |g|^2 output mode
     void* g2;            // [nk_total][nq_total][nm][nw][nw]
     long nq_total;
@@ -150,6 +155,9 @@ struct EphEpilogue {
     int nblk;
 };
 void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st);
+// The per-q mode factors (esq, nbq) of the chunk, and with fkq != nullptr the
+// Fermi factors of its pairs, into the buffers e points at.
+void eph_epilogue_factors(const EphEpilogue& e, int f32, void* esq, double* nbq, double* fkq, hipStream_t st);
 // per pair: gw_bar[x][i][n] = sum_m U(k+q)_im sum_nu conj(es[x][nu]) 2 c lam_n w_q D_mnu g_mnu (FP64)
 void eph_adjoint_epilogue(const EphEpilogue& e, const double* lam, double* gw_bar, hipStream_t st);
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st);
