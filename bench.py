@@ -30,7 +30,7 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k-batch", type=int, default=32)
     ap.add_argument("--nq", type=int, default=1_000_000)
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6,fp16x3")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dyn-steps", type=int, default=200, help="timed RK4 steps of the dynamics workload (0: skip)")
@@ -43,12 +43,13 @@ def _parse():
     return ap.parse_args()
 
 
-BF16_PEAK = 2516.6
-# bf16 products per FP32-equivalent real product of each split path
-SPLIT_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
+BF16_PEAK = 2516.6   # dense bf16 and fp16 MFMA, TFLOP/s
+# 16-bit products per FP32-equivalent real product of each split path
+SPLIT_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 # ceiling of each path in algorithmic (FP32/FP64-equivalent) TFLOP/s: the split
-# paths run their products on the dense bf16 MFMA peak
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_PEAK / 3, "bf16x6": BF16_PEAK / 6}
+# paths run their products on the dense bf16/fp16 MFMA peak
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_PEAK / 3, "bf16x6": BF16_PEAK / 6,
+               "fp16x3": BF16_PEAK / 3}
 HBM_GBS = 8000.0
 
 
@@ -189,7 +190,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)",
-                  "bf16x6": "bf16x6 (f32 accumulate)"}[head],
+                  "bf16x6": "bf16x6 (f32 accumulate)", "fp16x3": "fp16x3 (f32 accumulate)"}[head],
         "data": "synthetic",
         "config": {"workload": "si-like rates: Nw=8, 6 modes, 512 Re x 512 Rp, %d k per step (of %d window k), "
                                "%d random q, T=300 K, sigma=5 meV" % (kb, nk_total, args.nq),
@@ -386,7 +387,7 @@ def cell_bench(px, args):
     pairs = len(ks) * len(q)
     fl_ep = 8.0 * nm * nw ** 3 + 8.0 * nm * nm * nw * nw       # rotation + projection per pair
     res = {}
-    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6", "fp16x3"):
         px.rates(dm, ks[:1], qd[:64], par, precision=prec)
         torch.cuda.synchronize()
         px.timer_reset()
@@ -410,7 +411,7 @@ def cell_bench(px, args):
     ke, qe = ks[:2], q[:16]
     ref = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision="fp64"))
     bmax = ref.flatten(2).abs().max(dim=2).values
-    for prec in ("fp32", "bf16x3", "bf16x6"):
+    for prec in ("fp32", "bf16x3", "bf16x6", "fp16x3"):
         got = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision=prec).double())
         res[prec]["g2_err_vs_fp64"] = float(((got - ref).abs().flatten(2).max(dim=2).values
                                              / bmax.clamp_min(1e-300)).max())
@@ -446,7 +447,8 @@ def measured_traffic(kernel):
 # kernel behind each precision's Rp contraction (Si-like shape: 384 output columns,
 # half-set form with real coefficients)
 RP_KERNEL = {"fp64": "k_phase_gemm<double, 4, true, false, false>", "fp32": "k_phase_gemm<float, 8, true, false, false>",
-             "bf16x3": "k_gemm_bf16_planes<3, 2, true>", "bf16x6": "k_gemm_bf16_planes<3, 3, true>"}
+             "bf16x3": "k_gemm_bf16_planes<3, 2, true, false>", "bf16x6": "k_gemm_bf16_planes<3, 3, true, false>",
+             "fp16x3": "k_gemm_bf16_planes<3, 2, true, true>"}
 
 
 def rp_flops_per_pair(rp, nw, nm):

@@ -32,7 +32,11 @@
  *    contraction, H(k+q), eigensolves, eps, omega and rate sums in FP64), or
  *    EPHX_BF16X3 (as FP32, but the Rp contraction of g runs on bf16 MFMA with
  *    each FP32 operand split into two bf16 parts and three products kept), or
- *    EPHX_BF16X6 (three bf16 parts per operand, six products kept).
+ *    EPHX_BF16X6 (three bf16 parts per operand, six products kept), or
+ *    EPHX_FP16X3 (two fp16 parts per operand, three products kept: 11
+ *    significant bits per part against bf16's 8; the g(k,Rp) operand is scaled
+ *    into fp16's range by a power of two fixed per model from a bound on its
+ *    entries, and the product scaled back).
  */
 #ifndef EPHX_H
 #define EPHX_H
@@ -56,6 +60,7 @@ extern "C" {
 #define EPHX_FP32 1
 #define EPHX_BF16X3 2
 #define EPHX_BF16X6 3
+#define EPHX_FP16X3 4
 
 /* Time steppers of ephx_dynamics_field (Sec. 2.1, carrier dynamics) */
 #define EPHX_RK4 0

@@ -7,7 +7,7 @@ The compiled library is loaded on first use of any public name (so that
 ``paper_2002_02045_amd.build`` can run before it exists); using the binding
 without a built libephx.so raises ImportError.
 """
-_PUBLIC = ("FP32", "FP64", "BF16X3", "BF16X6", "EphxError", "Model", "PairTable", "Params",
+_PUBLIC = ("FP32", "FP64", "BF16X3", "BF16X6", "FP16X3", "EphxError", "Model", "PairTable", "Params",
            "bands", "gkq", "gkq_pairs", "grid_states", "phonons", "rates", "rates_vjp", "RatesFunction",
            "MobilityFunction", "timer_enable", "timer_reset", "timer_get", "workspace_query")
 

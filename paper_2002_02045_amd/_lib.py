@@ -23,8 +23,8 @@ if not os.path.exists(LIB_PATH):
 
 lib = C.CDLL(LIB_PATH)
 
-FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+FP64, FP32, BF16X3, BF16X6, FP16X3 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6, "fp16x3": FP16X3}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTHERM", -5: "ENAN", -6: "EUNSUPPORTED"}
 
 

@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (BF16X3, BF16X6, FP32, FP64, EphxError, check, host_ptr, lib, ptr, stream_ptr,  # noqa: F401
+from ._lib import (BF16X3, BF16X6, FP16X3, FP32, FP64, EphxError, check, host_ptr, lib, ptr, stream_ptr,  # noqa: F401
                    timer_enable, timer_get, timer_reset)
 
 F64 = torch.float64

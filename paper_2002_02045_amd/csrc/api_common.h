@@ -79,6 +79,7 @@ struct ephx_model {
     int32_t* d_rp_half = nullptr;  // [n_rp_half][3] its vectors
     int32_t* d_rp_pair = nullptr;  // [n_rp_half][2] index of R and of -R (-1: absent) in the Rp list
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
+    double g_scale = 1.0;        // power of two taking the Rp-contraction operand of g into fp16 range
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
     double* d_minv = nullptr;    // [nm]
     double* d_wg = nullptr;      // [n_re_g][n_rp_g] weight products, only if not all 1

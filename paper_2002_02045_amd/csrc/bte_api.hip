@@ -352,7 +352,7 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
         require(n_states >= 1 && n_states <= 60000, "table_create: need 1 <= n_states <= 60000");
         require(k_idx && band, "table_create: null state arrays");
         require(precision == EPHX_FP64 || precision == EPHX_FP32 || precision == EPHX_BF16X3 ||
-                    precision == EPHX_BF16X6,
+                    precision == EPHX_BF16X6 || precision == EPHX_FP16X3,
                 "table_create: unknown precision");
         require(std::isfinite(omega_cut), "table_create: omega_cut not finite");
         const long ng = (long)n1 * n2 * n3;
@@ -427,7 +427,10 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
             const long nre_cols = (long)m->n_rp_g * nm * nw2;
             const long ncol = (long)nm * nw;       // Rp-contraction columns per source
             const int kp = ((m->n_rp_g + 31) / 32) * 32;
-            const int nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+            const int nsplit = (precision == EPHX_BF16X3 || precision == EPHX_FP16X3) ? 2
+                               : (precision == EPHX_BF16X6 ? 3 : 0);
+            const int f16s = precision == EPHX_FP16X3 ? 1 : 0;
+            const double gsc = f16s ? m->g_scale : 1.0;
             int sc = (int)std::max(1L, std::min<long>(64, (1L << 29) / std::max(1L, (long)S * ncol * 16)));
             sc = std::min(sc, S);
             double* gk = (double*)t->ws.get("t.gk", (size_t)sc * nre_cols * 16);
@@ -450,9 +453,10 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
                     phase_gemm_f32(S, (int)ncol, m->n_rp_g, nb, dks, dnks + 3L * s0, m->d_rp_g, gcol32, sB,
                                    (float*)gwt, (long)S * ncol, st);
                 } else {
-                    split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ncol, kp, gcol, gbf, st);
-                    phase_gemm_bf16(nsplit, S, (int)ncol, m->n_rp_g, kp, nb, dks, dnks + 3L * s0, m->d_rp_g, gbf,
-                                    2L * nsplit * ncol * kp, (float*)gwt, (long)S * ncol, st);
+                    split_bf16_f64(nsplit, f16s, gsc, nb, m->n_rp_g, (int)ncol, kp, gcol, gbf, st);
+                    phase_gemm_bf16(nsplit, f16s, S, (int)ncol, m->n_rp_g, kp, nb, dks, dnks + 3L * s0, m->d_rp_g,
+                                    gbf, 2L * nsplit * ncol * kp, (float*)gwt, (long)S * ncol, (float)(1.0 / gsc),
+                                    st);
                 }
                 PairEpilogue e{};
                 e.ns_chunk = nb;

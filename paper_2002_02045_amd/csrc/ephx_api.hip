@@ -379,6 +379,28 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                         for (size_t i = 0; i < per; ++i) g[o + i] = w * d->g[o + i];
                     }
                 m->d_g = (double*)up(g.data(), ng * sizeof(double));
+                // fp16 scale of the Rp-contraction operand: an entry of g(k,Rp) V
+                // (V unitary, or one of its columns) is at most sum_Re sum_j
+                // |g(Re,Rp)_ij| for its row i, and a half-set coefficient at most twice
+                // that; the largest power of two keeping it under 2^14 (fp16 ends at
+                // 65504) is the model's scale
+                std::vector<double> rs((size_t)d->n_rp_g * nm * nw, 0.0);
+                for (int e = 0; e < d->n_re_g; ++e)
+                    for (int p = 0; p < d->n_rp_g; ++p)
+                        for (int a = 0; a < nm; ++a)
+                            for (int i = 0; i < nw; ++i) {
+                                double t = 0.0;
+                                for (int j = 0; j < nw; ++j) {
+                                    const size_t o = (((((size_t)e * d->n_rp_g + p) * nm + a) * nw + i) * nw + j) * 2;
+                                    t += std::hypot(g[o], g[o + 1]);
+                                }
+                                rs[((size_t)p * nm + a) * nw + i] += t;
+                            }
+                double bound = 0.0;
+                for (double v : rs) bound = std::max(bound, 2.0 * v);
+                m->g_scale = bound > 0.0 ? std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(
+                                                                                           std::log2(16384.0 / bound)))))
+                                         : 1.0;
             }
             {
                 bool unit = true;
@@ -518,6 +540,7 @@ struct DriverPlan {
     long ngcol, nre_cols;
     bool f32, wide;
     size_t npair;
+    bool f16;      // split parts in fp16 (FP16x3)
     bool half;     // Rp sum over the half set with real coefficients
     int kh, kh16;  // half-set size, and rounded up to 16
 };
@@ -544,7 +567,8 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
     d.kh = m->n_rp_half;
     d.kh16 = ((d.kh + 15) / 16) * 16;
     d.kp = d.half ? 2 * d.kh16 : ((m->n_rp_g + 31) / 32) * 32;
-    d.nsplit = precision == EPHX_BF16X3 ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+    d.nsplit = (precision == EPHX_BF16X3 || precision == EPHX_FP16X3) ? 2 : (precision == EPHX_BF16X6 ? 3 : 0);
+    d.f16 = precision == EPHX_FP16X3;
     d.npair = (size_t)d.bk_eff * d.qc;
     return d;
 }
@@ -634,6 +658,9 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
     uint16_t* gpbf = nullptr;
     void* gph = nullptr;   // half-set coefficients [k][Kh][2][ngcol] complex (FP64, FP32)
     const bool half = dp.half;
+    // fp16 parts: g(k,Rp) U(k) scaled into fp16 range (bf16 keeps FP32's range)
+    const int f16s = dp.f16 ? 1 : 0;
+    const double gsc = dp.f16 ? m->g_scale : 1.0;
     if (half && !dp.nsplit) gph = m->ws.get("drv.gph", (size_t)bk_eff * dp.kh * 2 * ngcol * (f32 ? 8 : 16));
     if (precision == EPHX_FP32 && !half) gp32 = (float*)m->ws.get("drv.gp32", (size_t)bk_eff * nre_cols * 8);
     const int nsplit = dp.nsplit;
@@ -681,14 +708,15 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
         if (half) {
             if (nsplit)
-                split_bf16_half(nsplit, nb, m->n_rp_g, (int)ngcol, dp.kh, dp.kh16, m->d_rp_pair, gp, gpbf, st);
+                split_bf16_half(nsplit, f16s, gsc, nb, m->n_rp_g, (int)ngcol, dp.kh, dp.kh16, m->d_rp_pair, gp, gpbf,
+                                st);
             else if (precision == EPHX_FP32)
                 half_combine_f32(nb, m->n_rp_g, (int)ngcol, dp.kh, m->d_rp_pair, gp, (float*)gph, st);
             else
                 half_combine_f64(nb, m->n_rp_g, (int)ngcol, dp.kh, m->d_rp_pair, gp, (double*)gph, st);
         } else {
             if (precision == EPHX_FP32) convert_f64_f32((long)nb * nre_cols * 2, gp, gp32, st);
-            if (nsplit) split_bf16_f64(nsplit, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
+            if (nsplit) split_bf16_f64(nsplit, f16s, gsc, nb, m->n_rp_g, (int)ngcol, kp, gp, gpbf, st);
         }
         if (acc) hip_check(hipMemsetAsync(acc, 0, (size_t)nb * nw * nm * 8, st), "hipMemsetAsync");
         for (int q0 = 0; q0 < nq; q0 += qc) {
@@ -709,16 +737,16 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             if (nsplit) {
                 StageTimer tph("rp_phases", st);
                 if (half)
-                    phase_planes_half(nsplit, nqc, dp.kh, dp.kh16, qb, m->d_rp_half, qpl, st);
+                    phase_planes_half(nsplit, f16s, nqc, dp.kh, dp.kh16, qb, m->d_rp_half, qpl, st);
                 else
-                    phase_planes_bf16(nsplit, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
+                    phase_planes_bf16(nsplit, f16s, nqc, m->n_rp_g, kp, qb, m->d_rp_g, qpl, st);
             }
             // Rp contraction per k
             StageTimer trp("rp_contraction", st);
             const long sh = (long)dp.kh * 2 * ngcol;
             if (nsplit)
-                gemm_bf16_planes(nsplit, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp, (float*)gw,
-                                 (long)nqc * ngcol, half ? 1 : 0, st);
+                gemm_bf16_planes(nsplit, f16s, nqc, (int)ngcol, kp, nb, qpl, gpbf, 2L * nsplit * ngcol * kp,
+                                 (float*)gw, (long)nqc * ngcol, half ? 1 : 0, (float)(1.0 / gsc), st);
             else if (half && precision == EPHX_FP64)
                 phase_gemm_half_f64(nqc, (int)ngcol, dp.kh, nb, qb, m->d_rp_half, (const double*)gph, sh,
                                     (double*)gw, (long)nqc * ngcol, st);
@@ -964,7 +992,7 @@ extern "C" int ephx_phonons(ephx_model* m, int nq, const double* q_red, double* 
 
 static void check_precision(int precision) {
     require(precision == EPHX_FP64 || precision == EPHX_FP32 || precision == EPHX_BF16X3 ||
-                precision == EPHX_BF16X6,
+                precision == EPHX_BF16X6 || precision == EPHX_FP16X3,
             "unknown precision");
 }
 

@@ -66,16 +66,18 @@ void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x
                     hipStream_t st);
 // Split-bf16 contraction: B given as 2*nsplit bf16 planes [Z][2*nsplit][N][Kp]
 // (re parts then im parts), Kp % 32 == 0; nsplit 2 = BF16x3, 3 = BF16x6.
-void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
-                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC,
+// f16 = 1 (nsplit 2): fp16 parts instead ("FP16x3"), B scaled by a power of two
+// when split and the output multiplied by oscale, its inverse (1 for bf16).
+void phase_gemm_bf16(int nsplit, int f16, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
+                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC, float oscale,
                      hipStream_t st);
 // Split-bf16 phase planes [2*nsplit][M][Kp] of exp(2 pi i x_m . n_r) (cos parts
 // then sin parts), and the contraction C[z] = A B[z] that reads them.
-void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const int32_t* nvec, uint16_t* out,
-                       hipStream_t st);
+void phase_planes_bf16(int nsplit, int f16, int M, int K, int Kp, const double* x, const int32_t* nvec,
+                       uint16_t* out, hipStream_t st);
 // real_a = 1: A is real, [nsplit][M][Kp] (half-set cos and sin parts along k).
-void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
-                      float* C, long sC, int real_a, hipStream_t st);
+void gemm_bf16_planes(int nsplit, int f16, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs,
+                      long sB, float* C, long sC, int real_a, float oscale, hipStream_t st);
 // Half-set form of a Fourier sum over a list closed under R -> -R apart from
 // unpaired vectors (see phase_gemm.hip): pair [Kh][2] = (index of R_h, index of
 // -R_h or -1) into the list, G [Z][K][N] complex double.
@@ -91,12 +93,12 @@ void phase_gemm_half_f64(int M, int N, int Kh, int Z, const double* x, const int
                          double* C, long sC, hipStream_t st);
 void phase_gemm_half_f32(int M, int N, int Kh, int Z, const double* x, const int32_t* nvec, const float* B, long sB,
                          float* C, long sC, hipStream_t st);
-void split_bf16_half(int nsplit, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair, const double* G,
-                     uint16_t* out, hipStream_t st);
-void phase_planes_half(int nsplit, int M, int Kh, int Kh16, const double* x, const int32_t* nvec, uint16_t* out,
-                       hipStream_t st);
-// Split complex double B[Z][K][N] into those planes.
-void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
+void split_bf16_half(int nsplit, int f16, double scale, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair,
+                     const double* G, uint16_t* out, hipStream_t st);
+void phase_planes_half(int nsplit, int f16, int M, int Kh, int Kh16, const double* x, const int32_t* nvec,
+                       uint16_t* out, hipStream_t st);
+// Split complex double B[Z][K][N], times scale, into those planes.
+void split_bf16_f64(int nsplit, int f16, double scale, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
                     hipStream_t st);
 
 // Hermitian eigensolver in FP64: n <= kEigMax by wavefronts (64/n-ish matrices

@@ -196,24 +196,52 @@ __device__ __forceinline__ void split_n(float x, unsigned short* part) {
     }
 }
 
+// split x into NS fp16 parts (round to nearest even each time): 11 significant
+// bits per part against 8 for bf16, over a narrower exponent range (the
+// callers scale the operand into it)
+template <int NS>
+__device__ __forceinline__ void split_h(float x, unsigned short* part) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const _Float16 h = (_Float16)x;
+        part[i] = __builtin_bit_cast(unsigned short, h);
+        x -= (float)h;
+    }
+}
+template <int NS, bool F16>
+__device__ __forceinline__ void split_p(float x, unsigned short* part) {
+    if constexpr (F16)
+        split_h<NS>(x, part);
+    else
+        split_n<NS>(x, part);
+}
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <bool F16>
 __device__ __forceinline__ flt4 mfma_bf(const u16x8& a, const u16x8& b, flt4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
 constexpr int kBK = 32;     // K per MFMA step
 constexpr int kPadK = 8;    // LDS row padding (bf16 elements)
 
 // NS = 2: "BF16x3" (products p_i q_j with i + j <= 1, three per real product);
-// NS = 3: "BF16x6" (i + j <= 2, six per real product).  Accumulation in FP32;
-// the smallest products are issued first.
-template <int CB, int NS>
+// NS = 3: "BF16x6" (i + j <= 2, six per real product).  F16: the parts are fp16
+// ("FP16x3" with NS = 2), B scaled by a power of two that the output undoes
+// (oscale).  Accumulation in FP32; the smallest products are issued first.
+template <int CB, int NS, bool F16 = false>
 __global__ __launch_bounds__(256) void k_phase_gemm_bf16(int M, int N, int K, int Kp,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ x0,
                                                          const int32_t* __restrict__ nvec,
                                                          const uint16_t* __restrict__ Bs, long sB,
-                                                         float* __restrict__ C, long sC) {
+                                                         float* __restrict__ C, long sC, float oscale) {
     constexpr int BN = 16 * CB;
     constexpr int NP = 2 * NS;   // planes: re parts 0..NS-1, im parts NS..2NS-1
     __shared__ __attribute__((aligned(16))) uint16_t bsh[NP][BN][kBK + kPadK];
@@ -269,13 +297,13 @@ __global__ __launch_bounds__(256) void k_phase_gemm_bf16(int M, int N, int K, in
             float pc = 0.f, ps = 0.f;
             if (rowok && kc + kk < K) phase_of(reduced_arg(xa, xb, xc, ns[kk]), pc, ps);
             unsigned short pr[NS], pi[NS];
-            split_n<NS>(pc, pr);
-            split_n<NS>(ps, pi);
+            split_p<NS, F16>(pc, pr);
+            split_p<NS, F16>(ps, pi);
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
                 ar[t][j] = pr[t];
                 ai[t][j] = pi[t];
-                nai[t][j] = pi[t] ^ 0x8000u;
+                nai[t][j] = pi[t] ^ 0x8000u;   // sign bit of bf16 and fp16 alike
             }
         }
 #pragma unroll
@@ -292,10 +320,10 @@ __global__ __launch_bounds__(256) void k_phase_gemm_bf16(int M, int N, int K, in
 #pragma unroll
                 for (int i = 0; i <= ord; ++i) {
                     const int j = ord - i;
-                    are[cb] = mfma_bf(ar[i], br[j], are[cb]);
-                    are[cb] = mfma_bf(nai[i], bi[j], are[cb]);
-                    aim[cb] = mfma_bf(ar[i], bi[j], aim[cb]);
-                    aim[cb] = mfma_bf(ai[i], br[j], aim[cb]);
+                    are[cb] = mfma_bf<F16>(ar[i], br[j], are[cb]);
+                    are[cb] = mfma_bf<F16>(nai[i], bi[j], are[cb]);
+                    aim[cb] = mfma_bf<F16>(ar[i], bi[j], aim[cb]);
+                    aim[cb] = mfma_bf<F16>(ai[i], br[j], aim[cb]);
                 }
             }
         }
@@ -309,15 +337,16 @@ __global__ __launch_bounds__(256) void k_phase_gemm_bf16(int M, int N, int K, in
             const int row = row0 + wave * 16 + AccOf<float>::row(lk, v);
             if (row < M && col < N) {
                 const long off = ((long)row * N + col) * 2;
-                cz[off] = are[cb][v];
-                cz[off + 1] = aim[cb][v];
+                cz[off] = are[cb][v] * oscale;
+                cz[off + 1] = aim[cb][v] * oscale;
             }
         }
     }
 }
 
-template <int NS>
-__global__ void k_split_bf16(int K, int N, int Kp, const double* __restrict__ B, uint16_t* __restrict__ out) {
+template <int NS, bool F16 = false>
+__global__ void k_split_bf16(int K, int N, int Kp, double scale, const double* __restrict__ B,
+                             uint16_t* __restrict__ out) {
     // one thread per (z, n, k) output element, k fastest; planes re_0..re_{NS-1}, im_0..
     const int z = blockIdx.z;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,12 +355,12 @@ __global__ void k_split_bf16(int K, int N, int Kp, const double* __restrict__ B,
     float re = 0.f, im = 0.f;
     if (k < K) {
         const long off = ((long)z * K * N + (long)k * N + n) * 2;
-        re = (float)B[off];
-        im = (float)B[off + 1];
+        re = (float)(scale * B[off]);
+        im = (float)(scale * B[off + 1]);
     }
     unsigned short pr[NS], pi[NS];
-    split_n<NS>(re, pr);
-    split_n<NS>(im, pi);
+    split_p<NS, F16>(re, pr);
+    split_p<NS, F16>(im, pi);
     uint16_t* oz = out + (long)z * 2 * NS * N * Kp;
     for (int t = 0; t < NS; ++t) {
         oz[((long)t * N + n) * Kp + k] = pr[t];
@@ -345,7 +374,7 @@ __global__ void k_split_bf16(int K, int N, int Kp, const double* __restrict__ B,
 //   planes[NS + t][m][r] = part t of sin(2 pi x_m . n_r)
 // r padded to Kp with zero parts.  The values equal those the in-register
 // path generates (same reduced argument, same FP32 sin/cos, same split).
-template <int NS>
+template <int NS, bool F16 = false>
 __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ x, const int32_t* __restrict__ nvec,
                                uint16_t* __restrict__ out) {
     const int kg = Kp / 8;
@@ -359,8 +388,8 @@ __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ 
         float pc = 0.f, ps = 0.f;
         if (r0 + j < K) phase_of(reduced_arg(xa, xb, xc, nvec + 3L * (r0 + j)), pc, ps);
         unsigned short hr[NS], hi[NS];
-        split_n<NS>(pc, hr);
-        split_n<NS>(ps, hi);
+        split_p<NS, F16>(pc, hr);
+        split_p<NS, F16>(ps, hi);
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             pr[t][j] = hr[t];
@@ -393,9 +422,14 @@ __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ 
 // of the row, so the 16-lane passes of a ds_read_b128 hit distinct banks.
 typedef float flt16 __attribute__((ext_vector_type(16)));
 
+template <bool F16>
 __device__ __forceinline__ flt16 mfma_bf32(const u16x8& a, const u16x8& b, flt16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
 }
 
 constexpr int kBMP = 128;              // rows per workgroup (32 per wave)
@@ -404,11 +438,13 @@ __device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) 
 
 // RA = true: A is real, [NS][M][Kp] (the cos and sin parts of a half-set sum
 // side by side along k), and C = A B takes two MFMAs per product instead of four.
-template <int CT, int NS, bool RA = false>
+// F16 = true: fp16 parts (FP16x3), the output multiplied by oscale (the power of
+// two that undoes the scaling of B).
+template <int CT, int NS, bool RA = false, bool F16 = false>
 __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
                                                           const uint16_t* __restrict__ As,
                                                           const uint16_t* __restrict__ Bs, long sB,
-                                                          float* __restrict__ C, long sC) {
+                                                          float* __restrict__ C, long sC, float oscale) {
     constexpr int BN = 32 * CT;
     constexpr int NP = 2 * NS;
     constexpr int PLANE = BN * kBK;          // bf16 elements of one plane in one buffer
@@ -514,11 +550,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
 #pragma unroll
                 for (int i = 0; i <= ord; ++i) {
                     const int j = ord - i;
-                    are[ct] = mfma_bf32(ar[s][i], br[cs][j], are[ct]);
-                    aim[ct] = mfma_bf32(ar[s][i], bi[cs][j], aim[ct]);
+                    are[ct] = mfma_bf32<F16>(ar[s][i], br[cs][j], are[ct]);
+                    aim[ct] = mfma_bf32<F16>(ar[s][i], bi[cs][j], aim[ct]);
                     if (!RA) {
-                        are[ct] = mfma_bf32(nai[s][i], bi[cs][j], are[ct]);
-                        aim[ct] = mfma_bf32(ai[s][i], br[cs][j], aim[ct]);
+                        are[ct] = mfma_bf32<F16>(nai[s][i], bi[cs][j], are[ct]);
+                        aim[ct] = mfma_bf32<F16>(ai[s][i], br[cs][j], aim[ct]);
                     }
                 }
             }
@@ -532,8 +568,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
             const int row = row0 + wave * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
             if (row < M && col < N) {
                 const long off = ((long)row * N + col) * 2;
-                cz[off] = are[ct][v];
-                cz[off + 1] = aim[ct][v];
+                cz[off] = are[ct][v] * oscale;
+                cz[off + 1] = aim[ct][v] * oscale;
             }
         }
     }
@@ -568,8 +604,8 @@ __global__ void k_half_combine(int K, int N, int Kh, const int32_t* __restrict__
 // The same coefficients as split-bf16 planes for the real-A contraction:
 // [Z][2NS][N][2 Kh16] (re parts, then im parts), k = h for Gc_h and Kh16 + h for
 // Gs_h, zero parts at h >= Kh (Kh16 = Kh rounded up to 16).
-template <int NS>
-__global__ void k_split_bf16_half(int K, int N, int Kh, int Kh16, const int32_t* __restrict__ pair,
+template <int NS, bool F16 = false>
+__global__ void k_split_bf16_half(int K, int N, int Kh, int Kh16, double scale, const int32_t* __restrict__ pair,
                                   const double* __restrict__ G, uint16_t* __restrict__ out) {
     const int z = blockIdx.z;
     const int Kp = 2 * Kh16;
@@ -585,12 +621,12 @@ __global__ void k_split_bf16_half(int K, int N, int Kh, int Kh16, const int32_t*
         const double ar = gz[((long)p * N + n) * 2], ai = gz[((long)p * N + n) * 2 + 1];
         const double br = q >= 0 ? gz[((long)q * N + n) * 2] : 0.0;
         const double bi = q >= 0 ? gz[((long)q * N + n) * 2 + 1] : 0.0;
-        re = (float)(sn ? bi - ai : ar + br);
-        im = (float)(sn ? ar - br : ai + bi);
+        re = (float)(scale * (sn ? bi - ai : ar + br));
+        im = (float)(scale * (sn ? ar - br : ai + bi));
     }
     unsigned short pr[NS], pi[NS];
-    split_n<NS>(re, pr);
-    split_n<NS>(im, pi);
+    split_p<NS, F16>(re, pr);
+    split_p<NS, F16>(im, pi);
     uint16_t* oz = out + (long)z * 2 * NS * N * Kp;
     for (int t = 0; t < NS; ++t) {
         oz[((long)t * N + n) * Kp + k] = pr[t];
@@ -600,7 +636,7 @@ __global__ void k_split_bf16_half(int K, int N, int Kh, int Kh16, const int32_t*
 
 // Real phase planes of a half set for the same contraction: [NS][M][2 Kh16],
 // part t of cos(2 pi x_m.R_h) at k = h and of sin(2 pi x_m.R_h) at Kh16 + h.
-template <int NS>
+template <int NS, bool F16 = false>
 __global__ void k_phase_planes_half(int M, int Kh, int Kh16, const double* __restrict__ x,
                                     const int32_t* __restrict__ nvec, uint16_t* __restrict__ out) {
     const int kg = Kh16 / 8, Kp = 2 * Kh16;
@@ -614,8 +650,8 @@ __global__ void k_phase_planes_half(int M, int Kh, int Kh16, const double* __res
         float pc = 0.f, ps = 0.f;
         if (h0 + j < Kh) phase_of(reduced_arg(xa, xb, xc, nvec + 3L * (h0 + j)), pc, ps);
         unsigned short hr[NS], hi[NS];
-        split_n<NS>(pc, hr);
-        split_n<NS>(ps, hi);
+        split_p<NS, F16>(pc, hr);
+        split_p<NS, F16>(ps, hi);
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             pr[t][j] = hr[t];
@@ -736,48 +772,59 @@ void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x
     check_launch("phase_gemm_f32");
 }
 
-void phase_gemm_bf16(int nsplit, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
-                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC, hipStream_t st) {
+void phase_gemm_bf16(int nsplit, int f16, int M, int N, int K, int Kp, int Z, const double* x, const double* x0,
+                     const int32_t* nvec, const uint16_t* Bs, long sB, float* C, long sC, float oscale,
+                     hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0 || Kp < K) throw Error{-1, "phase_gemm_bf16: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "phase_gemm_bf16: nsplit must be 2 or 3"};
+    if (f16 && nsplit != 2) throw Error{-1, "phase_gemm_bf16: fp16 parts need nsplit 2"};
     const int cb = pick_cb(N, 8);
     dim3 grid((N + 16 * cb - 1) / (16 * cb), (M + kBM - 1) / kBM, Z);
-#define EPHX_BF(CBV, NSV) \
-    hipLaunchKernelGGL((k_phase_gemm_bf16<CBV, NSV>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, C, sC)
-    if (nsplit == 2) {
-        if (cb == 3) EPHX_BF(3, 2);
-        else if (cb == 4) EPHX_BF(4, 2);
-        else EPHX_BF(8, 2);
+#define EPHX_BF(CBV, NSV, F16V)                                                                                      \
+    hipLaunchKernelGGL((k_phase_gemm_bf16<CBV, NSV, F16V>), grid, dim3(256), 0, st, M, N, K, Kp, x, x0, nvec, Bs, sB, \
+                       C, sC, oscale)
+    if (f16) {
+        if (cb == 3) EPHX_BF(3, 2, true);
+        else if (cb == 4) EPHX_BF(4, 2, true);
+        else EPHX_BF(8, 2, true);
+    } else if (nsplit == 2) {
+        if (cb == 3) EPHX_BF(3, 2, false);
+        else if (cb == 4) EPHX_BF(4, 2, false);
+        else EPHX_BF(8, 2, false);
     } else {
-        if (cb == 3) EPHX_BF(3, 3);
-        else if (cb == 4) EPHX_BF(4, 3);
-        else EPHX_BF(8, 3);
+        if (cb == 3) EPHX_BF(3, 3, false);
+        else if (cb == 4) EPHX_BF(4, 3, false);
+        else EPHX_BF(8, 3, false);
     }
 #undef EPHX_BF
     check_launch("phase_gemm_bf16");
 }
 
-void phase_planes_bf16(int nsplit, int M, int K, int Kp, const double* x, const int32_t* nvec, uint16_t* out,
-                       hipStream_t st) {
+void phase_planes_bf16(int nsplit, int f16, int M, int K, int Kp, const double* x, const int32_t* nvec,
+                       uint16_t* out, hipStream_t st) {
     if (M <= 0) return;
     if (Kp % kBK != 0 || Kp < K) throw Error{-1, "phase_planes_bf16: bad Kp"};
+    if (f16 && nsplit != 2) throw Error{-1, "phase_planes_bf16: fp16 parts need nsplit 2"};
     const long total = (long)M * (Kp / 8);
     dim3 grid((unsigned)((total + 255) / 256));
-    if (nsplit == 2)
-        hipLaunchKernelGGL(k_phase_planes<2>, grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
+    if (f16)
+        hipLaunchKernelGGL((k_phase_planes<2, true>), grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
+    else if (nsplit == 2)
+        hipLaunchKernelGGL((k_phase_planes<2, false>), grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
     else if (nsplit == 3)
-        hipLaunchKernelGGL(k_phase_planes<3>, grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
+        hipLaunchKernelGGL((k_phase_planes<3, false>), grid, dim3(256), 0, st, M, K, Kp, x, nvec, out);
     else
         throw Error{-1, "phase_planes_bf16: nsplit must be 2 or 3"};
     check_launch("phase_planes_bf16");
 }
 
-void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs, long sB,
-                      float* C, long sC, int real_a, hipStream_t st) {
+void gemm_bf16_planes(int nsplit, int f16, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs,
+                      long sB, float* C, long sC, int real_a, float oscale, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
     if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
+    if (f16 && nsplit != 2) throw Error{-1, "gemm_bf16_planes: fp16 parts need nsplit 2"};
     // real A: 96-column tiles where they divide N (72 KB of LDS for BF16x6, two
     // workgroups per CU)
     const int ct = N <= 64 ? 2 : (real_a && N % 96 == 0 ? 3 : 4);
@@ -785,26 +832,26 @@ void gemm_bf16_planes(int nsplit, int M, int N, int Kp, int Z, const uint16_t* A
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
     dim3 grid((unsigned)nblk);
-#define EPHX_BFP(CTV, NSV, RAV)                                                                                  \
-    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV, RAV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, Bs, \
-                       sB, C, sC)
-    if (real_a) {
-        if (nsplit == 2) {
-            if (ct == 2) EPHX_BFP(2, 2, true);
-            else if (ct == 3) EPHX_BFP(3, 2, true);
-            else EPHX_BFP(4, 2, true);
-        } else {
-            if (ct == 2) EPHX_BFP(2, 3, true);
-            else if (ct == 3) EPHX_BFP(3, 3, true);
-            else EPHX_BFP(4, 3, true);
-        }
-    } else if (nsplit == 2) {
-        if (ct == 2) EPHX_BFP(2, 2, false);
-        else EPHX_BFP(4, 2, false);
+#define EPHX_BFP(CTV, NSV, RAV, F16V)                                                                              \
+    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV, RAV, F16V>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, \
+                       Bs, sB, C, sC, oscale)
+#define EPHX_BFP_CT(NSV, RAV, F16V)              \
+    do {                                         \
+        if (ct == 2) EPHX_BFP(2, NSV, RAV, F16V); \
+        else if (ct == 3) EPHX_BFP(3, NSV, RAV, F16V); \
+        else EPHX_BFP(4, NSV, RAV, F16V);         \
+    } while (0)
+    if (f16) {
+        if (real_a) EPHX_BFP_CT(2, true, true);
+        else EPHX_BFP_CT(2, false, true);
+    } else if (real_a) {
+        if (nsplit == 2) EPHX_BFP_CT(2, true, false);
+        else EPHX_BFP_CT(3, true, false);
     } else {
-        if (ct == 2) EPHX_BFP(2, 3, false);
-        else EPHX_BFP(4, 3, false);
+        if (nsplit == 2) EPHX_BFP_CT(2, false, false);
+        else EPHX_BFP_CT(3, false, false);
     }
+#undef EPHX_BFP_CT
 #undef EPHX_BFP
     check_launch("gemm_bf16_planes");
 }
@@ -825,31 +872,37 @@ void half_combine_f32(int Z, int K, int N, int Kh, const int32_t* pair, const do
     check_launch("half_combine_f32");
 }
 
-void split_bf16_half(int nsplit, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair, const double* G,
-                     uint16_t* out, hipStream_t st) {
+void split_bf16_half(int nsplit, int f16, double scale, int Z, int K, int N, int Kh, int Kh16, const int32_t* pair,
+                     const double* G, uint16_t* out, hipStream_t st) {
     if (Kh16 % 16 != 0 || Kh16 < Kh) throw Error{-1, "split_bf16_half: bad Kh16"};
+    if (f16 && nsplit != 2) throw Error{-1, "split_bf16_half: fp16 parts need nsplit 2"};
     const long total = (long)N * 2 * Kh16;
     if (total <= 0 || Z <= 0) return;
     dim3 grid((unsigned)((total + 255) / 256), 1, Z);
-    if (nsplit == 2)
-        hipLaunchKernelGGL(k_split_bf16_half<2>, grid, dim3(256), 0, st, K, N, Kh, Kh16, pair, G, out);
+    if (f16)
+        hipLaunchKernelGGL((k_split_bf16_half<2, true>), grid, dim3(256), 0, st, K, N, Kh, Kh16, scale, pair, G, out);
+    else if (nsplit == 2)
+        hipLaunchKernelGGL((k_split_bf16_half<2, false>), grid, dim3(256), 0, st, K, N, Kh, Kh16, scale, pair, G, out);
     else if (nsplit == 3)
-        hipLaunchKernelGGL(k_split_bf16_half<3>, grid, dim3(256), 0, st, K, N, Kh, Kh16, pair, G, out);
+        hipLaunchKernelGGL((k_split_bf16_half<3, false>), grid, dim3(256), 0, st, K, N, Kh, Kh16, scale, pair, G, out);
     else
         throw Error{-1, "split_bf16_half: nsplit must be 2 or 3"};
     check_launch("split_bf16_half");
 }
 
-void phase_planes_half(int nsplit, int M, int Kh, int Kh16, const double* x, const int32_t* nvec, uint16_t* out,
-                       hipStream_t st) {
+void phase_planes_half(int nsplit, int f16, int M, int Kh, int Kh16, const double* x, const int32_t* nvec,
+                       uint16_t* out, hipStream_t st) {
     if (M <= 0) return;
     if (Kh16 % 16 != 0 || Kh16 < Kh) throw Error{-1, "phase_planes_half: bad Kh16"};
+    if (f16 && nsplit != 2) throw Error{-1, "phase_planes_half: fp16 parts need nsplit 2"};
     const long total = (long)M * (Kh16 / 8);
     dim3 grid((unsigned)((total + 255) / 256));
-    if (nsplit == 2)
-        hipLaunchKernelGGL(k_phase_planes_half<2>, grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
+    if (f16)
+        hipLaunchKernelGGL((k_phase_planes_half<2, true>), grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
+    else if (nsplit == 2)
+        hipLaunchKernelGGL((k_phase_planes_half<2, false>), grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
     else if (nsplit == 3)
-        hipLaunchKernelGGL(k_phase_planes_half<3>, grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
+        hipLaunchKernelGGL((k_phase_planes_half<3, false>), grid, dim3(256), 0, st, M, Kh, Kh16, x, nvec, out);
     else
         throw Error{-1, "phase_planes_half: nsplit must be 2 or 3"};
     check_launch("phase_planes_half");
@@ -881,13 +934,17 @@ void phase_gemm_half_f32(int M, int N, int Kh, int Z, const double* x, const int
     check_launch("phase_gemm_half_f32");
 }
 
-void split_bf16_f64(int nsplit, int Z, int K, int N, int Kp, const double* B, uint16_t* out, hipStream_t st) {
+void split_bf16_f64(int nsplit, int f16, double scale, int Z, int K, int N, int Kp, const double* B, uint16_t* out,
+                    hipStream_t st) {
+    if (f16 && nsplit != 2) throw Error{-1, "split_bf16_f64: fp16 parts need nsplit 2"};
     const long total = (long)N * Kp;
     dim3 grid((unsigned)((total + 255) / 256), 1, Z);
-    if (nsplit == 2)
-        hipLaunchKernelGGL(k_split_bf16<2>, grid, dim3(256), 0, st, K, N, Kp, B, out);
+    if (f16)
+        hipLaunchKernelGGL((k_split_bf16<2, true>), grid, dim3(256), 0, st, K, N, Kp, scale, B, out);
+    else if (nsplit == 2)
+        hipLaunchKernelGGL((k_split_bf16<2, false>), grid, dim3(256), 0, st, K, N, Kp, scale, B, out);
     else
-        hipLaunchKernelGGL(k_split_bf16<3>, grid, dim3(256), 0, st, K, N, Kp, B, out);
+        hipLaunchKernelGGL((k_split_bf16<3, false>), grid, dim3(256), 0, st, K, N, Kp, scale, B, out);
     check_launch("split_bf16");
 }
 

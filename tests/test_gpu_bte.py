@@ -80,7 +80,7 @@ def small_case(tiny):
     return n, kk, bb, g2s, om, eps
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5), ("fp16x3", 1e-5)])
 def test_table_parity(lib, tiny, small_case, prec, tol):
     _say("pair table tiny 6^3, S=60, prec=%s" % prec)
     m, dm = tiny

@@ -91,7 +91,8 @@ def gkq_case(tiny):
 # BF16x3 (two bf16 parts, three products) carries a representation error of
 # ~3*2^-18 per product; its measured |g|^2 error on this case is 1.02e-5
 # (p99 8e-6), so its bound here is 2e-5.  BF16x6 meets 1e-5 with margin.
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-5), ("bf16x6", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-5), ("bf16x6", 1e-5),
+                                      ("fp16x3", 1e-5)])
 def test_gkq_parity(lib, tiny, gkq_case, prec, tol):
     _say("gkq parity tiny model prec=%s" % prec)
     m, dm = tiny
@@ -103,7 +104,7 @@ def test_gkq_parity(lib, tiny, gkq_case, prec, tol):
     assert emax <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5), ("fp16x3", 1e-5)])
 def test_gkq_parity_one_sided_rp(lib, prec, tol):
     """An Rp list without any +/-R pair (R = 0 and the vectors that are
     lexicographically positive) leaves the half-set form nothing to gain, so the
@@ -134,7 +135,7 @@ def test_rates_parity(lib, tiny):
     par = dict(temp=c["T"], mu=c["mu"], sigma=0.05)
     go, gmo = eph.rates(m, k, q, **par)
     p = lib.Params(temp=c["T"], mu=c["mu"], sigma=0.05, omega_cut=1e-4)
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16x6", 1e-4)):
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16x6", 1e-4), ("fp16x3", 1e-4)):
         g, gm = lib.rates(dm, k, q, p, precision=prec)
         err = rate_error(g.cpu().numpy(), go.numpy())
         errm = rate_error(gm.cpu().numpy(), gmo.numpy())

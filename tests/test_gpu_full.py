@@ -26,7 +26,8 @@ from oracle import eph
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4), ("bf16x6", 1e-5, 1e-4), ("bf16x3", 2e-5, 1e-4)]
+PRECS = [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4), ("bf16x6", 1e-5, 1e-4), ("bf16x3", 2e-5, 1e-4),
+         ("fp16x3", 1e-5, 1e-4)]
 
 
 def _say(msg):

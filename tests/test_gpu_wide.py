@@ -80,7 +80,7 @@ def wide_case(wide):
     return k, q, blk, ref
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5), ("fp16x3", 1e-5)])
 def test_wide_gkq_parity(lib, wide, wide_case, prec, tol):
     _say("gkq parity nw=20, 15 modes, prec=%s" % prec)
     m, dm = wide
@@ -99,7 +99,7 @@ def test_wide_rates_parity(lib, wide):
     q = synth.random_points(206, 90)
     go, gmo = eph.rates(m, k, q, temp=300.0, mu=0.0, sigma=0.1)
     p = lib.Params(temp=300.0, mu=0.0, sigma=0.1, omega_cut=1e-4)
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x6", 1e-4)):
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x6", 1e-4), ("fp16x3", 1e-4)):
         g, gm = lib.rates(dm, k, q, p, precision=prec)
         err = rate_error(g.cpu().numpy(), go.numpy())
         errm = rate_error(gm.cpu().numpy(), gmo.numpy())
