@@ -440,11 +440,14 @@ __device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) 
 // side by side along k), and C = A B takes two MFMAs per product instead of four.
 // F16 = true: fp16 parts (FP16x3), the output multiplied by oscale (the power of
 // two that undoes the scaling of B).
-template <int CT, int NS, bool RA = false, bool F16 = false>
+template <int CT, int NS, bool RA = false, bool F16 = false, int RTW = 1>
 __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
                                                           const uint16_t* __restrict__ As,
                                                           const uint16_t* __restrict__ Bs, long sB,
                                                           float* __restrict__ C, long sC, float oscale) {
+    // RTW row tiles of 32 per wave: each B fragment read from LDS feeds RTW
+    // times the MFMAs
+    constexpr int BMW = 32 * RTW, BM = 4 * BMW;
     constexpr int BN = 32 * CT;
     constexpr int NP = 2 * NS;
     constexpr int PLANE = BN * kBK;          // bf16 elements of one plane in one buffer
@@ -458,24 +461,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
     const int base = nblk / 8, rem = nblk % 8;
     const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
     const int bx = tile % nbx, by = (tile / nbx) % nby, z = tile / (nbx * nby);
-    const int row0 = by * kBMP, col0 = bx * BN;
+    const int row0 = by * BM, col0 = bx * BN;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int l32 = lane & 31, kg = lane >> 5;
     const uint16_t* bz = Bs + (long)z * sB;
     float* cz = C + (long)z * sC * 2;
-    flt16 are[CT], aim[CT];
+    flt16 are[RTW][CT], aim[RTW][CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+    for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            are[ct][v] = 0.f;
-            aim[ct][v] = 0.f;
-        }
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                are[rt][ct][v] = 0.f;
+                aim[rt][ct][v] = 0.f;
+            }
     // rows and columns past the edge load the last valid one: their results are
     // never stored, and the loads need no branch
-    const int arow_i = min(row0 + wave * 32 + l32, M - 1);
-    const uint16_t* arow = As + (long)arow_i * Kp + 8 * kg;
+    const uint16_t* arow[RTW];
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+        arow[rt] = As + (long)min(row0 + wave * BMW + rt * 32 + l32, M - 1) * Kp + 8 * kg;
     const long plane = (long)M * Kp;
     const u16x8 sign = {0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u};
     // B panel of the chunk at kc into buffer h: wave w fills blocks w, w+4, ...;
@@ -494,15 +501,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
         }
     };
     // A fragments of the chunk at kc: k-steps s = 0, 1 of 16
-    u16x8 anr[2][NS], ani[2][NS];
+    u16x8 anr[RTW][2][NS], ani[RTW][2][NS];
     auto load_a = [&](int kc) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                anr[s][t] = *reinterpret_cast<const u16x8*>(arow + t * plane + kc + 16 * s);
-                if (!RA) ani[s][t] = *reinterpret_cast<const u16x8*>(arow + (NS + t) * plane + kc + 16 * s);
-            }
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int t = 0; t < NS; ++t) {
+                    anr[rt][s][t] = *reinterpret_cast<const u16x8*>(arow[rt] + t * plane + kc + 16 * s);
+                    if (!RA)
+                        ani[rt][s][t] = *reinterpret_cast<const u16x8*>(arow[rt] + (NS + t) * plane + kc + 16 * s);
+                }
     };
     issue_b(0, 0);
     load_a(0);
@@ -512,17 +522,19 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
         // every wave has finished reading the other buffer
         __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        u16x8 ar[2][NS], ai[2][NS], nai[2][NS];
+        u16x8 ar[RTW][2][NS], ai[RTW][2][NS], nai[RTW][2][NS];
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                ar[s][t] = anr[s][t];
-                if (!RA) {
-                    ai[s][t] = ani[s][t];
-                    nai[s][t] = ani[s][t] ^ sign;
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int t = 0; t < NS; ++t) {
+                    ar[rt][s][t] = anr[rt][s][t];
+                    if (!RA) {
+                        ai[rt][s][t] = ani[rt][s][t];
+                        nai[rt][s][t] = ani[rt][s][t] ^ sign;
+                    }
                 }
-            }
         if (kc + kBK < Kp) {
             issue_b(kc + kBK, h ^ 1);
             load_a(kc + kBK);
@@ -546,33 +558,37 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
             if (g + 1 < 2 * CT) read_b(g + 1, (g + 1) & 1);
             const int ct = g >> 1, s = g & 1, cs = g & 1;
 #pragma unroll
-            for (int ord = NS - 1; ord >= 0; --ord) {
+            for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-                for (int i = 0; i <= ord; ++i) {
-                    const int j = ord - i;
-                    are[ct] = mfma_bf32<F16>(ar[s][i], br[cs][j], are[ct]);
-                    aim[ct] = mfma_bf32<F16>(ar[s][i], bi[cs][j], aim[ct]);
-                    if (!RA) {
-                        are[ct] = mfma_bf32<F16>(nai[s][i], bi[cs][j], are[ct]);
-                        aim[ct] = mfma_bf32<F16>(ai[s][i], br[cs][j], aim[ct]);
+                for (int ord = NS - 1; ord >= 0; --ord) {
+#pragma unroll
+                    for (int i = 0; i <= ord; ++i) {
+                        const int j = ord - i;
+                        are[rt][ct] = mfma_bf32<F16>(ar[rt][s][i], br[cs][j], are[rt][ct]);
+                        aim[rt][ct] = mfma_bf32<F16>(ar[rt][s][i], bi[cs][j], aim[rt][ct]);
+                        if (!RA) {
+                            are[rt][ct] = mfma_bf32<F16>(nai[rt][s][i], bi[cs][j], are[rt][ct]);
+                            aim[rt][ct] = mfma_bf32<F16>(ai[rt][s][i], br[cs][j], aim[rt][ct]);
+                        }
                     }
+                }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int col = col0 + ct * 32 + l32;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = row0 + wave * BMW + rt * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+                if (row < M && col < N) {
+                    const long off = ((long)row * N + col) * 2;
+                    cz[off] = are[rt][ct][v] * oscale;
+                    cz[off + 1] = aim[rt][ct][v] * oscale;
                 }
             }
         }
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const int col = col0 + ct * 32 + l32;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int row = row0 + wave * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
-            if (row < M && col < N) {
-                const long off = ((long)row * N + col) * 2;
-                cz[off] = are[ct][v] * oscale;
-                cz[off + 1] = aim[ct][v] * oscale;
-            }
-        }
-    }
 }
 
 // Half-set form of a Fourier sum over a vector list that is closed under
@@ -828,28 +844,30 @@ void gemm_bf16_planes(int nsplit, int f16, int M, int N, int Kp, int Z, const ui
     // real A: 96-column tiles where they divide N (72 KB of LDS for BF16x6, two
     // workgroups per CU)
     const int ct = N <= 64 ? 2 : (real_a && N % 96 == 0 ? 3 : 4);
-    const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + kBMP - 1) / kBMP;
+    // two 32-row tiles per wave for the three-product real-A forms
+    const int rtw = real_a && nsplit == 2 ? 2 : 1;
+    const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + kBMP * rtw - 1) / (kBMP * rtw);
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
     dim3 grid((unsigned)nblk);
-#define EPHX_BFP(CTV, NSV, RAV, F16V)                                                                              \
-    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV, RAV, F16V>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, A, \
-                       Bs, sB, C, sC, oscale)
-#define EPHX_BFP_CT(NSV, RAV, F16V)              \
-    do {                                         \
-        if (ct == 2) EPHX_BFP(2, NSV, RAV, F16V); \
-        else if (ct == 3) EPHX_BFP(3, NSV, RAV, F16V); \
-        else EPHX_BFP(4, NSV, RAV, F16V);         \
+#define EPHX_BFP(CTV, NSV, RAV, F16V, RTV)                                                                           \
+    hipLaunchKernelGGL((k_gemm_bf16_planes<CTV, NSV, RAV, F16V, RTV>), grid, dim3(256), 0, st, M, N, Kp, nbx, nby, Z, \
+                       A, Bs, sB, C, sC, oscale)
+#define EPHX_BFP_CT(NSV, RAV, F16V, RTV)                \
+    do {                                                \
+        if (ct == 2) EPHX_BFP(2, NSV, RAV, F16V, RTV);       \
+        else if (ct == 3) EPHX_BFP(3, NSV, RAV, F16V, RTV);  \
+        else EPHX_BFP(4, NSV, RAV, F16V, RTV);               \
     } while (0)
     if (f16) {
-        if (real_a) EPHX_BFP_CT(2, true, true);
-        else EPHX_BFP_CT(2, false, true);
+        if (real_a) EPHX_BFP_CT(2, true, true, 2);
+        else EPHX_BFP_CT(2, false, true, 1);
     } else if (real_a) {
-        if (nsplit == 2) EPHX_BFP_CT(2, true, false);
-        else EPHX_BFP_CT(3, true, false);
+        if (nsplit == 2) EPHX_BFP_CT(2, true, false, 2);
+        else EPHX_BFP_CT(3, true, false, 1);
     } else {
-        if (nsplit == 2) EPHX_BFP_CT(2, false, false);
-        else EPHX_BFP_CT(3, false, false);
+        if (nsplit == 2) EPHX_BFP_CT(2, false, false, 1);
+        else EPHX_BFP_CT(3, false, false, 1);
     }
 #undef EPHX_BFP_CT
 #undef EPHX_BFP
