@@ -195,7 +195,8 @@ int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red,
  * eigenvectors of H and D do not depend on g, so the chain is the adjoint of
  * Eqs. eph_mat, eph_mat_wann2 and scatter_rate: per pair
  * g_bar = 2 (2 pi/hbar) gamma_bar w_q D g, back through the mode projection and
- * rotation, then the conjugate-phase sums over q and k. */
+ * rotation, then the conjugate-phase sums over q and k.  Above Nw = 16 or 12
+ * modes the per-pair adjoint runs as batched GEMMs, like the forward. */
 int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
                    const double* q_red, const double* q_w, const double* gamma_bar, double* g_bar,
                    void* stream);

@@ -245,8 +245,10 @@ __global__ __launch_bounds__(256) void k_wide_rates(WideChunk w) {
     w.partial[(((long)z * w.nblk + blk) * nw + n) * nm + nu] = acc * (2.0 * kPi / kHbarEvFs);
 }
 
+// rotation, long-range term and projection: w.g ends as g_mn,nu; w.gh and
+// w.pmat hold g^H and P(q)
 template <typename T>
-void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
+void wide_forward(const WideChunk& w, hipStream_t st) {
     const int nw = w.nw, nm = w.nm, nw2 = nw * nw;
     const long npair = (long)w.nkb * w.nq;
     T* gw = reinterpret_cast<T*>(w.g);
@@ -295,6 +297,13 @@ void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
         b.sc1 = b.sb1;
         launch_cgemm<T, double, T, false>(nm, nw2, nm, npair, b, w.pmat, nm, gh, nw2, gw, nw2, st);
     }
+}
+
+template <typename T>
+void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
+    const int nw = w.nw, nm = w.nm, nw2 = nw * nw;
+    const long npair = (long)w.nkb * w.nq;
+    wide_forward<T>(w, st);
     if (rates) {
         if (w.qpb > kWideQ) throw Error{-1, "wide_rates: q block too large"};
         hipLaunchKernelGGL(k_wide_rates<T>, dim3((nm * nw + 255) / 256, w.nblk, w.nkb), dim3(256), 0, st, w);
@@ -306,7 +315,79 @@ void wide_chunk(const WideChunk& w, int rates, hipStream_t st) {
     }
 }
 
+// Adjoint of the rates for L = sum_nk lam_nk Gamma_nk, per element (pair, nu, m, n):
+//   gbar_mn,nu = 2 (2 pi/hbar) lam_n w_q D_mn,nu g_mn,nu,
+//   D = delta(e_n - hw - e_m)(1 + N - f_m) + delta(e_n + hw - e_m)(N + f_m)
+// (FP64, the same Gaussians and cut-offs as the forward).
+__global__ void k_wide_rates_bar(WideChunk w, const double* __restrict__ lam, double* __restrict__ gbar) {
+    const int nw = w.nw, nm = w.nm;
+    const long per = (long)nm * nw * nw;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)w.nkb * w.nq * per) return;
+    const long pair = t / per;
+    const int nu = (int)((t % per) / (nw * nw)), m = (int)((t / nw) % nw), n = (int)(t % nw);
+    const int z = (int)(pair / w.nq);
+    const long qg = (long)w.q_off + pair % w.nq;
+    const double om = w.omega[qg * nm + nu];
+    double f = 0.0;
+    if (om > w.omega_cut) {
+        const double kt = kBoltzEv * w.temp;
+        const double is = 1.0 / w.sigma, nrm = 1.0 / (sqrt(kPi) * w.sigma);
+        const double nb = 1.0 / expm1(om / kt);
+        const double em = w.ekq[pair * nw + m];
+        const double fm = 1.0 / (exp((em - w.mu) / kt) + 1.0);
+        const double en = w.ek[(long)z * nw + n];
+        const double wq = w.qw ? w.qw[qg] : w.uniform_w;
+        const double x1 = (en - om - em) * is, x2 = (en + om - em) * is;
+        const double de = x1 * x1 > 200.0 ? 0.0 : nrm * exp(-x1 * x1);
+        const double da = x2 * x2 > 200.0 ? 0.0 : nrm * exp(-x2 * x2);
+        f = 2.0 * (2.0 * kPi / kHbarEvFs) * lam[(long)(w.k_off + z) * nw + n] * wq *
+            (de * (1.0 + nb - fm) + da * (nb + fm));
+    }
+    const double* g = reinterpret_cast<const double*>(w.g);
+    gbar[2 * t] = f * g[2 * t];
+    gbar[2 * t + 1] = f * g[2 * t + 1];
+}
+
 }  // namespace
+
+// FP64: g'W_bar[pair][x] = U(k+q) sum_nu conj(P_nu,x) gbar_nu, through w.g and
+// w.gh as work (the forward is recomputed first).
+void eph_wide_rates_vjp(const WideChunk& w, const double* lam, double* gwbar, hipStream_t st) {
+    if (w.nkb <= 0 || w.nq <= 0) return;
+    const int nw = w.nw, nm = w.nm, nw2 = nw * nw;
+    const long npair = (long)w.nkb * w.nq;
+    wide_forward<double>(w, st);
+    double* g = reinterpret_cast<double*>(w.g);
+    double* gb = reinterpret_cast<double*>(w.gh);
+    const long tot = npair * nm * nw2;
+    hipLaunchKernelGGL(k_wide_rates_bar, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w, lam, gb);
+    check_launch("wide_rates_bar");
+    {
+        // adjoint of the projection: batch (z, q), A = P(q) read conjugate-transposed
+        CBatch b{};
+        b.n1 = w.nq;
+        b.sa0 = 0;
+        b.sa1 = (long)nm * nm;
+        b.sb0 = (long)w.nq * nm * nw2;
+        b.sb1 = (long)nm * nw2;
+        b.sc0 = b.sb0;
+        b.sc1 = b.sb1;
+        launch_cgemm<double, double, double, true>(nm, nw2, nm, npair, b, w.pmat, nm, gb, nw2, g, nw2, st);
+    }
+    {
+        // adjoint of the rotation: batch (pair, x), A = U(k+q)
+        CBatch b{};
+        b.n1 = nm;
+        b.sa0 = nw2;
+        b.sa1 = 0;
+        b.sb0 = (long)nm * nw2;
+        b.sb1 = nw2;
+        b.sc0 = (long)nm * nw2;
+        b.sc1 = nw2;
+        launch_cgemm<double, double, double, false>(nw, nw, nw, npair * nm, b, w.ukq, nw, g, nw, gwbar, nw, st);
+    }
+}
 
 void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st) {
     if (w.nkb <= 0 || w.nq <= 0) return;

@@ -881,8 +881,15 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
         frohlich(nq, q, m->pd, lr, st);
     }
     negated_vectors(m);
+    const bool wide = is_wide(m);
     const int bk = std::min(nk, 16);
-    const int qc = (int)std::max(64L, std::min((long)nq, (1L << 17) / bk));
+    int qc = (int)std::max(64L, std::min((long)nq, (1L << 17) / bk));
+    if (wide) {
+        // large models: the per-pair blocks (g'^W, its adjoint and the GEMM work,
+        // nm nw^2 complex each) set the chunk, about 6 GB of them
+        const long per_pair = ngcol * 16 * 3 + (long)nw2 * 48 + (m->polar ? (long)nw2 * 16 : 0);
+        qc = (int)std::max(1L, std::min((long)nq, std::max(16L, (6L << 30) / per_pair) / bk));
+    }
     double* ek = (double*)m->ws.get("adj.ek", (size_t)bk * nw * 8);
     double* uk = (double*)m->ws.get("adj.uk", (size_t)bk * nw2 * 16);
     double* gk = (double*)m->ws.get("adj.gk", (size_t)bk * nre_cols * 16);
@@ -895,6 +902,9 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
     double* ukq = (double*)m->ws.get("adj.ukq", npair * nw2 * 16);
     double* gw = (double*)m->ws.get("adj.gw", npair * ngcol * 16);
     double* gwb = (double*)m->ws.get("adj.gwb", npair * ngcol * 16);
+    double* gh = wide ? (double*)m->ws.get("adj.gh", npair * ngcol * 16) : nullptr;
+    double* pmat = wide ? (double*)m->ws.get("adj.pmat", (size_t)qc * nm * nm * 16) : nullptr;
+    double* ovb = wide && m->polar ? (double*)m->ws.get("adj.ov", npair * nw2 * 16) : nullptr;
     hip_check(hipMemsetAsync(gbar, 0, (size_t)m->n_re_g * nre_cols * 16, st), "hipMemsetAsync");
     for (int k0 = 0; k0 < nk; k0 += bk) {
         const int nb = std::min(bk, nk - k0);
@@ -910,6 +920,37 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
             hkq_eig(m, (long)nb * nqc, hkq, ekq, ukq, st);
             phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, gw,
                            (long)nqc * ngcol, st);
+            if (wide) {
+                WideChunk w{};
+                w.nkb = nb;
+                w.nq = nqc;
+                w.q_off = q0;
+                w.nw = nw;
+                w.nm = nm;
+                w.g = gw;
+                w.gh = gh;
+                w.pmat = pmat;
+                w.ov = ovb;
+                w.ukq = ukq;
+                w.ekq = ekq;
+                w.ek = ek;
+                w.uk = uk;
+                w.omega = om;
+                w.evec = ev;
+                w.lr = lr;
+                w.minv = m->d_minv;
+                w.omega_cut = p->omega_cut;
+                w.temp = p->temp;
+                w.mu = p->mu;
+                w.sigma = p->sigma;
+                w.qw = qw;
+                w.uniform_w = 1.0 / nq;
+                w.k_off = k0;
+                eph_wide_rates_vjp(w, lam, gwb, st);
+                phase_gemm_adj_f64(m->n_rp_g, (int)ngcol, nqc, nb, m->d_nrp_g, qb, gwb, (long)nqc * ngcol, gpb,
+                                   nre_cols, q0 > 0 ? 1 : 0, st);
+                continue;
+            }
             EphEpilogue e{};
             e.nkb = nb;
             e.nq = nqc;
@@ -955,8 +996,6 @@ extern "C" int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const
         require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
                 "rates_vjp: need temp > 0, sigma > 0, finite mu and omega_cut");
         require(g_bar != nullptr, "rates_vjp: null output");
-        if (is_wide(m))
-            throw Error{EPHX_EUNSUPPORTED, "rates_vjp: not built for models with nw > 16 or more than 12 modes"};
         hipStream_t st = (hipStream_t)stream;
         if (nk == 0 || nq == 0) {
             hip_check(hipMemsetAsync(g_bar, 0, (size_t)m->n_re_g * m->n_rp_g * m->nm * m->nw * m->nw * 16, st),

@@ -205,6 +205,9 @@ struct WideChunk {
     int nblk, qpb;
 };
 void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st);
+// Adjoint of the rates of a chunk (FP64; w.g holds g'^W on entry and is work):
+// gwbar [nkb][nq][nm][nw][nw] = dL/dg'^W for L = sum_nk lam_nk Gamma_nk.
+void eph_wide_rates_vjp(const WideChunk& w, const double* lam, double* gwbar, hipStream_t st);
 
 // Froehlich term: lr[q][3*kappa+a] (complex double) for q in [nq][3].
 struct PolarDev {
