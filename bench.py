@@ -415,6 +415,20 @@ def cell_bench(px, args):
         got = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision=prec).double())
         res[prec]["g2_err_vs_fp64"] = float(((got - ref).abs().flatten(2).max(dim=2).values
                                              / bmax.clamp_min(1e-300)).max())
+    # adjoint of the rates w.r.t. g(Re,Rp) (FP64) on a slice: 4 k x 64 q
+    ka, qa = ks[:4], qd[:64]
+    lam = torch.ones((len(ka), nw), dtype=torch.float64, device="cuda")
+    px.rates_vjp(dm, ka, qa[:8], par, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gbar = px.rates_vjp(dm, ka, qa, par, lam)
+    torch.cuda.synchronize()
+    dt_adj = time.perf_counter() - t0
+    adj = {"pairs": len(ka) * len(qa), "seconds": round(dt_adj, 4), "pairs_per_s": len(ka) * len(qa) / dt_adj,
+           "g_bar_bytes": gbar.numel() * 16}
+    log("large cell rates adjoint w.r.t. g(Re,Rp): %d pairs in %.3f s (%.3g pairs/s), g_bar %.2f GB"
+        % (adj["pairs"], dt_adj, adj["pairs_per_s"], adj["g_bar_bytes"] / 1e9))
+    del gbar
     del dm
     return {
         "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, large cell)",
@@ -422,6 +436,7 @@ def cell_bench(px, args):
                                "(3^3 sets), %d window k x %d random q, T=300 K, sigma=5 meV" % (n_re, n_rp, len(ks), len(q))},
         "flops_per_pair": {"rp_contraction": fl_rp, "rotation_projection": fl_ep},
         "by_precision": res,
+        "rates_adjoint_fp64": adj,
     }
 
 
