@@ -279,13 +279,16 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     __shared__ double red[2][256];
     __shared__ double dg[kWgMax];
     __shared__ int rk[kWgMax];
-    __shared__ double sbuf[kLds ? 4 * kWgLds * kWgLds : 2];
+    // in LDS the rows are padded by one complex element, so that a column
+    // (stride ld) walks across the banks instead of hitting one
+    __shared__ double sbuf[kLds ? 4 * kWgLds * (kWgLds + 1) : 2];
     const int tid = threadIdx.x;
     const long mi = blockIdx.x;
     double* ga = A + mi * strideA * 2;
     double* gv = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
+    const int ld = kLds ? n + 1 : n;   // complex elements per row of a and v
     double* a = kLds ? sbuf : ga;
-    double* v = kLds ? (gv ? sbuf + 2 * kWgLds * kWgLds : nullptr) : gv;
+    double* v = kLds ? (gv ? sbuf + 2 * kWgLds * (kWgLds + 1) : nullptr) : gv;
     const int nn = n * n;
     // Hermitian part 0.5 (A + A^dag), V = I
     for (int e = tid; e < nn; e += 256) {
@@ -293,17 +296,17 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
         if (i < j) {
             const double xr = 0.5 * (ga[2 * e] + ga[2 * (j * n + i)]);
             const double xi = 0.5 * (ga[2 * e + 1] - ga[2 * (j * n + i) + 1]);
-            a[2 * e] = xr;
-            a[2 * e + 1] = xi;
-            a[2 * (j * n + i)] = xr;
-            a[2 * (j * n + i) + 1] = -xi;
+            a[2 * (i * ld + j)] = xr;
+            a[2 * (i * ld + j) + 1] = xi;
+            a[2 * (j * ld + i)] = xr;
+            a[2 * (j * ld + i) + 1] = -xi;
         } else if (i == j) {
-            a[2 * e] = ga[2 * e];
-            a[2 * e + 1] = 0.0;
+            a[2 * (i * ld + i)] = ga[2 * e];
+            a[2 * (i * ld + i) + 1] = 0.0;
         }
         if (v) {
-            v[2 * e] = i == j ? 1.0 : 0.0;
-            v[2 * e + 1] = 0.0;
+            v[2 * (i * ld + j)] = i == j ? 1.0 : 0.0;
+            v[2 * (i * ld + j) + 1] = 0.0;
         }
     }
     __syncthreads();
@@ -311,9 +314,10 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     for (int sweep = 0; sweep < 50; ++sweep) {
         double off = 0.0, tot = 0.0;
         for (int e = tid; e < nn; e += 256) {
-            const double m2 = a[2 * e] * a[2 * e] + a[2 * e + 1] * a[2 * e + 1];
+            const int i = e / n, j = e % n;
+            const double m2 = a[2 * (i * ld + j)] * a[2 * (i * ld + j)] + a[2 * (i * ld + j) + 1] * a[2 * (i * ld + j) + 1];
             tot += m2;
-            off += (e / n != e % n) ? m2 : 0.0;
+            off += (i != j) ? m2 : 0.0;
         }
         red[0][tid] = off;
         red[1][tid] = tot;
@@ -334,11 +338,11 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
                 const int p = i1 < i2 ? i1 : i2, q = i1 < i2 ? i2 : i1;
                 double c = 1.0, sr = 0.0, si = 0.0;
                 if (q < n) {
-                    const double apr = a[2 * (p * n + q)], api = a[2 * (p * n + q) + 1];
+                    const double apr = a[2 * (p * ld + q)], api = a[2 * (p * ld + q) + 1];
                     const double m2 = apr * apr + api * api;
                     if (m2 > 0.0) {
                         // t/|a_pq| and se as in the wavefront solver
-                        const double d = a[2 * (q * n + q)] - a[2 * (p * n + p)];
+                        const double d = a[2 * (q * ld + q)] - a[2 * (p * ld + p)];
                         const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
                         c = rsqrt1(fma(tm * tm, m2, 1.0));
                         const double w = tm * c;
@@ -359,16 +363,16 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
                 const int p = pp[k], q = qq[k];
                 if (p == q) continue;
                 const double c = rc[k], sr = rsr[k], si = rsi[k];
-                double* x = a + 2 * (i * n + p);
-                double* y = a + 2 * (i * n + q);
+                double* x = a + 2 * (i * ld + p);
+                double* y = a + 2 * (i * ld + q);
                 const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
                 x[0] = c * xr - (sr * yr + si * yi);
                 x[1] = c * xi - (sr * yi - si * yr);
                 y[0] = (sr * xr - si * xi) + c * yr;
                 y[1] = (sr * xi + si * xr) + c * yi;
                 if (v) {
-                    double* u = v + 2 * (i * n + p);
-                    double* w = v + 2 * (i * n + q);
+                    double* u = v + 2 * (i * ld + p);
+                    double* w = v + 2 * (i * ld + q);
                     const double ur = u[0], ui = u[1], wr = w[0], wi = w[1];
                     u[0] = c * ur - (sr * wr + si * wi);
                     u[1] = c * ui - (sr * wi - si * wr);
@@ -383,8 +387,8 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
                 const int p = pp[k], q = qq[k];
                 if (p == q) continue;
                 const double c = rc[k], sr = rsr[k], si = rsi[k];
-                double* x = a + 2 * (p * n + j);
-                double* y = a + 2 * (q * n + j);
+                double* x = a + 2 * (p * ld + j);
+                double* y = a + 2 * (q * ld + j);
                 const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
                 x[0] = c * xr - (sr * yr - si * yi);
                 x[1] = c * xi - (sr * yi + si * yr);
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
         }
     }
     // sort ascending, ties by index
-    for (int i = tid; i < n; i += 256) dg[i] = a[2 * (i * n + i)];
+    for (int i = tid; i < n; i += 256) dg[i] = a[2 * (i * ld + i)];
     __syncthreads();
     for (int i = tid; i < n; i += 256) {
         int r = 0;
@@ -409,8 +413,8 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
             // columns of V go to their ranks directly
             for (int e = tid; e < nn; e += 256) {
                 const int i = e / n, c = e % n;
-                gv[2 * (i * n + rk[c])] = v[2 * e];
-                gv[2 * (i * n + rk[c]) + 1] = v[2 * e + 1];
+                gv[2 * (i * n + rk[c])] = v[2 * (i * ld + c)];
+                gv[2 * (i * n + rk[c]) + 1] = v[2 * (i * ld + c) + 1];
             }
         } else {
             // permute the columns of V through A's storage
