@@ -70,6 +70,37 @@ def test_wide_phonons_parity(lib, wide):
     assert float(res.abs().max()) <= 1e-10 * float(lam.abs().max())
 
 
+def test_eig_order_64_bands_and_120_modes(lib):
+    """The two sizes at the ends of the workgroup eigensolver's range: H(k) of
+    order 64 (the largest kept in LDS with its eigenvectors) and D(q) of order
+    120 (the large cell's 40 atoms, above the LDS range)."""
+    _say("bands parity, nw=64; phonons parity, 120 modes")
+    m = synth.make_config_model("wide", nw=64)
+    dm = lib.Model(m)
+    k = np.vstack([np.zeros((1, 3)), synth.random_points(205, 11)])
+    eps, u, _ = lib.bands(dm, k, want_u=True)
+    eo, _ = interp.bands(m, k)
+    scale = float(eo.abs().max())
+    assert float((eps.cpu() - eo).abs().max()) <= 1e-10 * scale
+    hk = interp.hamiltonian_k(m, k)
+    uc = u.cpu()
+    assert float((hk @ uc - uc * eps.cpu()[:, None, :]).abs().max()) <= 1e-10 * scale
+    assert float((uc.mH @ uc - torch.eye(64, dtype=torch.complex128)).abs().max()) <= 1e-12
+    del dm
+    mc = synth.make_config_model("cell", nw=2)
+    dc = lib.Model(mc)
+    q = np.vstack([np.zeros((1, 3)), synth.random_points(206, 7)])
+    om, ev = lib.phonons(dc, q)
+    oo, _ = interp.phonons(mc, q)
+    wmax = float(oo.abs().max())
+    assert float((om.cpu()[1:] - oo[1:]).abs().max()) <= 1e-10 * wmax
+    d = interp.dynamical_matrix(mc, q)
+    evc = ev.cpu()
+    lam = om.cpu().sign() * om.cpu() ** 2 / 0.004180159280496722
+    assert float((d @ evc - evc * lam[:, None, :]).abs().max()) <= 1e-10 * float(lam.abs().max())
+    assert float((evc.mH @ evc - torch.eye(120, dtype=torch.complex128)).abs().max()) <= 1e-12
+
+
 @pytest.fixture(scope="module")
 def wide_case(wide):
     m, _ = wide
