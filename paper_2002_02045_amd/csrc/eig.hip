@@ -432,6 +432,206 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     }
 }
 
+// Orders above the LDS range of k_eig_wg (64 < n <= 128): A is kept in LDS in
+// the packed Hermitian form (n*n reals, P[i][j] = Re A_ij for i <= j and Im A_ji
+// for i > j: 131 KB at n = 128) and each round applies J^dag A J at once, block
+// by block: the rows of pair a and the columns of pair b form a 2 x 2 block B,
+// and its new value is J_a^dag B J_b (the same column-then-row arithmetic as
+// the two-phase update), so only the blocks with a <= b are formed and the
+// rest follows by Hermiticity.  The eigenvectors accumulate transposed, V^T,
+// in A's global storage (the input is overwritten), so that the column update
+// V J of a round walks contiguous memory.
+__global__ __launch_bounds__(256) void k_eig_wg_packed(int n, double* __restrict__ A, long strideA,
+                                                       double* __restrict__ evals, double* __restrict__ evecs) {
+    __shared__ double P[kWgMax * kWgMax];
+    __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
+    __shared__ double rc[kWgMax / 2], rsr[kWgMax / 2], rsi[kWgMax / 2];
+    __shared__ double red[2][256];
+    __shared__ double dg[kWgMax];
+    __shared__ int rk[kWgMax];
+    const int tid = threadIdx.x;
+    const long mi = blockIdx.x;
+    double* ga = A + mi * strideA * 2;
+    const bool want_v = evecs != nullptr;
+    const int nn = n * n;
+    // packed Hermitian part 0.5 (A + A^dag)
+    for (int e = tid; e < nn; e += 256) {
+        const int i = e / n, j = e % n;
+        if (i < j) {
+            P[i * n + j] = 0.5 * (ga[2 * e] + ga[2 * (j * n + i)]);
+            P[j * n + i] = 0.5 * (ga[2 * e + 1] - ga[2 * (j * n + i) + 1]);
+        } else if (i == j) {
+            P[i * n + i] = ga[2 * e];
+        }
+    }
+    __syncthreads();
+    // V^T = I over A's storage (read complete above)
+    if (want_v)
+        for (int e = tid; e < nn; e += 256) {
+            ga[2 * e] = (e / n == e % n) ? 1.0 : 0.0;
+            ga[2 * e + 1] = 0.0;
+        }
+    // element (i, j), i != j, of the Hermitian matrix from the packed form
+    auto get = [&](int i, int j, double& re, double& im) {
+        if (i < j) {
+            re = P[i * n + j];
+            im = P[j * n + i];
+        } else {
+            re = P[j * n + i];
+            im = -P[i * n + j];
+        }
+    };
+    auto put = [&](int i, int j, double re, double im) {
+        if (i < j) {
+            P[i * n + j] = re;
+            P[j * n + i] = im;
+        } else {
+            P[j * n + i] = re;
+            P[i * n + j] = -im;
+        }
+    };
+    const int ne = n + (n & 1), np = ne / 2;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < nn; e += 256) {
+            const int i = e / n, j = e % n;
+            if (i == j) {
+                tot += P[e] * P[e];
+            } else if (i < j) {
+                const double m2 = 2.0 * (P[e] * P[e] + P[j * n + i] * P[j * n + i]);
+                tot += m2;
+                off += m2;
+            }
+        }
+        red[0][tid] = off;
+        red[1][tid] = tot;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (tid < w) {
+                red[0][tid] += red[0][tid + w];
+                red[1][tid] += red[1][tid + w];
+            }
+            __syncthreads();
+        }
+        const bool done = !(red[0][0] > 1e-30 * red[1][0]);
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < ne - 1; ++r) {
+            if (tid < np) {
+                const int i1 = circle_index(tid, r, ne), i2 = circle_index(ne - 1 - tid, r, ne);
+                const int p = i1 < i2 ? i1 : i2, q = i1 < i2 ? i2 : i1;
+                double c = 1.0, sr = 0.0, si = 0.0;
+                if (q < n) {
+                    const double apr = P[p * n + q], api = P[q * n + p];
+                    const double m2 = apr * apr + api * api;
+                    if (m2 > 0.0) {
+                        const double d = P[q * n + q] - P[p * n + p];
+                        const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
+                        c = rsqrt1(fma(tm * tm, m2, 1.0));
+                        const double w = tm * c;
+                        sr = w * apr;
+                        si = w * api;
+                    }
+                }
+                pp[tid] = p;
+                qq[tid] = q < n ? q : p;   // a dummy partner never rotates
+                rc[tid] = c;
+                rsr[tid] = sr;
+                rsi[tid] = si;
+            }
+            __syncthreads();
+            // blocks (a, b), a <= b: B' = J_a^dag B J_b with J = [[c, se], [-conj(se), c]]
+            for (int t = tid; t < np * np; t += 256) {
+                const int a = t / np, b = t % np;
+                if (a > b) continue;
+                const int ra[2] = {pp[a], qq[a]}, cb[2] = {pp[b], qq[b]};
+                const int nr = ra[1] != ra[0] ? 2 : 1, nc = cb[1] != cb[0] ? 2 : 1;
+                double br_[2][2], bi_[2][2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int i = ra[x], j = cb[y];
+                        if (i == j) {
+                            br_[x][y] = P[i * n + i];
+                            bi_[x][y] = 0.0;
+                        } else {
+                            get(i, j, br_[x][y], bi_[x][y]);
+                        }
+                    }
+                // T = B J_b: T_.p = c B_.p - conj(s) B_.q ; T_.q = s B_.p + c B_.q
+                const double cb_ = rc[b], sbr = rsr[b], sbi = rsi[b];
+                double tr[2][2], ti[2][2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    const double ur = br_[x][0], ui = bi_[x][0], wr = br_[x][1], wi = bi_[x][1];
+                    tr[x][0] = cb_ * ur - (sbr * wr + sbi * wi);
+                    ti[x][0] = cb_ * ui - (sbr * wi - sbi * wr);
+                    tr[x][1] = (sbr * ur - sbi * ui) + cb_ * wr;
+                    ti[x][1] = (sbr * ui + sbi * ur) + cb_ * wi;
+                }
+                // B' = J_a^dag T: B'_p. = c T_p. - s T_q. ; B'_q. = conj(s) T_p. + c T_q.
+                const double ca = rc[a], sar = rsr[a], sai = rsi[a];
+                double orr[2][2], oi[2][2];
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const double xr = tr[0][y], xi = ti[0][y], yr = tr[1][y], yi = ti[1][y];
+                    orr[0][y] = ca * xr - (sar * yr - sai * yi);
+                    oi[0][y] = ca * xi - (sar * yi + sai * yr);
+                    orr[1][y] = (sar * xr + sai * xi) + ca * yr;
+                    oi[1][y] = (sar * xi - sai * xr) + ca * yi;
+                }
+                if (a == b) {
+                    // Hermitian diagonal block: two real diagonal entries, one pair
+                    P[ra[0] * n + ra[0]] = orr[0][0];
+                    if (nr == 2) {
+                        P[ra[1] * n + ra[1]] = orr[1][1];
+                        put(ra[0], ra[1], orr[0][1], oi[0][1]);
+                    }
+                } else {
+                    for (int x = 0; x < nr; ++x)
+                        for (int y = 0; y < nc; ++y) put(ra[x], cb[y], orr[x][y], oi[x][y]);
+                }
+            }
+            // V <- V J on V^T: rows p, q of V^T, contiguous over i
+            if (want_v)
+                for (int t = tid; t < np * n; t += 256) {
+                    const int b = t / n, i = t % n;
+                    const int p = pp[b], q = qq[b];
+                    if (p == q) continue;
+                    const double c = rc[b], sr = rsr[b], si = rsi[b];
+                    double* u = ga + 2 * ((long)p * n + i);
+                    double* w = ga + 2 * ((long)q * n + i);
+                    const double ur = u[0], ui = u[1], wr = w[0], wi = w[1];
+                    u[0] = c * ur - (sr * wr + si * wi);
+                    u[1] = c * ui - (sr * wi - si * wr);
+                    w[0] = (sr * ur - si * ui) + c * wr;
+                    w[1] = (sr * ui + si * ur) + c * wi;
+                }
+            __syncthreads();
+        }
+    }
+    // sort ascending, ties by index
+    for (int i = tid; i < n; i += 256) dg[i] = P[i * n + i];
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+        int r = 0;
+        for (int m = 0; m < n; ++m) r += (dg[m] < dg[i] || (dg[m] == dg[i] && m < i)) ? 1 : 0;
+        rk[i] = r;
+        evals[mi * n + r] = dg[i];
+    }
+    __syncthreads();
+    if (want_v) {
+        // column c of V (row c of V^T) goes to column rank(c) of the output
+        double* gv = evecs + mi * (long)n * n * 2;
+        for (int e = tid; e < nn; e += 256) {
+            const int c = e / n, i = e % n;
+            gv[2 * (i * n + rk[c])] = ga[2 * e];
+            gv[2 * (i * n + rk[c]) + 1] = ga[2 * e + 1];
+        }
+    }
+}
+
 __global__ void k_phonon_omega(long count, double* lam) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
@@ -473,7 +673,7 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
             hipLaunchKernelGGL(k_eig_wg<true>, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
                                evecs);
         else
-            hipLaunchKernelGGL(k_eig_wg<false>, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
+            hipLaunchKernelGGL(k_eig_wg_packed, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
                                evecs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
