@@ -259,19 +259,17 @@ __global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restri
 // Larger matrices (8 < n <= 128, e.g. H(k) of a 64-function model, D(q) of a
 // 40-atom cell): one 256-thread workgroup per matrix, the same rotations and
 // convergence test, with the n/2 disjoint rotations of a round (circle-method
-// ordering) applied by all threads at once.  Every round is three barriers
-// apart, so the latency of A and V decides the time: for n <= 64 both live in
-// LDS (2 x 64 KB); larger A (overwritten) and V (the eigenvector output) stay
-// in global memory, served by the workgroup's L1/L2.  The rotation parameters
-// of a round go through LDS.
+// ordering) applied by all threads at once.  For n <= 64 (k_eig_wg) A and V
+// live in LDS (2 x 65 KB, rows padded by one element) and a round is a column
+// pass and a row pass, three barriers apart; above, see k_eig_wg_packed.  The
+// rotation parameters of a round go through LDS.
 constexpr int kWgMax = 128;
-constexpr int kWgLds = 64;     // largest order kept in LDS
+constexpr int kWgLds = 64;     // largest order kept in LDS with its eigenvectors
 
 __device__ __forceinline__ int circle_index(int pos, int r, int ne) {
     return pos == 0 ? 0 : (pos - 1 + r) % (ne - 1) + 1;
 }
 
-template <bool kLds>
 __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, long strideA, double* __restrict__ evals,
                                                 double* __restrict__ evecs) {
     __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
@@ -281,14 +279,14 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     __shared__ int rk[kWgMax];
     // in LDS the rows are padded by one complex element, so that a column
     // (stride ld) walks across the banks instead of hitting one
-    __shared__ double sbuf[kLds ? 4 * kWgLds * (kWgLds + 1) : 2];
+    __shared__ double sbuf[4 * kWgLds * (kWgLds + 1)];
     const int tid = threadIdx.x;
     const long mi = blockIdx.x;
     double* ga = A + mi * strideA * 2;
     double* gv = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
-    const int ld = kLds ? n + 1 : n;   // complex elements per row of a and v
-    double* a = kLds ? sbuf : ga;
-    double* v = kLds ? (gv ? sbuf + 2 * kWgLds * (kWgLds + 1) : nullptr) : gv;
+    const int ld = n + 1;   // complex elements per row of a and v
+    double* a = sbuf;
+    double* v = gv ? sbuf + 2 * kWgLds * (kWgLds + 1) : nullptr;
     const int nn = n * n;
     // Hermitian part 0.5 (A + A^dag), V = I
     for (int e = tid; e < nn; e += 256) {
@@ -409,25 +407,11 @@ __global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, l
     }
     __syncthreads();
     if (gv) {
-        if (kLds) {
-            // columns of V go to their ranks directly
-            for (int e = tid; e < nn; e += 256) {
-                const int i = e / n, c = e % n;
-                gv[2 * (i * n + rk[c])] = v[2 * (i * ld + c)];
-                gv[2 * (i * n + rk[c]) + 1] = v[2 * (i * ld + c) + 1];
-            }
-        } else {
-            // permute the columns of V through A's storage
-            for (int e = tid; e < nn; e += 256) {
-                a[2 * e] = v[2 * e];
-                a[2 * e + 1] = v[2 * e + 1];
-            }
-            __syncthreads();
-            for (int e = tid; e < nn; e += 256) {
-                const int i = e / n, c = e % n;
-                v[2 * (i * n + rk[c])] = a[2 * e];
-                v[2 * (i * n + rk[c]) + 1] = a[2 * e + 1];
-            }
+        // columns of V go to their ranks directly
+        for (int e = tid; e < nn; e += 256) {
+            const int i = e / n, c = e % n;
+            gv[2 * (i * n + rk[c])] = v[2 * (i * ld + c)];
+            gv[2 * (i * n + rk[c]) + 1] = v[2 * (i * ld + c) + 1];
         }
     }
 }
@@ -670,7 +654,7 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
     if (n > kEigMax) {
         if (a_f32) throw Error{-1, "eig_herm: matrices above order 8 must be FP64"};
         if (n <= kWgLds)
-            hipLaunchKernelGGL(k_eig_wg<true>, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
+            hipLaunchKernelGGL(k_eig_wg, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
                                evecs);
         else
             hipLaunchKernelGGL(k_eig_wg_packed, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
