@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
     }
 }
 
-// ------------------------------------------------------------ split-bf16 variants
+// ------------------------------------------- split-precision (bf16 / fp16) variants
 __device__ __forceinline__ unsigned short bf16_bits_rn(float f) {
     unsigned int u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);
@@ -368,7 +368,7 @@ __global__ void k_split_bf16(int K, int N, int Kp, double scale, const double* _
     }
 }
 
-// Split-bf16 phase planes of one point set, computed once and read by every
+// Split phase planes (bf16, or fp16 with F16) of one point set, computed once and read by every
 // contraction over the same points (all k of a batch, all column blocks):
 //   planes[t][m][r]      = part t of cos(2 pi x_m . n_r)      (t < NS)
 //   planes[NS + t][m][r] = part t of sin(2 pi x_m . n_r)
@@ -403,12 +403,13 @@ __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ 
     }
 }
 
-// C[z] = A B[z] with A given as phase planes [2NS][M][Kp] and B[z] as planes
-// [2NS][N][Kp], on the 32x32x16 bf16 MFMA (twice the rate of the 16x16x32
-// shape on gfx950, measured from registers).  Operand lane l holds row (A) or
-// column (B) l%32 and the 8 consecutive k of group l/32; accumulator element v
-// of lane l is C[8(v/4) + 4(l/32) + v%4][l%32].  A workgroup owns 128 rows x
-// 32*CT columns, wave w the rows 32w..32w+31 against all CT column tiles.
+// C[z] = A B[z] with A given as phase planes [2NS][M][Kp] (real A: [NS][M][Kp])
+// and B[z] as planes [2NS][N][Kp], on the 32x32x16 bf16 (or fp16) MFMA (twice
+// the rate of the 16x16x32 shape on gfx950, measured from registers).  Operand
+// lane l holds row (A) or column (B) l%32 and the 8 consecutive k of group
+// l/32; accumulator element v of lane l is C[8(v/4) + 4(l/32) + v%4][l%32].  A
+// workgroup owns 128 RTW rows x 32*CT columns, wave w the rows of its RTW
+// 32-row tiles against all CT column tiles.
 // Workgroups are numbered so that each of the 8 XCDs (which receive
 // consecutive workgroup ids in turn) runs a contiguous range of (column, row, z)
 // tiles: the B panel of one z stays in that XCD's L2 while its row tiles
@@ -617,7 +618,8 @@ __global__ void k_half_combine(int K, int N, int Kh, const int32_t* __restrict__
     oz[(((long)h * 2 + 1) * N + n) * 2 + 1] = (T)(ar - br);
 }
 
-// The same coefficients as split-bf16 planes for the real-A contraction:
+// The same coefficients as split planes (bf16, or fp16 with F16, after the
+// scale) for the real-A contraction:
 // [Z][2NS][N][2 Kh16] (re parts, then im parts), k = h for Gc_h and Kh16 + h for
 // Gs_h, zero parts at h >= Kh (Kh16 = Kh rounded up to 16).
 template <int NS, bool F16 = false>
