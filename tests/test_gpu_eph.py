@@ -126,6 +126,27 @@ def test_gkq_parity_one_sided_rp(lib, prec, tol):
     assert emax <= tol
 
 
+@pytest.mark.parametrize("factor", [1e-6, 1e6])
+def test_fp16x3_scale_of_g(lib, factor):
+    """FP16x3 scales the g(k,Rp) operand into fp16's range by a power of two
+    fixed per model: a coupling tensor a million times smaller or larger than
+    the tiny model's must give the same relative |g|^2 error (no underflow to
+    zero, no overflow to inf)."""
+    import dataclasses
+    m = synth.make_config_model("tiny")
+    m = dataclasses.replace(m, g=m.g * factor)
+    _say("FP16x3 with g scaled by %g" % factor)
+    k = synth.random_points(151, 5)
+    q = synth.random_points(152, 60)
+    blk, ref = _oracle_g2_groups(m, k, q)
+    g2 = lib.gkq(lib.Model(m), k, q, precision="fp16x3")
+    assert bool(torch.isfinite(g2).all())
+    got = group_sums_g2(g2.double().cpu().numpy(), blk["eps_k"], blk["eps_kq"], blk["omega"])
+    emax, e99 = g2_error(got, ref)
+    _say("  |g|^2 error: max %.3e  p99 %.3e" % (emax, e99))
+    assert emax <= 1e-5
+
+
 def test_rates_parity(lib, tiny):
     _say("rates parity tiny model")
     m, dm = tiny
