@@ -247,7 +247,6 @@ def dynamics_bench(px, dm, model, args):
     dt = time.perf_counter() - t0
     px.timer_enable(False)
     ns, ms = px.timer_get("collision_stream")
-    nf, msf = px.timer_get("collision_finish")
     npm, mspm = px.timer_get("stream_permute")
     px.timer_reset()
     ld = (S + 63) // 64 * 64
@@ -287,7 +286,7 @@ def dynamics_bench(px, dm, model, args):
             "traffic": measured_traffic("k_stream<float, 1, 1>"), "traffic_unit": "HBM bytes per launch",
                      "bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms / ns, 5),
                      "dense_bytes": 4.0 * S * S, "live_tiles": n_live, "tiles": n_tiles},
-        "collision_evals_per_s": ns / (1e-3 * (ms + msf + mspm)) if ms > 0 else None,
+        "collision_evals_per_s": ns / (1e-3 * (ms + mspm)) if ms > 0 else None,
         "gather_reduce_ms_per_pass": round(mspm / max(1, ns), 5),
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,

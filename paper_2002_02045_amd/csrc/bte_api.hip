@@ -179,18 +179,24 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
                     const Field* fld = nullptr) {
     const int S = t->S;
     const StreamPlan pl = plan_for(t, 0, 1, 1, st);
-    double* omf = (double*)t->ws.get("c.omf", S * 8);
     double* rowp = (double*)t->ws.get("c.rowp", (size_t)pl.n_ct * S * 8);
     double* colp = (double*)t->ws.get("c.colp", (size_t)pl.n_rt * S * 8);
-    occ_vectors(S, y, nullptr, omf, nullptr, nullptr, st);
-    VecPtrs x{{omf, nullptr, nullptr, nullptr}}, yy{{y, nullptr, nullptr, nullptr}};
-    const PassOut po = one_pass(t, pl, t->d_p, x, yy, rowp, colp, st, "collision_stream");
+    // three kernels per evaluation: 1 - f and f gathered to matrix order, the
+    // stream over P, and the partials reduced and finished in state order
+    {
+        StageTimer tm("stream_permute", st);
+        gather_occupations(pl, y, st);
+    }
+    {
+        StageTimer tm("collision_stream", st);
+        stream_run(pl, t->ld, t->d_p, rowp, colp, st);
+    }
     CollisionFinish cf{};
     cf.S = S;
-    cf.n_rt = po.n_rt;
-    cf.n_ct = po.n_ct;
-    cf.rowp = po.rowp;
-    cf.colp = po.colp;
+    cf.n_rt = pl.n_rt;
+    cf.n_ct = pl.n_ct;
+    cf.rowp = rowp;
+    cf.colp = colp;
     cf.f = y;
     cf.c = t->c;
     cf.i_out = i_out;
@@ -202,8 +208,8 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
     cf.f_next = f_next;
     cf.nbr = fld ? fld->nbr : nullptr;
     for (int d = 0; d < 3; ++d) cf.dc[d] = fld ? fld->dc[d] : 0.0;
-    StageTimer tm("collision_finish", st);
-    collision_finish(cf, st);
+    StageTimer tm("stream_permute", st);
+    reduce_finish(pl, cf, st);
 }
 
 // f_bar = lam^T dI/df at f; s_bar (=/+=) lam^T dI/ds

@@ -366,29 +366,6 @@ __global__ __launch_bounds__(256) void k_stream(int S, long ld, const T* __restr
     }
 }
 
-__global__ void k_collision_finish(CollisionFinish cf) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= cf.S) return;
-    double r = 0.0, c = 0.0;
-    for (int ct = 0; ct < cf.n_ct; ++ct) r += cf.rowp[(long)ct * cf.S + s];
-    for (int rt = 0; rt < cf.n_rt; ++rt) c += cf.colp[(long)rt * cf.S + s];
-    const double f = cf.f[s];
-    const double i = -cf.c * (f * r - (1.0 - f) * c);
-    if (cf.i_out) cf.i_out[s] = i;
-    if (cf.acc) {
-        double rhs = i;
-        if (cf.nbr) {
-            const int32_t* nb = cf.nbr + 6L * s;
-            for (int d = 0; d < 3; ++d) {
-                const int p = nb[2 * d], m = nb[2 * d + 1];
-                rhs += cf.dc[d] * ((p >= 0 ? cf.f[p] : 0.0) - (m >= 0 ? cf.f[m] : 0.0));
-            }
-        }
-        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * rhs;
-        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * rhs;
-    }
-}
-
 // f_bar_u = -c [ lam_u (R0_u + C0_u) - C1_u - R1_u ]
 __global__ void k_vjp_finish(int S, int n_ct, int n_rt, const double* __restrict__ rowp,
                              const double* __restrict__ colp, const double* __restrict__ lam, double c,
@@ -889,6 +866,48 @@ __global__ void k_gather_vectors(int S, int nv, const int32_t* __restrict__ perm
     for (int k = 0; k < nv; ++k) out[(long)k * S + i] = k < na ? x.p[k][s] : y.p[k - na][s];
 }
 
+// The collision pass's vectors in matrix order straight from the occupations:
+// gbuf[0][i] = 1 - f[perm[i]] (rows), gbuf[1][i] = f[perm[i]] (columns)
+__global__ void k_gather_occupations(int S, const int32_t* __restrict__ perm, const double* __restrict__ f,
+                                     double* __restrict__ gbuf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const double fs = f[perm[i]];
+    gbuf[i] = 1.0 - fs;
+    gbuf[(long)S + i] = fs;
+}
+
+// The pass's partials reduced and the collision finished in one kernel: the
+// thread of matrix index i sums the row partials (n_ct) and column partials
+// (n_rt) of state s = perm[i] in fixed order, then forms
+//   I_s = -c [ f_s R_s - (1 - f_s) C_s ]
+// and the RK4 / Euler stage update: acc_s (=/+=) w_acc (I_s + drift_s),
+// f_next_s = f_base_s + a_next (I_s + drift_s), the drift from the neighbour
+// table (cf.rowp, cf.colp hold the unreduced matrix-order partials).
+__global__ void k_reduce_finish(CollisionFinish cf, const int32_t* __restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cf.S) return;
+    const int s = perm[i];
+    double r = 0.0, c = 0.0;
+    for (int ct = 0; ct < cf.n_ct; ++ct) r += cf.rowp[(long)ct * cf.S + i];
+    for (int rt = 0; rt < cf.n_rt; ++rt) c += cf.colp[(long)rt * cf.S + i];
+    const double f = cf.f[s];
+    const double in = -cf.c * (f * r - (1.0 - f) * c);
+    if (cf.i_out) cf.i_out[s] = in;
+    if (cf.acc) {
+        double rhs = in;
+        if (cf.nbr) {
+            const int32_t* nb = cf.nbr + 6L * s;
+            for (int d = 0; d < 3; ++d) {
+                const int p = nb[2 * d], m = nb[2 * d + 1];
+                rhs += cf.dc[d] * ((p >= 0 ? cf.f[p] : 0.0) - (m >= 0 ? cf.f[m] : 0.0));
+            }
+        }
+        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * rhs;
+        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * rhs;
+    }
+}
+
 // rout[a][perm[i]] = sum_ct rowp[a][ct][i], cout[b][perm[i]] = sum_rt colp[b][rt][i]
 // (fixed order: deterministic)
 __global__ void k_reduce_partials(int S, int na, int n_ct, const double* __restrict__ rowp, int nb, int n_rt,
@@ -959,9 +978,18 @@ PassOut stream_reduce(const StreamPlan& pl, const double* rowp, const double* co
     return out;
 }
 
-void collision_finish(const CollisionFinish& cf, hipStream_t st) {
-    hipLaunchKernelGGL(k_collision_finish, dim3((cf.S + 255) / 256), dim3(256), 0, st, cf);
-    check_launch("collision_finish");
+void gather_occupations(const StreamPlan& pl, const double* f, hipStream_t st) {
+    if (pl.S <= 0) return;
+    if (pl.na != 1 || pl.nb != 1 || !pl.perm || !pl.gbuf) throw Error{-1, "gather_occupations: needs a 1+1 plan"};
+    hipLaunchKernelGGL(k_gather_occupations, dim3((pl.S + 255) / 256), dim3(256), 0, st, pl.S, pl.perm, f, pl.gbuf);
+    check_launch("gather_occupations");
+}
+
+void reduce_finish(const StreamPlan& pl, const CollisionFinish& cf, hipStream_t st) {
+    if (cf.S <= 0) return;
+    if (!pl.perm || cf.S != pl.S) throw Error{-1, "reduce_finish: plan and finish disagree"};
+    hipLaunchKernelGGL(k_reduce_finish, dim3((cf.S + 255) / 256), dim3(256), 0, st, cf, pl.perm);
+    check_launch("reduce_finish");
 }
 
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,

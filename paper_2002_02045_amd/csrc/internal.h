@@ -376,7 +376,13 @@ struct CollisionFinish {
     const int32_t* nbr;
     double dc[3];
 };
-void collision_finish(const CollisionFinish& cf, hipStream_t st);
+// The collision pass of a 1+1 plan without the separate occupation, gather and
+// reduction kernels: gather_occupations fills the plan's gather buffer with
+// 1 - f and f in matrix order; reduce_finish takes the stream's unreduced
+// matrix-order partials (cf.rowp [n_ct][S], cf.colp [n_rt][S]) to I and the
+// stage update in state order.
+void gather_occupations(const StreamPlan& pl, const double* f, hipStream_t st);
+void reduce_finish(const StreamPlan& pl, const CollisionFinish& cf, hipStream_t st);
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
                 double* fbar, hipStream_t st);
 // s_bar[nu] (= or +=) -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t); part: [nm][S] scratch
