@@ -285,6 +285,25 @@ def dynamics_bench(px, dm, model, args):
     if not bool(torch.isfinite(f2).all()):
         raise RuntimeError("field dynamics produced non-finite occupations")
     log("dynamics: %.1f Euler steps/s with E = %g V/A along x" % (args.dyn_steps / dt_e, efield[0]))
+    # backward through time: the forward with checkpoints every 50 steps, then
+    # the reverse RK4 that replays each segment from its checkpoint (Eq. BTE_E
+    # with E = 0), for the gradients w.r.t. f0 and the six mode scales
+    nb = max(50, args.dyn_steps // 50 * 50)
+    ck = 50
+    tab.dynamics_vjp(tab.dynamics(f0, cfg["dt"], ck, ckpt_every=ck)[1], cfg["dt"], ck, ck, f0)   # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fT, cks = tab.dynamics(f0, cfg["dt"], nb, ckpt_every=ck)
+    torch.cuda.synchronize()
+    t_fwd_ck = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    f0_bar, s_bar = tab.dynamics_vjp(cks, cfg["dt"], nb, ck, torch.ones_like(fT))
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    if not (bool(torch.isfinite(f0_bar).all()) and bool(torch.isfinite(s_bar).all())):
+        raise RuntimeError("dynamics adjoint produced non-finite gradients")
+    log("dynamics: backward through %d RK4 steps %.3f s (%.1f steps/s, %.2fx the forward with checkpoints)" % (
+        nb, t_bwd, nb / t_bwd, t_bwd / t_fwd_ck))
     out = {
         "metric": "BTE collision steps/s (RK4 steps of the carrier dynamics)",
         "value": args.dyn_steps / dt, "unit": "RK4 steps/s", "steps": args.dyn_steps,
@@ -302,6 +321,8 @@ def dynamics_bench(px, dm, model, args):
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,
         "euler_field_steps_per_s": args.dyn_steps / dt_e, "euler_field_V_per_A": efield,
+        "rk4_backward_steps_per_s": nb / t_bwd, "rk4_backward_steps": nb, "rk4_backward_ckpt_every": ck,
+        "rk4_backward_over_forward": t_bwd / t_fwd_ck,
     }
     out["transport"] = transport_bench(px, dm, tab, kk, bb, ee, n, f1, cfg)
     tab.close()

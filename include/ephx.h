@@ -277,7 +277,10 @@ int ephx_dynamics_field(ephx_table* t, const double* f0, double dt, int n_steps,
 
 /* Vector-Jacobian product of the collision integral: given f and lambda
  * (device [S]), f_bar = lambda^T dI/df (device [S]) and, if s_bar is not
- * NULL, s_bar[nu] = lambda^T dI/ds_nu (device [3nat]). */
+ * NULL, s_bar[nu] = lambda^T dI/ds_nu (device [3nat]).  The first s_bar after
+ * each ephx_collision_setup builds the collision matrix of every mode alone
+ * (3nat more matrices the size of the collision matrix, kept by the table);
+ * s_bar then costs one banded pass over each of them. */
 int ephx_collision_vjp(ephx_table* t, const double* f, const double* lam, double* f_bar,
                        double* s_bar, void* stream);
 

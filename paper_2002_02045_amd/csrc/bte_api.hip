@@ -26,6 +26,9 @@ struct ephx_table {
     void* d_g2 = nullptr;         // [nm][S][ld]
     void* d_p = nullptr;          // [S][ld] collision matrix
     void* d_w = nullptr;          // [S][ld] transport matrix
+    void* d_pmode = nullptr;      // [nm][S][ld] collision matrix of each mode alone at unit scale
+    double* d_eunit = nullptr;    // [nm][nm] unit scale vectors
+    int pmode_gen = -1;           // gen[0] the per-mode matrices were built for
     double* d_scale = nullptr;    // [nm] collision mode scales
     double* d_unit = nullptr;     // [nm] ones (transport matrix)
     double* d_ones = nullptr;     // [S]
@@ -212,6 +215,27 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
     reduce_finish(pl, cf, st);
 }
 
+// The per-mode matrices P^nu = dP/ds_nu, in the layout and band of P, built
+// when a mode-scale gradient is first asked for after each collision setup.
+void ensure_pmode(ephx_table* t, hipStream_t st) {
+    if (t->pmode_gen == t->gen[0]) return;
+    const size_t esz = t->f32 ? 4 : 8, mat = (size_t)t->S * t->ld * esz;
+    if (!t->d_pmode) {
+        t->d_pmode = t->alloc(t->nm * mat);
+        hip_check(hipMemsetAsync(t->d_pmode, 0, t->nm * mat, st), "hipMemsetAsync");
+        std::vector<double> eu((size_t)t->nm * t->nm, 0.0);
+        for (int nu = 0; nu < t->nm; ++nu) eu[(size_t)nu * t->nm + nu] = 1.0;
+        t->d_eunit = (double*)t->alloc(eu.size() * 8);
+        hip_check(hipMemcpyAsync(t->d_eunit, eu.data(), eu.size() * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    }
+    StageTimer tm("matrix_build", st);
+    for (int nu = 0; nu < t->nm; ++nu)
+        build_matrix(0, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
+                     t->d_eps, t->par.temp, t->par.mu, t->par.sigma, t->par.omega_cut, t->d_eunit + nu * t->nm,
+                     t->d_perm, (char*)t->d_pmode + nu * mat, st);
+    t->pmode_gen = t->gen[0];
+}
+
 // f_bar = lam^T dI/df at f; s_bar (=/+=) lam^T dI/ds
 void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, double* fbar, double* sbar,
                         int s_accumulate, hipStream_t st) {
@@ -228,9 +252,17 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     const PassOut po = one_pass(t, pl, t->d_p, x, y, rowp, colp, st, "collision_stream");
     vjp_finish(S, po.n_ct, po.n_rt, po.rowp, po.colp, lam, t->c, fbar, st);
     if (sbar) {
-        double* part = (double*)t->ws.get("v.part", (size_t)t->nm * S * 8);
-        mode_vjp(S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega, t->d_eps,
-                 t->par.temp, t->par.sigma, t->par.omega_cut, f, lam, part, t->c, sbar, s_accumulate, st);
+        // per mode: rows P^nu (1-f) and P^nu (lam (1-f)), one banded pass each
+        ensure_pmode(t, st);
+        const StreamPlan pm = plan_for(t, 0, 2, 0, st);
+        double* rowm = (double*)t->ws.get("v.rowm", (size_t)2 * pm.n_ct * S * 8);
+        const size_t mat = (size_t)S * t->ld * (t->f32 ? 4 : 8);
+        VecPtrs xm{{o0, o1, nullptr, nullptr}}, ym{{nullptr, nullptr, nullptr, nullptr}};
+        for (int nu = 0; nu < t->nm; ++nu) {
+            const PassOut pr = one_pass(t, pm, (const char*)t->d_pmode + nu * mat, xm, ym, rowm, nullptr, st,
+                                        "mode_stream");
+            mode_finish(S, pr.rowp, pr.rowp + S, f, lam, t->c, sbar + nu, s_accumulate, st);
+        }
     }
 }
 

@@ -384,53 +384,23 @@ __global__ void k_vjp_finish(int S, int n_ct, int n_rt, const double* __restrict
     fbar[u] = -c * (lam[u] * (r0 + c0) - c1 - r1);
 }
 
-// s_bar_nu partial: for row s, sum_t P^nu_st b_t (lam_s - lam_t) * a_s, P^nu from
-// the per-mode table and the collision weights; one block per (row s, mode).
-template <typename T>
-__global__ void k_mode_vjp(int S, int nm, long ld, const T* __restrict__ g2, const int32_t* __restrict__ kc, int n1,
-                           int n2, int n3, const double* __restrict__ omega, const double* __restrict__ eps,
-                           double temp, double sigma, double omega_cut, const double* __restrict__ f,
-                           const double* __restrict__ lam, double* __restrict__ part) {
+// s_bar_nu = (acc ? s_bar_nu : 0) - c sum_s f_s (lam_s R1_s - R2_s) with
+// R1 = P^nu (1 - f), R2 = P^nu (lam (1 - f)) (state order), P^nu the collision
+// matrix of mode nu alone at unit scale: the derivative of lam^T I[f] with
+// respect to the mode scale s_nu.  One block; fixed summation order.
+__global__ void k_mode_finish(int S, const double* __restrict__ r1, const double* __restrict__ r2,
+                              const double* __restrict__ f, const double* __restrict__ lam, double c,
+                              double* __restrict__ out, int accumulate) {
     __shared__ double red[256];
-    const int s = blockIdx.x, nu = blockIdx.y;
-    const double kt = kBoltzEv * temp;
-    const double is = 1.0 / sigma, nrm = 1.0 / (sqrt(kPi) * sigma);
-    const double fs = f[s], ls = lam[s];
     double acc = 0.0;
-    for (int t = threadIdx.x; t < S; t += 256) {
-        const long iq = grid_q(kc, s, t, n1, n2, n3);
-        const double om = omega[iq * nm + nu];
-        if (!(om > omega_cut)) continue;
-        const double nb = 1.0 / expm1(om / kt);
-        const double d = eps[s] - eps[t];
-        const double x1 = (d - om) * is, x2 = (d + om) * is;
-        const double de = x1 * x1 > kDeltaCut2 ? 0.0 : nrm * exp(-x1 * x1);
-        const double da = x2 * x2 > kDeltaCut2 ? 0.0 : nrm * exp(-x2 * x2);
-        const double p = (double)g2[((long)nu * S + s) * ld + t] * (de * (nb + 1.0) + da * nb);
-        acc += p * (1.0 - f[t]) * (ls - lam[t]);
-    }
+    for (int s = threadIdx.x; s < S; s += 256) acc += f[s] * (lam[s] * r1[s] - r2[s]);
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(long)nu * S + s] = fs * red[0];
-}
-
-__global__ void k_sum_rows(int S, int nm, const double* __restrict__ part, double c, double* __restrict__ out,
-                           int accumulate) {
-    __shared__ double red[256];
-    const int nu = blockIdx.x;
-    double acc = 0.0;
-    for (int s = threadIdx.x; s < S; s += 256) acc += part[(long)nu * S + s];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[nu] = (accumulate ? out[nu] : 0.0) - c * red[0];
+    if (threadIdx.x == 0) *out = (accumulate ? *out : 0.0) - c * red[0];
 }
 
 // ITA update: F[s][a] = F0[s][a] + tau_s/N_q * sum_ct rowp[a][ct][s]; also gamma from a ones pass
@@ -781,6 +751,7 @@ int slot_count(int f32, int na, int nb) {
     if (na == 1 && nb == 1) slots = stream_slots<T, 1, 1>();      \
     else if (na == 2 && nb == 2) slots = stream_slots<T, 2, 2>(); \
     else if (na == 1 && nb == 0) slots = stream_slots<T, 1, 0>(); \
+    else if (na == 2 && nb == 0) slots = stream_slots<T, 2, 0>(); \
     else if (na == 3 && nb == 0) slots = stream_slots<T, 3, 0>(); \
     else if (na == 0 && nb == 3) slots = stream_slots<T, 0, 3>(); \
     else throw Error{-1, "stream_plan: unsupported vector counts"};
@@ -953,6 +924,7 @@ void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, doub
             if (na == 1 && nb == 1) EPHX_STREAM(float, 1, 1);
             else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
             else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
+            else if (na == 2 && nb == 0) EPHX_STREAM(float, 2, 0);
             else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
             else if (na == 0 && nb == 3) EPHX_STREAM(float, 0, 3);
             else throw Error{-1, "stream_pass: unsupported vector counts"};
@@ -960,6 +932,7 @@ void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, doub
             if (na == 1 && nb == 1) EPHX_STREAM(double, 1, 1);
             else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
             else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
+            else if (na == 2 && nb == 0) EPHX_STREAM(double, 2, 0);
             else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
             else if (na == 0 && nb == 3) EPHX_STREAM(double, 0, 3);
             else throw Error{-1, "stream_pass: unsupported vector counts"};
@@ -998,18 +971,10 @@ void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* col
     check_launch("vjp_finish");
 }
 
-void mode_vjp(int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2, int n3,
-              const double* omega, const double* eps, double temp, double sigma, double omega_cut, const double* f,
-              const double* lam, double* part, double c, double* sbar, int accumulate, hipStream_t st) {
-    dim3 grid(S, nm);
-    if (f32)
-        hipLaunchKernelGGL(k_mode_vjp<float>, grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc, n1, n2, n3,
-                           omega, eps, temp, sigma, omega_cut, f, lam, part);
-    else
-        hipLaunchKernelGGL(k_mode_vjp<double>, grid, dim3(256), 0, st, S, nm, ld, (const double*)g2, kc, n1, n2, n3,
-                           omega, eps, temp, sigma, omega_cut, f, lam, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3(nm), dim3(256), 0, st, S, nm, part, c, sbar, accumulate);
-    check_launch("mode_vjp");
+void mode_finish(int S, const double* r1, const double* r2, const double* f, const double* lam, double c,
+                 double* out, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_mode_finish, dim3(1), dim3(256), 0, st, S, r1, r2, f, lam, c, out, accumulate);
+    check_launch("mode_finish");
 }
 
 void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0, double* f,

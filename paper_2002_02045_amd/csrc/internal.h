@@ -385,11 +385,10 @@ void gather_occupations(const StreamPlan& pl, const double* f, hipStream_t st);
 void reduce_finish(const StreamPlan& pl, const CollisionFinish& cf, hipStream_t st);
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
                 double* fbar, hipStream_t st);
-// s_bar[nu] (= or +=) -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t); part: [nm][S] scratch
-void mode_vjp(int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2, int n3,
-              const double* omega, const double* eps, double temp, double sigma, double omega_cut,
-              const double* f, const double* lam, double* part, double c, double* sbar, int accumulate,
-              hipStream_t st);
+// *out (= or +=) -c sum_s f_s (lam_s r1_s - r2_s), r1 = P^nu (1-f), r2 = P^nu (lam (1-f)):
+// the mode-scale derivative -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t)
+void mode_finish(int S, const double* r1, const double* r2, const double* f, const double* lam, double c,
+                 double* out, int accumulate, hipStream_t st);
 void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0,
                double* f, hipStream_t st);
 void ita_update(int S, int n_ct, const double* rowp, double n_q, const double* tau, const double* f0, double* f,
