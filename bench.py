@@ -370,7 +370,9 @@ def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
             1e3 * t_ita, ms_build, ms_st / n_st, alg / (ms_st / n_st * 1e-3) / 1e9, len(energies), 1e3 * t_tdf,
             1e3 * t_pop,
             float(mob[0, 0]), 1e6 * float(seebeck[0, 0])))
+    adj = mobility_adjoint_bench(px, dm, cfg)
     return {
+        "mobility_adjoint": adj,
         "ita_ms": round(1e3 * t_ita, 3), "ita_iterations": 10, "w_build_ms": round(ms_build, 3),
         "transport_stream_avg_ms": round(ms_st / n_st, 5),
         "transport_stream_gbs": round(alg / (ms_st / n_st * 1e-3) / 1e9, 1),
@@ -381,6 +383,40 @@ def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
         "population_integral": float(np.trapezoid(pop.cpu().numpy(), energies)),
         "carriers": float(f_t.sum()),
     }
+
+
+def mobility_adjoint_bench(px, dm, cfg, grid=24, count=1500):
+    """Adjoint of the ITA mobility w.r.t. g(Re,Rp) (FP64 table, 10 iterations)
+    on the lowest conduction states of a 24^3 grid: the reverse fixed-point
+    iterations with W^T, then every state pair's g(k,q) again and its
+    derivative back through the mode projection, the rotations and both
+    Fourier sums into g(Re,Rp)."""
+    import torch
+
+    n = (grid,) * 3
+    kk, bb, ee = px.grid_states(dm, n, mode="lowest", band_lo=dm.nw // 2, count=count)
+    S = len(kk)
+    tab = px.PairTable(dm, n, kk, bb, precision="fp64")
+    pts = np.stack([kk // (n[1] * n[2]), (kk // n[2]) % n[1], kk % n[2]], axis=-1) / np.asarray(n, dtype=np.float64)
+    _, _, v = px.bands(dm, pts, want_u=False, want_vel=True)
+    vel = v[torch.arange(len(bb), device=v.device), torch.as_tensor(bb, device=v.device)].contiguous()
+    par = px.Params(temp=cfg["T"], mu=float(ee.min()) - 0.2, sigma=cfg["sigma"], omega_cut=cfg["omega_cut"],
+                    n_q=float(np.prod(n)))
+    mob_bar = np.zeros((3, 3))
+    mob_bar[0, 0] = 1.0
+    tab.mobility_vjp(par, vel, 10, mob_bar)                        # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb = tab.mobility_vjp(par, vel, 10, mob_bar)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    if not bool(torch.isfinite(torch.view_as_real(gb)).all()):
+        raise RuntimeError("mobility adjoint produced non-finite gradients")
+    tab.close()
+    log("mobility adjoint w.r.t. g(Re,Rp): %d states on %d^3, %d pairs in %.3f s (%.3g pairs/s), g_bar %.2f GB" % (
+        S, grid, S * S, t_adj, S * S / t_adj, gb.numel() * 16 / 1e9))
+    return {"states": S, "grid": grid, "pairs": S * S, "s": round(t_adj, 4), "pairs_per_s": S * S / t_adj,
+            "iterations": 10, "precision": "fp64"}
 
 
 def cell_bench(px, args):
