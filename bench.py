@@ -38,6 +38,8 @@ def _parse():
     ap.add_argument("--dyn-states", type=int, default=20_000)
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="first run a 1 GiB device fill and a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-adjoints", action="store_true",
+                    help="skip the RK4 backward and the mobility adjoint legs (e.g. under hardware counters)")
     ap.add_argument("--cell-k", type=int, default=32, help="k points of the large-cell slice (0: skip)")
     ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
     return ap.parse_args()
@@ -285,25 +287,7 @@ def dynamics_bench(px, dm, model, args):
     if not bool(torch.isfinite(f2).all()):
         raise RuntimeError("field dynamics produced non-finite occupations")
     log("dynamics: %.1f Euler steps/s with E = %g V/A along x" % (args.dyn_steps / dt_e, efield[0]))
-    # backward through time: the forward with checkpoints every 50 steps, then
-    # the reverse RK4 that replays each segment from its checkpoint (Eq. BTE_E
-    # with E = 0), for the gradients w.r.t. f0 and the six mode scales
-    nb = max(50, args.dyn_steps // 50 * 50)
-    ck = 50
-    tab.dynamics_vjp(tab.dynamics(f0, cfg["dt"], ck, ckpt_every=ck)[1], cfg["dt"], ck, ck, f0)   # warmup
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fT, cks = tab.dynamics(f0, cfg["dt"], nb, ckpt_every=ck)
-    torch.cuda.synchronize()
-    t_fwd_ck = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    f0_bar, s_bar = tab.dynamics_vjp(cks, cfg["dt"], nb, ck, torch.ones_like(fT))
-    torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
-    if not (bool(torch.isfinite(f0_bar).all()) and bool(torch.isfinite(s_bar).all())):
-        raise RuntimeError("dynamics adjoint produced non-finite gradients")
-    log("dynamics: backward through %d RK4 steps %.3f s (%.1f steps/s, %.2fx the forward with checkpoints)" % (
-        nb, t_bwd, nb / t_bwd, t_bwd / t_fwd_ck))
+    bwd = {} if args.no_adjoints else rk4_backward(tab, f0, cfg, args)
     out = {
         "metric": "BTE collision steps/s (RK4 steps of the carrier dynamics)",
         "value": args.dyn_steps / dt, "unit": "RK4 steps/s", "steps": args.dyn_steps,
@@ -321,15 +305,40 @@ def dynamics_bench(px, dm, model, args):
         "table_build_s": round(t_table, 3), "setup_s": round(t_setup, 3),
         "carrier_number_drift": drift,
         "euler_field_steps_per_s": args.dyn_steps / dt_e, "euler_field_V_per_A": efield,
-        "rk4_backward_steps_per_s": nb / t_bwd, "rk4_backward_steps": nb, "rk4_backward_ckpt_every": ck,
-        "rk4_backward_over_forward": t_bwd / t_fwd_ck,
+        **bwd,
     }
-    out["transport"] = transport_bench(px, dm, tab, kk, bb, ee, n, f1, cfg)
+    out["transport"] = transport_bench(px, dm, tab, kk, bb, ee, n, f1, cfg, args)
     tab.close()
     return out
 
 
-def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
+def rk4_backward(tab, f0, cfg, args):
+    """Backward through time: the forward with checkpoints every 50 steps, then
+    the reverse RK4 that replays each segment from its checkpoint (Eq. BTE_E
+    with E = 0), for the gradients w.r.t. f0 and the six mode scales."""
+    import torch
+
+    nb = max(50, args.dyn_steps // 50 * 50)
+    ck = 50
+    tab.dynamics_vjp(tab.dynamics(f0, cfg["dt"], ck, ckpt_every=ck)[1], cfg["dt"], ck, ck, f0)   # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fT, cks = tab.dynamics(f0, cfg["dt"], nb, ckpt_every=ck)
+    torch.cuda.synchronize()
+    t_fwd_ck = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    f0_bar, s_bar = tab.dynamics_vjp(cks, cfg["dt"], nb, ck, torch.ones_like(fT))
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    if not (bool(torch.isfinite(f0_bar).all()) and bool(torch.isfinite(s_bar).all())):
+        raise RuntimeError("dynamics adjoint produced non-finite gradients")
+    log("dynamics: backward through %d RK4 steps %.3f s (%.1f steps/s, %.2fx the forward with checkpoints)" % (
+        nb, t_bwd, nb / t_bwd, t_bwd / t_fwd_ck))
+    return {"rk4_backward_steps_per_s": nb / t_bwd, "rk4_backward_steps": nb, "rk4_backward_ckpt_every": ck,
+            "rk4_backward_over_forward": t_bwd / t_fwd_ck}
+
+
+def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg, args):
     """On the dynamics states: ITA mobility (Eqs. BTE_iter, cond, 10 iterations,
     FP32 transport matrix), the TDF by tetrahedra on 512 energies with sigma and
     Seebeck (Eqs. cond_tdf2, cond_tdf, seebeck), and the population p(E,t) of the
@@ -370,7 +379,7 @@ def transport_bench(px, dm, tab, kk, bb, ee, n, f_t, cfg):
             1e3 * t_ita, ms_build, ms_st / n_st, alg / (ms_st / n_st * 1e-3) / 1e9, len(energies), 1e3 * t_tdf,
             1e3 * t_pop,
             float(mob[0, 0]), 1e6 * float(seebeck[0, 0])))
-    adj = mobility_adjoint_bench(px, dm, cfg)
+    adj = None if args.no_adjoints else mobility_adjoint_bench(px, dm, cfg)
     return {
         "mobility_adjoint": adj,
         "ita_ms": round(1e3 * t_ita, 3), "ita_iterations": 10, "w_build_ms": round(ms_build, 3),
