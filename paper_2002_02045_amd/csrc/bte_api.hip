@@ -253,16 +253,30 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     vjp_finish(S, po.n_ct, po.n_rt, po.rowp, po.colp, lam, t->c, fbar, st);
     if (sbar) {
         // per mode: rows P^nu (1-f) and P^nu (lam (1-f)), one banded pass each
+        // (the vectors are gathered once; the partials of all modes are reduced
+        // together, as 2 nm row vectors, and finished in one launch)
         ensure_pmode(t, st);
         const StreamPlan pm = plan_for(t, 0, 2, 0, st);
-        double* rowm = (double*)t->ws.get("v.rowm", (size_t)2 * pm.n_ct * S * 8);
+        const size_t part = (size_t)2 * pm.n_ct * S;
+        double* rowm = (double*)t->ws.get("v.rowm", t->nm * part * 8);
         const size_t mat = (size_t)S * t->ld * (t->f32 ? 4 : 8);
         VecPtrs xm{{o0, o1, nullptr, nullptr}}, ym{{nullptr, nullptr, nullptr, nullptr}};
-        for (int nu = 0; nu < t->nm; ++nu) {
-            const PassOut pr = one_pass(t, pm, (const char*)t->d_pmode + nu * mat, xm, ym, rowm, nullptr, st,
-                                        "mode_stream");
-            mode_finish(S, pr.rowp, pr.rowp + S, f, lam, t->c, sbar + nu, s_accumulate, st);
+        {
+            StageTimer tm("stream_permute", st);
+            stream_gather(pm, xm, ym, st);
         }
+        {
+            StageTimer tm("mode_stream", st);
+            for (int nu = 0; nu < t->nm; ++nu)
+                stream_run(pm, t->ld, (const char*)t->d_pmode + nu * mat, rowm + nu * part, nullptr, st);
+        }
+        StreamPlan pr = pm;
+        pr.na = 2 * t->nm;
+        pr.nb = 0;
+        pr.rout = (double*)t->ws.get("v.routm", (size_t)2 * t->nm * S * 8);
+        StageTimer tm("stream_permute", st);
+        const PassOut po2 = stream_reduce(pr, rowm, nullptr, st);
+        mode_finish(S, t->nm, po2.rowp, f, lam, t->c, sbar, s_accumulate, st);
     }
 }
 

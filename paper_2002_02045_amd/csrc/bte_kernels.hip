@@ -385,13 +385,17 @@ __global__ void k_vjp_finish(int S, int n_ct, int n_rt, const double* __restrict
 }
 
 // s_bar_nu = (acc ? s_bar_nu : 0) - c sum_s f_s (lam_s R1_s - R2_s) with
-// R1 = P^nu (1 - f), R2 = P^nu (lam (1 - f)) (state order), P^nu the collision
-// matrix of mode nu alone at unit scale: the derivative of lam^T I[f] with
-// respect to the mode scale s_nu.  One block; fixed summation order.
-__global__ void k_mode_finish(int S, const double* __restrict__ r1, const double* __restrict__ r2,
-                              const double* __restrict__ f, const double* __restrict__ lam, double c,
-                              double* __restrict__ out, int accumulate) {
+// R1 = P^nu (1 - f), R2 = P^nu (lam (1 - f)) (state order; r[2 nu], r[2 nu + 1]),
+// P^nu the collision matrix of mode nu alone at unit scale: the derivative of
+// lam^T I[f] with respect to the mode scale s_nu.  One block per mode; fixed
+// summation order.
+__global__ void k_mode_finish(int S, const double* __restrict__ r, const double* __restrict__ f,
+                              const double* __restrict__ lam, double c, double* __restrict__ sbar, int accumulate) {
     __shared__ double red[256];
+    const int nu = blockIdx.x;
+    const double* r1 = r + (long)2 * nu * S;
+    const double* r2 = r1 + S;
+    double* out = sbar + nu;
     double acc = 0.0;
     for (int s = threadIdx.x; s < S; s += 256) acc += f[s] * (lam[s] * r1[s] - r2[s]);
     red[threadIdx.x] = acc;
@@ -971,9 +975,9 @@ void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* col
     check_launch("vjp_finish");
 }
 
-void mode_finish(int S, const double* r1, const double* r2, const double* f, const double* lam, double c,
-                 double* out, int accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_mode_finish, dim3(1), dim3(256), 0, st, S, r1, r2, f, lam, c, out, accumulate);
+void mode_finish(int S, int nm, const double* r, const double* f, const double* lam, double c, double* sbar,
+                 int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_mode_finish, dim3(nm), dim3(256), 0, st, S, r, f, lam, c, sbar, accumulate);
     check_launch("mode_finish");
 }
 
