@@ -236,6 +236,47 @@ void ensure_pmode(ephx_table* t, hipStream_t st) {
     t->pmode_gen = t->gen[0];
 }
 
+// s_bar (=/+=) sum_j lam_j^T dI/ds at f_j for ns pairs (f_j, lam_j): per mode,
+// banded passes over P^nu with the rows (1-f_j) and lam_j (1-f_j), two pairs
+// (four row vectors) per pass; the vectors of a pass are gathered once, and
+// the partials of all modes are reduced together and finished in one launch.
+void mode_grad(ephx_table* t, int ns, const double* const* f, const double* const* lam, double* sbar,
+               int accumulate, hipStream_t st) {
+    const int S = t->S;
+    ensure_pmode(t, st);
+    const size_t mat = (size_t)S * t->ld * (t->f32 ? 4 : 8);
+    double* o[4];
+    for (int q = 0; q < 4; ++q) o[q] = (double*)t->ws.get("v.om" + std::to_string(q), (size_t)S * 8);
+    double* o2 = (double*)t->ws.get("v.omx", (size_t)S * 8);   // lam f, not used here
+    for (int j0 = 0; j0 < ns; j0 += 2) {
+        const int m = std::min(2, ns - j0);
+        for (int jj = 0; jj < m; ++jj) occ_vectors(S, f[j0 + jj], lam[j0 + jj], o[2 * jj], o[2 * jj + 1], o2, st);
+        const StreamPlan pm = plan_for(t, 0, 2 * m, 0, st);
+        const size_t part = (size_t)2 * m * pm.n_ct * S;
+        double* rowm = (double*)t->ws.get("v.rowm", (size_t)t->nm * 4 * pm.n_ct * S * 8);
+        VecPtrs xm{{o[0], o[1], m > 1 ? o[2] : nullptr, m > 1 ? o[3] : nullptr}};
+        VecPtrs ym{{nullptr, nullptr, nullptr, nullptr}};
+        {
+            StageTimer tm("stream_permute", st);
+            stream_gather(pm, xm, ym, st);
+        }
+        {
+            StageTimer tm("mode_stream", st);
+            for (int nu = 0; nu < t->nm; ++nu)
+                stream_run(pm, t->ld, (const char*)t->d_pmode + nu * mat, rowm + nu * part, nullptr, st);
+        }
+        StreamPlan pr = pm;
+        pr.na = 2 * m * t->nm;
+        pr.nb = 0;
+        pr.rout = (double*)t->ws.get("v.routm", (size_t)4 * t->nm * S * 8);
+        StageTimer tm("stream_permute", st);
+        const PassOut po = stream_reduce(pr, rowm, nullptr, st);
+        VecPtrs fv{{f[j0], m > 1 ? f[j0 + 1] : nullptr, nullptr, nullptr}};
+        VecPtrs lv{{lam[j0], m > 1 ? lam[j0 + 1] : nullptr, nullptr, nullptr}};
+        mode_finish(S, t->nm, m, po.rowp, fv, lv, t->c, sbar, accumulate || j0 > 0, st);
+    }
+}
+
 // f_bar = lam^T dI/df at f; s_bar (=/+=) lam^T dI/ds
 void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, double* fbar, double* sbar,
                         int s_accumulate, hipStream_t st) {
@@ -252,31 +293,7 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     const PassOut po = one_pass(t, pl, t->d_p, x, y, rowp, colp, st, "collision_stream");
     vjp_finish(S, po.n_ct, po.n_rt, po.rowp, po.colp, lam, t->c, fbar, st);
     if (sbar) {
-        // per mode: rows P^nu (1-f) and P^nu (lam (1-f)), one banded pass each
-        // (the vectors are gathered once; the partials of all modes are reduced
-        // together, as 2 nm row vectors, and finished in one launch)
-        ensure_pmode(t, st);
-        const StreamPlan pm = plan_for(t, 0, 2, 0, st);
-        const size_t part = (size_t)2 * pm.n_ct * S;
-        double* rowm = (double*)t->ws.get("v.rowm", t->nm * part * 8);
-        const size_t mat = (size_t)S * t->ld * (t->f32 ? 4 : 8);
-        VecPtrs xm{{o0, o1, nullptr, nullptr}}, ym{{nullptr, nullptr, nullptr, nullptr}};
-        {
-            StageTimer tm("stream_permute", st);
-            stream_gather(pm, xm, ym, st);
-        }
-        {
-            StageTimer tm("mode_stream", st);
-            for (int nu = 0; nu < t->nm; ++nu)
-                stream_run(pm, t->ld, (const char*)t->d_pmode + nu * mat, rowm + nu * part, nullptr, st);
-        }
-        StreamPlan pr = pm;
-        pr.na = 2 * t->nm;
-        pr.nb = 0;
-        pr.rout = (double*)t->ws.get("v.routm", (size_t)2 * t->nm * S * 8);
-        StageTimer tm("stream_permute", st);
-        const PassOut po2 = stream_reduce(pr, rowm, nullptr, st);
-        mode_finish(S, t->nm, po2.rowp, f, lam, t->c, sbar, s_accumulate, st);
+        mode_grad(t, 1, &f, &lam, sbar, s_accumulate, st);
     }
 }
 
@@ -700,7 +717,8 @@ extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, 
         const int S = t->S;
         const int L = ckpt_every;
         double* a = (double*)t->ws.get("b.a", S * 8);
-        double* kb = (double*)t->ws.get("b.kb", S * 8);
+        double* kbs[4];   // the stage adjoints k_i_bar of one step, kept for the mode-scale gradient
+        for (int i = 0; i < 4; ++i) kbs[i] = (double*)t->ws.get("b.kb" + std::to_string(i), S * 8);
         double* yb[4];
         for (int i = 0; i < 4; ++i) yb[i] = (double*)t->ws.get("b.yb" + std::to_string(i), S * 8);
         double* ys = (double*)t->ws.get("b.ys", (size_t)L * 4 * S * 8);   // stage inputs of the segment
@@ -721,17 +739,23 @@ extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, 
                 const double* Y[4];
                 for (int i = 0; i < 4; ++i) Y[i] = ys + ((size_t)j * 4 + i) * S;
                 // k4b = dt/6 a ; Y4b = J4^T k4b
-                lincomb(S, Lincomb{1, 0.0, {dt / 6.0}, {a}}, kb, st);
-                collision_vjp_impl(t, Y[3], kb, yb[3], s_bar, 1, st);
+                lincomb(S, Lincomb{1, 0.0, {dt / 6.0}, {a}}, kbs[3], st);
+                collision_vjp_impl(t, Y[3], kbs[3], yb[3], nullptr, 1, st);
                 // k3b = dt/3 a + dt Y4b
-                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt}, {a, yb[3]}}, kb, st);
-                collision_vjp_impl(t, Y[2], kb, yb[2], s_bar, 1, st);
+                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt}, {a, yb[3]}}, kbs[2], st);
+                collision_vjp_impl(t, Y[2], kbs[2], yb[2], nullptr, 1, st);
                 // k2b = dt/3 a + dt/2 Y3b
-                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt / 2.0}, {a, yb[2]}}, kb, st);
-                collision_vjp_impl(t, Y[1], kb, yb[1], s_bar, 1, st);
+                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt / 2.0}, {a, yb[2]}}, kbs[1], st);
+                collision_vjp_impl(t, Y[1], kbs[1], yb[1], nullptr, 1, st);
                 // k1b = dt/6 a + dt/2 Y2b
-                lincomb(S, Lincomb{2, 0.0, {dt / 6.0, dt / 2.0}, {a, yb[1]}}, kb, st);
-                collision_vjp_impl(t, Y[0], kb, yb[0], s_bar, 1, st);
+                lincomb(S, Lincomb{2, 0.0, {dt / 6.0, dt / 2.0}, {a, yb[1]}}, kbs[0], st);
+                collision_vjp_impl(t, Y[0], kbs[0], yb[0], nullptr, 1, st);
+                // s_bar += sum_i k_i_bar^T dI/ds at Y_i, the four stages two to a pass
+                if (s_bar) {
+                    const double* fs[4] = {Y[0], Y[1], Y[2], Y[3]};
+                    const double* ls[4] = {kbs[0], kbs[1], kbs[2], kbs[3]};
+                    mode_grad(t, 4, fs, ls, s_bar, 1, st);
+                }
                 // a <- a + Y1b + Y2b + Y3b + Y4b
                 lincomb(S, Lincomb{5, 0.0, {1.0, 1.0, 1.0, 1.0, 1.0}, {a, yb[0], yb[1], yb[2], yb[3]}}, a, st);
             }

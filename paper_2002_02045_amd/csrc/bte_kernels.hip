@@ -384,20 +384,24 @@ __global__ void k_vjp_finish(int S, int n_ct, int n_rt, const double* __restrict
     fbar[u] = -c * (lam[u] * (r0 + c0) - c1 - r1);
 }
 
-// s_bar_nu = (acc ? s_bar_nu : 0) - c sum_s f_s (lam_s R1_s - R2_s) with
-// R1 = P^nu (1 - f), R2 = P^nu (lam (1 - f)) (state order; r[2 nu], r[2 nu + 1]),
-// P^nu the collision matrix of mode nu alone at unit scale: the derivative of
-// lam^T I[f] with respect to the mode scale s_nu.  One block per mode; fixed
-// summation order.
-__global__ void k_mode_finish(int S, const double* __restrict__ r, const double* __restrict__ f,
-                              const double* __restrict__ lam, double c, double* __restrict__ sbar, int accumulate) {
+// s_bar_nu = (acc ? s_bar_nu : 0) - c sum_j sum_s f_js (lam_js R1_js - R2_js)
+// over ns pairs (f_j, lam_j), with R1_j = P^nu (1 - f_j), R2_j = P^nu (lam_j (1 - f_j))
+// (state order; r[2 (nu ns + j)] and the next row), P^nu the collision matrix
+// of mode nu alone at unit scale: the derivative of sum_j lam_j^T I[f_j] with
+// respect to the mode scale s_nu.  One block per mode; fixed summation order.
+__global__ void k_mode_finish(int S, int ns, const double* __restrict__ r, VecPtrs f, VecPtrs lam, double c,
+                              double* __restrict__ sbar, int accumulate) {
     __shared__ double red[256];
     const int nu = blockIdx.x;
-    const double* r1 = r + (long)2 * nu * S;
-    const double* r2 = r1 + S;
     double* out = sbar + nu;
     double acc = 0.0;
-    for (int s = threadIdx.x; s < S; s += 256) acc += f[s] * (lam[s] * r1[s] - r2[s]);
+    for (int j = 0; j < ns; ++j) {
+        const double* r1 = r + (long)2 * (nu * ns + j) * S;
+        const double* r2 = r1 + S;
+        const double* fj = f.p[j];
+        const double* lj = lam.p[j];
+        for (int s = threadIdx.x; s < S; s += 256) acc += fj[s] * (lj[s] * r1[s] - r2[s]);
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -756,6 +760,7 @@ int slot_count(int f32, int na, int nb) {
     else if (na == 2 && nb == 2) slots = stream_slots<T, 2, 2>(); \
     else if (na == 1 && nb == 0) slots = stream_slots<T, 1, 0>(); \
     else if (na == 2 && nb == 0) slots = stream_slots<T, 2, 0>(); \
+    else if (na == 4 && nb == 0) slots = stream_slots<T, 4, 0>(); \
     else if (na == 3 && nb == 0) slots = stream_slots<T, 3, 0>(); \
     else if (na == 0 && nb == 3) slots = stream_slots<T, 0, 3>(); \
     else throw Error{-1, "stream_plan: unsupported vector counts"};
@@ -929,6 +934,7 @@ void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, doub
             else if (na == 2 && nb == 2) EPHX_STREAM(float, 2, 2);
             else if (na == 1 && nb == 0) EPHX_STREAM(float, 1, 0);
             else if (na == 2 && nb == 0) EPHX_STREAM(float, 2, 0);
+            else if (na == 4 && nb == 0) EPHX_STREAM(float, 4, 0);
             else if (na == 3 && nb == 0) EPHX_STREAM(float, 3, 0);
             else if (na == 0 && nb == 3) EPHX_STREAM(float, 0, 3);
             else throw Error{-1, "stream_pass: unsupported vector counts"};
@@ -937,6 +943,7 @@ void stream_run(const StreamPlan& pl, long ld, const void* P, double* rowp, doub
             else if (na == 2 && nb == 2) EPHX_STREAM(double, 2, 2);
             else if (na == 1 && nb == 0) EPHX_STREAM(double, 1, 0);
             else if (na == 2 && nb == 0) EPHX_STREAM(double, 2, 0);
+            else if (na == 4 && nb == 0) EPHX_STREAM(double, 4, 0);
             else if (na == 3 && nb == 0) EPHX_STREAM(double, 3, 0);
             else if (na == 0 && nb == 3) EPHX_STREAM(double, 0, 3);
             else throw Error{-1, "stream_pass: unsupported vector counts"};
@@ -975,9 +982,10 @@ void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* col
     check_launch("vjp_finish");
 }
 
-void mode_finish(int S, int nm, const double* r, const double* f, const double* lam, double c, double* sbar,
+void mode_finish(int S, int nm, int ns, const double* r, VecPtrs f, VecPtrs lam, double c, double* sbar,
                  int accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_mode_finish, dim3(nm), dim3(256), 0, st, S, r, f, lam, c, sbar, accumulate);
+    if (ns < 1 || ns > 4) throw Error{-1, "mode_finish: 1 to 4 pairs"};
+    hipLaunchKernelGGL(k_mode_finish, dim3(nm), dim3(256), 0, st, S, ns, r, f, lam, c, sbar, accumulate);
     check_launch("mode_finish");
 }
 

@@ -385,10 +385,10 @@ void gather_occupations(const StreamPlan& pl, const double* f, hipStream_t st);
 void reduce_finish(const StreamPlan& pl, const CollisionFinish& cf, hipStream_t st);
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
                 double* fbar, hipStream_t st);
-// sbar[nu] (= or +=) -c sum_s f_s (lam_s r1_s - r2_s) with r1 = r[2 nu] = P^nu (1-f),
-// r2 = r[2 nu + 1] = P^nu (lam (1-f)) ([2 nm][S]): the mode-scale derivative
-// -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t)
-void mode_finish(int S, int nm, const double* r, const double* f, const double* lam, double c, double* sbar,
+// sbar[nu] (= or +=) -c sum_j sum_s f_js (lam_js r1_s - r2_s) over ns pairs (f_j, lam_j),
+// r1 = r[2 (nu ns + j)] = P^nu (1-f_j), r2 = the next row = P^nu (lam_j (1-f_j))
+// ([2 nm ns][S]): the mode-scale derivative -c sum_st P^nu_st f_s (1-f_t) (lam_s - lam_t)
+void mode_finish(int S, int nm, int ns, const double* r, VecPtrs f, VecPtrs lam, double c, double* sbar,
                  int accumulate, hipStream_t st);
 void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0,
                double* f, hipStream_t st);
