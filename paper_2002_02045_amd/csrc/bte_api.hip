@@ -115,7 +115,7 @@ void ensure_order(ephx_table* t, hipStream_t st) {
     for (int i = 0; i < S; ++i) t->h_esort[i] = e[perm[i]];
     double wmax = 0.0;
     for (double w : om)
-        if (std::isfinite(w)) wmax = std::max(wmax, w);
+        if (std::isfinite(w)) wmax = std::max(wmax, std::fabs(w));   // |omega|: a mode below a negative cut counts too
     t->omega_max = wmax;
     t->d_perm = (int32_t*)t->alloc((size_t)std::max(1, S) * 4);
     hip_check(hipMemcpy(t->d_perm, perm.data(), (size_t)S * 4, hipMemcpyHostToDevice), "hipMemcpy");
@@ -125,11 +125,12 @@ void ensure_order(ephx_table* t, hipStream_t st) {
 void build_banded(ephx_table* t, int matrix, const ephx_params* p, const double* scale, void* out, hipStream_t st) {
     ensure_order(t, st);
     StageTimer tm("matrix_build", st);
-    build_matrix(matrix, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
-                 t->d_eps, p->temp, p->mu, p->sigma, p->omega_cut, scale, t->d_perm, out, st);
     // |e_s - e_t| > omega + 6 sigma (with a margin for rounding) puts both
     // delta arguments beyond the cut for every mode
-    t->band[matrix] = t->omega_max + 6.0 * p->sigma * (1.0 + 1e-9) + 1e-12;
+    const double hw = t->omega_max + 6.0 * p->sigma * (1.0 + 1e-9) + 1e-12;
+    build_matrix(matrix, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
+                 t->d_eps, p->temp, p->mu, p->sigma, p->omega_cut, scale, t->d_perm, out, hw, st);
+    t->band[matrix] = hw;
     ++t->gen[matrix];
 }
 
@@ -232,7 +233,7 @@ void ensure_pmode(ephx_table* t, hipStream_t st) {
     for (int nu = 0; nu < t->nm; ++nu)
         build_matrix(0, t->S, t->nm, t->ld, t->d_g2, t->f32 ? 1 : 0, t->d_kc, t->n1, t->n2, t->n3, t->d_omega,
                      t->d_eps, t->par.temp, t->par.mu, t->par.sigma, t->par.omega_cut, t->d_eunit + nu * t->nm,
-                     t->d_perm, (char*)t->d_pmode + nu * mat, st);
+                     t->d_perm, (char*)t->d_pmode + nu * mat, t->band[0], st);
     t->pmode_gen = t->gen[0];
 }
 

@@ -176,12 +176,15 @@ __global__ void k_symmetrise(int S, long ld, T* g) {
 // P[s][t] = sum_nu scale_nu G[nu][s][t] w_nu(s,t) with
 //   collision:  w = delta(D - hw)(N+1) + delta(D + hw) N
 //   transport:  w = (2 pi/hbar)[delta(D - hw)(1 + N - f0_t) + delta(D + hw)(N + f0_t)]
+// Pairs with |D| > dcut (> 0: at least the largest phonon energy + 6 sigma, so
+// both delta arguments of every mode lie beyond the cut) are written as the
+// exact zero the sum gives, without evaluating it.
 template <typename T, bool TRANSPORT>
 __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2, const int32_t* __restrict__ kc,
                                int n1, int n2, int n3, const double* __restrict__ omega,
                                const double* __restrict__ eps, double temp, double mu, double sigma,
                                double omega_cut, const double* __restrict__ scale,
-                               const int32_t* __restrict__ perm, T* __restrict__ out) {
+                               const int32_t* __restrict__ perm, T* __restrict__ out, double dcut) {
     // 1-D grid of 256-column chunks, rows padded to a multiple of 8.  Blocks are
     // dealt to the 8 XCDs in turn, so every chunk of row i lands on XCD i % 8
     // and the gathered reads of G[.][perm[i]][.] share that XCD's L2.
@@ -194,6 +197,10 @@ __global__ void k_build_matrix(int S, int nm, long ld, const T* __restrict__ g2,
     const int s = perm ? perm[i] : i, t = perm ? perm[j] : j;
     const long iq = grid_q(kc, s, t, n1, n2, n3);
     const double d = eps[s] - eps[t];
+    if (dcut > 0.0 && fabs(d) > dcut) {
+        out[(long)i * ld + j] = (T)0;
+        return;
+    }
     const double kt = kBoltzEv * temp;
     const double is = 1.0 / sigma, nrm = 1.0 / (sqrt(kPi) * sigma);
     double f0t = 0.0;
@@ -709,23 +716,24 @@ void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st)
 
 void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc, int n1, int n2,
                   int n3, const double* omega, const double* eps, double temp, double mu, double sigma,
-                  double omega_cut, const double* scale, const int32_t* perm, void* out, hipStream_t st) {
+                  double omega_cut, const double* scale, const int32_t* perm, void* out, double dcut,
+                  hipStream_t st) {
     if (S <= 0) return;
     dim3 grid((unsigned)((long)(S + 255) / 256 * ((S + 7) / 8 * 8)));
     if (f32) {
         if (transport)
             hipLaunchKernelGGL((k_build_matrix<float, true>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
-                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out);
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out, dcut);
         else
             hipLaunchKernelGGL((k_build_matrix<float, false>), grid, dim3(256), 0, st, S, nm, ld, (const float*)g2, kc,
-                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out);
+                               n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (float*)out, dcut);
     } else {
         if (transport)
             hipLaunchKernelGGL((k_build_matrix<double, true>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
-                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out);
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out, dcut);
         else
             hipLaunchKernelGGL((k_build_matrix<double, false>), grid, dim3(256), 0, st, S, nm, ld, (const double*)g2,
-                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out);
+                               kc, n1, n2, n3, omega, eps, temp, mu, sigma, omega_cut, scale, perm, (double*)out, dcut);
     }
     check_launch("build_matrix");
 }

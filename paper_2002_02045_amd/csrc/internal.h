@@ -301,11 +301,13 @@ void apply_u_column(int Z, int nrp, int nm, int nw, const double* g, const doubl
 void table_symmetrise(int nm, int S, long ld, void* g2, int f32, hipStream_t st);
 // transport = 0: collision matrix P (mode scales applied);
 // transport = 1: scattering probabilities W (Eq. BTE_W, 1/fs, scale ignored but required).
-// Row/column i of out is state perm[i] (perm nullptr: identity).
+// Row/column i of out is state perm[i] (perm nullptr: identity).  Entries whose
+// energy difference exceeds dcut > 0 (at least the largest phonon energy +
+// 6 sigma) are written as zero without evaluating the sum; dcut <= 0: none.
 void build_matrix(int transport, int S, int nm, long ld, const void* g2, int f32, const int32_t* kc,
                   int n1, int n2, int n3, const double* omega, const double* eps, double temp,
                   double mu, double sigma, double omega_cut, const double* scale, const int32_t* perm,
-                  void* out, hipStream_t st);
+                  void* out, double dcut, hipStream_t st);
 
 // Streaming pass over a dense S x S matrix P (row stride ld):
 //   rowp[a][ct][s] = sum_{t in col tile ct} P[s][t] x_a[t]      (a < na)
