@@ -9,8 +9,8 @@ import scipy.linalg
 import torch
 
 import synth
-from oracle import bte, grid, interp
-from oracle.units import HBAR_EV_FS, KB_EV
+from oracle import bte, eph, grid, interp
+from oracle.units import HBAR2_AMU_A2, HBAR_EV_FS, KB_EV
 
 
 # --------------------------------------------------------------- grids and pairs
@@ -243,3 +243,61 @@ def test_pair_entries_match_the_table():
     for i, (s, t) in enumerate(pairs):
         assert torch.allclose(e2[i], g2s[s, t], rtol=1e-12, atol=1e-300)
         assert torch.allclose(eo[i], om[s, t], rtol=1e-12, atol=1e-300)
+
+
+def test_transport_matrix_two_state_closed_form():
+    """Eq. BTE_W for two states eps_2 - eps_1 = hw0 and one mode, every delta
+    term kept (sigma is not small against hw0):
+      W_st = (2 pi/hbar) G [delta(eps_s - hw - eps_t)(1 + N - f0_t) + delta(eps_s + hw - eps_t)(N + f0_t)]
+    The occupation is the final state's; mu is placed so that f0_1 and f0_2
+    differ by a factor ~2."""
+    hw0, temp, sig, gg, mu = 0.03, 300.0, 0.02, 0.7, 0.12
+    eps = torch.tensor([0.1, 0.1 + hw0], dtype=torch.float64)
+    g2 = torch.full((2, 2, 1), gg, dtype=torch.float64)
+    om = torch.full((2, 2, 1), hw0, dtype=torch.float64)
+    w = bte.transport_matrix(eps, g2, om, temp=temp, mu=mu, sigma=sig)
+    kt = KB_EV * temp
+    nb = 1.0 / (math.exp(hw0 / kt) - 1.0)
+    f0 = [1.0 / (math.exp((float(e) - mu) / kt) + 1.0) for e in eps]
+    assert 1.5 < f0[0] / f0[1] < 2.5
+
+    def delta(x):
+        return math.exp(-(x / sig) ** 2) / (math.sqrt(math.pi) * sig)
+
+    c = 2 * math.pi / HBAR_EV_FS * gg
+    for s in range(2):
+        for t in range(2):
+            d = float(eps[s] - eps[t])
+            ref = c * (delta(d - hw0) * (1 + nb - f0[t]) + delta(d + hw0) * (nb + f0[t]))
+            assert abs(float(w[s, t]) - ref) <= 1e-12 * ref
+
+
+def test_transport_matrix_row_sums_are_the_rates():
+    """On a complete grid (every k, every band a state) the row sum of W over
+    the final states, divided by N_q, is the scattering rate of Eq. scatter_rate
+    with the grid as the q set: the flat-band Einstein model, whose rates are
+    pinned in closed form, with a coupling gamma^a_mn Hermitian in (m, n) so
+    that the symmetrised table has the same mode sums as |g(s->t)|^2."""
+    hw, mass, sig, temp, mu = 0.05, 20.0, 0.02, 300.0, 0.02
+    lev = [0.0, 0.05]
+    rng = np.random.default_rng(11)
+    gam = rng.standard_normal((3, 2, 2)) + 1j * rng.standard_normal((3, 2, 2))
+    gam = 0.5 * (gam + gam.conj().transpose(0, 2, 1))
+    z = np.zeros((1, 3), np.int32)
+    m = synth.Model(
+        lattice=synth.fcc_lattice(5.0), tau=np.zeros((1, 3)), mass=np.array([mass]), nw=2,
+        wf_centres=np.zeros((2, 3)), re=z, w_re=np.ones(1), h=np.diag(lev).astype(complex)[None],
+        rp_ph=z, w_rp_ph=np.ones(1), ifc=(hw ** 2 * mass / HBAR2_AMU_A2) * np.eye(3)[None],
+        re_g=z, w_re_g=np.ones(1), rp_g=z, w_rp_g=np.ones(1), g=gam[None, None])
+    n = (2, 2, 2)
+    nk = 8
+    kk = np.repeat(np.arange(nk), 2).astype(np.int32)
+    bb = np.tile(np.arange(2), nk).astype(np.int32)
+    g2s, om = bte.pair_table(m, n, kk, bb)
+    eps = bte.state_energies(m, kk, bb, n)
+    w = bte.transport_matrix(eps, g2s, om, temp=temp, mu=mu, sigma=sig)
+    pts = grid.grid_points(n)
+    gamma, _ = eph.rates(m, pts, pts, temp=temp, mu=mu, sigma=sig)
+    ref = gamma[torch.as_tensor(kk), torch.as_tensor(bb)]
+    assert float(ref.min()) > 0
+    assert torch.allclose(w.sum(dim=1) / nk, ref, rtol=1e-12)

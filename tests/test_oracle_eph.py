@@ -255,3 +255,96 @@ def test_rates_positive_and_quadratic_in_g(tiny_model):
     m2.g = 2.0 * m2.g
     g2v, _ = eph.rates(m2, k, q, **par)
     assert torch.allclose(g2v, 4.0 * g1, rtol=1e-12)
+
+
+# --------------------------------------------------------------- atom relabelling
+
+def _relabel_atom(model, kap, t):
+    """The same crystal with atom kap taken from the neighbouring cell:
+    tau'_kap = tau_kap + T, T = t . (a_1, a_2, a_3).  Atom (kap, cell R) of the
+    new labels is atom (kap, cell R + T) of the old ones, so the tensors that
+    index an atomic displacement by its cell are re-indexed (Sec. 2.2.2, 2.2.3):
+      C'_{k k'}(R) = C_{k k'}(R + T_k' - T_k),   g'^{k a}(Re, Rp) = g^{k a}(Re, Rp + T_k),
+    with T_k = T for k = kap and 0 otherwise.  The R lists grow by the shifted
+    vectors (the oracle takes any list); entries with no source stay zero."""
+    t = np.asarray(t, dtype=np.int64)
+    nat = model.nat
+    shift = [t if k == kap else np.zeros(3, np.int64) for k in range(nat)]
+    m = copy.deepcopy(model)
+    m.tau = model.tau.copy()
+    m.tau[kap] = model.tau[kap] + t @ model.lattice
+
+    def union(vecs, extra):
+        seen = {tuple(int(x) for x in v): None for v in vecs}
+        for e in extra:
+            for v in vecs:
+                seen.setdefault(tuple(int(x) for x in (v + e)), None)
+        return np.array(list(seen), dtype=np.int32)
+
+    old_ph = {tuple(int(x) for x in v): i for i, v in enumerate(model.rp_ph)}
+    rp_ph = union(model.rp_ph, [t, -t])
+    ifc = np.zeros((len(rp_ph),) + model.ifc.shape[1:])
+    for i, r in enumerate(rp_ph):
+        for k in range(nat):
+            for kk in range(nat):
+                src = old_ph.get(tuple(int(x) for x in (r + shift[kk] - shift[k])))
+                if src is not None:
+                    ifc[i, 3 * k:3 * k + 3, 3 * kk:3 * kk + 3] = model.ifc[src, 3 * k:3 * k + 3, 3 * kk:3 * kk + 3]
+    m.rp_ph, m.w_rp_ph, m.ifc = rp_ph, np.ones(len(rp_ph)), ifc
+    old_g = {tuple(int(x) for x in v): i for i, v in enumerate(model.rp_g)}
+    rp_g = union(model.rp_g, [-t])
+    g = np.zeros((model.g.shape[0], len(rp_g)) + model.g.shape[2:], dtype=complex)
+    for i, r in enumerate(rp_g):
+        for k in range(nat):
+            src = old_g.get(tuple(int(x) for x in (r + shift[k])))
+            if src is not None:
+                g[:, i, 3 * k:3 * k + 3] = model.g[:, src, 3 * k:3 * k + 3]
+    m.rp_g, m.w_rp_g, m.g = rp_g, np.ones(len(rp_g)), g
+    return m
+
+
+def _mode_group_sums(blk):
+    """|g|^2 summed over all bands and over degenerate mode groups (1e-4 eV)."""
+    g2 = (blk["g"].abs() ** 2).sum(dim=(-1, -2))                # (k, q, nu)
+    om = blk["omega"].numpy()
+    out = torch.zeros_like(g2)
+    for iq in range(om.shape[0]):
+        grp = interp.degenerate_groups(om[iq], 1e-4)
+        for gi in grp:
+            out[:, iq, gi[0]] = g2[:, iq, gi].sum(dim=-1)
+    return out
+
+
+@pytest.mark.parametrize("long_range_only", [False, True])
+def test_atom_relabelling_leaves_coupling_unchanged(long_range_only):
+    """Moving atom kappa by a lattice vector T (and re-indexing the force
+    constants and g(Re,Rp) to match) describes the same crystal: D(q) becomes
+    L D(q) L^dag with L = diag(e^{iq.T_kappa}), the eigenvectors pick up
+    e^{iq.T_kappa} on atom kappa, the short-range g^W picks up e^{-iq.T_kappa},
+    and so must the Froehlich term through its phase e^{-i tau_kappa.(q+G)}
+    (Eq. e_ph_long).  |g_mn,nu| is then unchanged; the opposite sign of that
+    phase would leave a factor e^{2iq.T} on atom kappa's long-range part.
+    Checked with the short- and long-range parts together and with the
+    long-range part alone (g(Re,Rp) = 0), and with the LO-TO part of D(q) on,
+    whose phase e^{i(q+G).(tau_k - tau_k')} must follow the same relabelling."""
+    m, pol = _polar_model()
+    if long_range_only:
+        m = copy.deepcopy(m)
+        m.g[:] = 0
+    k = synth.random_points(90, 2)
+    q = synth.random_points(91, 5)
+    for lo_to in (False, True):
+        polar = dict(pol, lo_to=lo_to)
+        ref = eph.eph_pipeline(m, k, q, polar)
+        for kap, t in ((1, (1, 0, 0)), (0, (0, -1, 2))):
+            mr = _relabel_atom(m, kap, t)
+            got = eph.eph_pipeline(mr, k, q, polar)
+            assert torch.allclose(got["omega"], ref["omega"], rtol=1e-10, atol=1e-12)
+            a, b = _mode_group_sums(got), _mode_group_sums(ref)
+            assert float(b.max()) > 0
+            assert float((a - b).abs().max()) <= 1e-10 * float(b.max())
+            # the relabelled model really differs: its long-range term alone
+            # changes by the phase e^{-iq.T} on atom kappa
+            c0 = eph.frohlich(m, q, **pol)
+            c1 = eph.frohlich(mr, q, **pol)
+            assert not torch.allclose(c0, c1, atol=1e-6 * float(c0.abs().max()))
