@@ -26,7 +26,10 @@
  *    compute call is asynchronous on it, except where a host output is
  *    documented (those calls synchronise the stream before returning).
  *  - Calls on one handle must not overlap in time (they share work buffers);
- *    calls on distinct handles are independent.
+ *    calls on distinct handles are independent.  A handle's work buffers grow
+ *    on demand: a call that needs more than the handle holds frees and
+ *    allocates device memory, which synchronises the device (size them ahead
+ *    with ephx_workspace_query and a first call).
  *  - Precision: EPHX_FP64 (all steps FP64), EPHX_FP32 (Rp contraction of g,
  *    band rotation and mode projection in FP32; phases reduced in FP64; the Re
  *    contraction, H(k+q), eigensolves, eps, omega and rate sums in FP64), or
@@ -127,12 +130,26 @@ typedef struct {
 const char* ephx_last_error(void);
 const char* ephx_version(void);
 
-/* Copy a model to the current device.  Checks sizes (nw <= 16, 3*natoms <= 12 in
- * this build), finiteness and the Hermiticity relations above (relative
- * tolerance 1e-12) -> EPHX_EINVAL / EPHX_ENAN / EPHX_ENOTHERM.  *out receives
- * a handle that the caller releases with ephx_model_destroy. */
+/* Copy a model to the current device.  Checks sizes (1 <= nw <= 64 and
+ * 1 <= natoms <= 42, i.e. at most 126 modes, in this build; above nw = 16 or
+ * 12 modes the per-pair work runs as batched GEMMs and the calls marked so
+ * below return EPHX_EUNSUPPORTED), finiteness and the Hermiticity relations
+ * above (relative tolerance 1e-12) -> EPHX_EINVAL / EPHX_ENAN / EPHX_ENOTHERM.
+ * *out receives a handle that the caller releases with ephx_model_destroy. */
 int ephx_model_create(const ephx_model_desc* d, ephx_model** out);
 int ephx_model_destroy(ephx_model* m);
+
+/* Replace the model's coupling tensor g(Re,Rp) of Eq. eph_mat_wann (the
+ * quantity the adjoints ephx_rates_vjp / ephx_mobility_vjp differentiate
+ * against) by new values on the device, keeping every other part of the model.
+ * g: device complex128 [n_re_g][n_rp_g][3nat][nw][nw], the layout and units of
+ * ephx_model_desc.g (weights not folded in: the model's weights are applied
+ * again), owned by the caller and only read.  The fp16 scale of the FP16x3
+ * contraction is recomputed from the new values.  Checks finiteness
+ * (EPHX_ENAN, the model then keeps its previous g).  Synchronises `stream`
+ * (the scale is read back); later calls on the model use the new g.  Pair
+ * tables created before keep the |g|^2 they were built from. */
+int ephx_model_set_g(ephx_model* m, const double* g, void* stream);
 
 /* Band interpolation, Eqs. wannier_3, velocity, wannier_4.
  * k_red device [nk][3]; eps device [nk][nw] (ascending);
@@ -215,8 +232,9 @@ int ephx_grid_states(ephx_model* m, const int n_grid[3], int mode, int band_lo, 
                      double e_lo, double e_hi, int count, int capacity, int* n_states,
                      int32_t* k_idx, int32_t* band, double* eps, void* stream);
 
-/* Pair table of S grid states (host arrays k_idx[S], band[S] as returned above):
- * for every ordered pair (s,t), q = k_t - k_s on the grid and
+/* Pair table of S grid states (host arrays k_idx[S], band[S] as returned above),
+ * the (k, q) pairs of Sec. 4.3 with commensurate k and q grids and both ends in
+ * the energy window: for every ordered pair (s,t), q = k_t - k_s on the grid and
  *   G[nu][s][t] = 1/2 (|g_{n_t n_s nu}(k_s, q)|^2 + |g_{n_s n_t nu}(k_t, -q)|^2)   (FP32)
  * together with omega_nu(q).  The symmetrisation gives |g(s->t)|^2 = |g(t->s)|^2,
  * which exact carrier conservation needs.  precision selects the arithmetic of
@@ -297,16 +315,32 @@ int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, int n_steps
  * states with equilibrium occupations f0 = Fermi-Dirac(p->mu, p->temp):
  *   Gamma_s = (1/N_q) sum_t W_st, tau = 1/Gamma, F^0 = tau v,
  *   F^{i+1} = F^0 + (tau/N_q) sum_t W_st F^i.
- * vel device [S][3] (Angstrom/fs); n_iter = 0 gives the RTA.  F_out device
- * [S][3] (Angstrom), tau_out device [S] (fs) or NULL.  The mobility of Eq. cond
- * divided by e n_c, mu_ab = e sum v^a F^b (-df0/de) / sum f0, goes to
- * mob_out (device double [3][3], cm^2/(V s)) unless NULL. */
-int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter,
-                  double* f_out, double* tau_out, double* mob_out, void* stream);
+ * Stopping rule (Eq. BTE_iter iterates until F changes by less than a
+ * threshold): with tol > 0 the iteration stops after the first update i + 1
+ * with max_{s,a} |F^{i+1} - F^i| < tol * max_{s,a} |F^{i+1}|, or after
+ * n_iter_max updates; with tol <= 0 exactly n_iter_max updates are made.
+ * n_iter_max = 0 gives the RTA.  With tol > 0 every iteration reads two
+ * doubles back, so the call then synchronises `stream` once per iteration.
+ * vel device [S][3] (Angstrom/fs).  F_out device [S][3] (Angstrom), tau_out
+ * device [S] (fs) or NULL.  The mobility of Eq. cond divided by e n_c,
+ * mu_ab = e sum v^a F^b (-df0/de) / sum f0, goes to mob_out (device double
+ * [3][3], cm^2/(V s)) unless NULL.  Host outputs (each may be NULL): *n_iter
+ * the number of updates made; *last_change the relative change of the last
+ * update (-1 when tol <= 0, where it is not measured).  A result with
+ * *n_iter == n_iter_max and *last_change >= tol did not converge.  When Gamma
+ * is the row sum of the same W, (tau/N_q) W has the constant vector as a unit
+ * eigenvector, so the iteration converges only for F^0 orthogonal to it (for
+ * example an inversion- or time-reversal-symmetric set of states, where F^0 is
+ * odd).  A non-finite iterate returns EPHX_ENAN. */
+int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter_max, double tol,
+                  double* f_out, double* tau_out, double* mob_out, int* n_iter, double* last_change,
+                  void* stream);
 
 /* Adjoint of ephx_mobility with respect to the coupling tensor (FP64): for
  * L = sum_ab mob_bar[a][b] mu_ab (mob_bar device double [3][3]) and the same
- * table, p, vel and n_iter as the forward call, writes g_bar = dL/dRe g(Re,Rp)
+ * table, p and vel as the forward call, with n_iter the number of updates the
+ * forward made (its *n_iter: the gradient is that of the iterate returned,
+ * not an implicit derivative of the fixed point), writes g_bar = dL/dRe g(Re,Rp)
  * + i dL/dIm g(Re,Rp) (device complex128, layout of the model's g, overwritten).
  * The chain is the reverse of Eqs. BTE_iter and cond (the iteration is rerun
  * and kept, then reversed with one pass of W^T per iteration), W_bar through

@@ -101,6 +101,28 @@ def collision(f, eps, g2s, omega, *, temp, sigma, n_q, omega_cut=1e-4, mode_scal
     return -(TWO_PI / HBAR_EV_FS) / n_q * term.sum(dim=(1, 2))
 
 
+def collision_rows(rows, f, eps, g2_rows, omega_rows, *, temp, sigma, n_q, omega_cut=1e-4, mode_scale=None):
+    """The entries `rows` of the collision integral of `collision` (Eq.
+    e_ph_scattering), from those rows of the table alone: g2_rows and
+    omega_rows are (len(rows), S, nmodes), the rows s of g2s and omega.  For
+    tables too large to hold whole; the terms are those of `collision`."""
+    f = t64(f)
+    eps = t64(eps)
+    rows = torch.as_tensor(np.asarray(rows), dtype=torch.long)
+    g2_rows, omega_rows = t64(g2_rows), t64(omega_rows)
+    nb = bose(omega_rows, temp, omega_cut)
+    fs = f[rows][:, None, None]
+    ft = f[None, :, None]
+    f_abs = fs * (1 - ft) * nb - ft * (1 - fs) * (nb + 1)
+    f_em = fs * (1 - ft) * (nb + 1) - ft * (1 - fs) * nb
+    d = eps[rows][:, None, None] - eps[None, :, None]
+    term = g2_rows * (gauss_delta(d - omega_rows, sigma) * f_em + gauss_delta(d + omega_rows, sigma) * f_abs)
+    term = torch.where(omega_rows > omega_cut, term, torch.zeros_like(term))
+    if mode_scale is not None:
+        term = term * t64(mode_scale)[None, None, :]
+    return -(TWO_PI / HBAR_EV_FS) / n_q * term.sum(dim=(1, 2))
+
+
 def rk4_step(f, dt, rhs):
     """Classic four-stage Runge-Kutta step (the paper's default integrator)."""
     k1 = rhs(f)
@@ -158,6 +180,56 @@ def ita(w, vel, n_q, n_iter, gamma=None):
     f = f0
     for _ in range(n_iter):
         f = f0 + (tau / n_q)[:, None] * (w @ f)
+    return f, tau
+
+
+def ita_converged(w, vel, n_q, n_iter_max, tol, gamma=None):
+    """The iteration of `ita` run until F stops changing (Eq. BTE_iter): after
+    each update F^{i+1}, stop if max_{s,a} |F^{i+1} - F^i| < tol max_{s,a} |F^{i+1}|,
+    and in any case after n_iter_max updates.  Returns (F, tau, number of updates,
+    relative change of the last update; -1 if none was made)."""
+    w = t64(w)
+    vel = t64(vel)
+    if gamma is None:
+        gamma = w.sum(dim=1) / n_q
+    tau = 1.0 / gamma
+    f0 = tau[:, None] * vel
+    f = f0
+    change = -1.0
+    n = 0
+    for i in range(n_iter_max):
+        fn = f0 + (tau / n_q)[:, None] * (w @ f)
+        amax = float(fn.abs().max())
+        change = float((fn - f).abs().max()) / amax if amax > 0 else 0.0
+        f = fn
+        n = i + 1
+        if change < tol:
+            break
+    return f, tau, n, change
+
+
+def ita_dense_odd(w, vel, n_q, partner, gamma=None):
+    """The fixed point of Eq. BTE_iter, F = tau v + (tau/N_q) W F, by a dense
+    solve on the odd vectors, F_partner[s] = -F_s, where partner[s] is the state
+    at -k_s with the same band (a permutation, partner[s] = s at k = -k).  When
+    W and tau are invariant under s -> partner[s] and v is odd, the iteration
+    stays among odd vectors and converges there, even though (1 - diag(tau/N_q)
+    W) itself is singular (its rows sum to zero, more than once if the states
+    fall into groups that do not scatter into each other).  Returns (F, tau)."""
+    w = t64(w)
+    vel = t64(vel)
+    partner = np.asarray(partner)
+    if gamma is None:
+        gamma = w.sum(dim=1) / n_q
+    tau = 1.0 / gamma
+    m = (tau / n_q)[:, None] * w
+    rep = np.array([s for s in range(len(partner)) if s < partner[s]], dtype=np.int64)
+    # F on the representatives x; F[partner[rep]] = -x; F = 0 where partner[s] = s
+    a = torch.eye(len(rep), dtype=F64) - (m[rep][:, rep] - m[rep][:, partner[rep]])
+    x = torch.linalg.solve(a, tau[rep, None] * vel[rep])
+    f = torch.zeros_like(vel)
+    f[rep] = x
+    f[partner[rep]] = -x
     return f, tau
 
 

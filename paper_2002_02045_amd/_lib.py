@@ -80,7 +80,8 @@ _SIGS = {
     "ephx_table_stream_info": ([_P, _I, _P, _P, _P, _P], _I),
     "ephx_collision_vjp": ([_P, _P, _P, _P, _P, _P], _I),
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),
-    "ephx_mobility": ([_P, _P, _P, _I, _P, _P, _P, _P], _I),
+    "ephx_mobility": ([_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P], _I),
+    "ephx_model_set_g": ([_P, _P, _P], _I),
     "ephx_mobility_vjp": ([_P, _P, _P, _I, _P, _P, _P], _I),
     "ephx_tdf": ([_P, _P, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "ephx_population": ([_P, _P, _I, _P, _P, _P], _I),

@@ -81,6 +81,16 @@ class Model:
         self.nmodes = 3 * self.nat
         self.g_shape = tuple(np.asarray(src.g).shape)
 
+    def set_g(self, g):
+        """Replace the model's g(Re,Rp) by a complex128 device tensor of shape
+        g_shape (ephx_model_set_g; synchronises the current stream)."""
+        if not (torch.is_tensor(g) and g.is_cuda and g.dtype == torch.complex128):
+            raise TypeError("g must be a complex128 tensor on the GPU")
+        if tuple(g.shape) != self.g_shape:
+            raise ValueError("g has shape %s, the model's is %s" % (tuple(g.shape), self.g_shape))
+        g = g.detach().contiguous()
+        check(lib.ephx_model_set_g(self._h, ptr(g), stream_ptr()))
+
     def close(self):
         if self._h:
             check(lib.ephx_model_destroy(self._h))
@@ -181,35 +191,49 @@ def rates_vjp(model, k, q, params, gamma_bar, q_weights=None):
 
 
 class RatesFunction(torch.autograd.Function):
-    """Gamma(g(Re,Rp)) with the hand-written adjoint (FP64).  The forward takes
-    the coupling tensor as a complex128 tensor only to connect the graph; the
-    library's model holds the values that are used."""
+    """Gamma(g(Re,Rp)) (nk, nw) in FP64 with the hand-written adjoint.  g is a
+    complex128 device tensor of the model's g_shape: the forward loads it into
+    the model (ephx_model_set_g) and computes the rates from it; the backward
+    loads it again (the model may have been given other values meanwhile) and
+    returns dL/dRe g + i dL/dIm g."""
 
     @staticmethod
-    def forward(ctx, g, model, k, q, params):
-        gam, _ = rates(model, k, q, params, precision="fp64", mode_resolved=False)
-        ctx.model, ctx.k, ctx.q, ctx.params = model, k, q, params
+    def forward(ctx, g, model, k, q, params, q_weights=None):
+        model.set_g(g)
+        gam, _ = rates(model, k, q, params, precision="fp64", q_weights=q_weights, mode_resolved=False)
+        ctx.save_for_backward(g)
+        ctx.model, ctx.k, ctx.q, ctx.params, ctx.q_weights = model, k, q, params, q_weights
         return gam
 
     @staticmethod
     def backward(ctx, gbar):
-        return rates_vjp(ctx.model, ctx.k, ctx.q, ctx.params, gbar), None, None, None, None
+        (g,) = ctx.saved_tensors
+        ctx.model.set_g(g)
+        gb = rates_vjp(ctx.model, ctx.k, ctx.q, ctx.params, gbar.contiguous(), q_weights=ctx.q_weights)
+        return gb, None, None, None, None, None
 
 
 class MobilityFunction(torch.autograd.Function):
-    """mu(g(Re,Rp)) (3x3, cm^2/(V s)) of a pair table with the hand-written
-    adjoint (FP64).  As for RatesFunction, g only connects the graph: the
-    table built from the library's model holds the values that are used."""
+    """mu(g(Re,Rp)) (3x3, cm^2/(V s)) in FP64 with the hand-written adjoint: the
+    forward loads g into the model, builds the FP64 pair table of the given grid
+    states from it and runs n_iter updates of the iterative BTE; the backward
+    loads g again and reverses that chain (ephx_mobility_vjp)."""
 
     @staticmethod
-    def forward(ctx, g, table, params, vel, n_iter):
+    def forward(ctx, g, model, n_grid, k_idx, band, params, vel, n_iter):
+        model.set_g(g)
+        table = PairTable(model, n_grid, k_idx, band, precision="fp64")
         _, _, mob = table.mobility(params, vel, n_iter)
-        ctx.table, ctx.params, ctx.vel, ctx.n_iter = table, params, vel, n_iter
+        ctx.save_for_backward(g)
+        ctx.model, ctx.table, ctx.params, ctx.vel, ctx.n_iter = model, table, params, vel, n_iter
         return mob
 
     @staticmethod
     def backward(ctx, mob_bar):
-        return ctx.table.mobility_vjp(ctx.params, ctx.vel, ctx.n_iter, mob_bar), None, None, None, None
+        (g,) = ctx.saved_tensors
+        ctx.model.set_g(g)
+        gb = ctx.table.mobility_vjp(ctx.params, ctx.vel, ctx.n_iter, mob_bar.contiguous())
+        return gb, None, None, None, None, None, None, None
 
 
 def grid_states(model, n_grid, *, mode="window", band_lo=0, band_hi=None, e_lo=0.0, e_hi=0.0, count=0,
@@ -323,14 +347,24 @@ class PairTable:
         return f0b, sb
 
     def mobility(self, params, vel, n_iter):
+        """(F (S,3), tau (S,), mu (3,3)) after exactly n_iter updates of the ITA."""
+        ff, tau, mob, _, _ = self.ita(params, vel, n_iter, tol=0.0)
+        return ff, tau, mob
+
+    def ita(self, params, vel, n_iter_max, tol):
+        """Iterate the linearised BTE until the largest change of F is below tol
+        times its largest component, at most n_iter_max updates (tol <= 0: exactly
+        n_iter_max).  Returns (F, tau, mu, n_iter made, last relative change)."""
         vel = torch.as_tensor(vel, dtype=F64, device="cuda").contiguous()
         ff = torch.empty((self.S, 3), dtype=F64, device="cuda")
         tau = torch.empty(self.S, dtype=F64, device="cuda")
         mob = torch.empty((3, 3), dtype=F64, device="cuda")
+        n = C.c_int(0)
+        chg = C.c_double(0.0)
         pc = params.c()
-        check(lib.ephx_mobility(self._h, C.byref(pc), ptr(vel), int(n_iter), ptr(ff), ptr(tau), ptr(mob),
-                                stream_ptr()))
-        return ff, tau, mob
+        check(lib.ephx_mobility(self._h, C.byref(pc), ptr(vel), int(n_iter_max), float(tol), ptr(ff), ptr(tau),
+                                ptr(mob), C.byref(n), C.byref(chg), stream_ptr()))
+        return ff, tau, mob, int(n.value), float(chg.value)
 
     def tdf(self, params, vel, f_ita, energies):
         """(TDF [n_E][3][3] in 1/(fs A eV), sigma [3][3] in S/m, Seebeck [3][3] in V/K)."""

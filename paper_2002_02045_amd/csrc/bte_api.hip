@@ -2,6 +2,7 @@
 // integral, RK4 dynamics and their adjoints, and the iterative linearised BTE.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <unordered_map>
@@ -765,12 +766,14 @@ extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, 
     });
 }
 
-extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter, double* f_out,
-                             double* tau_out, double* mob_out, void* stream) {
+extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* vel, int n_iter_max, double tol,
+                             double* f_out, double* tau_out, double* mob_out, int* n_iter, double* last_change,
+                             void* stream) {
     return guarded([&] {
         require(t != nullptr && p != nullptr, "mobility: null argument");
         require(vel != nullptr, "mobility: null velocities");
-        require(n_iter >= 0, "mobility: n_iter < 0");
+        require(n_iter_max >= 0, "mobility: n_iter_max < 0");
+        require(std::isfinite(tol), "mobility: tol is not finite");
         require(p->temp > 0 && p->sigma > 0 && p->n_q > 0 && std::isfinite(p->mu), "mobility: bad parameters");
         hipStream_t st = (hipStream_t)stream;
         const int S = t->S;
@@ -789,12 +792,33 @@ extern "C" int ephx_mobility(ephx_table* t, const ephx_params* p, const double* 
         VecPtrs one{{t->d_ones, nullptr, nullptr, nullptr}}, none{{nullptr, nullptr, nullptr, nullptr}};
         PassOut po = one_pass(t, pl1, t->d_w, one, none, rowp, nullptr, st, "transport_stream");
         ita_gamma(S, po.n_ct, po.rowp, p->n_q, vel, tau, f0, f, st);
-        for (int it = 0; it < n_iter; ++it) {
+        // with tol > 0: stop after the first iteration whose largest change of any
+        // component is below tol times the largest component (one 16-byte read
+        // back per iteration); with tol <= 0: exactly n_iter_max iterations
+        unsigned long long* chg = tol > 0 ? (unsigned long long*)t->ws.get("m.chg", 2 * 8) : nullptr;
+        int done = 0;
+        double change = -1.0;
+        for (int it = 0; it < n_iter_max; ++it) {
             VecPtrs x{{f, f + S, f + 2 * S, nullptr}};
             po = one_pass(t, pl3, t->d_w, x, none, rowp, nullptr, st, "transport_stream");
-            ita_update(S, po.n_ct, po.rowp, p->n_q, tau, f0, fn, st);
+            if (chg) hip_check(hipMemsetAsync(chg, 0, 2 * 8, st), "hipMemsetAsync");
+            ita_update(S, po.n_ct, po.rowp, p->n_q, tau, f0, fn, st, f, chg);
             std::swap(f, fn);
+            done = it + 1;
+            if (chg) {
+                unsigned long long h[2] = {0, 0};
+                hip_check(hipMemcpyAsync(h, chg, sizeof(h), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                double dmax, amax;
+                std::memcpy(&dmax, &h[0], 8);
+                std::memcpy(&amax, &h[1], 8);
+                if (!std::isfinite(dmax) || !std::isfinite(amax)) throw Error{EPHX_ENAN, "mobility: non-finite iterate"};
+                change = amax > 0 ? dmax / amax : 0.0;
+                if (change < tol) break;
+            }
         }
+        if (n_iter) *n_iter = done;
+        if (last_change) *last_change = change;
         mobility_reduce(S, t->d_eps, vel, f, p->mu, p->temp, f_out, mob_out, st);
         if (tau_out) hip_check(hipMemcpyAsync(tau_out, tau, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
     });

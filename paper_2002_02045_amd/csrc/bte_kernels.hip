@@ -433,14 +433,41 @@ __global__ void k_ita_gamma(int S, int n_ct, const double* __restrict__ rowp, do
     }
 }
 
+// With chg != nullptr, also max_{s,a} |F_new - F_prev| and max_{s,a} |F_new|
+// into chg[0], chg[1] (bit patterns of non-negative doubles, which atomicMax
+// orders like the values; cleared by the caller).
 __global__ void k_ita_update(int S, int n_ct, const double* __restrict__ rowp, double n_q, const double* __restrict__ tau,
-                             const double* __restrict__ f0, double* __restrict__ f) {
+                             const double* __restrict__ f0, double* __restrict__ f, const double* __restrict__ fprev,
+                             unsigned long long* __restrict__ chg) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    for (int a = 0; a < 3; ++a) {
-        double r = 0.0;
-        for (int ct = 0; ct < n_ct; ++ct) r += rowp[((long)a * n_ct + ct) * S + s];
-        f[(long)a * S + s] = f0[(long)a * S + s] + tau[s] / n_q * r;
+    double dmax = 0.0, amax = 0.0;
+    if (s < S) {
+        for (int a = 0; a < 3; ++a) {
+            double r = 0.0;
+            for (int ct = 0; ct < n_ct; ++ct) r += rowp[((long)a * n_ct + ct) * S + s];
+            const double v = f0[(long)a * S + s] + tau[s] / n_q * r;
+            f[(long)a * S + s] = v;
+            if (chg) {
+                dmax = fmax(dmax, fabs(v - fprev[(long)a * S + s]));
+                amax = fmax(amax, fabs(v));
+            }
+        }
+    }
+    if (!chg) return;
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = dmax;
+    red[1][threadIdx.x] = amax;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&chg[0], (unsigned long long)__double_as_longlong(red[0][0]));
+        atomicMax(&chg[1], (unsigned long long)__double_as_longlong(red[1][0]));
     }
 }
 
@@ -1004,8 +1031,9 @@ void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* ve
 }
 
 void ita_update(int S, int n_ct, const double* rowp, double n_q, const double* tau, const double* f0, double* f,
-                hipStream_t st) {
-    hipLaunchKernelGGL(k_ita_update, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, rowp, n_q, tau, f0, f);
+                hipStream_t st, const double* fprev, unsigned long long* chg) {
+    hipLaunchKernelGGL(k_ita_update, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, rowp, n_q, tau, f0, f, fprev,
+                       chg);
     check_launch("ita_update");
 }
 

@@ -195,6 +195,46 @@ __global__ void k_scale_rows(long rows, long cols, const double* __restrict__ w,
     data[2 * t + 1] *= s;
 }
 
+// Bound of the fp16 scale of a device copy of g(Re,Rp), times the weights
+// w[Re][Rp] if given: for each (Rp, mode component, row i) the sum over Re and
+// j of |w g_ij|, then
+// the largest of them, as the bit pattern of a non-negative double in out[0]
+// (atomicMax on the pattern orders non-negative doubles); out[1] != 0 if an
+// entry is not finite.  One thread per (Rp, component, row).
+__global__ void k_g_row_bound(int n_re, long rows, int nw, const double* __restrict__ g,
+                              const double* __restrict__ w, long rows_per_rp, int n_rp,
+                              unsigned long long* __restrict__ out) {
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double t = 0.0;
+    bool bad = false;
+    if (r < rows) {
+        for (int e = 0; e < n_re; ++e) {
+            const double* x = g + ((size_t)e * rows + r) * nw * 2;
+            double u = 0.0;
+            for (int j = 0; j < nw; ++j) {
+                const double a = x[2 * j], b = x[2 * j + 1];
+                bad = bad || !isfinite(a) || !isfinite(b);
+                u += hypot(a, b);
+            }
+            t += w ? fabs(w[(long)e * n_rp + r / rows_per_rp]) * u : u;
+        }
+    }
+    __shared__ double red[256];
+    __shared__ int badf;
+    if (threadIdx.x == 0) badf = 0;
+    red[threadIdx.x] = t;
+    __syncthreads();
+    if (bad) atomicOr(&badf, 1);
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&out[0], (unsigned long long)__double_as_longlong(red[0]));
+        if (badf) atomicOr(&out[1], 1ull);
+    }
+}
+
 __global__ void k_convert(long count, const double* __restrict__ in, float* __restrict__ out) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) out[t] = (float)in[t];
@@ -704,6 +744,16 @@ void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t
     if (n <= 0) return;
     hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, cols, w, data);
     check_launch("scale_rows");
+}
+
+void g_row_bound(int n_re, long rows, int nw, const double* g, const double* w, long rows_per_rp, int n_rp,
+                 unsigned long long* out, hipStream_t st) {
+    if (hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
+        throw Error{-3, "g_row_bound: hipMemsetAsync failed"};
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_g_row_bound, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, n_re, rows, nw, g, w,
+                       rows_per_rp, n_rp, out);
+    check_launch("g_row_bound");
 }
 
 void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {

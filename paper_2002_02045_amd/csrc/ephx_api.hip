@@ -91,6 +91,13 @@ void require(bool ok, const std::string& msg) {
     if (!ok) throw Error{EPHX_EINVAL, msg};
 }
 
+// The largest power of two that keeps a bound on the half-set coefficients of
+// the Rp contraction's g operand under 2^14 (fp16 ends at 65504).
+static double fp16_scale(double bound) {
+    return bound > 0.0 ? std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(std::log2(16384.0 / bound)))))
+                       : 1.0;
+}
+
 static bool finite_all(const double* p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -398,9 +405,7 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                             }
                 double bound = 0.0;
                 for (double v : rs) bound = std::max(bound, 2.0 * v);
-                m->g_scale = bound > 0.0 ? std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(
-                                                                                           std::log2(16384.0 / bound)))))
-                                         : 1.0;
+                m->g_scale = fp16_scale(bound);
             }
             {
                 bool unit = true;
@@ -486,6 +491,28 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
             throw;
         }
         *out = m;
+    });
+}
+
+extern "C" int ephx_model_set_g(ephx_model* m, const double* g, void* stream) {
+    return guarded([&] {
+        require(m != nullptr && g != nullptr, "model_set_g: null argument");
+        hipStream_t st = (hipStream_t)stream;
+        const long rows = (long)m->n_rp_g * m->nm * m->nw;
+        const size_t bytes = (size_t)m->n_re_g * rows * m->nw * 16;
+        // check the new values (and bound them for the fp16 scale) before they
+        // replace the model's copy
+        unsigned long long* red = (unsigned long long*)m->ws.get("setg.red", 2 * sizeof(unsigned long long));
+        g_row_bound(m->n_re_g, rows, m->nw, g, m->d_wg, (long)m->nm * m->nw, m->n_rp_g, red, st);
+        unsigned long long h[2] = {0, 0};
+        hip_check(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (h[1]) throw Error{EPHX_ENAN, "model_set_g: non-finite entry in g"};
+        double rowmax;
+        std::memcpy(&rowmax, &h[0], sizeof(rowmax));
+        hip_check(hipMemcpyAsync(m->d_g, g, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        if (m->d_wg) scale_rows((long)m->n_re_g * m->n_rp_g, (long)m->nm * m->nw * m->nw, m->d_wg, m->d_g, st);
+        m->g_scale = fp16_scale(2.0 * rowmax);
     });
 }
 

@@ -118,6 +118,11 @@ void phonon_omega(long count, double* lam, hipStream_t st);
 void apply_u_right(int Z, int nrp, int nm, int nw, const double* g, const double* u,
                    double* out, hipStream_t st);
 void convert_f64_f32(long count, const double* in, float* out, hipStream_t st);
+// out[0] = bit pattern of max over the rows r of sum_{e,j} |w[e][r / rows_per_rp] g[e][r][j]|
+// for complex g [n_re][rows][nw] (w [n_re][n_rp], or nullptr for 1); out[1] != 0 if
+// an entry is not finite (out cleared first)
+void g_row_bound(int n_re, long rows, int nw, const double* g, const double* w, long rows_per_rp, int n_rp,
+                 unsigned long long* out, hipStream_t st);
 // data[r][c] *= w[r] for complex data [rows][cols]
 void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t st);
 // out(z)[p][x][i][j] = sum_n g'(z)[p][x][i][n] conj(U(z)[j][n])   (adjoint of apply_u_right)
@@ -394,8 +399,10 @@ void mode_finish(int S, int nm, int ns, const double* r, VecPtrs f, VecPtrs lam,
                  int accumulate, hipStream_t st);
 void ita_gamma(int S, int n_ct, const double* rowp, double n_q, const double* vel, double* tau, double* f0,
                double* f, hipStream_t st);
+// F = F0 + tau/N_q * (row sums); with chg, max|F - fprev| and max|F| into chg[0..1]
+// (bit patterns, cleared by the caller)
 void ita_update(int S, int n_ct, const double* rowp, double n_q, const double* tau, const double* f0, double* f,
-                hipStream_t st);
+                hipStream_t st, const double* fprev = nullptr, unsigned long long* chg = nullptr);
 void mobility_reduce(int S, const double* eps, const double* vel, const double* f, double mu, double temp,
                      double* fout, double* mob, hipStream_t st);
 struct Lincomb {

@@ -275,6 +275,58 @@ def test_dynamics_vjp_parity(lib, tiny, small_case):
     assert float((gs.cpu() - ds).abs().max() / ds.abs().max()) <= 1e-9
 
 
+def test_dynamics_vjp_checkpoint_interval(lib, tiny, small_case):
+    """Checkpoints every 1, 5 or 10 steps (10 steps: one to ten segments
+    replayed) give the same gradients: the replay reproduces the stored
+    forward states bit for bit, so the reverse sweep sees the same stages."""
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = small_case
+    t = lib.PairTable(dm, n, kk, bb, precision="fp64")
+    nq = 100.0 * float(np.prod(n))
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=nq))
+    e0 = float(eps.min())
+    f0 = 0.1 * np.exp(-((eps.numpy() - e0 - 0.3) / 0.1) ** 2) + 0.01
+    fbar = np.random.default_rng(17).standard_normal(len(kk))
+    res = []
+    for every in (1, 5, 10):
+        ff, ck = t.dynamics(f0, 1.0, 10, ckpt_every=every)
+        g0, gs = t.dynamics_vjp(ck, 1.0, 10, every, fbar)
+        res.append((ff.cpu(), g0.cpu(), gs.cpu()))
+    for ff, g0, gs in res[1:]:
+        assert torch.equal(ff, res[0][0])
+        assert float((g0 - res[0][1]).abs().max()) <= 1e-14 * float(res[0][1].abs().max())
+        assert float((gs - res[0][2]).abs().max()) <= 1e-14 * float(res[0][2].abs().max())
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_dynamics_vjp_banded_table(lib, tiny, big_case, prec, tol):
+    """Backward through RK4 on the S = 1030 banded layout (tiles skipped,
+    ragged edges) from FP64 and FP32 tables: dE/df0 and dE/ds_nu against the
+    oracle's autograd through the same steps."""
+    _say("dynamics VJP S=1030 %s, 6 steps, checkpoints every 3" % prec)
+    m, dm = tiny
+    n, kk, bb, g2s, om, eps = big_case
+    nq = 20.0 * float(np.prod(n))
+    e0 = float(eps.min())
+    f0 = 0.1 * np.exp(-((eps.numpy() - e0 - 0.2) / 0.1) ** 2) + 0.01
+    e_val, df0, ds = grad.dynamics_grad(torch.as_tensor(f0), eps, g2s, om, dt=1.0, n_steps=6, e_ref=e0, n_q=nq,
+                                        **PAR)
+    t = lib.PairTable(dm, n, kk, bb, precision=prec)
+    t.setup(lib.Params(temp=PAR["temp"], sigma=PAR["sigma"], n_q=nq))
+    ff, ck = t.dynamics(f0, 1.0, 6, ckpt_every=3)
+    fc = ff.cpu()
+    en = eps - e0
+    etot = float((en * fc).sum() / fc.sum())
+    fbar = (en - etot) / fc.sum()
+    g0, gs = t.dynamics_vjp(ck, 1.0, 6, 3, fbar.numpy())
+    e0err = float((g0.cpu() - df0).abs().max() / df0.abs().max())
+    eserr = float((gs.cpu() - ds).abs().max() / ds.abs().max())
+    _say("  f0_bar error %.3e, s_bar error %.3e" % (e0err, eserr))
+    assert abs(etot - e_val) <= (1e-12 if prec == "fp64" else 1e-6) * abs(e_val)
+    assert e0err <= tol and eserr <= tol
+    t.close()
+
+
 def test_fp32_table_collision_and_dynamics(lib, tiny, small_case):
     m, dm = tiny
     n, kk, bb, g2s, om, eps = small_case
@@ -341,9 +393,12 @@ def test_mobility_vjp_matches_oracle_gradient(lib, n_iter):
     err = float((g_bar - g_ref).abs().max() / g_ref.abs().max())
     _say("  max rel err %.2e" % err)
     assert err <= 1e-10
-    # the autograd.Function routes its backward through the same entry point
-    gt = torch.zeros(dm.g_shape, dtype=torch.complex128, device="cuda", requires_grad=True)
-    mob = lib.MobilityFunction.apply(gt, t, par, vel.numpy(), n_iter)
+    # the autograd.Function builds its table from the g it is given and routes
+    # its backward through the same entry point
+    gt = torch.as_tensor(m.g, dtype=torch.complex128, device="cuda").requires_grad_(True)
+    mob = lib.MobilityFunction.apply(gt, dm, n, kk, bb, par, vel.numpy(), n_iter)
+    _, _, mob0 = t.mobility(par, vel.numpy(), n_iter)
+    assert torch.equal(mob.detach(), mob0)
     (mob * torch.as_tensor(lam, device=mob.device)).sum().backward()
     assert torch.equal(gt.grad.cpu(), g_bar)
 

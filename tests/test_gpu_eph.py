@@ -90,9 +90,14 @@ def gkq_case(tiny):
 
 # BF16x3 (two bf16 parts, three products) carries a representation error of
 # ~3*2^-18 per product; its measured |g|^2 error on this case is 1.02e-5
-# (p99 8e-6), so its bound here is 2e-5.  BF16x6 meets 1e-5 with margin.
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-5), ("bf16x6", 1e-5),
-                                      ("fp16x3", 1e-5)])
+# (p99 8e-6): it misses the 1e-5 contract, which is recorded as an expected
+# failure, and a separate regression bound of 2e-5 guards it.  BF16x6 and
+# FP16x3 meet 1e-5 with margin.
+@pytest.mark.parametrize("prec,tol", [
+    ("fp64", 1e-10), ("fp32", 1e-5),
+    pytest.param("bf16x3", 1e-5, marks=pytest.mark.xfail(
+        strict=True, reason="two bf16 parts per operand: measured 1.02e-5 here, 1.1-1.3e-5 elsewhere")),
+    ("bf16x6", 1e-5), ("fp16x3", 1e-5)])
 def test_gkq_parity(lib, tiny, gkq_case, prec, tol):
     _say("gkq parity tiny model prec=%s" % prec)
     m, dm = tiny
@@ -102,6 +107,12 @@ def test_gkq_parity(lib, tiny, gkq_case, prec, tol):
     emax, e99 = g2_error(got, ref)
     _say("  |g|^2 error %s: max %.3e  p99 %.3e" % (prec, emax, e99))
     assert emax <= tol
+
+
+def test_gkq_bf16x3_regression_bound(lib, tiny, gkq_case):
+    """BF16x3 below the 1e-5 contract is not met (see test_gkq_parity); this
+    holds it to its measured level so that a regression still fails."""
+    test_gkq_parity(lib, tiny, gkq_case, "bf16x3", 2e-5)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x6", 1e-5), ("fp16x3", 1e-5)])
@@ -253,9 +264,12 @@ def test_rates_vjp_parity_and_finite_difference(lib, tiny):
     ad = float((gb.numpy().real * direc.real + gb.numpy().imag * direc.imag).sum())
     _say("  directional FD %.9e vs adjoint %.9e" % (fd, ad))
     assert abs(fd - ad) <= 1e-6 * abs(ad)
-    # the autograd Function routes backward through the same entry point
-    gt = torch.zeros(m.g.shape, dtype=torch.complex128, device="cuda", requires_grad=True)
+    # the autograd Function computes from the g it is given and routes its
+    # backward through the same entry point
+    gt = torch.as_tensor(m.g, dtype=torch.complex128, device="cuda").requires_grad_(True)
     gam = lib.RatesFunction.apply(gt, dm, k, q, p)
+    g0, _ = lib.rates(dm, k, q, p, mode_resolved=False)
+    assert torch.equal(gam.detach(), g0)
     (gam * torch.as_tensor(lam, device="cuda")).sum().backward()
     assert torch.allclose(gt.grad.cpu(), gb)
 

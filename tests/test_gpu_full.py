@@ -11,7 +11,8 @@ Model: the benchmark's Si-like model (Nw = 8, 6 modes, 512 Re x 512 Rp).
   full list while the result depends only on the sample, which the oracle
   evaluates directly.  A second property holds at any size: splitting the q
   list in two and recombining the halves by their weights gives the same rates.
-Tolerances as elsewhere: FP64 1e-10; FP32 / BF16x6 |g|^2 1e-5, BF16x3 2e-5;
+Tolerances as elsewhere: FP64 1e-10; |g|^2 1e-5 for every reduced precision
+(BF16x3 meets it on this sample, 7.7e-6, though not on the tiny model);
 rates 1e-4 for the reduced precisions.
 """
 import sys
@@ -26,7 +27,7 @@ from oracle import eph
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4), ("bf16x6", 1e-5, 1e-4), ("bf16x3", 2e-5, 1e-4),
+PRECS = [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4), ("bf16x6", 1e-5, 1e-4), ("bf16x3", 1e-5, 1e-4),
          ("fp16x3", 1e-5, 1e-4)]
 
 
@@ -157,17 +158,35 @@ def test_full_size_dynamics_table_sampled(lib, si):
         worst = max(worst, float(np.abs(gs - rs).max()) / scale if ref[i].abs().max() > 0 else float(np.abs(gs).max()))
     _say("  table error on %d sampled pairs: %.3e" % (len(pairs), worst))
     assert worst <= 1e-5
+    # rows of the table for the collision check below: 24 random states, the
+    # 20 around the hot-carrier peak and the 20 lowest
+    f0 = cfg["f0_peak"] * np.exp(-((e_s - e_s.min() - cfg["f0_centre"]) ** 2) / (2 * cfg["f0_width"] ** 2))
+    peak = np.argsort(np.abs(e_s - e_s.min() - cfg["f0_centre"]))[:20]
+    rows = np.unique(np.concatenate([rng.choice(S, 24, replace=False), peak, order[:20]]))
+    g_rows = g[:, torch.as_tensor(rows, device=g.device), :].permute(1, 2, 0).double().cpu()   # [row][t][nu]
     del g
     torch.cuda.empty_cache()
     t.setup(lib.Params(temp=cfg["T"], sigma=cfg["sigma"], omega_cut=cfg["omega_cut"], n_q=float(np.prod(n))))
     live, n_live, n_tiles = t.stream_info("collision")
-    f0 = cfg["f0_peak"] * np.exp(-((e_s - e_s.min() - cfg["f0_centre"]) ** 2) / (2 * cfg["f0_width"] ** 2))
     i_out = t.collision(f0).cpu()
     cons = abs(float(i_out.sum())) / float(i_out.abs().sum())
     _say("  banded pass: %d of %d tiles (%.3f of S^2); conservation %.2e" % (n_live, n_tiles, live / S ** 2, cons))
     assert 0 < n_live < n_tiles
     assert cons <= 1e-12
     t.close()
+    # the banded pass on the full table against Eq. e_ph_scattering applied to
+    # the same rows of the table, with the oracle's phonon energies: a dropped
+    # or misplaced live tile changes these rows while conserving carriers
+    _say("oracle phonons on the 80^3 grid, collision of %d sampled rows" % len(rows))
+    om_grid = torch.cat([interp.phonons(m, pts[i:i + 65536])[0] for i in range(0, len(pts), 65536)])
+    iq = grid.pair_q_index(kk[rows][:, None], kk[None, :], n)            # [row][t]
+    om_rows = om_grid[torch.as_tensor(iq)]                                 # [row][t][nu]
+    ref_i = bte.collision_rows(rows, f0, e_s, g_rows, om_rows, temp=cfg["T"], sigma=cfg["sigma"],
+                               n_q=float(np.prod(n)), omega_cut=cfg["omega_cut"])
+    err_i = float((i_out[rows] - ref_i).abs().max() / ref_i.abs().max())
+    _say("  collision rows error %.3e (largest |I| %.3e)" % (err_i, float(ref_i.abs().max())))
+    assert float(ref_i.abs().max()) > 0
+    assert err_i <= 1e-4
 
 
 def group_labels_modes(omega, tol=1e-4):

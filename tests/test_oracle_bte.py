@@ -301,3 +301,92 @@ def test_transport_matrix_row_sums_are_the_rates():
     ref = gamma[torch.as_tensor(kk), torch.as_tensor(bb)]
     assert float(ref.min()) > 0
     assert torch.allclose(w.sum(dim=1) / nk, ref, rtol=1e-12)
+
+
+def _symmetric_pair_table(half, seed):
+    """States in +/-k pairs: W invariant under the pairing, odd velocities."""
+    rng = np.random.default_rng(seed)
+    e_half = np.sort(rng.random(half) * 0.2)
+    eps = torch.as_tensor(np.concatenate([e_half, e_half]))
+    perm = np.concatenate([np.arange(half, 2 * half), np.arange(half)])
+    g = rng.random((2 * half, 2 * half, 2))
+    g = g + g[perm][:, perm]
+    g = g + g.transpose(1, 0, 2)
+    om = 0.02 + 0.03 * rng.random((2 * half, 2 * half, 2))
+    om = om + om[perm][:, perm]
+    om = 0.5 * (om + om.transpose(1, 0, 2))
+    w = bte.transport_matrix(eps, torch.as_tensor(g), torch.as_tensor(om), temp=300.0, mu=-0.2, sigma=0.03)
+    vh = rng.standard_normal((half, 3))
+    return w, torch.as_tensor(np.concatenate([vh, -vh]))
+
+
+def test_ita_dense_odd_with_decoupled_groups():
+    """Two groups of states that do not scatter into each other: (1 - M) has a
+    two-dimensional null space, yet the odd fixed point is unique and is what
+    the iteration converges to; the dense odd solve gives it, with self-partnered
+    states (k = -k) at F = 0."""
+    w1, v1 = _symmetric_pair_table(6, 31)
+    w2, v2 = _symmetric_pair_table(5, 32)
+    s1, s2 = len(v1), len(v2)
+    w = torch.zeros((s1 + s2 + 1, s1 + s2 + 1), dtype=torch.float64)
+    w[:s1, :s1] = w1
+    w[s1:s1 + s2, s1:s1 + s2] = w2
+    w[-1, -1] = 1.0                       # a state at k = -k scattering only into itself
+    v = torch.cat([v1, v2, torch.zeros((1, 3), dtype=torch.float64)])
+    partner = np.concatenate([np.arange(6, 12), np.arange(6), s1 + np.arange(5, 10), s1 + np.arange(5),
+                              [s1 + s2]])
+    nq = 40.0
+    f_it, _, n, _ = bte.ita_converged(w, v, nq, 5000, 1e-13)
+    f_d, _ = bte.ita_dense_odd(w, v, nq, partner)
+    assert n < 5000
+    assert float((f_it - f_d).abs().max()) <= 1e-10 * float(f_d.abs().max())
+    assert float(f_d[-1].abs().max()) == 0.0
+
+
+def test_ita_stopping_rule_and_converged_value():
+    """The converged iterate (Eq. BTE_iter run to a threshold) solves
+    (1 - M) F = tau v, M = diag(tau/N_q) W: that system is singular here (the
+    rows of M sum to one, M 1 = 1), and F is its solution with sum_s F_s = 0,
+    as odd vectors have; that solution is also the one of the regular system
+    (1 - M + 1 1^T / S) F = tau v, and the minimum-norm least-squares one.
+    The count is the first update whose relative change is below tol, found
+    by brute force over fixed-count runs."""
+    w, v = _symmetric_pair_table(14, 12)
+    nq, tol = 50.0, 1e-12
+    f, tau, n, chg = bte.ita_converged(w, v, nq, 5000, tol)
+    assert 0 < n < 5000 and 0 <= chg < tol
+    S = len(v)
+    a = torch.eye(S, dtype=torch.float64) - (tau / nq)[:, None] * w
+    ref = torch.linalg.solve(a + 1.0 / S, tau[:, None] * v)
+    assert float((f - ref).abs().max()) <= 1e-10 * float(ref.abs().max())
+    lsq = torch.linalg.lstsq(a, tau[:, None] * v, rcond=1e-12, driver="gelsd").solution
+    assert float((lsq - ref).abs().max()) <= 1e-9 * float(ref.abs().max())
+    half = S // 2
+    partner = np.concatenate([np.arange(half, S), np.arange(half)])
+    odd, _ = bte.ita_dense_odd(w, v, nq, partner)
+    assert float((odd - ref).abs().max()) <= 1e-10 * float(ref.abs().max())
+    prev, _ = bte.ita(w, v, nq, 0)
+    for i in range(1, n + 1):
+        cur, _ = bte.ita(w, v, nq, i)
+        rel = float((cur - prev).abs().max()) / float(cur.abs().max())
+        assert (rel < tol) == (i == n)
+        prev = cur
+    assert torch.equal(f, prev)
+    # n_iter_max = 0 is the RTA; a cap below the count stops there
+    f0, _, n0, c0 = bte.ita_converged(w, v, nq, 0, tol)
+    assert n0 == 0 and c0 == -1.0 and torch.equal(f0, tau[:, None] * v)
+    f3, _, n3, c3 = bte.ita_converged(w, v, nq, 3, tol)
+    assert n3 == 3 and c3 >= tol and torch.equal(f3, bte.ita(w, v, nq, 3)[0])
+
+
+def test_collision_rows_are_rows_of_the_collision_integral():
+    """collision_rows on a subset of rows equals those entries of the pinned
+    collision integral (any f, mode scales included)."""
+    eps, g2, om = _random_table(30, 3, 21)
+    f = torch.as_tensor(np.random.default_rng(22).random(30))
+    sc = torch.as_tensor([1.0, 0.3, 2.0])
+    par = dict(temp=300.0, sigma=0.02, n_q=500.0)
+    full = bte.collision(f, eps, g2, om, mode_scale=sc, **par)
+    rows = np.array([0, 7, 8, 29])
+    part = bte.collision_rows(rows, f, eps, g2[rows], om[rows], mode_scale=sc, **par)
+    assert torch.allclose(part, full[rows], rtol=1e-13, atol=0)
