@@ -257,6 +257,22 @@ int ephx_collision_setup(ephx_table* t, const ephx_params* p, const double* mode
                          void* stream);
 int ephx_collision(ephx_table* t, const double* f, double* i_out, void* stream);
 
+/* ephx_collision for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same result, computed by the same kernels, but the call allocates
+ * nothing.  Its work memory (the occupations gathered into matrix order and
+ * the row and column partials of the pass, (2 + column tiles + row tiles) * S
+ * doubles) lives in one static 64 MiB device array per GPU, held by the
+ * library until the process ends; a table that needs more returns
+ * EPHX_EINVAL with the size in ephx_last_error().  ephx_collision_setup must
+ * have been called on the table (it builds the pass's tile list), on the
+ * table's device, which must be current (else EPHX_EINVAL).  All calls on one
+ * GPU share that array: calls that overlap in time on one GPU (two streams,
+ * two tables, two threads) race and must be serialised by the caller.  Every
+ * entry of the work memory is written before it is read, so nothing is
+ * cleared between calls.  f, i_out: device double [S], as for ephx_collision. */
+int ephx_collision_noalloc(ephx_table* t, const double* f, double* i_out, void* stream);
+
 /* Storage of the collision matrix (matrix 0, after ephx_collision_setup) or
  * the transport matrix (matrix 1, after ephx_mobility): both are kept with
  * rows and columns in ascending state energy, and the Gaussian delta of

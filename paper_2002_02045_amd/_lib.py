@@ -73,6 +73,7 @@ _SIGS = {
     "ephx_table_g2": ([_P, _P, _P, _P], _I),
     "ephx_collision_setup": ([_P, _P, _P, _P], _I),
     "ephx_collision": ([_P, _P, _P, _P], _I),
+    "ephx_collision_noalloc": ([_P, _P, _P, _P], _I),
     "ephx_dynamics": ([_P, _P, _D, _I, _I, _P, _P, _P], _I),
     "ephx_dynamics_field": ([_P, _P, _D, _I, _I, _P, _I, _P, _P, _P], _I),
     "ephx_gkq_pairs": ([_P, _I, _P, _I, _P, _I, _P, _P, _I, _D, _P, _P], _I),

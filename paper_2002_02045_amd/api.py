@@ -302,6 +302,17 @@ class PairTable:
         check(lib.ephx_collision(self._h, ptr(f), ptr(out), stream_ptr()))
         return out
 
+    def collision_noalloc(self, f, out):
+        """I[f] into the caller's device tensor `out` (S doubles) through the
+        entry point that allocates nothing (its work memory is the library's
+        static per-GPU array; calls overlapping on one GPU race)."""
+        if not (torch.is_tensor(f) and f.is_cuda and f.dtype == F64 and f.numel() == self.S):
+            raise TypeError("f must be a float64 device tensor of S entries")
+        if not (torch.is_tensor(out) and out.is_cuda and out.dtype == F64 and out.numel() == self.S):
+            raise TypeError("out must be a float64 device tensor of S entries")
+        check(lib.ephx_collision_noalloc(self._h, ptr(f), ptr(out), stream_ptr()))
+        return out
+
     def dynamics(self, f0, dt, n_steps, ckpt_every=0, method="rk4", efield=None):
         """f after n_steps steps of dt fs ("rk4" or "euler"), with an optional
         field (V/Angstrom, Cartesian); checkpoints every ckpt_every steps."""

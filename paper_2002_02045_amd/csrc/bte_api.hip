@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <unordered_map>
 #include <vector>
@@ -611,6 +612,9 @@ extern "C" int ephx_collision_setup(ephx_table* t, const ephx_params* p, const d
         build_banded(t, 0, p, t->d_scale, t->d_p, st);
         t->par = *p;
         t->c = 2.0 * kPi / kHbarEvFs / p->n_q;
+        // the tile list of the collision pass, so that ephx_collision_noalloc
+        // finds it ready
+        (void)plan_for(t, 0, 1, 1, st);
         t->ready = true;
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     });
@@ -646,6 +650,80 @@ extern "C" int ephx_collision(ephx_table* t, const double* f, double* i_out, voi
         require_ready(t);
         require(f && i_out, "collision: null array");
         collision_eval(t, f, i_out, nullptr, 0, 0.0, nullptr, 0.0, nullptr, (hipStream_t)stream);
+    });
+}
+
+namespace {
+
+// Work memory of ephx_collision_noalloc: one array per device for the whole
+// process (each GPU the library runs on holds its own copy at its own
+// address).  Host code must use the address from hipGetSymbolAddress, never
+// the array's name, which on the host is only a stand-in for the symbol.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its scratch
+
+// Address of the current device's scratch, looked up once per device.
+void* scratch_on(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Error{EPHX_EHIP, "hipGetSymbolAddress(scratch) returned no address"};
+    g_scratch_ptr[dev] = p;
+    return p;
+}
+
+}  // namespace
+
+// ephx_collision with every work buffer (the occupations gathered into matrix
+// order and the row and column partials of the pass) in the static scratch
+// array: the call allocates nothing.  The collision plan it needs (the live
+// tile list) is built by ephx_collision_setup.
+extern "C" int ephx_collision_noalloc(ephx_table* t, const double* f, double* i_out, void* stream) {
+    return guarded([&] {
+        require_ready(t);
+        require(f && i_out, "collision_noalloc: null array");
+        int dev = -1;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        require(dev == t->m->device, "collision_noalloc: the table lives on device " + std::to_string(t->m->device) +
+                                         ", the current device is " + std::to_string(dev));
+        auto it = t->plans.find(0 * 64 + 1 * 8 + 1);
+        require(it != t->plans.end() && it->second.gen == t->gen[0],
+                "collision_noalloc: no collision plan for the current setup (call ephx_collision_setup)");
+        StreamPlan pl = it->second.pl;
+        const int S = t->S;
+        // gathered 1 - f and f [2][S], row partials [n_ct][S], column partials [n_rt][S]
+        const size_t vec = (size_t)S * 8;
+        const size_t need = (2 + (size_t)pl.n_ct + (size_t)pl.n_rt) * vec;
+        if (need > kNoAllocScratchBytes)
+            throw Error{EPHX_EINVAL, "collision_noalloc: this table needs " + std::to_string(need) +
+                                         " bytes of work memory, more than the " +
+                                         std::to_string(kNoAllocScratchBytes) + " the library holds"};
+        if (S == 0) return;
+        char* base = (char*)scratch_on(dev);
+        hipStream_t st = (hipStream_t)stream;
+        pl.gbuf = (double*)base;
+        pl.rout = nullptr;
+        pl.cout = nullptr;
+        double* rowp = (double*)(base + 2 * vec);
+        double* colp = rowp + (size_t)pl.n_ct * S;
+        // every entry of the buffers is written before it is read (dead tiles
+        // write zero partials), so nothing is cleared
+        gather_occupations(pl, f, st);
+        stream_run(pl, t->ld, t->d_p, rowp, colp, st);
+        CollisionFinish cf{};
+        cf.S = S;
+        cf.n_rt = pl.n_rt;
+        cf.n_ct = pl.n_ct;
+        cf.rowp = rowp;
+        cf.colp = colp;
+        cf.f = f;
+        cf.c = t->c;
+        cf.i_out = i_out;
+        reduce_finish(pl, cf, st);
     });
 }
 
