@@ -40,6 +40,7 @@ def _parse():
                     help="first run a 1 GiB device fill and a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--no-adjoints", action="store_true",
                     help="skip the RK4 backward and the mobility adjoint legs (e.g. under hardware counters)")
+    ap.add_argument("--gaas-grid", type=int, default=100, help="k = q grid of the GaAs-like transport leg (0: skip)")
     ap.add_argument("--cell-k", type=int, default=32, help="k points of the large-cell slice (0: skip)")
     ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
     return ap.parse_args()
@@ -181,6 +182,10 @@ def main():
     if args.dyn_steps > 0:
         dyn = dynamics_bench(px, dm, model, args)
 
+    gaas = None
+    if args.gaas_grid > 0:
+        gaas = gaas_bench(px, args)
+
     cell = None
     if args.cell_k > 0:
         del dm
@@ -210,6 +215,7 @@ def main():
         "by_precision": {p: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in d.items()}
                          for p, d in results.items()},
         "dynamics": dyn,
+        "gaas_transport": gaas,
         "large_cell": cell,
     }
     print(json.dumps(out), flush=True)
@@ -428,6 +434,148 @@ def mobility_adjoint_bench(px, dm, cfg, grid=24, count=1500):
             "iterations": 10, "precision": "fp64"}
 
 
+def fermi_level(eps, n_c, temp, n_k, volume, spin=2.0):
+    """Chemical potential (eV) that puts n_c carriers per cm^3 in the given
+    states (spin degeneracy 2, N_k grid points, cell volume in A^3), by
+    bisection on the Fermi-Dirac sum (a set-up parameter of the transport leg)."""
+    kt = 8.617333262e-5 * temp
+    lo, hi = float(eps.min()) - 2.0, float(eps.max()) + 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        x = np.clip((eps - mid) / kt, -700.0, 700.0)
+        n = spin / (n_k * volume) * float(np.sum(1.0 / (np.exp(x) + 1.0))) * 1e24
+        lo, hi = (mid, hi) if n < n_c else (lo, mid)
+    return 0.5 * (lo + hi)
+
+
+def gaas_bench(px, args):
+    """GaAs-like polar transport: Nw = 8, 2 atoms (Ga, As masses), Z* = +-2.1,
+    eps_inf = 10.9, real H, C and g on 512 Re x 512 Rp, the Froehlich term of
+    Eq. e_ph_long in g (FP64, every q); the conduction states of a 0.2 eV window
+    above the CBM on the n^3 k = q grid; mu for 1e17 carriers per cm^3 at
+    300 K, sigma = 5 meV.  Pair tables in FP64 and FP32; the iterative BTE
+    (Eq. BTE_iter) run to its threshold on each, the mobility (Eq. cond), and
+    the adjoint d mu_xx / d g(Re,Rp) at full size, with a central-difference
+    check of it on a 20^3 grid."""
+    import torch
+
+    import synth
+    cfg = synth.CONFIGS["gaas"]
+    m = synth.make_config_model("gaas")
+    a = synth.models.A_GAAS
+    pol = dict(alpha_ewald=(2 * np.pi / a) ** 2, gcut=4 * 2 * np.pi / a)
+    dm = px.Model(m, polar=pol)
+    n = (args.gaas_grid,) * 3
+    nk = float(np.prod(n))
+    cb = m.nw // 2
+    t0 = time.perf_counter()
+    cbm = float(px.grid_states(dm, n, mode="lowest", band_lo=cb, count=1)[2].min())
+    kk, bb, ee = px.grid_states(dm, n, mode="window", band_lo=cb, band_hi=m.nw, e_lo=cbm - 1e-3,
+                                e_hi=cbm + cfg["window"])
+    t_states = time.perf_counter() - t0
+    S = len(kk)
+    mu = fermi_level(ee, cfg["n_c"], cfg["T"], nk, m.volume())
+    par = px.Params(temp=cfg["T"], mu=mu, sigma=cfg["sigma"], omega_cut=cfg["omega_cut"], n_q=nk)
+    pts = np.stack([kk // (n[1] * n[2]), (kk // n[2]) % n[1], kk % n[2]], axis=-1) / np.asarray(n, dtype=np.float64)
+    _, _, v = px.bands(dm, pts, want_u=False, want_vel=True)
+    vel = v[torch.arange(S, device=v.device), torch.as_tensor(bb, device=v.device)].contiguous()
+    log("gaas: %d window states on %s (CBM %.4f eV, mu %.4f eV for %.0e cm^-3), states %.1f s" % (
+        S, "x".join(map(str, n)), cbm, mu, cfg["n_c"], t_states))
+    out = {"workload": "gaas-like polar transport: Nw=8, 2 atoms, Z*=+-2.1, eps_inf=10.9, 512 Re x 512 Rp, "
+                       "Froehlich term, %s k=q grid, %d states in a %.1f eV window above the CBM, n_c=%.0e cm^-3, "
+                       "T=300 K, sigma=5 meV" % ("x".join(map(str, n)), S, cfg["window"], cfg["n_c"]),
+           "states": S, "mu_eV_above_cbm": mu - cbm}
+    mobs = {}
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-6)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tab = px.PairTable(dm, n, kk, bb, precision=prec)
+        torch.cuda.synchronize()
+        t_table = time.perf_counter() - t0
+        tab.ita(par, vel, 2, 0.0)                                   # builds W and the plans
+        torch.cuda.synchronize()
+        px.timer_reset()
+        px.timer_enable(True)
+        t0 = time.perf_counter()
+        ff, _, mob, n_it, chg = tab.ita(par, vel, 2000, tol)
+        torch.cuda.synchronize()
+        t_ita = time.perf_counter() - t0
+        px.timer_enable(False)
+        n_st, ms_st = px.timer_get("transport_stream")
+        _, ms_build = px.timer_get("matrix_build")
+        px.timer_reset()
+        live = tab.stream_info("transport")[0]
+        esz = 8 if prec == "fp64" else 4
+        gbs = esz * live / (ms_st / n_st * 1e-3) / 1e9
+        mobs[prec] = mob.cpu().numpy()
+        out[prec] = {"table_build_s": round(t_table, 3), "tol": tol, "iterations": n_it, "last_change": chg,
+                     "ita_s": round(t_ita, 4), "ms_per_iteration": round(1e3 * t_ita / max(1, n_it), 4),
+                     "w_build_ms": round(ms_build, 3), "transport_stream_avg_ms": round(ms_st / n_st, 5),
+                     "transport_stream_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_GBS, 4),
+                     "mobility_cm2_per_Vs": [float(mobs[prec][i, i]) for i in range(3)]}
+        log("gaas %s: table %.2f s, ITA to %.0e in %d updates (%.1f ms, %.3f ms each, stream %.0f GB/s), "
+            "mu_xx %.5g cm^2/Vs" % (prec, t_table, tol, n_it, 1e3 * t_ita, 1e3 * t_ita / max(1, n_it), gbs,
+                                    float(mob[0, 0])))
+        if prec == "fp64":
+            lam = np.zeros((3, 3))
+            lam[0, 0] = 1.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gb = tab.mobility_vjp(par, vel, n_it, lam)
+            torch.cuda.synchronize()
+            t_adj = time.perf_counter() - t0
+            out["adjoint_fp64"] = {"pairs": S * S, "iterations": n_it, "s": round(t_adj, 3),
+                                   "pairs_per_s": S * S / t_adj}
+            log("gaas: adjoint d mu_xx / d g(Re,Rp) through %d updates, %d pairs in %.2f s" % (n_it, S * S, t_adj))
+            del gb
+        tab.close()
+        torch.cuda.empty_cache()
+    d = np.diagonal(mobs["fp32"]) / np.diagonal(mobs["fp64"]) - 1.0
+    out["fp32_mobility_rel_err_vs_fp64_gpu"] = float(np.abs(d).max())
+    out["fd_check"] = gaas_fd_check(px, dm, m, cfg, par, 20)
+    return out
+
+
+def gaas_fd_check(px, dm, m, cfg, par, grid):
+    """Directional derivative of mu_xx w.r.t. g(Re,Rp) from the adjoint against
+    a central difference of the library's own mobility, on a small grid."""
+    import torch
+
+    n = (grid,) * 3
+    cb = m.nw // 2
+    cbm = float(px.grid_states(dm, n, mode="lowest", band_lo=cb, count=1)[2].min())
+    kk, bb, ee = px.grid_states(dm, n, mode="window", band_lo=cb, band_hi=m.nw, e_lo=cbm - 1e-3,
+                                e_hi=cbm + cfg["window"])
+    pts = np.stack([kk // (n[1] * n[2]), (kk // n[2]) % n[1], kk % n[2]], axis=-1) / np.asarray(n, dtype=np.float64)
+    _, _, v = px.bands(dm, pts, want_u=False, want_vel=True)
+    vel = v[torch.arange(len(kk), device=v.device), torch.as_tensor(bb, device=v.device)].contiguous()
+    p = px.Params(temp=par.temp, mu=par.mu, sigma=par.sigma, omega_cut=par.omega_cut, n_q=float(np.prod(n)))
+    g0 = torch.as_tensor(m.g, dtype=torch.complex128, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(cfg["seed"] + 300)
+    d = torch.randn(g0.shape, dtype=torch.complex128, device="cuda", generator=gen) * g0.abs()
+    lam = np.zeros((3, 3))
+    lam[0, 0] = 1.0
+    tab = px.PairTable(dm, n, kk, bb, precision="fp64")
+    _, _, _, n_it, _ = tab.ita(p, vel, 2000, 1e-10)
+    gb = tab.mobility_vjp(p, vel, n_it, lam)
+    ad = float((gb.conj() * d).real.sum())
+    tab.close()
+    h = 1e-4
+    vals = []
+    for sgn in (1.0, -1.0):
+        dm.set_g(g0 + sgn * h * d)
+        t = px.PairTable(dm, n, kk, bb, precision="fp64")
+        vals.append(float(t.mobility(p, vel, n_it)[2][0, 0]))
+        t.close()
+    dm.set_g(g0)
+    fd = (vals[0] - vals[1]) / (2 * h)
+    rel = abs(fd - ad) / abs(ad)
+    log("gaas: d mu_xx/dg along a random direction on %d^3 (%d states, %d updates): adjoint %.8e, central "
+        "difference %.8e, relative difference %.2e" % (grid, len(kk), n_it, ad, fd, rel))
+    return {"grid": grid, "states": len(kk), "iterations": n_it, "adjoint": ad, "central_difference": fd,
+            "h": h, "rel_diff": rel}
+
+
 def cell_bench(px, args):
     """Large cell (40 atoms, 120 modes, 64 Wannier functions, simple-cubic
     10 Angstrom cell, 3^3 real-space sets): scattering rates on a slice of
@@ -602,7 +750,37 @@ def cpu_baseline(model, kpts, q, cfg, seconds):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": "1 window k x %d q of the same workload (FP64 oracle, %.1f s, host cpu_count %d)" % (
-                done, dt, os.cpu_count())}
+                done, dt, os.cpu_count()),
+            "host": host_info()}
+
+
+def host_info():
+    """CPU model, logical CPUs, BLAS threads and RAM of the host the oracle ran on."""
+    import platform
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()
+                if d.get("user_api") == "blas"]
+    except Exception:
+        pass
+    try:
+        ram = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 2 ** 30
+    except (ValueError, OSError):
+        ram = None
+    import torch
+    return {"cpu_model": model or platform.processor(), "logical_cpus": os.cpu_count(),
+            "torch_threads": torch.get_num_threads(), "blas": blas,
+            "ram_gib": round(ram, 1) if ram else None}
 
 
 if __name__ == "__main__":
