@@ -31,6 +31,9 @@ struct ephx_table {
     void* d_pmode = nullptr;      // [nm][S][ld] collision matrix of each mode alone at unit scale
     double* d_eunit = nullptr;    // [nm][nm] unit scale vectors
     int pmode_gen = -1;           // gen[0] the per-mode matrices were built for
+    const int32_t* panel_tiles = nullptr;   // live tiles of the per-mode matrices for the stage-panel gradient
+    int n_panel_tiles = 0;
+    int panel_gen = -1;
     double* d_scale = nullptr;    // [nm] collision mode scales
     double* d_unit = nullptr;     // [nm] ones (transport matrix)
     double* d_ones = nullptr;     // [S]
@@ -180,16 +183,21 @@ struct Field {
     double dc[3] = {0.0, 0.0, 0.0};
 };
 
+// gathered: the plan's gather buffer already holds y (written by the previous
+// evaluation's finish); gather_next: this evaluation's finish writes the next
+// one's occupations there (f_next, or acc when next_from_acc).
 void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, int acc_init, double w_acc,
                     const double* f_base, double a_next, double* f_next, hipStream_t st,
-                    const Field* fld = nullptr) {
+                    const Field* fld = nullptr, bool gathered = false, bool gather_next = false,
+                    bool next_from_acc = false) {
     const int S = t->S;
     const StreamPlan pl = plan_for(t, 0, 1, 1, st);
     double* rowp = (double*)t->ws.get("c.rowp", (size_t)pl.n_ct * S * 8);
     double* colp = (double*)t->ws.get("c.colp", (size_t)pl.n_rt * S * 8);
-    // three kernels per evaluation: 1 - f and f gathered to matrix order, the
-    // stream over P, and the partials reduced and finished in state order
-    {
+    // kernels per evaluation: 1 - f and f gathered to matrix order (unless the
+    // previous finish did it), the stream over P, and the partials reduced and
+    // finished in state order
+    if (!gathered) {
         StageTimer tm("stream_permute", st);
         gather_occupations(pl, y, st);
     }
@@ -214,6 +222,10 @@ void collision_eval(ephx_table* t, const double* y, double* i_out, double* acc, 
     cf.f_next = f_next;
     cf.nbr = fld ? fld->nbr : nullptr;
     for (int d = 0; d < 3; ++d) cf.dc[d] = fld ? fld->dc[d] : 0.0;
+    if (gather_next && acc && (next_from_acc || f_next)) {
+        cf.gnext = pl.gbuf;
+        cf.gnext_acc = next_from_acc ? 1 : 0;
+    }
     StageTimer tm("stream_permute", st);
     reduce_finish(pl, cf, st);
 }
@@ -237,6 +249,24 @@ void ensure_pmode(ephx_table* t, hipStream_t st) {
                      t->d_eps, t->par.temp, t->par.mu, t->par.sigma, t->par.omega_cut, t->d_eunit + nu * t->nm,
                      t->d_perm, (char*)t->d_pmode + nu * mat, t->band[0], st);
     t->pmode_gen = t->gen[0];
+}
+
+// Live kPT x kPT tiles of the per-mode matrices (energy order, band of P),
+// built once per collision setup.
+void panel_tiles(ephx_table* t, hipStream_t st, const int32_t*& tiles, int& n) {
+    if (t->panel_gen != t->gen[0]) {
+        std::vector<int32_t> h;
+        mode_panel_tiles(t->h_esort, t->band[0], h);
+        // earlier launches on this stream may still read the old list
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        int32_t* d = (int32_t*)t->ws.get("panel.tiles", std::max<size_t>(8, h.size() * 4));
+        if (!h.empty()) hip_check(hipMemcpy(d, h.data(), h.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+        t->panel_tiles = d;
+        t->n_panel_tiles = (int)(h.size() / 2);
+        t->panel_gen = t->gen[0];
+    }
+    tiles = t->panel_tiles;
+    n = t->n_panel_tiles;
 }
 
 // s_bar (=/+=) sum_j lam_j^T dI/ds at f_j for ns pairs (f_j, lam_j): per mode,
@@ -300,19 +330,24 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
     }
 }
 
-// One RK4 step f -> f_new; stage inputs optionally saved (Y1..Y4)
+// One RK4 step f -> f_new; stage inputs optionally saved (Y1..Y4).  gathered:
+// the collision plan's gather buffer holds f on entry; it holds f_new on exit
+// (each stage's finish gathers the next stage's input).
 void rk4_step(ephx_table* t, const double* f, double dt, double* f_new, double* y2, double* y3, double* y4,
-              hipStream_t st, const Field* fld = nullptr) {
+              hipStream_t st, const Field* fld, bool& gathered) {
     // stage 1 at f: acc = f + dt/6 k1 ; y2 = f + dt/2 k1
-    collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st, fld);
-    collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st, fld);
-    collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st, fld);
-    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st, fld);
+    collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st, fld, gathered, true);
+    collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st, fld, true, true);
+    collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st, fld, true, true);
+    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st, fld, true, true, true);
+    gathered = true;
 }
 
 // One explicit Euler step f -> f_new = f + dt (I[f] + drift)
-void euler_step(ephx_table* t, const double* f, double dt, double* f_new, hipStream_t st, const Field* fld) {
-    collision_eval(t, f, nullptr, f_new, 1, dt, f, 0.0, nullptr, st, fld);
+void euler_step(ephx_table* t, const double* f, double dt, double* f_new, hipStream_t st, const Field* fld,
+                bool& gathered) {
+    collision_eval(t, f, nullptr, f_new, 1, dt, f, 0.0, nullptr, st, fld, gathered, true, true);
+    gathered = true;
 }
 
 // Neighbours of each state along +/- each reduced direction, same band, on
@@ -764,9 +799,10 @@ extern "C" int ephx_dynamics_field(ephx_table* t, const double* f0, double dt, i
         double* y4 = (double*)t->ws.get("d.y4", S * 8);
         hip_check(hipMemcpyAsync(fa, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
         if (ckpts) hip_check(hipMemcpyAsync(ckpts, f0, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        bool gathered = false;
         for (int n = 0; n < n_steps; ++n) {
-            if (method == EPHX_RK4) rk4_step(t, fa, dt, fb, y2, y3, y4, st, fp);
-            else euler_step(t, fa, dt, fb, st, fp);
+            if (method == EPHX_RK4) rk4_step(t, fa, dt, fb, y2, y3, y4, st, fp, gathered);
+            else euler_step(t, fa, dt, fb, st, fp, gathered);
             std::swap(fa, fb);
             if (ckpts && (n + 1) % ckpt_every == 0)
                 hip_check(hipMemcpyAsync(ckpts + (size_t)((n + 1) / ckpt_every) * S, fa, S * 8,
@@ -797,47 +833,64 @@ extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, 
         const int S = t->S;
         const int L = ckpt_every;
         double* a = (double*)t->ws.get("b.a", S * 8);
-        double* kbs[4];   // the stage adjoints k_i_bar of one step, kept for the mode-scale gradient
-        for (int i = 0; i < 4; ++i) kbs[i] = (double*)t->ws.get("b.kb" + std::to_string(i), S * 8);
         double* yb[4];
         for (int i = 0; i < 4; ++i) yb[i] = (double*)t->ws.get("b.yb" + std::to_string(i), S * 8);
         double* ys = (double*)t->ws.get("b.ys", (size_t)L * 4 * S * 8);   // stage inputs of the segment
+        // the stage adjoints k_i_bar of the segment, [step][stage][S] like ys,
+        // kept for the segment's mode-scale gradient
+        double* kbp = (double*)t->ws.get("b.kbp", (size_t)L * 4 * S * 8);
         double* fn = (double*)t->ws.get("b.fn", S * 8);
         hip_check(hipMemcpyAsync(a, f_bar_final, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-        if (s_bar) hip_check(hipMemsetAsync(s_bar, 0, t->nm * 8, st), "hipMemsetAsync");
+        const int32_t* ptiles = nullptr;
+        int n_ptiles = 0;
+        double *pwork = nullptr, *ppart = nullptr;
+        if (s_bar) {
+            hip_check(hipMemsetAsync(s_bar, 0, t->nm * 8, st), "hipMemsetAsync");
+            ensure_pmode(t, st);
+            panel_tiles(t, st, ptiles, n_ptiles);
+            pwork = (double*)t->ws.get("b.pwork", (size_t)4 * 4 * L * S * 8);
+            ppart = (double*)t->ws.get("b.ppart", (size_t)std::max(1, n_ptiles) * t->nm * 8);
+        }
+        const StreamPlan pl2 = plan_for(t, 0, 2, 2, st);
+        double* rowp2 = (double*)t->ws.get("b.rowp", (size_t)2 * pl2.n_ct * S * 8);
+        double* colp2 = (double*)t->ws.get("b.colp", (size_t)2 * pl2.n_rt * S * 8);
         const int nseg = n_steps / L;
         for (int seg = nseg - 1; seg >= 0; --seg) {
             // replay the segment, keeping the four stage inputs of each step
             const double* cur = ckpts + (size_t)seg * S;
+            bool gathered = false;
             for (int j = 0; j < L; ++j) {
                 double* y1 = ys + ((size_t)j * 4) * S;
                 hip_check(hipMemcpyAsync(y1, cur, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-                rk4_step(t, y1, dt, fn, y1 + S, y1 + 2 * S, y1 + 3 * S, st);
+                rk4_step(t, y1, dt, fn, y1 + S, y1 + 2 * S, y1 + 3 * S, st, nullptr, gathered);
                 cur = fn;
             }
             for (int j = L - 1; j >= 0; --j) {
                 const double* Y[4];
-                for (int i = 0; i < 4; ++i) Y[i] = ys + ((size_t)j * 4 + i) * S;
-                // k4b = dt/6 a ; Y4b = J4^T k4b
-                lincomb(S, Lincomb{1, 0.0, {dt / 6.0}, {a}}, kbs[3], st);
-                collision_vjp_impl(t, Y[3], kbs[3], yb[3], nullptr, 1, st);
-                // k3b = dt/3 a + dt Y4b
-                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt}, {a, yb[3]}}, kbs[2], st);
-                collision_vjp_impl(t, Y[2], kbs[2], yb[2], nullptr, 1, st);
-                // k2b = dt/3 a + dt/2 Y3b
-                lincomb(S, Lincomb{2, 0.0, {dt / 3.0, dt / 2.0}, {a, yb[2]}}, kbs[1], st);
-                collision_vjp_impl(t, Y[1], kbs[1], yb[1], nullptr, 1, st);
-                // k1b = dt/6 a + dt/2 Y2b
-                lincomb(S, Lincomb{2, 0.0, {dt / 6.0, dt / 2.0}, {a, yb[1]}}, kbs[0], st);
-                collision_vjp_impl(t, Y[0], kbs[0], yb[0], nullptr, 1, st);
-                // s_bar += sum_i k_i_bar^T dI/ds at Y_i, the four stages two to a pass
-                if (s_bar) {
-                    const double* fs[4] = {Y[0], Y[1], Y[2], Y[3]};
-                    const double* ls[4] = {kbs[0], kbs[1], kbs[2], kbs[3]};
-                    mode_grad(t, 4, fs, ls, s_bar, 1, st);
+                double* kbs[4];
+                for (int i = 0; i < 4; ++i) {
+                    Y[i] = ys + ((size_t)j * 4 + i) * S;
+                    kbs[i] = kbp + ((size_t)j * 4 + i) * S;
                 }
-                // a <- a + Y1b + Y2b + Y3b + Y4b
-                lincomb(S, Lincomb{5, 0.0, {1.0, 1.0, 1.0, 1.0, 1.0}, {a, yb[0], yb[1], yb[2], yb[3]}}, a, st);
+                // k4b = dt/6 a ; Y4b = J4^T k4b
+                adjoint_stage(pl2, t->ld, t->d_p, Y[3], Lincomb{1, 0.0, {dt / 6.0}, {a}}, kbs[3], t->c, rowp2,
+                              colp2, yb[3], nullptr, nullptr, nullptr, nullptr, st);
+                // k3b = dt/3 a + dt Y4b
+                adjoint_stage(pl2, t->ld, t->d_p, Y[2], Lincomb{2, 0.0, {dt / 3.0, dt}, {a, yb[3]}}, kbs[2], t->c,
+                              rowp2, colp2, yb[2], nullptr, nullptr, nullptr, nullptr, st);
+                // k2b = dt/3 a + dt/2 Y3b
+                adjoint_stage(pl2, t->ld, t->d_p, Y[1], Lincomb{2, 0.0, {dt / 3.0, dt / 2.0}, {a, yb[2]}}, kbs[1],
+                              t->c, rowp2, colp2, yb[1], nullptr, nullptr, nullptr, nullptr, st);
+                // k1b = dt/6 a + dt/2 Y2b; then a <- a + Y1b + Y2b + Y3b + Y4b
+                adjoint_stage(pl2, t->ld, t->d_p, Y[0], Lincomb{2, 0.0, {dt / 6.0, dt / 2.0}, {a, yb[1]}}, kbs[0],
+                              t->c, rowp2, colp2, yb[0], a, yb[1], yb[2], yb[3], st);
+            }
+            // s_bar += sum over the segment's 4L stages of k_i_bar^T dI/ds at Y_i:
+            // one pass over each per-mode matrix for the whole segment
+            if (s_bar) {
+                StageTimer tm("mode_panel", st);
+                mode_panel(S, t->ld, 4 * L, t->nm, t->f32 ? 1 : 0, t->d_pmode, (long)S * t->ld,
+                           t->d_perm, ys, kbp, pwork, ptiles, n_ptiles, ppart, t->c, s_bar, 1, st);
             }
         }
         hip_check(hipMemcpyAsync(f0_bar, a, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");

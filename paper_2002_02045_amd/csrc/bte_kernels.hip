@@ -715,6 +715,183 @@ __global__ void k_fill(long n, double v, double* out) {
     if (i < n) out[i] = v;
 }
 
+// ---------------------------------------------------------------- mode-scale gradient over a panel of stages
+// For J stages (f_j, lam_j), the mode-scale gradient of the collision integral
+// summed over the stages is
+//   s_bar_nu = -c sum_j sum_st P^nu_st f_js (1 - f_jt)(lam_js - lam_jt)
+//            = -c sum_st P^nu_st M_st,   M = A B^T - C D^T,
+// with the rows a_j = f_j lam_j, c_j = f_j and the columns b_j = 1 - f_j,
+// d_j = lam_j (1 - f_j) (matrix order).  One pass forms M tile by tile (a
+// rank-2J product in FP64 registers) and reads every per-mode matrix once,
+// instead of one pass over each P^nu per stage.
+
+// A, B, C, D [J][S] in matrix order from f, lam [J][S] in state order
+__global__ void k_panel_gather(int S, int J, const int32_t* __restrict__ perm, const double* __restrict__ f,
+                               const double* __restrict__ lam, double* __restrict__ A, double* __restrict__ B,
+                               double* __restrict__ C, double* __restrict__ D) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)J * S) return;
+    const long j = t / S;
+    const int i = (int)(t % S);
+    const long src = j * S + perm[i];
+    const double fv = f[src], lv = lam[src];
+    A[t] = fv * lv;
+    B[t] = 1.0 - fv;
+    C[t] = fv;
+    D[t] = lv * (1.0 - fv);
+}
+
+constexpr int kPT = 128;   // panel tile: kPT x kPT entries per 256-thread workgroup
+constexpr int kPJ = 16;    // stages staged in LDS at a time (a multiple of 4)
+
+// One live tile per workgroup, M formed on the FP64 matrix cores: the K
+// dimension is the stage index, M = A B^T - C D^T as two 16 x 16 x 4 products
+// per block and four stages.  Wave w owns rows 64 (w / 2) + [0, 64) and
+// columns 64 (w % 2) + [0, 64) of the tile: 4 x 4 blocks of 16 x 16.  Operand
+// layout of v_mfma_f64_16x16x4f64: lane l gives A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it holds D[l / 16 + 4 v][l % 16], v = 0..3.
+// partial[tile][nu] = sum over the tile of P^nu_rc M_rc.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode_panel(int S, long ld, int J, int nm, const T* __restrict__ pm,
+                                                    long mat, const double* __restrict__ A,
+                                                    const double* __restrict__ B, const double* __restrict__ C,
+                                                    const double* __restrict__ D, const int32_t* __restrict__ tiles,
+                                                    double* __restrict__ partial) {
+    // the staged vectors [a, -c, b, d][stage][entry] while M is formed, then
+    // M itself [row][column] (FP64) for the contraction with the per-mode
+    // matrices, read in rows of 16-byte loads
+    __shared__ __attribute__((aligned(16))) double ms[kPT * kPT];
+    __shared__ double red[kMaxModes][256];
+    static_assert(4 * kPJ * kPT <= kPT * kPT, "staging space");
+    double* stg = ms;
+    const int tile = blockIdx.x;
+    const int r0 = tiles[2 * tile] * kPT, c0 = tiles[2 * tile + 1] * kPT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+    const int li = l & 15, lk = l >> 4;
+    f64x4 m[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) m[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // each chunk of kPJ stages goes global -> registers -> LDS; the next
+    // chunk's loads are issued before the current chunk's products
+    constexpr int kPer = kPJ * kPT / 256;
+    double q[4][kPer];
+    auto load = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int x = tid + 256 * u;
+            const int j = j0 + x / kPT, e = x % kPT;
+            const bool jr = j < J;
+            const int r = r0 + e, c = c0 + e;
+            q[0][u] = jr && r < S ? A[(long)j * S + r] : 0.0;
+            q[1][u] = jr && r < S ? -C[(long)j * S + r] : 0.0;
+            q[2][u] = jr && c < S ? B[(long)j * S + c] : 0.0;
+            q[3][u] = jr && c < S ? D[(long)j * S + c] : 0.0;
+        }
+    };
+    auto at = [&](int v, int jj, int e) -> double& { return stg[(v * kPJ + jj) * kPT + e]; };
+    load(0);
+    for (int j0 = 0; j0 < J; j0 += kPJ) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int x = tid + 256 * u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) at(v, x / kPT, x % kPT) = q[v][u];
+        }
+        __syncthreads();
+        if (j0 + kPJ < J) load(j0 + kPJ);
+#pragma unroll
+        for (int k4 = 0; k4 < kPJ; k4 += 4) {
+            double oa[4], oc[4], ob[4], od[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                oa[a] = at(0, k4 + lk, wr + 16 * a + li);
+                oc[a] = at(1, k4 + lk, wr + 16 * a + li);
+                ob[a] = at(2, k4 + lk, wc + 16 * a + li);
+                od[a] = at(3, k4 + lk, wc + 16 * a + li);
+            }
+            // the two updates of a block are 16 instructions apart
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) m[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[a], ob[b], m[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) m[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(oc[a], od[b], m[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // M into LDS, [row][column]
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) ms[(wr + 16 * a + lk + 4 * v) * kPT + wc + 16 * b + li] = m[a][b][v];
+    __syncthreads();
+    // sum P^nu_rc M_rc: thread t takes 4 consecutive columns 4 (t % 32) of the
+    // rows t / 32 + 8 i; a row of the tile is 32 lanes x 16 bytes (FP32)
+    double acc[kMaxModes];
+#pragma unroll
+    for (int nu = 0; nu < kMaxModes; ++nu) acc[nu] = 0.0;
+    const int cg = 4 * (tid & 31);
+    if (c0 + cg < S) {
+#pragma unroll 4
+        for (int i = 0; i < kPT / 8; ++i) {
+            const int rl = (tid >> 5) + 8 * i;
+            const int r = r0 + rl;
+            if (r >= S) break;
+            const double* mr = ms + rl * kPT + cg;
+            const double x0 = mr[0], x1 = mr[1], x2 = mr[2], x3 = mr[3];
+            const T* p = pm + (long)r * ld + c0 + cg;
+#pragma unroll
+            for (int nu = 0; nu < kMaxModes; ++nu)
+                if (nu < nm) {
+                    const T* pn = p + (long)nu * mat;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(pn);
+                        acc[nu] = fma((double)v.x, x0, fma((double)v.y, x1, fma((double)v.z, x2, fma((double)v.w, x3, acc[nu]))));
+                    } else {
+                        const double2 v0 = reinterpret_cast<const double2*>(pn)[0];
+                        const double2 v1 = reinterpret_cast<const double2*>(pn)[1];
+                        acc[nu] = fma(v0.x, x0, fma(v0.y, x1, fma(v1.x, x2, fma(v1.y, x3, acc[nu]))));
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int nu = 0; nu < kMaxModes; ++nu)
+        if (nu < nm) red[nu][tid] = acc[nu];
+    __syncthreads();
+    for (int x = 128; x >= 1; x >>= 1) {
+        if (tid < x)
+            for (int nu = 0; nu < nm; ++nu) red[nu][tid] += red[nu][tid + x];
+        __syncthreads();
+    }
+    if (tid < nm) partial[(long)tile * nm + tid] = red[tid][0];
+}
+
+// s_bar[nu] (=/+=) -c sum over tiles of partial[tile][nu], in tile order
+__global__ void k_mode_panel_finish(int n_tiles, int nm, const double* __restrict__ partial, double c,
+                                    double* __restrict__ sbar, int accumulate) {
+    __shared__ double red[256];
+    const int nu = blockIdx.x;
+    double a = 0.0;
+    for (int t = threadIdx.x; t < n_tiles; t += 256) a += partial[(long)t * nm + nu];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sbar[nu] = (accumulate ? sbar[nu] : 0.0) - c * red[0];
+}
+
 }  // namespace
 
 long table_ld(int S) { return ((long)S + 63) / 64 * 64; }
@@ -918,9 +1095,58 @@ __global__ void k_reduce_finish(CollisionFinish cf, const int32_t* __restrict__ 
                 rhs += cf.dc[d] * ((p >= 0 ? cf.f[p] : 0.0) - (m >= 0 ? cf.f[m] : 0.0));
             }
         }
-        cf.acc[s] = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * rhs;
-        if (cf.f_next) cf.f_next[s] = cf.f_base[s] + cf.a_next * rhs;
+        const double an = (cf.acc_init ? cf.f_base[s] : cf.acc[s]) + cf.w_acc * rhs;
+        cf.acc[s] = an;
+        const double fn = cf.f_next ? cf.f_base[s] + cf.a_next * rhs : 0.0;
+        if (cf.f_next) cf.f_next[s] = fn;
+        if (cf.gnext) {
+            const double v = cf.gnext_acc ? an : fn;
+            cf.gnext[i] = 1.0 - v;
+            cf.gnext[(long)cf.S + i] = v;
+        }
     }
+}
+
+// Reverse-RK4 stage, before the pass: lam = c0 + sum_k c_k v_k (state order,
+// into lam_out) and the 2+2 pass's vectors in matrix order.
+__global__ void k_adj_prep(int S, const int32_t* __restrict__ perm, Lincomb lc, const double* __restrict__ Y,
+                           double* __restrict__ lam_out, double* __restrict__ gbuf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const int s = perm[i];
+    double lam = lc.c0;
+    for (int k = 0; k < lc.n; ++k) lam += lc.c[k] * lc.v[k][s];
+    lam_out[s] = lam;
+    const double f = Y[s];
+    gbuf[i] = 1.0 - f;
+    gbuf[(long)S + i] = lam * (1.0 - f);
+    gbuf[2L * S + i] = f;
+    gbuf[3L * S + i] = lam * f;
+}
+
+// ... and after it: ybar_s = -c (lam_s (R0 + C0) - C1 - R1) from the unreduced
+// partials (rows P(1-f), P(lam(1-f)); columns P^T f, P^T(lam f)); with a_acc,
+// a_s += ybar_s + yb1_s + yb2_s + yb3_s.
+__global__ void k_adj_finish(int S, const int32_t* __restrict__ perm, int n_ct, int n_rt,
+                             const double* __restrict__ rowp, const double* __restrict__ colp,
+                             const double* __restrict__ lam, double c, double* __restrict__ ybar,
+                             double* __restrict__ a_acc, const double* __restrict__ yb1,
+                             const double* __restrict__ yb2, const double* __restrict__ yb3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const int s = perm[i];
+    double r0 = 0.0, r1 = 0.0, c0 = 0.0, c1 = 0.0;
+    for (int ct = 0; ct < n_ct; ++ct) {
+        r0 += rowp[(long)ct * S + i];
+        r1 += rowp[((long)n_ct + ct) * S + i];
+    }
+    for (int rt = 0; rt < n_rt; ++rt) {
+        c0 += colp[(long)rt * S + i];
+        c1 += colp[((long)n_rt + rt) * S + i];
+    }
+    const double y = -c * (lam[s] * (r0 + c0) - c1 - r1);
+    ybar[s] = y;
+    if (a_acc) a_acc[s] = a_acc[s] + y + yb1[s] + yb2[s] + yb3[s];
 }
 
 // rout[a][perm[i]] = sum_ct rowp[a][ct][i], cout[b][perm[i]] = sum_rt colp[b][rt][i]
@@ -1011,6 +1237,21 @@ void reduce_finish(const StreamPlan& pl, const CollisionFinish& cf, hipStream_t 
     check_launch("reduce_finish");
 }
 
+void adjoint_stage(const StreamPlan& pl, long ld, const void* P, const double* Y, const Lincomb& lc, double* lam_out,
+                   double c, double* rowp, double* colp, double* ybar, double* a_acc, const double* yb1,
+                   const double* yb2, const double* yb3, hipStream_t st) {
+    const int S = pl.S;
+    if (S <= 0) return;
+    if (pl.na != 2 || pl.nb != 2 || !pl.perm || !pl.gbuf) throw Error{-1, "adjoint_stage: needs a 2+2 plan"};
+    if (a_acc && !(yb1 && yb2 && yb3)) throw Error{-1, "adjoint_stage: accumulation needs the other stages"};
+    hipLaunchKernelGGL(k_adj_prep, dim3((S + 255) / 256), dim3(256), 0, st, S, pl.perm, lc, Y, lam_out, pl.gbuf);
+    check_launch("adj_prep");
+    stream_run(pl, ld, P, rowp, colp, st);
+    hipLaunchKernelGGL(k_adj_finish, dim3((S + 255) / 256), dim3(256), 0, st, S, pl.perm, pl.n_ct, pl.n_rt, rowp, colp,
+                       lam_out, c, ybar, a_acc, yb1, yb2, yb3);
+    check_launch("adj_finish");
+}
+
 void vjp_finish(int S, int n_ct, int n_rt, const double* rowp, const double* colp, const double* lam, double c,
                 double* fbar, hipStream_t st) {
     hipLaunchKernelGGL(k_vjp_finish, dim3((S + 255) / 256), dim3(256), 0, st, S, n_ct, n_rt, rowp, colp, lam, c, fbar);
@@ -1091,6 +1332,50 @@ void axpy_copy(int S, const double* x, double a, const double* y, double* out, h
 void lincomb(int S, const Lincomb& lc, double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_lincomb, dim3((S + 255) / 256), dim3(256), 0, st, S, lc, out);
     check_launch("lincomb");
+}
+
+int mode_panel_tile() { return kPT; }
+
+void mode_panel_tiles(const std::vector<double>& esort, double half_width, std::vector<int32_t>& tiles) {
+    const int S = (int)esort.size();
+    const int nt = (S + kPT - 1) / kPT;
+    tiles.clear();
+    for (int rt = 0; rt < nt; ++rt)
+        for (int ct = 0; ct < nt; ++ct) {
+            const int r0 = rt * kPT, r1 = std::min(S, r0 + kPT);
+            const int c0 = ct * kPT, c1 = std::min(S, c0 + kPT);
+            // every entry of a tile whose energies differ everywhere by more than
+            // the band's half-width is zero in every per-mode matrix
+            const double gap = std::max(esort[c0] - esort[r1 - 1], esort[r0] - esort[c1 - 1]);
+            if (gap > half_width) continue;
+            tiles.push_back(rt);
+            tiles.push_back(ct);
+        }
+}
+
+void mode_panel(int S, long ld, int J, int nm, int f32, const void* pm, long mat_elems, const int32_t* perm,
+                const double* f, const double* lam, double* work, const int32_t* tiles, int n_tiles,
+                double* partial, double c, double* sbar, int accumulate, hipStream_t st) {
+    if (S <= 0 || J <= 0 || nm > kMaxModes) throw Error{-1, "mode_panel: bad sizes"};
+    double* A = work;
+    double* B = A + (long)J * S;
+    double* C = B + (long)J * S;
+    double* D = C + (long)J * S;
+    const long n = (long)J * S;
+    hipLaunchKernelGGL(k_panel_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, J, perm, f, lam, A, B,
+                       C, D);
+    check_launch("panel_gather");
+    if (n_tiles > 0) {
+        if (f32)
+            hipLaunchKernelGGL(k_mode_panel<float>, dim3(n_tiles), dim3(256), 0, st, S, ld, J, nm, (const float*)pm,
+                               mat_elems, A, B, C, D, tiles, partial);
+        else
+            hipLaunchKernelGGL(k_mode_panel<double>, dim3(n_tiles), dim3(256), 0, st, S, ld, J, nm, (const double*)pm,
+                               mat_elems, A, B, C, D, tiles, partial);
+        check_launch("mode_panel");
+    }
+    hipLaunchKernelGGL(k_mode_panel_finish, dim3(nm), dim3(256), 0, st, n_tiles, nm, partial, c, sbar, accumulate);
+    check_launch("mode_panel_finish");
 }
 
 void occ_vectors(int S, const double* f, const double* lam, double* o0, double* o1, double* o2, hipStream_t st) {

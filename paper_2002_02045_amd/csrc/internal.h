@@ -382,6 +382,10 @@ struct CollisionFinish {
     // dc[i] = (|e|/hbar)(E . a_i)/(2 pi) (N_i/2); nbr nullptr = no field
     const int32_t* nbr;
     double dc[3];
+    // with gnext: the next pass's occupations gathered to matrix order
+    // ([2][S]: 1 - v, v), v = the updated acc (gnext_acc) or f_next
+    double* gnext;
+    int gnext_acc;
 };
 // The collision pass of a 1+1 plan without the separate occupation, gather and
 // reduction kernels: gather_occupations fills the plan's gather buffer with
@@ -412,7 +416,27 @@ struct Lincomb {
     const double* v[5];
 };
 void lincomb(int S, const Lincomb& lc, double* out, hipStream_t st);
+// One stage of the reverse RK4 as three launches: prep forms lam = lincomb(lc)
+// (state order, into lam_out) and the 2+2 pass's vectors of Y in matrix order
+// (pl.gbuf: 1 - f, lam (1 - f), f, lam f); the stream; finish reduces the
+// partials and writes ybar = lam^T dI/dY (state order) and, with a_acc,
+// a += ybar + yb1 + yb2 + yb3.
+void adjoint_stage(const StreamPlan& pl, long ld, const void* P, const double* Y, const Lincomb& lc, double* lam_out,
+                   double c, double* rowp, double* colp, double* ybar, double* a_acc, const double* yb1,
+                   const double* yb2, const double* yb3, hipStream_t st);
 void occ_vectors(int S, const double* f, const double* lam, double* o0, double* o1, double* o2, hipStream_t st);
+// Mode-scale gradient of the collision integral summed over J stages (f_j,
+// lam_j), f and lam [J][S] in state order:
+//   sbar[nu] (=/+=) -c sum_j sum_st P^nu_st f_js (1 - f_jt)(lam_js - lam_jt)
+// over the live kPT x kPT tiles (tiles [n_tiles][2] = (row tile, column tile)
+// of the matrices in energy order, perm as for the stream); pm holds the nm
+// per-mode matrices [S][ld] of element type float (f32) or double, mat_elems
+// apart.  work: 4 J S doubles; partial: n_tiles * nm doubles.
+int mode_panel_tile();
+void mode_panel_tiles(const std::vector<double>& esort, double half_width, std::vector<int32_t>& tiles);
+void mode_panel(int S, long ld, int J, int nm, int f32, const void* pm, long mat_elems, const int32_t* perm,
+                const double* f, const double* lam, double* work, const int32_t* tiles, int n_tiles,
+                double* partial, double c, double* sbar, int accumulate, hipStream_t st);
 void axpy_copy(int S, const double* x, double a, const double* y, double* out, hipStream_t st);
 void fill(long n, double v, double* out, hipStream_t st);
 
