@@ -451,8 +451,16 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
                 } else if (om > e.omega_cut) {
                     const double nb = s_nb[nu];
                     const T x1 = (T)(en[t] - om - em) * is, x2 = (T)(en[t] + om - em) * is;
-                    const T d_em = x1 * x1 > (T)200 ? (T)0 : nrm * exp(-x1 * x1);
-                    const T d_ab = x2 * x2 > (T)200 ? (T)0 : nrm * exp(-x2 * x2);
+                    const T y1 = x1 * x1, y2 = x2 * x2;
+                    T d_em, d_ab;
+                    if constexpr (sizeof(T) == 4) {
+                        // exp(-y) = 2^(-y log2 e) on the hardware exp2 (FP32 paths)
+                        d_em = y1 > (T)200 ? (T)0 : nrm * __builtin_amdgcn_exp2f(-y1 * 1.4426950408889634f);
+                        d_ab = y2 > (T)200 ? (T)0 : nrm * __builtin_amdgcn_exp2f(-y2 * 1.4426950408889634f);
+                    } else {
+                        d_em = y1 > (T)200 ? (T)0 : nrm * exp(-y1);
+                        d_ab = y2 > (T)200 ? (T)0 : nrm * exp(-y2);
+                    }
                     acc[t][nu] += wq * (double)g2 * ((double)d_em * (1.0 + nb - fm) + (double)d_ab * (nb + fm));
                 }
             }
