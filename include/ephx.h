@@ -205,6 +205,33 @@ int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red,
                const double* q_red, const double* q_w, int precision, double* gamma,
                double* gamma_mode, void* stream);
 
+/* Parts of |g|^2 for the rates of polar models (Eq. e_ph_long): the
+ * long-range coupling alone, g_L = sqrt(hbar/2 omega) sum_{kappa a} e/sqrt(M)
+ * C^{kappa a}(q) [U^dag(k+q) U(k)]_mn, or what remains of |g|^2 without it. */
+#define EPHX_PART_FULL 0
+#define EPHX_PART_POLAR 1   /* |g_L|^2 */
+#define EPHX_PART_RMPOL 2   /* |g|^2 - |g_L|^2 */
+
+/* ephx_rates with |g|^2 replaced by one of the parts above (EPHX_PART_FULL
+ * is ephx_rates).  The rates are linear in |g|^2, so the two parts add up to
+ * the full rates on any q set.  EPHX_EINVAL for a part other than FULL on a
+ * model without the Froehlich term; EPHX_EUNSUPPORTED above nw = 16 or 12
+ * modes. */
+int ephx_rates_part(ephx_model* m, const ephx_params* p, int part, int nk, const double* k_red, int nq,
+                    const double* q_red, const double* q_w, int precision, double* gamma, double* gamma_mode,
+                    void* stream);
+
+/* Polar split of the q sum (Sec. 4.3 and 5.2: small-q polar scattering is
+ * sampled best from a distribution peaked at Gamma, the rest uniformly):
+ *   Gamma = sum_{q in set u} w_u(q) Gamma_rmpol(q) + sum_{q in set c} w_c(q) Gamma_polar(q),
+ * each part estimated with its own q set and weights (device arrays as for
+ * ephx_rates: q [n][3], w [n] or NULL for 1/n), e.g. uniform points for the
+ * first and Cauchy points with weights 1/(n p(q)) for the second.  gamma,
+ * gamma_mode as for ephx_rates.  Needs a polar model (else EPHX_EINVAL). */
+int ephx_rates_polar_split(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq_u,
+                           const double* q_u, const double* w_u, int nq_c, const double* q_c,
+                           const double* w_c, int precision, double* gamma, double* gamma_mode, void* stream);
+
 /* Adjoint of ephx_rates with respect to the coupling tensor (FP64): for
  * L = sum_nk gamma_bar[n][k] Gamma_nk (gamma_bar device [nk][nw]), writes
  * g_bar = dL/dRe g(Re,Rp) + i dL/dIm g(Re,Rp), device complex128 with the

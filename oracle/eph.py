@@ -9,6 +9,7 @@ Array layouts (shared with the library only as a documented convention):
 """
 from __future__ import annotations
 
+import copy
 import math
 
 import torch
@@ -153,21 +154,39 @@ def g_abs_modes(g2v):
 
 
 def rates(model, k, q, *, temp, mu, sigma, omega_cut=1e-4, q_weights=None,
-          polar=None, chunk=64):
+          polar=None, chunk=64, part="full"):
     """Scattering rates (Eq. scatter_rate with W of Eq. BTE_W), in 1/fs:
 
       Gamma_nk = sum_q w_q sum_{m,nu} (2 pi/hbar) |g_mn,nu(k,q)|^2
                  [ delta(eps_nk - hw - eps_mk+q)(1 + N - f_m) + delta(eps_nk + hw - eps_mk+q)(N + f_m) ]
 
-    w_q = 1/N_q unless given.  Returns (gamma (nk,nw), gamma_mode (nk,nw,nm))."""
+    w_q = 1/N_q unless given.  Returns (gamma (nk,nw), gamma_mode (nk,nw,nm)).
+
+    part (polar models): "full" uses |g|^2; "polar" the long-range coupling
+    alone, |g_L|^2, with g_L the Froehlich term of Eq. e_ph_long taken through
+    the same rotation and mode projection (the pipeline with g(Re,Rp) = 0);
+    "rmpol" the rest, |g|^2 - |g_L|^2.  The rates are linear in |g|^2, so the
+    two parts add up to the full rates for any q set, and each part's q sum
+    can be estimated with its own sampling (the polar split of Sec. 5.2)."""
+    if part not in ("full", "polar", "rmpol"):
+        raise ValueError("part must be full, polar or rmpol")
+    if part != "full" and polar is None:
+        raise ValueError("the polar and rmpol parts need a polar model")
     k, q = t64(k), t64(q)
     nq = q.shape[0]
     w = torch.full((nq,), 1.0 / nq, dtype=F64) if q_weights is None else t64(q_weights)
     nk, nw, nm = k.shape[0], model.nw, model.nmodes
     gmode = torch.zeros((nk, nw, nm), dtype=F64)
+    m_lr = None
+    if part != "full":
+        m_lr = copy.copy(model)
+        m_lr.g = torch.zeros_like(torch.as_tensor(model.g, dtype=C128))
     for s in range(0, nq, chunk):
         blk = eph_pipeline(model, k, q[s:s + chunk], polar, omega_cut)
         gg = blk["g"].abs() ** 2                                  # (k,q,nu,m,n)
+        if part != "full":
+            gl = eph_pipeline(m_lr, k, q[s:s + chunk], polar, omega_cut)["g"].abs() ** 2
+            gg = gl if part == "polar" else gg - gl
         om = blk["omega"]                                         # (q,nu)
         nb = bose(om, temp, omega_cut)
         fm = fermi(blk["eps_kq"], mu, temp)                       # (k,q,m)

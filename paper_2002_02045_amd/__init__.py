@@ -8,7 +8,8 @@ The compiled library is loaded on first use of any public name (so that
 without a built libephx.so raises ImportError.
 """
 _PUBLIC = ("FP32", "FP64", "BF16X3", "BF16X6", "FP16X3", "EphxError", "Model", "PairTable", "Params",
-           "bands", "gkq", "gkq_pairs", "grid_states", "phonons", "rates", "rates_vjp", "RatesFunction",
+           "bands", "gkq", "gkq_pairs", "grid_states", "phonons", "rates", "rates_part", "rates_polar_split",
+           "rates_vjp", "RatesFunction",
            "MobilityFunction", "timer_enable", "timer_reset", "timer_get", "workspace_query")
 
 

@@ -67,6 +67,8 @@ _SIGS = {
     "ephx_gkq": ([_P, _I, _P, _I, _P, _I, _D, _P, _P], _I),
     "ephx_rates": ([_P, _P, _I, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "ephx_rates_vjp": ([_P, _P, _I, _P, _I, _P, _P, _P, _P, _P], _I),
+    "ephx_rates_part": ([_P, _P, _I, _I, _P, _I, _P, _P, _I, _P, _P, _P], _I),
+    "ephx_rates_polar_split": ([_P, _P, _I, _P, _I, _P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "ephx_grid_states": ([_P, _P, _I, _I, _I, _D, _D, _I, _I, _P, _P, _P, _P, _P], _I),
     "ephx_table_create": ([_P, _P, _I, _P, _P, _I, _D, _P, _P], _I),
     "ephx_table_destroy": ([_P], _I),

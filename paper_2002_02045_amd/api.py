@@ -178,6 +178,41 @@ def rates(model, k, q, params, precision="fp64", q_weights=None, mode_resolved=T
     return gam, gmode
 
 
+PARTS = {"full": 0, "polar": 1, "rmpol": 2}
+
+
+def rates_part(model, k, q, params, part, precision="fp64", q_weights=None, mode_resolved=True):
+    """Rates of the long-range part |g_L|^2 ("polar") or of the rest
+    |g|^2 - |g_L|^2 ("rmpol"), or of all of it ("full"), as for rates()."""
+    p = _prec(precision)
+    kt, qt = _pts(k), _pts(q)
+    nk = kt.shape[0]
+    gam = torch.empty((nk, model.nw), dtype=F64, device="cuda")
+    gmode = torch.empty((nk, model.nw, model.nmodes), dtype=F64, device="cuda") if mode_resolved else None
+    qw = None if q_weights is None else torch.as_tensor(q_weights, dtype=F64, device="cuda").contiguous()
+    pc = params.c()
+    check(lib.ephx_rates_part(model.handle, C.byref(pc), PARTS[part], nk, ptr(kt), qt.shape[0], ptr(qt), ptr(qw), p,
+                              ptr(gam), ptr(gmode), stream_ptr()))
+    return gam, gmode
+
+
+def rates_polar_split(model, k, q_uniform, q_cauchy, params, precision="fp64", w_uniform=None, w_cauchy=None,
+                      mode_resolved=True):
+    """Polar split of the q sum: the rest |g|^2 - |g_L|^2 over q_uniform (weights
+    w_uniform or 1/n) plus the long-range part over q_cauchy (weights w_cauchy)."""
+    p = _prec(precision)
+    kt, qu, qc = _pts(k), _pts(q_uniform), _pts(q_cauchy)
+    nk = kt.shape[0]
+    gam = torch.empty((nk, model.nw), dtype=F64, device="cuda")
+    gmode = torch.empty((nk, model.nw, model.nmodes), dtype=F64, device="cuda") if mode_resolved else None
+    wu = None if w_uniform is None else torch.as_tensor(w_uniform, dtype=F64, device="cuda").contiguous()
+    wc = None if w_cauchy is None else torch.as_tensor(w_cauchy, dtype=F64, device="cuda").contiguous()
+    pc = params.c()
+    check(lib.ephx_rates_polar_split(model.handle, C.byref(pc), nk, ptr(kt), qu.shape[0], ptr(qu), ptr(wu),
+                                     qc.shape[0], ptr(qc), ptr(wc), p, ptr(gam), ptr(gmode), stream_ptr()))
+    return gam, gmode
+
+
 def rates_vjp(model, k, q, params, gamma_bar, q_weights=None):
     """dL/dg(Re,Rp) (complex128, layout of the model's g) for L = sum gamma_bar * Gamma."""
     kt, qt = _pts(k), _pts(q)

@@ -426,9 +426,9 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
                     for (int i = 0; i < nw; ++i) cjfma(a, s_u[i * nw + m], s_gw[(x * nw + i) * nw + n]);
                 gh[x] = a;
             }
+            cx<T> ov = {0, 0};
             if (e.lr != nullptr) {
                 // Wannier-gauge long-range term C(q) delta_ij, rotated: C(q) [U^dag(k+q) U(k)]_mn
-                cx<T> ov = {0, 0};
                 const double* ukz = e.uk + (long)z * nw2 * 2;
                 for (int i = 0; i < nw; ++i) cjfma(ov, s_u[i * nw + m], ldd<T>(ukz, (long)i * nw + n));
 #pragma unroll
@@ -444,7 +444,16 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 #pragma unroll
                 for (int x = 0; x < MM; ++x)
                     if (x < nm) cfma(g, s_es[x * nm + nu], gh[x]);
-                const T g2 = g.x * g.x + g.y * g.y;
+                T g2 = g.x * g.x + g.y * g.y;
+                if (RATES && e.part != 0) {
+                    // long-range coupling alone: g_L = (sum_x es[x][nu] C_x(q)) [U^dag(k+q) U(k)]_mn
+                    cx<T> l = {0, 0};
+#pragma unroll
+                    for (int x = 0; x < MM; ++x)
+                        if (x < nm) cfma(l, s_es[x * nm + nu], ldd<T>(e.lr, qg * nm + x));
+                    const T gl2 = (l.x * l.x + l.y * l.y) * (ov.x * ov.x + ov.y * ov.y);
+                    g2 = e.part == 1 ? gl2 : g2 - gl2;
+                }
                 if (!RATES) {
                     const long off = ((((long)(e.k_off + z) * e.nq_total + qg) * nm + nu) * nw + m) * nw + n;
                     reinterpret_cast<T*>(e.g2)[off] = om > e.omega_cut ? g2 : (T)0;
@@ -745,6 +754,19 @@ void eph_adjoint_epilogue(const EphEpilogue& e, const double* lam, double* gw_ba
     if (lds > 65536) throw Error{-6, "rates_vjp: nw^2 * 3nat too large for one workgroup's staging buffer"};
     hipLaunchKernelGGL(k_eph_adjoint, grid, dim3(64), lds, st, e, lam, gw_bar);
     check_launch("eph_adjoint_epilogue");
+}
+
+namespace {
+__global__ void k_add_into(long n, const double* __restrict__ src, double* __restrict__ dst) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] += src[t];
+}
+}  // namespace
+
+void add_into(long n, const double* src, double* dst, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, src, dst);
+    check_launch("add_into");
 }
 
 void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t st) {

@@ -653,7 +653,7 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
 
 void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q, int precision,
                 double omega_cut, void* g2, const ephx_params* p, const double* qw, double* gamma,
-                double* gmode, hipStream_t st) {
+                double* gmode, hipStream_t st, int part = 0) {
     const DriverPlan dp = driver_plan(m, nk, nq, precision);
     const int nw = dp.nw, nm = dp.nm, nw2 = dp.nw2;
     const long ngcol = dp.ngcol;
@@ -861,6 +861,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
                 e.uniform_w = 1.0 / nq;
                 e.partial = partial;
                 e.nblk = eph_epilogue_blocks(nqc);
+                e.part = part;
                 eph_epilogue_rates(e, f32 ? 1 : 0, st);
                 rates_reduce(nb, e.nblk, nw, nm, partial, acc, st);
             }
@@ -1139,8 +1140,20 @@ extern "C" int ephx_workspace_query(ephx_model* m, int call, int nk, int nq, int
 extern "C" int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq,
                           const double* q_red, const double* q_w, int precision, double* gamma, double* gamma_mode,
                           void* stream) {
+    return ephx_rates_part(m, p, EPHX_PART_FULL, nk, k_red, nq, q_red, q_w, precision, gamma, gamma_mode, stream);
+}
+
+extern "C" int ephx_rates_part(ephx_model* m, const ephx_params* p, int part, int nk, const double* k_red, int nq,
+                               const double* q_red, const double* q_w, int precision, double* gamma,
+                               double* gamma_mode, void* stream) {
     return guarded([&] {
         require(m != nullptr && p != nullptr, "rates: null argument");
+        require(part == EPHX_PART_FULL || part == EPHX_PART_POLAR || part == EPHX_PART_RMPOL,
+                "rates: part must be EPHX_PART_FULL, EPHX_PART_POLAR or EPHX_PART_RMPOL");
+        require(part == EPHX_PART_FULL || m->polar, "rates: the polar and rmpol parts need a polar model");
+        if (part != EPHX_PART_FULL && is_wide(m))
+            throw Error{EPHX_EUNSUPPORTED, "rates: the polar and rmpol parts are not built for nw > 16 or more than "
+                                           "12 modes"};
         require(nk >= 0 && nq >= 0, "rates: negative size");
         require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
                 "rates: need temp > 0, sigma > 0, finite mu and omega_cut");
@@ -1156,6 +1169,32 @@ extern "C" int ephx_rates(ephx_model* m, const ephx_params* p, int nk, const dou
         }
         require(q_red != nullptr, "rates: null q array");
         eph_driver(m, nk, k_red, nq, q_red, precision, p->omega_cut, nullptr, p, q_w, gamma, gamma_mode,
-                   (hipStream_t)stream);
+                   (hipStream_t)stream, part);
+    });
+}
+
+extern "C" int ephx_rates_polar_split(ephx_model* m, const ephx_params* p, int nk, const double* k_red, int nq_u,
+                                      const double* q_u, const double* w_u, int nq_c, const double* q_c,
+                                      const double* w_c, int precision, double* gamma, double* gamma_mode,
+                                      void* stream) {
+    return guarded([&] {
+        require(m != nullptr && p != nullptr, "rates_polar_split: null argument");
+        require(m->polar, "rates_polar_split: needs a polar model");
+        require(nk >= 0 && nq_u >= 0 && nq_c >= 0, "rates_polar_split: negative size");
+        if (nk == 0) return;
+        require(k_red && gamma, "rates_polar_split: null array");
+        hipStream_t st = (hipStream_t)stream;
+        // the long-range part on the second q set into work buffers, then the rest
+        // on the first set into the outputs, then the sum
+        double* g2 = (double*)m->ws.get("split.g", (size_t)nk * m->nw * 8);
+        double* gm2 = gamma_mode ? (double*)m->ws.get("split.gm", (size_t)nk * m->nw * m->nm * 8) : nullptr;
+        auto check = [](int rc) {
+            if (rc != EPHX_OK) throw Error{rc, std::string("rates_polar_split: ") + g_last_error};
+        };
+        check(ephx_rates_part(m, p, EPHX_PART_POLAR, nk, k_red, nq_c, q_c, w_c, precision, g2, gm2, stream));
+        check(ephx_rates_part(m, p, EPHX_PART_RMPOL, nk, k_red, nq_u, q_u, w_u, precision, gamma, gamma_mode,
+                              stream));
+        add_into((long)nk * m->nw, g2, gamma, st);
+        if (gamma_mode) add_into((long)nk * m->nw * m->nm, gm2, gamma_mode, st);
     });
 }

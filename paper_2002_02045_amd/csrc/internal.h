@@ -123,6 +123,8 @@ void convert_f64_f32(long count, const double* in, float* out, hipStream_t st);
 // an entry is not finite (out cleared first)
 void g_row_bound(int n_re, long rows, int nw, const double* g, const double* w, long rows_per_rp, int n_rp,
                  unsigned long long* out, hipStream_t st);
+// dst[i] += src[i], i < n
+void add_into(long n, const double* src, double* dst, hipStream_t st);
 // data[r][c] *= w[r] for complex data [rows][cols]
 void scale_rows(long rows, long cols, const double* w, double* data, hipStream_t st);
 // out(z)[p][x][i][j] = sum_n g'(z)[p][x][i][n] conj(U(z)[j][n])   (adjoint of apply_u_right)
@@ -160,6 +162,9 @@ struct EphEpilogue {
     double uniform_w;
     double* partial;     // [nkb][nblk][nw][nm]
     int nblk;
+    // rates of a part of |g|^2 (polar models): 0 all of it, 1 the long-range
+    // coupling alone |g_L|^2, 2 the rest |g|^2 - |g_L|^2
+    int part;
 };
 void eph_epilogue_g2(const EphEpilogue& e, int f32, hipStream_t st);
 // The per-q mode factors (esq, nbq) of the chunk, and with fkq != nullptr the

@@ -348,3 +348,34 @@ def test_atom_relabelling_leaves_coupling_unchanged(long_range_only):
             c0 = eph.frohlich(m, q, **pol)
             c1 = eph.frohlich(mr, q, **pol)
             assert not torch.allclose(c0, c1, atol=1e-6 * float(c0.abs().max()))
+
+
+# --------------------------------------------------------------- polar split
+
+def test_polar_split_parts_add_up_and_reduce_correctly():
+    """The rates are linear in |g|^2: the long-range part and the remainder
+    add up to the full rates for the same q set (each weighted sum of the
+    polar split estimates its own part).  The long-range part equals the full
+    rates of the model with g(Re,Rp) = 0; on a model without Born charges'
+    effect (Z* = 0) it vanishes and the remainder is the full rate."""
+    m, pol = _polar_model()
+    k = synth.random_points(95, 3)
+    q = synth.random_points(96, 40)
+    par = dict(temp=300.0, mu=0.0, sigma=0.06, polar=pol)
+    full, fm = eph.rates(m, k, q, **par)
+    lr, lm = eph.rates(m, k, q, part="polar", **par)
+    rest, rm = eph.rates(m, k, q, part="rmpol", **par)
+    assert float(full.max()) > 0 and float(lr.max()) > 0
+    assert torch.allclose(lr + rest, full, rtol=1e-12, atol=1e-14 * float(full.max()))
+    assert torch.allclose(lm + rm, fm, rtol=1e-12, atol=1e-14 * float(fm.max()))
+    m0 = copy.deepcopy(m)
+    m0.g[:] = 0
+    lr0, _ = eph.rates(m0, k, q, **par)
+    assert torch.allclose(lr, lr0, rtol=1e-13)
+    mz = copy.deepcopy(m)
+    mz.zstar = 0.0 * m.zstar
+    lz, _ = eph.rates(mz, k, q, part="polar", **par)
+    fz, _ = eph.rates(mz, k, q, **par)
+    rz, _ = eph.rates(mz, k, q, part="rmpol", **par)
+    assert float(lz.abs().max()) == 0.0
+    assert torch.allclose(rz, fz, rtol=1e-14)
