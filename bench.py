@@ -42,7 +42,7 @@ def _parse():
                     help="skip the RK4 backward and the mobility adjoint legs (e.g. under hardware counters)")
     ap.add_argument("--gaas-grid", type=int, default=100, help="k = q grid of the GaAs-like transport leg (0: skip)")
     ap.add_argument("--cell-k", type=int, default=32, help="k points of the large-cell slice (0: skip)")
-    ap.add_argument("--cell-q", type=int, default=512, help="q points of the large-cell slice")
+    ap.add_argument("--cell-q", type=int, default=4096, help="q points of the large-cell slice")
     return ap.parse_args()
 
 
@@ -578,26 +578,30 @@ def gaas_fd_check(px, dm, m, cfg, par, grid):
 
 def cell_bench(px, args):
     """Large cell (40 atoms, 120 modes, 64 Wannier functions, simple-cubic
-    10 Angstrom cell, 3^3 real-space sets): scattering rates on a slice of
-    k points in the 0.3 eV window above the CBM against random q, per
-    precision, with the stage split and the MFMA rates of the Rp contraction
-    and of the batched rotation + projection GEMMs."""
+    10 Angstrom cell) on its named 6^3 real-space sets: 216 Re x 216 Rp, so
+    g(Re,Rp) has 2.3e10 complex entries (183 GB as complex float), drawn on the
+    device by the counter scheme.  Scattering rates on a slice of k points in
+    the 0.3 eV window above the CBM against random q, per precision, with the
+    stage split and the MFMA rates of the Rp contraction and of the batched
+    rotation + projection GEMMs.  The adjoint w.r.t. g(Re,Rp) would need the
+    gradient (367 GB in complex128) beside g on one GPU; it is timed on the
+    3^3 sets (27 x 27, uploaded g)."""
     import torch
 
     import synth
     cfg = synth.CONFIGS["cell"]
     t0 = time.perf_counter()
-    m = synth.make_config_model("cell")
+    m, env, seed = synth.make_counter_model("cell", n_grid=6, full=False)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    dm = px.Model(m)
+    dm = px.Model(m, drawn=(seed, env))
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t0
     nw, nm, n_rp, n_re = m.nw, m.nmodes, len(m.rp_g), len(m.re_g)
     fl_rp = rp_flops_per_pair(m.rp_g, nw, nm)
-    log("large cell: nw=%d modes=%d Re=%d Rp=%d, g(Re,Rp) %.1f GB; generated %.1fs, loaded %.1fs"
-        % (nw, nm, n_re, n_rp, m.g.nbytes / 1e9, t_gen, t_load))
-    del m
+    g_bytes = n_re * n_rp * nm * nw * nw * 8
+    log("large cell: nw=%d modes=%d Re=%d Rp=%d, g(Re,Rp) %.1f GB complex float drawn on the device; host part "
+        "%.1fs, model with draws %.1fs" % (nw, nm, n_re, n_rp, g_bytes / 1e9, t_gen, t_load))
     cb = nw // 2
     cand = synth.random_points(cfg["seed"] + 100, 20_000)
     ec, _, _ = px.bands(dm, cand, want_u=False)
@@ -639,8 +643,32 @@ def cell_bench(px, args):
         got = group_sums(px, dm, ke, qe, px.gkq(dm, ke, qe, precision=prec).double())
         res[prec]["g2_err_vs_fp64"] = float(((got - ref).abs().flatten(2).max(dim=2).values
                                              / bmax.clamp_min(1e-300)).max())
-    # adjoint of the rates w.r.t. g(Re,Rp) (FP64) on a slice: 4 k x 64 q
-    ka, qa = ks[:4], qd[:64]
+    dm.close()
+    del dm
+    torch.cuda.empty_cache()
+    adj = cell_adjoint_bench(px, cfg, ks, q, par)
+    return {
+        "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, large cell)",
+        "config": {"workload": "large cell: 40 atoms (120 modes), Nw=64, simple cubic a=10 A, %d Re x %d Rp "
+                               "(6^3 sets, g drawn on the device, %.0f GB complex float), %d window k x %d random q, "
+                               "T=300 K, sigma=5 meV" % (n_re, n_rp, g_bytes / 1e9, len(ks), len(q))},
+        "flops_per_pair": {"rp_contraction": fl_rp, "rotation_projection": fl_ep},
+        "by_precision": res,
+        "rates_adjoint_fp64": adj,
+    }
+
+
+def cell_adjoint_bench(px, cfg, ks, q, par):
+    """Adjoint of the rates w.r.t. g(Re,Rp) (FP64) on the large cell's 3^3 sets
+    (uploaded g, 5.7 GB): 4 k x 64 q."""
+    import torch
+
+    import synth
+    m = synth.make_config_model("cell")
+    dm = px.Model(m)
+    nw, n_re, n_rp = m.nw, len(m.re_g), len(m.rp_g)
+    del m
+    ka, qa = ks[:4], torch.as_tensor(q[:64], device="cuda")
     lam = torch.ones((len(ka), nw), dtype=torch.float64, device="cuda")
     px.rates_vjp(dm, ka, qa[:8], par, lam)
     torch.cuda.synchronize()
@@ -648,20 +676,14 @@ def cell_bench(px, args):
     gbar = px.rates_vjp(dm, ka, qa, par, lam)
     torch.cuda.synchronize()
     dt_adj = time.perf_counter() - t0
-    adj = {"pairs": len(ka) * len(qa), "seconds": round(dt_adj, 4), "pairs_per_s": len(ka) * len(qa) / dt_adj,
-           "g_bar_bytes": gbar.numel() * 16}
-    log("large cell rates adjoint w.r.t. g(Re,Rp): %d pairs in %.3f s (%.3g pairs/s), g_bar %.2f GB"
+    adj = {"sets": "%d Re x %d Rp (3^3)" % (n_re, n_rp), "pairs": len(ka) * len(qa), "seconds": round(dt_adj, 4),
+           "pairs_per_s": len(ka) * len(qa) / dt_adj, "g_bar_bytes": gbar.numel() * 16}
+    log("large cell (3^3 sets) rates adjoint w.r.t. g(Re,Rp): %d pairs in %.3f s (%.3g pairs/s), g_bar %.2f GB"
         % (adj["pairs"], dt_adj, adj["pairs_per_s"], adj["g_bar_bytes"] / 1e9))
     del gbar
-    del dm
-    return {
-        "metric": "|g(k,q)|^2 pairs/s (scattering-rate pipeline, large cell)",
-        "config": {"workload": "large cell: 40 atoms (120 modes), Nw=64, simple cubic a=10 A, %d Re x %d Rp "
-                               "(3^3 sets), %d window k x %d random q, T=300 K, sigma=5 meV" % (n_re, n_rp, len(ks), len(q))},
-        "flops_per_pair": {"rp_contraction": fl_rp, "rotation_projection": fl_ep},
-        "by_precision": res,
-        "rates_adjoint_fp64": adj,
-    }
+    dm.close()
+    torch.cuda.empty_cache()
+    return adj
 
 
 def measured_traffic(kernel):

@@ -112,6 +112,23 @@ typedef struct {
     const double* eps_inf;
     double alpha_ewald;
     double gcut;
+    /* g_gen = 1: g is not given (g may be NULL) but drawn on the device and
+     * stored as complex float, for tensors too large to pass from the host
+     * (216 x 216 vectors, 120 modes and 64 functions: 1.1e10 entries, 183 GB
+     * of complex float).  Entry t of the flat
+     * [n_re_g][n_rp_g][3nat][nw][nw] index is drawn by Philox4x32-10 (Salmon
+     * et al., SC11) under the key (g_seed mod 2^32, g_seed div 2^32): the six
+     * blocks with 64-bit counter 6t + b (b = 0..5; counter words 2, 3 zero),
+     * the twelve words of blocks 0-2 summed exactly for the real part and of
+     * blocks 3-5 for the imaginary part, x = sum * 2^-32 - 6, and the stored
+     * value float(g_env[Re][Rp] * x).  g_env: host double [n_re_g][n_rp_g];
+     * the weights w_re_g, w_rp_g must be NULL or 1.  Such a model supports
+     * bands, phonons, gkq, gkq_pairs and rates (the Re contraction reads the
+     * complex float tensor in FP64 arithmetic); pair tables, ephx_model_set_g
+     * and the adjoints w.r.t. g return EPHX_EUNSUPPORTED. */
+    int g_gen;
+    uint64_t g_seed;
+    const double* g_env;
 } ephx_model_desc;
 
 /* Physical parameters of rates, tables and transport.
@@ -138,6 +155,13 @@ const char* ephx_version(void);
  * *out receives a handle that the caller releases with ephx_model_destroy. */
 int ephx_model_create(const ephx_model_desc* d, ephx_model** out);
 int ephx_model_destroy(ephx_model* m);
+
+/* Diagnostic read-back of the model's device copy of g(Re,Rp) (Eq.
+ * eph_mat_wann, weights folded in; the complex-float values of a drawn g
+ * widened to double): out[2i], out[2i+1] = entry idx[i] of the flat
+ * [n_re_g][n_rp_g][3nat][nw][nw] index.  idx and out are host arrays of n
+ * entries; an index out of range returns EPHX_EINVAL.  Synchronous. */
+int ephx_model_g_entries(ephx_model* m, int n, const int64_t* idx, double* out);
 
 /* Replace the model's coupling tensor g(Re,Rp) of Eq. eph_mat_wann (the
  * quantity the adjoints ephx_rates_vjp / ephx_mobility_vjp differentiate

@@ -46,6 +46,7 @@ class ModelDesc(C.Structure):
         ("g", C.c_void_p),
         ("polar", C.c_int), ("zstar", C.c_void_p), ("eps_inf", C.c_void_p),
         ("alpha_ewald", C.c_double), ("gcut", C.c_double),
+        ("g_gen", C.c_int), ("g_seed", C.c_uint64), ("g_env", C.c_void_p),
     ]
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "ephx_dynamics_vjp": ([_P, _P, _D, _I, _I, _P, _P, _P, _P], _I),
     "ephx_mobility": ([_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P], _I),
     "ephx_model_set_g": ([_P, _P, _P], _I),
+    "ephx_model_g_entries": ([_P, _I, _P, _P], _I),
     "ephx_mobility_vjp": ([_P, _P, _P, _I, _P, _P, _P], _I),
     "ephx_tdf": ([_P, _P, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "ephx_population": ([_P, _P, _I, _P, _P, _P], _I),

@@ -40,9 +40,12 @@ class Params:
 class Model:
     """Device copy of a Wannier model.  `src` needs the attributes lattice, tau,
     mass, nw, re, w_re, h, rp_ph, w_rp_ph, ifc, re_g, w_re_g, rp_g, w_rp_g, g
-    and optionally zstar, eps_inf (+ polar = dict(alpha_ewald, gcut))."""
+    and optionally zstar, eps_inf (+ polar = dict(alpha_ewald, gcut)).  With
+    drawn = (seed, env) the coupling tensor is not uploaded but drawn on the
+    device by the counter scheme (complex float, env [nRe][nRp] amplitudes);
+    src.g is then ignored."""
 
-    def __init__(self, src, polar=None):
+    def __init__(self, src, polar=None, drawn=None):
         def f64(a):
             return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
@@ -55,7 +58,8 @@ class Model:
         keep = dict(
             tau=f64(src.tau), mass=f64(src.mass), re=i32(src.re), w_re=f64(src.w_re), h=c128(src.h),
             rp_ph=i32(src.rp_ph), w_rp_ph=f64(src.w_rp_ph), ifc=f64(src.ifc), re_g=i32(src.re_g),
-            w_re_g=f64(src.w_re_g), rp_g=i32(src.rp_g), w_rp_g=f64(src.w_rp_g), g=c128(src.g))
+            w_re_g=f64(src.w_re_g), rp_g=i32(src.rp_g), w_rp_g=f64(src.w_rp_g),
+            g=None if drawn is not None else c128(src.g))
         d = _lib.ModelDesc()
         d.lattice[:] = [float(v) for v in np.asarray(src.lattice, dtype=np.float64).ravel()]
         d.natoms = keep["tau"].shape[0]
@@ -67,6 +71,9 @@ class Model:
         d.n_re_g, d.re_g, d.w_re_g = len(keep["re_g"]), host_ptr(keep["re_g"]), host_ptr(keep["w_re_g"])
         d.n_rp_g, d.rp_g, d.w_rp_g = len(keep["rp_g"]), host_ptr(keep["rp_g"]), host_ptr(keep["w_rp_g"])
         d.g = host_ptr(keep["g"])
+        if drawn is not None:
+            keep["env"] = f64(drawn[1])
+            d.g_gen, d.g_seed, d.g_env = 1, int(drawn[0]), host_ptr(keep["env"])
         if polar is not None:
             keep["zstar"] = f64(src.zstar)
             keep["eps"] = f64(src.eps_inf)
@@ -79,7 +86,7 @@ class Model:
         self.nw = int(src.nw)
         self.nat = d.natoms
         self.nmodes = 3 * self.nat
-        self.g_shape = tuple(np.asarray(src.g).shape)
+        self.g_shape = (len(keep["re_g"]), len(keep["rp_g"]), self.nmodes, self.nw, self.nw)
 
     def set_g(self, g):
         """Replace the model's g(Re,Rp) by a complex128 device tensor of shape
@@ -90,6 +97,13 @@ class Model:
             raise ValueError("g has shape %s, the model's is %s" % (tuple(g.shape), self.g_shape))
         g = g.detach().contiguous()
         check(lib.ephx_model_set_g(self._h, ptr(g), stream_ptr()))
+
+    def g_entries(self, idx):
+        """Entries of the device copy of g at flat indices idx (complex128 numpy)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.empty(2 * len(idx), dtype=np.float64)
+        check(lib.ephx_model_g_entries(self._h, len(idx), host_ptr(idx), host_ptr(out)))
+        return out.view(np.complex128)
 
     def close(self):
         if self._h:

@@ -81,6 +81,8 @@ struct ephx_model {
     double* d_cm = nullptr;      // [n_rp_ph][nm*nm] complex, C / sqrt(M M')
     double g_scale = 1.0;        // power of two taking the Rp-contraction operand of g into fp16 range
     double* d_g = nullptr;       // [n_re_g][n_rp_g][nm][nw][nw] complex
+    float* d_g32 = nullptr;      // the same as complex float when counter-drawn (g_c64)
+    bool g_c64 = false;
     double* d_minv = nullptr;    // [nm]
     double* d_wg = nullptr;      // [n_re_g][n_rp_g] weight products, only if not all 1
     double* d_nrp_g = nullptr;   // -Rp then -Re as doubles (adjoint sums), created on first use

@@ -454,6 +454,7 @@ extern "C" int ephx_table_create(ephx_model* m, const int n_grid[3], int n_state
         *out = nullptr;
         if (is_wide(m))
             throw Error{EPHX_EUNSUPPORTED, "table_create: not built for models with nw > 16 or more than 12 modes"};
+        if (m->g_c64) throw Error{EPHX_EUNSUPPORTED, "table_create: not built for a counter-drawn (complex float) g"};
         int n1, n2, n3;
         grid_dims(n_grid, n1, n2, n3);
         require(n_states >= 1 && n_states <= 60000, "table_create: need 1 <= n_states <= 60000");

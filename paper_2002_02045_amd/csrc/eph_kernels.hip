@@ -201,7 +201,8 @@ __global__ void k_scale_rows(long rows, long cols, const double* __restrict__ w,
 // the largest of them, as the bit pattern of a non-negative double in out[0]
 // (atomicMax on the pattern orders non-negative doubles); out[1] != 0 if an
 // entry is not finite.  One thread per (Rp, component, row).
-__global__ void k_g_row_bound(int n_re, long rows, int nw, const double* __restrict__ g,
+template <typename TG>
+__global__ void k_g_row_bound(int n_re, long rows, int nw, const TG* __restrict__ g,
                               const double* __restrict__ w, long rows_per_rp, int n_rp,
                               unsigned long long* __restrict__ out) {
     const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +210,7 @@ __global__ void k_g_row_bound(int n_re, long rows, int nw, const double* __restr
     bool bad = false;
     if (r < rows) {
         for (int e = 0; e < n_re; ++e) {
-            const double* x = g + ((size_t)e * rows + r) * nw * 2;
+            const TG* x = g + ((size_t)e * rows + r) * nw * 2;
             double u = 0.0;
             for (int j = 0; j < nw; ++j) {
                 const double a = x[2 * j], b = x[2 * j + 1];
@@ -232,6 +233,48 @@ __global__ void k_g_row_bound(int n_re, long rows, int nw, const double* __restr
     if (threadIdx.x == 0) {
         atomicMax(&out[0], (unsigned long long)__double_as_longlong(red[0]));
         if (badf) atomicOr(&out[1], 1ull);
+    }
+}
+
+// g(Re,Rp) drawn on the device by the counter scheme of the inputs: Philox4x32
+// with 10 rounds (Salmon et al., SC11: multipliers 0xD2511F53 and 0xCD9E8D57,
+// key increments 0x9E3779B9 and 0xBB67AE85), six blocks per complex entry t
+// with the 64-bit counter 6t + b, and an Irwin-Hall sum of twelve words per
+// part: x = (sum of the words) 2^-32 - 6, stored as float(env[Re][Rp] x).
+__device__ __forceinline__ void philox10(unsigned int& c0, unsigned int& c1, unsigned int& c2, unsigned int& c3,
+                                         unsigned int k0, unsigned int k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned int hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const unsigned int hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const unsigned int n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// A grid-stride loop: the dispatch counts work-items in 32 bits, and the
+// large cell's tensor has 2.3e10 entries.
+__global__ void k_gen_coupling(long n, long per, int n_rp, unsigned long long seed, const double* __restrict__ env,
+                               float* __restrict__ out) {
+    const unsigned int k0 = (unsigned int)(seed & 0xFFFFFFFFull), k1 = (unsigned int)(seed >> 32);
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        unsigned long long sum[2] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            const unsigned long long ctr = (unsigned long long)t * 6ull + (unsigned long long)b;
+            unsigned int c0 = (unsigned int)(ctr & 0xFFFFFFFFull), c1 = (unsigned int)(ctr >> 32), c2 = 0, c3 = 0;
+            philox10(c0, c1, c2, c3, k0, k1);
+            sum[b / 3] += (unsigned long long)c0 + c1 + (unsigned long long)c2 + c3;
+        }
+        const double a = env[t / per];
+        const double xr = (double)sum[0] * 0x1p-32 - 6.0, xi = (double)sum[1] * 0x1p-32 - 6.0;
+        out[2 * t] = (float)(a * xr);
+        out[2 * t + 1] = (float)(a * xi);
     }
 }
 
@@ -781,9 +824,27 @@ void g_row_bound(int n_re, long rows, int nw, const double* g, const double* w, 
     if (hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
         throw Error{-3, "g_row_bound: hipMemsetAsync failed"};
     if (rows <= 0) return;
-    hipLaunchKernelGGL(k_g_row_bound, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, n_re, rows, nw, g, w,
-                       rows_per_rp, n_rp, out);
+    hipLaunchKernelGGL(k_g_row_bound<double>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, n_re, rows, nw,
+                       g, w, rows_per_rp, n_rp, out);
     check_launch("g_row_bound");
+}
+
+void g_row_bound_f32(int n_re, long rows, int nw, const float* g, unsigned long long* out, hipStream_t st) {
+    if (hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
+        throw Error{-3, "g_row_bound: hipMemsetAsync failed"};
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_g_row_bound<float>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, n_re, rows, nw,
+                       g, (const double*)nullptr, 1L, 1, out);
+    check_launch("g_row_bound");
+}
+
+void gen_coupling(int n_re, int n_rp, long per, unsigned long long seed, const double* env, float* out,
+                  hipStream_t st) {
+    const long n = (long)n_re * n_rp * per;
+    if (n <= 0) return;
+    const long blocks = std::min<long>((n + 255) / 256, 1L << 20);
+    hipLaunchKernelGGL(k_gen_coupling, dim3((unsigned)blocks), dim3(256), 0, st, n, per, n_rp, seed, env, out);
+    check_launch("gen_coupling");
 }
 
 void convert_f64_f32(long count, const double* in, float* out, hipStream_t st) {

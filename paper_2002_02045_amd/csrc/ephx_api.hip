@@ -163,12 +163,23 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
         require(d->natoms >= 1 && 3 * d->natoms <= kMaxModesWide, "model_create: need 1 <= natoms <= 42");
         require(d->nw >= 1 && d->nw <= kMaxNwWide, "model_create: need 1 <= nw <= 64");
         require(d->n_re >= 1 && d->n_rp_ph >= 1 && d->n_re_g >= 1 && d->n_rp_g >= 1, "model_create: empty vector set");
-        require(d->tau && d->mass && d->re && d->h && d->rp_ph && d->ifc && d->re_g && d->rp_g && d->g,
+        require(d->g_gen == 0 || d->g_gen == 1, "model_create: g_gen must be 0 (g given) or 1 (counter-drawn)");
+        const bool gen = d->g_gen == 1;
+        require(d->tau && d->mass && d->re && d->h && d->rp_ph && d->ifc && d->re_g && d->rp_g && (gen || d->g),
                 "model_create: null array");
+        require(!gen || d->g_env, "model_create: a counter-drawn g needs g_env");
         const int nw = d->nw, nat = d->natoms, nm = 3 * nat, nw2 = nw * nw;
         const size_t nh = (size_t)d->n_re * nw2 * 2, nc = (size_t)d->n_rp_ph * nm * nm;
         const size_t ng = (size_t)d->n_re_g * d->n_rp_g * nm * nw2 * 2;
-        if (!finite_all(d->h, nh) || !finite_all(d->ifc, nc) || !finite_all(d->g, ng) ||
+        if (gen) {
+            bool unit = true;
+            for (int e = 0; e < d->n_re_g && d->w_re_g; ++e) unit = unit && d->w_re_g[e] == 1.0;
+            for (int p = 0; p < d->n_rp_g && d->w_rp_g; ++p) unit = unit && d->w_rp_g[p] == 1.0;
+            require(unit, "model_create: a counter-drawn g takes unit weights on Re and Rp");
+            if (!finite_all(d->g_env, (size_t)d->n_re_g * d->n_rp_g))
+                throw Error{EPHX_ENAN, "model_create: non-finite g_env"};
+        }
+        if (!finite_all(d->h, nh) || !finite_all(d->ifc, nc) || (!gen && !finite_all(d->g, ng)) ||
             !finite_all(d->tau, 3 * nat) || !finite_all(d->mass, nat) || !finite_all(&d->lattice[0][0], 9))
             throw Error{EPHX_ENAN, "model_create: non-finite value in the model"};
         for (int a = 0; a < nat; ++a) require(d->mass[a] > 0.0, "model_create: masses must be positive");
@@ -375,8 +386,24 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                             w * d->ifc[((size_t)r * nm + a) * nm + b] / std::sqrt(d->mass[a / 3] * d->mass[b / 3]);
             }
             m->d_cm = (double*)up(cm.data(), cm.size() * sizeof(double));
-            // g(Re,Rp) with both weights folded
-            {
+            if (gen) {
+                // g(Re,Rp) drawn on the device by the counter scheme, stored as
+                // complex float; the fp16 scale from its entries as below
+                const long per = (long)nm * nw2;
+                double* denv = (double*)dev_upload(d->g_env, (size_t)d->n_re_g * d->n_rp_g * 8);
+                m->d_g32 = (float*)up(nullptr, (size_t)d->n_re_g * d->n_rp_g * per * 8);
+                m->g_c64 = true;
+                gen_coupling(d->n_re_g, d->n_rp_g, per, (unsigned long long)d->g_seed, denv, m->d_g32, nullptr);
+                unsigned long long* red = (unsigned long long*)m->ws.get("create.red", 16);
+                g_row_bound_f32(d->n_re_g, (long)d->n_rp_g * nm * nw, nw, m->d_g32, red, nullptr);
+                unsigned long long h2[2] = {0, 0};
+                hip_check(hipMemcpy(h2, red, sizeof(h2), hipMemcpyDeviceToHost), "hipMemcpy");
+                (void)hipFree(denv);
+                if (h2[1]) throw Error{EPHX_ENAN, "model_create: non-finite drawn g"};
+                double rowmax;
+                std::memcpy(&rowmax, &h2[0], 8);
+                m->g_scale = fp16_scale(2.0 * rowmax);
+            } else {
                 const size_t per = (size_t)nm * nw2 * 2;
                 std::vector<double> g(ng);
                 for (int e = 0; e < d->n_re_g; ++e)
@@ -407,7 +434,7 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
                 for (double v : rs) bound = std::max(bound, 2.0 * v);
                 m->g_scale = fp16_scale(bound);
             }
-            {
+            if (!gen) {
                 bool unit = true;
                 std::vector<double> wg((size_t)d->n_re_g * d->n_rp_g);
                 for (int e = 0; e < d->n_re_g; ++e)
@@ -497,6 +524,7 @@ extern "C" int ephx_model_create(const ephx_model_desc* d, ephx_model** out) {
 extern "C" int ephx_model_set_g(ephx_model* m, const double* g, void* stream) {
     return guarded([&] {
         require(m != nullptr && g != nullptr, "model_set_g: null argument");
+        if (m->g_c64) throw Error{EPHX_EUNSUPPORTED, "model_set_g: the model's g is counter-drawn (complex float)"};
         hipStream_t st = (hipStream_t)stream;
         const long rows = (long)m->n_rp_g * m->nm * m->nw;
         const size_t bytes = (size_t)m->n_re_g * rows * m->nw * 16;
@@ -513,6 +541,25 @@ extern "C" int ephx_model_set_g(ephx_model* m, const double* g, void* stream) {
         hip_check(hipMemcpyAsync(m->d_g, g, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
         if (m->d_wg) scale_rows((long)m->n_re_g * m->n_rp_g, (long)m->nm * m->nw * m->nw, m->d_wg, m->d_g, st);
         m->g_scale = fp16_scale(2.0 * rowmax);
+    });
+}
+
+extern "C" int ephx_model_g_entries(ephx_model* m, int n, const int64_t* idx, double* out) {
+    return guarded([&] {
+        require(m != nullptr && (n == 0 || (idx && out)), "model_g_entries: null argument");
+        require(n >= 0, "model_g_entries: n < 0");
+        const int64_t total = (int64_t)m->n_re_g * m->n_rp_g * m->nm * m->nw * m->nw;
+        for (int i = 0; i < n; ++i) require(idx[i] >= 0 && idx[i] < total, "model_g_entries: index out of range");
+        for (int i = 0; i < n; ++i) {
+            if (m->g_c64) {
+                float v[2];
+                hip_check(hipMemcpy(v, m->d_g32 + 2 * idx[i], 8, hipMemcpyDeviceToHost), "hipMemcpy");
+                out[2 * i] = v[0];
+                out[2 * i + 1] = v[1];
+            } else {
+                hip_check(hipMemcpy(out + 2 * i, m->d_g + 2 * idx[i], 16, hipMemcpyDeviceToHost), "hipMemcpy");
+            }
+        }
     });
 }
 
@@ -580,7 +627,12 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
     d.ngcol = (long)d.nm * d.nw2;                    // columns of the Rp contraction
     d.nre_cols = (long)m->n_rp_g * d.ngcol;          // columns of the Re contraction
     d.f32 = precision != EPHX_FP64;
-    const int bk = std::max(1, std::min(nk, std::max(1, (int)(((size_t)3 << 30) / (d.nre_cols * 16 * 2)))));
+    // k per Re contraction pass: g(k,Rp) and g(k,Rp)U(k) in FP64 take 32 bytes
+    // per column and k; 3 GiB of them, or, for a counter-drawn complex-float
+    // g (whose every pass reads the whole tensor), up to 8 k within 32 GiB
+    const size_t kbudget = m->g_c64 ? ((size_t)32 << 30) : ((size_t)3 << 30);
+    int bk = std::max(1, std::min(nk, std::max(1, (int)(kbudget / (d.nre_cols * 16 * 2)))));
+    if (m->g_c64) bk = std::min(bk, 8);
     // large models: the per-pair blocks (nm nw^2 complex, twice) set the chunk size
     d.wide = d.nw > kMaxNw || d.nm > kMaxModes;
     const long pair_bytes = d.ngcol * (d.f32 ? 8 : 16) * 2 + (long)d.nw2 * 48;
@@ -730,7 +782,10 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         // Re contraction (FP64, amortised over all q), then U(k) on the right
         {
             StageTimer t("re_contraction", st);
-            phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
+            if (m->g_c64)
+                phase_gemm_f64_b32(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g32, 0, gk, 0, st);
+            else
+                phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
         }
         apply_u_right(nb, m->n_rp_g, nm, nw, gk, uk, gp, st);
         if (half) {
@@ -1024,6 +1079,8 @@ extern "C" int ephx_rates_vjp(ephx_model* m, const ephx_params* p, int nk, const
         require(p->temp > 0 && p->sigma > 0 && std::isfinite(p->mu) && std::isfinite(p->omega_cut),
                 "rates_vjp: need temp > 0, sigma > 0, finite mu and omega_cut");
         require(g_bar != nullptr, "rates_vjp: null output");
+        if (m->g_c64)
+            throw Error{EPHX_EUNSUPPORTED, "rates_vjp: not built for a counter-drawn (complex float) g"};
         hipStream_t st = (hipStream_t)stream;
         if (nk == 0 || nq == 0) {
             hip_check(hipMemsetAsync(g_bar, 0, (size_t)m->n_re_g * m->n_rp_g * m->nm * m->nw * m->nw * 16, st),

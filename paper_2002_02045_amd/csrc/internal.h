@@ -61,6 +61,9 @@ void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int 
                    hipStream_t st);
 void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
                                 double* C, hipStream_t st);
+// phase_gemm_f64 with a complex-float B (FP64 arithmetic; B widened on load)
+void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
+                        const float* B, long sB, double* C, long sC, hipStream_t st);
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const float* B, long sB, float* C, long sC,
                     hipStream_t st);
@@ -123,6 +126,12 @@ void convert_f64_f32(long count, const double* in, float* out, hipStream_t st);
 // an entry is not finite (out cleared first)
 void g_row_bound(int n_re, long rows, int nw, const double* g, const double* w, long rows_per_rp, int n_rp,
                  unsigned long long* out, hipStream_t st);
+// the same bound for complex float g [n_re][rows][nw] with unit weights
+void g_row_bound_f32(int n_re, long rows, int nw, const float* g, unsigned long long* out, hipStream_t st);
+// g(Re,Rp) [n_re][n_rp][per] complex float drawn by the counter scheme
+// (Philox4x32-10, Irwin-Hall twelve-word variates) with amplitudes env [n_re][n_rp]
+void gen_coupling(int n_re, int n_rp, long per, unsigned long long seed, const double* env, float* out,
+                  hipStream_t st);
 // dst[i] += src[i], i < n
 void add_into(long n, const double* src, double* dst, hipStream_t st);
 // data[r][c] *= w[r] for complex data [rows][cols]

@@ -67,32 +67,40 @@ constexpr int kKC = 16;
 // KD = true: the contraction-side points are real (double [K][3]) instead of
 // integer vectors -- used by the adjoint sums over q and k; ACC = true adds the
 // product to C.
-template <typename T, int CB, bool HERM = false, bool KD = false, bool ACC = false>
+// TB: element type of B (float B is widened as it is staged, for FP64 sums
+// over a complex-float coupling tensor).  WC = true (few rows, M <= 16): the
+// four waves take the same 16 rows and four consecutive column blocks, so a
+// workgroup covers 16 rows x 64 CB columns instead of padding M to 64 rows.
+template <typename T, int CB, bool HERM = false, bool KD = false, bool ACC = false, typename TB = T,
+          bool WC = false>
 __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const double* __restrict__ x,
                                                     const double* __restrict__ x0,
                                                     const void* __restrict__ nvec_,
-                                                    const T* __restrict__ B, long sB,
+                                                    const TB* __restrict__ B, long sB,
                                                     T* __restrict__ C, long sC, int cg) {
     typedef typename AccOf<T>::type acc_t;
     typedef typename std::conditional<KD, double, int32_t>::type NT;
     const NT* nvec = reinterpret_cast<const NT*>(nvec_);
     constexpr int BN = 16 * CB;
     constexpr int NB = HERM ? 2 : 1;
+    constexpr int WBN = WC ? 4 * BN : BN;     // columns of the workgroup
     // component-major rows: the 16 lanes of a read phase take 16 consecutive
     // columns of one component, one contiguous run of LDS words (no bank
     // conflicts; a column-major [BN][components] layout had 3.7 per read)
-    __shared__ T bs[kKC][2 * NB][BN];
+    __shared__ T bs[kKC][2 * NB][WBN];
     __shared__ NT ns[kKC][3];
     const int z = blockIdx.z;
-    const int row0 = blockIdx.y * kBM;
-    const int col0 = blockIdx.x * BN;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const T* bz = B + (long)z * sB * 2;
+    const int row0 = WC ? blockIdx.y * 16 : blockIdx.y * kBM;
+    const int col0 = blockIdx.x * WBN;
+    const int wrow = WC ? 0 : wave * 16;      // the wave's first row in the tile
+    const int wcol = WC ? wave * BN : 0;      // ... and first column
+    const TB* bz = B + (long)z * sB * 2;
     T* cz = C + (long)z * sC * 2;
 
-    const int arow = row0 + wave * 16 + li;
+    const int arow = row0 + wrow + li;
     const bool rowok = arow < M;
     double xa = 0.0, xb = 0.0, xc = 0.0;
     if (rowok) {
@@ -114,16 +122,16 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
     }
 
     for (int kc = 0; kc < K; kc += kKC) {
-        for (int e = tid; e < kKC * BN; e += 256) {
-            const int kk = e / BN, nn = e % BN;
+        for (int e = tid; e < kKC * WBN; e += 256) {
+            const int kk = e / WBN, nn = e % WBN;
             const int r = kc + kk, col = col0 + nn;
 #pragma unroll
             for (int h = 0; h < NB; ++h) {
                 T re = 0, im = 0;
                 if (r < K && col < N) {
                     const long off = (((long)r * NB + h) * N + col) * 2;
-                    re = bz[off];
-                    im = bz[off + 1];
+                    re = (T)bz[off];
+                    im = (T)bz[off + 1];
                 }
                 bs[kk][2 * h][nn] = re;
                 bs[kk][2 * h + 1][nn] = im;
@@ -142,11 +150,11 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
             const T nps = -ps;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                const T bre = bs[kk][0][cb * 16 + li];
-                const T bim = bs[kk][1][cb * 16 + li];
+                const T bre = bs[kk][0][wcol + cb * 16 + li];
+                const T bim = bs[kk][1][wcol + cb * 16 + li];
                 if (HERM) {
-                    const T b2re = bs[kk][2 * NB - 2][cb * 16 + li];
-                    const T b2im = bs[kk][2 * NB - 1][cb * 16 + li];
+                    const T b2re = bs[kk][2 * NB - 2][wcol + cb * 16 + li];
+                    const T b2im = bs[kk][2 * NB - 1][wcol + cb * 16 + li];
                     are[cb] = mfma(pc, bre, are[cb]);
                     are[cb] = mfma(ps, b2re, are[cb]);
                     aim[cb] = mfma(pc, bim, aim[cb]);
@@ -163,10 +171,10 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-        const int col = col0 + cb * 16 + li;
+        const int col = col0 + wcol + cb * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = row0 + wave * 16 + AccOf<T>::row(lk, v);
+            const int row = row0 + wrow + AccOf<T>::row(lk, v);
             if (row < M && col < N) {
                 // cg > 0: the columns are groups of cg (one matrix each), stored
                 // group-major as [N/cg][M][cg]
@@ -731,6 +739,22 @@ void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x
     else
         hipLaunchKernelGGL((k_phase_gemm<double, 4>), grid, dim3(256), 0, st, M, N, K, x, x0, nvec, B, sB, C, sC, 0);
     check_launch("phase_gemm_f64");
+}
+
+void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
+                        const float* B, long sB, double* C, long sC, hipStream_t st) {
+    if (M <= 0 || N <= 0 || Z <= 0) return;
+    if (M <= 16) {
+        // a k batch of at most 16: 16-row tiles, the waves along the columns
+        dim3 grid((N + 255) / 256, 1, Z);
+        hipLaunchKernelGGL((k_phase_gemm<double, 4, false, false, false, float, true>), grid, dim3(256), 0, st, M, N,
+                           K, x, x0, (const void*)nvec, B, sB, C, sC, 0);
+    } else {
+        dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, Z);
+        hipLaunchKernelGGL((k_phase_gemm<double, 4, false, false, false, float>), grid, dim3(256), 0, st, M, N, K, x,
+                           x0, (const void*)nvec, B, sB, C, sC, 0);
+    }
+    check_launch("phase_gemm_f64_b32");
 }
 
 void phase_gemm_adj_f64(int M, int N, int K, int Z, const double* x, const double* kpts, const double* B, long sB,

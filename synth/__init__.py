@@ -18,6 +18,11 @@ from .models import (  # noqa: F401
     ws_vectors,
     make_model,
     make_config_model,
+    make_counter_model,
+    counter_coupling,
+    counter_normals,
+    coupling_envelope,
+    philox4x32_10,
     random_points,
     cauchy_points,
     CONFIGS,

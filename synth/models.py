@@ -200,9 +200,11 @@ def make_model(
     zstar=None,
     eps_inf=None,
     name="model",
+    draw_g=True,
 ):
     """Draw a complete synthetic model on the least-distance set of an
-    n_grid^3 supercell (the same set for H, C, Re and Rp)."""
+    n_grid^3 supercell (the same set for H, C, Re and Rp).  draw_g=False
+    leaves g empty (it is drawn last, so H and C are unchanged)."""
     lattice = np.asarray(lattice, float)
     tau = np.asarray(tau, float)
     mass = np.asarray(mass, float)
@@ -221,7 +223,8 @@ def make_model(
     h = hermitian_hoppings(rng, vecs, lattice, nw, a_h, decay, onsite=onsite, real=real,
                            nn_hop=hop)
     ifc = spring_ifc(rng, vecs, lattice, tau, s_k, decay)
-    g = coupling_tensor(rng, vecs, vecs, lattice, 3 * nat, nw, a_g, decay, real=real)
+    g = (coupling_tensor(rng, vecs, vecs, lattice, 3 * nat, nw, a_g, decay, real=real) if draw_g
+         else np.zeros((0,), dtype=np.complex128))
     wf = np.repeat(tau, int(np.ceil(nw / nat)), axis=0)[:nw]
     ones = np.ones(nr)
     return Model(
@@ -274,6 +277,98 @@ def cauchy_points(seed: int, n: int, gamma: float):
     return x, 1.0 / (n * p)
 
 
+# ---------------------------------------------------------------- counter-based coupling draws
+# For models too large to draw on the host (the 6^3 large cell's g(Re,Rp) is
+# 1.1e10 complex entries), the coupling tensor is drawn from a counter-based
+# generator that the device reproduces bit for bit: Philox4x32-10 (Salmon,
+# Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC11),
+# and an exact integer Irwin-Hall sum of twelve uniform 32-bit words as the
+# (approximately) normal variate.  Complex entry t (flat index over
+# [Re][Rp][3nat][nw][nw]) takes the six blocks with 64-bit counter 6t + b
+# (b = 0..5, words 2 and 3 of the counter zero) under the key (seed mod 2^32,
+# seed div 2^32): blocks 0-2 give the real part, blocks 3-5 the imaginary part,
+#   x = (sum of the 12 words) * 2^-32 - 6      (exact in double),
+# and the stored value is float(env[Re][Rp] * x) (complex64; env is a given
+# amplitude per (Re, Rp), so both sides round the same product).
+
+_PHILOX_M = (np.uint64(0xD2511F53), np.uint64(0xCD9E8D57))
+_PHILOX_W = (np.uint32(0x9E3779B9), np.uint32(0xBB67AE85))
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32 with 10 rounds on uint32 arrays (counter words c0..c3, key
+    words k0, k1); returns the four output words."""
+    c = [np.asarray(x, dtype=np.uint32) for x in (c0, c1, c2, c3)]
+    k0 = np.asarray(k0, dtype=np.uint32).copy()
+    k1 = np.asarray(k1, dtype=np.uint32).copy()
+    lo32 = np.uint64(0xFFFFFFFF)
+    with np.errstate(over="ignore"):
+        for _ in range(10):
+            p0 = _PHILOX_M[0] * c[0].astype(np.uint64)
+            p1 = _PHILOX_M[1] * c[2].astype(np.uint64)
+            hi0, lo0 = (p0 >> np.uint64(32)).astype(np.uint32), (p0 & lo32).astype(np.uint32)
+            hi1, lo1 = (p1 >> np.uint64(32)).astype(np.uint32), (p1 & lo32).astype(np.uint32)
+            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+            k0 = k0 + _PHILOX_W[0]
+            k1 = k1 + _PHILOX_W[1]
+    return c
+
+
+def counter_normals(t, seed):
+    """The real and imaginary variates of complex entries t (int64 array) under
+    the scheme above: two float64 arrays, each an Irwin-Hall(12) - 6 value."""
+    t = np.asarray(t, dtype=np.uint64)
+    k0 = np.uint32(seed & 0xFFFFFFFF)
+    k1 = np.uint32((seed >> 32) & 0xFFFFFFFF)
+    out = []
+    for half in range(2):
+        acc = np.zeros(t.shape, dtype=np.uint64)
+        for b in range(3 * half, 3 * half + 3):
+            ctr = t * np.uint64(6) + np.uint64(b)
+            words = philox4x32_10((ctr & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                                  (ctr >> np.uint64(32)).astype(np.uint32), 0, 0, k0, k1)
+            for w in words:
+                acc += w.astype(np.uint64)
+        out.append(acc.astype(np.float64) * 2.0 ** -32 - 6.0)
+    return out[0], out[1]
+
+
+def coupling_envelope(re, rp, lattice, amp, decay):
+    """env[Re][Rp] = amp exp(-(|Re| + |Rp|)/decay) / sqrt(2): the amplitude of
+    the counter-drawn g (a complex variate of unit variance per entry)."""
+    de = np.linalg.norm(np.asarray(re, float) @ lattice, axis=1)
+    dp = np.linalg.norm(np.asarray(rp, float) @ lattice, axis=1)
+    return amp * np.exp(-(de[:, None] + dp[None, :]) / decay) / np.sqrt(2.0)
+
+
+def counter_coupling(env, per, seed, entries=None):
+    """Complex64 g from the counter scheme: the whole tensor [nRe][nRp][per]
+    (small models), or, with entries (flat complex indices), those entries."""
+    n_re, n_rp = env.shape
+    t = np.arange(n_re * n_rp * per, dtype=np.int64) if entries is None else np.asarray(entries, dtype=np.int64)
+    xr, xi = counter_normals(t, seed)
+    a = env.reshape(-1)[t // per]
+    g = (a * xr).astype(np.float32) + 1j * (a * xi).astype(np.float32)
+    return g.astype(np.complex64) if entries is not None else g.astype(np.complex64).reshape(n_re, n_rp, per)
+
+
+def make_counter_model(name: str, *, n_grid=None, nw=None, seed=None, full=True):
+    """The model of a workload with g(Re,Rp) drawn by the counter scheme instead
+    of NumPy's generator; returns (model, env, seed).  With full=False the
+    model's g is left empty (the device draws it; the host evaluates chosen
+    entries with counter_coupling)."""
+    c = CONFIGS[name]
+    m = make_config_model(name, n_grid=n_grid, nw=nw, draw_g=False)
+    a = c["a"]
+    env = coupling_envelope(m.re_g, m.rp_g, m.lattice, c["a_g"], 1.5 * a)
+    seed = int(c["seed"] + 500 if seed is None else seed)
+    per = m.nmodes * m.nw * m.nw
+    if full:
+        g = counter_coupling(env, per, seed).astype(np.complex128)
+        m = dataclasses.replace(m, g=g.reshape(len(m.re_g), len(m.rp_g), m.nmodes, m.nw, m.nw))
+    return m, env, seed
+
+
 SEED_BASE = 20020205
 
 # Workload definitions.  Physical parameters follow the readings listed in the
@@ -322,7 +417,7 @@ CONFIGS = {
 }
 
 
-def make_config_model(name: str, *, real=None, n_grid=None, nw=None) -> Model:
+def make_config_model(name: str, *, real=None, n_grid=None, nw=None, draw_g=True) -> Model:
     c = CONFIGS[name]
     if real is None:
         real = bool(c.get("real", False))
@@ -343,5 +438,5 @@ def make_config_model(name: str, *, real=None, n_grid=None, nw=None) -> Model:
         lattice=lat, tau=tau, mass=masses,
         nw=nw or c["nw"], n_grid=n_grid or c["n_grid"], seed=c["seed"],
         a_h=c["a_h"], a_g=c["a_g"], s_k=c["s_k"], nn_hop=c["nn_hop"], decay=1.5 * a, real=real,
-        zstar=zstar, eps_inf=eps, name=name,
+        zstar=zstar, eps_inf=eps, name=name, draw_g=draw_g,
     )

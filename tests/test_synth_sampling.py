@@ -74,3 +74,34 @@ def test_cauchy_reduces_variance_for_a_peak_at_gamma():
     assert abs(f(qu).mean() - exact) <= 5 * np.sqrt(var_u / len(qu))
     assert abs(np.mean(len(qc) * wc * f(qc)) - exact) <= 5 * np.sqrt(var_c / len(qc))
     assert var_c < 0.01 * var_u
+
+
+# --------------------------------------------------------------- counter-based draws
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the known-answer vectors of its authors' reference
+    implementation (counter, key -> output)."""
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+             ((0xffffffff,) * 4, (0xffffffff, 0xffffffff), (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+             ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+              (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for ctr, key, want in cases:
+        got = synth.philox4x32_10(*[np.uint32(x) for x in ctr], np.uint32(key[0]), np.uint32(key[1]))
+        assert tuple(int(x) for x in got) == want
+
+
+def test_counter_normals_moments_and_entry_access():
+    """The Irwin-Hall(12) variates have mean 0 and variance 1 (sample of 2e5),
+    lie in [-6, 6], and an entry drawn alone equals the same entry of the whole
+    tensor (the draw depends only on the entry's index)."""
+    t = np.arange(200_000)
+    xr, xi = synth.counter_normals(t, 1234567)
+    for x in (xr, xi):
+        assert abs(x.mean()) < 0.01 and abs(x.var() - 1.0) < 0.01
+        assert x.min() >= -6.0 and x.max() <= 6.0
+    assert abs(np.corrcoef(xr, xi)[0, 1]) < 0.01
+    env = np.abs(np.random.default_rng(3).random((5, 7))) + 0.1
+    full = synth.counter_coupling(env, 12, 99)
+    idx = np.array([0, 1, 11, 12, 419])
+    part = synth.counter_coupling(env, 12, 99, entries=idx)
+    assert np.array_equal(full.reshape(-1)[idx], part)
