@@ -1,62 +1,30 @@
-// Batched Hermitian eigensolver in FP64 for the small matrices of the method:
+// Batched Hermitian eigensolvers in FP64 for the small matrices of the method:
 // H(k) and H(k+q) (n = Nw, Eq. wannier_3) and D(q) (n = 3 nat, Eq. IFC2).
 //
-// Cyclic Jacobi with plane rotations applied to disjoint pairs in parallel
-// (Golub & Van Loan, "Matrix Computations", Sec. 8.5, in its complex Hermitian
-// form).  For a pair (p, q), p < q, with a_pq = |a_pq| e^{i phi}:
+// n <= 8: one matrix per lane, 64 per wavefront: Householder reduction to a
+// real tridiagonal matrix, implicit QL with Wilkinson shifts, eigenvectors
+// U = Q Z (eig_ql.h).  About 240 VALU instructions per 8 x 8 matrix against
+// about 950 for cyclic Jacobi with one lane per row, which it replaces.
+//
+// 8 < n <= 128: one workgroup per matrix, cyclic Jacobi with plane rotations
+// applied to disjoint pairs in parallel (Golub & Van Loan, "Matrix
+// Computations", Sec. 8.5, in its complex Hermitian form).  For a pair (p, q),
+// p < q, with a_pq = |a_pq| e^{i phi}:
 //   th = (a_qq - a_pp)/(2|a_pq|), t = sgn(th)/(|th| + sqrt(th^2 + 1)),
 //   c = 1/sqrt(1 + t^2), s = t c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi},
-// and A <- J^dag A J, V <- V J.
+// and A <- J^dag A J, V <- V J.  Sweeps run until the off-diagonal Frobenius
+// norm is below 1e-15 of the matrix norm.
 //
-// Layout: one lane per matrix row, R = 2^ceil(log2 n) lanes per matrix (rows
-// and columns beyond n are zero and never rotate), 64/R matrices per
-// wavefront.  Round m = 1..R-1 of a sweep pairs row i with row i^m; over a
-// sweep every pair meets once.  Lane i keeps its row in lane-relative order:
-// register d holds column i^d (the diagonal is register 0).  Then every
-// exchange between lanes is "read register e of lane i^x" with x and e fixed
-// at compile time: XOR 1, 2, 3 by DPP quad permutes and XOR 7 by the DPP
-// half-row mirror inside the VALU, XOR 4..6 by the LDS crossbar's bit-mask
-// swizzle (no memory access).  Sweeps run until the off-diagonal Frobenius norm of
-// every matrix in the wavefront is below 1e-15 of its norm; eigenpairs are
-// then sorted ascending.
-#include <type_traits>
-
+// Both sort the eigenpairs ascending, ties by index.
 #include "internal.h"
+#include "eig_ql.h"
 
 namespace ephx {
 namespace {
 
-// value of lane (lane ^ X) within each group of 8 lanes
-template <int X>
-__device__ __forceinline__ int xlane(int v) {
-    static_assert(X >= 0 && X < 8, "lane offset");
-    constexpr int kQuad = X == 1 ? 0xB1 : (X == 2 ? 0x4E : 0x1B);   // XOR 1, 2, 3
-    constexpr int kMirror = 0x141;                                                      // lane -> 7 - lane
-    // every lane has a source under these permutations, so the destination is
-    // written in full (bound_ctrl set: no "old" value has to be placed first);
-    // the callers run with every lane of the wavefront active
-    if (X == 0) return v;
-    if (X <= 3) return __builtin_amdgcn_update_dpp(0, v, kQuad, 0xF, 0xF, true);
-    if (X == 7) return __builtin_amdgcn_update_dpp(0, v, kMirror, 0xF, 0xF, true);
-    // XOR 4..6 would take two DPP moves; the LDS crossbar's bit-mask swizzle
-    // (lane ^ X within groups of 32, no memory access) does it in one
-    // instruction outside the VALU, which this solver keeps busy
-    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
-}
-template <int X>
-__device__ __forceinline__ double xlane(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = xlane<X>((int)(b & 0xffffffffLL)), hi = xlane<X>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-struct Cx {
-    double r, i;
-};
-
 // 1/b and 1/sqrt(x) from the hardware estimates refined by two Newton steps
 // each (quadratic convergence from the estimate's ~1e-8 relative error to the
-// last bits); b > 0, x >= 1 where they are used.
+// last bits); any nonzero b, any positive normal x.
 __device__ __forceinline__ double recip(double b) {
     double y = __builtin_amdgcn_rcp(b);
     y = y * fma(-b, y, 2.0);
@@ -69,196 +37,72 @@ __device__ __forceinline__ double rsqrt1(double x) {
     return y * fma(-h * y, y, 1.5);
 }
 
-// Columns c1 = i^D (register D) and c2 = i^D^M (register E = D^M) form one pair
-// of the round, rotated with the parameters of lane i^D's pair.  With X_p, X_q
-// the columns of the pair (p < q),
-//   (XJ)_{.p} = c X_p - conj(se) X_q ,   (XJ)_{.q} = c X_q + se X_p ,
-// so each register is updated as  x_D <- c x_D + s_D x_E,  x_E <- c x_E + s_E x_D
-// with s = -conj(se) for the p column and s = se for the q column: the two
-// differ only in the sign of the real part, so no operand is selected.
-template <int R, int M, int D>
-__device__ __forceinline__ void column_pair(int i, Cx (&a)[R], Cx (&v)[R], double c, double sr, double si) {
-    constexpr int E = D ^ M;
-    constexpr int kTop = M >= 4 ? 4 : (M >= 2 ? 2 : 1);   // highest bit of M
-    const double cc = xlane<D>(c), s_r = xlane<D>(sr), s_i = xlane<D>(si);
-    const bool d_is_p = ((i ^ D) & kTop) == 0;
-    const double rd = d_is_p ? -s_r : s_r;   // real part of s_D; s_E has -rd
-    const Cx xd = a[D], xe = a[E];
-    a[D] = Cx{fma(cc, xd.r, fma(rd, xe.r, -s_i * xe.i)), fma(cc, xd.i, fma(rd, xe.i, s_i * xe.r))};
-    a[E] = Cx{fma(cc, xe.r, fma(-rd, xd.r, -s_i * xd.i)), fma(cc, xe.i, fma(-rd, xd.i, s_i * xd.r))};
-    const Cx yd = v[D], ye = v[E];
-    v[D] = Cx{fma(cc, yd.r, fma(rd, ye.r, -s_i * ye.i)), fma(cc, yd.i, fma(rd, ye.i, s_i * ye.r))};
-    v[E] = Cx{fma(cc, ye.r, fma(-rd, yd.r, -s_i * yd.i)), fma(cc, ye.i, fma(-rd, yd.i, s_i * yd.r))};
-}
+// Device arithmetic of the one-lane-per-matrix solver (eig_ql.h): the
+// refined inverse square root and reciprocal above (any positive x; any
+// nonzero b), and the wavefront vote that keeps a QL iteration running while
+// any lane's block is unreduced.
+struct LaneMath {
+    static __device__ __forceinline__ double rsqrt(double x) { return rsqrt1(x); }
+    static __device__ __forceinline__ double rcp(double b) { return recip(b); }
+    static __device__ __forceinline__ bool any(bool p) { return __any(p); }
+};
 
-template <int R, int M, int D>
-__device__ __forceinline__ void column_pairs(int i, Cx (&a)[R], Cx (&v)[R], double c, double sr, double si) {
-    if constexpr (D < R) {
-        if constexpr (D < (D ^ M)) column_pair<R, M, D>(i, a, v, c, sr, si);
-        column_pairs<R, M, D + 1>(i, a, v, c, sr, si);
-    }
-}
-
-template <int R, int M, int D>
-__device__ __forceinline__ void fetch_partner_row(const Cx (&a)[R], Cx (&q)[R]) {
-    // partner row i^M, column i^D sits in the partner's register D^M
-    if constexpr (D < R) {
-        q[D].r = xlane<M>(a[D ^ M].r);
-        q[D].i = xlane<M>(a[D ^ M].i);
-        fetch_partner_row<R, M, D + 1>(a, q);
-    }
-}
-
-template <int R, int M>
-__device__ __forceinline__ void jacobi_round(int i, Cx (&a)[R], Cx (&v)[R]) {
-    // rotation of the pair (i, i^M), evaluated by its lower lane and copied
-    const bool lower = i < (i ^ M);
-    const double dself = a[0].r;
-    const double dpart = xlane<M>(a[0].r);
-    // t and s of the header, divided by |a_pq| so that neither |a_pq| nor the
-    // phase needs its own root or quotient: with d = a_qq - a_pp and
-    // m2 = |a_pq|^2, t/|a_pq| = 2 sgn(d)/(|d| + sqrt(d^2 + 4 m2)) and
-    // se = (t/|a_pq|) c a_pq
-    const double apr = a[M].r, api = a[M].i;   // A[i][i^M]
-    const double m2 = apr * apr + api * api;
-    const double d = dpart - dself;
-    const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
-    const double c0 = rsqrt1(fma(tm * tm, m2, 1.0));
-    const double w = tm * c0;
-    const bool rot = m2 > 0.0;
-    double c = rot ? c0 : 1.0;
-    double sr = rot ? w * apr : 0.0;
-    double si = rot ? w * api : 0.0;
-    const double cp = xlane<M>(c), srp = xlane<M>(sr), sip = xlane<M>(si);
-    c = lower ? c : cp;
-    sr = lower ? sr : srp;
-    si = lower ? si : sip;
-    // column rotations A J and V J for every pair of the round
-    column_pairs<R, M, 0>(i, a, v, c, sr, si);
-    // row rotation J^dag A with the partner row: lower row p <- c A_p - se A_q,
-    // upper row q <- c A_q + conj(se) A_p, i.e. a <- c a + t q with
-    // t = (-sr, -si) or (sr, -si)
-    Cx q[R];
-    fetch_partner_row<R, M, 0>(a, q);
-    const double tr = lower ? -sr : sr;
+template <int N, int C>
+__device__ __forceinline__ void store_lane_vectors(const HermLane<N>& s, const int (&rk)[N], double* out) {
+    if constexpr (C < N) {
+        double xr[N], xi[N];
+        herm_eigenvector<N, C>(s, xr, xi);
 #pragma unroll
-    for (int d = 0; d < R; ++d)
-        a[d] = Cx{fma(c, a[d].r, fma(tr, q[d].r, si * q[d].i)), fma(c, a[d].i, fma(tr, q[d].i, -si * q[d].r))};
-}
-
-template <int R, int M>
-__device__ __forceinline__ void jacobi_sweep(int i, Cx (&a)[R], Cx (&v)[R]) {
-    if constexpr (M < R) {
-        jacobi_round<R, M>(i, a, v);
-        jacobi_sweep<R, M + 1>(i, a, v);
-    }
-}
-
-template <int R, int X>
-__device__ __forceinline__ double group_sum(double x) {
-    if constexpr (X < R) return group_sum<R, 2 * X>(x + xlane<X>(x));
-    return x;
-}
-
-template <int R, int E>
-__device__ __forceinline__ void rank_step(int i, int n, double d, int& rk) {
-    if constexpr (E < R) {
-        const double de = xlane<E>(d);
-        const int j = i ^ E;
-        rk += (E != 0 && j < n && (de < d || (de == d && j < i))) ? 1 : 0;
-        rank_step<R, E + 1>(i, n, d, rk);
-    }
-}
-
-template <int R, int E, typename F>
-__device__ __forceinline__ void for_offsets(F&& f) {
-    if constexpr (E < R) {
-        f(std::integral_constant<int, E>{});
-        for_offsets<R, E + 1>(f);
-    }
-}
-
-// PK = false: A holds n*n complex entries per matrix (stride strideA complex
-// elements) and the Hermitian part 0.5 (A + A^dag) is taken.  PK = true: A
-// holds the packed Hermitian form, n*n reals per matrix (stride strideA reals)
-// with P[i][j] = Re X_ij for i <= j and P[i][j] = Im X_ji for i > j.
-template <typename Tin, int N, bool PK = false>
-__global__ __launch_bounds__(256) void k_eig_rows(int batch, const Tin* __restrict__ A, long strideA,
-                                                  double* __restrict__ evals, double* __restrict__ evecs) {
-    constexpr int R = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
-    const int lane = threadIdx.x & 63;
-    const long slot = ((long)blockIdx.x * 256 + threadIdx.x) / R;
-    const int i = lane % R;
-    const bool valid = slot < batch;
-    const bool act = valid && i < N;
-    Cx a[R], v[R];
-#pragma unroll
-    for (int d = 0; d < R; ++d) {
-        a[d] = Cx{0.0, 0.0};
-        v[d] = Cx{d == 0 ? 1.0 : 0.0, 0.0};
-    }
-    if (act && PK) {
-        const Tin* ab = A + slot * strideA;
-#pragma unroll
-        for (int d = 0; d < R; ++d) {
-            const int j = i ^ d;
-            if (j < N) {
-                const int lo = i < j ? i : j, hi = i < j ? j : i;
-                const double re = (double)ab[lo * N + hi];
-                const double im = d == 0 ? 0.0 : (i < j ? 1.0 : -1.0) * (double)ab[hi * N + lo];
-                a[d] = Cx{re, im};
-            }
+        for (int i = 0; i < N; ++i) {
+            out[(i * N + rk[C]) * 2] = xr[i];
+            out[(i * N + rk[C]) * 2 + 1] = xi[i];
         }
-    } else if (act) {
-        const Tin* ab = A + slot * strideA * 2;
+        store_lane_vectors<N, C + 1>(s, rk, out);
+    }
+}
+
+// One matrix per lane (n <= 8): Householder tridiagonalisation, implicit QL,
+// eigenvectors U = Q Z (eig_ql.h).  PK selects the packed Hermitian input, else the Hermitian part of a complex
+// n x n matrix is taken; eigenvalues ascending, ties by index, eigenvector c
+// in column c of evecs[slot] (row-major complex n x n).
+template <typename Tin, int N, bool PK = false>
+__global__ __launch_bounds__(256) void k_eig_lane(int batch, const Tin* __restrict__ A, long strideA,
+                                                  double* __restrict__ evals, double* __restrict__ evecs) {
+    const long slot = (long)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = slot < batch;
+    HermLane<N> s;
 #pragma unroll
-        for (int d = 0; d < R; ++d) {
-            const int j = i ^ d;
-            if (j < N) {
-                // Hermitian part 0.5 (A + A^dag)
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double re = 0.0, im = 0.0;
+            if (valid && PK) {
+                const Tin* ab = A + slot * strideA;
+                re = (double)ab[j * N + i];
+                im = i == j ? 0.0 : -(double)ab[i * N + j];
+            } else if (valid) {
+                const Tin* ab = A + slot * strideA * 2;
                 const double xr = (double)ab[2 * (i * N + j)], xi = (double)ab[2 * (i * N + j) + 1];
                 const double yr = (double)ab[2 * (j * N + i)], yi = (double)ab[2 * (j * N + i) + 1];
-                a[d] = Cx{0.5 * (xr + yr), 0.5 * (xi - yi)};
+                re = 0.5 * (xr + yr);
+                im = i == j ? 0.0 : 0.5 * (xi - yi);
             }
+            s.ar[i][j] = re;
+            s.ai[i][j] = im;
         }
-    }
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, tot = 0.0;
+    herm_tridiagonalize<LaneMath, N>(s);
+    tridiag_ql<LaneMath, N>(s);
+    int rk[N];
+    eig_ranks<N>(s.d, rk);
+    if (!valid) return;
 #pragma unroll
-        for (int d = 0; d < R; ++d) {
-            const double m2 = a[d].r * a[d].r + a[d].i * a[d].i;
-            tot += m2;
-            off += d != 0 ? m2 : 0.0;
-        }
-        off = group_sum<R, 1>(off);
-        tot = group_sum<R, 1>(tot);
-        const bool done = !(off > 1e-30 * tot);
-        if (__all(done)) break;
-        jacobi_sweep<R, 1>(i, a, v);
-    }
-    // sort ascending, ties by index
-    const double dv = a[0].r;
-    int rk = 0;
-    rank_step<R, 0>(i, N, dv, rk);
-    if (act) evals[slot * N + rk] = dv;
-    if (evecs != nullptr) {
-        // V[i][c] with c = i^e sits in register e; its column goes to rank(c)
-        for_offsets<R, 0>([&](auto ec) {
-            constexpr int E = decltype(ec)::value;
-            const int rc = xlane<E>(rk);
-            const int c = i ^ E;
-            if (act && c < N) {
-                const long off = ((slot * N + i) * N + rc) * 2;
-                evecs[off] = v[E].r;
-                evecs[off + 1] = v[E].i;
-            }
-        });
-    }
+    for (int c = 0; c < N; ++c) evals[slot * N + rk[c]] = s.d[c];
+    if (evecs != nullptr) store_lane_vectors<N, 0>(s, rk, evecs + slot * N * N * 2);
 }
 
 // Larger matrices (8 < n <= 128, e.g. H(k) of a 64-function model, D(q) of a
-// 40-atom cell): one 256-thread workgroup per matrix, the same rotations and
-// convergence test, with the n/2 disjoint rotations of a round (circle-method
+// 40-atom cell): one 256-thread workgroup per matrix, the Jacobi rotations of
+// the header, with the n/2 disjoint rotations of a round (circle-method
 // ordering) applied by all threads at once.  For n <= 64 (k_eig_wg) A and V
 // live in LDS (2 x 65 KB, rows padded by one element) and a round is a column
 // pass and a row pass, three barriers apart; above, see k_eig_wg_packed.  The
@@ -625,13 +469,11 @@ __global__ void k_phonon_omega(long count, double* lam) {
 
 template <typename Tin, bool PK = false>
 void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, double* evecs, hipStream_t st) {
-    const int R = n <= 1 ? 1 : (n <= 2 ? 2 : (n <= 4 ? 4 : 8));
-    const long threads = (long)batch * R;
-    dim3 grid((unsigned)((threads + 255) / 256));
+    dim3 grid((unsigned)(((long)batch + 255) / 256));
     switch (n) {
 #define EPHX_EIG_CASE(NN) \
     case NN:                                                                                                \
-        hipLaunchKernelGGL((k_eig_rows<Tin, NN, PK>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); \
+        hipLaunchKernelGGL((k_eig_lane<Tin, NN, PK>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); \
         break;
         EPHX_EIG_CASE(1)
         EPHX_EIG_CASE(2)
