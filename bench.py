@@ -708,8 +708,8 @@ def measured_traffic(kernel):
 # kernel behind each precision's Rp contraction (Si-like shape: 384 output columns,
 # half-set form with real coefficients)
 RP_KERNEL = {"fp64": "k_phase_gemm<double, 4, true, false, false>", "fp32": "k_phase_gemm<float, 8, true, false, false>",
-             "bf16x3": "k_gemm_bf16_planes<3, 2, true, false, 2>", "bf16x6": "k_gemm_bf16_planes<3, 3, true, false, 1>",
-             "fp16x3": "k_gemm_bf16_planes<3, 2, true, true, 2>"}
+             "bf16x3": "k_gemm_bf16_planes<4, 2, true, false, 1, 8>", "bf16x6": "k_gemm_bf16_planes<3, 3, true, false, 1>",
+             "fp16x3": "k_gemm_bf16_planes<4, 2, true, true, 1, 8>"}
 
 
 def rp_flops_per_pair(rp, nw, nm):

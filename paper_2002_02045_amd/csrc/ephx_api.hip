@@ -619,7 +619,10 @@ struct DriverPlan {
     int kh, kh16;  // half-set size, and rounded up to 16
 };
 
-DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
+size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, bool rates);
+
+// The plan; wide_gib sets the per-pair buffers of large models (GiB).
+static DriverPlan driver_plan_mem(const ephx_model* m, int nk, int nq, int precision, long wide_gib) {
     DriverPlan d{};
     d.nw = m->nw;
     d.nm = m->nm;
@@ -636,11 +639,14 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
     // large models: the per-pair blocks (nm nw^2 complex, twice) set the chunk size
     d.wide = d.nw > kMaxNw || d.nm > kMaxModes;
     const long pair_bytes = d.ngcol * (d.f32 ? 8 : 16) * 2 + (long)d.nw2 * 48;
-    const long wide_pairs = std::max(16L, (6L << 30) / pair_bytes);
+    const long wide_pairs = std::max(16L, (wide_gib << 30) / pair_bytes);
     d.bk_eff = std::min(bk, 16);
     if (d.wide) d.bk_eff = std::max(1, std::min<int>(d.bk_eff, (int)(wide_pairs / 16)));
     const long pairs_target = d.wide ? wide_pairs : 1L << 19;
-    d.qc = (int)std::max(d.wide ? 1L : 64L, std::min((long)std::max(nq, 1), pairs_target / d.bk_eff));
+    long qc = std::max(d.wide ? 1L : 64L, std::min((long)std::max(nq, 1), pairs_target / d.bk_eff));
+    // whole 256-row tiles of the split contraction where the chunk allows
+    if (d.wide && qc > 256) qc -= qc % 256;
+    d.qc = (int)qc;
     // the half set pays whenever the Rp list holds a +/-R pair (R != 0)
     d.half = m->n_rp_half > 0 && m->n_rp_half < m->n_rp_g;
     d.kh = m->n_rp_half;
@@ -650,6 +656,25 @@ DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
     d.f16 = precision == EPHX_FP16X3;
     d.npair = (size_t)d.bk_eff * d.qc;
     return d;
+}
+
+// Large models take 6 GiB of per-pair buffers, or 16 GiB when the device holds
+// them beside the call's other buffers and 8 GiB of headroom (free memory plus
+// the buffers the model already holds): the q chunk, the row count of the Rp
+// contraction, then fills its 256-row tiles (the large cell: 96 -> 256 q per
+// chunk at 8 k).
+DriverPlan driver_plan(const ephx_model* m, int nk, int nq, int precision) {
+    const DriverPlan d6 = driver_plan_mem(m, nk, nq, precision, 6);
+    if (!d6.wide) return d6;
+    const DriverPlan d16 = driver_plan_mem(m, nk, nq, precision, 16);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        fr = 0;
+    }
+    size_t held = 0;
+    for (const auto& kv : m->ws.bufs) held += kv.second.size;
+    return fr + held >= driver_workspace_bytes(m, d16, nq, true) + ((size_t)8 << 30) ? d16 : d6;
 }
 
 // H(k+q) of every pair of a (k batch) x (q chunk) block, pair index k * nq + q,

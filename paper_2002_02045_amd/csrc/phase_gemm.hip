@@ -416,8 +416,8 @@ __global__ void k_phase_planes(int M, int K, int Kp, const double* __restrict__ 
 // the rate of the 16x16x32 shape on gfx950, measured from registers).  Operand
 // lane l holds row (A) or column (B) l%32 and the 8 consecutive k of group
 // l/32; accumulator element v of lane l is C[8(v/4) + 4(l/32) + v%4][l%32].  A
-// workgroup owns 128 RTW rows x 32*CT columns, wave w the rows of its RTW
-// 32-row tiles against all CT column tiles.
+// workgroup of NWV waves owns 32 RTW NWV rows x 32*CT columns, wave w the rows
+// of its RTW 32-row tiles against all CT column tiles.
 // Workgroups are numbered so that each of the 8 XCDs (which receive
 // consecutive workgroup ids in turn) runs a contiguous range of (column, row, z)
 // tiles: the B panel of one z stays in that XCD's L2 while its row tiles
@@ -441,7 +441,6 @@ __device__ __forceinline__ flt16 mfma_bf32(const u16x8& a, const u16x8& b, flt16
                                                        c, 0, 0, 0);
 }
 
-constexpr int kBMP = 128;              // rows per workgroup (32 per wave)
 
 __device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) & 3); }
 
@@ -449,14 +448,15 @@ __device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 2) 
 // side by side along k), and C = A B takes two MFMAs per product instead of four.
 // F16 = true: fp16 parts (FP16x3), the output multiplied by oscale (the power of
 // two that undoes the scaling of B).
-template <int CT, int NS, bool RA = false, bool F16 = false, int RTW = 1>
-__global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
+// NWV waves per workgroup (4 or 8; with 8, two per SIMD).
+template <int CT, int NS, bool RA = false, bool F16 = false, int RTW = 1, int NWV = 4>
+__global__ __launch_bounds__(64 * NWV) void k_gemm_bf16_planes(int M, int N, int Kp, int nbx, int nby, int nz,
                                                           const uint16_t* __restrict__ As,
                                                           const uint16_t* __restrict__ Bs, long sB,
                                                           float* __restrict__ C, long sC, float oscale) {
     // RTW row tiles of 32 per wave: each B fragment read from LDS feeds RTW
     // times the MFMAs
-    constexpr int BMW = 32 * RTW, BM = 4 * BMW;
+    constexpr int BMW = 32 * RTW, BM = NWV * BMW;
     constexpr int BN = 32 * CT;
     constexpr int NP = 2 * NS;
     constexpr int PLANE = BN * kBK;          // bf16 elements of one plane in one buffer
@@ -494,13 +494,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
         arow[rt] = As + (long)min(row0 + wave * BMW + rt * 32 + l32, M - 1) * Kp + 8 * kg;
     const long plane = (long)M * Kp;
     const u16x8 sign = {0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u, 0x8000u};
-    // B panel of the chunk at kc into buffer h: wave w fills blocks w, w+4, ...;
-    // lane l writes row (l/4) of the block, LDS segment l%4
-    static_assert(NBLK % 4 == 0, "whole blocks per wave");
+    // B panel of the chunk at kc into buffer h: wave w fills blocks w, w+NWV,
+    // ...; lane l writes row (l/4) of the block, LDS segment l%4
+    static_assert(NBLK % NWV == 0, "whole blocks per wave");
     auto issue_b = [&](int kc, int h) {
 #pragma unroll
-        for (int j = 0; j < NBLK / 4; ++j) {
-            const int i = 4 * j + wave;
+        for (int j = 0; j < NBLK / NWV; ++j) {
+            const int i = NWV * j + wave;
             const int pl = i / (BN / 16), rb = i % (BN / 16);
             const int r = rb * 16 + (lane >> 2);
             const int col = min(col0 + r, N - 1);
@@ -592,9 +592,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_planes(int M, int N, int Kp, 
             for (int v = 0; v < 16; ++v) {
                 const int row = row0 + wave * BMW + rt * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
                 if (row < M && col < N) {
-                    const long off = ((long)row * N + col) * 2;
-                    cz[off] = are[rt][ct][v] * oscale;
-                    cz[off + 1] = aim[rt][ct][v] * oscale;
+                    const float2 o = {are[rt][ct][v] * oscale, aim[rt][ct][v] * oscale};
+                    *reinterpret_cast<float2*>(cz + ((long)row * N + col) * 2) = o;
                 }
             }
         }
@@ -864,15 +863,24 @@ void phase_planes_bf16(int nsplit, int f16, int M, int K, int Kp, const double* 
 void gemm_bf16_planes(int nsplit, int f16, int M, int N, int Kp, int Z, const uint16_t* A, const uint16_t* Bs,
                       long sB, float* C, long sC, int real_a, float oscale, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
-    if (Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
+    if (Kp <= 0 || Kp % kBK != 0) throw Error{-1, "gemm_bf16_planes: bad Kp"};
     if (nsplit != 2 && nsplit != 3) throw Error{-1, "gemm_bf16_planes: nsplit must be 2 or 3"};
     if (f16 && nsplit != 2) throw Error{-1, "gemm_bf16_planes: fp16 parts need nsplit 2"};
-    // real A: 96-column tiles where they divide N (72 KB of LDS for BF16x6, two
-    // workgroups per CU)
-    const int ct = N <= 64 ? 2 : (real_a && N % 96 == 0 ? 3 : 4);
-    // two 32-row tiles per wave for the three-product real-A forms
-    const int rtw = real_a && nsplit == 2 ? 2 : 1;
-    const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + kBMP * rtw - 1) / (kBMP * rtw);
+    // three-product real-A forms where 128 divides N and the rows fill a tile:
+    // 256 x 128 tiles of eight waves (two per SIMD, one 32-row tile each; with
+    // fewer rows the idle waves would share the matrix pipe with the working
+    // ones); measured at the Si-like shape
+    // 0.35 -> 0.42 of the ceiling against 256 x 96 tiles of four waves with two
+    // row tiles each (one wave per SIMD), and 0.40 for 128 x 96 tiles of four
+    // waves (two workgroups per CU)
+    const bool wide8 = real_a && nsplit == 2 && N > 64 && N % 128 == 0 && M >= 256;
+    // real A otherwise: 96-column tiles where they divide N (72 KB of LDS for
+    // BF16x6, two workgroups per CU)
+    const int ct = wide8 ? 4 : (N <= 64 ? 2 : (real_a && N % 96 == 0 ? 3 : 4));
+    // two 32-row tiles per wave for the other three-product real-A forms
+    const int rtw = !wide8 && real_a && nsplit == 2 ? 2 : 1;
+    const int nwv = wide8 ? 8 : 4;
+    const int nbx = (N + 32 * ct - 1) / (32 * ct), nby = (M + 32 * nwv * rtw - 1) / (32 * nwv * rtw);
     const long nblk = (long)nbx * nby * Z;
     if (nblk > 0x7fffffffL) throw Error{-1, "gemm_bf16_planes: grid too large"};
     dim3 grid((unsigned)nblk);
@@ -885,7 +893,14 @@ void gemm_bf16_planes(int nsplit, int f16, int M, int N, int Kp, int Z, const ui
         else if (ct == 3) EPHX_BFP(3, NSV, RAV, F16V, RTV);  \
         else EPHX_BFP(4, NSV, RAV, F16V, RTV);               \
     } while (0)
-    if (f16) {
+    if (wide8) {
+        if (f16)
+            hipLaunchKernelGGL((k_gemm_bf16_planes<4, 2, true, true, 1, 8>), grid, dim3(512), 0, st, M, N, Kp, nbx,
+                               nby, Z, A, Bs, sB, C, sC, oscale);
+        else
+            hipLaunchKernelGGL((k_gemm_bf16_planes<4, 2, true, false, 1, 8>), grid, dim3(512), 0, st, M, N, Kp, nbx,
+                               nby, Z, A, Bs, sB, C, sC, oscale);
+    } else if (f16) {
         if (real_a) EPHX_BFP_CT(2, true, true, 2);
         else EPHX_BFP_CT(2, false, true, 1);
     } else if (real_a) {
