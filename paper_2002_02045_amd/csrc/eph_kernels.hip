@@ -13,6 +13,8 @@ inline void check_launch(const char* what) {
     if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 struct cx {
     T x, y;
@@ -539,6 +541,189 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
     }
 }
 
+// The rates epilogue of the FP32 paths for Nw = 8 bands and 6 modes on the
+// matrix cores.  One wavefront walks kQPB pairs of one k; per pair
+//   rotation   X[x][m][n] = sum_i conj(U_im(k+q)) g'[x][i][n]
+// is a real 16 x 16 by 16 x 48 product (rows (m, re|im), contraction (i, re|im),
+// columns (x, n)): 12 v_mfma_f32_16x16x4f32 with both operands loaded in
+// operand layout (A from U(k+q), B from g'); X goes through LDS to the layout
+//   projection g[nu][m][n] = sum_x es[x][nu] X[x][m][n]
+// needs, a 12 x 12 by 12 x 64 real product (rows (nu, re|im), contraction
+// (x, re|im), columns (m, n)): 12 more MFMAs (rows 12..15 zero).  Lane l then
+// holds g for modes 2(l/16), 2(l/16)+1 at the columns (m, n), n = l%8, of
+// its four column blocks, and forms |g|^2 and the Gaussian-weighted terms
+// for its k-side band n; the lanes l, l^8 (the two halves of m) are summed in
+// fixed order.  Same sums as k_eph_epilogue<float, true, 8, 6> (the products'
+// rounding differs); no long-range term, no part selection.
+// The kernel is bound by reading g' and U (3.5 KB per pair): each wavefront
+// keeps kEpiDepth pairs' operands in flight in a register ring, and the
+// pair's few band and mode values (energies, occupations, omega, Bose factors,
+// the q weight) are wavefront-uniform scalar loads, outside that ring.
+constexpr int kEpiDepth = 4;
+static_assert(kQPB % kEpiDepth == 0, "whole ring turns per workgroup");
+
+// read-only, wavefront-uniform values through the constant address space:
+// scalar loads, counted apart from the vector loads in flight
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p, long i) {
+    return reinterpret_cast<const __attribute__((address_space(4))) T*>(reinterpret_cast<uintptr_t>(p))[i];
+}
+
+struct EpiOperands {
+    float2 ga[3], gb[3];   // g'[2 cb + l%16/8][l/16 (+4)][l%8] (re, im)
+    double2 ua, ub;        // U[l/16 (+4)][l%8] (re, im)
+    cx<float> es[3];       // es[(4 ks + l/16)/2][l%16/2]
+};
+
+__global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
+    constexpr int NW = 8, NM = 6, GSZ = NM * NW * NW * 2;   // floats of one pair's g'
+    constexpr int XLD = 65;                                 // LDS row stride of X
+    __shared__ float xs[12 * XLD];
+    const int z = blockIdx.y, blk = blockIdx.x, lane = threadIdx.x;
+    const int q0 = blk * kQPB, q1 = min(e.nq, q0 + kQPB);
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int pm = l16 >> 3, n = l16 & 7;      // column parity bit, k-side band
+    const int mr = l16 & 7;                    // rotation row: band m of row l16
+    const bool ci_r = l16 >= 8;                // rotation row holds the imaginary part
+    const int nup = l16 >> 1, co = l16 & 1;    // projection row: mode, re|im
+    const bool rv = l16 < 12;
+    const int ci = lg & 1;                     // projection contraction index: re|im of X
+    const int nupc = min(nup, NM - 1);
+    const float* gwz = reinterpret_cast<const float*>(e.gw) + (long)z * e.nq * GSZ;
+    const cx<float>* esq = reinterpret_cast<const cx<float>*>(e.esq);
+    const double en = e.ek[(long)z * NW + n];
+    const float is = (float)(1.0 / e.sigma);
+    double acc[2] = {0.0, 0.0};
+    EpiOperands ring[kEpiDepth];
+    // loads of pair ql (any pair of the block: past the last one they are
+    // never used), unconditional so every pair waits only for its own
+    auto fetch = [&](int ql, EpiOperands& o) {
+        const float* gp = gwz + (long)ql * GSZ;
+#pragma unroll
+        for (int cb = 0; cb < 3; ++cb) {
+            const int x = 2 * cb + pm;
+            o.ga[cb] = *reinterpret_cast<const float2*>(gp + ((x * NW + lg) * NW + n) * 2);
+            o.gb[cb] = *reinterpret_cast<const float2*>(gp + ((x * NW + 4 + lg) * NW + n) * 2);
+        }
+        const double* uq = e.ukq + ((long)z * e.nq + ql) * NW * NW * 2;
+        o.ua = *reinterpret_cast<const double2*>(uq + (lg * NW + mr) * 2);
+        o.ub = *reinterpret_cast<const double2*>(uq + ((4 + lg) * NW + mr) * 2);
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks) o.es[ks] = esq[(long)ql * NM * NM + ((4 * ks + lg) >> 1) * NM + nupc];
+    };
+    auto pair_step = [&](int ql, EpiOperands& o) {
+        // rotation from the ring slot, then the slot refilled (its values are
+        // consumed by the issued products and the projection operands)
+        const float uar = (float)o.ua.x, uai = (float)o.ua.y, ubr = (float)o.ub.x, ubi = (float)o.ub.y;
+        const float a[4] = {ci_r ? -uai : uar, ci_r ? -ubi : ubr, ci_r ? uar : uai, ci_r ? ubr : ubi};
+        flt4 xr[3];
+#pragma unroll
+        for (int cb = 0; cb < 3; ++cb) {
+            xr[cb] = flt4{0.f, 0.f, 0.f, 0.f};
+            xr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], o.ga[cb].x, xr[cb], 0, 0, 0);
+            xr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], o.gb[cb].x, xr[cb], 0, 0, 0);
+            xr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], o.ga[cb].y, xr[cb], 0, 0, 0);
+            xr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], o.gb[cb].y, xr[cb], 0, 0, 0);
+        }
+        float pa[3];
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks) {
+            const cx<float> es = o.es[ks];
+            pa[ks] = !rv ? 0.f : (co == 0 ? (ci == 0 ? es.x : -es.y) : (ci == 0 ? es.y : es.x));
+        }
+        fetch(min(ql + kEpiDepth, q1 - 1), o);
+        if (ql >= q1) return;   // uniform: past the block's last pair
+        // band and mode values of the pair: uniform loads, converted once per
+        // pair to what this lane uses: eps_n(k) - eps_m(k+q) and f_m(k+q) for
+        // its four m, omega and the Bose factor of its two modes
+        const long pair = (long)z * e.nq + ql, qg = (long)e.q_off + ql;
+        float dm[4], fmf[4], omf[2], nbf[2];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double e0 = ld_uniform(e.ekq, pair * NW + 2 * cb), e1 = ld_uniform(e.ekq, pair * NW + 2 * cb + 1);
+            const double f0 = ld_uniform(e.fkq, pair * NW + 2 * cb), f1 = ld_uniform(e.fkq, pair * NW + 2 * cb + 1);
+            dm[cb] = (float)(en - (pm ? e1 : e0));
+            fmf[cb] = (float)(pm ? f1 : f0);
+        }
+        bool live[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double omj = ld_uniform(e.omega, qg * NM + j), nbj = ld_uniform(e.nbq, (long)ql * NM + j);
+#pragma unroll
+            for (int nu = 2 + j; nu < NM; nu += 2) {
+                const double o2 = ld_uniform(e.omega, qg * NM + nu), b2 = ld_uniform(e.nbq, (long)ql * NM + nu);
+                if (nu == 2 * lg + j) {
+                    omj = o2;
+                    nbj = b2;
+                }
+            }
+            live[j] = omj > e.omega_cut;
+            omf[j] = (float)omj;
+            nbf[j] = (float)nbj;
+        }
+        const double wq = e.qw ? ld_uniform(e.qw, qg) : e.uniform_w;
+        // X[x][m][n] (re|im) to LDS as row 2x + (re|im), column 8m + n; element v
+        // of lane l is row 4(l/16) + v of the rotation, i.e. m = (4 l/16 + v) % 8
+        // and re|im = l/32
+#pragma unroll
+        for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 4 * lg + v;
+                xs[(2 * (2 * cb + pm) + (r >> 3)) * XLD + 8 * (r & 7) + n] = xr[cb][v];
+            }
+        // the workgroup is one wavefront: its LDS writes are complete once its
+        // LDS counter drains (a __syncthreads() here would also wait for the
+        // loads in flight)
+        __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        flt4 gr[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            gr[cb] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 3; ++ks)
+                gr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[ks], xs[(4 * ks + lg) * XLD + 16 * cb + l16], gr[cb], 0,
+                                                              0, 0);
+        }
+        // element v of lane l: mode 2 (l/16) + v/2, re|im = v%2, column (m, n) =
+        // (2 cb + l%16 / 8, l%8); lanes with l/16 = 3 hold the zero rows.
+        // exp(-x^2) = 2^-(x sqrt(log2 e))^2; below 2^-126 it is zero or
+        // subnormal, as the cut at (x/sigma)^2 > 200 of the FP64 path
+        if (lg < 3) {
+            const float isl = is * 1.2011224087864498f;   // sqrt(log2 e) / sigma
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!live[j]) continue;
+                float t = 0.f;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const float g2 = gr[cb][2 * j] * gr[cb][2 * j] + gr[cb][2 * j + 1] * gr[cb][2 * j + 1];
+                    const float x1 = (dm[cb] - omf[j]) * isl, x2 = (dm[cb] + omf[j]) * isl;
+                    const float d1 = __builtin_amdgcn_exp2f(-x1 * x1), d2 = __builtin_amdgcn_exp2f(-x2 * x2);
+                    t += g2 * (d1 * (1.f + nbf[j] - fmf[cb]) + d2 * (nbf[j] + fmf[cb]));
+                }
+                acc[j] += wq * (double)t;
+            }
+        }
+    };
+    if (q0 < q1) {
+#pragma unroll
+        for (int j = 0; j < kEpiDepth; ++j) fetch(min(q0 + j, q1 - 1), ring[j]);
+        for (int g0 = q0; g0 < q0 + kQPB; g0 += kEpiDepth) {
+#pragma unroll
+            for (int j = 0; j < kEpiDepth; ++j) pair_step(g0 + j, ring[j]);
+        }
+    }
+    // the two halves of m (lanes l and l^8), then partial[z][blk][n][nu]
+    const double nrm = 1.0 / (sqrt(kPi) * e.sigma);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 8, 64);
+    if (pm == 0 && lg < 3)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            e.partial[(((long)z * e.nblk + blk) * NW + n) * NM + 2 * lg + j] = acc[j] * nrm * (2.0 * kPi / kHbarEvFs);
+}
+
 template <typename T, bool RATES>
 void launch_epilogue(const EphEpilogue& e, dim3 grid, size_t lds, hipStream_t st) {
     // the fixed-size instances read the precomputed factors; without them the
@@ -919,6 +1104,12 @@ void eph_epilogue_factors(const EphEpilogue& e, int f32, void* esq, double* nbq,
 
 void eph_epilogue_rates(const EphEpilogue& e, int f32, hipStream_t st) {
     dim3 grid(eph_epilogue_blocks(e.nq), e.nkb);
+    if (f32 && e.nw == 8 && e.nm == 6 && e.lr == nullptr && e.part == 0 && e.esq != nullptr && e.nbq != nullptr &&
+        e.fkq != nullptr) {
+        hipLaunchKernelGGL(k_eph_rates_mfma, grid, dim3(64), 0, st, e);
+        check_launch("eph_epilogue_rates");
+        return;
+    }
     const size_t lds = f32 ? epilogue_lds<float>(e.nw, e.nm) : epilogue_lds<double>(e.nw, e.nm);
     if (lds > 65536) throw Error{-6, "rates: nw^2 * 3nat too large for one workgroup's staging buffer"};
     if (f32) launch_epilogue<float, true>(e, grid, lds, st);
