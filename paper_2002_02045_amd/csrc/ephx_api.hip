@@ -689,7 +689,8 @@ static void hkq_fourier(ephx_model* m, int nb, const double* kb, const double* h
                         double* hkq, hipStream_t st) {
     const int nw2 = m->nw * m->nw;
     if (m->d_h_pack)
-        phase_gemm_herm_groups_f64(nq, nb, m->h_pack, m->n_re_half, qb, m->d_re_half, hfold, hkq, st);
+        phase_gemm_herm_groups_f64(nq, nb, m->h_pack, m->n_re_half, qb, m->d_re_half, hfold, hkq,
+                                   (double*)m->ws.get("hkq.ptab", (size_t)nq * m->n_re_half * 16), st);
     else
         phase_gemm_herm_f64(nq, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, hkq, (long)nq * nw2, st);
 }
@@ -721,6 +722,7 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
     }
     b += d.npair * (nw2 * 16 + nw * 8 + nw2 * 16);                        // H(k+q), eps, U
     b += hfold_bytes(m, d.bk_eff);                                        // k-folded half set
+    if (m->d_h_pack) b += (size_t)d.qc * m->n_re_half * 16;                  // phase table of H(k+q)
     b += d.npair * d.ngcol * (d.f32 ? 8 : 16) * (d.wide ? 2 : 1);         // g^W (and g^H)
     if (d.wide) b += (size_t)d.qc * nm * nm * 16 + (m->polar ? d.npair * nw2 * 16 : 0);
     if (rates) b += (size_t)d.bk_eff * eph_epilogue_blocks(d.qc) * nw * nm * 8 + (size_t)d.bk_eff * nw * nm * 8;

@@ -56,11 +56,12 @@ void phase_gemm_herm_f64(int M, int N, int Kh, int Z, const double* x, const dou
 //  fold_herm_f64: hpack [Kh][2][P] (packed A_r, B_r; P = n*n rounded up to even)
 //    -> out [Kh][2][nk][P], the coefficients of the sum at k + q as a sum over q;
 //  phase_gemm_herm_groups_f64: C [nk][M][P] = sum_r cos/sin(2 pi x_m.n_r) out_r,
-//    one phase per (m, r) for all nk matrices (B given as [Kh][2][nk*P/2] complex).
+//    one phase per (m, r) for all nk matrices (B given as [Kh][2][nk*P/2] complex);
+//    tab: work buffer of M * Kh * 16 bytes (the phase table).
 void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int P, const double* hpack, double* out,
                    hipStream_t st);
 void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
-                                double* C, hipStream_t st);
+                                double* C, double* tab, hipStream_t st);
 // phase_gemm_f64 with a complex-float B (FP64 arithmetic; B widened on load)
 void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
                         const float* B, long sB, double* C, long sC, hipStream_t st);

@@ -71,8 +71,12 @@ constexpr int kKC = 16;
 // over a complex-float coupling tensor).  WC = true (few rows, M <= 16): the
 // four waves take the same 16 rows and four consecutive column blocks, so a
 // workgroup covers 16 rows x 64 CB columns instead of padding M to 64 rows.
+// PT = true: the phases come from a table [M][K] of (cos, sin) that x0 points
+// to (filled by k_phase_table with the same expression, so the same values),
+// each lane loading its four of a chunk one chunk ahead, instead of every
+// column block of the launch generating them again.
 template <typename T, int CB, bool HERM = false, bool KD = false, bool ACC = false, typename TB = T,
-          bool WC = false>
+          bool WC = false, bool PT = false>
 __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const double* __restrict__ x,
                                                     const double* __restrict__ x0,
                                                     const void* __restrict__ nvec_,
@@ -108,11 +112,20 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
         xb = x[3 * arow + 1];
         xc = x[3 * arow + 2];
     }
-    if (x0 != nullptr) {
+    if (!PT && x0 != nullptr) {
         xa += x0[3 * z];
         xb += x0[3 * z + 1];
         xc += x0[3 * z + 2];
     }
+    // PT: this lane's (cos, sin) for the four k-steps of a chunk
+    const double2* tab = reinterpret_cast<const double2*>(x0);
+    const long trow = (long)min(arow, M - 1) * K;
+    double2 tph[kKC / 4];
+    auto load_ph = [&](int kc) {
+#pragma unroll
+        for (int s = 0; s < kKC / 4; ++s) tph[s] = tab[trow + min(kc + 4 * s + lk, K - 1)];
+    };
+    if (PT && K > 0) load_ph(0);
 
     acc_t are[CB], aim[CB];
 #pragma unroll
@@ -142,11 +155,24 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
             ns[kk][d] = (kc + kk < K) ? nvec[3 * (kc + kk) + d] : 0;
         }
         __syncthreads();
+        double2 cph[kKC / 4];
+        if (PT) {
+#pragma unroll
+            for (int s = 0; s < kKC / 4; ++s) cph[s] = tph[s];
+            if (kc + kKC < K) load_ph(kc + kKC);
+        }
 #pragma unroll
         for (int s = 0; s < kKC / 4; ++s) {
             const int kk = 4 * s + lk;
             T pc = 0, ps = 0;
-            if (rowok && kc + kk < K) phase_of(reduced_arg(xa, xb, xc, ns[kk]), pc, ps);
+            if (rowok && kc + kk < K) {
+                if (PT) {
+                    pc = (T)cph[s].x;
+                    ps = (T)cph[s].y;
+                } else {
+                    phase_of(reduced_arg(xa, xb, xc, ns[kk]), pc, ps);
+                }
+            }
             const T nps = -ps;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
@@ -714,6 +740,18 @@ __global__ void k_fold_herm(int nk, const double* __restrict__ kpts, int Kh, con
     out[(((long)r * 2 + 1) * nk + kk) * P + e] = fma(c, b, -s * a);
 }
 
+// Phase table of one point set against a vector list: tab[m][r] =
+// (cos, sin)(2 pi x_m . n_r), the argument reduced in FP64 as in the sums.
+__global__ void k_phase_table(int M, int K, const double* __restrict__ x, const int32_t* __restrict__ nvec,
+                              double2* __restrict__ tab) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)M * K) return;
+    const int m = (int)(t / K), r = (int)(t % K);
+    double c, s;
+    phase_of(reduced_arg(x[3L * m], x[3L * m + 1], x[3L * m + 2], nvec + 3L * r), c, s);
+    tab[t] = double2{c, s};
+}
+
 inline void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string(what) + ": " + hipGetErrorString(e)};
@@ -787,15 +825,19 @@ void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int 
 }
 
 void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
-                                double* C, hipStream_t st) {
+                                double* C, double* tab, hipStream_t st) {
     if (M <= 0 || nk <= 0 || Kh <= 0) return;
     if (P <= 0 || P % 2 != 0) throw Error{-1, "phase_gemm_herm_groups_f64: P must be even"};
     const int cg = P / 2, N = nk * cg;
+    // the rows' phases once (every column block of the launch reads them)
+    const long nt = (long)M * Kh;
+    hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, M, Kh, x, nvec,
+                       reinterpret_cast<double2*>(tab));
     // column blocks fastest: the 8 XCDs take the blocks in turn, so each XCD
     // reads the coefficients of a fixed subset of the k
     dim3 grid((N + 63) / 64, (M + kBM - 1) / kBM, 1);
-    hipLaunchKernelGGL((k_phase_gemm<double, 4, true>), grid, dim3(256), 0, st, M, N, Kh, x, (const double*)nullptr,
-                       nvec, B, 0L, C, 0L, cg);
+    hipLaunchKernelGGL((k_phase_gemm<double, 4, true, false, false, double, false, true>), grid, dim3(256), 0, st, M,
+                       N, Kh, x, (const double*)tab, nvec, B, 0L, C, 0L, cg);
     check_launch("phase_gemm_herm_groups_f64");
 }
 
