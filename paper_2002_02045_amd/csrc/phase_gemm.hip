@@ -134,20 +134,21 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
         aim[cb] = acc_t{0, 0, 0, 0};
     }
 
+    typedef TB tb2 __attribute__((ext_vector_type(2)));
     for (int kc = 0; kc < K; kc += kKC) {
+        // rows past K and columns past N load the last valid one (a row past K
+        // meets a zero phase, a column past N is never stored): no branch, one
+        // (re, im) load per element and plane
+        static_assert(kKC * WBN % 256 == 0, "whole elements per thread");
+#pragma unroll
         for (int e = tid; e < kKC * WBN; e += 256) {
             const int kk = e / WBN, nn = e % WBN;
-            const int r = kc + kk, col = col0 + nn;
+            const long r = min(kc + kk, K - 1), col = min(col0 + nn, N - 1);
 #pragma unroll
             for (int h = 0; h < NB; ++h) {
-                T re = 0, im = 0;
-                if (r < K && col < N) {
-                    const long off = (((long)r * NB + h) * N + col) * 2;
-                    re = (T)bz[off];
-                    im = (T)bz[off + 1];
-                }
-                bs[kk][2 * h][nn] = re;
-                bs[kk][2 * h + 1][nn] = im;
+                const tb2 v = *reinterpret_cast<const tb2*>(bz + ((r * NB + h) * N + col) * 2);
+                bs[kk][2 * h][nn] = (T)v.x;
+                bs[kk][2 * h + 1][nn] = (T)v.y;
             }
         }
         if (tid < kKC * 3) {
