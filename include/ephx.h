@@ -19,7 +19,9 @@
  *  - k and q points are reduced (crystal) coordinates, double[n][3].
  *  - Complex arrays are interleaved (re, im) doubles or floats, row-major.
  *  - "device" arrays are owned by the caller, allocated on the current HIP
- *    device, contiguous and row-major; "host" arrays are ordinary host memory.
+ *    device, contiguous, row-major and 16-byte aligned (as hipMalloc and
+ *    torch allocate them: kernels move complex doubles as 16-byte vectors);
+ *    "host" arrays are ordinary host memory.
  *  - The library owns the opaque handles (ephx_model, ephx_table), their
  *    device copies and their work buffers; release them with *_destroy.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Every

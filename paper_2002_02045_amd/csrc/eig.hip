@@ -53,10 +53,7 @@ __device__ __forceinline__ void store_lane_vectors(const HermLane<N>& s, const i
         double xr[N], xi[N];
         herm_eigenvector<N, C>(s, xr, xi);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            out[(i * N + rk[C]) * 2] = xr[i];
-            out[(i * N + rk[C]) * 2 + 1] = xi[i];
-        }
+        for (int i = 0; i < N; ++i) *reinterpret_cast<double2*>(out + (i * N + rk[C]) * 2) = double2{xr[i], xi[i]};
         store_lane_vectors<N, C + 1>(s, rk, out);
     }
 }

@@ -113,7 +113,10 @@ __host__ __device__ __forceinline__ void herm_tridiagonalize(HermLane<N>& s) {
 }
 
 // Implicit QL iterations deflating row l; e[m] counts as zero once
-// |e[m]| <= 2^-53 (|d[m]| + |d[m+1]|).
+// |e[m]| <= 2^-53 (|d[m]| + |d[m+1]|).  Every update is a select on the
+// lane's predicates, and the sweep's rotations reach Z after the sweep, one
+// row of Z at a time: written so, the compiler keeps one copy of Z and no
+// copies of it at the joins of the predicated code.
 template <class MathT, int N, int L>
 __host__ __device__ __forceinline__ void ql_deflate(double (&d)[N], double (&e)[N], double (&z)[N][N], int max_iter) {
     if constexpr (L < N - 1) {
@@ -121,19 +124,19 @@ __host__ __device__ __forceinline__ void ql_deflate(double (&d)[N], double (&e)[
             int m = N - 1;
 #pragma unroll
             for (int mm = N - 2; mm >= L; --mm)
-                if (fabs(e[mm]) <= 1.1102230246251565e-16 * (fabs(d[mm]) + fabs(d[mm + 1]))) m = mm;
+                m = fabs(e[mm]) <= 1.1102230246251565e-16 * (fabs(d[mm]) + fabs(d[mm + 1])) ? mm : m;
             const bool act = m != L;
             if (!MathT::any(act)) break;
             double dm = d[N - 1];
 #pragma unroll
-            for (int mm = L; mm < N - 1; ++mm)
-                if (m == mm) dm = d[mm];
+            for (int mm = L; mm < N - 1; ++mm) dm = m == mm ? d[mm] : dm;
             // Wilkinson shift from the leading 2x2 block of [L, m]
             const double el = act ? e[L] : 1.0;
             double g = (d[L + 1] - d[L]) * MathT::rcp(2.0 * el);
             const double r = (g * g + 1.0) * MathT::rsqrt(g * g + 1.0);
             g = dm - d[L] + el * MathT::rcp(g + (g >= 0.0 ? r : -r));
             double sn = 1.0, cs = 1.0, p = 0.0;
+            double zs[N - 1], zc[N - 1];
             bool brk = false;
 #pragma unroll
             for (int i = N - 2; i >= L; --i) {
@@ -147,32 +150,31 @@ __host__ __device__ __forceinline__ void ql_deflate(double (&d)[N], double (&e)[
                 const double g1 = d[i + 1] - p;
                 const double q1 = (d[i] - g1) * s1 + 2.0 * c1 * b;
                 const double p1 = s1 * q1;
-                if (upd) {
-                    e[i + 1] = r2 * ir;
-                    sn = s1;
-                    cs = c1;
-                    d[i + 1] = g1 + p1;
-                    p = p1;
-                    g = c1 * q1 - b;
-                }
-                if (zero) d[i + 1] -= p;
+                e[i + 1] = upd ? r2 * ir : e[i + 1];
+                d[i + 1] = upd ? g1 + p1 : (zero ? d[i + 1] - p : d[i + 1]);
+                sn = upd ? s1 : sn;
+                cs = upd ? c1 : cs;
+                p = upd ? p1 : p;
+                g = upd ? c1 * q1 - b : g;
                 brk = brk || zero;
-                const double zs = upd ? s1 : 0.0, zc = upd ? c1 : 1.0;
+                zs[i] = upd ? s1 : 0.0;
+                zc[i] = upd ? c1 : 1.0;
+            }
+            // the sweep's rotations applied to the rows of Z, one row at a time
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
+            for (int k = 0; k < N; ++k)
+#pragma unroll
+                for (int i = N - 2; i >= L; --i) {
                     const double zf = z[k][i + 1];
-                    z[k][i + 1] = zs * z[k][i] + zc * zf;
-                    z[k][i] = zc * z[k][i] - zs * zf;
+                    z[k][i + 1] = zs[i] * z[k][i] + zc[i] * zf;
+                    z[k][i] = zc[i] * z[k][i] - zs[i] * zf;
                 }
-            }
-            if (act && !brk) {
-                d[L] -= p;
-                e[L] = g;
-            }
+            const bool fin = act && !brk;
+            d[L] = fin ? d[L] - p : d[L];
+            e[L] = fin ? g : e[L];
             // e[m] is zero after the sweep, completed or cut short
 #pragma unroll
-            for (int mm = L + 1; mm < N; ++mm)
-                if (act && m == mm) e[mm] = 0.0;
+            for (int mm = L + 1; mm < N; ++mm) e[mm] = act && m == mm ? 0.0 : e[mm];
         }
         ql_deflate<MathT, N, L + 1>(d, e, z, max_iter);
     }

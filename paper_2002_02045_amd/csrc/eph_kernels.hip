@@ -555,12 +555,22 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 // for its k-side band n; the lanes l, l^8 (the two halves of m) are summed in
 // fixed order.  Same sums as k_eph_epilogue<float, true, 8, 6> (the products'
 // rounding differs); no long-range term, no part selection.
-// The kernel is bound by reading g' and U (3.5 KB per pair): each wavefront
-// keeps kEpiDepth pairs' operands in flight in a register ring, and the
-// pair's few band and mode values (energies, occupations, omega, Bose factors,
-// the q weight) are wavefront-uniform scalar loads, outside that ring.
+// Each wavefront keeps kEpiDepth pairs' operands in flight in a register
+// ring.  A pair's band and mode values (energies, Fermi and Bose factors,
+// omega) reach the lanes through LDS: each lane loads one of them, converts
+// it and writes it where the lanes that use it read it as one vector, so no
+// lane selects among wavefront-uniform values.
 constexpr int kEpiDepth = 4;
 static_assert(kQPB % kEpiDepth == 0, "whole ring turns per workgroup");
+
+// LDS staging of a pair's band and mode values, in floats:
+//   [0, 64)   eps_n(k) - eps_m(k+q) at ((m % 2) 8 + n) 4 + m / 2, so that lane
+//             (m % 2, n) reads its four m = 2 cb + m % 2 as one float4
+//   [64, 72)  f_m(k+q) at (m % 2) 4 + m / 2
+//   [72, 78)  omega_nu; [78, 84) Bose factor n_nu; [84, 90) 1 if omega_nu is
+//             above the cut, else 0 (lane group lg reads nu = 2 lg, 2 lg + 1)
+//   95        written by lanes that carry no value
+constexpr int kPsD = 0, kPsF = 64, kPsOm = 72, kPsNb = 78, kPsLive = 84, kPsDump = 95, kPsLen = 96;
 
 // read-only, wavefront-uniform values through the constant address space:
 // scalar loads, counted apart from the vector loads in flight
@@ -572,13 +582,16 @@ __device__ __forceinline__ T ld_uniform(const T* p, long i) {
 struct EpiOperands {
     float2 ga[3], gb[3];   // g'[2 cb + l%16/8][l/16 (+4)][l%8] (re, im)
     double2 ua, ub;        // U[l/16 (+4)][l%8] (re, im)
-    cx<float> es[3];       // es[(4 ks + l/16)/2][l%16/2]
+    float es[3];           // the one component of es[(4 ks + l/16)/2][l%16/2] lane l multiplies
+    double em;             // eps_{l/8}(k+q)
+    double sv;             // f_l(k+q) (l < 8), omega_{l-16} (16 <= l < 22), n_{l-24} (24 <= l < 30)
 };
 
 __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
     constexpr int NW = 8, NM = 6, GSZ = NM * NW * NW * 2;   // floats of one pair's g'
     constexpr int XLD = 65;                                 // LDS row stride of X
     __shared__ float xs[12 * XLD];
+    __shared__ __align__(16) float ps[kPsLen];
     const int z = blockIdx.y, blk = blockIdx.x, lane = threadIdx.x;
     const int q0 = blk * kQPB, q1 = min(e.nq, q0 + kQPB);
     const int l16 = lane & 15, lg = lane >> 4;
@@ -589,8 +602,36 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
     const bool rv = l16 < 12;
     const int ci = lg & 1;                     // projection contraction index: re|im of X
     const int nupc = min(nup, NM - 1);
+    // projection operand: component co ^ ci of es, negated for (re row, im part)
+    const int esc = co ^ ci;
+    const float ess = co == 0 && ci == 1 ? -1.f : 1.f;
     const float* gwz = reinterpret_cast<const float*>(e.gw) + (long)z * e.nq * GSZ;
-    const cx<float>* esq = reinterpret_cast<const cx<float>*>(e.esq);
+    const float* esq = reinterpret_cast<const float*>(e.esq);
+    // staging roles: lane l forms eps_n(k) - eps_m(k+q) for m = l/8, n = l%8,
+    // and carries one small value (see EpiOperands::sv)
+    const int mst = lane >> 3;
+    const int dst_d = kPsD + ((mst & 1) * 8 + n) * 4 + (mst >> 1);
+    const double* svb;
+    long svs;
+    int dst_v;
+    if (lane < 8) {
+        svb = e.fkq + (long)z * e.nq * NW + lane;
+        svs = NW;
+        dst_v = kPsF + (lane & 1) * 4 + (lane >> 1);
+    } else if (lane >= 16 && lane < 22) {
+        svb = e.omega + (long)e.q_off * NM + (lane - 16);
+        svs = NM;
+        dst_v = kPsOm + lane - 16;
+    } else if (lane >= 24 && lane < 30) {
+        svb = e.nbq + (lane - 24);
+        svs = NM;
+        dst_v = kPsNb + lane - 24;
+    } else {
+        svb = e.fkq + (long)z * e.nq * NW + (lane & 7);
+        svs = NW;
+        dst_v = kPsDump;
+    }
+    const int dst_l = lane >= 16 && lane < 22 ? kPsLive + lane - 16 : kPsDump;
     const double en = e.ek[(long)z * NW + n];
     const float is = (float)(1.0 / e.sigma);
     double acc[2] = {0.0, 0.0};
@@ -605,15 +646,18 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
             o.ga[cb] = *reinterpret_cast<const float2*>(gp + ((x * NW + lg) * NW + n) * 2);
             o.gb[cb] = *reinterpret_cast<const float2*>(gp + ((x * NW + 4 + lg) * NW + n) * 2);
         }
-        const double* uq = e.ukq + ((long)z * e.nq + ql) * NW * NW * 2;
+        const long pair = (long)z * e.nq + ql;
+        const double* uq = e.ukq + pair * NW * NW * 2;
         o.ua = *reinterpret_cast<const double2*>(uq + (lg * NW + mr) * 2);
         o.ub = *reinterpret_cast<const double2*>(uq + ((4 + lg) * NW + mr) * 2);
 #pragma unroll
-        for (int ks = 0; ks < 3; ++ks) o.es[ks] = esq[(long)ql * NM * NM + ((4 * ks + lg) >> 1) * NM + nupc];
+        for (int ks = 0; ks < 3; ++ks) o.es[ks] = esq[((long)ql * NM * NM + ((4 * ks + lg) >> 1) * NM + nupc) * 2 + esc];
+        o.em = e.ekq[pair * NW + mst];
+        o.sv = svb[(long)ql * svs];
     };
     auto pair_step = [&](int ql, EpiOperands& o) {
         // rotation from the ring slot, then the slot refilled (its values are
-        // consumed by the issued products and the projection operands)
+        // consumed by the issued products and the staging below)
         const float uar = (float)o.ua.x, uai = (float)o.ua.y, ubr = (float)o.ub.x, ubi = (float)o.ub.y;
         const float a[4] = {ci_r ? -uai : uar, ci_r ? -ubi : ubr, ci_r ? uar : uai, ci_r ? ubr : ubi};
         flt4 xr[3];
@@ -627,41 +671,11 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
         }
         float pa[3];
 #pragma unroll
-        for (int ks = 0; ks < 3; ++ks) {
-            const cx<float> es = o.es[ks];
-            pa[ks] = !rv ? 0.f : (co == 0 ? (ci == 0 ? es.x : -es.y) : (ci == 0 ? es.y : es.x));
-        }
+        for (int ks = 0; ks < 3; ++ks) pa[ks] = rv ? ess * o.es[ks] : 0.f;
+        const float dv = (float)(en - o.em), sv = (float)o.sv, lv = o.sv > e.omega_cut ? 1.f : 0.f;
         fetch(min(ql + kEpiDepth, q1 - 1), o);
         if (ql >= q1) return;   // uniform: past the block's last pair
-        // band and mode values of the pair: uniform loads, converted once per
-        // pair to what this lane uses: eps_n(k) - eps_m(k+q) and f_m(k+q) for
-        // its four m, omega and the Bose factor of its two modes
-        const long pair = (long)z * e.nq + ql, qg = (long)e.q_off + ql;
-        float dm[4], fmf[4], omf[2], nbf[2];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const double e0 = ld_uniform(e.ekq, pair * NW + 2 * cb), e1 = ld_uniform(e.ekq, pair * NW + 2 * cb + 1);
-            const double f0 = ld_uniform(e.fkq, pair * NW + 2 * cb), f1 = ld_uniform(e.fkq, pair * NW + 2 * cb + 1);
-            dm[cb] = (float)(en - (pm ? e1 : e0));
-            fmf[cb] = (float)(pm ? f1 : f0);
-        }
-        bool live[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            double omj = ld_uniform(e.omega, qg * NM + j), nbj = ld_uniform(e.nbq, (long)ql * NM + j);
-#pragma unroll
-            for (int nu = 2 + j; nu < NM; nu += 2) {
-                const double o2 = ld_uniform(e.omega, qg * NM + nu), b2 = ld_uniform(e.nbq, (long)ql * NM + nu);
-                if (nu == 2 * lg + j) {
-                    omj = o2;
-                    nbj = b2;
-                }
-            }
-            live[j] = omj > e.omega_cut;
-            omf[j] = (float)omj;
-            nbf[j] = (float)nbj;
-        }
-        const double wq = e.qw ? ld_uniform(e.qw, qg) : e.uniform_w;
+        const double wq = e.qw ? ld_uniform(e.qw, (long)e.q_off + ql) : e.uniform_w;
         // X[x][m][n] (re|im) to LDS as row 2x + (re|im), column 8m + n; element v
         // of lane l is row 4(l/16) + v of the rotation, i.e. m = (4 l/16 + v) % 8
         // and re|im = l/32
@@ -672,6 +686,9 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
                 const int r = 4 * lg + v;
                 xs[(2 * (2 * cb + pm) + (r >> 3)) * XLD + 8 * (r & 7) + n] = xr[cb][v];
             }
+        ps[dst_d] = dv;
+        ps[dst_v] = sv;
+        ps[dst_l] = lv;
         // the workgroup is one wavefront: its LDS writes are complete once its
         // LDS counter drains (a __syncthreads() here would also wait for the
         // loads in flight)
@@ -690,17 +707,23 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
         // exp(-x^2) = 2^-(x sqrt(log2 e))^2; below 2^-126 it is zero or
         // subnormal, as the cut at (x/sigma)^2 > 200 of the FP64 path
         if (lg < 3) {
+            const flt4 dm = *reinterpret_cast<const flt4*>(ps + kPsD + (pm * 8 + n) * 4);
+            const flt4 fm = *reinterpret_cast<const flt4*>(ps + kPsF + pm * 4);
+            const float2 om = *reinterpret_cast<const float2*>(ps + kPsOm + 2 * lg);
+            const float2 nb = *reinterpret_cast<const float2*>(ps + kPsNb + 2 * lg);
+            const float2 live = *reinterpret_cast<const float2*>(ps + kPsLive + 2 * lg);
             const float isl = is * 1.2011224087864498f;   // sqrt(log2 e) / sigma
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (!live[j]) continue;
+                if ((j ? live.y : live.x) == 0.f) continue;
+                const float omj = j ? om.y : om.x, nbj = j ? nb.y : nb.x;
                 float t = 0.f;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
                     const float g2 = gr[cb][2 * j] * gr[cb][2 * j] + gr[cb][2 * j + 1] * gr[cb][2 * j + 1];
-                    const float x1 = (dm[cb] - omf[j]) * isl, x2 = (dm[cb] + omf[j]) * isl;
+                    const float x1 = (dm[cb] - omj) * isl, x2 = (dm[cb] + omj) * isl;
                     const float d1 = __builtin_amdgcn_exp2f(-x1 * x1), d2 = __builtin_amdgcn_exp2f(-x2 * x2);
-                    t += g2 * (d1 * (1.f + nbf[j] - fmf[cb]) + d2 * (nbf[j] + fmf[cb]));
+                    t += g2 * (d1 * (1.f + nbj - fm[cb]) + d2 * (nbj + fm[cb]));
                 }
                 acc[j] += wq * (double)t;
             }
