@@ -20,6 +20,12 @@ FLAGS = [
 ]
 
 
+# per-source flags: the rates epilogue's matrix products keep their
+# accumulators in ordinary VGPRs (no copies out of AGPRs between the rotation,
+# the projection and the weighting of each pair)
+EXTRA = {"eph_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _hipcc():
     for c in ("/opt/rocm/bin/hipcc", "hipcc"):
         if os.path.exists(c) or c == "hipcc":
@@ -34,7 +40,7 @@ def build(verbose=False, jobs=6):
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

@@ -333,14 +333,16 @@ void collision_vjp_impl(ephx_table* t, const double* f, const double* lam, doubl
 // One RK4 step f -> f_new; stage inputs optionally saved (Y1..Y4).  gathered:
 // the collision plan's gather buffer holds f on entry; it holds f_new on exit
 // (each stage's finish gathers the next stage's input).
+// With stage4 = false the step stops once y4 is formed (f_new is then
+// incomplete): a replay that needs the stage inputs but not the result.
 void rk4_step(ephx_table* t, const double* f, double dt, double* f_new, double* y2, double* y3, double* y4,
-              hipStream_t st, const Field* fld, bool& gathered) {
+              hipStream_t st, const Field* fld, bool& gathered, bool stage4 = true) {
     // stage 1 at f: acc = f + dt/6 k1 ; y2 = f + dt/2 k1
     collision_eval(t, f, nullptr, f_new, 1, dt / 6.0, f, dt / 2.0, y2, st, fld, gathered, true);
     collision_eval(t, y2, nullptr, f_new, 0, dt / 3.0, f, dt / 2.0, y3, st, fld, true, true);
     collision_eval(t, y3, nullptr, f_new, 0, dt / 3.0, f, dt, y4, st, fld, true, true);
-    collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st, fld, true, true, true);
-    gathered = true;
+    if (stage4) collision_eval(t, y4, nullptr, f_new, 0, dt / 6.0, f, 0.0, nullptr, st, fld, true, true, true);
+    gathered = stage4;
 }
 
 // One explicit Euler step f -> f_new = f + dt (I[f] + drift)
@@ -857,14 +859,18 @@ extern "C" int ephx_dynamics_vjp(ephx_table* t, const double* ckpts, double dt, 
         double* colp2 = (double*)t->ws.get("b.colp", (size_t)2 * pl2.n_rt * S * 8);
         const int nseg = n_steps / L;
         for (int seg = nseg - 1; seg >= 0; --seg) {
-            // replay the segment, keeping the four stage inputs of each step
-            const double* cur = ckpts + (size_t)seg * S;
+            // replay the segment, keeping the four stage inputs of each step:
+            // step j starts from its slot (j, 0) and writes its result into
+            // slot (j + 1, 0); the last step's result (the next checkpoint)
+            // is not needed, and neither is its fourth stage
+            hip_check(hipMemcpyAsync(ys, ckpts + (size_t)seg * S, S * 8, hipMemcpyDeviceToDevice, st),
+                      "hipMemcpyAsync");
             bool gathered = false;
             for (int j = 0; j < L; ++j) {
                 double* y1 = ys + ((size_t)j * 4) * S;
-                hip_check(hipMemcpyAsync(y1, cur, S * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-                rk4_step(t, y1, dt, fn, y1 + S, y1 + 2 * S, y1 + 3 * S, st, nullptr, gathered);
-                cur = fn;
+                const bool last = j + 1 == L;
+                rk4_step(t, y1, dt, last ? fn : y1 + 4 * S, y1 + S, y1 + 2 * S, y1 + 3 * S, st, nullptr, gathered,
+                         !last);
             }
             for (int j = L - 1; j >= 0; --j) {
                 const double* Y[4];

@@ -560,7 +560,7 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 // omega) reach the lanes through LDS: each lane loads one of them, converts
 // it and writes it where the lanes that use it read it as one vector, so no
 // lane selects among wavefront-uniform values.
-constexpr int kEpiDepth = 4;
+constexpr int kEpiDepth = 2;   // with 2, three wavefronts fit a SIMD
 static_assert(kQPB % kEpiDepth == 0, "whole ring turns per workgroup");
 
 // LDS staging of a pair's band and mode values, in floats:
@@ -713,15 +713,19 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
             const float2 nb = *reinterpret_cast<const float2*>(ps + kPsNb + 2 * lg);
             const float2 live = *reinterpret_cast<const float2*>(ps + kPsLive + 2 * lg);
             const float isl = is * 1.2011224087864498f;   // sqrt(log2 e) / sigma
+            // arguments in units of sigma / sqrt(log2 e): x = dm' -+ om'
+            float dms[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) dms[cb] = dm[cb] * isl;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if ((j ? live.y : live.x) == 0.f) continue;
-                const float omj = j ? om.y : om.x, nbj = j ? nb.y : nb.x;
+                const float oms = (j ? om.y : om.x) * isl, nbj = j ? nb.y : nb.x;
                 float t = 0.f;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
                     const float g2 = gr[cb][2 * j] * gr[cb][2 * j] + gr[cb][2 * j + 1] * gr[cb][2 * j + 1];
-                    const float x1 = (dm[cb] - omj) * isl, x2 = (dm[cb] + omj) * isl;
+                    const float x1 = dms[cb] - oms, x2 = dms[cb] + oms;
                     const float d1 = __builtin_amdgcn_exp2f(-x1 * x1), d2 = __builtin_amdgcn_exp2f(-x2 * x2);
                     t += g2 * (d1 * (1.f + nbj - fm[cb]) + d2 * (nbj + fm[cb]));
                 }
