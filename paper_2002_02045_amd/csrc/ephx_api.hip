@@ -640,8 +640,10 @@ static DriverPlan driver_plan_mem(const ephx_model* m, int nk, int nq, int preci
     d.wide = d.nw > kMaxNw || d.nm > kMaxModes;
     const long pair_bytes = d.ngcol * (d.f32 ? 8 : 16) * 2 + (long)d.nw2 * 48;
     const long wide_pairs = std::max(16L, (wide_gib << 30) / pair_bytes);
-    d.bk_eff = std::min(bk, 16);
-    if (d.wide) d.bk_eff = std::max(1, std::min<int>(d.bk_eff, (int)(wide_pairs / 16)));
+    // up to 32 k per batch (16 for large models): the q-only work of a chunk
+    // (phase planes and table, mode factors) is done once per batch
+    d.bk_eff = std::min(bk, 32);
+    if (d.wide) d.bk_eff = std::max(1, std::min<int>(std::min(d.bk_eff, 16), (int)(wide_pairs / 16)));
     const long pairs_target = d.wide ? wide_pairs : 1L << 19;
     long qc = std::max(d.wide ? 1L : 64L, std::min((long)std::max(nq, 1), pairs_target / d.bk_eff));
     // whole 256-row tiles of the split contraction where the chunk allows
