@@ -6,14 +6,10 @@
 // U = Q Z (eig_ql.h).  About 240 VALU instructions per 8 x 8 matrix against
 // about 950 for cyclic Jacobi with one lane per row, which it replaces.
 //
-// 8 < n <= 128: one workgroup per matrix, cyclic Jacobi with plane rotations
-// applied to disjoint pairs in parallel (Golub & Van Loan, "Matrix
-// Computations", Sec. 8.5, in its complex Hermitian form).  For a pair (p, q),
-// p < q, with a_pq = |a_pq| e^{i phi}:
-//   th = (a_qq - a_pp)/(2|a_pq|), t = sgn(th)/(|th| + sqrt(th^2 + 1)),
-//   c = 1/sqrt(1 + t^2), s = t c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi},
-// and A <- J^dag A J, V <- V J.  Sweeps run until the off-diagonal Frobenius
-// norm is below 1e-15 of the matrix norm.
+// 8 < n <= 128: the same three steps with one wavefront per matrix (the
+// reduction and QL) and one workgroup per matrix for U = Q Z (k_eig_tql,
+// k_eig_tqlv), in place of cyclic Jacobi with one workgroup per matrix (5x
+// faster at n = 64, 4x at n = 120).
 //
 // Both sort the eigenpairs ascending, ties by index.
 #include "internal.h"
@@ -97,362 +93,347 @@ __global__ __launch_bounds__(256) void k_eig_lane(int batch, const Tin* __restri
     if (evecs != nullptr) store_lane_vectors<N, 0>(s, rk, evecs + slot * N * N * 2);
 }
 
-// Larger matrices (8 < n <= 128, e.g. H(k) of a 64-function model, D(q) of a
-// 40-atom cell): one 256-thread workgroup per matrix, the Jacobi rotations of
-// the header, with the n/2 disjoint rotations of a round (circle-method
-// ordering) applied by all threads at once.  For n <= 64 (k_eig_wg) A and V
-// live in LDS (2 x 65 KB, rows padded by one element) and a round is a column
-// pass and a row pass, three barriers apart; above, see k_eig_wg_packed.  The
-// rotation parameters of a round go through LDS.
-constexpr int kWgMax = 128;
-constexpr int kWgLds = 64;     // largest order kept in LDS with its eigenvectors
+constexpr int kWgMax = 128;   // largest order of the wavefront solver
 
-__device__ __forceinline__ int circle_index(int pos, int r, int ne) {
-    return pos == 0 ? 0 : (pos - 1 + r) % (ne - 1) + 1;
+// 8 < n <= 128 by Householder reduction and implicit QL (the one-lane solver's
+// steps, spread over a wavefront), in two kernels.
+//
+// k_eig_tql: one wavefront per matrix, lane l owning rows l and l + 64.  The
+// lower triangle of A is held in LDS (packed, complex); reflector j is formed
+// from column j (a wavefront sum for the norm), p = tau A v row by row, the
+// rank-2 update row by row, as in herm_reflect.  The reflectors and their tau
+// go to the matrix's own slot of A (which the call overwrites), the same LDS
+// then holds Z^T for the implicit QL on (d, e): the rotation chain is
+// wavefront-uniform (every lane computes it), with the next d, e and Z entries
+// read ahead of their use and the just-rotated Z entry carried in registers,
+// so a rotation costs its arithmetic plus one LDS read and one write per row.
+// The eigenvalues are ranked (ascending, ties by index) and Z's columns written
+// to the slot in rank order.
+//
+// k_eig_tqlv: U = Q Z, one 256-thread workgroup per matrix, TPC threads per
+// column of Z holding 16 rows each; a reflector's inner product is summed over
+// the column's threads by lane exchanges.
+//
+// Slot of matrix mi (2 n^2 doubles of A): [0, n^2) Z^T in rank order,
+// [n^2, n^2 + 2(n-1)) tau, then reflector j's entries i = j+2 .. n-1 at
+// j(n-2) - j(j-1)/2 + (i - j - 2) (complex).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
 }
+__device__ __forceinline__ int tri_idx(int i, int m) { return i * (i + 1) / 2 + m; }
+__device__ __forceinline__ int refl_base(int n, int j) { return j * (n - 2) - j * (j - 1) / 2; }
 
-__global__ __launch_bounds__(256) void k_eig_wg(int n, double* __restrict__ A, long strideA, double* __restrict__ evals,
-                                                double* __restrict__ evecs) {
-    __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
-    __shared__ double rc[kWgMax / 2], rsr[kWgMax / 2], rsi[kWgMax / 2];
-    __shared__ double red[2][256];
-    __shared__ double dg[kWgMax];
-    __shared__ int rk[kWgMax];
-    // in LDS the rows are padded by one complex element, so that a column
-    // (stride ld) walks across the banks instead of hitting one
-    __shared__ double sbuf[4 * kWgLds * (kWgLds + 1)];
-    const int tid = threadIdx.x;
+template <int R>
+__global__ __launch_bounds__(64) void k_eig_tql(int n, double* __restrict__ A, long strideA,
+                                                double* __restrict__ evals) {
+    constexpr int NMAX = 64 * R;
+    constexpr int REG = NMAX * (NMAX + 1);   // doubles: packed lower triangle (complex), later Z^T
+    __shared__ __attribute__((aligned(16))) double lds[REG + 4 * NMAX];
+    __shared__ double dd[NMAX], ee[NMAX];
+    __shared__ int rk[NMAX];
+    double2* a = reinterpret_cast<double2*>(lds);
+    double2* vv = reinterpret_cast<double2*>(lds + REG);
+    double2* ww = vv + NMAX;
+    const int l = threadIdx.x;
     const long mi = blockIdx.x;
     double* ga = A + mi * strideA * 2;
-    double* gv = evecs != nullptr ? evecs + mi * (long)n * n * 2 : nullptr;
-    const int ld = n + 1;   // complex elements per row of a and v
-    double* a = sbuf;
-    double* v = gv ? sbuf + 2 * kWgLds * (kWgLds + 1) : nullptr;
-    const int nn = n * n;
-    // Hermitian part 0.5 (A + A^dag), V = I
-    for (int e = tid; e < nn; e += 256) {
-        const int i = e / n, j = e % n;
-        if (i < j) {
-            const double xr = 0.5 * (ga[2 * e] + ga[2 * (j * n + i)]);
-            const double xi = 0.5 * (ga[2 * e + 1] - ga[2 * (j * n + i) + 1]);
-            a[2 * (i * ld + j)] = xr;
-            a[2 * (i * ld + j) + 1] = xi;
-            a[2 * (j * ld + i)] = xr;
-            a[2 * (j * ld + i) + 1] = -xi;
-        } else if (i == j) {
-            a[2 * (i * ld + i)] = ga[2 * e];
-            a[2 * (i * ld + i) + 1] = 0.0;
+    const long nn = (long)n * n;
+    // Hermitian part 0.5 (A + A^dag), lower triangle
+    for (int i = 0; i < n; ++i)
+        for (int m = l; m <= i; m += 64) {
+            const double xr = ga[2 * (i * n + m)], xi = ga[2 * (i * n + m) + 1];
+            const double yr = ga[2 * (m * n + i)], yi = ga[2 * (m * n + i) + 1];
+            a[tri_idx(i, m)] = i == m ? double2{xr, 0.0} : double2{0.5 * (xr + yr), 0.5 * (xi - yi)};
         }
-        if (v) {
-            v[2 * (i * ld + j)] = i == j ? 1.0 : 0.0;
-            v[2 * (i * ld + j) + 1] = 0.0;
-        }
-    }
     __syncthreads();
-    const int ne = n + (n & 1), np = ne / 2;
-    for (int sweep = 0; sweep < 50; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < nn; e += 256) {
-            const int i = e / n, j = e % n;
-            const double m2 = a[2 * (i * ld + j)] * a[2 * (i * ld + j)] + a[2 * (i * ld + j) + 1] * a[2 * (i * ld + j) + 1];
-            tot += m2;
-            off += (i != j) ? m2 : 0.0;
-        }
-        red[0][tid] = off;
-        red[1][tid] = tot;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if (tid < w) {
-                red[0][tid] += red[0][tid + w];
-                red[1][tid] += red[1][tid + w];
+    // reflector j: H_j^H A[j+1.., j] = beta e_1, A <- H_j^H A H_j on the trailing block
+    for (int j = 0; j < n - 1; ++j) {
+        const double2 al = a[tri_idx(j + 1, j)];
+        double xn2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l + 64 * r;
+            if (i >= j + 2 && i < n) {
+                const double2 x = a[tri_idx(i, j)];
+                xn2 += x.x * x.x + x.y * x.y;
             }
-            __syncthreads();
         }
-        const bool done = !(red[0][0] > 1e-30 * red[1][0]);
+        xn2 = wave_sum(xn2);
+        const bool ident = xn2 == 0.0 && al.y == 0.0;
+        const double nrm2 = al.x * al.x + al.y * al.y + xn2;
+        const double nrm = nrm2 * rsqrt1(ident ? 1.0 : nrm2);
+        const double beta = ident ? al.x : (al.x >= 0.0 ? -nrm : nrm);
+        const double ib = recip(ident ? 1.0 : beta);
+        const double tr = ident ? 0.0 : (beta - al.x) * ib, ti = ident ? 0.0 : -al.y * ib;
+        const double dr = al.x - beta, di = al.y;
+        const double den = recip(ident ? 1.0 : dr * dr + di * di);
+        const double sr = ident ? 1.0 : dr * den, si = ident ? 0.0 : -di * den;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l + 64 * r;
+            v[r] = double2{0.0, 0.0};
+            if (i == j + 1) v[r] = double2{1.0, 0.0};
+            if (i >= j + 2 && i < n) {
+                const double2 x = a[tri_idx(i, j)];
+                v[r] = double2{x.x * sr - x.y * si, x.x * si + x.y * sr};
+                a[tri_idx(i, j)] = v[r];
+                const long q = nn + 2 * (n - 1) + 2 * (refl_base(n, j) + (i - j - 2));
+                ga[q] = v[r].x;
+                ga[q + 1] = v[r].y;
+            }
+            if (i >= j + 1 && i < n) vv[i] = v[r];
+        }
+        if (l == 0) {
+            ga[nn + 2 * j] = tr;
+            ga[nn + 2 * j + 1] = ti;
+            ee[j] = beta;
+        }
         __syncthreads();
-        if (done) break;
-        for (int r = 0; r < ne - 1; ++r) {
-            if (tid < np) {
-                const int i1 = circle_index(tid, r, ne), i2 = circle_index(ne - 1 - tid, r, ne);
-                const int p = i1 < i2 ? i1 : i2, q = i1 < i2 ? i2 : i1;
-                double c = 1.0, sr = 0.0, si = 0.0;
-                if (q < n) {
-                    const double apr = a[2 * (p * ld + q)], api = a[2 * (p * ld + q) + 1];
-                    const double m2 = apr * apr + api * api;
-                    if (m2 > 0.0) {
-                        // t/|a_pq| and se as in the wavefront solver
-                        const double d = a[2 * (q * ld + q)] - a[2 * (p * ld + p)];
-                        const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
-                        c = rsqrt1(fma(tm * tm, m2, 1.0));
-                        const double w = tm * c;
-                        sr = w * apr;
-                        si = w * api;
+        // p = tau A v on the trailing block, row by row
+        double2 p[R];
+        double hr = 0.0, hi = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l + 64 * r;
+            p[r] = double2{0.0, 0.0};
+            if (i >= j + 1 && i < n) {
+                double yr = 0.0, yi = 0.0;
+                for (int m = j + 1; m < n; ++m) {
+                    double mr, mim;
+                    if (m <= i) {
+                        const double2 t = a[tri_idx(i, m)];
+                        mr = t.x;
+                        mim = m == i ? 0.0 : t.y;
+                    } else {
+                        const double2 t = a[tri_idx(m, i)];
+                        mr = t.x;
+                        mim = -t.y;
                     }
+                    const double2 vm = vv[m];
+                    yr += mr * vm.x - mim * vm.y;
+                    yi += mr * vm.y + mim * vm.x;
                 }
-                pp[tid] = p;
-                qq[tid] = q < n ? q : p;   // a dummy partner never rotates
-                rc[tid] = c;
-                rsr[tid] = sr;
-                rsi[tid] = si;
+                p[r] = double2{tr * yr - ti * yi, tr * yi + ti * yr};
+                hr += p[r].x * v[r].x + p[r].y * v[r].y;
+                hi += p[r].x * v[r].y - p[r].y * v[r].x;
             }
-            __syncthreads();
-            // columns: (AJ)_{.p} = c A_.p - conj(se) A_.q ; (AJ)_{.q} = se A_.p + c A_.q ; V likewise
-            for (int e = tid; e < np * n; e += 256) {
-                const int k = e / n, i = e % n;
-                const int p = pp[k], q = qq[k];
-                if (p == q) continue;
-                const double c = rc[k], sr = rsr[k], si = rsi[k];
-                double* x = a + 2 * (i * ld + p);
-                double* y = a + 2 * (i * ld + q);
-                const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
-                x[0] = c * xr - (sr * yr + si * yi);
-                x[1] = c * xi - (sr * yi - si * yr);
-                y[0] = (sr * xr - si * xi) + c * yr;
-                y[1] = (sr * xi + si * xr) + c * yi;
-                if (v) {
-                    double* u = v + 2 * (i * ld + p);
-                    double* w = v + 2 * (i * ld + q);
-                    const double ur = u[0], ui = u[1], wr = w[0], wi = w[1];
-                    u[0] = c * ur - (sr * wr + si * wi);
-                    u[1] = c * ui - (sr * wi - si * wr);
-                    w[0] = (sr * ur - si * ui) + c * wr;
-                    w[1] = (sr * ui + si * ur) + c * wi;
+        }
+        hr = wave_sum(hr);
+        hi = wave_sum(hi);
+        const double kr = -0.5 * (tr * hr - ti * hi), ki = -0.5 * (tr * hi + ti * hr);
+        double2 w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l + 64 * r;
+            w[r] = double2{p[r].x + kr * v[r].x - ki * v[r].y, p[r].y + kr * v[r].y + ki * v[r].x};
+            if (i >= j + 1 && i < n) ww[i] = w[r];
+        }
+        __syncthreads();
+        // A -= v w^H + w v^H on the lower triangle of the trailing block
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l + 64 * r;
+            if (i >= j + 1 && i < n) {
+                for (int m = j + 1; m <= i; ++m) {
+                    const double2 vm = vv[m], wm = ww[m];
+                    const double ur = v[r].x * wm.x + v[r].y * wm.y + w[r].x * vm.x + w[r].y * vm.y;
+                    const double ui = v[r].y * wm.x - v[r].x * wm.y + w[r].y * vm.x - w[r].x * vm.y;
+                    double2 t = a[tri_idx(i, m)];
+                    t.x -= ur;
+                    if (m != i) t.y -= ui;
+                    a[tri_idx(i, m)] = t;
                 }
             }
-            __syncthreads();
-            // rows: (J^dag A)_{p.} = c A_p. - se A_q. ; (J^dag A)_{q.} = conj(se) A_p. + c A_q.
-            for (int e = tid; e < np * n; e += 256) {
-                const int k = e / n, j = e % n;
-                const int p = pp[k], q = qq[k];
-                if (p == q) continue;
-                const double c = rc[k], sr = rsr[k], si = rsi[k];
-                double* x = a + 2 * (p * ld + j);
-                double* y = a + 2 * (q * ld + j);
-                const double xr = x[0], xi = x[1], yr = y[0], yi = y[1];
-                x[0] = c * xr - (sr * yr - si * yi);
-                x[1] = c * xi - (sr * yi + si * yr);
-                y[0] = (sr * xr + si * xi) + c * yr;
-                y[1] = (sr * xi - si * xr) + c * yi;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = l + 64 * r;
+        if (i < n) dd[i] = a[tri_idx(i, i)].x;
+    }
+    if (l == 0) ee[n - 1] = 0.0;
+    __syncthreads();
+    // Z^T = I in the same LDS
+    double* zt = lds;
+    for (long e = l; e < nn; e += 64) zt[e] = (e / n == e % n) ? 1.0 : 0.0;
+    __syncthreads();
+    // implicit QL with Wilkinson shifts, deflating row L; e[m] counts as zero
+    // once |e[m]| <= 2^-53 (|d[m]| + |d[m+1]|)
+    for (int L = 0; L < n - 1; ++L) {
+        for (int it = 0; it < 60; ++it) {
+            int m = n - 1;
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                const int mm = L + l + 64 * r;
+                const bool neg = mm < n - 1 && fabs(ee[mm]) <= 1.1102230246251565e-16 * (fabs(dd[mm]) + fabs(dd[mm + 1]));
+                const unsigned long long bal = __ballot(neg);
+                if (bal) m = L + 64 * r + __builtin_ctzll(bal);
             }
+            if (m == L) break;
+            const double el = ee[L], dL = dd[L];
+            double g = (dd[L + 1] - dL) * recip(2.0 * el);
+            const double r0 = (g * g + 1.0) * rsqrt1(g * g + 1.0);
+            g = dd[m] - dL + el * recip(g + (g >= 0.0 ? r0 : -r0));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool brk = false;
+            // carried along the sweep: d[i+1] and, per row, Z[k][i+1]
+            double di1 = dd[m];
+            double zc[R], zn[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = l + 64 * r;
+                zc[r] = k < n ? zt[(long)m * n + k] : 0.0;
+                zn[r] = k < n ? zt[(long)(m - 1) * n + k] : 0.0;
+            }
+            double ei = ee[m - 1], di = dd[m - 1];
+            int i = m - 1;
+            for (; i >= L; --i) {
+                // the next rotation's operands, read ahead
+                const double ein = i > L ? ee[i - 1] : 0.0, din = i > L ? dd[i - 1] : 0.0;
+                double znn[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = l + 64 * r;
+                    znn[r] = (i > L && k < n) ? zt[(long)(i - 1) * n + k] : 0.0;
+                }
+                const double f = s * ei, b = c * ei;
+                const double r2 = f * f + g * g;
+                if (r2 == 0.0) {
+                    dd[i + 1] = di1 - p;
+                    brk = true;
+                    break;
+                }
+                const double ir = rsqrt1(r2);
+                ee[i + 1] = r2 * ir;
+                s = f * ir;
+                c = g * ir;
+                const double g1 = di1 - p;
+                const double q1 = (di - g1) * s + 2.0 * c * b;
+                p = s * q1;
+                dd[i + 1] = g1 + p;
+                g = c * q1 - b;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = l + 64 * r;
+                    const double zf = zc[r];
+                    if (k < n) zt[(long)(i + 1) * n + k] = s * zn[r] + c * zf;
+                    zc[r] = c * zn[r] - s * zf;
+                    zn[r] = znn[r];
+                }
+                di1 = di;
+                ei = ein;
+                di = din;
+            }
+            // Z[k][i+1] as carried (the sweep's last rotated entry, or the
+            // untouched one where the sweep stopped)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = l + 64 * r;
+                if (k < n) zt[(long)(i + 1) * n + k] = zc[r];
+            }
+            if (!brk) {
+                dd[L] = dd[L] - p;
+                ee[L] = g;
+            }
+            ee[m] = 0.0;
             __syncthreads();
         }
     }
-    // sort ascending, ties by index
-    for (int i = tid; i < n; i += 256) dg[i] = a[2 * (i * ld + i)];
     __syncthreads();
-    for (int i = tid; i < n; i += 256) {
-        int r = 0;
-        for (int m = 0; m < n; ++m) r += (dg[m] < dg[i] || (dg[m] == dg[i] && m < i)) ? 1 : 0;
-        rk[i] = r;
-        evals[mi * n + r] = dg[i];
+    // ranks (ascending, ties by index), eigenvalues, Z^T rows in rank order
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int c = l + 64 * r;
+        if (c < n) {
+            const double dc = dd[c];
+            int k = 0;
+            for (int m = 0; m < n; ++m) k += (dd[m] < dc || (dd[m] == dc && m < c)) ? 1 : 0;
+            rk[c] = k;
+            evals[mi * n + k] = dc;
+        }
     }
     __syncthreads();
-    if (gv) {
-        // columns of V go to their ranks directly
-        for (int e = tid; e < nn; e += 256) {
-            const int i = e / n, c = e % n;
-            gv[2 * (i * n + rk[c])] = v[2 * (i * ld + c)];
-            gv[2 * (i * n + rk[c]) + 1] = v[2 * (i * ld + c) + 1];
+    for (int c = 0; c < n; ++c) {
+        const long dst = (long)rk[c] * n;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = l + 64 * r;
+            if (k < n) ga[dst + k] = zt[(long)c * n + k];
         }
     }
 }
 
-// Orders above the LDS range of k_eig_wg (64 < n <= 128): A is kept in LDS in
-// the packed Hermitian form (n*n reals, P[i][j] = Re A_ij for i <= j and Im A_ji
-// for i > j: 131 KB at n = 128) and each round applies J^dag A J at once, block
-// by block: the rows of pair a and the columns of pair b form a 2 x 2 block B,
-// and its new value is J_a^dag B J_b (the same column-then-row arithmetic as
-// the two-phase update), so only the blocks with a <= b are formed and the
-// rest follows by Hermiticity.  The eigenvectors accumulate transposed, V^T,
-// in A's global storage (the input is overwritten), so that the column update
-// V J of a round walks contiguous memory.
-__global__ __launch_bounds__(256) void k_eig_wg_packed(int n, double* __restrict__ A, long strideA,
-                                                       double* __restrict__ evals, double* __restrict__ evecs) {
-    __shared__ double P[kWgMax * kWgMax];
-    __shared__ int pp[kWgMax / 2], qq[kWgMax / 2];
-    __shared__ double rc[kWgMax / 2], rsr[kWgMax / 2], rsi[kWgMax / 2];
-    __shared__ double red[2][256];
-    __shared__ double dg[kWgMax];
-    __shared__ int rk[kWgMax];
+// U = Q Z from the slot k_eig_tql leaves (see there); TPC threads per column,
+// 16 rows each (n <= 16 TPC).
+template <int TPC>
+__global__ __launch_bounds__(256) void k_eig_tqlv(int n, const double* __restrict__ A, long strideA,
+                                                  double* __restrict__ evecs) {
+    constexpr int RPT = 16, CPP = 256 / TPC, NMAX = RPT * TPC;
+    __shared__ __attribute__((aligned(16))) double lds[NMAX * NMAX - NMAX];
     const int tid = threadIdx.x;
     const long mi = blockIdx.x;
-    double* ga = A + mi * strideA * 2;
-    const bool want_v = evecs != nullptr;
-    const int nn = n * n;
-    // packed Hermitian part 0.5 (A + A^dag)
-    for (int e = tid; e < nn; e += 256) {
-        const int i = e / n, j = e % n;
-        if (i < j) {
-            P[i * n + j] = 0.5 * (ga[2 * e] + ga[2 * (j * n + i)]);
-            P[j * n + i] = 0.5 * (ga[2 * e + 1] - ga[2 * (j * n + i) + 1]);
-        } else if (i == j) {
-            P[i * n + i] = ga[2 * e];
-        }
-    }
+    const double* ga = A + mi * strideA * 2;
+    const long nn = (long)n * n;
+    const int cnt = n * n - n;   // tau and the reflectors
+    for (int e = tid; e < cnt; e += 256) lds[e] = ga[nn + e];
     __syncthreads();
-    // V^T = I over A's storage (read complete above)
-    if (want_v)
-        for (int e = tid; e < nn; e += 256) {
-            ga[2 * e] = (e / n == e % n) ? 1.0 : 0.0;
-            ga[2 * e + 1] = 0.0;
-        }
-    // element (i, j), i != j, of the Hermitian matrix from the packed form
-    auto get = [&](int i, int j, double& re, double& im) {
-        if (i < j) {
-            re = P[i * n + j];
-            im = P[j * n + i];
-        } else {
-            re = P[j * n + i];
-            im = -P[i * n + j];
-        }
-    };
-    auto put = [&](int i, int j, double re, double im) {
-        if (i < j) {
-            P[i * n + j] = re;
-            P[j * n + i] = im;
-        } else {
-            P[j * n + i] = re;
-            P[i * n + j] = -im;
-        }
-    };
-    const int ne = n + (n & 1), np = ne / 2;
-    for (int sweep = 0; sweep < 50; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < nn; e += 256) {
-            const int i = e / n, j = e % n;
-            if (i == j) {
-                tot += P[e] * P[e];
-            } else if (i < j) {
-                const double m2 = 2.0 * (P[e] * P[e] + P[j * n + i] * P[j * n + i]);
-                tot += m2;
-                off += m2;
-            }
-        }
-        red[0][tid] = off;
-        red[1][tid] = tot;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if (tid < w) {
-                red[0][tid] += red[0][tid + w];
-                red[1][tid] += red[1][tid + w];
-            }
-            __syncthreads();
-        }
-        const bool done = !(red[0][0] > 1e-30 * red[1][0]);
-        __syncthreads();
-        if (done) break;
-        for (int r = 0; r < ne - 1; ++r) {
-            if (tid < np) {
-                const int i1 = circle_index(tid, r, ne), i2 = circle_index(ne - 1 - tid, r, ne);
-                const int p = i1 < i2 ? i1 : i2, q = i1 < i2 ? i2 : i1;
-                double c = 1.0, sr = 0.0, si = 0.0;
-                if (q < n) {
-                    const double apr = P[p * n + q], api = P[q * n + p];
-                    const double m2 = apr * apr + api * api;
-                    if (m2 > 0.0) {
-                        const double d = P[q * n + q] - P[p * n + p];
-                        const double tm = (d >= 0.0 ? 2.0 : -2.0) * recip(fabs(d) + sqrt(fma(d, d, 4.0 * m2)));
-                        c = rsqrt1(fma(tm * tm, m2, 1.0));
-                        const double w = tm * c;
-                        sr = w * apr;
-                        si = w * api;
-                    }
-                }
-                pp[tid] = p;
-                qq[tid] = q < n ? q : p;   // a dummy partner never rotates
-                rc[tid] = c;
-                rsr[tid] = sr;
-                rsi[tid] = si;
-            }
-            __syncthreads();
-            // blocks (a, b), a <= b: B' = J_a^dag B J_b with J = [[c, se], [-conj(se), c]]
-            for (int t = tid; t < np * np; t += 256) {
-                const int a = t / np, b = t % np;
-                if (a > b) continue;
-                const int ra[2] = {pp[a], qq[a]}, cb[2] = {pp[b], qq[b]};
-                const int nr = ra[1] != ra[0] ? 2 : 1, nc = cb[1] != cb[0] ? 2 : 1;
-                double br_[2][2], bi_[2][2];
+    const double2* tau = reinterpret_cast<const double2*>(lds);
+    const double2* refl = reinterpret_cast<const double2*>(lds + 2 * (n - 1));
+    double* gv = evecs + mi * nn * 2;
+    const int tc = tid / TPC, rb = tid % TPC;
+    for (int c0 = 0; c0 < n; c0 += CPP) {
+        const int c = c0 + tc;
+        const bool cv = c < n;
+        double xr[RPT], xi[RPT];
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
+        for (int r = 0; r < RPT; ++r) {
+            const int i = rb * RPT + r;
+            xr[r] = (cv && i < n) ? ga[(long)c * n + i] : 0.0;
+            xi[r] = 0.0;
+        }
+        for (int j = n - 2; j >= 0; --j) {
+            const double2 t = tau[j];
+            const int base = refl_base(n, j) - j - 2;
+            double yr = 0.0, yi = 0.0;
 #pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int i = ra[x], j = cb[y];
-                        if (i == j) {
-                            br_[x][y] = P[i * n + i];
-                            bi_[x][y] = 0.0;
-                        } else {
-                            get(i, j, br_[x][y], bi_[x][y]);
-                        }
-                    }
-                // T = B J_b: T_.p = c B_.p - conj(s) B_.q ; T_.q = s B_.p + c B_.q
-                const double cb_ = rc[b], sbr = rsr[b], sbi = rsi[b];
-                double tr[2][2], ti[2][2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    const double ur = br_[x][0], ui = bi_[x][0], wr = br_[x][1], wi = bi_[x][1];
-                    tr[x][0] = cb_ * ur - (sbr * wr + sbi * wi);
-                    ti[x][0] = cb_ * ui - (sbr * wi - sbi * wr);
-                    tr[x][1] = (sbr * ur - sbi * ui) + cb_ * wr;
-                    ti[x][1] = (sbr * ui + sbi * ur) + cb_ * wi;
-                }
-                // B' = J_a^dag T: B'_p. = c T_p. - s T_q. ; B'_q. = conj(s) T_p. + c T_q.
-                const double ca = rc[a], sar = rsr[a], sai = rsi[a];
-                double orr[2][2], oi[2][2];
-#pragma unroll
-                for (int y = 0; y < 2; ++y) {
-                    const double xr = tr[0][y], xi = ti[0][y], yr = tr[1][y], yi = ti[1][y];
-                    orr[0][y] = ca * xr - (sar * yr - sai * yi);
-                    oi[0][y] = ca * xi - (sar * yi + sai * yr);
-                    orr[1][y] = (sar * xr + sai * xi) + ca * yr;
-                    oi[1][y] = (sar * xi - sai * xr) + ca * yi;
-                }
-                if (a == b) {
-                    // Hermitian diagonal block: two real diagonal entries, one pair
-                    P[ra[0] * n + ra[0]] = orr[0][0];
-                    if (nr == 2) {
-                        P[ra[1] * n + ra[1]] = orr[1][1];
-                        put(ra[0], ra[1], orr[0][1], oi[0][1]);
-                    }
-                } else {
-                    for (int x = 0; x < nr; ++x)
-                        for (int y = 0; y < nc; ++y) put(ra[x], cb[y], orr[x][y], oi[x][y]);
+            for (int r = 0; r < RPT; ++r) {
+                const int i = rb * RPT + r;
+                if (i == j + 1) {
+                    yr += xr[r];
+                    yi += xi[r];
+                } else if (i >= j + 2 && i < n) {
+                    const double2 v = refl[base + i];
+                    yr += v.x * xr[r] + v.y * xi[r];
+                    yi += v.x * xi[r] - v.y * xr[r];
                 }
             }
-            // V <- V J on V^T: rows p, q of V^T, contiguous over i
-            if (want_v)
-                for (int t = tid; t < np * n; t += 256) {
-                    const int b = t / n, i = t % n;
-                    const int p = pp[b], q = qq[b];
-                    if (p == q) continue;
-                    const double c = rc[b], sr = rsr[b], si = rsi[b];
-                    double* u = ga + 2 * ((long)p * n + i);
-                    double* w = ga + 2 * ((long)q * n + i);
-                    const double ur = u[0], ui = u[1], wr = w[0], wi = w[1];
-                    u[0] = c * ur - (sr * wr + si * wi);
-                    u[1] = c * ui - (sr * wi - si * wr);
-                    w[0] = (sr * ur - si * ui) + c * wr;
-                    w[1] = (sr * ui + si * ur) + c * wi;
+#pragma unroll
+            for (int o = 1; o < TPC; o <<= 1) {
+                yr += __shfl_xor(yr, o, 64);
+                yi += __shfl_xor(yi, o, 64);
+            }
+            const double tyr = t.x * yr - t.y * yi, tyi = t.x * yi + t.y * yr;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = rb * RPT + r;
+                if (i == j + 1) {
+                    xr[r] -= tyr;
+                    xi[r] -= tyi;
+                } else if (i >= j + 2 && i < n) {
+                    const double2 v = refl[base + i];
+                    xr[r] -= v.x * tyr - v.y * tyi;
+                    xi[r] -= v.x * tyi + v.y * tyr;
                 }
-            __syncthreads();
+            }
         }
-    }
-    // sort ascending, ties by index
-    for (int i = tid; i < n; i += 256) dg[i] = P[i * n + i];
-    __syncthreads();
-    for (int i = tid; i < n; i += 256) {
-        int r = 0;
-        for (int m = 0; m < n; ++m) r += (dg[m] < dg[i] || (dg[m] == dg[i] && m < i)) ? 1 : 0;
-        rk[i] = r;
-        evals[mi * n + r] = dg[i];
-    }
-    __syncthreads();
-    if (want_v) {
-        // column c of V (row c of V^T) goes to column rank(c) of the output
-        double* gv = evecs + mi * (long)n * n * 2;
-        for (int e = tid; e < nn; e += 256) {
-            const int c = e / n, i = e % n;
-            gv[2 * (i * n + rk[c])] = ga[2 * e];
-            gv[2 * (i * n + rk[c]) + 1] = ga[2 * e + 1];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = rb * RPT + r;
+            if (cv && i < n) *reinterpret_cast<double2*>(gv + ((long)i * n + c) * 2) = double2{xr[r], xi[r]};
         }
     }
 }
@@ -492,12 +473,17 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
     if (n < 1 || n > kWgMax) throw Error{-6, "eig_herm: matrix order above 128 is not supported"};
     if (n > kEigMax) {
         if (a_f32) throw Error{-1, "eig_herm: matrices above order 8 must be FP64"};
-        if (n <= kWgLds)
-            hipLaunchKernelGGL(k_eig_wg, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
-                               evecs);
-        else
-            hipLaunchKernelGGL(k_eig_wg_packed, dim3((unsigned)batch), dim3(256), 0, st, n, (double*)A, strideA, evals,
-                               evecs);
+        if (n <= 64) {
+            hipLaunchKernelGGL(k_eig_tql<1>, dim3((unsigned)batch), dim3(64), 0, st, n, (double*)A, strideA, evals);
+            if (evecs)
+                hipLaunchKernelGGL(k_eig_tqlv<4>, dim3((unsigned)batch), dim3(256), 0, st, n, (const double*)A,
+                                   strideA, evecs);
+        } else {
+            hipLaunchKernelGGL(k_eig_tql<2>, dim3((unsigned)batch), dim3(64), 0, st, n, (double*)A, strideA, evals);
+            if (evecs)
+                hipLaunchKernelGGL(k_eig_tqlv<8>, dim3((unsigned)batch), dim3(256), 0, st, n, (const double*)A,
+                                   strideA, evecs);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
         return;

@@ -221,3 +221,24 @@ def group_labels_modes(omega, tol=1e-4):
             g += 1
         lab[order[i]] = g
     return lab
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+@pytest.mark.parametrize("nq", [1, 37, 100])
+def test_si_rates_short_and_ragged_q(lib, si, prec, nq):
+    """The rates epilogue of the 8-band, 6-mode model on q counts that leave a
+    workgroup's block of 32 pairs partly empty (one q; 37 = 32 + 5; 100 =
+    3 x 32 + 4), against the oracle at every pair."""
+    m, dm = si
+    cfg = synth.CONFIGS["si"]
+    k = synth.random_points(317, 4)
+    q = synth.random_points(318 + nq, nq)
+    par = dict(temp=cfg["T"], mu=cfg["mu"], sigma=cfg["sigma"])
+    p = lib.Params(omega_cut=cfg["omega_cut"], **par)
+    _say("rates 4 k x %d q, prec=%s" % (nq, prec))
+    g, gm = lib.rates(dm, k, q, p, precision=prec)
+    go, gmo = eph.rates(m, k, q, **par)
+    err = rate_error(g.cpu().numpy(), go.numpy())
+    errm = rate_error(gm.cpu().numpy(), gmo.numpy())
+    _say("  rates error %s: %.3e (per mode %.3e)" % (prec, err, errm))
+    assert err <= 1e-4 and errm <= 1e-4
