@@ -110,3 +110,31 @@ def test_degenerate_rates_group_sums(lib, deg):
     err = float((a - b).abs().max() / b.abs().max())
     _say("  rates group-sum error fp64 %.3e" % err)
     assert err <= 1e-10
+
+
+def test_fourfold_degenerate_bands_order_16(lib):
+    """Order 16 (the wavefront eigensolver, 8 < n <= 64) on H(R) (x) I_4 of the
+    tiny model: every band four-fold degenerate at every k.  The eigenvalues
+    are the tiny model's, each repeated four times (a closed form), U solves
+    (H(k) (x) I_4) U = U diag(eps) and is unitary."""
+    m = synth.make_config_model("tiny")
+    mq = copy.deepcopy(m)
+    mq.nw = 4 * m.nw
+    mq.h = np.stack([np.kron(x, np.eye(4)) for x in m.h])
+    mq.g = np.kron(m.g, np.eye(4))
+    mq.wf_centres = np.repeat(m.wf_centres, 4, axis=0)
+    dm = lib.Model(mq)
+    k = np.vstack([np.zeros((1, 3)), [[0.5, 0.5, 0.5]], synth.random_points(143, 70)])
+    _say("bands of the four-fold model, order 16, %d k" % len(k))
+    eps, u, _ = lib.bands(dm, k, want_u=True)
+    eo, _ = interp.bands(m, k)
+    want = np.repeat(eo.numpy(), 4, axis=1)
+    scale = float(np.abs(want).max())
+    assert float(np.abs(eps.cpu().numpy() - want).max()) <= 1e-10 * scale
+    hk = interp.hamiltonian_k(m, k).numpy()
+    hq = np.stack([np.kron(x, np.eye(4)) for x in hk])
+    uc = u.cpu().numpy()
+    res = hq @ uc - uc * eps.cpu().numpy()[:, None, :]
+    assert float(np.abs(res).max()) <= 1e-10 * scale
+    eye = np.eye(mq.nw)
+    assert float(np.abs(np.conj(np.swapaxes(uc, 1, 2)) @ uc - eye).max()) <= 1e-12
