@@ -25,7 +25,7 @@ constexpr double kDegTol = 1e-4;                        // degenerate-group thre
 
 constexpr int kMaxNw = 16;      // Wannier functions handled by the per-pair kernels
 constexpr int kMaxModes = 12;   // 3*natoms handled by the per-pair kernels
-constexpr int kEigMax = 8;      // largest matrix of the wavefront Jacobi eigensolver
+constexpr int kEigMax = 8;      // largest matrix of the one-lane eigensolver (eig_ql.h)
 constexpr int kMaxNwWide = 64;  // Wannier functions of the batched-GEMM path
 constexpr int kMaxModesWide = 126;   // 3*natoms of the batched-GEMM path (eigensolver n <= 128)
 
