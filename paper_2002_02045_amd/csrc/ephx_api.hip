@@ -725,6 +725,7 @@ size_t driver_workspace_bytes(const ephx_model* m, const DriverPlan& d, int nq, 
     b += d.npair * (nw2 * 16 + nw * 8 + nw2 * 16);                        // H(k+q), eps, U
     b += hfold_bytes(m, d.bk_eff);                                        // k-folded half set
     if (m->d_h_pack) b += (size_t)d.qc * m->n_re_half * 16;                  // phase table of H(k+q)
+    if (m->g_c64) b += (size_t)d.bk_eff * m->n_re_g * 16;                    // phase table of the Re sum
     b += d.npair * d.ngcol * (d.f32 ? 8 : 16) * (d.wide ? 2 : 1);         // g^W (and g^H)
     if (d.wide) b += (size_t)d.qc * nm * nm * 16 + (m->polar ? d.npair * nw2 * 16 : 0);
     if (rates) b += (size_t)d.bk_eff * eph_epilogue_blocks(d.qc) * nw * nm * 8 + (size_t)d.bk_eff * nw * nm * 8;
@@ -812,7 +813,8 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         {
             StageTimer t("re_contraction", st);
             if (m->g_c64)
-                phase_gemm_f64_b32(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g32, 0, gk, 0, st);
+                phase_gemm_f64_b32(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g32, 0, gk, 0,
+                                   (double*)m->ws.get("drv.retab", (size_t)bk_eff * m->n_re_g * 16), st);
             else
                 phase_gemm_f64(nb, (int)nre_cols, m->n_re_g, 1, kb, nullptr, m->d_re_g, m->d_g, 0, gk, 0, st);
         }

@@ -62,9 +62,11 @@ void fold_herm_f64(int nk, const double* kpts, int Kh, const int32_t* nvec, int 
                    hipStream_t st);
 void phase_gemm_herm_groups_f64(int M, int nk, int P, int Kh, const double* x, const int32_t* nvec, const double* B,
                                 double* C, double* tab, hipStream_t st);
-// phase_gemm_f64 with a complex-float B (FP64 arithmetic; B widened on load)
+// phase_gemm_f64 with a complex-float B (FP64 arithmetic; B widened on load).
+// tab (M*K complex doubles of work memory, or nullptr): with M <= 16, Z = 1
+// and no x0 the rows' phases are formed there once per call.
 void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
-                        const float* B, long sB, double* C, long sC, hipStream_t st);
+                        const float* B, long sB, double* C, long sC, double* tab, hipStream_t st);
 void phase_gemm_f32(int M, int N, int K, int Z, const double* x, const double* x0,
                     const int32_t* nvec, const float* B, long sB, float* C, long sC,
                     hipStream_t st);

@@ -741,6 +741,55 @@ __global__ void k_fold_herm(int nk, const double* __restrict__ kpts, int Kh, con
     out[(((long)r * 2 + 1) * nk + kk) * P + e] = fma(c, b, -s * a);
 }
 
+// C[m] = sum_r e^{2 pi i x_m.n_r} B[r] for a few rows m (M <= MR, a k batch)
+// against a complex-float B of very many columns (the drawn g(Re,Rp) of a
+// large cell, 10^8 columns): one thread per column streams its B[r][col]
+// down r, widens it and accumulates every row in FP64 registers; the phases,
+// the same for every thread, come from a table [M][K] by scalar loads.  One
+// pass over B at the HBM rate, instead of MFMA tiles whose 16 rows are half
+// empty for 8 k and whose B panel is widened through LDS.
+template <int MR, int CPT>
+__global__ __launch_bounds__(256) void k_re_sum_b32(int M, long N, int K, const double2* __restrict__ tab,
+                                                    const float* __restrict__ B, double* __restrict__ C) {
+    // CPT adjacent columns per thread (CPT = 2: N even, one 16-byte load per
+    // vector r); past the end the last column is loaded and nothing stored
+    typedef float fv __attribute__((ext_vector_type(2 * CPT)));
+    const long col = CPT * ((long)blockIdx.x * 256 + threadIdx.x);
+    const bool ok = col < N;
+    const long cc = ok ? col : N - CPT;
+    const auto* ut = reinterpret_cast<const __attribute__((address_space(4))) double*>(reinterpret_cast<uintptr_t>(tab));
+    double ar[CPT][MR], ai[CPT][MR];
+#pragma unroll
+    for (int h = 0; h < CPT; ++h)
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            ar[h][m] = 0.0;
+            ai[h][m] = 0.0;
+        }
+#pragma unroll 4
+    for (int r = 0; r < K; ++r) {
+        const fv b = *reinterpret_cast<const fv*>(B + ((long)r * N + cc) * 2);
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            if (m < M) {
+                const double pc = ut[2 * ((long)m * K + r)], ps = ut[2 * ((long)m * K + r) + 1];
+#pragma unroll
+                for (int h = 0; h < CPT; ++h) {
+                    const double br = b[2 * h], bi = b[2 * h + 1];
+                    ar[h][m] += pc * br - ps * bi;
+                    ai[h][m] += pc * bi + ps * br;
+                }
+            }
+        }
+    }
+    if (!ok) return;
+#pragma unroll
+    for (int h = 0; h < CPT; ++h)
+#pragma unroll
+        for (int m = 0; m < MR; ++m)
+            if (m < M) *reinterpret_cast<double2*>(C + ((long)m * N + col + h) * 2) = double2{ar[h][m], ai[h][m]};
+}
+
 // Phase table of one point set against a vector list: tab[m][r] =
 // (cos, sin)(2 pi x_m . n_r), the argument reduced in FP64 as in the sums.
 __global__ void k_phase_table(int M, int K, const double* __restrict__ x, const int32_t* __restrict__ nvec,
@@ -780,9 +829,24 @@ void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x
 }
 
 void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
-                        const float* B, long sB, double* C, long sC, hipStream_t st) {
+                        const float* B, long sB, double* C, long sC, double* tab, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
-    if (M <= 16) {
+    if (M <= 8 && tab != nullptr && x0 == nullptr && Z == 1 && K > 0) {
+        // a k batch of at most 8: the rows' phases once into a table, then one
+        // streaming pass over B (k_re_sum_b32)
+        const long nt = (long)M * K;
+        hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, M, K, x, nvec,
+                           reinterpret_cast<double2*>(tab));
+        const int cpt = N % 2 == 0 ? 2 : 1;
+        const long nb = ((long)N + 256 * cpt - 1) / (256 * cpt);
+        if (nb > 0x7fffffffL) throw Error{-1, "phase_gemm_f64_b32: grid too large"};
+        if (cpt == 2)
+            hipLaunchKernelGGL((k_re_sum_b32<8, 2>), dim3((unsigned)nb), dim3(256), 0, st, M, (long)N, K,
+                               reinterpret_cast<const double2*>(tab), B, C);
+        else
+            hipLaunchKernelGGL((k_re_sum_b32<8, 1>), dim3((unsigned)nb), dim3(256), 0, st, M, (long)N, K,
+                               reinterpret_cast<const double2*>(tab), B, C);
+    } else if (M <= 16) {
         // a k batch of at most 16: 16-row tiles, the waves along the columns
         dim3 grid((N + 255) / 256, 1, Z);
         hipLaunchKernelGGL((k_phase_gemm<double, 4, false, false, false, float, true>), grid, dim3(256), 0, st, M, N,
