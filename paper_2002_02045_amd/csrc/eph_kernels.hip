@@ -983,6 +983,20 @@ __global__ void k_band_velocity(int nk, int nw, const double* __restrict__ dh, c
 
 void apply_u_right(int Z, int nrp, int nm, int nw, const double* g, const double* u, double* out, hipStream_t st) {
     const long per = (long)nrp * nm * nw * nw;
+    if (nw > 16) {
+        // large models: Z x nrp x nm products of nw x nw blocks with U(k) on
+        // the matrix cores (U shared by the blocks of one k)
+        CBatch b{};
+        b.n1 = (long)nrp * nm;
+        b.sa0 = per;
+        b.sa1 = (long)nw * nw;
+        b.sb0 = (long)nw * nw;
+        b.sb1 = 0;
+        b.sc0 = per;
+        b.sc1 = (long)nw * nw;
+        cgemm_f64_batched(nw, nw, nw, (long)Z * nrp * nm, b, g, nw, u, nw, out, nw, st);
+        return;
+    }
     hipLaunchKernelGGL(k_apply_u_right, dim3((unsigned)((per + 255) / 256), Z), dim3(256), 0, st, nrp, nm, nw, g, u, out);
     check_launch("apply_u_right");
 }

@@ -389,6 +389,11 @@ void eph_wide_rates_vjp(const WideChunk& w, const double* lam, double* gwbar, hi
     }
 }
 
+void cgemm_f64_batched(int M, int N, int K, long nbatch, const CBatch& b, const double* A, long lda, const double* B,
+                       long ldb, double* C, long ldc, hipStream_t st) {
+    launch_cgemm<double, double, double, false>(M, N, K, nbatch, b, A, lda, B, ldb, C, ldc, st);
+}
+
 void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st) {
     if (w.nkb <= 0 || w.nq <= 0) return;
     if (f32)

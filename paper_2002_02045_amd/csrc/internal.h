@@ -227,6 +227,10 @@ struct WideChunk {
     int nblk, qpb;
 };
 void eph_wide_chunk(const WideChunk& w, int f32, int rates, hipStream_t st);
+// C[b] = A[b] B[b] for a batch of complex FP64 matrices (row-major, strides of
+// CBatch) on the FP64 matrix cores, 64 x 64 tiles
+void cgemm_f64_batched(int M, int N, int K, long nbatch, const CBatch& b, const double* A, long lda, const double* B,
+                       long ldb, double* C, long ldc, hipStream_t st);
 // Adjoint of the rates of a chunk (FP64; w.g holds g'^W on entry and is work):
 // gwbar [nkb][nq][nm][nw][nw] = dL/dg'^W for L = sum_nk lam_nk Gamma_nk.
 void eph_wide_rates_vjp(const WideChunk& w, const double* lam, double* gwbar, hipStream_t st);
