@@ -751,8 +751,8 @@ __global__ void k_fold_herm(int nk, const double* __restrict__ kpts, int Kh, con
 template <int MR, int CPT>
 __global__ __launch_bounds__(256) void k_re_sum_b32(int M, long N, int K, const double2* __restrict__ tab,
                                                     const float* __restrict__ B, double* __restrict__ C) {
-    // CPT adjacent columns per thread (CPT = 2: N even, one 16-byte load per
-    // vector r); past the end the last column is loaded and nothing stored
+    // CPT adjacent columns per thread (CPT = 2 needs N even: one 16-byte load
+    // per vector r); past the end the last columns are loaded, nothing stored
     typedef float fv __attribute__((ext_vector_type(2 * CPT)));
     const long col = CPT * ((long)blockIdx.x * 256 + threadIdx.x);
     const bool ok = col < N;
@@ -831,21 +831,16 @@ void phase_gemm_f64(int M, int N, int K, int Z, const double* x, const double* x
 void phase_gemm_f64_b32(int M, int N, int K, int Z, const double* x, const double* x0, const int32_t* nvec,
                         const float* B, long sB, double* C, long sC, double* tab, hipStream_t st) {
     if (M <= 0 || N <= 0 || Z <= 0) return;
-    if (M <= 8 && tab != nullptr && x0 == nullptr && Z == 1 && K > 0) {
-        // a k batch of at most 8: the rows' phases once into a table, then one
-        // streaming pass over B (k_re_sum_b32)
+    if (M <= 8 && N % 2 == 0 && tab != nullptr && x0 == nullptr && Z == 1 && K > 0) {
+        // a k batch of at most 8 (and an even column count): the rows' phases
+        // once into a table, then one streaming pass over B (k_re_sum_b32)
         const long nt = (long)M * K;
         hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, M, K, x, nvec,
                            reinterpret_cast<double2*>(tab));
-        const int cpt = N % 2 == 0 ? 2 : 1;
-        const long nb = ((long)N + 256 * cpt - 1) / (256 * cpt);
+        const long nb = ((long)N + 511) / 512;
         if (nb > 0x7fffffffL) throw Error{-1, "phase_gemm_f64_b32: grid too large"};
-        if (cpt == 2)
-            hipLaunchKernelGGL((k_re_sum_b32<8, 2>), dim3((unsigned)nb), dim3(256), 0, st, M, (long)N, K,
-                               reinterpret_cast<const double2*>(tab), B, C);
-        else
-            hipLaunchKernelGGL((k_re_sum_b32<8, 1>), dim3((unsigned)nb), dim3(256), 0, st, M, (long)N, K,
-                               reinterpret_cast<const double2*>(tab), B, C);
+        hipLaunchKernelGGL((k_re_sum_b32<8, 2>), dim3((unsigned)nb), dim3(256), 0, st, M, (long)N, K,
+                           reinterpret_cast<const double2*>(tab), B, C);
     } else if (M <= 16) {
         // a k batch of at most 16: 16-row tiles, the waves along the columns
         dim3 grid((N + 255) / 256, 1, Z);
