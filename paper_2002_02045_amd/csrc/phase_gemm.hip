@@ -138,17 +138,28 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
     for (int kc = 0; kc < K; kc += kKC) {
         // rows past K and columns past N load the last valid one (a row past K
         // meets a zero phase, a column past N is never stored): no branch, one
-        // (re, im) load per element and plane
+        // (re, im) load per element and plane.  Every load of the chunk is
+        // issued before the first LDS write, so the thread waits on one
+        // memory latency per chunk, not one per element.
         static_assert(kKC * WBN % 256 == 0, "whole elements per thread");
+        constexpr int EPT = kKC * WBN / 256;
+        tb2 bv[EPT][NB];
 #pragma unroll
-        for (int e = tid; e < kKC * WBN; e += 256) {
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
             const int kk = e / WBN, nn = e % WBN;
             const long r = min(kc + kk, K - 1), col = min(col0 + nn, N - 1);
 #pragma unroll
+            for (int h = 0; h < NB; ++h) bv[j][h] = *reinterpret_cast<const tb2*>(bz + ((r * NB + h) * N + col) * 2);
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
+            const int kk = e / WBN, nn = e % WBN;
+#pragma unroll
             for (int h = 0; h < NB; ++h) {
-                const tb2 v = *reinterpret_cast<const tb2*>(bz + ((r * NB + h) * N + col) * 2);
-                bs[kk][2 * h][nn] = (T)v.x;
-                bs[kk][2 * h + 1][nn] = (T)v.y;
+                bs[kk][2 * h][nn] = (T)bv[j][h].x;
+                bs[kk][2 * h + 1][nn] = (T)bv[j][h].y;
             }
         }
         if (tid < kKC * 3) {
@@ -164,6 +175,9 @@ __global__ __launch_bounds__(256) void k_phase_gemm(int M, int N, int K, const d
         }
 #pragma unroll
         for (int s = 0; s < kKC / 4; ++s) {
+            // k-steps wholly past K add nothing (zero phases): skipped, a
+            // branch on a workgroup-uniform value
+            if (kc + 4 * s >= K) break;
             const int kk = 4 * s + lk;
             T pc = 0, ps = 0;
             if (rowok && kc + kk < K) {
