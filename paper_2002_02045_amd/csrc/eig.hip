@@ -18,19 +18,23 @@
 namespace ephx {
 namespace {
 
-// 1/b and 1/sqrt(x) from the hardware estimates refined by two Newton steps
-// each (quadratic convergence from the estimate's ~1e-8 relative error to the
-// last bits); any nonzero b, any positive normal x.
+// 1/b and 1/sqrt(x) from the hardware estimates (relative error below 6e-8,
+// measured) and one third-order correction each: with e the estimate's
+// residual, 1/b = r / (1 - e), e = 1 - b r, and 1/sqrt(x) = y (1 - e)^(-1/2),
+// e = 1 - x y^2, truncated after e^2 (the dropped terms are below 1e-21
+// relative).  Any nonzero b, any positive normal x; within 2 ulp (measured),
+// as two Newton steps, with three dependent operations after the estimate
+// instead of four (1/b) and four instead of six (1/sqrt(x)): the QL rotation
+// chain, one inverse root per rotation, is latency-bound.
 __device__ __forceinline__ double recip(double b) {
-    double y = __builtin_amdgcn_rcp(b);
-    y = y * fma(-b, y, 2.0);
-    return y * fma(-b, y, 2.0);
+    const double r = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ double rsqrt1(double x) {
-    const double h = 0.5 * x;
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * fma(-h * y, y, 1.5);
-    return y * fma(-h * y, y, 1.5);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // Device arithmetic of the one-lane-per-matrix solver (eig_ql.h): the
