@@ -145,7 +145,10 @@ __host__ __device__ __forceinline__ void ql_deflate(double (&d)[N], double (&e)[
                 const double r2 = f * f + g * g;
                 const bool zero = on && r2 == 0.0;
                 const bool upd = on && !zero;
-                const double ir = MathT::rsqrt(upd ? r2 : 1.0);
+                // a lane that does not update (r2 = 0 among them, where ir is
+                // infinite) discards all that ir feeds through the selects
+                // below, so the inverse root waits on nothing but r2
+                const double ir = MathT::rsqrt(r2);
                 const double s1 = f * ir, c1 = g * ir;
                 const double g1 = d[i + 1] - p;
                 const double q1 = (d[i] - g1) * s1 + 2.0 * c1 * b;
