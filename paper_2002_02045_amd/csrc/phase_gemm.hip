@@ -590,9 +590,15 @@ __global__ __launch_bounds__(64 * NWV) void k_gemm_bf16_planes(int M, int N, int
             load_a(kc + kBK);
         }
         const uint16_t* bb = bsh + h * BUF;
-        // groups g = (column tile, k-step); the B fragments of group g+1 are read
-        // from LDS while the MFMAs of group g run
-        u16x8 br[2][NS], bi[2][NS];
+        // groups g = (column tile, k-step); the B fragments of group g + RD are
+        // read from LDS while the MFMAs of group g run, RD = 2 for two-part
+        // operands (three register slots, the order held by scheduling
+        // barriers: left alone, the compiler moved each read next to its
+        // MFMAs and reused one register set, so most MFMAs waited on an LDS
+        // read issued just before them; 2-3 % faster at the Si-like shape),
+        // RD = 1 for three parts (the barriers cost those forms registers).
+        constexpr int RD = NS == 2 ? 2 : 1, NSL = RD + 1;
+        u16x8 br[NSL][NS], bi[NSL][NS];
         auto read_b = [&](int g, int slotb) {
             const int nn = (g >> 1) * 32 + l32;
             const int so = nn * kBK + 8 * swz(nn, 2 * (g & 1) + kg);
@@ -602,11 +608,13 @@ __global__ __launch_bounds__(64 * NWV) void k_gemm_bf16_planes(int M, int N, int
                 bi[slotb][t] = *reinterpret_cast<const u16x8*>(bb + (NS + t) * PLANE + so);
             }
         };
-        read_b(0, 0);
+#pragma unroll
+        for (int g = 0; g < RD; ++g) read_b(g, g);
 #pragma unroll
         for (int g = 0; g < 2 * CT; ++g) {
-            if (g + 1 < 2 * CT) read_b(g + 1, (g + 1) & 1);
-            const int ct = g >> 1, s = g & 1, cs = g & 1;
+            if (g + RD < 2 * CT) read_b(g + RD, (g + RD) % NSL);
+            if constexpr (RD == 2) __builtin_amdgcn_sched_barrier(0);
+            const int ct = g >> 1, s = g & 1, cs = g % NSL;
 #pragma unroll
             for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
@@ -622,6 +630,7 @@ __global__ __launch_bounds__(64 * NWV) void k_gemm_bf16_planes(int M, int N, int
                         }
                     }
                 }
+            if constexpr (RD == 2) __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
