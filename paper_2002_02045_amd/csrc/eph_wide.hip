@@ -72,40 +72,37 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
         are[cb] = acc_t{0, 0, 0, 0};
         aim[cb] = acc_t{0, 0, 0, 0};
     }
+    typedef TA ta2 __attribute__((ext_vector_type(2)));
+    typedef TB tb2 __attribute__((ext_vector_type(2)));
+    constexpr int EPT = kKs * kT / 256;   // elements of each operand per thread and step
     for (int kc = 0; kc < K; kc += kKs) {
-        for (int e = tid; e < kKs * kT; e += 256) {
+        // every load of the step first (indices clamped into the matrices,
+        // the values past their edges replaced by zeros below), then the LDS
+        // writes: the thread waits on one memory latency per step
+        ta2 av[EPT];
+        tb2 bv[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
             // A: for CA the stored matrix is read along m (contiguous), else along k
-            int kk, m;
-            if (CA) {
-                kk = e / kT;
-                m = e % kT;
-            } else {
-                m = e / kKs;
-                kk = e % kKs;
-            }
-            T re = 0, im = 0;
-            if (kc + kk < K && row0 + m < M) {
-                if (CA) {
-                    const long o = (long)(kc + kk) * lda + row0 + m;
-                    re = (T)A[2 * o];
-                    im = -(T)A[2 * o + 1];
-                } else {
-                    const long o = (long)(row0 + m) * lda + kc + kk;
-                    re = (T)A[2 * o];
-                    im = (T)A[2 * o + 1];
-                }
-            }
-            as[kk][m][0] = re;
-            as[kk][m][1] = im;
+            const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
+            const long ka = min(kc + kk, K - 1), ma = min(row0 + m, M - 1);
+            av[j] = *reinterpret_cast<const ta2*>(A + 2 * (CA ? ka * lda + ma : ma * lda + ka));
             const int kb = e / kT, n = e % kT;
-            T br = 0, bi = 0;
-            if (kc + kb < K && col0 + n < N) {
-                const long o = (long)(kc + kb) * ldb + col0 + n;
-                br = (T)B[2 * o];
-                bi = (T)B[2 * o + 1];
-            }
-            bs[kb][n][0] = br;
-            bs[kb][n][1] = bi;
+            const long kbb = min(kc + kb, K - 1), nb = min(col0 + n, N - 1);
+            bv[j] = *reinterpret_cast<const tb2*>(B + 2 * (kbb * ldb + nb));
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
+            const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
+            const bool aok = kc + kk < K && row0 + m < M;
+            as[kk][m][0] = aok ? (T)av[j].x : (T)0;
+            as[kk][m][1] = aok ? (CA ? -(T)av[j].y : (T)av[j].y) : (T)0;
+            const int kb = e / kT, n = e % kT;
+            const bool bok = kc + kb < K && col0 + n < N;
+            bs[kb][n][0] = bok ? (T)bv[j].x : (T)0;
+            bs[kb][n][1] = bok ? (T)bv[j].y : (T)0;
         }
         __syncthreads();
 #pragma unroll
