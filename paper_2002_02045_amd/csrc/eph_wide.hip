@@ -75,34 +75,43 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
     typedef TA ta2 __attribute__((ext_vector_type(2)));
     typedef TB tb2 __attribute__((ext_vector_type(2)));
     constexpr int EPT = kKs * kT / 256;   // elements of each operand per thread and step
+    // elements whose loads are issued together before their LDS writes: all
+    // of a step's for FP32 tiles; half for FP64, whose operands and addresses
+    // would otherwise halve the waves a SIMD holds
+    constexpr int EB = sizeof(T) == 4 ? EPT : EPT / 2;
     for (int kc = 0; kc < K; kc += kKs) {
-        // every load of the step first (indices clamped into the matrices,
-        // the values past their edges replaced by zeros below), then the LDS
-        // writes: the thread waits on one memory latency per step
-        ta2 av[EPT];
-        tb2 bv[EPT];
+        // indices clamped into the matrices, the values past their edges
+        // replaced by zeros: the thread waits on EPT / EB memory latencies per
+        // step instead of one per element
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = tid + 256 * j;
-            // A: for CA the stored matrix is read along m (contiguous), else along k
-            const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
-            const long ka = min(kc + kk, K - 1), ma = min(row0 + m, M - 1);
-            av[j] = *reinterpret_cast<const ta2*>(A + 2 * (CA ? ka * lda + ma : ma * lda + ka));
-            const int kb = e / kT, n = e % kT;
-            const long kbb = min(kc + kb, K - 1), nb = min(col0 + n, N - 1);
-            bv[j] = *reinterpret_cast<const tb2*>(B + 2 * (kbb * ldb + nb));
-        }
+        for (int j0 = 0; j0 < EPT; j0 += EB) {
+            ta2 av[EB];
+            tb2 bv[EB];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = tid + 256 * j;
-            const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
-            const bool aok = kc + kk < K && row0 + m < M;
-            as[kk][m][0] = aok ? (T)av[j].x : (T)0;
-            as[kk][m][1] = aok ? (CA ? -(T)av[j].y : (T)av[j].y) : (T)0;
-            const int kb = e / kT, n = e % kT;
-            const bool bok = kc + kb < K && col0 + n < N;
-            bs[kb][n][0] = bok ? (T)bv[j].x : (T)0;
-            bs[kb][n][1] = bok ? (T)bv[j].y : (T)0;
+            for (int jj = 0; jj < EB; ++jj) {
+                const int e = tid + 256 * (j0 + jj);
+                // A: for CA the stored matrix is read along m (contiguous), else along k
+                const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
+                const long ka = min(kc + kk, K - 1), ma = min(row0 + m, M - 1);
+                av[jj] = *reinterpret_cast<const ta2*>(A + 2 * (CA ? ka * lda + ma : ma * lda + ka));
+                const int kb = e / kT, n = e % kT;
+                const long kbb = min(kc + kb, K - 1), nb = min(col0 + n, N - 1);
+                bv[jj] = *reinterpret_cast<const tb2*>(B + 2 * (kbb * ldb + nb));
+            }
+#pragma unroll
+            for (int jj = 0; jj < EB; ++jj) {
+                const int e = tid + 256 * (j0 + jj);
+                const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
+                const bool aok = kc + kk < K && row0 + m < M;
+                as[kk][m][0] = aok ? (T)av[jj].x : (T)0;
+                as[kk][m][1] = aok ? (CA ? -(T)av[jj].y : (T)av[jj].y) : (T)0;
+                const int kb = e / kT, n = e % kT;
+                const bool bok = kc + kb < K && col0 + n < N;
+                bs[kb][n][0] = bok ? (T)bv[jj].x : (T)0;
+                bs[kb][n][1] = bok ? (T)bv[jj].y : (T)0;
+            }
+            // keeps the next batch's loads behind these writes
+            if constexpr (EB < EPT) __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
 #pragma unroll
