@@ -798,9 +798,12 @@ __global__ __launch_bounds__(256) void k_re_sum_b32(int M, long N, int K, const 
                 const double pc = ut[2 * ((long)m * K + r)], ps = ut[2 * ((long)m * K + r) + 1];
 #pragma unroll
                 for (int h = 0; h < CPT; ++h) {
+                    // two FMAs into the accumulator per real part (the
+                    // expression acc + (p b - q c) costs a product, an FMA and
+                    // an add)
                     const double br = b[2 * h], bi = b[2 * h + 1];
-                    ar[h][m] += pc * br - ps * bi;
-                    ai[h][m] += pc * bi + ps * br;
+                    ar[h][m] = fma(-ps, bi, fma(pc, br, ar[h][m]));
+                    ai[h][m] = fma(ps, br, fma(pc, bi, ai[h][m]));
                 }
             }
         }
