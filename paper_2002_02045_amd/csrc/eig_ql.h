@@ -36,7 +36,7 @@ __host__ __device__ __forceinline__ void herm_reflect(HermLane<N>& s) {
         const double alr = s.ar[J + 1][J], ali = s.ai[J + 1][J];
         double xn2 = 0.0;
 #pragma unroll
-        for (int i = J + 2; i < N; ++i) xn2 += s.ar[i][J] * s.ar[i][J] + s.ai[i][J] * s.ai[i][J];
+        for (int i = J + 2; i < N; ++i) xn2 = fma(s.ar[i][J], s.ar[i][J], fma(s.ai[i][J], s.ai[i][J], xn2));
         const bool ident = xn2 == 0.0 && ali == 0.0;
         const double nrm2 = alr * alr + ali * ali + xn2;
         const double nrm = nrm2 * MathT::rsqrt(ident ? 1.0 : nrm2);
@@ -70,8 +70,8 @@ __host__ __device__ __forceinline__ void herm_reflect(HermLane<N>& s) {
                 const int ia = J + 1 + a, ibb = J + 1 + b;
                 const double mr = a >= b ? s.ar[ia][ibb] : s.ar[ibb][ia];
                 const double mi = a > b ? s.ai[ia][ibb] : (a == b ? 0.0 : -s.ai[ibb][ia]);
-                yr += mr * vr[b] - mi * vi[b];
-                yi += mr * vi[b] + mi * vr[b];
+                yr = fma(mr, vr[b], fma(-mi, vi[b], yr));
+                yi = fma(mr, vi[b], fma(mi, vr[b], yi));
             }
             pr[a] = tr * yr - ti * yi;
             pi[a] = tr * yi + ti * yr;
@@ -79,8 +79,8 @@ __host__ __device__ __forceinline__ void herm_reflect(HermLane<N>& s) {
         double hr = 0.0, hi = 0.0;   // p^H v
 #pragma unroll
         for (int a = 0; a < L; ++a) {
-            hr += pr[a] * vr[a] + pi[a] * vi[a];
-            hi += pr[a] * vi[a] - pi[a] * vr[a];
+            hr = fma(pr[a], vr[a], fma(pi[a], vi[a], hr));
+            hi = fma(pr[a], vi[a], fma(-pi[a], vr[a], hi));
         }
         const double kr = -0.5 * (tr * hr - ti * hi), ki = -0.5 * (tr * hi + ti * hr);
 #pragma unroll
@@ -94,11 +94,13 @@ __host__ __device__ __forceinline__ void herm_reflect(HermLane<N>& s) {
         for (int a = 0; a < L; ++a)
 #pragma unroll
             for (int b = 0; b <= a; ++b) {
-                // v_a conj(w_b) + w_a conj(v_b)
-                const double ur = vr[a] * pr[b] + vi[a] * pi[b] + pr[a] * vr[b] + pi[a] * vi[b];
-                const double ui = vi[a] * pr[b] - vr[a] * pi[b] + pi[a] * vr[b] - pr[a] * vi[b];
-                s.ar[J + 1 + a][J + 1 + b] -= ur;
-                if (a != b) s.ai[J + 1 + a][J + 1 + b] -= ui;
+                // minus v_a conj(w_b) + w_a conj(v_b), as FMAs into the entry
+                double& xr = s.ar[J + 1 + a][J + 1 + b];
+                xr = fma(-vr[a], pr[b], fma(-vi[a], pi[b], fma(-pr[a], vr[b], fma(-pi[a], vi[b], xr))));
+                if (a != b) {
+                    double& xi = s.ai[J + 1 + a][J + 1 + b];
+                    xi = fma(-vi[a], pr[b], fma(vr[a], pi[b], fma(-pi[a], vr[b], fma(pr[a], vi[b], xi))));
+                }
             }
         herm_reflect<MathT, N, J + 1>(s);
     }
@@ -203,8 +205,8 @@ __host__ __device__ __forceinline__ void herm_back_step(const HermLane<N>& s, do
         double yr = xr[J + 1], yi = xi[J + 1];
 #pragma unroll
         for (int i = J + 2; i < N; ++i) {
-            yr += s.ar[i][J] * xr[i] + s.ai[i][J] * xi[i];
-            yi += s.ar[i][J] * xi[i] - s.ai[i][J] * xr[i];
+            yr = fma(s.ar[i][J], xr[i], fma(s.ai[i][J], xi[i], yr));
+            yi = fma(s.ar[i][J], xi[i], fma(-s.ai[i][J], xr[i], yi));
         }
         // x -= tau v y
         const double tyr = tr * yr - ti * yi, tyi = tr * yi + ti * yr;
@@ -212,8 +214,8 @@ __host__ __device__ __forceinline__ void herm_back_step(const HermLane<N>& s, do
         xi[J + 1] -= tyi;
 #pragma unroll
         for (int i = J + 2; i < N; ++i) {
-            xr[i] -= s.ar[i][J] * tyr - s.ai[i][J] * tyi;
-            xi[i] -= s.ar[i][J] * tyi + s.ai[i][J] * tyr;
+            xr[i] = fma(-s.ar[i][J], tyr, fma(s.ai[i][J], tyi, xr[i]));
+            xi[i] = fma(-s.ar[i][J], tyi, fma(-s.ai[i][J], tyr, xi[i]));
         }
         herm_back_step<N, J - 1>(s, xr, xi);
     }
