@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64) void k_eig_tql(int n, double* __restrict__ A, l
             const int i = l + 64 * r;
             if (i >= j + 2 && i < n) {
                 const double2 x = a[tri_idx(i, j)];
-                xn2 += x.x * x.x + x.y * x.y;
+                xn2 = fma(x.x, x.x, fma(x.y, x.y, xn2));
             }
         }
         xn2 = wave_sum(xn2);
@@ -217,12 +217,12 @@ __global__ __launch_bounds__(64) void k_eig_tql(int n, double* __restrict__ A, l
                         mim = -t.y;
                     }
                     const double2 vm = vv[m];
-                    yr += mr * vm.x - mim * vm.y;
-                    yi += mr * vm.y + mim * vm.x;
+                    yr = fma(mr, vm.x, fma(-mim, vm.y, yr));
+                    yi = fma(mr, vm.y, fma(mim, vm.x, yi));
                 }
                 p[r] = double2{tr * yr - ti * yi, tr * yi + ti * yr};
-                hr += p[r].x * v[r].x + p[r].y * v[r].y;
-                hi += p[r].x * v[r].y - p[r].y * v[r].x;
+                hr = fma(p[r].x, v[r].x, fma(p[r].y, v[r].y, hr));
+                hi = fma(p[r].x, v[r].y, fma(-p[r].y, v[r].x, hi));
             }
         }
         hr = wave_sum(hr);
@@ -242,12 +242,12 @@ __global__ __launch_bounds__(64) void k_eig_tql(int n, double* __restrict__ A, l
             const int i = l + 64 * r;
             if (i >= j + 1 && i < n) {
                 for (int m = j + 1; m <= i; ++m) {
+                    // minus v_i conj(w_m) + w_i conj(v_m), as FMAs into the entry
                     const double2 vm = vv[m], wm = ww[m];
-                    const double ur = v[r].x * wm.x + v[r].y * wm.y + w[r].x * vm.x + w[r].y * vm.y;
-                    const double ui = v[r].y * wm.x - v[r].x * wm.y + w[r].y * vm.x - w[r].x * vm.y;
                     double2 t = a[tri_idx(i, m)];
-                    t.x -= ur;
-                    if (m != i) t.y -= ui;
+                    t.x = fma(-v[r].x, wm.x, fma(-v[r].y, wm.y, fma(-w[r].x, vm.x, fma(-w[r].y, vm.y, t.x))));
+                    if (m != i)
+                        t.y = fma(-v[r].y, wm.x, fma(v[r].x, wm.y, fma(-w[r].y, vm.x, fma(w[r].x, vm.y, t.y))));
                     a[tri_idx(i, m)] = t;
                 }
             }
@@ -411,8 +411,8 @@ __global__ __launch_bounds__(256) void k_eig_tqlv(int n, const double* __restric
                     yi += xi[r];
                 } else if (i >= j + 2 && i < n) {
                     const double2 v = refl[base + i];
-                    yr += v.x * xr[r] + v.y * xi[r];
-                    yi += v.x * xi[r] - v.y * xr[r];
+                    yr = fma(v.x, xr[r], fma(v.y, xi[r], yr));
+                    yi = fma(v.x, xi[r], fma(-v.y, xr[r], yi));
                 }
             }
 #pragma unroll
@@ -429,8 +429,8 @@ __global__ __launch_bounds__(256) void k_eig_tqlv(int n, const double* __restric
                     xi[r] -= tyi;
                 } else if (i >= j + 2 && i < n) {
                     const double2 v = refl[base + i];
-                    xr[r] -= v.x * tyr - v.y * tyi;
-                    xi[r] -= v.x * tyi + v.y * tyr;
+                    xr[r] = fma(-v.x, tyr, fma(v.y, tyi, xr[r]));
+                    xi[r] = fma(-v.x, tyi, fma(-v.y, tyr, xi[r]));
                 }
             }
         }

@@ -87,8 +87,8 @@ __global__ void k_apply_u_right_adj(int nrp, int nm, int nw, const double* __res
     cx<double> acc = {0.0, 0.0};
     for (int n = 0; n < nw; ++n) {
         const cx<double> a = ld(gz, row * nw + n), b = ld(uz, (long)j * nw + n);
-        acc.x += a.x * b.x + a.y * b.y;   // a * conj(b)
-        acc.y += a.y * b.x - a.x * b.y;
+        acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));   // a * conj(b)
+        acc.y = fma(a.y, b.x, fma(-a.x, b.y, acc.y));
     }
     out[((long)z * per + t) * 2] = acc.x;
     out[((long)z * per + t) * 2 + 1] = acc.y;
