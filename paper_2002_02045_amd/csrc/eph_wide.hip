@@ -46,14 +46,16 @@ constexpr int kKs = 16;   // K per staging step
 // Batched complex GEMM, C[b] = op(A[b]) B[b], row-major, interleaved complex.
 // op(A)(m,k) = A[m*lda + k], or conj(A[k*lda + m]) when CA.  The batch index is
 // b = (b0 * n1 + b1), offsets b0*s?0 + b1*s?1 (complex elements).  256 threads
-// own a 64 x 64 tile: wave w the rows 16w..16w+15, four 16-column MFMA blocks.
-template <typename T, typename TA, typename TB, bool CA>
+// own a 64 x 16 CB tile: wave w the rows 16w..16w+15, CB 16-column MFMA
+// blocks (CB = 8 halves the A reads per product where N allows).
+template <typename T, typename TA, typename TB, bool CA, int CB = 4>
 __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int ntl, CBatch bt, const TA* __restrict__ A,
                                                long lda, const TB* __restrict__ B, long ldb, T* __restrict__ C,
                                                long ldc) {
     typedef typename Acc<T>::type acc_t;
+    constexpr int kTN = 16 * CB;   // columns of the tile
     __shared__ T as[kKs][kT][2];   // [k][m]
-    __shared__ T bs[kKs][kT][2];   // [k][n]
+    __shared__ T bs[kKs][kTN][2];  // [k][n]
     long bid = blockIdx.x;
     const int nti = (int)(bid % ntl);
     bid /= ntl;
@@ -63,55 +65,64 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
     A += 2 * (b0 * bt.sa0 + b1 * bt.sa1);
     B += 2 * (b0 * bt.sb0 + b1 * bt.sb1);
     C += 2 * (b0 * bt.sc0 + b1 * bt.sc1);
-    const int row0 = mti * kT, col0 = nti * kT;
+    const int row0 = mti * kT, col0 = nti * kTN;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    acc_t are[4], aim[4];
+    acc_t are[CB], aim[CB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
         are[cb] = acc_t{0, 0, 0, 0};
         aim[cb] = acc_t{0, 0, 0, 0};
     }
     typedef TA ta2 __attribute__((ext_vector_type(2)));
     typedef TB tb2 __attribute__((ext_vector_type(2)));
-    constexpr int EPT = kKs * kT / 256;   // elements of each operand per thread and step
-    // elements whose loads are issued together before their LDS writes: all
-    // of a step's for FP32 tiles; half for FP64, whose operands and addresses
-    // would otherwise halve the waves a SIMD holds
-    constexpr int EB = sizeof(T) == 4 ? EPT : EPT / 2;
+    constexpr int EPA = kKs * kT / 256, EPB = kKs * kTN / 256;   // elements per thread and step
+    // load phases per step: all of a step's loads are issued before its LDS
+    // writes for FP32 tiles; FP64 takes two phases held apart by a scheduling
+    // barrier, whose operands and addresses would otherwise halve the waves a
+    // SIMD holds
+    constexpr int NPH = sizeof(T) == 4 ? 1 : 2, PA = EPA / NPH, PB = EPB / NPH;
     for (int kc = 0; kc < K; kc += kKs) {
         // indices clamped into the matrices, the values past their edges
-        // replaced by zeros: the thread waits on EPT / EB memory latencies per
-        // step instead of one per element
+        // replaced by zeros: the thread waits on NPH memory latencies per step
+        // instead of one per element
 #pragma unroll
-        for (int j0 = 0; j0 < EPT; j0 += EB) {
-            ta2 av[EB];
-            tb2 bv[EB];
+        for (int ph = 0; ph < NPH; ++ph) {
+            ta2 av[PA];
+            tb2 bv[PB];
 #pragma unroll
-            for (int jj = 0; jj < EB; ++jj) {
-                const int e = tid + 256 * (j0 + jj);
+            for (int jj = 0; jj < PA; ++jj) {
+                const int e = tid + 256 * (ph * PA + jj);
                 // A: for CA the stored matrix is read along m (contiguous), else along k
                 const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
                 const long ka = min(kc + kk, K - 1), ma = min(row0 + m, M - 1);
                 av[jj] = *reinterpret_cast<const ta2*>(A + 2 * (CA ? ka * lda + ma : ma * lda + ka));
-                const int kb = e / kT, n = e % kT;
+            }
+#pragma unroll
+            for (int jj = 0; jj < PB; ++jj) {
+                const int e = tid + 256 * (ph * PB + jj);
+                const int kb = e / kTN, n = e % kTN;
                 const long kbb = min(kc + kb, K - 1), nb = min(col0 + n, N - 1);
                 bv[jj] = *reinterpret_cast<const tb2*>(B + 2 * (kbb * ldb + nb));
             }
 #pragma unroll
-            for (int jj = 0; jj < EB; ++jj) {
-                const int e = tid + 256 * (j0 + jj);
+            for (int jj = 0; jj < PA; ++jj) {
+                const int e = tid + 256 * (ph * PA + jj);
                 const int kk = CA ? e / kT : e % kKs, m = CA ? e % kT : e / kKs;
                 const bool aok = kc + kk < K && row0 + m < M;
                 as[kk][m][0] = aok ? (T)av[jj].x : (T)0;
                 as[kk][m][1] = aok ? (CA ? -(T)av[jj].y : (T)av[jj].y) : (T)0;
-                const int kb = e / kT, n = e % kT;
+            }
+#pragma unroll
+            for (int jj = 0; jj < PB; ++jj) {
+                const int e = tid + 256 * (ph * PB + jj);
+                const int kb = e / kTN, n = e % kTN;
                 const bool bok = kc + kb < K && col0 + n < N;
                 bs[kb][n][0] = bok ? (T)bv[jj].x : (T)0;
                 bs[kb][n][1] = bok ? (T)bv[jj].y : (T)0;
             }
-            // keeps the next batch's loads behind these writes
-            if constexpr (EB < EPT) __builtin_amdgcn_sched_barrier(0);
+            // keeps the next phase's loads behind these writes
+            if constexpr (NPH > 1) __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
 #pragma unroll
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
             const int kk = 4 * s + lk;
             const T ar = as[kk][wave * 16 + li][0], ai = as[kk][wave * 16 + li][1];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < CB; ++cb) {
                 const T br = bs[kk][cb * 16 + li][0], bi = bs[kk][cb * 16 + li][1];
                 are[cb] = mfma(ar, br, are[cb]);
                 are[cb] = mfma(-ai, bi, are[cb]);
@@ -130,7 +141,7 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
         __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
         const int col = col0 + cb * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -147,11 +158,23 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, int mt, int 
 template <typename T, typename TA, typename TB, bool CA>
 void launch_cgemm(int M, int N, int K, long nbatch, const CBatch& bt, const TA* A, long lda, const TB* B, long ldb,
                   T* C, long ldc, hipStream_t st) {
-    const int mt = (M + kT - 1) / kT, ntl = (N + kT - 1) / kT;
+    // 128-column tiles for FP32 products wide enough to fill them (the mode
+    // projection, N = Nw^2): each staged A element then feeds twice the MFMAs
+    const bool wide = sizeof(T) == 4 && N >= 128;
+    const int tn = wide ? 128 : 64;
+    const int mt = (M + kT - 1) / kT, ntl = (N + tn - 1) / tn;
     const long blocks = nbatch * mt * ntl;
     if (blocks <= 0) return;
     if (blocks > 0x7fffffffL) throw Error{-1, "cgemm: grid too large"};
-    hipLaunchKernelGGL((k_cgemm<T, TA, TB, CA>), dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, mt, ntl, bt, A,
+    if constexpr (sizeof(T) == 4) {
+        if (wide) {
+            hipLaunchKernelGGL((k_cgemm<T, TA, TB, CA, 8>), dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, mt, ntl,
+                               bt, A, lda, B, ldb, C, ldc);
+            check_launch("cgemm");
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_cgemm<T, TA, TB, CA, 4>), dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, mt, ntl, bt, A,
                        lda, B, ldb, C, ldc);
     check_launch("cgemm");
 }
