@@ -179,9 +179,11 @@ void launch_cgemm(int M, int N, int K, long nbatch, const CBatch& bt, const TA* 
     check_launch("cgemm");
 }
 
-// P[q][nu][x] = sqrt(hbar^2/(2 M_x omega_nu)) e_x,nu(q) (zero for omega <= cut)
+// P[q][nu][x] = sqrt(hbar^2/(2 M_x omega_nu)) e_x,nu(q) (zero for omega <= cut),
+// formed in FP64 and stored in the precision of the product that reads it
+template <typename TP>
 __global__ void k_proj_matrix(int nq, int q_off, int nm, const double* __restrict__ omega, const double* __restrict__ evec,
-                              const double* __restrict__ minv, double omega_cut, double* __restrict__ P) {
+                              const double* __restrict__ minv, double omega_cut, TP* __restrict__ P) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long per = (long)nm * nm;
     if (t >= nq * per) return;
@@ -190,8 +192,8 @@ __global__ void k_proj_matrix(int nq, int q_off, int nm, const double* __restric
     const long qg = q_off + q;
     const double om = omega[qg * nm + nu];
     const double amp = om > omega_cut ? sqrt(kHbar2AmuA2 / (2.0 * om)) * minv[x] : 0.0;
-    P[2 * t] = amp * evec[2 * ((qg * nm + x) * nm + nu)];
-    P[2 * t + 1] = amp * evec[2 * ((qg * nm + x) * nm + nu) + 1];
+    P[2 * t] = (TP)(amp * evec[2 * ((qg * nm + x) * nm + nu)]);
+    P[2 * t + 1] = (TP)(amp * evec[2 * ((qg * nm + x) * nm + nu) + 1]);
 }
 
 // gh[pair][x][m][n] += C_x(q) ov[pair][m][n]
@@ -313,8 +315,11 @@ void wide_forward(const WideChunk& w, hipStream_t st) {
     // projection: batch (z, q), A = P(q), result over g'^W's storage
     {
         const long tot = (long)w.nq * nm * nm;
-        hipLaunchKernelGGL(k_proj_matrix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.nq, w.q_off, nm,
-                           w.omega, w.evec, w.minv, w.omega_cut, w.pmat);
+        // P in T: the FP32 product reads half the bytes of its shared operand,
+        // the same values it would have rounded while staging FP64 ones
+        T* pm = reinterpret_cast<T*>(w.pmat);
+        hipLaunchKernelGGL(k_proj_matrix<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.nq, w.q_off, nm,
+                           w.omega, w.evec, w.minv, w.omega_cut, pm);
         check_launch("proj_matrix");
         CBatch b{};
         b.n1 = w.nq;
@@ -324,7 +329,7 @@ void wide_forward(const WideChunk& w, hipStream_t st) {
         b.sb1 = (long)nm * nw2;
         b.sc0 = b.sb0;
         b.sc1 = b.sb1;
-        launch_cgemm<T, double, T, false>(nm, nw2, nm, npair, b, w.pmat, nm, gh, nw2, gw, nw2, st);
+        launch_cgemm<T, T, T, false>(nm, nw2, nm, npair, b, pm, nm, gh, nw2, gw, nw2, st);
     }
 }
 
