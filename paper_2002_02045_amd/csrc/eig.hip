@@ -47,25 +47,61 @@ struct LaneMath {
     static __device__ __forceinline__ bool any(bool p) { return __any(p); }
 };
 
-template <int N, int C>
-__device__ __forceinline__ void store_lane_vectors(const HermLane<N>& s, const int (&rk)[N], double* out) {
+template <int N, int C, class RS>
+__device__ __forceinline__ void store_lane_vectors(const HermLane<N>& s, const RS& rs, const int (&rk)[N],
+                                                   double* out) {
     if constexpr (C < N) {
         double xr[N], xi[N];
-        herm_eigenvector<N, C>(s, xr, xi);
+        herm_eigenvector<N, C>(s, rs, xr, xi);
 #pragma unroll
         for (int i = 0; i < N; ++i) *reinterpret_cast<double2*>(out + (i * N + rk[C]) * 2) = double2{xr[i], xi[i]};
-        store_lane_vectors<N, C + 1>(s, rk, out);
+        // the next column reads the reflectors in LDS again rather than
+        // holding them in registers across columns
+        __asm__ volatile("" ::: "memory");
+        store_lane_vectors<N, C + 1>(s, rs, rk, out);
     }
 }
+
+// The 8 x 8 solver keeps reflectors 0..3 (18 complex entries, 288 bytes per
+// lane) in LDS from the end of the reduction to the back-transform, entry e
+// of lane t at [e][t].  Its registers then stay under 256 and two 256-lane
+// workgroups (72 KB of LDS each) share a CU: two waves per SIMD, one issuing
+// while the other waits on the QL rotation chain.  (Parked in global memory
+// instead, the reflectors of the resident waves did not stay in L2.)
+constexpr int kReflLds = 4;
+template <int N>
+constexpr int refl_lds_entries() {
+    int c = 0;
+    for (int j = 0; j < kReflLds && j < N - 2; ++j) c += N - 2 - j;
+    return c;
+}
+__host__ __device__ constexpr int refl_entry(int n, int i, int j) { return j * (n - 2) - j * (j - 1) / 2 + (i - j - 2); }
+
+template <int N>
+struct ReflInLds {
+    const HermLane<N>& s;
+    const double2* lds;
+    int t;
+    __device__ __forceinline__ double re(int i, int j) const {
+        return j < kReflLds ? lds[refl_entry(N, i, j) * 256 + t].x : s.ar[i][j];
+    }
+    __device__ __forceinline__ double im(int i, int j) const {
+        return j < kReflLds ? lds[refl_entry(N, i, j) * 256 + t].y : s.ai[i][j];
+    }
+};
 
 // One matrix per lane (n <= 8): Householder tridiagonalisation, implicit QL,
 // eigenvectors U = Q Z (eig_ql.h).  PK selects the packed Hermitian input, else the Hermitian part of a complex
 // n x n matrix is taken; eigenvalues ascending, ties by index, eigenvector c
 // in column c of evecs[slot] (row-major complex n x n).
 template <typename Tin, int N, bool PK = false>
-__global__ __launch_bounds__(256) void k_eig_lane(int batch, const Tin* __restrict__ A, long strideA,
-                                                  double* __restrict__ evals, double* __restrict__ evecs) {
-    const long slot = (long)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 8 ? 2 : 1))) void k_eig_lane(
+    int batch, const Tin* __restrict__ A, long strideA, double* __restrict__ evals, double* __restrict__ evecs) {
+    constexpr bool LR = N == 8;
+    constexpr int NE = LR ? refl_lds_entries<N>() : 1;
+    __shared__ double2 rl[NE * 256];
+    const int tid = threadIdx.x;
+    const long slot = (long)blockIdx.x * 256 + tid;
     const bool valid = slot < batch;
     HermLane<N> s;
 #pragma unroll
@@ -88,13 +124,25 @@ __global__ __launch_bounds__(256) void k_eig_lane(int batch, const Tin* __restri
             s.ai[i][j] = im;
         }
     herm_tridiagonalize<LaneMath, N>(s);
+    if constexpr (LR) {
+#pragma unroll
+        for (int j = 0; j < kReflLds; ++j)
+#pragma unroll
+            for (int i = j + 2; i < N; ++i) rl[refl_entry(N, i, j) * 256 + tid] = double2{s.ar[i][j], s.ai[i][j]};
+        // the entries are read back from LDS, not kept in registers
+        __asm__ volatile("" ::: "memory");
+    }
     tridiag_ql<LaneMath, N>(s);
     int rk[N];
     eig_ranks<N>(s.d, rk);
     if (!valid) return;
 #pragma unroll
     for (int c = 0; c < N; ++c) evals[slot * N + rk[c]] = s.d[c];
-    if (evecs != nullptr) store_lane_vectors<N, 0>(s, rk, evecs + slot * N * N * 2);
+    if (evecs == nullptr) return;
+    if constexpr (LR)
+        store_lane_vectors<N, 0>(s, ReflInLds<N>{s, rl, tid}, rk, evecs + slot * N * N * 2);
+    else
+        store_lane_vectors<N, 0>(s, ReflInRegs<N>{s}, rk, evecs + slot * N * N * 2);
 }
 
 constexpr int kWgMax = 128;   // largest order of the wavefront solver

@@ -194,19 +194,31 @@ __host__ __device__ __forceinline__ void tridiag_ql(HermLane<N>& s, int max_iter
     ql_deflate<MathT, N, 0>(s.d, s.e, s.z, max_iter);
 }
 
+// Where the back-transform reads reflector J's entries (i >= J+2): the lane's
+// registers by default; a caller may move some reflectors elsewhere (the
+// device solver keeps the first ones in LDS while QL runs).
+template <int N>
+struct ReflInRegs {
+    const HermLane<N>& s;
+    __host__ __device__ __forceinline__ double re(int i, int j) const { return s.ar[i][j]; }
+    __host__ __device__ __forceinline__ double im(int i, int j) const { return s.ai[i][j]; }
+};
+
 // Column C of U = Q Z, Q = H_0 H_1 ... H_{N-2}: reflector J applied to rows
 // J+1 .. after the reflectors above it.  Columns are independent, so a caller
 // forms and stores them one at a time.
-template <int N, int J>
-__host__ __device__ __forceinline__ void herm_back_step(const HermLane<N>& s, double (&xr)[N], double (&xi)[N]) {
+template <int N, int J, class RS>
+__host__ __device__ __forceinline__ void herm_back_step(const HermLane<N>& s, const RS& rs, double (&xr)[N],
+                                                        double (&xi)[N]) {
     if constexpr (J >= 0) {
         const double tr = s.taur[J], ti = s.taui[J];
         // y = v^H x
         double yr = xr[J + 1], yi = xi[J + 1];
 #pragma unroll
         for (int i = J + 2; i < N; ++i) {
-            yr = fma(s.ar[i][J], xr[i], fma(s.ai[i][J], xi[i], yr));
-            yi = fma(s.ar[i][J], xi[i], fma(-s.ai[i][J], xr[i], yi));
+            const double vr = rs.re(i, J), vi = rs.im(i, J);
+            yr = fma(vr, xr[i], fma(vi, xi[i], yr));
+            yi = fma(vr, xi[i], fma(-vi, xr[i], yi));
         }
         // x -= tau v y
         const double tyr = tr * yr - ti * yi, tyi = tr * yi + ti * yr;
@@ -214,21 +226,23 @@ __host__ __device__ __forceinline__ void herm_back_step(const HermLane<N>& s, do
         xi[J + 1] -= tyi;
 #pragma unroll
         for (int i = J + 2; i < N; ++i) {
-            xr[i] = fma(-s.ar[i][J], tyr, fma(s.ai[i][J], tyi, xr[i]));
-            xi[i] = fma(-s.ar[i][J], tyi, fma(-s.ai[i][J], tyr, xi[i]));
+            const double vr = rs.re(i, J), vi = rs.im(i, J);
+            xr[i] = fma(-vr, tyr, fma(vi, tyi, xr[i]));
+            xi[i] = fma(-vr, tyi, fma(-vi, tyr, xi[i]));
         }
-        herm_back_step<N, J - 1>(s, xr, xi);
+        herm_back_step<N, J - 1>(s, rs, xr, xi);
     }
 }
 
-template <int N, int C>
-__host__ __device__ __forceinline__ void herm_eigenvector(const HermLane<N>& s, double (&xr)[N], double (&xi)[N]) {
+template <int N, int C, class RS>
+__host__ __device__ __forceinline__ void herm_eigenvector(const HermLane<N>& s, const RS& rs, double (&xr)[N],
+                                                          double (&xi)[N]) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         xr[i] = s.z[i][C];
         xi[i] = 0.0;
     }
-    herm_back_step<N, N - 2>(s, xr, xi);
+    herm_back_step<N, N - 2>(s, rs, xr, xi);
 }
 
 // rank of each eigenvalue in ascending order, ties by index

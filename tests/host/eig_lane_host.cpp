@@ -19,7 +19,7 @@ template <int N, int C>
 void store_cols(const ephx::HermLane<N>& s, const int* rk, double* v) {
     if constexpr (C < N) {
         double xr[N], xi[N];
-        ephx::herm_eigenvector<N, C>(s, xr, xi);
+        ephx::herm_eigenvector<N, C>(s, ephx::ReflInRegs<N>{s}, xr, xi);
         for (int i = 0; i < N; ++i) { v[(i * N + rk[C]) * 2] = xr[i]; v[(i * N + rk[C]) * 2 + 1] = xi[i]; }
         store_cols<N, C + 1>(s, rk, v);
     }
