@@ -47,18 +47,23 @@ struct LaneMath {
     static __device__ __forceinline__ bool any(bool p) { return __any(p); }
 };
 
+// column C of U to its ranked column: row-major (entry (i, c) at i N + c), or
+// column-major when cm (at c N + i: the column is one contiguous 16 N bytes,
+// whole cache lines, where the row-major stores land 16 N bytes apart and
+// leave lines half written)
 template <int N, int C, class RS>
 __device__ __forceinline__ void store_lane_vectors(const HermLane<N>& s, const RS& rs, const int (&rk)[N],
-                                                   double* out) {
+                                                   double* out, int cm) {
     if constexpr (C < N) {
         double xr[N], xi[N];
         herm_eigenvector<N, C>(s, rs, xr, xi);
 #pragma unroll
-        for (int i = 0; i < N; ++i) *reinterpret_cast<double2*>(out + (i * N + rk[C]) * 2) = double2{xr[i], xi[i]};
+        for (int i = 0; i < N; ++i)
+            *reinterpret_cast<double2*>(out + (cm ? rk[C] * N + i : i * N + rk[C]) * 2) = double2{xr[i], xi[i]};
         // the next column reads the reflectors in LDS again rather than
         // holding them in registers across columns
         __asm__ volatile("" ::: "memory");
-        store_lane_vectors<N, C + 1>(s, rs, rk, out);
+        store_lane_vectors<N, C + 1>(s, rs, rk, out, cm);
     }
 }
 
@@ -96,7 +101,8 @@ struct ReflInLds {
 // in column c of evecs[slot] (row-major complex n x n).
 template <typename Tin, int N, bool PK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 8 ? 2 : 1))) void k_eig_lane(
-    int batch, const Tin* __restrict__ A, long strideA, double* __restrict__ evals, double* __restrict__ evecs) {
+    int batch, const Tin* __restrict__ A, long strideA, double* __restrict__ evals, double* __restrict__ evecs,
+    int cm) {
     constexpr bool LR = N == 8;
     constexpr int NE = LR ? refl_lds_entries<N>() : 1;
     __shared__ double2 rl[NE * 256];
@@ -140,9 +146,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 8 ? 2 
     for (int c = 0; c < N; ++c) evals[slot * N + rk[c]] = s.d[c];
     if (evecs == nullptr) return;
     if constexpr (LR)
-        store_lane_vectors<N, 0>(s, ReflInLds<N>{s, rl, tid}, rk, evecs + slot * N * N * 2);
+        store_lane_vectors<N, 0>(s, ReflInLds<N>{s, rl, tid}, rk, evecs + slot * N * N * 2, cm);
     else
-        store_lane_vectors<N, 0>(s, ReflInRegs<N>{s}, rk, evecs + slot * N * N * 2);
+        store_lane_vectors<N, 0>(s, ReflInRegs<N>{s}, rk, evecs + slot * N * N * 2, cm);
 }
 
 constexpr int kWgMax = 128;   // largest order of the wavefront solver
@@ -498,12 +504,12 @@ __global__ void k_phonon_omega(long count, double* lam) {
 }
 
 template <typename Tin, bool PK = false>
-void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, double* evecs, hipStream_t st) {
+void launch_eig(int batch, int n, const Tin* A, long strideA, double* evals, double* evecs, int cm, hipStream_t st) {
     dim3 grid((unsigned)(((long)batch + 255) / 256));
     switch (n) {
 #define EPHX_EIG_CASE(NN) \
     case NN:                                                                                                \
-        hipLaunchKernelGGL((k_eig_lane<Tin, NN, PK>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs); \
+        hipLaunchKernelGGL((k_eig_lane<Tin, NN, PK>), grid, dim3(256), 0, st, batch, A, strideA, evals, evecs, cm); \
         break;
         EPHX_EIG_CASE(1)
         EPHX_EIG_CASE(2)
@@ -541,18 +547,19 @@ void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals,
         return;
     }
     if (a_f32)
-        launch_eig(batch, n, (const float*)A, strideA, evals, evecs, st);
+        launch_eig(batch, n, (const float*)A, strideA, evals, evecs, 0, st);
     else
-        launch_eig(batch, n, (const double*)A, strideA, evals, evecs, st);
+        launch_eig(batch, n, (const double*)A, strideA, evals, evecs, 0, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string("eig_herm: ") + hipGetErrorString(e)};
 }
 
-void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, hipStream_t st) {
+void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, int evecs_cm,
+                     hipStream_t st) {
     if (batch <= 0) return;
     if (n < 1 || n > kEigMax) throw Error{-6, "eig_herm_packed: matrix order must be 1..8"};
     if (strideP < (long)n * n) throw Error{-1, "eig_herm_packed: stride below n*n"};
-    launch_eig<double, true>(batch, n, P, strideP, evals, evecs, st);
+    launch_eig<double, true>(batch, n, P, strideP, evals, evecs, evecs_cm, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{-3, std::string("eig_herm_packed: ") + hipGetErrorString(e)};
 }

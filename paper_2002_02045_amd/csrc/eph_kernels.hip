@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64) void k_eph_adjoint(EphEpilogue e, const double*
         const double* gp = gwz + (long)ql * ng * 2;
         const double* uq = e.ukq + pair * nw2 * 2;
         for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
-        for (int i = lane; i < nw2; i += 64) s_u[i] = ld(uq, i);
+        for (int i = lane; i < nw2; i += 64) s_u[i] = ld(uq, e.u_cm ? (i % nw) * nw + i / nw : i);
         for (int i = lane; i < nm * nm; i += 64) {
             const int x = i / nm, nu = i % nm;
             const double om = e.omega[qg * nm + nu];
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
 #pragma unroll
         for (int j = 0; j < UPL; ++j) {
             const int i = lane + 64 * j;
-            if (i < nw2) ru[j] = ldd<T>(uq, i);
+            if (i < nw2) ru[j] = ldd<T>(uq, e.u_cm ? (i % nw) * nw + i / nw : i);
         }
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(64) void k_eph_epilogue(EphEpilogue e) {
             const T* gp = gwz + (long)ql * ng * 2;
             const double* uq = e.ukq + pair * nw2 * 2;
             for (int i = lane; i < ng; i += 64) s_gw[i] = ld(gp, i);
-            for (int i = lane; i < nw2; i += 64) s_u[i] = ldd<T>(uq, i);
+            for (int i = lane; i < nw2; i += 64) s_u[i] = ldd<T>(uq, e.u_cm ? (i % nw) * nw + i / nw : i);
             for (int i = lane; i < nm * nm; i += 64) {
                 const int x = i / nm, nu = i % nm;
                 const double om = e.omega[qg * nm + nu];
@@ -633,6 +633,9 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
     }
     const int dst_l = lane >= 16 && lane < 22 ? kPsLive + lane - 16 : kPsDump;
     const double en = e.ek[(long)z * NW + n];
+    // U(k+q) entries (i, m) = (l/16 (+4), l%8) of lane l, in either stored layout
+    const int ua_off = (e.u_cm ? mr * NW + lg : lg * NW + mr) * 2;
+    const int ub_off = (e.u_cm ? mr * NW + 4 + lg : (4 + lg) * NW + mr) * 2;
     const float is = (float)(1.0 / e.sigma);
     double acc[2] = {0.0, 0.0};
     EpiOperands ring[kEpiDepth];
@@ -648,8 +651,8 @@ __global__ __launch_bounds__(64) void k_eph_rates_mfma(EphEpilogue e) {
         }
         const long pair = (long)z * e.nq + ql;
         const double* uq = e.ukq + pair * NW * NW * 2;
-        o.ua = *reinterpret_cast<const double2*>(uq + (lg * NW + mr) * 2);
-        o.ub = *reinterpret_cast<const double2*>(uq + ((4 + lg) * NW + mr) * 2);
+        o.ua = *reinterpret_cast<const double2*>(uq + ua_off);
+        o.ub = *reinterpret_cast<const double2*>(uq + ub_off);
 #pragma unroll
         for (int ks = 0; ks < 3; ++ks) o.es[ks] = esq[((long)ql * NM * NM + ((4 * ks + lg) >> 1) * NM + nupc) * 2 + esc];
         o.em = e.ekq[pair * NW + mst];

@@ -696,11 +696,16 @@ static void hkq_fourier(ephx_model* m, int nb, const double* kb, const double* h
     else
         phase_gemm_herm_f64(nq, nw2, m->n_re_half, nb, qb, kb, m->d_re_half, m->d_h_half, hkq, (long)nq * nw2, st);
 }
-static void hkq_eig(ephx_model* m, long npair, double* hkq, double* ekq, double* ukq, hipStream_t st) {
-    if (m->d_h_pack)
-        eig_herm_packed((int)npair, m->nw, hkq, m->h_pack, ekq, ukq, st);
-    else
-        eig_herm((int)npair, m->nw, hkq, 0, m->nw * m->nw, ekq, ukq, st);
+// H(k+q) eigenpairs; U(k+q) column-major per matrix when want_cm and the
+// one-lane solver runs (the epilogues read either layout, the batched-GEMM
+// path of large models only row-major).  Returns the layout written.
+static int hkq_eig(ephx_model* m, long npair, double* hkq, double* ekq, double* ukq, bool want_cm, hipStream_t st) {
+    if (m->d_h_pack) {
+        eig_herm_packed((int)npair, m->nw, hkq, m->h_pack, ekq, ukq, want_cm ? 1 : 0, st);
+        return want_cm ? 1 : 0;
+    }
+    eig_herm((int)npair, m->nw, hkq, 0, m->nw * m->nw, ekq, ukq, st);
+    return 0;
 }
 static size_t hfold_bytes(const ephx_model* m, int nb) {
     return m->d_h_pack ? (size_t)m->n_re_half * 2 * nb * m->h_pack * 8 : 0;
@@ -801,6 +806,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
         partial = (double*)m->ws.get("drv.partial", (size_t)bk_eff * nblk * nw * nm * 8);
         acc = (double*)m->ws.get("drv.acc", (size_t)bk_eff * nw * nm * 8);
     }
+    int u_cm = 0;   // layout of U(k+q) the eigensolver wrote (column-major: 1)
     for (int k0 = 0; k0 < nk; k0 += bk_eff) {
         const int nb = std::min(bk_eff, nk - k0);
         const double* kb = k + 3L * k0;
@@ -844,7 +850,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             }
             {
                 StageTimer t("eig_hkq", st);
-                hkq_eig(m, (long)nb * nqc, (double*)hkq, ekq, ukq, st);
+                u_cm = hkq_eig(m, (long)nb * nqc, (double*)hkq, ekq, ukq, !wide, st);
             }
             // phases of the q chunk for the split-bf16 paths, shared by every k of the batch
             if (nsplit) {
@@ -919,6 +925,7 @@ void eph_driver(ephx_model* m, int nk, const double* k, int nq, const double* q,
             e.nm = nm;
             e.gw = gw;
             e.ukq = ukq;
+            e.u_cm = u_cm;
             e.ekq = ekq;
             e.ek = ek;
             e.uk = uk;
@@ -1020,6 +1027,7 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
     double* pmat = wide ? (double*)m->ws.get("adj.pmat", (size_t)qc * nm * nm * 16) : nullptr;
     double* ovb = wide && m->polar ? (double*)m->ws.get("adj.ov", npair * nw2 * 16) : nullptr;
     hip_check(hipMemsetAsync(gbar, 0, (size_t)m->n_re_g * nre_cols * 16, st), "hipMemsetAsync");
+    int u_cm = 0;   // layout of U(k+q) the eigensolver wrote (column-major: 1)
     for (int k0 = 0; k0 < nk; k0 += bk) {
         const int nb = std::min(bk, nk - k0);
         const double* kb = k + 3L * k0;
@@ -1031,7 +1039,7 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
             const int nqc = std::min(qc, nq - q0);
             const double* qb = q + 3L * q0;
             hkq_fourier(m, nb, kb, hfold, nqc, qb, hkq, st);
-            hkq_eig(m, (long)nb * nqc, hkq, ekq, ukq, st);
+            u_cm = hkq_eig(m, (long)nb * nqc, hkq, ekq, ukq, !wide, st);
             phase_gemm_f64(nqc, (int)ngcol, m->n_rp_g, nb, qb, nullptr, m->d_rp_g, gp, nre_cols, gw,
                            (long)nqc * ngcol, st);
             if (wide) {
@@ -1073,6 +1081,7 @@ void rates_vjp_impl(ephx_model* m, const ephx_params* p, int nk, const double* k
             e.nm = nm;
             e.gw = gw;
             e.ukq = ukq;
+            e.u_cm = u_cm;
             e.ekq = ekq;
             e.ek = ek;
             e.uk = uk;

@@ -114,8 +114,11 @@ void split_bf16_f64(int nsplit, int f16, double scale, int Z, int K, int N, int 
 // [batch][n][n] complex double (column j = eigenvector j) or nullptr.
 void eig_herm(int batch, int n, void* A, int a_f32, long strideA, double* evals, double* evecs, hipStream_t st);
 // The same for n <= 8 from the packed Hermitian form: n*n reals per matrix
-// (stride strideP reals), P[i][j] = Re X_ij for i <= j, Im X_ji for i > j.
-void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, hipStream_t st);
+// (stride strideP reals), P[i][j] = Re X_ij for i <= j, Im X_ji for i > j;
+// evecs_cm = 1 stores each matrix's eigenvectors column-major (eigenvector j
+// at [j][0..n), contiguous).
+void eig_herm_packed(int batch, int n, const double* P, long strideP, double* evals, double* evecs, int evecs_cm,
+                     hipStream_t st);
 
 // omega_nu = sign(lam) sqrt(|hbar^2/amu/A^2 * lam|) in place.
 void phonon_omega(long count, double* lam, hipStream_t st);
@@ -151,6 +154,7 @@ struct EphEpilogue {
     int nw, nm;
     const void* gw;     // [nkb][nq][nm][nw][nw] complex (float or double)
     const double* ukq;  // [nkb][nq][nw][nw] complex
+    int u_cm;           // 1: each U(k+q) stored column-major ([m][i], eigenvector m contiguous)
     const double* ekq;  // [nkb][nq][nw]
     const double* ek;   // [nkb][nw]
     const double* uk;   // [nkb][nw][nw] complex (polar term)
